@@ -1,0 +1,514 @@
+/*
+ * dect_oracle.c -- plain FP64 CPU oracle of the DECT reconstruction path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package's smoke check and
+ * the benchmark's CPU-baseline leg load this library.  It shares no code,
+ * header or table with the GPU library: it implements the same mathematics
+ * from the paper (Li et al., "Efficient Image Reconstruction and Practical
+ * Decomposition for Dual-energy CT") in the most direct form, slowly.
+ *
+ * Contents and the passage each follows:
+ *   or_project / or_backproject  Joseph ray-driven line integrals of the image
+ *                                and their literal transpose (the linear model
+ *                                A x = m of Eq. 1; A^T of the gradient G_f, Eq. 9)
+ *   or_grad / or_gradT           backward differences of the TV norm (Eq. 2)
+ *                                and their exact adjoint
+ *   or_shrink                    the z-subproblem's closed form (Eq. 8, read as
+ *                                isotropic shrinkage)
+ *   or_adm                       the reconstruction procedure (Eq. 10) for one
+ *                                energy block of Eq. 3, with the f-gradient of
+ *                                Eq. 9 and a Barzilai-Borwein step
+ *   or_dinv                      direct decomposition u = D^{-1} x (Eqs. 11-12)
+ *   or_edges_f32                 Prewitt edge weights e_ik (after Eq. 14); the
+ *                                threshold decision is taken in FP32 because it
+ *                                turns floats into a binary map
+ *   or_laplacian                 the Hessian of R(u) (Eq. 14), halved
+ *   or_pcg                       Jacobi-preconditioned CG for Eq. 15
+ *
+ * Readings of the paper taken here (each is also listed in the design notes):
+ *   - separable TV per energy block, zero difference on the first row/column;
+ *   - lambda has z's shape (two planes); xi is a free parameter;
+ *   - the BB step is BB1 = <s,s>/<s,y> with y the change of the f-gradient
+ *     at fixed (z, lambda), i.e. y = (mu A^T A + rho grad^T grad) s; the first
+ *     step is the exact line-search (Cauchy) step along G; a non-positive
+ *     <s,y> keeps the previous step;
+ *   - Eq. 15 with grad R = 2L (L the edge-weighted graph Laplacian) reads
+ *     (I + gamma L) u = D^{-1} x per material.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    int32_t nx, ny;
+    double pixel;
+    int32_t n_views;
+    const double *angles; /* NULL: theta_v = 2*pi*v/n_views */
+    int32_t n_bins;
+    double bin, det_offset, sod, sdd;
+} or_geom;
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Source position and (unnormalised) direction source -> centre of bin b. */
+static void ray_of(const or_geom *g, int v, int b, double *sx, double *sy, double *dx, double *dy)
+{
+    double th = g->angles ? g->angles[v] : 2.0 * M_PI * v / g->n_views;
+    double ct = cos(th), st = sin(th);
+    double u = (b - (g->n_bins - 1) / 2.0) * g->bin + g->det_offset;
+    double px = -(g->sdd - g->sod) * ct - u * st;
+    double py = -(g->sdd - g->sod) * st + u * ct;
+    *sx = g->sod * ct;
+    *sy = g->sod * st;
+    *dx = px - *sx;
+    *dy = py - *sy;
+}
+
+/*
+ * Walk one Joseph ray.  The driving axis is the one the ray is more aligned
+ * with (ties go to x).  On every line of the driving axis the ray's crossing
+ * is interpolated linearly between the two nearest pixel centres of that line;
+ * pixels outside the grid are zero.  Each line's two weights are scaled by the
+ * ray length per line, pixel / |cos| of the angle to the driving axis.
+ * mode 0: return sum_lines weight * X.  mode 1: X += weight * y (transpose).
+ */
+static double joseph_walk(const or_geom *g, int v, int b, double *X, double y, int mode)
+{
+    const int nx = g->nx, ny = g->ny;
+    const double dl = g->pixel;
+    double sx, sy, dx, dy;
+    ray_of(g, v, b, &sx, &sy, &dx, &dy);
+    const double len = sqrt(dx * dx + dy * dy);
+    double acc = 0.0;
+    if (fabs(dx) >= fabs(dy)) {
+        const double L = dl * len / fabs(dx);
+        for (int c = 0; c < nx; ++c) {
+            double xc = (c - (nx - 1) / 2.0) * dl;
+            double yy = sy + (xc - sx) * dy / dx;
+            double q = yy / dl + (ny - 1) / 2.0;
+            double fq = floor(q);
+            if (fq < -1.0 || fq > ny - 1.0) continue;
+            int r0 = (int)fq;
+            double w = q - fq;
+            if (r0 >= 0) {
+                if (mode == 0) acc += L * (1.0 - w) * X[(size_t)r0 * nx + c];
+                else X[(size_t)r0 * nx + c] += L * (1.0 - w) * y;
+            }
+            if (r0 + 1 <= ny - 1) {
+                if (mode == 0) acc += L * w * X[(size_t)(r0 + 1) * nx + c];
+                else X[(size_t)(r0 + 1) * nx + c] += L * w * y;
+            }
+        }
+    } else {
+        const double L = dl * len / fabs(dy);
+        for (int r = 0; r < ny; ++r) {
+            double yr = (r - (ny - 1) / 2.0) * dl;
+            double xx = sx + (yr - sy) * dx / dy;
+            double q = xx / dl + (nx - 1) / 2.0;
+            double fq = floor(q);
+            if (fq < -1.0 || fq > nx - 1.0) continue;
+            int c0 = (int)fq;
+            double w = q - fq;
+            if (c0 >= 0) {
+                if (mode == 0) acc += L * (1.0 - w) * X[(size_t)r * nx + c0];
+                else X[(size_t)r * nx + c0] += L * (1.0 - w) * y;
+            }
+            if (c0 + 1 <= nx - 1) {
+                if (mode == 0) acc += L * w * X[(size_t)r * nx + c0 + 1];
+                else X[(size_t)r * nx + c0 + 1] += L * w * y;
+            }
+        }
+    }
+    return acc;
+}
+
+/* Number of (ray, driving line) samples whose crossing lies in (-1, n). */
+int64_t or_count_samples(const or_geom *g)
+{
+    int64_t total = 0;
+    for (int v = 0; v < g->n_views; ++v)
+        for (int b = 0; b < g->n_bins; ++b) {
+            double sx, sy, dx, dy;
+            ray_of(g, v, b, &sx, &sy, &dx, &dy);
+            int xmaj = fabs(dx) >= fabs(dy);
+            int nl = xmaj ? g->nx : g->ny, nq = xmaj ? g->ny : g->nx;
+            for (int i = 0; i < nl; ++i) {
+                double q;
+                if (xmaj) {
+                    double xc = (i - (g->nx - 1) / 2.0) * g->pixel;
+                    q = (sy + (xc - sx) * dy / dx) / g->pixel + (g->ny - 1) / 2.0;
+                } else {
+                    double yr = (i - (g->ny - 1) / 2.0) * g->pixel;
+                    q = (sx + (yr - sy) * dx / dy) / g->pixel + (g->nx - 1) / 2.0;
+                }
+                if (q > -1.0 && q < nq) ++total;
+            }
+        }
+    return total;
+}
+
+/* sino[v][b] = (A img)[v,b] */
+void or_project(const or_geom *g, const double *img, double *sino)
+{
+    const int V = g->n_views, B = g->n_bins;
+#pragma omp parallel for schedule(static)
+    for (int v = 0; v < V; ++v)
+        for (int b = 0; b < B; ++b)
+            sino[(size_t)v * B + b] = joseph_walk(g, v, b, (double *)img, 0.0, 0);
+}
+
+/* img = A^T sino: every ray scatters its weights back.  Views are split into
+ * fixed contiguous chunks, one private image each, summed in chunk order, so
+ * the result does not depend on thread timing. */
+void or_backproject(const or_geom *g, const double *sino, double *img)
+{
+    const int V = g->n_views, B = g->n_bins;
+    const size_t N = (size_t)g->nx * g->ny;
+    int T = or_num_threads();
+    if (T > V) T = V;
+    if (T < 1) T = 1;
+    double *buf = (double *)calloc((size_t)T * N, sizeof(double));
+#pragma omp parallel for schedule(static, 1) num_threads(T)
+    for (int t = 0; t < T; ++t) {
+        int v0 = (int)((int64_t)V * t / T), v1 = (int)((int64_t)V * (t + 1) / T);
+        double *mine = buf + (size_t)t * N;
+        for (int v = v0; v < v1; ++v)
+            for (int b = 0; b < B; ++b)
+                joseph_walk(g, v, b, mine, sino[(size_t)v * B + b], 1);
+    }
+    for (size_t i = 0; i < N; ++i) {
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += buf[(size_t)t * N + i];
+        img[i] = s;
+    }
+    free(buf);
+}
+
+/* Backward differences (Eq. 2): planes [0] = along x (columns), [1] = along y
+ * (rows); the first column/row has zero difference. */
+void or_grad(int nx, int ny, const double *x, double *gx, double *gy)
+{
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            size_t i = (size_t)r * nx + c;
+            gx[i] = c >= 1 ? x[i] - x[i - 1] : 0.0;
+            gy[i] = r >= 1 ? x[i] - x[i - nx] : 0.0;
+        }
+}
+
+/* Exact adjoint of or_grad. */
+void or_gradT(int nx, int ny, const double *px, const double *py, double *out)
+{
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            size_t i = (size_t)r * nx + c;
+            double s = 0.0;
+            if (c >= 1) s += px[i];
+            if (c + 1 <= nx - 1) s -= px[i + 1];
+            if (r >= 1) s += py[i];
+            if (r + 1 <= ny - 1) s -= py[i + nx];
+            out[i] = s;
+        }
+}
+
+/* Isotropic shrinkage: argmin_z |z| + 1/(2t) |z - v|^2 = max(|v| - t, 0) v/|v|. */
+void or_shrink(size_t n, const double *vx, const double *vy, double t, double *zx, double *zy)
+{
+    for (size_t i = 0; i < n; ++i) {
+        double m = sqrt(vx[i] * vx[i] + vy[i] * vy[i]);
+        double s = m > t ? (m - t) / m : 0.0;
+        zx[i] = s * vx[i];
+        zy[i] = s * vy[i];
+    }
+}
+
+static double dot(size_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* TV norm of Eq. 2. */
+double or_tv(int nx, int ny, const double *x)
+{
+    size_t N = (size_t)nx * ny;
+    double *gx = malloc(N * sizeof(double)), *gy = malloc(N * sizeof(double));
+    or_grad(nx, ny, x, gx, gy);
+    double s = 0.0;
+    for (size_t i = 0; i < N; ++i) s += sqrt(gx[i] * gx[i] + gy[i] * gy[i]);
+    free(gx);
+    free(gy);
+    return s;
+}
+
+/*
+ * ADM-TV for one energy block of Eq. 3 (the two blocks decouple because W is
+ * block-diagonal and the TV is applied per block).
+ *
+ * In:  m [V][B] measured projections of this energy; beta the Eq. 3 weight;
+ *      x0 [ny][nx] start image (NULL: zeros).
+ * Out: x_out = f / beta after the last iteration; optional lam_out, z_out
+ *      [2][ny][nx]; log [(K+1)][5] rows (J(f^k), alpha^k, |grad f^k - z^k|,
+ *      |f^k - f^{k-1}|/|f^{k-1}|, |G^k|) -- the last row holds J(f^K).
+ * Returns the number of iterations run (stops early when tol > 0 and the
+ * relative image change drops below tol).
+ */
+int or_adm(const or_geom *g, const double *m, double beta, double mu, double rho, double xi,
+           int K, double tol, const double *x0, double *x_out, double *lam_out, double *z_out,
+           double *log)
+{
+    const int nx = g->nx, ny = g->ny;
+    const size_t N = (size_t)nx * ny, M = (size_t)g->n_views * g->n_bins;
+    double *f = calloc(N, sizeof(double)), *fo = calloc(N, sizeof(double));
+    double *G = calloc(N, sizeof(double)), *h = calloc(N, sizeof(double)), *ho = calloc(N, sizeof(double));
+    double *lx = calloc(N, sizeof(double)), *ly = calloc(N, sizeof(double));
+    double *zx = calloc(N, sizeof(double)), *zy = calloc(N, sizeof(double));
+    double *dx = calloc(N, sizeof(double)), *dy = calloc(N, sizeof(double));
+    double *wx = calloc(N, sizeof(double)), *wy = calloc(N, sizeof(double));
+    double *t1 = calloc(N, sizeof(double)), *s = calloc(N, sizeof(double)), *y = calloc(N, sizeof(double));
+    double *gs = calloc(M, sizeof(double)), *r = calloc(M, sizeof(double)), *p = calloc(M, sizeof(double));
+
+    for (size_t j = 0; j < M; ++j) gs[j] = beta * m[j];
+    if (x0)
+        for (size_t i = 0; i < N; ++i) f[i] = beta * x0[i];
+    /* r = A f - g ; h = mu A^T r */
+    or_project(g, f, r);
+    for (size_t j = 0; j < M; ++j) r[j] -= gs[j];
+    or_backproject(g, r, h);
+    for (size_t i = 0; i < N; ++i) h[i] *= mu;
+
+    double alpha = 0.0, relchg = 0.0;
+    int k;
+    for (k = 0; k < K; ++k) {
+        /* z-step (Eq. 8): z = shrink(grad f - lambda/rho, 1/rho) */
+        or_grad(nx, ny, f, dx, dy);
+        double tvf = 0.0;
+        for (size_t i = 0; i < N; ++i) {
+            tvf += sqrt(dx[i] * dx[i] + dy[i] * dy[i]);
+            wx[i] = dx[i] - lx[i] / rho;
+            wy[i] = dy[i] - ly[i] / rho;
+        }
+        or_shrink(N, wx, wy, 1.0 / rho, zx, zy);
+        /* G = mu A^T (A f - g) + rho grad^T (grad f - z) - grad^T lambda (Eq. 9) */
+        for (size_t i = 0; i < N; ++i) {
+            wx[i] = rho * (dx[i] - zx[i]) - lx[i];
+            wy[i] = rho * (dy[i] - zy[i]) - ly[i];
+        }
+        or_gradT(nx, ny, wx, wy, G);
+        for (size_t i = 0; i < N; ++i) G[i] += h[i];
+        double pres = 0.0;
+        for (size_t i = 0; i < N; ++i)
+            pres += (dx[i] - zx[i]) * (dx[i] - zx[i]) + (dy[i] - zy[i]) * (dy[i] - zy[i]);
+        if (k == 0) {
+            /* exact minimiser of the f-subproblem along -G */
+            or_project(g, G, p);
+            or_grad(nx, ny, G, wx, wy);
+            double gg = dot(N, G, G);
+            double den = mu * dot(M, p, p) + rho * (dot(N, wx, wx) + dot(N, wy, wy));
+            alpha = den > 0.0 ? gg / den : 0.0;
+        }
+        if (log) {
+            double *row = log + (size_t)k * 5;
+            row[0] = tvf + 0.5 * mu * dot(M, r, r);
+            row[1] = alpha;
+            row[2] = sqrt(pres);
+            row[3] = relchg;
+            row[4] = sqrt(dot(N, G, G));
+        }
+        /* f-step (Eq. 9) and the new gradient's data part */
+        memcpy(fo, f, N * sizeof(double));
+        memcpy(ho, h, N * sizeof(double));
+        for (size_t i = 0; i < N; ++i) f[i] -= alpha * G[i];
+        or_project(g, f, r);
+        for (size_t j = 0; j < M; ++j) r[j] -= gs[j];
+        or_backproject(g, r, h);
+        for (size_t i = 0; i < N; ++i) h[i] *= mu;
+        /* BB step from s = f^{k+1} - f^k, y = change of the f-gradient */
+        for (size_t i = 0; i < N; ++i) s[i] = f[i] - fo[i];
+        or_grad(nx, ny, s, wx, wy);
+        or_gradT(nx, ny, wx, wy, t1);
+        for (size_t i = 0; i < N; ++i) y[i] = (h[i] - ho[i]) + rho * t1[i];
+        double ss = dot(N, s, s), sy = dot(N, s, y);
+        if (sy > 0.0) alpha = ss / sy;
+        double fn = sqrt(dot(N, fo, fo));
+        relchg = fn > 0.0 ? sqrt(ss) / fn : (ss > 0.0 ? INFINITY : 0.0);
+        /* multiplier step (Eq. 7) */
+        or_grad(nx, ny, f, dx, dy);
+        for (size_t i = 0; i < N; ++i) {
+            lx[i] -= xi * (dx[i] - zx[i]);
+            ly[i] -= xi * (dy[i] - zy[i]);
+        }
+        if (tol > 0.0 && relchg < tol) {
+            ++k;
+            break;
+        }
+    }
+    if (log) {
+        or_grad(nx, ny, f, dx, dy);
+        double tvf = 0.0;
+        for (size_t i = 0; i < N; ++i) tvf += sqrt(dx[i] * dx[i] + dy[i] * dy[i]);
+        double *row = log + (size_t)k * 5;
+        row[0] = tvf + 0.5 * mu * dot(M, r, r);
+        row[1] = alpha;
+        row[2] = 0.0;
+        row[3] = relchg;
+        row[4] = 0.0;
+    }
+    for (size_t i = 0; i < N; ++i) x_out[i] = f[i] / beta;
+    if (lam_out) {
+        memcpy(lam_out, lx, N * sizeof(double));
+        memcpy(lam_out + N, ly, N * sizeof(double));
+    }
+    if (z_out) {
+        memcpy(z_out, zx, N * sizeof(double));
+        memcpy(z_out + N, zy, N * sizeof(double));
+    }
+    free(f); free(fo); free(G); free(h); free(ho); free(lx); free(ly); free(zx); free(zy);
+    free(dx); free(dy); free(wx); free(wy); free(t1); free(s); free(y); free(gs); free(r); free(p);
+    return k;
+}
+
+/* Eq. 12: x_h = eta_1H u1 + eta_2H u2, x_l = eta_1L u1 + eta_2L u2, inverted
+ * in closed form per pixel. */
+void or_dinv(size_t n, double e1h, double e2h, double e1l, double e2l, const double *xh,
+             const double *xl, double *u1, double *u2)
+{
+    double det = e1h * e2l - e2h * e1l;
+    for (size_t i = 0; i < n; ++i) {
+        u1[i] = (e2l * xh[i] - e2h * xl[i]) / det;
+        u2[i] = (e1h * xl[i] - e1l * xh[i]) / det;
+    }
+}
+
+/*
+ * Prewitt edge map and pair weights, in FP32 with a fixed operation order
+ * (the map is a threshold decision, so it is taken in the precision of the
+ * GPU kernel).  gx = right column sum - left column sum, gy = lower row sum -
+ * upper row sum, borders replicate; m2 = fmaf(gx, gx, gy*gy); edge where
+ * m2 > tau2 * max(m2).  e_right[r][c] couples (r,c)-(r,c+1), e_down[r][c]
+ * couples (r,c)-(r+1,c): eps if either pixel is an edge, else 1; pairs that
+ * leave the image get 0.
+ */
+void or_edges_f32(int nx, int ny, const float *x, float tau2, float eps, float *e_right,
+                  float *e_down, uint8_t *edge)
+{
+    size_t N = (size_t)nx * ny;
+    float *m2 = malloc(N * sizeof(float));
+    float mx = 0.0f;
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            int ru = r > 0 ? r - 1 : 0, rd = r < ny - 1 ? r + 1 : ny - 1;
+            int cl = c > 0 ? c - 1 : 0, cr = c < nx - 1 ? c + 1 : nx - 1;
+#define X(rr, cc) x[(size_t)(rr) * nx + (cc)]
+            float right = (X(ru, cr) + X(r, cr)) + X(rd, cr);
+            float left = (X(ru, cl) + X(r, cl)) + X(rd, cl);
+            float down = (X(rd, cl) + X(rd, c)) + X(rd, cr);
+            float up = (X(ru, cl) + X(ru, c)) + X(ru, cr);
+#undef X
+            float gx = right - left, gy = down - up;
+            float v = fmaf(gx, gx, gy * gy);
+            m2[(size_t)r * nx + c] = v;
+            if (v > mx) mx = v;
+        }
+    float thr = tau2 * mx;
+    for (size_t i = 0; i < N; ++i) edge[i] = m2[i] > thr;
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            size_t i = (size_t)r * nx + c;
+            e_right[i] = c + 1 < nx ? ((edge[i] || edge[i + 1]) ? eps : 1.0f) : 0.0f;
+            e_down[i] = r + 1 < ny ? ((edge[i] || edge[i + nx]) ? eps : 1.0f) : 0.0f;
+        }
+    free(m2);
+}
+
+/* (L u)_i = sum over the 4-neighbours k of e_ik (u_i - u_k) (Eq. 14). */
+void or_laplacian(int nx, int ny, const double *er, const double *ed, const double *u, double *out)
+{
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            size_t i = (size_t)r * nx + c;
+            double s = 0.0;
+            if (c + 1 < nx) s += er[i] * (u[i] - u[i + 1]);
+            if (c >= 1) s += er[i - 1] * (u[i] - u[i - 1]);
+            if (r + 1 < ny) s += ed[i] * (u[i] - u[i + nx]);
+            if (r >= 1) s += ed[i - nx] * (u[i] - u[i - nx]);
+            out[i] = s;
+        }
+}
+
+/*
+ * Jacobi-preconditioned CG for (I + gamma L) u = b, starting from u = b.
+ * Stops when |b - (I + gamma L) u| <= tol |b| or after max_iter iterations.
+ * Returns the iteration count; *relres receives the final relative residual.
+ */
+int or_pcg(int nx, int ny, const double *er, const double *ed, double gamma, const double *b,
+           double *u, int max_iter, double tol, double *relres)
+{
+    size_t N = (size_t)nx * ny;
+    double *res = malloc(N * sizeof(double)), *z = malloc(N * sizeof(double));
+    double *p = malloc(N * sizeof(double)), *q = malloc(N * sizeof(double));
+    double *dinv = malloc(N * sizeof(double));
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            size_t i = (size_t)r * nx + c;
+            double d = 0.0;
+            if (c + 1 < nx) d += er[i];
+            if (c >= 1) d += er[i - 1];
+            if (r + 1 < ny) d += ed[i];
+            if (r >= 1) d += ed[i - nx];
+            dinv[i] = 1.0 / (1.0 + gamma * d);
+        }
+    memcpy(u, b, N * sizeof(double));
+    or_laplacian(nx, ny, er, ed, u, q);
+    for (size_t i = 0; i < N; ++i) res[i] = b[i] - (u[i] + gamma * q[i]);
+    double bn = sqrt(dot(N, b, b));
+    double rn = sqrt(dot(N, res, res));
+    int it = 0;
+    if (bn == 0.0) {
+        memset(u, 0, N * sizeof(double));
+        rn = 0.0;
+        bn = 1.0;
+    }
+    for (size_t i = 0; i < N; ++i) z[i] = dinv[i] * res[i];
+    memcpy(p, z, N * sizeof(double));
+    double rz = dot(N, res, z);
+    while (it < max_iter && rn > tol * bn) {
+        or_laplacian(nx, ny, er, ed, p, q);
+        for (size_t i = 0; i < N; ++i) q[i] = p[i] + gamma * q[i];
+        double pq = dot(N, p, q);
+        if (pq <= 0.0) break;
+        double a = rz / pq;
+        for (size_t i = 0; i < N; ++i) {
+            u[i] += a * p[i];
+            res[i] -= a * q[i];
+        }
+        ++it;
+        rn = sqrt(dot(N, res, res));
+        for (size_t i = 0; i < N; ++i) z[i] = dinv[i] * res[i];
+        double rz2 = dot(N, res, z);
+        double beta = rz2 / rz;
+        rz = rz2;
+        for (size_t i = 0; i < N; ++i) p[i] = z[i] + beta * p[i];
+    }
+    if (relres) *relres = rn / bn;
+    free(res); free(z); free(p); free(q); free(dinv);
+    return it;
+}

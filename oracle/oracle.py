@@ -1,0 +1,240 @@
+"""ctypes front-end of the FP64 CPU oracle (dect_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the package's smoke
+check and by the benchmark's CPU-baseline leg, never by the GPU library or its
+Python binding.  It shares no code with them; geometry is passed as plain
+numbers following the same written conventions (image centred on the
+isocentre, theta_v = 2 pi v / V, flat centred detector, sinogram [V][B]).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dect_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, no FP contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+               _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Geom(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("pixel", ct.c_double),
+                ("n_views", ct.c_int32), ("angles", ct.POINTER(ct.c_double)),
+                ("n_bins", ct.c_int32), ("bin", ct.c_double), ("det_offset", ct.c_double),
+                ("sod", ct.c_double), ("sdd", ct.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ct.CDLL(_LIB)
+        P = ct.POINTER
+        d, i32, sz = ct.c_double, ct.c_int32, ct.c_size_t
+        pd = P(ct.c_double)
+        pf = P(ct.c_float)
+        L.or_num_threads.restype = ct.c_int
+        L.or_count_samples.argtypes = [P(_Geom)]
+        L.or_count_samples.restype = ct.c_int64
+        L.or_project.argtypes = [P(_Geom), pd, pd]
+        L.or_backproject.argtypes = [P(_Geom), pd, pd]
+        L.or_grad.argtypes = [ct.c_int, ct.c_int, pd, pd, pd]
+        L.or_gradT.argtypes = [ct.c_int, ct.c_int, pd, pd, pd]
+        L.or_shrink.argtypes = [sz, pd, pd, d, pd, pd]
+        L.or_tv.argtypes = [ct.c_int, ct.c_int, pd]
+        L.or_tv.restype = d
+        L.or_adm.argtypes = [P(_Geom), pd, d, d, d, d, ct.c_int, d, pd, pd, pd, pd, pd]
+        L.or_adm.restype = ct.c_int
+        L.or_dinv.argtypes = [sz, d, d, d, d, pd, pd, pd, pd]
+        L.or_edges_f32.argtypes = [ct.c_int, ct.c_int, pf, ct.c_float, ct.c_float, pf, pf,
+                                   P(ct.c_uint8)]
+        L.or_laplacian.argtypes = [ct.c_int, ct.c_int, pd, pd, pd, pd]
+        L.or_pcg.argtypes = [ct.c_int, ct.c_int, pd, pd, d, pd, pd, ct.c_int, d, pd]
+        L.or_pcg.restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def _p(a: Optional[np.ndarray], ctype=ct.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ct.POINTER(ctype))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OGeom:
+    """Geometry in the oracle's own struct; keeps the angle array alive."""
+
+    def __init__(self, nx, ny, pixel_mm, n_views, n_bins, bin_mm, sod_mm, sdd_mm,
+                 det_offset_mm=0.0, angles_rad: Optional[Sequence[float]] = None):
+        self.nx, self.ny, self.n_views, self.n_bins = int(nx), int(ny), int(n_views), int(n_bins)
+        self._angles = None if angles_rad is None else _f64(angles_rad)
+        self.s = _Geom(self.nx, self.ny, float(pixel_mm), self.n_views,
+                       _p(self._angles), self.n_bins, float(bin_mm), float(det_offset_mm),
+                       float(sod_mm), float(sdd_mm))
+
+    @classmethod
+    def of(cls, g) -> "OGeom":
+        """From any object with the Geometry field names."""
+        return cls(g.nx, g.ny, g.pixel_mm, g.n_views, g.n_bins, g.bin_mm, g.sod_mm, g.sdd_mm,
+                   g.det_offset_mm, g.angles_rad)
+
+
+def _og(g) -> OGeom:
+    return g if isinstance(g, OGeom) else OGeom.of(g)
+
+
+def count_samples(g) -> int:
+    og = _og(g)
+    return int(lib().or_count_samples(ct.byref(og.s)))
+
+
+def project(g, img: np.ndarray) -> np.ndarray:
+    og = _og(g)
+    x = _f64(img).reshape(og.ny, og.nx)
+    out = np.empty((og.n_views, og.n_bins))
+    lib().or_project(ct.byref(og.s), _p(x), _p(out))
+    return out
+
+
+def backproject(g, sino: np.ndarray) -> np.ndarray:
+    og = _og(g)
+    y = _f64(sino).reshape(og.n_views, og.n_bins)
+    out = np.empty((og.ny, og.nx))
+    lib().or_backproject(ct.byref(og.s), _p(y), _p(out))
+    return out
+
+
+def grad(x: np.ndarray):
+    x = _f64(x)
+    ny, nx = x.shape
+    gx, gy = np.empty_like(x), np.empty_like(x)
+    lib().or_grad(nx, ny, _p(x), _p(gx), _p(gy))
+    return gx, gy
+
+
+def gradT(px: np.ndarray, py: np.ndarray) -> np.ndarray:
+    px, py = _f64(px), _f64(py)
+    ny, nx = px.shape
+    out = np.empty_like(px)
+    lib().or_gradT(nx, ny, _p(px), _p(py), _p(out))
+    return out
+
+
+def shrink(vx, vy, t: float):
+    vx, vy = _f64(vx), _f64(vy)
+    zx, zy = np.empty_like(vx), np.empty_like(vy)
+    lib().or_shrink(vx.size, _p(vx), _p(vy), float(t), _p(zx), _p(zy))
+    return zx, zy
+
+
+def tv(x) -> float:
+    x = _f64(x)
+    return float(lib().or_tv(x.shape[1], x.shape[0], _p(x)))
+
+
+class AdmResult:
+    def __init__(self, x, lam, z, log, iters):
+        self.x, self.lam, self.z, self.log, self.iters = x, lam, z, log, iters
+
+    @property
+    def J(self):
+        return self.log[: self.iters + 1, 0]
+
+    @property
+    def alpha(self):
+        return self.log[: self.iters + 1, 1]
+
+
+def adm(g, m: np.ndarray, beta: float, mu: float, rho: float, xi: float, iters: int,
+        tol: float = 0.0, x0: Optional[np.ndarray] = None) -> AdmResult:
+    """ADM-TV (Eq. 10) for one energy; returns x = f / beta and the log."""
+    og = _og(g)
+    mm = _f64(m).reshape(og.n_views, og.n_bins)
+    x0c = None if x0 is None else _f64(x0).reshape(og.ny, og.nx)
+    x = np.empty((og.ny, og.nx))
+    lam = np.empty((2, og.ny, og.nx))
+    z = np.empty((2, og.ny, og.nx))
+    log = np.zeros((iters + 1, 5))
+    k = lib().or_adm(ct.byref(og.s), _p(mm), float(beta), float(mu), float(rho), float(xi),
+                     int(iters), float(tol), _p(x0c), _p(x), _p(lam), _p(z), _p(log))
+    return AdmResult(x, lam, z, log, int(k))
+
+
+def dinv(xh, xl, eta_water_high, eta_bone_high, eta_water_low, eta_bone_low):
+    xh, xl = _f64(xh), _f64(xl)
+    u1, u2 = np.empty_like(xh), np.empty_like(xh)
+    lib().or_dinv(xh.size, eta_water_high, eta_bone_high, eta_water_low, eta_bone_low,
+                  _p(xh), _p(xl), _p(u1), _p(u2))
+    return u1, u2
+
+
+def edges_f32(xl: np.ndarray, tau: float, eps: float):
+    """Prewitt edge weights; the decision is taken in FP32 (tau2 = fp32(tau*tau))."""
+    x = np.ascontiguousarray(xl, dtype=np.float32)
+    ny, nx = x.shape
+    er = np.empty_like(x)
+    ed = np.empty_like(x)
+    e = np.empty(x.shape, dtype=np.uint8)
+    lib().or_edges_f32(nx, ny, _p(x, ct.c_float), ct.c_float(np.float32(tau * tau)),
+                       ct.c_float(np.float32(eps)), _p(er, ct.c_float), _p(ed, ct.c_float),
+                       e.ctypes.data_as(ct.POINTER(ct.c_uint8)))
+    return er, ed, e
+
+
+def laplacian(er, ed, u):
+    er, ed, u = _f64(er), _f64(ed), _f64(u)
+    ny, nx = u.shape
+    out = np.empty_like(u)
+    lib().or_laplacian(nx, ny, _p(er), _p(ed), _p(u), _p(out))
+    return out
+
+
+def pcg(er, ed, gamma: float, b, max_iter: int = 500, tol: float = 1e-12):
+    er, ed, b = _f64(er), _f64(ed), _f64(b)
+    ny, nx = b.shape
+    u = np.empty_like(b)
+    rr = ct.c_double(0.0)
+    it = lib().or_pcg(nx, ny, _p(er), _p(ed), float(gamma), _p(b), _p(u), int(max_iter),
+                      float(tol), ct.byref(rr))
+    return u, int(it), float(rr.value)
+
+
+def pls(xh, xl, p, edge_w=None, tol: float = 1e-12):
+    """Full decomposition: D^{-1} x, edge weights on x_l (FP32 decision), PCG.
+
+    p carries eta_*, gamma, edge_eps, edge_tau, max_iter.  edge_w, when given,
+    is a shared [2][ny][nx] (right, down) weight map.
+    """
+    b1, b2 = dinv(xh, xl, p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
+    if edge_w is None:
+        er, ed, _ = edges_f32(xl, p.edge_tau, p.edge_eps)
+    else:
+        er, ed = edge_w[0], edge_w[1]
+    u1, it1, r1 = pcg(er, ed, p.gamma, b1, p.max_iter, tol)
+    u2, it2, r2 = pcg(er, ed, p.gamma, b2, p.max_iter, tol)
+    return u1, u2, (it1, it2), (r1, r2)
