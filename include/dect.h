@@ -1,0 +1,193 @@
+/*
+ * dect.h -- C ABI of libdect, the MI355X (gfx950) library for the hot path of
+ * dual-energy CT reconstruction and decomposition after Li et al.,
+ * "Efficient Image Reconstruction and Practical Decomposition for
+ * Dual-energy Computed Tomography" (arXiv 1607.01650).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Image: float32, row-major [ny][nx] (column index fastest).  Pixel (r, c)
+ *   has its centre at x = (c - (nx-1)/2) * pixel_mm, y = (r - (ny-1)/2) *
+ *   pixel_mm: the image is centred on the isocentre.
+ * Views: theta_v = 2*pi*v/n_views (counter-clockwise from +x) unless
+ *   angles_rad is given.  Source at sod_mm * (cos, sin)(theta).  Flat
+ *   detector line centred at -(sdd_mm - sod_mm) * (cos, sin)(theta) with axis
+ *   (-sin, cos)(theta); bin b is centred at u = (b - (n_bins-1)/2) * bin_mm +
+ *   det_offset_mm.  This is the central slice of the paper's cone-beam
+ *   scanner (Sec. 2.1, Fig. 1; Sec. 3).
+ * Sinogram: float32, row-major [n_views][n_bins].
+ * Batched arrays are stacked contiguously: item i starts at i * (ny*nx) or
+ *   i * (n_views*n_bins) elements.
+ * Memory: every d_* pointer is device memory owned by the caller, on the
+ *   current HIP device; the library never frees it.  The library owns its
+ *   cached geometry tables and scratch workspaces (per device, per geometry),
+ *   released by dect_release_caches() or at process exit.
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *   asynchronous on it unless a host-side report/log is requested, in which
+ *   case the call synchronises the stream before returning.
+ * Errors: every call returns a dect_status; arguments and geometry are
+ *   validated on the host before any launch and nothing is launched on
+ *   error.  dect_last_error() gives a message for the calling thread.
+ *   Calls are thread-safe with respect to the caches; concurrent calls that
+ *   share output buffers race like any other kernels.
+ */
+#ifndef DECT_H
+#define DECT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DECT_OK = 0,
+    DECT_ERR_INVALID_ARG = 1, /* null pointer, non-positive size, bad parameter */
+    DECT_ERR_GEOMETRY = 2,    /* source inside the image, SDD <= SOD, fan >= 90 deg */
+    DECT_ERR_HIP = 3,         /* a HIP runtime call failed */
+    DECT_ERR_NONFINITE = 4,   /* a reduction produced NaN/Inf (report.iters says when) */
+    DECT_WARN_MAXITER = 5     /* PCG stopped at max_iter above tolerance */
+} dect_status;
+
+/* 2-D fan-beam geometry with a flat detector line (Sec. 2.1 and Sec. 3:
+ * SOD, SDD, views and detector bins define the system matrix A of Eq. 1). */
+typedef struct {
+    int32_t nx, ny;           /* image size in pixels */
+    double pixel_mm;          /* square pixel side */
+    int32_t n_views;          /* number of projection views */
+    const double *angles_rad; /* host array [n_views] or NULL for 2*pi*v/n_views */
+    int32_t n_bins;           /* detector bins per view */
+    double bin_mm;            /* bin pitch on the detector line */
+    double det_offset_mm;     /* shift of the detector centre along its axis */
+    double sod_mm;            /* source to isocentre */
+    double sdd_mm;            /* source to detector */
+} dect_geometry;
+
+/* ADM-TV parameters (Eqs. 3-10 and Sec. 2.4). */
+enum { DECT_WARM_START = 1 /* start from d_x_* instead of zero images */ };
+typedef struct {
+    double mu;        /* data-fidelity weight of Eq. 4 */
+    double rho;       /* augmented-Lagrangian penalty of Eq. 6 */
+    double xi;        /* multiplier step of Eq. 7 */
+    double beta_high; /* noise-balancing scalar beta_1 of Eq. 3 (high energy) */
+    double beta_low;  /* beta_2 (low energy) */
+    int32_t max_iter; /* iterations to run (>= 0) */
+    double tol;       /* stop once |f^{k+1}-f^k| / |f^k| < tol for both
+                         energies (0 = run max_iter iterations) */
+    int32_t flags;    /* DECT_WARM_START */
+    double *log;      /* host [max_iter+1][4] or NULL: per energy-pair row
+                         {J_high(f^k), J_low(f^k), alpha_high^k, alpha_low^k};
+                         filling it synchronises the stream */
+} dect_adm_params;
+
+/* PLS decomposition parameters (Eqs. 11-15, Sec. 2.4, Sec. 3). */
+typedef struct {
+    double eta_water_high, eta_bone_high; /* eta_1H, eta_2H of Eq. 12 (1/mm) */
+    double eta_water_low, eta_bone_low;   /* eta_1L, eta_2L */
+    double gamma;                         /* smoothing weight of Eq. 13 */
+    double edge_eps;                      /* e_ik for pairs touching an edge pixel */
+    double edge_tau;                      /* edge if |Prewitt| > tau * max |Prewitt| */
+    int32_t max_iter;                     /* PCG iteration cap (paper: 500) */
+    double tol;                           /* PCG stop: |res| <= tol * |rhs| */
+} dect_pls_params;
+
+typedef struct {
+    int32_t iters;       /* ADM iterations run, or the larger PCG count */
+    double objective;    /* ADM: J of Eq. 4 summed over both energies at exit */
+    double rel_change;   /* ADM: last max relative image change */
+    double pcg_residual; /* PLS: max final relative residual of the materials */
+    int32_t status;      /* dect_status of the run */
+} dect_report;
+
+/* Opaque resumable ADM state: f, lambda, z, h, r and the step for both
+ * energies of one geometry.  Running K1 then K2 iterations through a state
+ * gives bitwise the same images as K1 + K2 iterations in one call. */
+typedef struct dect_adm_state dect_adm_state;
+
+/*
+ * Forward projection d_sino = A d_img (Eq. 1; Sec. 2.4's forward projector),
+ * with A the Joseph ray-driven linear-interpolation model: each ray steps
+ * along the image axis it is more aligned with and interpolates linearly
+ * between the two nearest pixel centres of every line it crosses; samples are
+ * scaled by the path length per line.  The paper's own A uses Siddon's
+ * intersection lengths; Joseph is the model implemented here.
+ * batch images [batch][ny][nx] -> [batch][n_views][n_bins].
+ */
+dect_status dect_project(const dect_geometry *geom, const float *d_img, float *d_sino,
+                         int32_t batch, void *stream);
+
+/*
+ * Back-projection d_img = A^T d_sino: the exact transpose of dect_project's
+ * matrix (the W^T of the gradient G_f after Eq. 9), evaluated in gather form:
+ * every output pixel sums over the rays that touch it, with the same
+ * interpolation weights as the forward pass, bit for bit; no atomics.
+ */
+dect_status dect_backproject(const dect_geometry *geom, const float *d_sino, float *d_img,
+                             int32_t batch, void *stream);
+
+/*
+ * TV-regularised ADM reconstruction of both energies (Eq. 10): the stacked
+ * system of Eq. 3 with f = (beta_1 x_h; beta_2 x_l), g = (beta_1 m_h;
+ * beta_2 m_l), minimising |grad f| + mu/2 |W f - g|^2 (Eq. 4) by the
+ * z-shrinkage (Eq. 8), one gradient step on f with a Barzilai-Borwein step
+ * (Eq. 9) and the multiplier step (Eq. 7).  TV is applied to each energy
+ * image separately.
+ * d_m_high/d_m_low: measured sinograms [n_views][n_bins].
+ * d_x_high/d_x_low: [ny][nx] outputs (x = f / beta); inputs too when
+ *   flags has DECT_WARM_START.
+ * state: NULL, or a state from dect_adm_state_create for this geometry;
+ *   an empty state starts a run, a used one continues it (x inputs ignored).
+ * rep: NULL, or filled after synchronising the stream.
+ */
+dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
+                        const dect_adm_params *params, float *d_x_high, float *d_x_low,
+                        dect_adm_state *state, dect_report *rep, void *stream);
+
+dect_status dect_adm_state_create(const dect_geometry *geom, dect_adm_state **out);
+dect_status dect_adm_state_destroy(dect_adm_state *state);
+
+/*
+ * Image-domain decomposition by penalised least squares (Eqs. 11-15): the
+ * direct decomposition b = D^{-1} x per pixel (Eq. 12), then per material
+ * (I + gamma L) u = b, the normal equations of Eq. 13 with the edge-weighted
+ * quadratic smoothness of Eq. 14 (grad R = 2 L, Eq. 15), solved by
+ * Jacobi-preconditioned CG from u = b.
+ * d_edge_w: NULL to detect edges on d_x_low (Prewitt, see
+ *   dect_pls_edge_weights), or a [2][ny][nx] map (right pairs, down pairs).
+ * d_u_water/d_u_bone: [ny][nx] outputs (unitless material fractions).
+ * rep: NULL or filled after synchronising (iterations, final residual).
+ */
+dect_status dect_pls_decompose(int32_t nx, int32_t ny, const float *d_x_high,
+                               const float *d_x_low, const dect_pls_params *params,
+                               const float *d_edge_w, float *d_u_water, float *d_u_bone,
+                               dect_report *rep, void *stream);
+
+/*
+ * Edge weights e_ik of Eq. 14 from a Prewitt edge map of d_x (Sec. 2.3:
+ * small at edges, one elsewhere): m2 = fmaf(gx, gx, gy*gy) with gx, gy the
+ * Prewitt responses (replicated borders), edge where m2 > fp32(tau^2) *
+ * max m2.  d_w[0][r][c] couples (r,c)-(r,c+1), d_w[1][r][c] couples
+ * (r,c)-(r+1,c): eps if either pixel is an edge, 1 otherwise, 0 for pairs
+ * leaving the image.  d_w is [2][ny][nx] float32.
+ */
+dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, double tau,
+                                  double eps, float *d_w, void *stream);
+
+/* Number of Joseph samples (ray, line) with the crossing inside (-1, n)
+ * for a geometry: the unit of projector work. */
+dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);
+
+/* Free cached tables and workspaces of the current device. */
+dect_status dect_release_caches(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *dect_last_error(void);
+
+/* Library version string. */
+const char *dect_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DECT_H */

@@ -1,0 +1,95 @@
+// extern "C" entry points of libdect (declared in include/dect.h).
+#include "common.h"
+
+namespace dect {
+const char *last_error();
+dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
+                   const dect_adm_params *P, float *xh, float *xl, dect_adm_state *state,
+                   dect_report *rep, hipStream_t s);
+dect_status adm_state_create(const dect_geometry *g, dect_adm_state **out);
+dect_status adm_state_destroy(dect_adm_state *S);
+void release_adm_states();
+dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
+                          const dect_pls_params *P, const float *ew, float *u1, float *u2,
+                          dect_report *rep, hipStream_t s);
+dect_status pls_edge_weights(int nx, int ny, const float *x, double tau, double eps, float *w,
+                             hipStream_t s);
+}  // namespace dect
+
+extern "C" {
+
+dect_status dect_project(const dect_geometry *geom, const float *d_img, float *d_sino,
+                         int32_t batch, void *stream)
+{
+    dect::set_error("");
+    return dect::project(geom, d_img, d_sino, batch, (hipStream_t)stream);
+}
+
+dect_status dect_backproject(const dect_geometry *geom, const float *d_sino, float *d_img,
+                             int32_t batch, void *stream)
+{
+    dect::set_error("");
+    return dect::backproject(geom, d_sino, d_img, batch, (hipStream_t)stream);
+}
+
+dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
+                        const dect_adm_params *params, float *d_x_high, float *d_x_low,
+                        dect_adm_state *state, dect_report *rep, void *stream)
+{
+    dect::set_error("");
+    return dect::adm_tv(geom, d_m_high, d_m_low, params, d_x_high, d_x_low, state, rep,
+                        (hipStream_t)stream);
+}
+
+dect_status dect_adm_state_create(const dect_geometry *geom, dect_adm_state **out)
+{
+    dect::set_error("");
+    return dect::adm_state_create(geom, out);
+}
+
+dect_status dect_adm_state_destroy(dect_adm_state *state)
+{
+    return dect::adm_state_destroy(state);
+}
+
+dect_status dect_pls_decompose(int32_t nx, int32_t ny, const float *d_x_high,
+                               const float *d_x_low, const dect_pls_params *params,
+                               const float *d_edge_w, float *d_u_water, float *d_u_bone,
+                               dect_report *rep, void *stream)
+{
+    dect::set_error("");
+    return dect::pls_decompose(nx, ny, d_x_high, d_x_low, params, d_edge_w, d_u_water, d_u_bone,
+                               rep, (hipStream_t)stream);
+}
+
+dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, double tau,
+                                  double eps, float *d_w, void *stream)
+{
+    dect::set_error("");
+    return dect::pls_edge_weights(nx, ny, d_x, tau, eps, d_w, (hipStream_t)stream);
+}
+
+dect_status dect_count_samples(const dect_geometry *geom, int64_t *out)
+{
+    dect::set_error("");
+    if (!out) return dect::fail(DECT_ERR_INVALID_ARG, "dect_count_samples: out is NULL");
+    dect::GeomTables *t = nullptr;
+    dect_status st = dect::get_tables(geom, &t);
+    if (st != DECT_OK) return st;
+    *out = t->samples;
+    return DECT_OK;
+}
+
+dect_status dect_release_caches(void)
+{
+    (void)hipDeviceSynchronize();
+    dect::release_adm_states();
+    dect::release_tables();
+    return DECT_OK;
+}
+
+const char *dect_last_error(void) { return dect::last_error(); }
+
+const char *dect_version(void) { return "libdect 0.1 (gfx950)"; }
+
+}  // extern "C"

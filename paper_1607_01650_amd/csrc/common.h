@@ -1,0 +1,123 @@
+// Internal declarations shared by the libdect translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dect.h"
+
+namespace dect {
+
+// ---------------------------------------------------------------- errors ---
+void set_error(const std::string &msg);
+dect_status fail(dect_status st, const std::string &msg);
+
+#define DECT_HIP(expr)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::dect::fail(DECT_ERR_HIP, std::string(#expr " failed: ") +            \
+                                                  hipGetErrorString(e_));                 \
+    } while (0)
+
+// ------------------------------------------------------------- geometry ---
+// Joseph line coordinate in 32.32 fixed point: the crossing of ray (v,b)
+// with driving line i (column for x-major rays, row for y-major rays) is at
+// q(i) = (a_fx + k_fx * i) / 2^32 in units of pixels along the other axis.
+// The integer form is exact, so the forward pass (incremental) and the
+// adjoint (direct, in FP64, which holds these integers exactly) agree bit
+// for bit on every interpolation weight.
+struct RayFwd {
+    int64_t a_fx;
+    int64_t k_fx;
+};
+struct RayAdj {  // the same two numbers as doubles (exact: |values| < 2^53)
+    double a;
+    double k;
+};
+// Per (view, 64-bin bundle): union of the valid driving-line ranges of the
+// bundle's x-major lanes [x0, x1] and y-major lanes [y0, y1] (empty: x0 > x1).
+struct Bundle {
+    int32_t x0, x1, y0, y1;
+};
+// Per view: detector-plane projection constants and the bin ranges of the
+// two ray classes (x-major bins [xb0, xb1), y-major bins [yb0, yb1)).
+struct ViewInfo {
+    float ct, st;
+    int32_t xb0, xb1, yb0, yb1;
+    int32_t pad0, pad1;
+};
+
+constexpr int kBundle = 64;   // bins per forward wavefront
+constexpr int kPad = 2;       // zero border of the padded image copies
+
+struct GeomKey {
+    int32_t nx, ny, V, B;
+    double pixel, bin, off, sod, sdd;
+    std::vector<double> angles;
+    int device;
+    bool operator==(const GeomKey &o) const;
+};
+
+// Device-resident tables of one geometry (shared by every batch item).
+struct GeomTables {
+    GeomKey key;
+    int nbundle = 0;
+    RayFwd *fwd = nullptr;     // [V*B]
+    RayAdj *adj = nullptr;     // [V*B]
+    float *len = nullptr;      // [V*B] path length per driving line (pixel/|cos|)
+    Bundle *bundles = nullptr; // [V*nbundle]
+    ViewInfo *views = nullptr; // [V]
+    int64_t samples = 0;       // Joseph samples with q in (-1, n)
+    ~GeomTables();
+};
+
+// Validates the geometry (DECT_ERR_GEOMETRY / DECT_ERR_INVALID_ARG) and
+// returns the cached tables for the current device, building them on first
+// use.
+dect_status get_tables(const dect_geometry *g, GeomTables **out);
+dect_status validate_geometry(const dect_geometry *g);
+void release_tables();
+
+// ----------------------------------------------------------- workspaces ---
+// A growable device buffer owned by the library.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    dect_status ensure(size_t n, bool zero = false);
+    ~DevBuf();
+};
+
+// ------------------------------------------------------------ projector ---
+struct ProjWork {
+    // padded copies [batch][ny+4][nx+4] and transposed [batch][nx+4][ny+4]
+    DevBuf pad, padT, partial, norm;
+};
+
+// img [batch][ny][nx] -> both padded layouts (borders stay zero).
+dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float *padT, int batch,
+                       hipStream_t s);
+// sino[e] = scale * A img[e] from the padded layouts.  norm_partial (may be
+// NULL) receives per-block sums of squares (double) for a later reduction.
+dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
+                       int batch, float scale, double *norm_partial, hipStream_t s);
+int fwd_blocks(const GeomTables &t);
+// img[e] = scale * A^T sino[e]; partial must hold nvg*batch*ny*nx floats when
+// adj_groups() > 1.
+int adj_groups(const GeomTables &t, int batch);
+dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float *partial,
+                       int batch, float scale, hipStream_t s);
+
+dect_status project(const dect_geometry *g, const float *img, float *sino, int batch,
+                    hipStream_t s);
+dect_status backproject(const dect_geometry *g, const float *sino, float *img, int batch,
+                        hipStream_t s);
+
+}  // namespace dect
+
+struct dect_adm_state;  // defined in adm.hip

@@ -1,0 +1,253 @@
+// Host side of the projector: geometry validation, the FP64 per-ray tables
+// (stored as exact 32.32 fixed point), their per-device cache, errors and
+// library-owned device buffers.
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "common.h"
+
+namespace dect {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+dect_status fail(dect_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+const char *last_error() { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------ DevBuf ---
+dect_status DevBuf::ensure(size_t n, bool zero)
+{
+    if (n <= bytes && ptr) return DECT_OK;
+    if (ptr) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    if (n == 0) return DECT_OK;
+    DECT_HIP(hipMalloc(&ptr, n));
+    bytes = n;
+    if (zero) DECT_HIP(hipMemset(ptr, 0, n));
+    return DECT_OK;
+}
+
+DevBuf::~DevBuf()
+{
+    if (ptr) (void)hipFree(ptr);
+}
+
+// ---------------------------------------------------------- geometry ---
+bool GeomKey::operator==(const GeomKey &o) const
+{
+    return nx == o.nx && ny == o.ny && V == o.V && B == o.B && pixel == o.pixel &&
+           bin == o.bin && off == o.off && sod == o.sod && sdd == o.sdd && angles == o.angles &&
+           device == o.device;
+}
+
+GeomTables::~GeomTables()
+{
+    if (fwd) (void)hipFree(fwd);
+    if (adj) (void)hipFree(adj);
+    if (len) (void)hipFree(len);
+    if (bundles) (void)hipFree(bundles);
+    if (views) (void)hipFree(views);
+}
+
+dect_status validate_geometry(const dect_geometry *g)
+{
+    if (!g) return fail(DECT_ERR_INVALID_ARG, "geometry is NULL");
+    if (g->nx <= 0 || g->ny <= 0 || g->n_views <= 0 || g->n_bins <= 0)
+        return fail(DECT_ERR_INVALID_ARG, "geometry sizes must be positive");
+    if (g->nx > 16384 || g->ny > 16384 || g->n_bins > (1 << 20) || g->n_views > (1 << 20))
+        return fail(DECT_ERR_INVALID_ARG, "geometry sizes exceed the supported maximum");
+    if (!(g->pixel_mm > 0.0) || !(g->bin_mm > 0.0) || !std::isfinite(g->pixel_mm) ||
+        !std::isfinite(g->bin_mm) || !std::isfinite(g->det_offset_mm))
+        return fail(DECT_ERR_INVALID_ARG, "pixel and bin sizes must be positive and finite");
+    double hx = 0.5 * g->nx * g->pixel_mm, hy = 0.5 * g->ny * g->pixel_mm;
+    double half_diag = std::sqrt(hx * hx + hy * hy);
+    if (!(g->sod_mm > half_diag) || !std::isfinite(g->sod_mm))
+        return fail(DECT_ERR_GEOMETRY, "source orbit (SOD) must lie outside the image");
+    if (!(g->sdd_mm > g->sod_mm) || !std::isfinite(g->sdd_mm))
+        return fail(DECT_ERR_GEOMETRY, "SDD must exceed SOD");
+    double half_fan = std::atan((0.5 * g->n_bins * g->bin_mm + std::fabs(g->det_offset_mm)) /
+                                g->sdd_mm);
+    if (!(half_fan < 0.25 * M_PI))
+        return fail(DECT_ERR_GEOMETRY, "fan angle must be below 90 degrees");
+    if (g->angles_rad)
+        for (int v = 0; v < g->n_views; ++v)
+            if (!std::isfinite(g->angles_rad[v]))
+                return fail(DECT_ERR_INVALID_ARG, "view angles must be finite");
+    return DECT_OK;
+}
+
+static constexpr double kTwo32 = 4294967296.0;
+
+// floor(x / 2^32) for int64 x (arithmetic shift floors).
+static inline int64_t fx_floor(int64_t x) { return x >> 32; }
+
+// Exact range of lines i in [0, n_line) with floor(q(i)) in [-1, n_q - 1].
+static void valid_range(int64_t a, int64_t k, int n_line, int n_q, int *lo, int *hi)
+{
+    auto ok = [&](int i) {
+        int64_t h = fx_floor(a + k * (int64_t)i);
+        return h >= -1 && h <= n_q - 1;
+    };
+    // q is linear in i: locate the crossing points with a double estimate,
+    // then settle them exactly with integer evaluation.
+    double ad = (double)a / kTwo32, kd = (double)k / kTwo32;
+    int l, h;
+    if (kd == 0.0) {
+        if (ok(0)) { l = 0; h = n_line - 1; }
+        else { l = 1; h = 0; }
+    } else {
+        double t0 = (-1.0 - ad) / kd, t1 = ((double)n_q - ad) / kd;
+        double tmin = std::fmin(t0, t1), tmax = std::fmax(t0, t1);
+        l = (int)std::max(0.0, std::min((double)n_line - 1, std::floor(tmin)));
+        h = (int)std::max(0.0, std::min((double)n_line - 1, std::ceil(tmax)));
+        // widen until the outside is invalid, then shrink to valid ends
+        while (l > 0 && ok(l - 1)) --l;
+        while (h < n_line - 1 && ok(h + 1)) ++h;
+        while (l <= h && !ok(l)) ++l;
+        while (h >= l && !ok(h)) --h;
+    }
+    *lo = l;
+    *hi = h;
+}
+
+static std::mutex g_cache_mu;
+static std::vector<std::unique_ptr<GeomTables>> g_cache;
+
+void release_tables()
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+        if ((*it)->key.device == dev) it = g_cache.erase(it);
+        else ++it;
+    }
+}
+
+dect_status get_tables(const dect_geometry *g, GeomTables **out)
+{
+    dect_status st = validate_geometry(g);
+    if (st != DECT_OK) return st;
+    int dev = 0;
+    DECT_HIP(hipGetDevice(&dev));
+    GeomKey key{g->nx, g->ny, g->n_views, g->n_bins, g->pixel_mm, g->bin_mm,
+                g->det_offset_mm, g->sod_mm, g->sdd_mm, {}, dev};
+    if (g->angles_rad) key.angles.assign(g->angles_rad, g->angles_rad + g->n_views);
+
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto &t : g_cache)
+        if (t->key == key) {
+            *out = t.get();
+            return DECT_OK;
+        }
+
+    const int nx = g->nx, ny = g->ny, V = g->n_views, B = g->n_bins;
+    const double dl = g->pixel_mm, R = g->sod_mm, D = g->sdd_mm;
+    const int nb = (B + kBundle - 1) / kBundle;
+    std::vector<RayFwd> fwd((size_t)V * B);
+    std::vector<RayAdj> adj((size_t)V * B);
+    std::vector<float> len((size_t)V * B);
+    std::vector<Bundle> bun((size_t)V * nb);
+    std::vector<ViewInfo> views(V);
+    int64_t samples = 0;
+
+    for (int v = 0; v < V; ++v) {
+        double th = g->angles_rad ? g->angles_rad[v] : 2.0 * M_PI * v / V;
+        double ct = std::cos(th), st = std::sin(th);
+        double sx = R * ct, sy = R * st;
+        std::vector<int> major(B), lo(B), hi(B);
+        for (int b = 0; b < B; ++b) {
+            double u = (b - (B - 1) / 2.0) * g->bin_mm + g->det_offset_mm;
+            double px = -(D - R) * ct - u * st, py = -(D - R) * st + u * ct;
+            double dx = px - sx, dy = py - sy;
+            double ln = std::sqrt(dx * dx + dy * dy);
+            bool xm = std::fabs(dx) >= std::fabs(dy);
+            double a, k, L;
+            if (xm) {  // q = row coordinate on column c
+                k = dy / dx;
+                double x0 = (0 - (nx - 1) / 2.0) * dl;
+                a = (sy + (x0 - sx) * k) / dl + (ny - 1) / 2.0;
+                L = dl * ln / std::fabs(dx);
+            } else {   // q = column coordinate on row r
+                k = dx / dy;
+                double y0 = (0 - (ny - 1) / 2.0) * dl;
+                a = (sx + (y0 - sy) * k) / dl + (nx - 1) / 2.0;
+                L = dl * ln / std::fabs(dy);
+            }
+            if (!(std::fabs(a) < 1e6)) a = std::copysign(1e6, a);  // ray far outside
+            int64_t afx = (int64_t)std::llround(a * kTwo32);
+            int64_t kfx = (int64_t)std::llround(k * kTwo32);
+            size_t i = (size_t)v * B + b;
+            fwd[i] = {afx, kfx};
+            adj[i] = {(double)afx / kTwo32, (double)kfx / kTwo32};
+            len[i] = xm ? (float)L : -(float)L;  // sign marks the class
+            major[b] = xm;
+            valid_range(afx, kfx, xm ? nx : ny, xm ? ny : nx, &lo[b], &hi[b]);
+            // samples with q strictly inside (-1, n): exclude q == -1 exactly
+            for (int c = lo[b]; c <= hi[b]; ++c) {
+                int64_t q = afx + kfx * (int64_t)c;
+                if (q != -(int64_t(1) << 32)) ++samples;
+            }
+        }
+        // class ranges: at most one switch between x-major and y-major bins
+        int switches = 0;
+        for (int b = 1; b < B; ++b) switches += major[b] != major[b - 1];
+        if (switches > 1)
+            return fail(DECT_ERR_GEOMETRY, "ray classes are not contiguous within a view");
+        ViewInfo vi{(float)ct, (float)st, 0, 0, 0, 0, 0, 0};
+        int first_x = -1, last_x = -2, first_y = -1, last_y = -2;
+        for (int b = 0; b < B; ++b) {
+            if (major[b]) { if (first_x < 0) first_x = b; last_x = b; }
+            else { if (first_y < 0) first_y = b; last_y = b; }
+        }
+        vi.xb0 = first_x < 0 ? 0 : first_x;
+        vi.xb1 = first_x < 0 ? 0 : last_x + 1;
+        vi.yb0 = first_y < 0 ? 0 : first_y;
+        vi.yb1 = first_y < 0 ? 0 : last_y + 1;
+        views[v] = vi;
+        for (int j = 0; j < nb; ++j) {
+            Bundle bb{1 << 30, -(1 << 30), 1 << 30, -(1 << 30)};
+            for (int b = j * kBundle; b < std::min(B, (j + 1) * kBundle); ++b) {
+                if (lo[b] > hi[b]) continue;
+                if (major[b]) { bb.x0 = std::min(bb.x0, lo[b]); bb.x1 = std::max(bb.x1, hi[b]); }
+                else { bb.y0 = std::min(bb.y0, lo[b]); bb.y1 = std::max(bb.y1, hi[b]); }
+            }
+            if (bb.x0 > bb.x1) { bb.x0 = 1; bb.x1 = 0; }
+            if (bb.y0 > bb.y1) { bb.y0 = 1; bb.y1 = 0; }
+            bun[(size_t)v * nb + j] = bb;
+        }
+    }
+
+    auto t = std::make_unique<GeomTables>();
+    t->key = key;
+    t->nbundle = nb;
+    t->samples = samples;
+    DECT_HIP(hipMalloc(&t->fwd, fwd.size() * sizeof(RayFwd)));
+    DECT_HIP(hipMalloc(&t->adj, adj.size() * sizeof(RayAdj)));
+    DECT_HIP(hipMalloc(&t->len, len.size() * sizeof(float)));
+    DECT_HIP(hipMalloc(&t->bundles, bun.size() * sizeof(Bundle)));
+    DECT_HIP(hipMalloc(&t->views, views.size() * sizeof(ViewInfo)));
+    DECT_HIP(hipMemcpy(t->fwd, fwd.data(), fwd.size() * sizeof(RayFwd), hipMemcpyHostToDevice));
+    DECT_HIP(hipMemcpy(t->adj, adj.data(), adj.size() * sizeof(RayAdj), hipMemcpyHostToDevice));
+    DECT_HIP(hipMemcpy(t->len, len.data(), len.size() * sizeof(float), hipMemcpyHostToDevice));
+    DECT_HIP(hipMemcpy(t->bundles, bun.data(), bun.size() * sizeof(Bundle),
+                       hipMemcpyHostToDevice));
+    DECT_HIP(hipMemcpy(t->views, views.data(), views.size() * sizeof(ViewInfo),
+                       hipMemcpyHostToDevice));
+    *out = t.get();
+    g_cache.push_back(std::move(t));
+    return DECT_OK;
+}
+
+}  // namespace dect

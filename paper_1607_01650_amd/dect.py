@@ -1,0 +1,319 @@
+"""Python binding of libdect: argument marshalling only.
+
+Every computation runs in the HIP kernels of libdect.so; torch supplies device
+memory and the current stream.  Importing works without a GPU, but every call
+needs the built library and a ROCm device and raises otherwise -- there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import configs as C
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdect.so")
+
+DECT_OK = 0
+DECT_ERR_INVALID_ARG = 1
+DECT_ERR_GEOMETRY = 2
+DECT_ERR_HIP = 3
+DECT_ERR_NONFINITE = 4
+DECT_WARN_MAXITER = 5
+DECT_WARM_START = 1
+
+_STATUS = {0: "OK", 1: "INVALID_ARG", 2: "GEOMETRY", 3: "HIP", 4: "NONFINITE", 5: "WARN_MAXITER"}
+
+
+class DectError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libdect {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dect_geometry(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("pixel_mm", ct.c_double),
+                ("n_views", ct.c_int32), ("angles_rad", ct.POINTER(ct.c_double)),
+                ("n_bins", ct.c_int32), ("bin_mm", ct.c_double), ("det_offset_mm", ct.c_double),
+                ("sod_mm", ct.c_double), ("sdd_mm", ct.c_double)]
+
+
+class dect_adm_params(ct.Structure):
+    _fields_ = [("mu", ct.c_double), ("rho", ct.c_double), ("xi", ct.c_double),
+                ("beta_high", ct.c_double), ("beta_low", ct.c_double), ("max_iter", ct.c_int32),
+                ("tol", ct.c_double), ("flags", ct.c_int32), ("log", ct.POINTER(ct.c_double))]
+
+
+class dect_pls_params(ct.Structure):
+    _fields_ = [("eta_water_high", ct.c_double), ("eta_bone_high", ct.c_double),
+                ("eta_water_low", ct.c_double), ("eta_bone_low", ct.c_double),
+                ("gamma", ct.c_double), ("edge_eps", ct.c_double), ("edge_tau", ct.c_double),
+                ("max_iter", ct.c_int32), ("tol", ct.c_double)]
+
+
+class dect_report(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("objective", ct.c_double), ("rel_change", ct.c_double),
+                ("pcg_residual", ct.c_double), ("status", ct.c_int32)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/dect.h
+_P = ct.POINTER
+SIGNATURES = {
+    "dect_project": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, ct.c_int32,
+                                ct.c_void_p]),
+    "dect_backproject": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, ct.c_int32,
+                                    ct.c_void_p]),
+    "dect_adm_tv": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, _P(dect_adm_params),
+                               ct.c_void_p, ct.c_void_p, ct.c_void_p, _P(dect_report),
+                               ct.c_void_p]),
+    "dect_adm_state_create": (ct.c_int, [_P(dect_geometry), _P(ct.c_void_p)]),
+    "dect_adm_state_destroy": (ct.c_int, [ct.c_void_p]),
+    "dect_pls_decompose": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                      _P(dect_pls_params), ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                      _P(dect_report), ct.c_void_p]),
+    "dect_pls_edge_weights": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_double,
+                                         ct.c_double, ct.c_void_p, ct.c_void_p]),
+    "dect_count_samples": (ct.c_int, [_P(dect_geometry), _P(ct.c_int64)]),
+    "dect_release_caches": (ct.c_int, []),
+    "dect_last_error": (ct.c_char_p, []),
+    "dect_version": (ct.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdect.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libdect.so not found at {LIB_PATH}: run __graft_entry__.build() "
+                               "or python -m paper_1607_01650_amd.build")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != DECT_OK:
+        msg = lib().dect_last_error().decode(errors="replace")
+        raise DectError(st, f"{what}: {msg}")
+
+
+class GeomArg:
+    """A dect_geometry struct plus the angle array it points to."""
+
+    def __init__(self, g: C.Geometry):
+        self.geom = g
+        self._angles = None
+        ap = None
+        if g.angles_rad is not None:
+            self._angles = np.ascontiguousarray(g.angles_rad, dtype=np.float64)
+            ap = self._angles.ctypes.data_as(ct.POINTER(ct.c_double))
+        self.s = dect_geometry(g.nx, g.ny, g.pixel_mm, g.n_views, ap, g.n_bins, g.bin_mm,
+                               g.det_offset_mm, g.sod_mm, g.sdd_mm)
+
+    @property
+    def ref(self):
+        return ct.byref(self.s)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name: str, shape_tail: Tuple[int, ...]):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a ROCm device tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., {shape_tail})")
+    return t
+
+
+def _batch(t, tail: int) -> int:
+    n = 1
+    for s in t.shape[:-tail]:
+        n *= int(s)
+    return n
+
+
+def count_samples(geom: C.Geometry) -> int:
+    out = ct.c_int64(0)
+    _check(lib().dect_count_samples(GeomArg(geom).ref, ct.byref(out)), "dect_count_samples")
+    return int(out.value)
+
+
+def project(img, geom: C.Geometry, out=None):
+    """A img for images [..., ny, nx] -> sinograms [..., V, B] (dect_project)."""
+    torch = _torch()
+    _dev(img, "img", (geom.ny, geom.nx))
+    lead = tuple(img.shape[:-2])
+    if out is None:
+        out = torch.empty(lead + (geom.n_views, geom.n_bins), device=img.device,
+                          dtype=torch.float32)
+    _dev(out, "out", (geom.n_views, geom.n_bins))
+    b = _batch(img, 2)
+    if b == 0:
+        return out
+    _check(lib().dect_project(GeomArg(geom).ref, ct.c_void_p(img.data_ptr()),
+                              ct.c_void_p(out.data_ptr()), b, _stream()), "dect_project")
+    return out
+
+
+def backproject(sino, geom: C.Geometry, out=None):
+    """A^T sino for sinograms [..., V, B] -> images [..., ny, nx] (dect_backproject)."""
+    torch = _torch()
+    _dev(sino, "sino", (geom.n_views, geom.n_bins))
+    lead = tuple(sino.shape[:-2])
+    if out is None:
+        out = torch.empty(lead + (geom.ny, geom.nx), device=sino.device, dtype=torch.float32)
+    _dev(out, "out", (geom.ny, geom.nx))
+    b = _batch(sino, 2)
+    if b == 0:
+        return out
+    _check(lib().dect_backproject(GeomArg(geom).ref, ct.c_void_p(sino.data_ptr()),
+                                  ct.c_void_p(out.data_ptr()), b, _stream()), "dect_backproject")
+    return out
+
+
+class AdmState:
+    """Resumable ADM state (dect_adm_state) for one geometry."""
+
+    def __init__(self, geom: C.Geometry):
+        self.geom = geom
+        h = ct.c_void_p(None)
+        _check(lib().dect_adm_state_create(GeomArg(geom).ref, ct.byref(h)),
+               "dect_adm_state_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().dect_adm_state_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AdmResult:
+    def __init__(self, x_high, x_low, report, log):
+        self.x_high, self.x_low, self.report, self.log = x_high, x_low, report, log
+
+    @property
+    def J(self):
+        """Objective of Eq. 4 per logged iteration, [rows][2] (high, low)."""
+        return None if self.log is None else self.log[:, 0:2]
+
+    @property
+    def alpha(self):
+        return None if self.log is None else self.log[:, 2:4]
+
+
+def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
+           state: Optional[AdmState] = None, want_log: bool = False,
+           out: Optional[Tuple] = None) -> AdmResult:
+    """ADM-TV reconstruction of both energies (dect_adm_tv).
+
+    m_high/m_low: [V, B] device sinograms.  x0: optional (x_high, x_low) warm
+    start.  Returns x_high, x_low [ny, nx] and, with want_log, the per-iteration
+    log [max_iter+1, 4] = (J_high, J_low, alpha_high, alpha_low).
+    """
+    torch = _torch()
+    _dev(m_high, "m_high", (geom.n_views, geom.n_bins))
+    _dev(m_low, "m_low", (geom.n_views, geom.n_bins))
+    flags = 0
+    if out is not None:
+        xh, xl = out
+    else:
+        xh = torch.empty((geom.ny, geom.nx), device=m_high.device, dtype=torch.float32)
+        xl = torch.empty_like(xh)
+    if x0 is not None:
+        xh.copy_(x0[0])
+        xl.copy_(x0[1])
+        flags |= DECT_WARM_START
+    _dev(xh, "x_high", (geom.ny, geom.nx))
+    _dev(xl, "x_low", (geom.ny, geom.nx))
+    log = None
+    logp = None
+    if want_log:
+        log = np.zeros((p.max_iter + 1, 4))
+        logp = log.ctypes.data_as(ct.POINTER(ct.c_double))
+    prm = dect_adm_params(p.mu, p.rho, p.xi, p.beta_high, p.beta_low, p.max_iter, p.tol, flags,
+                          logp)
+    rep = dect_report()
+    st = lib().dect_adm_tv(GeomArg(geom).ref, ct.c_void_p(m_high.data_ptr()),
+                           ct.c_void_p(m_low.data_ptr()), ct.byref(prm),
+                           ct.c_void_p(xh.data_ptr()), ct.c_void_p(xl.data_ptr()),
+                           state.handle if state is not None else None,
+                           ct.byref(rep) if want_log else None, _stream())
+    _check(st, "dect_adm_tv")
+    return AdmResult(xh, xl, rep if want_log else None, log)
+
+
+def pls_params(p: C.PlsParams) -> dect_pls_params:
+    return dect_pls_params(p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low,
+                           p.gamma, p.edge_eps, p.edge_tau, p.max_iter, p.tol)
+
+
+def pls_decompose(x_high, x_low, p: C.PlsParams, edge_w=None, report: bool = True):
+    """PLS decomposition (dect_pls_decompose) -> (u_water, u_bone, report)."""
+    torch = _torch()
+    ny, nx = x_high.shape[-2:]
+    _dev(x_high, "x_high", (ny, nx))
+    _dev(x_low, "x_low", (ny, nx))
+    if edge_w is not None:
+        _dev(edge_w, "edge_w", (2, ny, nx))
+    u1 = torch.empty((ny, nx), device=x_high.device, dtype=torch.float32)
+    u2 = torch.empty_like(u1)
+    rep = dect_report()
+    prm = pls_params(p)
+    st = lib().dect_pls_decompose(nx, ny, ct.c_void_p(x_high.data_ptr()),
+                                  ct.c_void_p(x_low.data_ptr()), ct.byref(prm),
+                                  ct.c_void_p(edge_w.data_ptr()) if edge_w is not None else None,
+                                  ct.c_void_p(u1.data_ptr()), ct.c_void_p(u2.data_ptr()),
+                                  ct.byref(rep) if report else None, _stream())
+    if st not in (DECT_OK, DECT_WARN_MAXITER):
+        _check(st, "dect_pls_decompose")
+    return u1, u2, (rep if report else None)
+
+
+def pls_edge_weights(x, tau: float, eps: float):
+    """Edge weights [2, ny, nx] (right pairs, down pairs) from a Prewitt map of x."""
+    torch = _torch()
+    ny, nx = x.shape[-2:]
+    _dev(x, "x", (ny, nx))
+    w = torch.empty((2, ny, nx), device=x.device, dtype=torch.float32)
+    _check(lib().dect_pls_edge_weights(nx, ny, ct.c_void_p(x.data_ptr()), float(tau), float(eps),
+                                       ct.c_void_p(w.data_ptr()), _stream()),
+           "dect_pls_edge_weights")
+    return w
+
+
+def release_caches():
+    lib().dect_release_caches()
+
+
+def version() -> str:
+    return lib().dect_version().decode()

@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports what include/dect.h declares; host-side
+validation rejects bad arguments before any GPU work (runs without a GPU)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_1607_01650_amd import configs as C
+from paper_1607_01650_amd import dect
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "dect.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dect_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dect.LIB_PATH):
+        pytest.skip("libdect.so not built")
+    return dect.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(dect.SIGNATURES), "binding and header disagree"
+
+
+def test_version(lib):
+    assert "gfx950" in dect.version()
+
+
+
+def test_geometry_validation(lib):
+    import dataclasses
+    cases = [
+        (dataclasses.replace(C.TINY, sod_mm=60.0), dect.DECT_ERR_GEOMETRY),   # source inside
+        (dataclasses.replace(C.TINY, sdd_mm=400.0), dect.DECT_ERR_GEOMETRY),  # SDD < SOD
+        (dataclasses.replace(C.TINY, n_bins=4000), dect.DECT_ERR_GEOMETRY),   # fan >= 90 deg
+        (dataclasses.replace(C.TINY, nx=0), dect.DECT_ERR_INVALID_ARG),
+        (dataclasses.replace(C.TINY, pixel_mm=-1.0), dect.DECT_ERR_INVALID_ARG),
+        (dataclasses.replace(C.TINY, angles_rad=[float("nan")] * 60), dect.DECT_ERR_INVALID_ARG),
+    ]
+    buf = ct.c_void_p(16)  # never dereferenced: validation fails first
+    for g, want in cases:
+        st = lib.dect_project(dect.GeomArg(g).ref, buf, buf, 1, None)
+        assert st == want, (g, st)
+        assert lib.dect_last_error().decode() != ""
+    assert lib.dect_project(None, buf, buf, 1, None) == dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_project(dect.GeomArg(C.TINY).ref, None, buf, 1, None) == dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_backproject(dect.GeomArg(C.TINY).ref, buf, buf, 0, None) == dect.DECT_ERR_INVALID_ARG
+
+
+def test_parameter_validation(lib):
+    buf = ct.c_void_p(16)
+    g = dect.GeomArg(C.TINY)
+    bad = dect.dect_adm_params(-1.0, 1.0, 1.0, 1.0, 1.0, 5, 0.0, 0, None)
+    assert lib.dect_adm_tv(g.ref, buf, buf, ct.byref(bad), buf, buf, None, None, None) == \
+        dect.DECT_ERR_INVALID_ARG
+    p = dect.pls_params(C.PlsParams())
+    sing = dect.dect_pls_params(1.0, 2.0, 2.0, 4.0, 1.0, 0.1, 0.25, 10, 1e-6)  # det D = 0
+    assert lib.dect_pls_decompose(8, 8, buf, buf, ct.byref(sing), None, buf, buf, None, None) == \
+        dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_pls_decompose(0, 8, buf, buf, ct.byref(p), None, buf, buf, None, None) == \
+        dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_pls_edge_weights(8, 8, buf, -1.0, 0.1, buf, None) == dect.DECT_ERR_INVALID_ARG
+
+
+def test_calls_fail_loudly_without_a_device(lib):
+    """No CPU fallback: the binding requires device tensors."""
+    import numpy as np
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        dect.project(torch.zeros((C.TINY.ny, C.TINY.nx)), C.TINY)
