@@ -420,7 +420,11 @@ struct dect_adm_state {
     bool started = false;
     double mu = 0, rho = 0, xi = 0, bh = 1, bl = 1;
     int nvg = 1, nb_tv = 0, nb_fwd = 0, nbi = 0, nbs = 0, nb_img = 0;
-    dect::DevBuf f, h, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, sc, logbuf, p_tvo;
+    dect::DevBuf f, h, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, adjcnt, sc, logbuf,
+        p_tvo;
+    void *graph_log = nullptr;
+    size_t graph_log_bytes = 0;
+    double graph_tol = -1.0;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;
     int parity = 0;  // lambda/z buffer holding the current values
@@ -455,7 +459,8 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
         (st = S->p_fwd.ensure((size_t)2 * S->nb_fwd * 8)) ||
         (st = S->p_rr.ensure((size_t)2 * S->nbs * 8)) ||
         (st = S->p_tvo.ensure((size_t)2 * S->nbi * 8)) ||
-        (st = S->adjpart.ensure((size_t)std::max(1, S->nvg) * 2 * N * 4)) ||
+        (st = S->adjpart.ensure(std::max<size_t>(1, adj_partial_floats(t, 2)) * 4)) ||
+        (st = S->adjcnt.ensure(adj_counters(t, 2) * sizeof(int), true)) ||
         (st = S->sc.ensure(2 * sizeof(AdmScalars))))
         return st;
     return DECT_OK;
@@ -493,8 +498,8 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_rr.ptr, S->nbs, 1,
                        tol);
     DECT_HIP(hipGetLastError());
-    return launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr, 2,
-                      (float)S->mu, s);
+    return launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr,
+                      (int *)S->adjcnt.ptr, 2, (float)S->mu, s);
 }
 
 static dect_status adm_start(dect_adm_state *S, const dect_geometry *g, const float *mh,
@@ -531,7 +536,7 @@ static dect_status adm_start(dect_adm_state *S, const dect_geometry *g, const fl
                        (const double *)S->p_rr.ptr, S->nbs, 0, 0.0);
     DECT_HIP(hipGetLastError());
     if ((st = launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr,
-                         2, (float)S->mu, s)))
+                         (int *)S->adjcnt.ptr, 2, (float)S->mu, s)))
         return st;
     S->started = true;
     return DECT_OK;
@@ -603,7 +608,9 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     const size_t N = (size_t)g->nx * g->ny;
     const int K = P->max_iter;
     const size_t log_rows = (size_t)K + 1;
-    if ((st = S->logbuf.ensure(log_rows * 4 * sizeof(double)))) return st;
+    // the device log keeps at least 4096 rows so that calls of different
+    // lengths reuse it (and the captured graph that points at it)
+    if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, 4096) * 4 * sizeof(double)))) return st;
     if (!S->started) {
         const bool warm = (P->flags & DECT_WARM_START) != 0;
         if ((st = adm_start(S, g, mh, ml, P, warm ? xh : nullptr, warm ? xl : nullptr, s)))
@@ -611,8 +618,15 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     }
     hipLaunchKernelGGL(k_set_log_base, dim3(1), dim3(64), 0, s, (AdmScalars *)S->sc.ptr);
     DECT_HIP(hipGetLastError());
-    // the log buffer and tol are baked into the graph's kernel arguments
-    if (K >= 2 && (st = build_graph(S, P->tol))) return st;
+    // the log buffer and tol are baked into the graph's kernel arguments:
+    // rebuild only when they change
+    if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
+                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol)) {
+        if ((st = build_graph(S, P->tol))) return st;
+        S->graph_log = S->logbuf.ptr;
+        S->graph_log_bytes = S->logbuf.bytes;
+        S->graph_tol = P->tol;
+    }
     int k = 0;
     if (S->parity == 1 && K > 0) {  // realign so the graph starts on parity 0
         if ((st = launch_iter(S, 1, P->tol, s))) return st;

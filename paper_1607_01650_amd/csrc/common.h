@@ -95,7 +95,8 @@ struct DevBuf {
 
 // ------------------------------------------------------------ projector ---
 struct ProjWork {
-    // padded copies [batch][ny+4][nx+4] and transposed [batch][nx+4][ny+4]
+    // padded copies [batch][ny+4][nx+4] and transposed [batch][nx+4][ny+4];
+    // adjoint view-group partial tiles and their completion counters
     DevBuf pad, padT, partial, norm;
 };
 
@@ -107,11 +108,14 @@ dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float 
 dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
                        int batch, float scale, double *norm_partial, hipStream_t s);
 int fwd_blocks(const GeomTables &t);
-// img[e] = scale * A^T sino[e]; partial must hold nvg*batch*ny*nx floats when
-// adj_groups() > 1.
+// img[e] = scale * A^T sino[e].  With several view groups (adj_groups > 1)
+// partial holds adj_partial_floats() floats and counters adj_counters() ints
+// that must be zero before the first launch (the kernel leaves them zero).
 int adj_groups(const GeomTables &t, int batch);
+size_t adj_partial_floats(const GeomTables &t, int batch);
+size_t adj_counters(const GeomTables &t, int batch);
 dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float *partial,
-                       int batch, float scale, hipStream_t s);
+                       int *counters, int batch, float scale, hipStream_t s);
 
 dect_status project(const dect_geometry *g, const float *img, float *sino, int batch,
                     hipStream_t s);

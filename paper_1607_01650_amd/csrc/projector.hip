@@ -156,9 +156,11 @@ __global__ __launch_bounds__(256) void k_adj(const float *__restrict__ sino,
                                              const float *__restrict__ len,
                                              const ViewInfo *__restrict__ views, AdjGeo geo,
                                              int nx, int ny, int V, int B, int ntx, int nvg,
-                                             float *__restrict__ out, float scale)
+                                             float *__restrict__ out, float *__restrict__ part,
+                                             int *__restrict__ counters, float scale)
 {
     __shared__ float acc[4][kTile * kTileLd];
+    __shared__ int is_last;
     const int e = blockIdx.z, g = blockIdx.y;
     const int tile = blockIdx.x;
     const int tr0 = (tile / ntx) * kTile, tc0 = (tile % ntx) * kTile;
@@ -236,31 +238,47 @@ __global__ __launch_bounds__(256) void k_adj(const float *__restrict__ sino,
         }
     }
     __syncthreads();
-    // sum the four wave accumulators in order and write the tile
     const size_t plane = (size_t)nx * ny;
-    float *dst = out + ((size_t)g * gridDim.z + e) * plane;
+    const int ntiles = gridDim.x;
+    float *dst = out + (size_t)e * plane;
+    if (nvg == 1) {  // sum the four wave accumulators in order and write the tile
+        for (int i = threadIdx.x; i < kTile * kTile; i += 256) {
+            int rr = i / kTile, cc = i % kTile;
+            int r = tr0 + rr, c = tc0 + cc;
+            if (r < ny && c < nx) {
+                int o = rr * kTileLd + cc;
+                float sum = ((acc[0][o] + acc[1][o]) + acc[2][o]) + acc[3][o];
+                dst[(size_t)r * nx + c] = sum * scale;
+            }
+        }
+        return;
+    }
+    // several view groups: park this group's tile, and let the last group to
+    // finish sum all of them in group order (deterministic) and write it
+    float *tiles = part + ((size_t)e * ntiles + tile) * nvg * (kTile * kTile);
+    for (int i = threadIdx.x; i < kTile * kTile; i += 256) {
+        int o = (i / kTile) * kTileLd + i % kTile;
+        tiles[(size_t)g * (kTile * kTile) + i] = ((acc[0][o] + acc[1][o]) + acc[2][o]) + acc[3][o];
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int prev = atomicAdd(&counters[e * ntiles + tile], 1);
+        is_last = prev == nvg - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
     for (int i = threadIdx.x; i < kTile * kTile; i += 256) {
         int rr = i / kTile, cc = i % kTile;
         int r = tr0 + rr, c = tc0 + cc;
         if (r < ny && c < nx) {
-            int o = rr * kTileLd + cc;
-            float s = ((acc[0][o] + acc[1][o]) + acc[2][o]) + acc[3][o];
-            dst[(size_t)r * nx + c] = s * scale;
+            float sum = 0.f;
+            for (int q = 0; q < nvg; ++q) sum += tiles[(size_t)q * (kTile * kTile) + i];
+            dst[(size_t)r * nx + c] = sum * scale;
         }
     }
-}
-
-// Sum view-group partials [nvg][batch][N] in order: out[e] = sum_g part[g][e].
-__global__ __launch_bounds__(256) void k_sum_groups(const float *__restrict__ part,
-                                                    float *__restrict__ out, int nvg, int batch,
-                                                    size_t plane, float scale)
-{
-    const int e = blockIdx.y;
-    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= plane) return;
-    float s = 0.f;
-    for (int g = 0; g < nvg; ++g) s += part[((size_t)g * batch + e) * plane + i];
-    out[(size_t)e * plane + i] = s * scale;
+    if (threadIdx.x == 0) counters[e * ntiles + tile] = 0;  // ready for the next launch
 }
 
 }  // namespace
@@ -303,8 +321,21 @@ int adj_groups(const GeomTables &t, int batch)
     return std::max(1, std::min(want, cap));
 }
 
+size_t adj_partial_floats(const GeomTables &t, int batch)
+{
+    const int tiles = ((t.key.nx + kTile - 1) / kTile) * ((t.key.ny + kTile - 1) / kTile);
+    const int nvg = adj_groups(t, batch);
+    return nvg > 1 ? (size_t)batch * tiles * nvg * kTile * kTile : 0;
+}
+
+size_t adj_counters(const GeomTables &t, int batch)
+{
+    const int tiles = ((t.key.nx + kTile - 1) / kTile) * ((t.key.ny + kTile - 1) / kTile);
+    return (size_t)batch * tiles;
+}
+
 dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float *partial,
-                       int batch, float scale, hipStream_t s)
+                       int *counters, int batch, float scale, hipStream_t s)
 {
     const GeomKey &k = t.key;
     const int ntx = (k.nx + kTile - 1) / kTile, nty = (k.ny + kTile - 1) / kTile;
@@ -319,31 +350,25 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
     geo.yoff = (float)((k.ny - 1) / 2.0 * k.pixel);
     geo.margin = 0.5f;
     dim3 grid(ntx * nty, nvg, batch);
-    float *dst = nvg > 1 ? partial : img;
     hipLaunchKernelGGL(k_adj, grid, dim3(256), 0, s, sino, t.adj, t.len, t.views, geo, k.nx,
-                       k.ny, k.V, k.B, ntx, nvg, dst, nvg > 1 ? 1.0f : scale);
+                       k.ny, k.V, k.B, ntx, nvg, img, partial, counters, scale);
     DECT_HIP(hipGetLastError());
-    if (nvg > 1) {
-        size_t plane = (size_t)k.nx * k.ny;
-        dim3 g2((unsigned)((plane + 255) / 256), batch);
-        hipLaunchKernelGGL(k_sum_groups, g2, dim3(256), 0, s, partial, img, nvg, batch, plane,
-                           scale);
-        DECT_HIP(hipGetLastError());
-    }
     return DECT_OK;
 }
 
 // ----------------------------------------------------- plain entry points ---
 static std::mutex g_ws_mu;
-static std::vector<std::pair<int, std::unique_ptr<ProjWork>>> g_ws;
+static std::vector<std::pair<std::pair<int, hipStream_t>, std::unique_ptr<ProjWork>>> g_ws;
 
-static ProjWork *workspace()
+// One workspace per (device, stream): calls on different streams never share
+// scratch memory.
+static ProjWork *workspace(hipStream_t s)
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
     for (auto &p : g_ws)
-        if (p.first == dev) return p.second.get();
-    g_ws.emplace_back(dev, std::make_unique<ProjWork>());
+        if (p.first.first == dev && p.first.second == s) return p.second.get();
+    g_ws.emplace_back(std::make_pair(dev, s), std::make_unique<ProjWork>());
     return g_ws.back().second.get();
 }
 
@@ -356,7 +381,7 @@ dect_status project(const dect_geometry *g, const float *img, float *sino, int b
     dect_status st = get_tables(g, &t);
     if (st != DECT_OK) return st;
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    ProjWork *w = workspace();
+    ProjWork *w = workspace(s);
     const size_t padn = (size_t)(g->nx + 2 * kPad) * (g->ny + 2 * kPad) * batch * sizeof(float);
     // the padded copies are reused across calls and geometries; k_pad writes
     // them whole, border included
@@ -380,16 +405,15 @@ dect_status backproject(const dect_geometry *g, const float *sino, float *img, i
     dect_status st = get_tables(g, &t);
     if (st != DECT_OK) return st;
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    ProjWork *w = workspace();
-    const int nvg = adj_groups(*t, batch);
-    if (nvg > 1) {
-        size_t need = (size_t)nvg * batch * g->nx * g->ny * sizeof(float);
-        if (w->partial.bytes < need) {
-            DECT_HIP(hipStreamSynchronize(s));
-            if ((st = w->partial.ensure(need)) != DECT_OK) return st;
-        }
+    ProjWork *w = workspace(s);
+    const size_t need = adj_partial_floats(*t, batch) * sizeof(float);
+    const size_t ncnt = adj_counters(*t, batch) * sizeof(int);
+    if (w->partial.bytes < need || w->norm.bytes < ncnt) {
+        DECT_HIP(hipStreamSynchronize(s));
+        if ((st = w->partial.ensure(need)) != DECT_OK) return st;
+        if ((st = w->norm.ensure(ncnt, true)) != DECT_OK) return st;  // counters start at zero
     }
-    return launch_adj(*t, sino, img, (float *)w->partial.ptr, batch, 1.0f, s);
+    return launch_adj(*t, sino, img, (float *)w->partial.ptr, (int *)w->norm.ptr, batch, 1.0f, s);
 }
 
 }  // namespace dect

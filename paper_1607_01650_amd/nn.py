@@ -1,0 +1,357 @@
+"""U-Net warm start built on the BF16 MFMA kernels of libdect (dect_nn_*).
+
+Network (4 levels, channels 32/48/64/96, two 3x3 convolutions per level,
+2x2 max pooling, 2x2 stride-2 transposed convolutions, skip concatenation,
+~0.49 M parameters): maps the early ADM-TV iterate of both energies (2
+channels, zero-padded to 8) to a residual that is added to it, predicting a
+late iterate.  Activations and weights are BF16 (NHWC), accumulation FP32,
+master weights and Adam moments FP32.  Forward and backward are explicit
+calls into the kernels; torch only holds device memory.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import dect
+
+CH = (32, 48, 64, 96)
+IN_CH = 8      # 2 image channels, zero-padded to the kernels' multiple of 8
+OUT_CH = 8     # output channels computed (the first 2 are used)
+
+_nn_ready = False
+
+
+def _lib():
+    global _nn_ready
+    L = dect.lib()
+    if not _nn_ready:
+        P, vp, i32, d, sz = ct.POINTER, ct.c_void_p, ct.c_int32, ct.c_double, ct.c_size_t
+        sig = {
+            "dect_nn_conv_fwd": [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, vp],
+            "dect_nn_weight_flip": [vp, vp, i32, i32, i32, vp],
+            "dect_nn_conv_wgrad": [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, sz, vp],
+            "dect_nn_relu_bwd": [vp, vp, vp, sz, vp],
+            "dect_nn_pool": [vp, vp, vp, i32, i32, i32, i32, i32, vp],
+            "dect_nn_shuffle": [vp, vp, i32, i32, i32, i32, i32, vp],
+            "dect_nn_concat": [vp, vp, vp, sz, i32, i32, i32, vp],
+            "dect_nn_add": [vp, vp, vp, sz, vp],
+            "dect_nn_convert": [vp, vp, sz, i32, vp],
+            "dect_nn_adam": [vp, vp, vp, vp, vp, sz, d, d, d, d, i32, d, vp],
+            "dect_nn_mse": [vp, vp, vp, vp, sz, i32, i32, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ct.c_int
+        L.dect_nn_wgrad_workspace.argtypes = [i32] * 6
+        L.dect_nn_wgrad_workspace.restype = sz
+        L.dect_nn_mse_partials.argtypes = [sz, i32]
+        L.dect_nn_mse_partials.restype = sz
+        L.dect_nn_last_error.restype = ct.c_char_p
+        _nn_ready = True
+    return L
+
+
+def _ck(st, what):
+    if st != 0:
+        raise dect.DectError(st, f"{what}: {_lib().dect_nn_last_error().decode()}")
+
+
+def _p(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _s():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- ops ---
+def conv_fwd(x, w, b, cout, ksize, relu, out_f32=False):
+    """x [N,H,W,Cin] bf16, w [taps,CoutP,Cin] bf16, b [CoutP] f32."""
+    N, H, W, Cin = x.shape
+    y = torch.empty((N, H, W, cout), device=x.device,
+                    dtype=torch.float32 if out_f32 else torch.bfloat16)
+    _ck(_lib().dect_nn_conv_fwd(_p(x), _p(w), _p(b), _p(y), N, H, W, Cin, cout, ksize,
+                                int(relu), int(out_f32), _s()), "conv_fwd")
+    return y
+
+
+def weight_flip(w, cin, cout, ksize):
+    cinp = (cin + 15) // 16 * 16
+    wd = torch.empty((ksize * ksize, cinp, cout), device=w.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_weight_flip(_p(w), _p(wd), cin, cout, ksize, _s()), "weight_flip")
+    return wd
+
+
+_ws: Dict[int, torch.Tensor] = {}
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    key = 0
+    t = _ws.get(key)
+    if t is None or t.numel() < nbytes:
+        t = torch.empty((nbytes,), dtype=torch.uint8, device=device)
+        _ws[key] = t
+    return t
+
+
+def conv_wgrad(dz, x, cout, ksize, dw, db):
+    N, H, W, Cin = x.shape
+    L = _lib()
+    nbytes = int(L.dect_nn_wgrad_workspace(N, H, W, Cin, cout, ksize))
+    ws = _workspace(nbytes, x.device)
+    _ck(L.dect_nn_conv_wgrad(_p(dz), _p(x), _p(dw), _p(db), N, H, W, Cin, cout, ksize, _p(ws),
+                             ws.numel(), _s()), "conv_wgrad")
+
+
+def relu_bwd(dy, y):
+    dz = torch.empty_like(dy)
+    _ck(_lib().dect_nn_relu_bwd(_p(dy), _p(y), _p(dz), dy.numel(), _s()), "relu_bwd")
+    return dz
+
+
+def pool_fwd(x):
+    N, H, W, C = x.shape
+    y = torch.empty((N, H // 2, W // 2, C), device=x.device, dtype=torch.bfloat16)
+    idx = torch.empty((N, H // 2, W // 2, C), device=x.device, dtype=torch.uint8)
+    _ck(_lib().dect_nn_pool(_p(x), _p(y), _p(idx), N, H, W, C, 0, _s()), "pool")
+    return y, idx
+
+
+def pool_bwd(dy, idx):
+    N, Ho, Wo, C = dy.shape
+    dx = torch.empty((N, 2 * Ho, 2 * Wo, C), device=dy.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_pool(_p(dy), _p(dx), _p(idx), N, 2 * Ho, 2 * Wo, C, 1, _s()), "pool_bwd")
+    return dx
+
+
+def shuffle(t, c):
+    N, H, W, C4 = t.shape
+    y = torch.empty((N, 2 * H, 2 * W, c), device=t.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_shuffle(_p(t), _p(y), N, H, W, c, 0, _s()), "shuffle")
+    return y
+
+
+def unshuffle(y, c):
+    N, H2, W2, _ = y.shape
+    t = torch.empty((N, H2 // 2, W2 // 2, 4 * c), device=y.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_shuffle(_p(y), _p(t), N, H2 // 2, W2 // 2, c, 1, _s()), "unshuffle")
+    return t
+
+
+def concat(a, b):
+    N, H, W, C1 = a.shape
+    C2 = b.shape[-1]
+    z = torch.empty((N, H, W, C1 + C2), device=a.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_concat(_p(a), _p(b), _p(z), N * H * W, C1, C2, 0, _s()), "concat")
+    return z
+
+
+def split(z, c1):
+    N, H, W, C = z.shape
+    a = torch.empty((N, H, W, c1), device=z.device, dtype=torch.bfloat16)
+    b = torch.empty((N, H, W, C - c1), device=z.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_concat(_p(a), _p(b), _p(z), N * H * W, c1, C - c1, 1, _s()), "split")
+    return a, b
+
+
+def add(a, b):
+    z = torch.empty_like(a)
+    _ck(_lib().dect_nn_add(_p(a), _p(b), _p(z), a.numel(), _s()), "add")
+    return z
+
+
+def to_bf16(x):
+    y = torch.empty(x.shape, device=x.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_convert(_p(x.contiguous()), _p(y), x.numel(), 1, _s()), "convert")
+    return y
+
+
+def to_f32(x):
+    y = torch.empty(x.shape, device=x.device, dtype=torch.float32)
+    _ck(_lib().dect_nn_convert(_p(x.contiguous()), _p(y), x.numel(), 0, _s()), "convert")
+    return y
+
+
+def mse(y, t, dy: Optional[torch.Tensor] = None, used: int = 2) -> torch.Tensor:
+    """Mean squared error (device scalar pieces) of y [..., C] f32 vs t [..., used]."""
+    C = y.shape[-1]
+    P = y.numel() // C
+    L = _lib()
+    parts = torch.empty((int(L.dect_nn_mse_partials(P, C)),), device=y.device,
+                        dtype=torch.float64)
+    _ck(L.dect_nn_mse(_p(y), _p(t), _p(dy), _p(parts), P, C, used, _s()), "mse")
+    return parts
+
+
+# --------------------------------------------------------------- layers ---
+class Conv:
+    """Convolution with FP32 master weights [taps, CoutP, Cin] and bias [CoutP]."""
+
+    def __init__(self, cin, cout, ksize, relu, gen: torch.Generator, device):
+        self.cin, self.cout, self.k, self.relu = cin, cout, ksize, relu
+        self.coutp = (cout + 15) // 16 * 16
+        taps = ksize * ksize
+        std = math.sqrt(2.0 / (cin * taps)) if relu else math.sqrt(1.0 / (cin * taps))
+        w = torch.randn((taps, self.coutp, cin), generator=gen, dtype=torch.float32) * std
+        w[:, cout:, :] = 0
+        self.w = w.to(device)
+        self.b = torch.zeros((self.coutp,), device=device)
+        self.wb = to_bf16(self.w)
+        self.gw = torch.zeros_like(self.w)
+        self.gb = torch.zeros_like(self.b)
+        self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.mb, self.vb = torch.zeros_like(self.b), torch.zeros_like(self.b)
+
+    def n_params(self):
+        return self.k * self.k * self.cout * self.cin + self.cout
+
+    def forward(self, x, out_f32=False):
+        return conv_fwd(x, self.wb, self.b, self.cout, self.k, self.relu, out_f32)
+
+    def backward(self, dy, x, y):
+        """dy at the output (bf16); returns dx (bf16); accumulates gw, gb."""
+        dz = relu_bwd(dy, y) if self.relu else dy
+        conv_wgrad(dz, x, self.cout, self.k, self.gw, self.gb)
+        wd = weight_flip(self.wb, self.cin, self.cout, self.k)
+        return conv_fwd(dz, wd, None, self.cin, self.k, False)
+
+    def adam(self, lr, step, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+        L = _lib()
+        s = _s()
+        _ck(L.dect_nn_adam(_p(self.w), _p(self.mw), _p(self.vw), _p(self.gw), _p(self.wb),
+                           self.w.numel(), lr, b1, b2, eps, step, wd, s), "adam")
+        _ck(L.dect_nn_adam(_p(self.b), _p(self.mb), _p(self.vb), _p(self.gb), None,
+                           self.b.numel(), lr, b1, b2, eps, step, 0.0, s), "adam")
+
+
+class UNet:
+    """4-level U-Net on BF16 MFMA kernels; input/output NHWC."""
+
+    def __init__(self, seed: int = 0, device="cuda", ch=CH):
+        g = torch.Generator().manual_seed(seed)
+        c0, c1, c2, c3 = ch
+        self.ch = ch
+        mk = lambda ci, co, k, relu: Conv(ci, co, k, relu, g, device)
+        self.enc = [[mk(IN_CH, c0, 3, True), mk(c0, c0, 3, True)],
+                    [mk(c0, c1, 3, True), mk(c1, c1, 3, True)],
+                    [mk(c1, c2, 3, True), mk(c2, c2, 3, True)],
+                    [mk(c2, c3, 3, True), mk(c3, c3, 3, True)]]
+        # transposed 2x2 stride-2 convs as 1x1 convs to 4*C channels + depth-to-space
+        self.up = [mk(c3, 4 * c2, 1, False), mk(c2, 4 * c1, 1, False), mk(c1, 4 * c0, 1, False)]
+        self.dec = [[mk(2 * c2, c2, 3, True), mk(c2, c2, 3, True)],
+                    [mk(2 * c1, c1, 3, True), mk(c1, c1, 3, True)],
+                    [mk(2 * c0, c0, 3, True), mk(c0, c0, 3, True)]]
+        self.out = mk(c0, OUT_CH, 1, False)
+        self.step = 0
+
+    def layers(self) -> List[Conv]:
+        out = [c for lvl in self.enc for c in lvl] + self.up
+        out += [c for lvl in self.dec for c in lvl] + [self.out]
+        return out
+
+    def n_params(self) -> int:
+        return sum(c.n_params() for c in self.layers())
+
+    # forward keeps what the backward pass needs
+    def forward(self, x, keep: bool = False):
+        """x [N,H,W,8] bf16 (H, W divisible by 8) -> residual [N,H,W,8] f32."""
+        t = {"x": x}
+        h = x
+        skips = []
+        for lvl in range(4):
+            a = self.enc[lvl][0].forward(h)
+            b = self.enc[lvl][1].forward(a)
+            t[f"e{lvl}a"], t[f"e{lvl}b"] = a, b
+            if lvl < 3:
+                skips.append(b)
+                h, idx = pool_fwd(b)
+                t[f"p{lvl}"], t[f"i{lvl}"] = h, idx
+            else:
+                h = b
+        for j, lvl in enumerate((2, 1, 0)):
+            c = self.ch[lvl]
+            tt = self.up[j].forward(h)
+            u = shuffle(tt, c)
+            z = concat(u, skips[lvl])
+            a = self.dec[j][0].forward(z)
+            b = self.dec[j][1].forward(a)
+            t[f"uin{j}"], t[f"z{j}"], t[f"d{j}a"], t[f"d{j}b"] = h, z, a, b
+            h = b
+        y = self.out.forward(h, out_f32=True)
+        t["dout_in"] = h
+        if keep:
+            self._t = t
+        return y
+
+    def zero_grad(self):
+        for c in self.layers():
+            c.gw.zero_()
+            c.gb.zero_()
+
+    def backward(self, dy):
+        """dy: gradient at the f32 output [N,H,W,8]; fills every layer's gw/gb."""
+        t = self._t
+        dh = self.out.backward(to_bf16(dy), t["dout_in"], None)
+        dskip = [None, None, None]
+        # decoder in reverse order: j = 2 (level 0) ... j = 0 (level 2)
+        for j in (2, 1, 0):
+            lvl = (2, 1, 0)[j]
+            c = self.ch[lvl]
+            da = self.dec[j][1].backward(dh, t[f"d{j}a"], t[f"d{j}b"])
+            dz = self.dec[j][0].backward(da, t[f"z{j}"], t[f"d{j}a"])
+            du, ds = split(dz, c)
+            dskip[lvl] = ds
+            dt = unshuffle(du, c)
+            dh = self.up[j].backward(dt, t[f"uin{j}"], None)
+        # encoder in reverse
+        for lvl in (3, 2, 1, 0):
+            if lvl < 3:
+                db_ = pool_bwd(dh, t[f"i{lvl}"])
+                dh = add(db_, dskip[lvl])
+            inp = t["x"] if lvl == 0 else t[f"p{lvl - 1}"]
+            da = self.enc[lvl][1].backward(dh, t[f"e{lvl}a"], t[f"e{lvl}b"])
+            dh = self.enc[lvl][0].backward(da, inp, t[f"e{lvl}a"])
+        self._t = None
+        return dh
+
+    def adam_step(self, lr: float):
+        self.step += 1
+        for c in self.layers():
+            c.adam(lr, self.step)
+
+    def state_dict(self):
+        return {f"l{i}": (c.w.cpu(), c.b.cpu()) for i, c in enumerate(self.layers())}
+
+    def load_state_dict(self, sd):
+        for i, c in enumerate(self.layers()):
+            w, b = sd[f"l{i}"]
+            c.w.copy_(w)
+            c.b.copy_(b)
+            c.wb = to_bf16(c.w)
+
+
+SCALE = 20.0  # network input/output scale: attenuation 1/mm x SCALE ~ O(1)
+
+
+def pack_input(f_high: torch.Tensor, f_low: torch.Tensor) -> torch.Tensor:
+    """Two [N,H,W] f32 images -> [N,H,W,8] bf16 scaled network input."""
+    N, H, W = f_high.shape
+    x = torch.zeros((N, H, W, IN_CH), device=f_high.device, dtype=torch.float32)
+    x[..., 0] = f_high * SCALE
+    x[..., 1] = f_low * SCALE
+    return to_bf16(x)
+
+
+def predict(net: UNet, f_high: torch.Tensor, f_low: torch.Tensor):
+    """Late-iterate estimate of both energies from early iterates [N,H,W]."""
+    x = pack_input(f_high, f_low)
+    r = net.forward(x)
+    base = to_f32(x)
+    y = (base[..., :2] + r[..., :2]) / SCALE
+    return y[..., 0].contiguous(), y[..., 1].contiguous()

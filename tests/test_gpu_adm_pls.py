@@ -156,3 +156,24 @@ def test_pls_maxiter_warning(torch, tiny):
     xh, xl = f32(tiny.x_true[0]), f32(tiny.x_true[1])
     _, _, rep = dect.pls_decompose(to_dev(torch, xh), to_dev(torch, xl), p)
     assert rep.status == dect.DECT_WARN_MAXITER and rep.iters == 2
+
+
+@pytest.mark.parametrize("views", [90, 720])
+def test_adm_paper_scale_parity_200(torch, views):
+    """512x512, 736 bins, both energies, 200 iterations vs the stored FP64 oracle
+    run (tests/golden/make_golden.py): rel-L2 <= 1e-4 per energy image."""
+    import os
+    dect = _dect()
+    path = os.path.join(os.path.dirname(__file__), "golden", f"adm512_v{views}_k200.npz")
+    gold = np.load(path)
+    g = C.paper_geometry(512, views)
+    s = P.make_slice(g, 0)
+    p = C.default_adm_params(g, 200)
+    assert abs(float(gold["mu"]) - p.mu) == 0 and float(gold["xi"]) == p.xi
+    r = dect.adm_tv(to_dev(torch, s.sino[0]), to_dev(torch, s.sino[1]), g, p, want_log=True)
+    for e, xe in enumerate((r.x_high, r.x_low)):
+        err = rel_l2(to_np(xe), gold["x"][e])
+        jerr = abs(r.J[200, e] - gold["J"][e][200]) / gold["J"][e][200]
+        print(f"V={views} energy {e}: image rel-L2 {err:.3e}  J200 rel err {jerr:.2e}", flush=True)
+        assert err <= 1e-4
+        assert jerr <= 1e-5
