@@ -173,6 +173,33 @@ dect_status dect_pls_decompose(int32_t nx, int32_t ny, const float *d_x_high,
 dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, double tau,
                                   double eps, float *d_w, void *stream);
 
+/*
+ * Batched ADM-TV (Eq. 10 for many slices at once): slices of uneven image
+ * size, view count and parameters, both energies each, advanced together;
+ * every phase of an iteration is one persistent launch over a work list that
+ * spans all slices, replayed from a hipGraph.  Starts from zero images.
+ * geoms/params: host arrays [n] (params[i].max_iter and flags are ignored).
+ * d_m_high, d_m_low, d_x_high, d_x_low: host arrays [n] of device pointers
+ *   to slice i's sinograms [V_i][B_i] and output images [ny_i][nx_i].
+ * objective: NULL or host [n], filled after synchronising the stream with
+ *   J(f^K) of Eq. 4 summed over both energies.
+ * dect_batch_tune times `iters` iterations for each adjoint view-group depth
+ * (1, 2, 4, 8 blocks per output tile) on the given data and keeps the
+ * fastest; dect_batch_set_groups fixes it (0 = built-in heuristic).
+ */
+typedef struct dect_batch dect_batch;
+dect_status dect_batch_create(const dect_geometry *geoms, const dect_adm_params *params,
+                              int32_t n, dect_batch **out);
+dect_status dect_batch_destroy(dect_batch *batch);
+dect_status dect_adm_tv_batched(dect_batch *batch, const float *const *d_m_high,
+                                const float *const *d_m_low, float *const *d_x_high,
+                                float *const *d_x_low, int32_t iters, double *objective,
+                                void *stream);
+dect_status dect_batch_tune(dect_batch *batch, const float *const *d_m_high,
+                            const float *const *d_m_low, int32_t iters, int32_t *chosen_groups,
+                            double *ms_per_iter, void *stream);
+dect_status dect_batch_set_groups(dect_batch *batch, int32_t groups);
+
 /* Number of Joseph samples (ray, line) with the crossing inside (-1, n)
  * for a geometry: the unit of projector work. */
 dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);

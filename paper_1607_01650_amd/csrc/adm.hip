@@ -22,53 +22,12 @@
 #include <cmath>
 #include <cstring>
 
-#include "common.h"
+#include "adm_device.h"
 
 namespace dect {
 namespace {
 
-constexpr int kT = 16;  // tv tile side
-
-struct AdmScalars {
-    double alpha;   // step used by the next update
-    double c_prev;  // Cauchy step of the previous G
-    double rr;      // |r^k|^2 of the current f
-    double J;       // last logged objective
-    double relchg;  // last relative image change
-    double beta;    // Eq. 3 weight of this energy
-    int32_t has_prev, stopped, nonfinite_iter, pending;
-    int64_t iter;      // iterations completed
-    int64_t log_base;  // iteration index of log row 0 for this call
-};
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Fixed-order sum over a 256-thread block of NV values; thread t < NV gets
-// the t-th total in `out`.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
-{
-    __shared__ double sh[4][NV];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-    if (lane == 0)
-#pragma unroll
-        for (int i = 0; i < NV; ++i) sh[wid][i] = v[i];
-    __syncthreads();
-    if ((int)threadIdx.x < NV) {
-        int t = threadIdx.x;
-        out[t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
-    }
-}
-
-// ------------------------------------------------------------- tv_fused ---
-// Regions relative to the tile origin (r0, c0): f on rows/cols -2..16 (19),
-// w on -1..16 (18), G on -1..15 (17), grad G on the 16x16 tile.
+// ------------------------------------------------------------- kernels ---
 __global__ __launch_bounds__(256) void k_tv_fused(
     const float *__restrict__ f, const float *__restrict__ h, const float *__restrict__ lam_in,
     const float *__restrict__ z_in, float *__restrict__ lam_out, float *__restrict__ z_out,
@@ -77,109 +36,24 @@ __global__ __launch_bounds__(256) void k_tv_fused(
 {
     const int e = blockIdx.z;
     if (sc[e].stopped) return;
-    const bool pending = sc[e].pending != 0;
-    __shared__ float sf[19][20];
-    __shared__ float swx[18][19], swy[18][19];
-    __shared__ float sg[17][18];
-    const int r0 = blockIdx.y * kT, c0 = blockIdx.x * kT;
-    const size_t N = (size_t)nx * ny;
-    const float *fe = f + e * N;
-    const float *he = h + e * N;
-    const float *lxi = lam_in + (size_t)(2 * e) * N, *lyi = lxi + N;
-    const float *zxi = z_in + (size_t)(2 * e) * N, *zyi = zxi + N;
-    float *lxo = lam_out + (size_t)(2 * e) * N, *lyo = lxo + N;
-    float *zxo = z_out + (size_t)(2 * e) * N, *zyo = zxo + N;
-    const float inv_rho = 1.0f / rho;
-
-    for (int i = threadIdx.x; i < 19 * 19; i += 256) {
-        int rr = i / 19, cc = i % 19;
-        int r = r0 - 2 + rr, c = c0 - 2 + cc;
-        sf[rr][cc] = (r >= 0 && r < ny && c >= 0 && c < nx) ? fe[(size_t)r * nx + c] : 0.f;
-    }
-    __syncthreads();
-
-    double tv = 0.0, pres = 0.0, ff = 0.0;
-    for (int i = threadIdx.x; i < 18 * 18; i += 256) {
-        int rr = i / 18, cc = i % 18;
-        int r = r0 - 1 + rr, c = c0 - 1 + cc;
-        float wx = 0.f, wy = 0.f;
-        if (r >= 0 && r < ny && c >= 0 && c < nx) {
-            size_t o = (size_t)r * nx + c;
-            float fc = sf[rr + 1][cc + 1];
-            float dx = c >= 1 ? fc - sf[rr + 1][cc] : 0.f;
-            float dy = r >= 1 ? fc - sf[rr][cc + 1] : 0.f;
-            float lx = lxi[o], ly = lyi[o];
-            if (pending) {
-                lx -= xi * (dx - zxi[o]);
-                ly -= xi * (dy - zyi[o]);
-            }
-            float vx = dx - lx / rho, vy = dy - ly / rho;
-            float n = sqrtf(vx * vx + vy * vy);
-            float s = n > inv_rho ? (n - inv_rho) / n : 0.f;
-            float zx = s * vx, zy = s * vy;
-            wx = rho * (dx - zx) - lx;
-            wy = rho * (dy - zy) - ly;
-            if (rr >= 1 && rr <= kT && cc >= 1 && cc <= kT) {
-                lxo[o] = lx;
-                lyo[o] = ly;
-                zxo[o] = zx;
-                zyo[o] = zy;
-                tv += (double)sqrtf(dx * dx + dy * dy);
-                double ex = (double)dx - zx, ey = (double)dy - zy;
-                pres += ex * ex + ey * ey;
-                ff += (double)fc * fc;
-            }
-        }
-        swx[rr][cc] = wx;
-        swy[rr][cc] = wy;
-    }
-    __syncthreads();
-
-    // G = h + grad^T w on rows/cols -1..15
-    for (int i = threadIdx.x; i < 17 * 17; i += 256) {
-        int rr = i / 17, cc = i % 17;
-        int r = r0 - 1 + rr, c = c0 - 1 + cc;
-        float gv = 0.f;
-        if (r >= 0 && r < ny && c >= 0 && c < nx) {
-            float s = he[(size_t)r * nx + c];
-            if (c >= 1) s += swx[rr][cc];
-            if (c + 1 <= nx - 1) s -= swx[rr][cc + 1];
-            if (r >= 1) s += swy[rr][cc];
-            if (r + 1 <= ny - 1) s -= swy[rr + 1][cc];
-            gv = s;
-        }
-        sg[rr][cc] = gv;
-    }
-    __syncthreads();
-
-    double gg = 0.0, gradg = 0.0;
-    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
-    const size_t poff = (size_t)e * pnx * pny;
-    {
-        int rr = threadIdx.x / kT, cc = threadIdx.x % kT;
-        int r = r0 + rr, c = c0 + cc;
-        if (r < ny && c < nx) {
-            float gv = sg[rr + 1][cc + 1];
-            float gx = c >= 1 ? gv - sg[rr + 1][cc] : 0.f;
-            float gy = r >= 1 ? gv - sg[rr][cc + 1] : 0.f;
-            gg = (double)gv * gv;
-            gradg = (double)gx * gx + (double)gy * gy;
-            gpad[poff + (size_t)(r + kPad) * pnx + c + kPad] = gv;
-        }
-        // transposed write: thread (rr, cc) writes element (cc, rr) of the tile
-        int rt = r0 + cc, ct = c0 + rr;
-        if (rt < ny && ct < nx) gpadT[poff + (size_t)(ct + kPad) * pny + rt + kPad] = sg[cc + 1][rr + 1];
-    }
-    double v[5] = {tv, gg, gradg, pres, ff};
-    __shared__ double outv[5];
-    block_sum<5>(v, outv);
-    __syncthreads();
-    if (threadIdx.x < 5)
-        partial[((size_t)e * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x) * 5 +
-                threadIdx.x] = outv[threadIdx.x];
+    const size_t N = (size_t)nx * ny, P = (size_t)(nx + 2 * kPad) * (ny + 2 * kPad);
+    AdmImg m{f + e * N,
+             h + e * N,
+             lam_in + (2 * e) * N,
+             lam_in + (2 * e + 1) * N,
+             z_in + (2 * e) * N,
+             z_in + (2 * e + 1) * N,
+             lam_out + (2 * e) * N,
+             lam_out + (2 * e + 1) * N,
+             z_out + (2 * e) * N,
+             z_out + (2 * e + 1) * N,
+             gpad + e * P,
+             gpadT + e * P};
+    const size_t blk = (size_t)e * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x;
+    tv_tile(blockIdx.y * kT, blockIdx.x * kT, m, partial + blk * 5, sc[e].pending != 0, nx, ny,
+            rho, xi);
 }
 
-// ------------------------------------------------------------- scalar ---
 // One block per energy.  nb_tv/nb_fwd: partial counts per energy.
 __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
                                                 const double *__restrict__ p_tv, int nb_tv,
@@ -188,44 +62,10 @@ __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
                                                 double mu, double rho)
 {
     const int e = blockIdx.x;
-    AdmScalars &s = sc[e];
-    if (s.stopped) return;
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    const double *pt = p_tv + (size_t)e * nb_tv * 5;
-    for (int i = threadIdx.x; i < nb_tv; i += 256)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) v[j] += pt[(size_t)i * 5 + j];
-    const double *pf = p_fwd + (size_t)e * nb_fwd;
-    for (int i = threadIdx.x; i < nb_fwd; i += 256) v[5] += pf[i];
-    __shared__ double tot[6];
-    block_sum<6>(v, tot);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const double tvf = tot[0], gg = tot[1], gradg = tot[2], ff = tot[4], pp = tot[5];
-    const double den = mu * pp + rho * gradg;
-    double c = den > 0.0 ? gg / den : (s.has_prev ? s.c_prev : 0.0);
-    double alpha = s.has_prev ? s.c_prev : c;
-    const double J = tvf + 0.5 * mu * s.rr;
-    const double relchg = ff > 0.0 ? alpha * sqrt(gg) / sqrt(ff) : (gg > 0.0 ? INFINITY : 0.0);
-    const int64_t k = s.iter;
-    int64_t row = k - s.log_base;
-    if (log && row >= 0 && row < log_rows) {
-        log[row * 4 + e] = J;
-        log[row * 4 + 2 + e] = alpha;
-    }
-    s.J = J;
-    s.alpha = alpha;
-    s.c_prev = c;
-    s.has_prev = 1;
-    s.relchg = relchg;
-    if (!isfinite(J) || !isfinite(alpha) || !isfinite(gg) || !isfinite(pp)) {
-        s.nonfinite_iter = (int32_t)(k + 1);
-        s.stopped = 1;
-        s.alpha = 0.0;
-    }
+    scalar_energy(sc[e], p_tv + (size_t)e * nb_tv * 5, nb_tv, p_fwd + (size_t)e * nb_fwd, nb_fwd,
+                  log, log_rows, e, mu, rho);
 }
 
-// ------------------------------------------------------------- update ---
 // blocks [0, nbi): f -= alpha G (image); blocks [nbi, nbi+nbs): r -= alpha p
 // and per-block |r|^2.
 __global__ __launch_bounds__(256) void k_update(float *__restrict__ f,
@@ -235,63 +75,18 @@ __global__ __launch_bounds__(256) void k_update(float *__restrict__ f,
                                                 int nx, int ny, int M, int nbi, int nbs)
 {
     const int e = blockIdx.y;
-    AdmScalars &s = sc[e];
-    if (s.stopped) return;
-    const float alpha = (float)s.alpha;
-    const size_t N = (size_t)nx * ny;
-    if ((int)blockIdx.x < nbi) {
-        const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
-        const float *ge = gpad + (size_t)e * pnx * pny;
-        float *fe = f + e * N;
-        for (int j = 0; j < 4; ++j) {
-            size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
-            if (i < N) {
-                int rr = (int)(i / nx), cc = (int)(i % nx);
-                fe[i] -= alpha * ge[(size_t)(rr + kPad) * pnx + cc + kPad];
-            }
-        }
-        return;
-    }
-    const int bs = blockIdx.x - nbi;
-    float *re = r + (size_t)e * M;
-    const float *pe = p + (size_t)e * M;
-    double acc[1] = {0.0};
-    for (int j = 0; j < 4; ++j) {
-        size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
-        if ((int)i < M) {
-            float nr = re[i] - alpha * pe[i];
-            re[i] = nr;
-            acc[0] += (double)nr * nr;
-        }
-    }
-    __shared__ double tot[1];
-    block_sum<1>(acc, tot);
-    __syncthreads();
-    if (threadIdx.x == 0) p_rr[(size_t)e * nbs + bs] = tot[0];
+    if (sc[e].stopped) return;
+    const size_t N = (size_t)nx * ny, P = (size_t)(nx + 2 * kPad) * (ny + 2 * kPad);
+    update_chunk(blockIdx.x, f + e * N, gpad + e * P, r + (size_t)e * M, p + (size_t)e * M,
+                 p_rr + (size_t)e * nbs, (float)sc[e].alpha, nx, ny, M, nbi);
 }
 
-// |r|^2 of every energy from the residual partials (fixed order).  After an
-// update (step != 0) it also counts the iteration, marks the deferred
-// multiplier step as pending and applies the relative-change stop rule.
 __global__ __launch_bounds__(256) void k_rr(AdmScalars *__restrict__ sc,
                                             const double *__restrict__ p_rr, int nbs, int step,
                                             double tol)
 {
     const int e = blockIdx.x;
-    if (step && sc[e].stopped) return;
-    double v[1] = {0.0};
-    for (int i = threadIdx.x; i < nbs; i += 256) v[0] += p_rr[(size_t)e * nbs + i];
-    __shared__ double tot[1];
-    block_sum<1>(v, tot);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    AdmScalars &s = sc[e];
-    s.rr = tot[0];
-    if (step) {
-        s.pending = 1;
-        s.iter += 1;
-        if (tol > 0.0 && s.relchg < tol) s.stopped = 1;
-    }
+    rr_energy(sc[e], p_rr + (size_t)e * nbs, nbs, step, tol);
 }
 
 // ------------------------------------------------------------- set-up ---
@@ -437,6 +232,86 @@ struct dect_adm_state {
 
 namespace dect {
 
+// Set-up of a run on raw state pointers: f = beta x0 (or 0), lambda = z = 0,
+// r = A f - beta m, h = mu A^T r, scalars reset.
+dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
+                     double mu, double bh, double bl, const float *x0h, const float *x0l,
+                     hipStream_t s)
+{
+    const size_t N = (size_t)t.key.nx * t.key.ny;
+    const int M = t.key.V * t.key.B;
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, P.sc, bh, bl);
+    DECT_HIP(hipGetLastError());
+    dim3 gi((unsigned)((N + 255) / 256), 2);
+    hipLaunchKernelGGL(k_init_image, gi, dim3(256), 0, s, P.f, x0h, x0l, (float)bh, (float)bl,
+                       P.lam, P.z, N);
+    DECT_HIP(hipGetLastError());
+    // r = A f - beta m (the padded G buffers serve as f's padded copies here)
+    dect_status st = launch_pad(t, P.f, P.gpad, P.gpadT, 2, s);
+    if (st) return st;
+    if ((st = launch_fwd(t, P.gpad, P.gpadT, P.r, 2, 1.0f, nullptr, s))) return st;
+    hipLaunchKernelGGL(k_init_resid, dim3(P.nbs, 2), dim3(256), 0, s, P.r, mh, ml, (float)bh,
+                       (float)bl, M, P.p_rr, P.nbs);
+    DECT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_rr, P.nbs, 0,
+                       0.0);
+    DECT_HIP(hipGetLastError());
+    return launch_adj(t, P.r, P.h, P.adjpart, P.adjcnt, 2, (float)mu, s);
+}
+
+// Marks the start of a call's log (row 0 = the next iteration).
+dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_log_base, dim3(1), dim3(64), 0, s, P.sc);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+// x = f / beta and the final objective J(f^K) into the scalars and the log.
+dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
+                       double bh, double bl, hipStream_t s)
+{
+    const size_t N = (size_t)t.key.nx * t.key.ny;
+    dim3 go((unsigned)((N + 255) / 256), 2);
+    hipLaunchKernelGGL(k_output, go, dim3(256), 0, s, (const float *)P.f, xh, xl, (float)bh,
+                       (float)bl, N);
+    DECT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tv_only, dim3(P.nbi, 2), dim3(256), 0, s, (const float *)P.f, P.p_tvo,
+                       t.key.nx, t.key.ny);
+    DECT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_final_J, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_tvo, P.nbi,
+                       P.log, P.log_rows, mu);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+static AdmPtrs ptrs_of(dect_adm_state *S)
+{
+    AdmPtrs P;
+    P.f = (float *)S->f.ptr;
+    P.h = (float *)S->h.ptr;
+    P.r = (float *)S->r.ptr;
+    P.p = (float *)S->p.ptr;
+    P.lam = (float *)S->lam.ptr;
+    P.z = (float *)S->z.ptr;
+    P.gpad = (float *)S->gpad.ptr;
+    P.gpadT = (float *)S->gpadT.ptr;
+    P.adjpart = (float *)S->adjpart.ptr;
+    P.adjcnt = (int *)S->adjcnt.ptr;
+    P.p_tv = (double *)S->p_tv.ptr;
+    P.p_fwd = (double *)S->p_fwd.ptr;
+    P.p_rr = (double *)S->p_rr.ptr;
+    P.p_tvo = (double *)S->p_tvo.ptr;
+    P.log = (double *)S->logbuf.ptr;
+    P.log_rows = (int)(S->logbuf.bytes / 32);
+    P.sc = (AdmScalars *)S->sc.ptr;
+    P.nb_tv = S->nb_tv;
+    P.nb_fwd = S->nb_fwd;
+    P.nbi = S->nbi;
+    P.nbs = S->nbs;
+    return P;
+}
+
 static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
 {
     dect_status st = get_tables(g, &S->t);
@@ -502,42 +377,17 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
                       (int *)S->adjcnt.ptr, 2, (float)S->mu, s);
 }
 
-static dect_status adm_start(dect_adm_state *S, const dect_geometry *g, const float *mh,
-                             const float *ml, const dect_adm_params *P, const float *x0h,
-                             const float *x0l, hipStream_t s)
+static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const float *mh,
+                             const float *ml, const float *x0h, const float *x0l, hipStream_t s)
 {
-    const GeomTables &t = *S->t;
-    const size_t N = (size_t)g->nx * g->ny;
-    const int M = g->n_views * g->n_bins;
     S->mu = P->mu;
     S->rho = P->rho;
     S->xi = P->xi;
     S->bh = P->beta_high;
     S->bl = P->beta_low;
     S->parity = 0;
-    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, (AdmScalars *)S->sc.ptr, S->bh,
-                       S->bl);
-    DECT_HIP(hipGetLastError());
-    dim3 gi((unsigned)((N + 255) / 256), 2);
-    hipLaunchKernelGGL(k_init_image, gi, dim3(256), 0, s, (float *)S->f.ptr, x0h, x0l,
-                       (float)S->bh, (float)S->bl, (float *)S->lam.ptr, (float *)S->z.ptr, N);
-    DECT_HIP(hipGetLastError());
-    // r = A f - beta m (the padded G buffers serve as f's padded copies here)
-    dect_status st = launch_pad(t, (const float *)S->f.ptr, (float *)S->gpad.ptr,
-                                (float *)S->gpadT.ptr, 2, s);
+    dect_status st = adm_init(*S->t, ptrs_of(S), mh, ml, S->mu, S->bh, S->bl, x0h, x0l, s);
     if (st) return st;
-    if ((st = launch_fwd(t, (const float *)S->gpad.ptr, (const float *)S->gpadT.ptr,
-                         (float *)S->r.ptr, 2, 1.0f, nullptr, s)))
-        return st;
-    hipLaunchKernelGGL(k_init_resid, dim3(S->nbs, 2), dim3(256), 0, s, (float *)S->r.ptr, mh, ml,
-                       (float)S->bh, (float)S->bl, M, (double *)S->p_rr.ptr, S->nbs);
-    DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, (AdmScalars *)S->sc.ptr,
-                       (const double *)S->p_rr.ptr, S->nbs, 0, 0.0);
-    DECT_HIP(hipGetLastError());
-    if ((st = launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr,
-                         (int *)S->adjcnt.ptr, 2, (float)S->mu, s)))
-        return st;
     S->started = true;
     return DECT_OK;
 }
@@ -613,11 +463,9 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, 4096) * 4 * sizeof(double)))) return st;
     if (!S->started) {
         const bool warm = (P->flags & DECT_WARM_START) != 0;
-        if ((st = adm_start(S, g, mh, ml, P, warm ? xh : nullptr, warm ? xl : nullptr, s)))
-            return st;
+        if ((st = adm_start(S, P, mh, ml, warm ? xh : nullptr, warm ? xl : nullptr, s))) return st;
     }
-    hipLaunchKernelGGL(k_set_log_base, dim3(1), dim3(64), 0, s, (AdmScalars *)S->sc.ptr);
-    DECT_HIP(hipGetLastError());
+    if ((st = adm_mark_log(ptrs_of(S), s))) return st;
     // the log buffer and tol are baked into the graph's kernel arguments:
     // rebuild only when they change
     if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
@@ -640,17 +488,7 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         ++k;
     }
     // outputs and the final objective
-    dim3 go((unsigned)((N + 255) / 256), 2);
-    hipLaunchKernelGGL(k_output, go, dim3(256), 0, s, (const float *)S->f.ptr, xh, xl,
-                       (float)S->bh, (float)S->bl, N);
-    DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tv_only, dim3(S->nbi, 2), dim3(256), 0, s, (const float *)S->f.ptr,
-                       (double *)S->p_tvo.ptr, g->nx, g->ny);
-    DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_final_J, dim3(2), dim3(256), 0, s, (AdmScalars *)S->sc.ptr,
-                       (const double *)S->p_tvo.ptr, S->nbi, (double *)S->logbuf.ptr,
-                       (int)log_rows, S->mu);
-    DECT_HIP(hipGetLastError());
+    if ((st = adm_finish(*S->t, ptrs_of(S), xh, xl, S->mu, S->bh, S->bl, s))) return st;
     if (rep || P->log) {
         DECT_HIP(hipStreamSynchronize(s));
         AdmScalars hs[2];

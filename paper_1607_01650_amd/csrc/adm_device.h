@@ -1,0 +1,280 @@
+// Device-side bodies of the ADM-TV kernels (Eq. 10), shared by the
+// single-geometry launches and the batched work-list launches.  Every body
+// keeps all threads of the block on the same path through its barriers, so a
+// persistent loop can run several items per block.
+#pragma once
+
+#include "common.h"
+
+namespace dect {
+
+constexpr int kT = 16;  // tv tile side
+
+struct AdmScalars {
+    double alpha;   // step used by the next update
+    double c_prev;  // Cauchy step of the previous G
+    double rr;      // |r^k|^2 of the current f
+    double J;       // last logged objective
+    double relchg;  // last relative image change
+    double beta;    // Eq. 3 weight of this energy
+    int32_t has_prev, stopped, nonfinite_iter, pending;
+    int64_t iter;      // iterations completed
+    int64_t log_base;  // iteration index of log row 0 for this call
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Fixed-order sum over a 256-thread block of NV values; every thread gets
+// the totals in `out` (LDS).  Ends with a barrier.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
+{
+    __shared__ double sh[4][NV];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[wid][i] = v[i];
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        int t = threadIdx.x;
+        out[t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+    }
+    __syncthreads();
+}
+
+// Device pointers of one slice's ADM state (both energies).  Layouts: f, h
+// [2][N]; r, p [2][M]; lambda, z [parity][energy][comp][N]; gpad, gpadT
+// [2][(ny+4)(nx+4)] / [2][(nx+4)(ny+4)]; partials per energy and block.
+struct AdmPtrs {
+    float *f, *h, *r, *p, *lam, *z, *gpad, *gpadT, *adjpart;
+    int *adjcnt;
+    double *p_tv, *p_fwd, *p_rr, *p_tvo, *log;
+    int log_rows;
+    AdmScalars *sc;
+    int nb_tv, nb_fwd, nbi, nbs;
+};
+
+dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
+                     double mu, double bh, double bl, const float *x0h, const float *x0l,
+                     hipStream_t s);
+dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s);
+dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
+                       double bh, double bl, hipStream_t s);
+
+// Pointers of one energy image's ADM state.
+struct AdmImg {
+    const float *f, *h, *lxi, *lyi, *zxi, *zyi;
+    float *lxo, *lyo, *zxo, *zyo, *gpad, *gpadT;
+};
+
+// ------------------------------------------------------------- tv_fused ---
+// Tile origin (r0, c0).  Regions relative to it: f on rows/cols -2..16 (19),
+// w on -1..16 (18), G on -1..15 (17), grad G on the 16x16 tile.  part5
+// receives (TV(f), |G|^2, |grad G|^2, |grad f - z|^2, |f|^2) of the tile.
+__device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part5,
+                                        bool pending, int nx, int ny, float rho, float xi)
+{
+    __shared__ float sf[19][20];
+    __shared__ float swx[18][19], swy[18][19];
+    __shared__ float sg[17][18];
+    __shared__ double outv[5];
+    const float inv_rho = 1.0f / rho;
+
+    for (int i = threadIdx.x; i < 19 * 19; i += 256) {
+        int rr = i / 19, cc = i % 19;
+        int r = r0 - 2 + rr, c = c0 - 2 + cc;
+        sf[rr][cc] = (r >= 0 && r < ny && c >= 0 && c < nx) ? m.f[(size_t)r * nx + c] : 0.f;
+    }
+    __syncthreads();
+
+    double tv = 0.0, pres = 0.0, ff = 0.0;
+    for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+        int rr = i / 18, cc = i % 18;
+        int r = r0 - 1 + rr, c = c0 - 1 + cc;
+        float wx = 0.f, wy = 0.f;
+        if (r >= 0 && r < ny && c >= 0 && c < nx) {
+            size_t o = (size_t)r * nx + c;
+            float fc = sf[rr + 1][cc + 1];
+            float dx = c >= 1 ? fc - sf[rr + 1][cc] : 0.f;
+            float dy = r >= 1 ? fc - sf[rr][cc + 1] : 0.f;
+            float lx = m.lxi[o], ly = m.lyi[o];
+            if (pending) {
+                lx -= xi * (dx - m.zxi[o]);
+                ly -= xi * (dy - m.zyi[o]);
+            }
+            float vx = dx - lx / rho, vy = dy - ly / rho;
+            float n = sqrtf(vx * vx + vy * vy);
+            float s = n > inv_rho ? (n - inv_rho) / n : 0.f;
+            float zx = s * vx, zy = s * vy;
+            wx = rho * (dx - zx) - lx;
+            wy = rho * (dy - zy) - ly;
+            if (rr >= 1 && rr <= kT && cc >= 1 && cc <= kT) {
+                m.lxo[o] = lx;
+                m.lyo[o] = ly;
+                m.zxo[o] = zx;
+                m.zyo[o] = zy;
+                tv += (double)sqrtf(dx * dx + dy * dy);
+                double ex = (double)dx - zx, ey = (double)dy - zy;
+                pres += ex * ex + ey * ey;
+                ff += (double)fc * fc;
+            }
+        }
+        swx[rr][cc] = wx;
+        swy[rr][cc] = wy;
+    }
+    __syncthreads();
+
+    // G = h + grad^T w on rows/cols -1..15
+    for (int i = threadIdx.x; i < 17 * 17; i += 256) {
+        int rr = i / 17, cc = i % 17;
+        int r = r0 - 1 + rr, c = c0 - 1 + cc;
+        float gv = 0.f;
+        if (r >= 0 && r < ny && c >= 0 && c < nx) {
+            float s = m.h[(size_t)r * nx + c];
+            if (c >= 1) s += swx[rr][cc];
+            if (c + 1 <= nx - 1) s -= swx[rr][cc + 1];
+            if (r >= 1) s += swy[rr][cc];
+            if (r + 1 <= ny - 1) s -= swy[rr + 1][cc];
+            gv = s;
+        }
+        sg[rr][cc] = gv;
+    }
+    __syncthreads();
+
+    double gg = 0.0, gradg = 0.0;
+    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
+    {
+        int rr = threadIdx.x / kT, cc = threadIdx.x % kT;
+        int r = r0 + rr, c = c0 + cc;
+        if (r < ny && c < nx) {
+            float gv = sg[rr + 1][cc + 1];
+            float gx = c >= 1 ? gv - sg[rr + 1][cc] : 0.f;
+            float gy = r >= 1 ? gv - sg[rr][cc + 1] : 0.f;
+            gg = (double)gv * gv;
+            gradg = (double)gx * gx + (double)gy * gy;
+            m.gpad[(size_t)(r + kPad) * pnx + c + kPad] = gv;
+        }
+        // transposed write: thread (rr, cc) writes element (cc, rr) of the tile
+        int rt = r0 + cc, ct = c0 + rr;
+        if (rt < ny && ct < nx) m.gpadT[(size_t)(ct + kPad) * pny + rt + kPad] = sg[cc + 1][rr + 1];
+    }
+    double v[5] = {tv, gg, gradg, pres, ff};
+    block_sum<5>(v, outv);
+    if (threadIdx.x < 5) part5[threadIdx.x] = outv[threadIdx.x];
+    __syncthreads();
+}
+
+// ------------------------------------------------------------- scalar ---
+// c^k = |G|^2 / (mu |A G|^2 + rho |grad G|^2) from the partials of one
+// energy; alpha^k = c^{k-1} (c^0 at the first step); J^k logged in column
+// `col` (and the step in column col + 2) of a [rows][4] log.
+__device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__restrict__ pt,
+                                              int nb_tv, const double *__restrict__ pf, int nb_fwd,
+                                              double *__restrict__ log, int log_rows, int col,
+                                              double mu, double rho)
+{
+    __shared__ double tot[6];
+    const bool run = !s.stopped;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (run) {
+        for (int i = threadIdx.x; i < nb_tv; i += 256)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) v[j] += pt[(size_t)i * 5 + j];
+        for (int i = threadIdx.x; i < nb_fwd; i += 256) v[5] += pf[i];
+    }
+    block_sum<6>(v, tot);
+    if (run && threadIdx.x == 0) {
+        const double tvf = tot[0], gg = tot[1], gradg = tot[2], ff = tot[4], pp = tot[5];
+        const double den = mu * pp + rho * gradg;
+        double c = den > 0.0 ? gg / den : (s.has_prev ? s.c_prev : 0.0);
+        double alpha = s.has_prev ? s.c_prev : c;
+        const double J = tvf + 0.5 * mu * s.rr;
+        const double relchg = ff > 0.0 ? alpha * sqrt(gg) / sqrt(ff) : (gg > 0.0 ? INFINITY : 0.0);
+        const int64_t k = s.iter;
+        int64_t row = k - s.log_base;
+        if (log && row >= 0 && row < log_rows) {
+            log[row * 4 + col] = J;
+            log[row * 4 + 2 + col] = alpha;
+        }
+        s.J = J;
+        s.alpha = alpha;
+        s.c_prev = c;
+        s.has_prev = 1;
+        s.relchg = relchg;
+        if (!isfinite(J) || !isfinite(alpha) || !isfinite(gg) || !isfinite(pp)) {
+            s.nonfinite_iter = (int32_t)(k + 1);
+            s.stopped = 1;
+            s.alpha = 0.0;
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------- update ---
+// Chunk bx of 1024 elements: bx < nbi updates the image f -= alpha G;
+// otherwise sinogram chunk bx - nbi: r -= alpha p, partial |r|^2 into
+// p_rr[bx - nbi].
+__device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
+                                             const float *__restrict__ gpad_e,
+                                             float *__restrict__ re, const float *__restrict__ pe,
+                                             double *__restrict__ p_rr, float alpha, int nx,
+                                             int ny, int M, int nbi)
+{
+    __shared__ double tot[1];
+    const size_t N = (size_t)nx * ny;
+    if (bx < nbi) {
+        const int pnx = nx + 2 * kPad;
+        for (int j = 0; j < 4; ++j) {
+            size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+            if (i < N) {
+                int rr = (int)(i / nx), cc = (int)(i % nx);
+                fe[i] -= alpha * gpad_e[(size_t)(rr + kPad) * pnx + cc + kPad];
+            }
+        }
+        return;  // uniform across the block
+    }
+    const int bs = bx - nbi;
+    double acc[1] = {0.0};
+    for (int j = 0; j < 4; ++j) {
+        size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
+        if ((int)i < M) {
+            float nr = re[i] - alpha * pe[i];
+            re[i] = nr;
+            acc[0] += (double)nr * nr;
+        }
+    }
+    block_sum<1>(acc, tot);
+    if (threadIdx.x == 0) p_rr[bs] = tot[0];
+    __syncthreads();
+}
+
+// |r|^2 from the residual partials of one energy; after an update
+// (step != 0) also counts the iteration, marks the deferred multiplier step
+// as pending and applies the relative-change stop rule.
+__device__ __forceinline__ void rr_energy(AdmScalars &s, const double *__restrict__ p_rr, int nbs,
+                                          int step, double tol)
+{
+    __shared__ double tot[1];
+    const bool run = !(step && s.stopped);
+    double v[1] = {0.0};
+    if (run)
+        for (int i = threadIdx.x; i < nbs; i += 256) v[0] += p_rr[i];
+    block_sum<1>(v, tot);
+    if (run && threadIdx.x == 0) {
+        s.rr = tot[0];
+        if (step) {
+            s.pending = 1;
+            s.iter += 1;
+            if (tol > 0.0 && s.relchg < tol) s.stopped = 1;
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace dect

@@ -14,9 +14,52 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
                           dect_report *rep, hipStream_t s);
 dect_status pls_edge_weights(int nx, int ny, const float *x, double tau, double eps, float *w,
                              hipStream_t s);
+dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm, int n,
+                         dect_batch **out);
+dect_status batch_destroy(dect_batch *b);
+dect_status adm_tv_batched(dect_batch *b, const float *const *mh, const float *const *ml,
+                           float *const *xh, float *const *xl, int iters, double *objective,
+                           hipStream_t s);
+dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const *ml, int iters,
+                       int32_t *chosen, double *ms_per_iter, hipStream_t s);
+dect_status batch_set_groups(dect_batch *b, int groups);
 }  // namespace dect
 
 extern "C" {
+
+dect_status dect_batch_create(const dect_geometry *geoms, const dect_adm_params *params,
+                              int32_t n, dect_batch **out)
+{
+    dect::set_error("");
+    return dect::batch_create(geoms, params, n, out);
+}
+
+dect_status dect_batch_destroy(dect_batch *batch) { return dect::batch_destroy(batch); }
+
+dect_status dect_adm_tv_batched(dect_batch *batch, const float *const *d_m_high,
+                                const float *const *d_m_low, float *const *d_x_high,
+                                float *const *d_x_low, int32_t iters, double *objective,
+                                void *stream)
+{
+    dect::set_error("");
+    return dect::adm_tv_batched(batch, d_m_high, d_m_low, d_x_high, d_x_low, iters, objective,
+                                (hipStream_t)stream);
+}
+
+dect_status dect_batch_tune(dect_batch *batch, const float *const *d_m_high,
+                            const float *const *d_m_low, int32_t iters, int32_t *chosen_groups,
+                            double *ms_per_iter, void *stream)
+{
+    dect::set_error("");
+    return dect::batch_tune(batch, d_m_high, d_m_low, iters, chosen_groups, ms_per_iter,
+                            (hipStream_t)stream);
+}
+
+dect_status dect_batch_set_groups(dect_batch *batch, int32_t groups)
+{
+    dect::set_error("");
+    return dect::batch_set_groups(batch, groups);
+}
 
 dect_status dect_project(const dect_geometry *geom, const float *d_img, float *d_sino,
                          int32_t batch, void *stream)

@@ -77,6 +77,15 @@ SIGNATURES = {
                                       _P(dect_report), ct.c_void_p]),
     "dect_pls_edge_weights": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_double,
                                          ct.c_double, ct.c_void_p, ct.c_void_p]),
+    "dect_batch_create": (ct.c_int, [_P(dect_geometry), _P(dect_adm_params), ct.c_int32,
+                                     _P(ct.c_void_p)]),
+    "dect_batch_destroy": (ct.c_int, [ct.c_void_p]),
+    "dect_adm_tv_batched": (ct.c_int, [ct.c_void_p, _P(ct.c_void_p), _P(ct.c_void_p),
+                                       _P(ct.c_void_p), _P(ct.c_void_p), ct.c_int32,
+                                       _P(ct.c_double), ct.c_void_p]),
+    "dect_batch_tune": (ct.c_int, [ct.c_void_p, _P(ct.c_void_p), _P(ct.c_void_p), ct.c_int32,
+                                   _P(ct.c_int32), _P(ct.c_double), ct.c_void_p]),
+    "dect_batch_set_groups": (ct.c_int, [ct.c_void_p, ct.c_int32]),
     "dect_count_samples": (ct.c_int, [_P(dect_geometry), _P(ct.c_int64)]),
     "dect_release_caches": (ct.c_int, []),
     "dect_last_error": (ct.c_char_p, []),
@@ -270,6 +279,66 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
                            ct.byref(rep) if want_log else None, _stream())
     _check(st, "dect_adm_tv")
     return AdmResult(xh, xl, rep if want_log else None, log)
+
+
+class AdmBatch:
+    """Many slices (own geometry and ADM parameters each) reconstructed together
+    (dect_batch_create / dect_adm_tv_batched)."""
+
+    def __init__(self, geoms: Sequence[C.Geometry], params: Sequence[C.AdmParams]):
+        n = len(geoms)
+        self.geoms = list(geoms)
+        self._g = [GeomArg(g) for g in geoms]
+        garr = (dect_geometry * n)(*[a.s for a in self._g])
+        parr = (dect_adm_params * n)(*[dect_adm_params(p.mu, p.rho, p.xi, p.beta_high,
+                                                       p.beta_low, p.max_iter, p.tol, 0, None)
+                                       for p in params])
+        h = ct.c_void_p(None)
+        _check(lib().dect_batch_create(garr, parr, n, ct.byref(h)), "dect_batch_create")
+        self.handle = h
+        self.n = n
+
+    @staticmethod
+    def _ptrs(ts):
+        return (ct.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def run(self, m_high, m_low, iters: int, out=None, want_objective: bool = False):
+        torch = _torch()
+        for i, g in enumerate(self.geoms):
+            _dev(m_high[i], "m_high", (g.n_views, g.n_bins))
+            _dev(m_low[i], "m_low", (g.n_views, g.n_bins))
+        if out is None:
+            xh = [torch.empty((g.ny, g.nx), device="cuda") for g in self.geoms]
+            xl = [torch.empty((g.ny, g.nx), device="cuda") for g in self.geoms]
+        else:
+            xh, xl = out
+        obj = (ct.c_double * self.n)() if want_objective else None
+        _check(lib().dect_adm_tv_batched(self.handle, self._ptrs(m_high), self._ptrs(m_low),
+                                         self._ptrs(xh), self._ptrs(xl), int(iters), obj,
+                                         _stream()), "dect_adm_tv_batched")
+        return xh, xl, (list(obj) if want_objective else None)
+
+    def tune(self, m_high, m_low, iters: int = 6):
+        g = ct.c_int32(0)
+        ms = ct.c_double(0.0)
+        _check(lib().dect_batch_tune(self.handle, self._ptrs(m_high), self._ptrs(m_low),
+                                     int(iters), ct.byref(g), ct.byref(ms), _stream()),
+               "dect_batch_tune")
+        return int(g.value), float(ms.value)
+
+    def set_groups(self, groups: int):
+        _check(lib().dect_batch_set_groups(self.handle, int(groups)), "dect_batch_set_groups")
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().dect_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pls_params(p: C.PlsParams) -> dect_pls_params:

@@ -43,9 +43,13 @@ def grad2d_T(px: torch.Tensor, py: torch.Tensor) -> torch.Tensor:
 
 
 def shrink(vx: torch.Tensor, vy: torch.Tensor, t: torch.Tensor):
-    """Isotropic shrinkage max(|v| - t, 0) v / |v| (zero where |v| <= t)."""
-    n = torch.sqrt(vx * vx + vy * vy)
-    s = torch.clamp(n - t, min=0.0) / torch.where(n > 0, n, torch.ones_like(n))
+    """Isotropic shrinkage max(|v| - t, 0) v / |v| (zero where |v| <= t).
+
+    |v| is evaluated as sqrt(max(|v|^2, 1e-30)): identical for |v| > 1e-15 (far
+    below any threshold t), and finite in value and gradient at v = 0.
+    """
+    n = torch.sqrt(torch.clamp(vx * vx + vy * vy, min=1e-30))
+    s = torch.clamp(n - t, min=0.0) / n
     return s * vx, s * vy
 
 

@@ -43,8 +43,7 @@ def test_projector_finite_differences(torch):
     (gx,) = torch.autograd.grad(L, x)
     eps = 1e-3
     for k in range(3):
-        d = torch.randn_like(x)
-        d /= d.norm()
+        d = torch.randn_like(x)  # unit RMS per element: eps * d is 1e-3 per pixel
         with torch.no_grad():
             fd = (loss(x + eps * d) - loss(x - eps * d)) / (2 * eps)
         an = (gx.double() * d.double()).sum()
@@ -76,9 +75,15 @@ def _setup(torch, n_steps=10):
 
 def _params(model):
     out = []
-    for k in range(model.n_steps):
-        out.append(tuple(float(v) for v in model.params_of(k)))
+    with torch_no_grad():
+        for k in range(model.n_steps):
+            out.append(tuple(float(v) for v in model.params_of(k)))
     return out
+
+
+def torch_no_grad():
+    import torch
+    return torch.no_grad()
 
 
 def test_unrolled_forward_parity(torch):

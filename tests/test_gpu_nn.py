@@ -125,7 +125,8 @@ def test_adam_and_mse(torch):
     dy = torch.empty((5, 7, 8), device="cuda")
     parts = nn.mse(torch.as_tensor(y).cuda(), torch.as_tensor(tgt).cuda(), dy)
     ref = np.mean((y[..., :2].astype(np.float64) - tgt) ** 2)
-    assert abs(float(parts.sum()) / (35 * 2) - ref) <= 1e-12 * 10
+    # the kernel forms y - t in FP32 (one rounding) and sums squares in FP64
+    assert abs(float(parts.sum()) / (35 * 2) - ref) <= 1e-6 * ref
     rdy = np.zeros_like(y, dtype=np.float64)
     rdy[..., :2] = 2 * (y[..., :2] - tgt) / (35 * 2)
     assert np.abs(dy.cpu().numpy() - rdy).max() <= 1e-7
@@ -157,15 +158,21 @@ def test_unet_forward_and_gradients_vs_oracle(torch):
     assert err <= 1e-2
     dy = np.zeros((2, 32, 64, 8))
     dy[..., :2] = rng.standard_normal((2, 32, 64, 2)) * 1e-3
+    # the backward pass is checked on the GPU's own forward activations: the
+    # ReLU masks and pooling choices are then identical on both sides, and the
+    # two differ only by accumulation order (and the bf16 roundings it flips)
+    gpu_tape = {k: (v.cpu().numpy() if k.startswith("i") else _np(v))
+                for k, v in net._t.items()}
     net.backward(torch.as_tensor(dy, dtype=torch.float32).cuda())
-    rg = R.unet_backward(L, tape, dy, net.ch)
+    rg = R.unet_backward(L, gpu_tape, dy, net.ch)
     worst = 0.0
     for i, c in enumerate(net.layers()):
         ew = rel_l2(_np(c.gw), rg[i][0])
         eb = rel_l2(_np(c.gb), rg[i][1])
+        print(f"  layer {i}: dW rel-L2 {ew:.2e}  db rel-L2 {eb:.2e}", flush=True)
         worst = max(worst, ew, eb)
     print(f"U-Net worst layer gradient rel-L2 vs oracle {worst:.2e}", flush=True)
-    assert worst <= 3e-2
+    assert worst <= 2e-2
 
 
 def test_unet_learns(torch):
