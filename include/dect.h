@@ -184,7 +184,7 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  * objective: NULL or host [n], filled after synchronising the stream with
  *   J(f^K) of Eq. 4 summed over both energies.
  * dect_batch_tune times `iters` iterations for each adjoint view-group depth
- * (1, 2, 4, 8 blocks per output tile) on the given data and keeps the
+ * (2, 4, 8, 16 blocks per output tile) on the given data and keeps the
  * fastest; dect_batch_set_groups fixes it (0 = built-in heuristic).
  */
 typedef struct dect_batch dect_batch;

@@ -220,12 +220,16 @@ struct dect_adm_state {
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
     double graph_tol = -1.0;
-    hipGraphExec_t graph = nullptr;
+    const float *mh = nullptr, *ml = nullptr;  // measured sinograms of the current call
+    const void *graph_mh = nullptr, *graph_ml = nullptr;
+    int64_t done = 0;                            // iterations completed (host count)
+    hipGraphExec_t graph = nullptr, graph_ref = nullptr;
     hipStream_t cap = nullptr;
     int parity = 0;  // lambda/z buffer holding the current values
     ~dect_adm_state()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
+        if (graph_ref) (void)hipGraphExecDestroy(graph_ref);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -263,6 +267,24 @@ dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, con
 dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_log_base, dim3(1), dim3(64), 0, s, P.sc);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+// Re-derive the residual from the image, r = A f - beta m (formed in FP64 in
+// the projector and rounded once), replacing the recurrence's value, which
+// does not see the FP32 rounding of the f steps; |r|^2 from the projector's
+// per-block sums.
+dect_status adm_refresh(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
+                        double bh, double bl, hipStream_t s)
+{
+    dect_status st = launch_pad(t, P.f, P.gpad, P.gpadT, 2, s);
+    if (st) return st;
+    if ((st = launch_fwd(t, P.gpad, P.gpadT, P.r, 2, 1.0f, P.p_fwd, s, mh, ml, (float)bh,
+                         (float)bl)))
+        return st;
+    hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_fwd, P.nb_fwd,
+                       0, 0.0);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -343,7 +365,7 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
 
 // Launch one iteration; `par` selects the lambda/z buffers holding the
 // current values.
-static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream_t s)
+static dect_status launch_iter(dect_adm_state *S, int par, double tol, bool refresh, hipStream_t s)
 {
     const GeomTables &t = *S->t;
     const int nx = t.key.nx, ny = t.key.ny;
@@ -373,6 +395,7 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_rr.ptr, S->nbs, 1,
                        tol);
     DECT_HIP(hipGetLastError());
+    if (refresh && (st = adm_refresh(t, ptrs_of(S), S->mh, S->ml, S->bh, S->bl, s))) return st;
     return launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr,
                       (int *)S->adjcnt.ptr, 2, (float)S->mu, s);
 }
@@ -392,16 +415,17 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     return DECT_OK;
 }
 
-static dect_status build_graph(dect_adm_state *S, double tol)
+static dect_status capture_pair(dect_adm_state *S, double tol, bool refresh_second,
+                                hipGraphExec_t *out)
 {
-    if (S->graph) {
-        (void)hipGraphExecDestroy(S->graph);
-        S->graph = nullptr;
+    if (*out) {
+        (void)hipGraphExecDestroy(*out);
+        *out = nullptr;
     }
     if (!S->cap) DECT_HIP(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
     DECT_HIP(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
-    dect_status st = launch_iter(S, 0, tol, S->cap);
-    if (!st) st = launch_iter(S, 1, tol, S->cap);
+    dect_status st = launch_iter(S, 0, tol, false, S->cap);
+    if (!st) st = launch_iter(S, 1, tol, refresh_second, S->cap);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(S->cap, &graph);
     if (st) {
@@ -409,10 +433,19 @@ static dect_status build_graph(dect_adm_state *S, double tol)
         return st;
     }
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&S->graph, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     return DECT_OK;
+}
+
+// Two graphs of an even/odd iteration pair: plain, and with the residual
+// refresh after the second iteration.
+static dect_status build_graph(dect_adm_state *S, double tol)
+{
+    dect_status st = capture_pair(S, tol, false, &S->graph);
+    if (!st) st = capture_pair(S, tol, true, &S->graph_ref);
+    return st;
 }
 
 static std::mutex g_adm_mu;
@@ -461,7 +494,10 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     // the device log keeps at least 4096 rows so that calls of different
     // lengths reuse it (and the captured graph that points at it)
     if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, 4096) * 4 * sizeof(double)))) return st;
+    S->mh = mh;
+    S->ml = ml;
     if (!S->started) {
+        S->done = 0;
         const bool warm = (P->flags & DECT_WARM_START) != 0;
         if ((st = adm_start(S, P, mh, ml, warm ? xh : nullptr, warm ? xl : nullptr, s))) return st;
     }
@@ -469,23 +505,34 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     // the log buffer and tol are baked into the graph's kernel arguments:
     // rebuild only when they change
     if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
-                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol)) {
+                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol ||
+                   S->graph_mh != (const void *)mh || S->graph_ml != (const void *)ml)) {
         if ((st = build_graph(S, P->tol))) return st;
         S->graph_log = S->logbuf.ptr;
         S->graph_log_bytes = S->logbuf.bytes;
         S->graph_tol = P->tol;
+        S->graph_mh = mh;
+        S->graph_ml = ml;
     }
+    // the residual is re-derived from the image after every kRefresh-th
+    // iteration (absolute count, so split runs refresh at the same points)
+    auto refresh_after = [](int64_t k_abs) { return (k_abs + 1) % kRefresh == 0; };
     int k = 0;
     if (S->parity == 1 && K > 0) {  // realign so the graph starts on parity 0
-        if ((st = launch_iter(S, 1, P->tol, s))) return st;
+        if ((st = launch_iter(S, 1, P->tol, refresh_after(S->done), s))) return st;
         S->parity = 0;
         ++k;
+        ++S->done;
     }
-    for (; k + 2 <= K; k += 2) DECT_HIP(hipGraphLaunch(S->graph, s));
+    for (; k + 2 <= K; k += 2) {
+        DECT_HIP(hipGraphLaunch(refresh_after(S->done + 1) ? S->graph_ref : S->graph, s));
+        S->done += 2;
+    }
     if (k < K) {
-        if ((st = launch_iter(S, 0, P->tol, s))) return st;
+        if ((st = launch_iter(S, 0, P->tol, refresh_after(S->done), s))) return st;
         S->parity = 1;
         ++k;
+        ++S->done;
     }
     // outputs and the final objective
     if ((st = adm_finish(*S->t, ptrs_of(S), xh, xl, S->mu, S->bh, S->bl, s))) return st;

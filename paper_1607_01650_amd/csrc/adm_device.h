@@ -64,6 +64,12 @@ dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, con
                      double mu, double bh, double bl, const float *x0h, const float *x0l,
                      hipStream_t s);
 dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s);
+dect_status adm_refresh(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
+                        double bh, double bl, hipStream_t s);
+
+// The residual r = A f - beta m is carried by the recurrence r -= alpha A G
+// and re-derived from f after every kRefresh-th iteration (even).
+constexpr int kRefresh = 10;
 dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
                        double bh, double bl, hipStream_t s);
 

@@ -132,16 +132,15 @@ __global__ __launch_bounds__(256) void kb_rr(const SliceDev *__restrict__ S,
 __global__ __launch_bounds__(256) void kb_adj(const SliceDev *__restrict__ S,
                                               const int4 *__restrict__ items, int n)
 {
-    __shared__ float acc[4][kTile * kTileLd];
-    __shared__ int is_last;
+    __shared__ AdjShared sh;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
         const int e = w.y, tile = w.z, g = w.w;
-        const int ntiles = d.ntx * ((d.ny + kTile - 1) / kTile);
+        const int ntiles = adj_tiles(d.nx, d.ny);
         if (!d.P.sc[e].stopped)
-            adj_block(acc, &is_last, d.P.r + (size_t)e * d.M, d.adj, d.len, d.views, d.geo, d.nx,
-                      d.ny, d.V, d.B, d.ntx, tile, g, d.nvg, d.P.h + (size_t)e * d.nx * d.ny,
+            adj_block(sh, d.P.r + (size_t)e * d.M, d.adj, d.len, d.views, d.geo, d.nx, d.ny, d.V,
+                      d.B, tile, g, d.nvg, d.P.h + (size_t)e * d.nx * d.ny,
                       d.nvg > 1 ? d.P.adjpart + ((size_t)e * ntiles + tile) * d.nvg * kTilePix
                                 : nullptr,
                       d.P.adjcnt + e * ntiles + tile, d.muf);
@@ -161,12 +160,15 @@ struct dect_batch {
     dect::DevBuf arena, slices, w_tv, w_fwd, w_se, w_upd, w_adj;
     int n_tv = 0, n_fwd = 0, n_se = 0, n_upd = 0, n_adj = 0;
     int g_tv = 0, g_fwd = 0, g_se = 0, g_upd = 0, g_adj = 0;
-    int nvg_max = 8, group_choice = 0;  // 0: per-slice heuristic, else fixed
-    hipGraphExec_t graph = nullptr;
+    int nvg_max = 16, group_choice = 0;  // 0: per-slice heuristic, else fixed
+    const float *const *mh = nullptr, *const *ml = nullptr;  // current call's sinograms
+    std::vector<const float *> graph_m;                       // the ones the graphs hold
+    hipGraphExec_t graph = nullptr, graph_ref = nullptr;
     hipStream_t cap = nullptr;
     ~dect_batch()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
+        if (graph_ref) (void)hipGraphExecDestroy(graph_ref);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -191,7 +193,7 @@ dect_status build_work(dect_batch *b)
                                   : heuristic_groups(t);
         d.nvg = nvg;
         const int gx = (d.nx + kT - 1) / kT, gy = (d.ny + kT - 1) / kT;
-        const int ntiles = d.ntx * ((d.ny + kTile - 1) / kTile);
+        const int ntiles = adj_tiles(d.nx, d.ny);
         for (int e = 0; e < 2; ++e) {
             for (int ty = 0; ty < gy; ++ty)
                 for (int tx = 0; tx < gx; ++tx) tv.push_back({1.0, make_int4(s, e, ty, tx)});
@@ -240,10 +242,14 @@ dect_status build_work(dect_batch *b)
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
+    if (b->graph_ref) {
+        (void)hipGraphExecDestroy(b->graph_ref);
+        b->graph_ref = nullptr;
+    }
     return DECT_OK;
 }
 
-dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
+dect_status launch_batch_iter(dect_batch *b, int par, bool refresh, hipStream_t s)
 {
     const SliceDev *S = (const SliceDev *)b->slices.ptr;
     hipLaunchKernelGGL(kb_tv, dim3(b->g_tv), dim3(256), 0, s, S, (const int4 *)b->w_tv.ptr, b->n_tv,
@@ -261,19 +267,30 @@ dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
     hipLaunchKernelGGL(kb_rr, dim3(b->g_se), dim3(256), 0, s, S, (const int4 *)b->w_se.ptr,
                        b->n_se);
     DECT_HIP(hipGetLastError());
+    if (refresh) {  // same schedule and kernels as the single-slice path
+        for (int i = 0; i < b->n; ++i) {
+            const dect_adm_params &p = b->prm[i];
+            dect_status st = adm_refresh(*b->t[i], b->host[i].P, b->mh[i], b->ml[i], p.beta_high,
+                                         p.beta_low, s);
+            if (st) return st;
+        }
+    }
     hipLaunchKernelGGL(kb_adj, dim3(b->g_adj), dim3(256), 0, s, S, (const int4 *)b->w_adj.ptr,
                        b->n_adj);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
 
-dect_status batch_graph(dect_batch *b)
+dect_status capture_pair(dect_batch *b, bool refresh_second, hipGraphExec_t *out)
 {
-    if (b->graph) return DECT_OK;
+    if (*out) {
+        (void)hipGraphExecDestroy(*out);
+        *out = nullptr;
+    }
     if (!b->cap) DECT_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     DECT_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    dect_status st = launch_batch_iter(b, 0, b->cap);
-    if (!st) st = launch_batch_iter(b, 1, b->cap);
+    dect_status st = launch_batch_iter(b, 0, false, b->cap);
+    if (!st) st = launch_batch_iter(b, 1, refresh_second, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (st) {
@@ -281,18 +298,37 @@ dect_status batch_graph(dect_batch *b)
         return st;
     }
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("batch capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("batch instantiate: ") + hipGetErrorString(e));
     return DECT_OK;
 }
 
+// Graphs of an even/odd iteration pair, plain and with the residual refresh
+// after the second; rebuilt when the work lists or the sinograms change.
+dect_status batch_graph(dect_batch *b)
+{
+    std::vector<const float *> m(2 * b->n);
+    for (int i = 0; i < b->n; ++i) {
+        m[2 * i] = b->mh[i];
+        m[2 * i + 1] = b->ml[i];
+    }
+    if (b->graph && b->graph_ref && m == b->graph_m) return DECT_OK;
+    dect_status st = capture_pair(b, false, &b->graph);
+    if (!st) st = capture_pair(b, true, &b->graph_ref);
+    if (!st) b->graph_m = m;
+    return st;
+}
+
 // Start every slice (f = 0) and run `iters` iterations (even/odd pairs from
-// the graph, an odd last one launched directly).
+// the graphs, an odd last one launched directly); the residual is refreshed
+// after the same iterations as in the single-slice path.
 dect_status batch_run(dect_batch *b, const float *const *mh, const float *const *ml, int iters,
                       hipStream_t s)
 {
     dect_status st;
+    b->mh = mh;
+    b->ml = ml;
     for (int i = 0; i < b->n; ++i) {
         const dect_adm_params &p = b->prm[i];
         if ((st = adm_init(*b->t[i], b->host[i].P, mh[i], ml[i], p.mu, p.beta_high, p.beta_low,
@@ -302,8 +338,9 @@ dect_status batch_run(dect_batch *b, const float *const *mh, const float *const 
     }
     if ((st = batch_graph(b))) return st;
     int k = 0;
-    for (; k + 2 <= iters; k += 2) DECT_HIP(hipGraphLaunch(b->graph, s));
-    if (k < iters && (st = launch_batch_iter(b, 0, s))) return st;
+    for (; k + 2 <= iters; k += 2)
+        DECT_HIP(hipGraphLaunch((k + 2) % kRefresh == 0 ? b->graph_ref : b->graph, s));
+    if (k < iters && (st = launch_batch_iter(b, 0, (k + 1) % kRefresh == 0, s))) return st;
     return DECT_OK;
 }
 
@@ -338,7 +375,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         z.nb_fwd = (size_t)fwd_blocks(t);
         z.nbi = (z.N + 1023) / 1024;
         z.nbs = (z.M + 1023) / 1024;
-        const size_t tiles = (size_t)((t.key.nx + kTile - 1) / kTile) * ((t.key.ny + kTile - 1) / kTile);
+        const size_t tiles = (size_t)adj_tiles(t.key.nx, t.key.ny);
         z.part = 2 * tiles * std::max(b->nvg_max, adj_groups(t, 2)) * kTilePix;
         z.cnt = 2 * tiles;
         size_t bytes = 0;
@@ -394,7 +431,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         d.B = t.key.B;
         d.M = (int)z.M;
         d.nbundle = t.nbundle;
-        d.ntx = (t.key.nx + kTile - 1) / kTile;
+        d.ntx = adj_tiles_x(t.key.nx);
         d.fwd = t.fwd;
         d.adj = t.adj;
         d.len = t.len;
@@ -455,7 +492,7 @@ dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const
 {
     if (!b || !mh || !ml || iters < 2)
         return fail(DECT_ERR_INVALID_ARG, "dect_batch_tune: bad arguments");
-    const int options[] = {1, 2, 4, 8};
+    const int options[] = {2, 4, 8, 16};
     double best = 1e30;
     int best_g = 0;
     hipEvent_t e0, e1;
@@ -492,7 +529,7 @@ dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const
 dect_status batch_set_groups(dect_batch *b, int groups)
 {
     if (!b || groups < 0 || groups > b->nvg_max)
-        return fail(DECT_ERR_INVALID_ARG, "dect_batch_set_groups: 0 (heuristic) .. 8");
+        return fail(DECT_ERR_INVALID_ARG, "dect_batch_set_groups: 0 (heuristic) .. 16");
     b->group_choice = groups;
     return build_work(b);
 }

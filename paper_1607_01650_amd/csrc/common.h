@@ -105,8 +105,12 @@ dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float 
                        hipStream_t s);
 // sino[e] = scale * A img[e] from the padded layouts.  norm_partial (may be
 // NULL) receives per-block sums of squares (double) for a later reduction.
+// With sub0/sub1 (items 0 and 1), sino[e] = scale * A img[e] - ss_e * sub_e,
+// formed in FP64 and rounded once.
 dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
-                       int batch, float scale, double *norm_partial, hipStream_t s);
+                       int batch, float scale, double *norm_partial, hipStream_t s,
+                       const float *sub0 = nullptr, const float *sub1 = nullptr,
+                       float ss0 = 0.f, float ss1 = 0.f);
 int fwd_blocks(const GeomTables &t);
 // img[e] = scale * A^T sino[e].  With several view groups (adj_groups > 1)
 // partial holds adj_partial_floats() floats and counters adj_counters() ints

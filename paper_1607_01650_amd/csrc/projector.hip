@@ -58,7 +58,9 @@ __global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ pad,
                                              const Bundle *__restrict__ bundles,
                                              float *__restrict__ sino, int nx, int ny, int V,
                                              int B, int nbundle, float scale,
-                                             double *__restrict__ partial)
+                                             double *__restrict__ partial,
+                                             const float *__restrict__ sub0,
+                                             const float *__restrict__ sub1, float ss0, float ss1)
 {
     const int e = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -68,7 +70,8 @@ __global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ pad,
     float result = 0.f;
     if (gw < V * nbundle)
         result = fwd_wave(pad + p_off, padT + p_off, rays, len, bundles,
-                          sino + (size_t)e * V * B, nx, ny, B, nbundle, gw, lane, scale);
+                          sino + (size_t)e * V * B, nx, ny, B, nbundle, gw, lane, scale,
+                          e == 0 ? sub0 : e == 1 ? sub1 : nullptr, e == 0 ? ss0 : ss1);
     if (NORM) {
         __shared__ double red[256];
         double tot = block_sum_256((double)result * (double)result, red);
@@ -81,17 +84,16 @@ __global__ __launch_bounds__(256) void k_adj(const float *__restrict__ sino,
                                              const RayAdj *__restrict__ rays,
                                              const float *__restrict__ len,
                                              const ViewInfo *__restrict__ views, AdjGeo geo,
-                                             int nx, int ny, int V, int B, int ntx, int nvg,
+                                             int nx, int ny, int V, int B, int nvg,
                                              float *__restrict__ out, float *__restrict__ part,
                                              int *__restrict__ counters, float scale)
 {
-    __shared__ float acc[4][kTile * kTileLd];
-    __shared__ int is_last;
+    __shared__ AdjShared sh;
     const int e = blockIdx.z, g = blockIdx.y, tile = blockIdx.x;
     const int ntiles = gridDim.x;
     const size_t plane = (size_t)nx * ny;
-    adj_block(acc, &is_last, sino + (size_t)e * V * B, rays, len, views, geo, nx, ny, V, B, ntx,
-              tile, g, nvg, out + (size_t)e * plane,
+    adj_block(sh, sino + (size_t)e * V * B, rays, len, views, geo, nx, ny, V, B, tile, g, nvg,
+              out + (size_t)e * plane,
               part ? part + ((size_t)e * ntiles + tile) * nvg * kTilePix : nullptr,
               counters ? counters + e * ntiles + tile : nullptr, scale);
 }
@@ -112,41 +114,42 @@ dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float 
 int fwd_blocks(const GeomTables &t) { return (t.key.V * t.nbundle + 3) / 4; }
 
 dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
-                       int batch, float scale, double *norm_partial, hipStream_t s)
+                       int batch, float scale, double *norm_partial, hipStream_t s,
+                       const float *sub0, const float *sub1, float ss0, float ss1)
 {
     const GeomKey &k = t.key;
     dim3 grid(fwd_blocks(t), batch);
     if (norm_partial)
         hipLaunchKernelGGL(k_fwd<true>, grid, dim3(256), 0, s, pad, padT, t.fwd, t.len,
                            t.bundles, sino, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
-                           norm_partial);
+                           norm_partial, sub0, sub1, ss0, ss1);
     else
         hipLaunchKernelGGL(k_fwd<false>, grid, dim3(256), 0, s, pad, padT, t.fwd, t.len,
                            t.bundles, sino, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
-                           (double *)nullptr);
+                           (double *)nullptr, sub0, sub1, ss0, ss1);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
 
+// View groups per output tile: enough blocks for four per compute unit
+// (1024 on 256 CUs), but at least 8 views per group.
 int adj_groups(const GeomTables &t, int batch)
 {
-    const int tiles = ((t.key.nx + kTile - 1) / kTile) * ((t.key.ny + kTile - 1) / kTile);
-    int want = (512 + tiles * batch - 1) / (tiles * batch);
+    const int tiles = adj_tiles(t.key.nx, t.key.ny);
+    int want = (1024 + tiles * batch - 1) / (tiles * batch);
     int cap = std::max(1, t.key.V / 8);
     return std::max(1, std::min(want, cap));
 }
 
 size_t adj_partial_floats(const GeomTables &t, int batch)
 {
-    const int tiles = ((t.key.nx + kTile - 1) / kTile) * ((t.key.ny + kTile - 1) / kTile);
     const int nvg = adj_groups(t, batch);
-    return nvg > 1 ? (size_t)batch * tiles * nvg * kTile * kTile : 0;
+    return nvg > 1 ? (size_t)batch * adj_tiles(t.key.nx, t.key.ny) * nvg * kTilePix : 0;
 }
 
 size_t adj_counters(const GeomTables &t, int batch)
 {
-    const int tiles = ((t.key.nx + kTile - 1) / kTile) * ((t.key.ny + kTile - 1) / kTile);
-    return (size_t)batch * tiles;
+    return (size_t)batch * adj_tiles(t.key.nx, t.key.ny);
 }
 
 AdjGeo adj_geometry(const GeomTables &t)
@@ -168,12 +171,11 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
                        int *counters, int batch, float scale, hipStream_t s)
 {
     const GeomKey &k = t.key;
-    const int ntx = (k.nx + kTile - 1) / kTile, nty = (k.ny + kTile - 1) / kTile;
     const int nvg = adj_groups(t, batch);
     const AdjGeo geo = adj_geometry(t);
-    dim3 grid(ntx * nty, nvg, batch);
+    dim3 grid(adj_tiles(k.nx, k.ny), nvg, batch);
     hipLaunchKernelGGL(k_adj, grid, dim3(256), 0, s, sino, t.adj, t.len, t.views, geo, k.nx,
-                       k.ny, k.V, k.B, ntx, nvg, img, partial, counters, scale);
+                       k.ny, k.V, k.B, nvg, img, partial, counters, scale);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }

@@ -1,7 +1,7 @@
 """Write the stored oracle results used by the paper-scale GPU parity tests.
 
 Calls only the FP64 oracle (oracle/) on the seeded synthetic inputs of the
-paper-scale workloads (512x512, 90 and 720 views over 360 degrees, 736 bins,
+paper-scale workloads (512x512, 90, 360 and 720 views over 360 degrees, 736 bins,
 both energies, 200 ADM-TV iterations) and stores the images as float32 plus
 the per-iteration objective.  Run from the repository root:
     python tests/golden/make_golden.py [90] [720]
@@ -42,4 +42,4 @@ def main(views):
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [90, 720])
+    main([int(a) for a in sys.argv[1:]] or [90, 360, 720])
