@@ -9,6 +9,14 @@ with 0.5 % Gaussian noise) are resident in HBM before timing starts.
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (the gather back-projection, timed with HIP events on the stream it
 is launched on) and the FP64 CPU oracle timed on a bounded sample.
+
+Other modes (for hardware-counter runs under rocprofv3, one GPU):
+  --mode projectors   only the back- and forward-projection launches of the
+                      roofline entry (same inputs and launch configuration)
+  --mode copy         device-to-device copies of --copy-mb MiB: a kernel of
+                      known traffic that calibrates FETCH_SIZE / WRITE_SIZE
+  --mode traffic      reads the counter CSVs of those runs (--pmc-dir) and
+                      writes profiles/adjoint_traffic.json (no GPU needed)
 """
 from __future__ import annotations
 
@@ -84,7 +92,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-launches", type=int, default=50)
+    ap.add_argument("--mode", choices=["metric", "projectors", "copy", "traffic"],
+                    default="metric")
+    ap.add_argument("--copy-mb", type=int, default=512)
+    ap.add_argument("--pmc-dir", default="gpurun_out/pmc")
+    ap.add_argument("--warm-cases", type=int, default=4,
+                    help="held-out cases for the learned-warm-start time-to-tol entry")
     args = ap.parse_args()
+    if args.mode == "traffic":
+        return traffic_summary(args.pmc_dir)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the whole path on a single MI355X "
               "(multi-GPU sharding is described, not built); use --gpus 1", file=sys.stderr)
@@ -96,6 +112,10 @@ def main():
     from paper_1607_01650_amd import configs as C, dect, phantom as P
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if args.mode == "copy":
+        return copy_probe(args.copy_mb, args.kernel_launches)
+    if args.mode == "projectors":
+        return projector_launches(args.kernel_launches)
     g = C.METRIC
     s = P.make_slice(g, 0)
     p = C.default_adm_params(g, args.steps)
@@ -161,6 +181,8 @@ def main():
     torch.cuda.synchronize()
     pls_ms = (time.perf_counter() - q0) * 1e3
 
+    warm = warm_start_extra(args.warm_cases)
+
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
     if os.path.exists(tfile):
@@ -189,24 +211,155 @@ def main():
                    "sdd_mm": g.sdd_mm, "mu": p.mu, "rho": p.rho, "xi": p.xi},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_adj (gather back-projection, 2 energies)",
+                     "traffic": traffic,
+                     "kernel": "k_adj + k_adj_sum (gather back-projection, 2 energies)",
                      "avg_launch_us": round(adj_ms * 1e3, 2),
                      "algorithmic_bytes": adj_bytes},
         "extra": {"fwd_projection_us_2energies": round(fwd_ms * 1e3, 2),
                   "samples_per_projection": S,
                   "ray_updates_per_s": round(4 * S * iters_per_s, 1),
                   "wall_s_timed": round(wall, 4),
-                  "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters},
+                  "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
+                  "warm_start": warm},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
     print(json.dumps(out), flush=True)
 
 
+def warm_start_extra(n: int):
+    """Time to the plain method's objective J(f^200), learned warm start vs
+    plain ADM, on the first n held-out phantoms (512x512, 90 views) with the
+    trained weights shipped in the package."""
+    if n <= 0:
+        return None
+    import numpy as np
+    from paper_1607_01650_amd import configs as C, nn as NN, warmstart as W
+    path = os.path.join(ROOT, "paper_1607_01650_amd", "weights", "unet_warmstart_512_90v.npz")
+    if not os.path.exists(path):
+        return None
+    geom = C.paper_geometry(512, 90)
+    net = NN.UNet(seed=0)
+    W.load_weights(net, path)
+    sol = W.Solver(geom)
+    rows = []
+    for sd in range(W.EVAL_SEED0, W.EVAL_SEED0 + n):
+        _, sino = W.make_case(geom, sd)
+        r = W.evaluate_case(net, sol, sino, reps=3)
+        rows.append(r)
+    ok = [r for r in rows if r["k_cont"] >= 0]
+    med = lambda a: float(np.median(a)) if len(a) else None
+    return {"workload": "512x512, 90 views, 736 bins, 2 energies; J_ref = J(plain f^200)",
+            "cases": n, "reached": len(ok),
+            "median_iters_plain": med([r["k_plain"] for r in rows]),
+            "median_iters_learned": med([W.EARLY + r["k_cont"] for r in ok]),
+            "median_ms_plain": med([r["t_plain_ms"] for r in ok]),
+            "median_ms_learned": med([r["t_learned_ms"] for r in ok]),
+            "median_time_ratio": med([r["t_learned_ms"] / r["t_plain_ms"] for r in ok])}
+
+
 def _kernel_hash() -> str:
+    """Hash of the projector sources: counter-derived traffic is only reported
+    for the kernels it was measured on."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1607_01650_amd", "csrc", "projector.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("projector.hip", "proj_device.h", "common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1607_01650_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def projector_launches(k: int):
+    """The roofline entry's projector launches alone (for counter runs)."""
+    import torch
+    from paper_1607_01650_amd import configs as C, dect
+    g = C.METRIC
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    r = torch.randn((2, g.n_views, g.n_bins), device="cuda", generator=gen)
+    img = torch.empty((2, g.ny, g.nx), device="cuda")
+    x = torch.randn((2, g.ny, g.nx), device="cuda", generator=gen)
+    sino = torch.empty((2, g.n_views, g.n_bins), device="cuda")
+    for _ in range(k):
+        dect.backproject(r, g, out=img)
+    for _ in range(k):
+        dect.project(x, g, out=sino)
+    torch.cuda.synchronize()
+    S = dect.count_samples(g)
+    M, N = g.n_views * g.n_bins, g.nx * g.ny
+    print(json.dumps({"mode": "projectors", "launches": k, "samples": S,
+                      "algorithmic_bytes_per_launch": 2 * (8 * S + 4 * M + 4 * N),
+                      "kernel_hash": _kernel_hash()}), flush=True)
+
+
+def copy_probe(mb: int, k: int):
+    """Device copies of known size (read mb MiB, write mb MiB per launch)."""
+    import torch
+    n = mb * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(k):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "launches": k}), flush=True)
+
+
+def _pmc_rows(path: str):
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    out = {}
+    for r in rows:
+        name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName") or ""
+        cname = r.get("Counter_Name") or r.get("Counter-Name") or ""
+        val = float(r.get("Counter_Value") or r.get("Counter-Value") or 0.0)
+        did = r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id") or ""
+        out.setdefault((name, cname), {}).setdefault(did, 0.0)
+        out[(name, cname)][did] += val
+    return out
+
+
+def traffic_summary(pmc_dir: str):
+    """HBM bytes per back-projection launch from FETCH_SIZE / WRITE_SIZE runs,
+    each scaled by what the same counter reads for the copy kernel."""
+    import glob
+    import statistics
+
+    def load(tag):
+        files = glob.glob(os.path.join(pmc_dir, tag, "**", "*counter_collection.csv"),
+                          recursive=True)
+        if not files:
+            raise SystemExit(f"no counter CSV under {pmc_dir}/{tag}")
+        return _pmc_rows(files[0])
+
+    def per_dispatch(rows, match, counter):
+        vals = []
+        for (name, cname), d in rows.items():
+            if cname == counter and match(name):
+                vals += list(d.values())
+        return statistics.median(vals) if vals else None, len(vals)
+
+    res = {}
+    for counter, tag in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        copy_rows = load(f"copy_{tag}")
+        proj_rows = load(f"proj_{tag}")
+        is_copy = lambda n: "copy" in n.lower() or "elementwise" in n.lower()
+        ck, nc = per_dispatch(copy_rows, is_copy, counter)
+        adj, na = per_dispatch(proj_rows, lambda n: "k_adj(" in n or "k_adjE" in n or
+                               n.split("(")[0].endswith("k_adj"), counter)
+        asum, ns = per_dispatch(proj_rows, lambda n: "k_adj_sum" in n, counter)
+        meta = json.load(open(os.path.join(pmc_dir, "copy_meta.json")))
+        true_bytes = meta["bytes_read"] if counter == "FETCH_SIZE" else meta["bytes_written"]
+        factor = ck * 1024.0 / true_bytes
+        res[counter] = {"copy_kib": ck, "copy_true_bytes": true_bytes, "factor": factor,
+                        "k_adj_kib": adj, "k_adj_sum_kib": asum,
+                        "bytes_per_launch": (adj + asum) * 1024.0 / factor,
+                        "dispatches": [nc, na, ns]}
+    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    out = {"kernel_hash": _kernel_hash(), "bytes_per_launch": round(total),
+           "counters": res, "pmc_dir": pmc_dir}
+    path = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -48,7 +48,8 @@ __global__ __launch_bounds__(256) void k_tv_fused(
              z_out + (2 * e) * N,
              z_out + (2 * e + 1) * N,
              gpad + e * P,
-             gpadT + e * P};
+             gpadT + e * P,
+             f + 2 * N + e * N};
     const size_t blk = (size_t)e * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x;
     tv_tile(blockIdx.y * kT, blockIdx.x * kT, m, partial + blk * 5, sc[e].pending != 0, nx, ny,
             rho, xi);
@@ -67,7 +68,8 @@ __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
 }
 
 // blocks [0, nbi): f -= alpha G (image); blocks [nbi, nbi+nbs): r -= alpha p
-// and per-block |r|^2.
+// and per-block |r|^2.  f, r and p hold their low parts after the two
+// energies' high parts ([4][N], [4][M]).
 __global__ __launch_bounds__(256) void k_update(float *__restrict__ f,
                                                 const float *__restrict__ gpad,
                                                 float *__restrict__ r, const float *__restrict__ p,
@@ -77,8 +79,10 @@ __global__ __launch_bounds__(256) void k_update(float *__restrict__ f,
     const int e = blockIdx.y;
     if (sc[e].stopped) return;
     const size_t N = (size_t)nx * ny, P = (size_t)(nx + 2 * kPad) * (ny + 2 * kPad);
-    update_chunk(blockIdx.x, f + e * N, gpad + e * P, r + (size_t)e * M, p + (size_t)e * M,
-                 p_rr + (size_t)e * nbs, (float)sc[e].alpha, nx, ny, M, nbi);
+    const size_t Ms = (size_t)M;
+    update_chunk(blockIdx.x, f + e * N, f + 2 * N + e * N, gpad + e * P, r + e * Ms,
+                 r + 2 * Ms + e * Ms, p + e * Ms, p + 2 * Ms + e * Ms, p_rr + (size_t)e * nbs,
+                 sc[e].alpha, nx, ny, M, nbi);
 }
 
 __global__ __launch_bounds__(256) void k_rr(AdmScalars *__restrict__ sc,
@@ -93,44 +97,22 @@ __global__ __launch_bounds__(256) void k_rr(AdmScalars *__restrict__ sc,
 // f = beta x0 (or 0), lambda = z = 0 for both parities.
 __global__ __launch_bounds__(256) void k_init_image(float *__restrict__ f,
                                                     const float *__restrict__ x0h,
-                                                    const float *__restrict__ x0l, float bh,
-                                                    float bl, float *__restrict__ lam,
+                                                    const float *__restrict__ x0l, double bh,
+                                                    double bl, float *__restrict__ lam,
                                                     float *__restrict__ z, size_t N)
 {
     const int e = blockIdx.y;
     size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
     const float *x0 = e == 0 ? x0h : x0l;
-    f[e * N + i] = x0 ? (e == 0 ? bh : bl) * x0[i] : 0.f;
+    const double d = x0 ? (e == 0 ? bh : bl) * (double)x0[i] : 0.0;
+    const float hi = (float)d;
+    f[e * N + i] = hi;                                  // f + flo = beta x0
+    f[2 * N + e * N + i] = (float)(d - (double)hi);
     for (int q = 0; q < 4; ++q) {  // [parity][energy][comp]: zero all of them
         lam[(size_t)q * N * 2 + (size_t)e * N + i] = 0.f;
         z[(size_t)q * N * 2 + (size_t)e * N + i] = 0.f;
     }
-}
-
-// r = r - beta m; per-block |r|^2.
-__global__ __launch_bounds__(256) void k_init_resid(float *__restrict__ r,
-                                                    const float *__restrict__ mh,
-                                                    const float *__restrict__ ml, float bh,
-                                                    float bl, int M, double *__restrict__ p_rr,
-                                                    int nbs)
-{
-    const int e = blockIdx.y;
-    const float *m = e == 0 ? mh : ml;
-    const float b = e == 0 ? bh : bl;
-    double acc[1] = {0.0};
-    for (int j = 0; j < 4; ++j) {
-        size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
-        if ((int)i < M) {
-            float nr = r[(size_t)e * M + i] - b * m[i];
-            r[(size_t)e * M + i] = nr;
-            acc[0] += (double)nr * nr;
-        }
-    }
-    __shared__ double tot[1];
-    block_sum<1>(acc, tot);
-    __syncthreads();
-    if (threadIdx.x == 0) p_rr[(size_t)e * nbs + blockIdx.x] = tot[0];
 }
 
 __global__ void k_init_scalars(AdmScalars *__restrict__ sc, double bh, double bl)
@@ -160,9 +142,10 @@ __global__ __launch_bounds__(256) void k_tv_only(const float *__restrict__ f,
         size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
         if (i < N) {
             int r = (int)(i / nx), c = (int)(i % nx);
-            float fc = f[e * N + i];
-            float dx = c >= 1 ? fc - f[e * N + i - 1] : 0.f;
-            float dy = r >= 1 ? fc - f[e * N + i - nx] : 0.f;
+            const float *fl = f + 2 * N;
+            float fc = f[e * N + i], lc = fl[e * N + i];
+            float dx = c >= 1 ? (fc - f[e * N + i - 1]) + (lc - fl[e * N + i - 1]) : 0.f;
+            float dy = r >= 1 ? (fc - f[e * N + i - nx]) + (lc - fl[e * N + i - nx]) : 0.f;
             v[0] += (double)sqrtf(dx * dx + dy * dy);
         }
     }
@@ -193,16 +176,17 @@ __global__ __launch_bounds__(256) void k_final_J(AdmScalars *__restrict__ sc,
     s.J = J;
 }
 
-// x = f / beta
+// x = (f + flo) / beta
 __global__ __launch_bounds__(256) void k_output(const float *__restrict__ f,
                                                 float *__restrict__ xh, float *__restrict__ xl,
-                                                float bh, float bl, size_t N)
+                                                double bh, double bl, size_t N)
 {
     const int e = blockIdx.y;
     size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
-    if (e == 0) xh[i] = f[i] / bh;
-    else xl[i] = f[N + i] / bl;
+    const double v = (double)f[e * N + i] + (double)f[2 * N + e * N + i];
+    if (e == 0) xh[i] = (float)(v / bh);
+    else xl[i] = (float)(v / bl);
 }
 
 }  // namespace
@@ -215,21 +199,17 @@ struct dect_adm_state {
     bool started = false;
     double mu = 0, rho = 0, xi = 0, bh = 1, bl = 1;
     int nvg = 1, nb_tv = 0, nb_fwd = 0, nbi = 0, nbs = 0, nb_img = 0;
-    dect::DevBuf f, h, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, adjcnt, sc, logbuf,
+    dect::DevBuf f, h, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, sc, logbuf,
         p_tvo;
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
     double graph_tol = -1.0;
-    const float *mh = nullptr, *ml = nullptr;  // measured sinograms of the current call
-    const void *graph_mh = nullptr, *graph_ml = nullptr;
-    int64_t done = 0;                            // iterations completed (host count)
-    hipGraphExec_t graph = nullptr, graph_ref = nullptr;
+    hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;
     int parity = 0;  // lambda/z buffer holding the current values
     ~dect_adm_state()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
-        if (graph_ref) (void)hipGraphExecDestroy(graph_ref);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -243,24 +223,21 @@ dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, con
                      hipStream_t s)
 {
     const size_t N = (size_t)t.key.nx * t.key.ny;
-    const int M = t.key.V * t.key.B;
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, P.sc, bh, bl);
     DECT_HIP(hipGetLastError());
     dim3 gi((unsigned)((N + 255) / 256), 2);
-    hipLaunchKernelGGL(k_init_image, gi, dim3(256), 0, s, P.f, x0h, x0l, (float)bh, (float)bl,
-                       P.lam, P.z, N);
+    hipLaunchKernelGGL(k_init_image, gi, dim3(256), 0, s, P.f, x0h, x0l, bh, bl, P.lam, P.z, N);
     DECT_HIP(hipGetLastError());
-    // r = A f - beta m (the padded G buffers serve as f's padded copies here)
+    // r + rlo = A f - beta m in FP64 (the padded G buffers serve as f's padded
+    // copies here), |r|^2 from the projector's per-block sums
     dect_status st = launch_pad(t, P.f, P.gpad, P.gpadT, 2, s);
     if (st) return st;
-    if ((st = launch_fwd(t, P.gpad, P.gpadT, P.r, 2, 1.0f, nullptr, s))) return st;
-    hipLaunchKernelGGL(k_init_resid, dim3(P.nbs, 2), dim3(256), 0, s, P.r, mh, ml, (float)bh,
-                       (float)bl, M, P.p_rr, P.nbs);
+    if ((st = launch_fwd(t, P.gpad, P.gpadT, P.r, 2, 1.0f, P.p_fwd, s, mh, ml, bh, bl, P.rlo)))
+        return st;
+    hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_fwd, P.nb_fwd,
+                       0, 0.0);
     DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_rr, P.nbs, 0,
-                       0.0);
-    DECT_HIP(hipGetLastError());
-    return launch_adj(t, P.r, P.h, P.adjpart, P.adjcnt, 2, (float)mu, s);
+    return launch_adj(t, P.r, P.h, P.adjpart, 2, (float)mu, s);
 }
 
 // Marks the start of a call's log (row 0 = the next iteration).
@@ -271,32 +248,13 @@ dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s)
     return DECT_OK;
 }
 
-// Re-derive the residual from the image, r = A f - beta m (formed in FP64 in
-// the projector and rounded once), replacing the recurrence's value, which
-// does not see the FP32 rounding of the f steps; |r|^2 from the projector's
-// per-block sums.
-dect_status adm_refresh(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
-                        double bh, double bl, hipStream_t s)
-{
-    dect_status st = launch_pad(t, P.f, P.gpad, P.gpadT, 2, s);
-    if (st) return st;
-    if ((st = launch_fwd(t, P.gpad, P.gpadT, P.r, 2, 1.0f, P.p_fwd, s, mh, ml, (float)bh,
-                         (float)bl)))
-        return st;
-    hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_fwd, P.nb_fwd,
-                       0, 0.0);
-    DECT_HIP(hipGetLastError());
-    return DECT_OK;
-}
-
 // x = f / beta and the final objective J(f^K) into the scalars and the log.
 dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
                        double bh, double bl, hipStream_t s)
 {
     const size_t N = (size_t)t.key.nx * t.key.ny;
     dim3 go((unsigned)((N + 255) / 256), 2);
-    hipLaunchKernelGGL(k_output, go, dim3(256), 0, s, (const float *)P.f, xh, xl, (float)bh,
-                       (float)bl, N);
+    hipLaunchKernelGGL(k_output, go, dim3(256), 0, s, (const float *)P.f, xh, xl, bh, bl, N);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_tv_only, dim3(P.nbi, 2), dim3(256), 0, s, (const float *)P.f, P.p_tvo,
                        t.key.nx, t.key.ny);
@@ -311,15 +269,18 @@ static AdmPtrs ptrs_of(dect_adm_state *S)
 {
     AdmPtrs P;
     P.f = (float *)S->f.ptr;
+    P.flo = P.f + 2 * (size_t)S->t->key.nx * S->t->key.ny;
     P.h = (float *)S->h.ptr;
+    const size_t M = (size_t)S->t->key.V * S->t->key.B;
     P.r = (float *)S->r.ptr;
+    P.rlo = P.r + 2 * M;
     P.p = (float *)S->p.ptr;
+    P.plo = P.p + 2 * M;
     P.lam = (float *)S->lam.ptr;
     P.z = (float *)S->z.ptr;
     P.gpad = (float *)S->gpad.ptr;
     P.gpadT = (float *)S->gpadT.ptr;
     P.adjpart = (float *)S->adjpart.ptr;
-    P.adjcnt = (int *)S->adjcnt.ptr;
     P.p_tv = (double *)S->p_tv.ptr;
     P.p_fwd = (double *)S->p_fwd.ptr;
     P.p_rr = (double *)S->p_rr.ptr;
@@ -348,8 +309,8 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
     S->nbi = (int)((N + 1023) / 1024);
     S->nbs = (int)((M + 1023) / 1024);
     S->nb_img = S->nbi;
-    if ((st = S->f.ensure(2 * N * 4)) || (st = S->h.ensure(2 * N * 4)) ||
-        (st = S->r.ensure(2 * M * 4)) || (st = S->p.ensure(2 * M * 4)) ||
+    if ((st = S->f.ensure(4 * N * 4)) || (st = S->h.ensure(2 * N * 4)) ||
+        (st = S->r.ensure(4 * M * 4)) || (st = S->p.ensure(4 * M * 4)) ||
         (st = S->lam.ensure(8 * N * 4)) || (st = S->z.ensure(8 * N * 4)) ||
         (st = S->gpad.ensure(2 * P * 4, true)) || (st = S->gpadT.ensure(2 * P * 4, true)) ||
         (st = S->p_tv.ensure((size_t)2 * S->nb_tv * 5 * 8)) ||
@@ -357,7 +318,6 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
         (st = S->p_rr.ensure((size_t)2 * S->nbs * 8)) ||
         (st = S->p_tvo.ensure((size_t)2 * S->nbi * 8)) ||
         (st = S->adjpart.ensure(std::max<size_t>(1, adj_partial_floats(t, 2)) * 4)) ||
-        (st = S->adjcnt.ensure(adj_counters(t, 2) * sizeof(int), true)) ||
         (st = S->sc.ensure(2 * sizeof(AdmScalars))))
         return st;
     return DECT_OK;
@@ -365,7 +325,7 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
 
 // Launch one iteration; `par` selects the lambda/z buffers holding the
 // current values.
-static dect_status launch_iter(dect_adm_state *S, int par, double tol, bool refresh, hipStream_t s)
+static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream_t s)
 {
     const GeomTables &t = *S->t;
     const int nx = t.key.nx, ny = t.key.ny;
@@ -381,8 +341,10 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, bool refr
                        (float *)S->gpad.ptr, (float *)S->gpadT.ptr, (double *)S->p_tv.ptr, sc,
                        nx, ny, (float)S->rho, (float)S->xi);
     DECT_HIP(hipGetLastError());
-    dect_status st = launch_fwd(t, (const float *)S->gpad.ptr, (const float *)S->gpadT.ptr,
-                                (float *)S->p.ptr, 2, 1.0f, (double *)S->p_fwd.ptr, s);
+    float *p = (float *)S->p.ptr;
+    dect_status st = launch_fwd(t, (const float *)S->gpad.ptr, (const float *)S->gpadT.ptr, p, 2,
+                                1.0f, (double *)S->p_fwd.ptr, s, nullptr, nullptr, 0.0, 0.0,
+                                p + 2 * (size_t)M);
     if (st) return st;
     hipLaunchKernelGGL(k_scalar, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_tv.ptr,
                        S->nb_tv, (const double *)S->p_fwd.ptr, S->nb_fwd,
@@ -395,9 +357,8 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, bool refr
     hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_rr.ptr, S->nbs, 1,
                        tol);
     DECT_HIP(hipGetLastError());
-    if (refresh && (st = adm_refresh(t, ptrs_of(S), S->mh, S->ml, S->bh, S->bl, s))) return st;
-    return launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr,
-                      (int *)S->adjcnt.ptr, 2, (float)S->mu, s);
+    return launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr, 2,
+                      (float)S->mu, s);
 }
 
 static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const float *mh,
@@ -415,17 +376,17 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     return DECT_OK;
 }
 
-static dect_status capture_pair(dect_adm_state *S, double tol, bool refresh_second,
-                                hipGraphExec_t *out)
+// The graph of an even/odd iteration pair.
+static dect_status build_graph(dect_adm_state *S, double tol)
 {
-    if (*out) {
-        (void)hipGraphExecDestroy(*out);
-        *out = nullptr;
+    if (S->graph) {
+        (void)hipGraphExecDestroy(S->graph);
+        S->graph = nullptr;
     }
     if (!S->cap) DECT_HIP(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
     DECT_HIP(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
-    dect_status st = launch_iter(S, 0, tol, false, S->cap);
-    if (!st) st = launch_iter(S, 1, tol, refresh_second, S->cap);
+    dect_status st = launch_iter(S, 0, tol, S->cap);
+    if (!st) st = launch_iter(S, 1, tol, S->cap);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(S->cap, &graph);
     if (st) {
@@ -433,19 +394,10 @@ static dect_status capture_pair(dect_adm_state *S, double tol, bool refresh_seco
         return st;
     }
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&S->graph, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     return DECT_OK;
-}
-
-// Two graphs of an even/odd iteration pair: plain, and with the residual
-// refresh after the second iteration.
-static dect_status build_graph(dect_adm_state *S, double tol)
-{
-    dect_status st = capture_pair(S, tol, false, &S->graph);
-    if (!st) st = capture_pair(S, tol, true, &S->graph_ref);
-    return st;
 }
 
 static std::mutex g_adm_mu;
@@ -494,10 +446,7 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     // the device log keeps at least 4096 rows so that calls of different
     // lengths reuse it (and the captured graph that points at it)
     if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, 4096) * 4 * sizeof(double)))) return st;
-    S->mh = mh;
-    S->ml = ml;
     if (!S->started) {
-        S->done = 0;
         const bool warm = (P->flags & DECT_WARM_START) != 0;
         if ((st = adm_start(S, P, mh, ml, warm ? xh : nullptr, warm ? xl : nullptr, s))) return st;
     }
@@ -505,34 +454,23 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     // the log buffer and tol are baked into the graph's kernel arguments:
     // rebuild only when they change
     if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
-                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol ||
-                   S->graph_mh != (const void *)mh || S->graph_ml != (const void *)ml)) {
+                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol)) {
         if ((st = build_graph(S, P->tol))) return st;
         S->graph_log = S->logbuf.ptr;
         S->graph_log_bytes = S->logbuf.bytes;
         S->graph_tol = P->tol;
-        S->graph_mh = mh;
-        S->graph_ml = ml;
     }
-    // the residual is re-derived from the image after every kRefresh-th
-    // iteration (absolute count, so split runs refresh at the same points)
-    auto refresh_after = [](int64_t k_abs) { return (k_abs + 1) % kRefresh == 0; };
     int k = 0;
     if (S->parity == 1 && K > 0) {  // realign so the graph starts on parity 0
-        if ((st = launch_iter(S, 1, P->tol, refresh_after(S->done), s))) return st;
+        if ((st = launch_iter(S, 1, P->tol, s))) return st;
         S->parity = 0;
         ++k;
-        ++S->done;
     }
-    for (; k + 2 <= K; k += 2) {
-        DECT_HIP(hipGraphLaunch(refresh_after(S->done + 1) ? S->graph_ref : S->graph, s));
-        S->done += 2;
-    }
+    for (; k + 2 <= K; k += 2) DECT_HIP(hipGraphLaunch(S->graph, s));
     if (k < K) {
-        if ((st = launch_iter(S, 0, P->tol, refresh_after(S->done), s))) return st;
+        if ((st = launch_iter(S, 0, P->tol, s))) return st;
         S->parity = 1;
         ++k;
-        ++S->done;
     }
     // outputs and the final objective
     if ((st = adm_finish(*S->t, ptrs_of(S), xh, xl, S->mu, S->bh, S->bl, s))) return st;

@@ -48,12 +48,18 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
     __syncthreads();
 }
 
-// Device pointers of one slice's ADM state (both energies).  Layouts: f, h
-// [2][N]; r, p [2][M]; lambda, z [parity][energy][comp][N]; gpad, gpadT
-// [2][(ny+4)(nx+4)] / [2][(nx+4)(ny+4)]; partials per energy and block.
+// Device pointers of one slice's ADM state (both energies).  Layouts: f, flo,
+// h [2][N]; r, rlo, p, plo [2][M]; lambda, z [parity][energy][comp][N];
+// gpad, gpadT [2][(ny+4)(nx+4)] / [2][(nx+4)(ny+4)]; partials per energy
+// and block.  The image and the residual r = A f - beta m are carried as
+// unevaluated sums of two FP32 values (f + flo, r + rlo, |lo| <= half an ulp
+// of the first part), and A G arrives as p + plo from the projector's FP64
+// sum; both updates are formed in FP64.  The iterates then take no FP32
+// rounding per step, which the iteration would amplify.  The projector,
+// the back-projector and the finite differences read FP32 values (f, r and
+// f + flo respectively).
 struct AdmPtrs {
-    float *f, *h, *r, *p, *lam, *z, *gpad, *gpadT, *adjpart;
-    int *adjcnt;
+    float *f, *flo, *h, *r, *rlo, *p, *plo, *lam, *z, *gpad, *gpadT, *adjpart;
     double *p_tv, *p_fwd, *p_rr, *p_tvo, *log;
     int log_rows;
     AdmScalars *sc;
@@ -64,12 +70,6 @@ dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, con
                      double mu, double bh, double bl, const float *x0h, const float *x0l,
                      hipStream_t s);
 dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s);
-dect_status adm_refresh(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
-                        double bh, double bl, hipStream_t s);
-
-// The residual r = A f - beta m is carried by the recurrence r -= alpha A G
-// and re-derived from f after every kRefresh-th iteration (even).
-constexpr int kRefresh = 10;
 dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
                        double bh, double bl, hipStream_t s);
 
@@ -77,6 +77,7 @@ dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *
 struct AdmImg {
     const float *f, *h, *lxi, *lyi, *zxi, *zyi;
     float *lxo, *lyo, *zxo, *zyo, *gpad, *gpadT;
+    const float *flo;
 };
 
 // ------------------------------------------------------------- tv_fused ---
@@ -86,7 +87,7 @@ struct AdmImg {
 __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part5,
                                         bool pending, int nx, int ny, float rho, float xi)
 {
-    __shared__ float sf[19][20];
+    __shared__ float sf[19][20], sl[19][20];
     __shared__ float swx[18][19], swy[18][19];
     __shared__ float sg[17][18];
     __shared__ double outv[5];
@@ -95,7 +96,9 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     for (int i = threadIdx.x; i < 19 * 19; i += 256) {
         int rr = i / 19, cc = i % 19;
         int r = r0 - 2 + rr, c = c0 - 2 + cc;
-        sf[rr][cc] = (r >= 0 && r < ny && c >= 0 && c < nx) ? m.f[(size_t)r * nx + c] : 0.f;
+        const bool in = r >= 0 && r < ny && c >= 0 && c < nx;
+        sf[rr][cc] = in ? m.f[(size_t)r * nx + c] : 0.f;
+        sl[rr][cc] = in ? m.flo[(size_t)r * nx + c] : 0.f;
     }
     __syncthreads();
 
@@ -106,9 +109,9 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
         float wx = 0.f, wy = 0.f;
         if (r >= 0 && r < ny && c >= 0 && c < nx) {
             size_t o = (size_t)r * nx + c;
-            float fc = sf[rr + 1][cc + 1];
-            float dx = c >= 1 ? fc - sf[rr + 1][cc] : 0.f;
-            float dy = r >= 1 ? fc - sf[rr][cc + 1] : 0.f;
+            float fc = sf[rr + 1][cc + 1], lc = sl[rr + 1][cc + 1];
+            float dx = c >= 1 ? (fc - sf[rr + 1][cc]) + (lc - sl[rr + 1][cc]) : 0.f;
+            float dy = r >= 1 ? (fc - sf[rr][cc + 1]) + (lc - sl[rr][cc + 1]) : 0.f;
             float lx = m.lxi[o], ly = m.lyi[o];
             if (pending) {
                 lx -= xi * (dx - m.zxi[o]);
@@ -223,13 +226,16 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
 }
 
 // ------------------------------------------------------------- update ---
-// Chunk bx of 1024 elements: bx < nbi updates the image f -= alpha G;
-// otherwise sinogram chunk bx - nbi: r -= alpha p, partial |r|^2 into
-// p_rr[bx - nbi].
+// Chunk bx of 1024 elements: bx < nbi updates the image (f + flo) -= alpha G
+// in FP64, split again into f + flo; otherwise sinogram chunk bx - nbi:
+// (r + rlo) -= alpha (p + plo) likewise, partial |r|^2 into p_rr[bx - nbi].
 __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
+                                             float *__restrict__ fle,
                                              const float *__restrict__ gpad_e,
-                                             float *__restrict__ re, const float *__restrict__ pe,
-                                             double *__restrict__ p_rr, float alpha, int nx,
+                                             float *__restrict__ re, float *__restrict__ rle,
+                                             const float *__restrict__ pe,
+                                             const float *__restrict__ ple,
+                                             double *__restrict__ p_rr, double alpha, int nx,
                                              int ny, int M, int nbi)
 {
     __shared__ double tot[1];
@@ -240,7 +246,11 @@ __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
             size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
             if (i < N) {
                 int rr = (int)(i / nx), cc = (int)(i % nx);
-                fe[i] -= alpha * gpad_e[(size_t)(rr + kPad) * pnx + cc + kPad];
+                const double g = gpad_e[(size_t)(rr + kPad) * pnx + cc + kPad];
+                const double d = ((double)fe[i] + (double)fle[i]) - alpha * g;
+                const float hi = (float)d;
+                fe[i] = hi;
+                fle[i] = (float)(d - (double)hi);
             }
         }
         return;  // uniform across the block
@@ -250,9 +260,12 @@ __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
     for (int j = 0; j < 4; ++j) {
         size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
         if ((int)i < M) {
-            float nr = re[i] - alpha * pe[i];
-            re[i] = nr;
-            acc[0] += (double)nr * nr;
+            const double d = ((double)re[i] + (double)rle[i]) -
+                             alpha * ((double)pe[i] + (double)ple[i]);
+            const float hi = (float)d;
+            re[i] = hi;
+            rle[i] = (float)(d - (double)hi);
+            acc[0] += d * d;
         }
     }
     block_sum<1>(acc, tot);

@@ -16,13 +16,12 @@
 namespace dect {
 
 struct SliceDev {
-    int nx, ny, V, B, nbundle, ntx, nvg, M;
+    int nx, ny, V, B, nbundle, nvg, M;
     const RayFwd *fwd;
     const RayAdj *adj;
     const float *len;
     const Bundle *bundles;
-    const ViewInfo *views;
-    AdjGeo geo;
+    const BinRange *bins;
     float rho, xi, muf;
     double mu, rhod, tol;
     AdmPtrs P;
@@ -38,7 +37,8 @@ __device__ __forceinline__ AdmImg img_of(const SliceDev &d, int e, int par)
     return AdmImg{d.P.f + e * N,          d.P.h + e * N,           lin + (2 * e) * N,
                   lin + (2 * e + 1) * N,  zin + (2 * e) * N,       zin + (2 * e + 1) * N,
                   lout + (2 * e) * N,     lout + (2 * e + 1) * N,  zout + (2 * e) * N,
-                  zout + (2 * e + 1) * N, d.P.gpad + e * Pp,       d.P.gpadT + e * Pp};
+                  zout + (2 * e + 1) * N, d.P.gpad + e * Pp,       d.P.gpadT + e * Pp,
+                  d.P.flo + e * N};
 }
 
 // item = (slice, energy, tile row, tile column)
@@ -73,12 +73,12 @@ __global__ __launch_bounds__(256) void kb_fwd(const SliceDev *__restrict__ S,
         if (!d.P.sc[e].stopped) {
             const size_t Pp = (size_t)(d.nx + 2 * kPad) * (d.ny + 2 * kPad);
             const int gw = blk * 4 + wid;
-            float result = 0.f;
+            double result = 0.0;
             if (gw < d.V * d.nbundle)
                 result = fwd_wave(d.P.gpad + e * Pp, d.P.gpadT + e * Pp, d.fwd, d.len, d.bundles,
                                   d.P.p + (size_t)e * d.M, d.nx, d.ny, d.B, d.nbundle, gw, lane,
-                                  1.0f);
-            double tot = block_sum_256((double)result * (double)result, red);
+                                  1.0f, nullptr, 0.0, d.P.plo + (size_t)e * d.M);
+            double tot = block_sum_256(result * result, red);
             if (threadIdx.x == 0) d.P.p_fwd[(size_t)e * d.P.nb_fwd + blk] = tot;
         }
         __syncthreads();
@@ -109,9 +109,11 @@ __global__ __launch_bounds__(256) void kb_update(const SliceDev *__restrict__ S,
         const int e = w.y;
         if (!d.P.sc[e].stopped) {
             const size_t N = (size_t)d.nx * d.ny, Pp = (size_t)(d.nx + 2 * kPad) * (d.ny + 2 * kPad);
-            update_chunk(w.z, d.P.f + e * N, d.P.gpad + e * Pp, d.P.r + (size_t)e * d.M,
-                         d.P.p + (size_t)e * d.M, d.P.p_rr + (size_t)e * d.P.nbs,
-                         (float)d.P.sc[e].alpha, d.nx, d.ny, d.M, d.P.nbi);
+            update_chunk(w.z, d.P.f + e * N, d.P.flo + e * N, d.P.gpad + e * Pp,
+                         d.P.r + (size_t)e * d.M, d.P.rlo + (size_t)e * d.M,
+                         d.P.p + (size_t)e * d.M, d.P.plo + (size_t)e * d.M,
+                         d.P.p_rr + (size_t)e * d.P.nbs, d.P.sc[e].alpha, d.nx, d.ny, d.M,
+                         d.P.nbi);
         }
         __syncthreads();
     }
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(256) void kb_rr(const SliceDev *__restrict__ S,
     }
 }
 
-// item = (slice, energy, tile, view group)
+// item = (slice, energy, strip of either ray class, view group)
 __global__ __launch_bounds__(256) void kb_adj(const SliceDev *__restrict__ S,
                                               const int4 *__restrict__ items, int n)
 {
@@ -136,15 +138,32 @@ __global__ __launch_bounds__(256) void kb_adj(const SliceDev *__restrict__ S,
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
-        const int e = w.y, tile = w.z, g = w.w;
-        const int ntiles = adj_tiles(d.nx, d.ny);
+        const int e = w.y, strip = w.z, g = w.w;
+        const size_t plane = (size_t)d.nx * d.ny;
+        const int cls = strip < adj_strips_x(d.nx, d.ny) ? 0 : 1;
         if (!d.P.sc[e].stopped)
-            adj_block(sh, d.P.r + (size_t)e * d.M, d.adj, d.len, d.views, d.geo, d.nx, d.ny, d.V,
-                      d.B, tile, g, d.nvg, d.P.h + (size_t)e * d.nx * d.ny,
-                      d.nvg > 1 ? d.P.adjpart + ((size_t)e * ntiles + tile) * d.nvg * kTilePix
-                                : nullptr,
-                      d.P.adjcnt + e * ntiles + tile, d.muf);
+            adj_block(sh, d.P.r + (size_t)e * d.M, d.adj, d.len, d.bins, d.nx, d.ny, d.V, d.B,
+                      strip, g, d.nvg,
+                      d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane);
         __syncthreads();
+    }
+}
+
+// item = (slice, energy, chunk of 1024 pixels): h = mu * (sum of the partials)
+__global__ __launch_bounds__(256) void kb_adj_sum(const SliceDev *__restrict__ S,
+                                                  const int4 *__restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        const SliceDev &d = S[w.x];
+        const int e = w.y;
+        if (d.P.sc[e].stopped) continue;
+        const size_t plane = (size_t)d.nx * d.ny;
+        const float *pe = d.P.adjpart + (size_t)e * 2 * d.nvg * plane;
+        for (int j = 0; j < 4; ++j) {
+            const size_t i = (size_t)w.z * 1024 + j * 256 + threadIdx.x;
+            if (i < plane) d.P.h[(size_t)e * plane + i] = adj_sum_pixel(pe, plane, d.nvg, i) * d.muf;
+        }
     }
 }
 
@@ -157,18 +176,15 @@ struct dect_batch {
     std::vector<dect_adm_params> prm;
     std::vector<dect::SliceDev> host;
     std::vector<size_t> off;  // arena offsets per slice
-    dect::DevBuf arena, slices, w_tv, w_fwd, w_se, w_upd, w_adj;
-    int n_tv = 0, n_fwd = 0, n_se = 0, n_upd = 0, n_adj = 0;
-    int g_tv = 0, g_fwd = 0, g_se = 0, g_upd = 0, g_adj = 0;
+    dect::DevBuf arena, slices, w_tv, w_fwd, w_se, w_upd, w_adj, w_sum;
+    int n_tv = 0, n_fwd = 0, n_se = 0, n_upd = 0, n_adj = 0, n_sum = 0;
+    int g_tv = 0, g_fwd = 0, g_se = 0, g_upd = 0, g_adj = 0, g_sum = 0;
     int nvg_max = 16, group_choice = 0;  // 0: per-slice heuristic, else fixed
-    const float *const *mh = nullptr, *const *ml = nullptr;  // current call's sinograms
-    std::vector<const float *> graph_m;                       // the ones the graphs hold
-    hipGraphExec_t graph = nullptr, graph_ref = nullptr;
+    hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;
     ~dect_batch()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
-        if (graph_ref) (void)hipGraphExecDestroy(graph_ref);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -183,7 +199,7 @@ int heuristic_groups(const GeomTables &t) { return adj_groups(t, 2); }
 // Work lists and persistent grid sizes for the current view-group choice.
 dect_status build_work(dect_batch *b)
 {
-    std::vector<std::pair<double, int4>> tv, fwd, se, upd, adj;
+    std::vector<std::pair<double, int4>> tv, fwd, se, upd, adj, sum;
     for (int s = 0; s < b->n; ++s) {
         SliceDev &d = b->host[s];
         const GeomTables &t = *b->t[s];
@@ -193,7 +209,8 @@ dect_status build_work(dect_batch *b)
                                   : heuristic_groups(t);
         d.nvg = nvg;
         const int gx = (d.nx + kT - 1) / kT, gy = (d.ny + kT - 1) / kT;
-        const int ntiles = adj_tiles(d.nx, d.ny);
+        const int nstrips = adj_strips(d.nx, d.ny);
+        const int nchunks = (d.nx * d.ny + 1023) / 1024;
         for (int e = 0; e < 2; ++e) {
             for (int ty = 0; ty < gy; ++ty)
                 for (int tx = 0; tx < gx; ++tx) tv.push_back({1.0, make_int4(s, e, ty, tx)});
@@ -201,9 +218,10 @@ dect_status build_work(dect_batch *b)
                 fwd.push_back({(double)std::max(d.nx, d.ny), make_int4(s, e, k, 0)});
             se.push_back({1.0, make_int4(s, e, 0, 0)});
             for (int k = 0; k < d.P.nbi + d.P.nbs; ++k) upd.push_back({1.0, make_int4(s, e, k, 0)});
-            for (int tile = 0; tile < ntiles; ++tile)
+            for (int strip = 0; strip < nstrips; ++strip)
                 for (int g = 0; g < nvg; ++g)
-                    adj.push_back({(double)d.V / nvg, make_int4(s, e, tile, g)});
+                    adj.push_back({(double)d.V / nvg, make_int4(s, e, strip, g)});
+            for (int k = 0; k < nchunks; ++k) sum.push_back({(double)nvg, make_int4(s, e, k, 0)});
         }
     }
     auto upload = [&](std::vector<std::pair<double, int4>> &v, DevBuf &buf, int &count) {
@@ -220,7 +238,7 @@ dect_status build_work(dect_batch *b)
     dect_status st;
     if ((st = upload(tv, b->w_tv, b->n_tv)) || (st = upload(fwd, b->w_fwd, b->n_fwd)) ||
         (st = upload(se, b->w_se, b->n_se)) || (st = upload(upd, b->w_upd, b->n_upd)) ||
-        (st = upload(adj, b->w_adj, b->n_adj)))
+        (st = upload(adj, b->w_adj, b->n_adj)) || (st = upload(sum, b->w_sum, b->n_sum)))
         return st;
     DECT_HIP(hipMemcpy(b->slices.ptr, b->host.data(), b->host.size() * sizeof(SliceDev),
                        hipMemcpyHostToDevice));
@@ -238,18 +256,15 @@ dect_status build_work(dect_batch *b)
     b->g_se = std::max(1, b->n_se);
     b->g_upd = grid((const void *)kb_update, b->n_upd);
     b->g_adj = grid((const void *)kb_adj, b->n_adj);
+    b->g_sum = grid((const void *)kb_adj_sum, b->n_sum);
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
-    if (b->graph_ref) {
-        (void)hipGraphExecDestroy(b->graph_ref);
-        b->graph_ref = nullptr;
-    }
     return DECT_OK;
 }
 
-dect_status launch_batch_iter(dect_batch *b, int par, bool refresh, hipStream_t s)
+dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
 {
     const SliceDev *S = (const SliceDev *)b->slices.ptr;
     hipLaunchKernelGGL(kb_tv, dim3(b->g_tv), dim3(256), 0, s, S, (const int4 *)b->w_tv.ptr, b->n_tv,
@@ -267,30 +282,23 @@ dect_status launch_batch_iter(dect_batch *b, int par, bool refresh, hipStream_t 
     hipLaunchKernelGGL(kb_rr, dim3(b->g_se), dim3(256), 0, s, S, (const int4 *)b->w_se.ptr,
                        b->n_se);
     DECT_HIP(hipGetLastError());
-    if (refresh) {  // same schedule and kernels as the single-slice path
-        for (int i = 0; i < b->n; ++i) {
-            const dect_adm_params &p = b->prm[i];
-            dect_status st = adm_refresh(*b->t[i], b->host[i].P, b->mh[i], b->ml[i], p.beta_high,
-                                         p.beta_low, s);
-            if (st) return st;
-        }
-    }
     hipLaunchKernelGGL(kb_adj, dim3(b->g_adj), dim3(256), 0, s, S, (const int4 *)b->w_adj.ptr,
                        b->n_adj);
+    DECT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(kb_adj_sum, dim3(b->g_sum), dim3(256), 0, s, S, (const int4 *)b->w_sum.ptr,
+                       b->n_sum);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
 
-dect_status capture_pair(dect_batch *b, bool refresh_second, hipGraphExec_t *out)
+// The graph of an even/odd iteration pair (rebuilt when the work lists change).
+dect_status batch_graph(dect_batch *b)
 {
-    if (*out) {
-        (void)hipGraphExecDestroy(*out);
-        *out = nullptr;
-    }
+    if (b->graph) return DECT_OK;
     if (!b->cap) DECT_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     DECT_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    dect_status st = launch_batch_iter(b, 0, false, b->cap);
-    if (!st) st = launch_batch_iter(b, 1, refresh_second, b->cap);
+    dect_status st = launch_batch_iter(b, 0, b->cap);
+    if (!st) st = launch_batch_iter(b, 1, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (st) {
@@ -298,37 +306,18 @@ dect_status capture_pair(dect_batch *b, bool refresh_second, hipGraphExec_t *out
         return st;
     }
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("batch capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("batch instantiate: ") + hipGetErrorString(e));
     return DECT_OK;
 }
 
-// Graphs of an even/odd iteration pair, plain and with the residual refresh
-// after the second; rebuilt when the work lists or the sinograms change.
-dect_status batch_graph(dect_batch *b)
-{
-    std::vector<const float *> m(2 * b->n);
-    for (int i = 0; i < b->n; ++i) {
-        m[2 * i] = b->mh[i];
-        m[2 * i + 1] = b->ml[i];
-    }
-    if (b->graph && b->graph_ref && m == b->graph_m) return DECT_OK;
-    dect_status st = capture_pair(b, false, &b->graph);
-    if (!st) st = capture_pair(b, true, &b->graph_ref);
-    if (!st) b->graph_m = m;
-    return st;
-}
-
 // Start every slice (f = 0) and run `iters` iterations (even/odd pairs from
-// the graphs, an odd last one launched directly); the residual is refreshed
-// after the same iterations as in the single-slice path.
+// the graph, an odd last one launched directly).
 dect_status batch_run(dect_batch *b, const float *const *mh, const float *const *ml, int iters,
                       hipStream_t s)
 {
     dect_status st;
-    b->mh = mh;
-    b->ml = ml;
     for (int i = 0; i < b->n; ++i) {
         const dect_adm_params &p = b->prm[i];
         if ((st = adm_init(*b->t[i], b->host[i].P, mh[i], ml[i], p.mu, p.beta_high, p.beta_low,
@@ -338,9 +327,8 @@ dect_status batch_run(dect_batch *b, const float *const *mh, const float *const 
     }
     if ((st = batch_graph(b))) return st;
     int k = 0;
-    for (; k + 2 <= iters; k += 2)
-        DECT_HIP(hipGraphLaunch((k + 2) % kRefresh == 0 ? b->graph_ref : b->graph, s));
-    if (k < iters && (st = launch_batch_iter(b, 0, (k + 1) % kRefresh == 0, s))) return st;
+    for (; k + 2 <= iters; k += 2) DECT_HIP(hipGraphLaunch(b->graph, s));
+    if (k < iters && (st = launch_batch_iter(b, 0, s))) return st;
     return DECT_OK;
 }
 
@@ -359,7 +347,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
     b->off.resize(n + 1);
     dect_status st;
     size_t total = 0;
-    struct Sizes { size_t N, M, Pp, nb_tv, nb_fwd, nbi, nbs, part, cnt; };
+    struct Sizes { size_t N, M, Pp, nb_tv, nb_fwd, nbi, nbs, part; };
     std::vector<Sizes> sz(n);
     for (int i = 0; i < n; ++i) {
         const dect_adm_params &p = prm[i];
@@ -375,15 +363,13 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         z.nb_fwd = (size_t)fwd_blocks(t);
         z.nbi = (z.N + 1023) / 1024;
         z.nbs = (z.M + 1023) / 1024;
-        const size_t tiles = (size_t)adj_tiles(t.key.nx, t.key.ny);
-        z.part = 2 * tiles * std::max(b->nvg_max, adj_groups(t, 2)) * kTilePix;
-        z.cnt = 2 * tiles;
+        z.part = adj_partial_floats(t, 2, std::max(b->nvg_max, adj_groups(t, 2)));
         size_t bytes = 0;
-        bytes += align256(2 * z.N * 4) * 2;         // f, h
-        bytes += align256(2 * z.M * 4) * 2;         // r, p
+        bytes += align256(4 * z.N * 4) + align256(2 * z.N * 4);  // f (+ flo), h
+        bytes += align256(4 * z.M * 4) * 2;         // r (+ rlo), p (+ plo)
         bytes += align256(8 * z.N * 4) * 2;         // lam, z
         bytes += align256(2 * z.Pp * 4) * 2;        // gpad, gpadT
-        bytes += align256(z.part * 4) + align256(z.cnt * 4);
+        bytes += align256(z.part * 4);
         bytes += align256(2 * z.nb_tv * 5 * 8) + align256(2 * z.nb_fwd * 8) +
                  align256(2 * z.nbs * 8) + align256(2 * z.nbi * 8);
         bytes += align256(2 * sizeof(AdmScalars));
@@ -391,7 +377,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         total += bytes;
     }
     b->off[n] = total;
-    if ((st = b->arena.ensure(total, true))) return st;  // zero: counters and pad borders
+    if ((st = b->arena.ensure(total, true))) return st;  // zero: pad borders
     if ((st = b->slices.ensure(n * sizeof(SliceDev)))) return st;
     for (int i = 0; i < n; ++i) {
         const GeomTables &t = *b->t[i];
@@ -404,16 +390,18 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         };
         SliceDev &d = b->host[i];
         std::memset(&d, 0, sizeof(d));
-        d.P.f = (float *)take(2 * z.N * 4);
+        d.P.f = (float *)take(4 * z.N * 4);
+        d.P.flo = d.P.f + 2 * z.N;
         d.P.h = (float *)take(2 * z.N * 4);
-        d.P.r = (float *)take(2 * z.M * 4);
-        d.P.p = (float *)take(2 * z.M * 4);
+        d.P.r = (float *)take(4 * z.M * 4);
+        d.P.rlo = d.P.r + 2 * z.M;
+        d.P.p = (float *)take(4 * z.M * 4);
+        d.P.plo = d.P.p + 2 * z.M;
         d.P.lam = (float *)take(8 * z.N * 4);
         d.P.z = (float *)take(8 * z.N * 4);
         d.P.gpad = (float *)take(2 * z.Pp * 4);
         d.P.gpadT = (float *)take(2 * z.Pp * 4);
         d.P.adjpart = (float *)take(z.part * 4);
-        d.P.adjcnt = (int *)take(z.cnt * 4);
         d.P.p_tv = (double *)take(2 * z.nb_tv * 5 * 8);
         d.P.p_fwd = (double *)take(2 * z.nb_fwd * 8);
         d.P.p_rr = (double *)take(2 * z.nbs * 8);
@@ -431,13 +419,11 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         d.B = t.key.B;
         d.M = (int)z.M;
         d.nbundle = t.nbundle;
-        d.ntx = adj_tiles_x(t.key.nx);
         d.fwd = t.fwd;
         d.adj = t.adj;
         d.len = t.len;
         d.bundles = t.bundles;
-        d.views = t.views;
-        d.geo = adj_geometry(t);
+        d.bins = t.adj_bins;
         d.rho = (float)prm[i].rho;
         d.xi = (float)prm[i].xi;
         d.muf = (float)prm[i].mu;

@@ -56,6 +56,28 @@ struct ViewInfo {
 constexpr int kBundle = 64;   // bins per forward wavefront
 constexpr int kPad = 2;       // zero border of the padded image copies
 
+// Adjoint strips.  The two ray classes are gathered separately: x-major rays
+// on strips of kSW image rows x kSL columns (lane = column, taps along the
+// rows), y-major rays on strips of kSW columns x kSL rows (lane = row, taps
+// along the columns) -- the same walk on the transposed image.  Strips are
+// numbered x-major first: strip = ts * ceil(n_lane / kSL) + ls within a class.
+constexpr int kSL = 64;  // strip length along the lane axis (one wavefront)
+constexpr int kSW = 32;  // strip width along the tap axis
+__host__ __device__ inline int adj_strips_cls(int n_lane, int n_tap)
+{
+    return ((n_lane + kSL - 1) / kSL) * ((n_tap + kSW - 1) / kSW);
+}
+__host__ __device__ inline int adj_strips_x(int nx, int ny) { return adj_strips_cls(nx, ny); }
+__host__ __device__ inline int adj_strips(int nx, int ny)
+{
+    return adj_strips_cls(nx, ny) + adj_strips_cls(ny, nx);
+}
+// Bins [lo, hi] of one view whose rays put a tap inside one strip (empty:
+// lo > hi); exact, from the fixed-point ray table.
+struct BinRange {
+    int32_t lo, hi;
+};
+
 struct GeomKey {
     int32_t nx, ny, V, B;
     double pixel, bin, off, sod, sdd;
@@ -73,6 +95,7 @@ struct GeomTables {
     float *len = nullptr;      // [V*B] path length per driving line (pixel/|cos|)
     Bundle *bundles = nullptr; // [V*nbundle]
     ViewInfo *views = nullptr; // [V]
+    BinRange *adj_bins = nullptr;  // [adj_strips][V]
     int64_t samples = 0;       // Joseph samples with q in (-1, n)
     ~GeomTables();
 };
@@ -96,8 +119,8 @@ struct DevBuf {
 // ------------------------------------------------------------ projector ---
 struct ProjWork {
     // padded copies [batch][ny+4][nx+4] and transposed [batch][nx+4][ny+4];
-    // adjoint view-group partial tiles and their completion counters
-    DevBuf pad, padT, partial, norm;
+    // adjoint partial images (per ray class and view group)
+    DevBuf pad, padT, partial;
 };
 
 // img [batch][ny][nx] -> both padded layouts (borders stay zero).
@@ -106,20 +129,19 @@ dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float 
 // sino[e] = scale * A img[e] from the padded layouts.  norm_partial (may be
 // NULL) receives per-block sums of squares (double) for a later reduction.
 // With sub0/sub1 (items 0 and 1), sino[e] = scale * A img[e] - ss_e * sub_e,
-// formed in FP64 and rounded once.
+// formed in FP64 and rounded once; with lo, lo[e] receives the rounding
+// remainder of every value (same layout as sino).
 dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
                        int batch, float scale, double *norm_partial, hipStream_t s,
                        const float *sub0 = nullptr, const float *sub1 = nullptr,
-                       float ss0 = 0.f, float ss1 = 0.f);
+                       double ss0 = 0.0, double ss1 = 0.0, float *lo = nullptr);
 int fwd_blocks(const GeomTables &t);
-// img[e] = scale * A^T sino[e].  With several view groups (adj_groups > 1)
-// partial holds adj_partial_floats() floats and counters adj_counters() ints
-// that must be zero before the first launch (the kernel leaves them zero).
+// img[e] = scale * A^T sino[e], through `partial`: adj_partial_floats()
+// floats of scratch (per item, both ray classes and every view group).
 int adj_groups(const GeomTables &t, int batch);
-size_t adj_partial_floats(const GeomTables &t, int batch);
-size_t adj_counters(const GeomTables &t, int batch);
+size_t adj_partial_floats(const GeomTables &t, int batch, int nvg = 0);
 dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float *partial,
-                       int *counters, int batch, float scale, hipStream_t s);
+                       int batch, float scale, hipStream_t s);
 
 dect_status project(const dect_geometry *g, const float *img, float *sino, int batch,
                     hipStream_t s);

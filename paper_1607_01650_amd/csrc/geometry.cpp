@@ -58,6 +58,7 @@ GeomTables::~GeomTables()
     if (len) (void)hipFree(len);
     if (bundles) (void)hipFree(bundles);
     if (views) (void)hipFree(views);
+    if (adj_bins) (void)hipFree(adj_bins);
 }
 
 dect_status validate_geometry(const dect_geometry *g)
@@ -229,6 +230,71 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
         }
     }
 
+    // Adjoint bin ranges: for every strip and view, the bins of the strip's
+    // ray class whose rays put a tap inside the strip.  A first guess comes
+    // from projecting the strip's corners onto the detector; both ends are
+    // then settled exactly on the fixed-point ray table (a ray hits the strip
+    // when its line coordinate q, linear along the lane axis, enters the tap
+    // interval (t0 - 1, t0 + kSW) somewhere on the strip's lanes).
+    const int nsx = adj_strips_x(nx, ny), nst = adj_strips(nx, ny);
+    if ((double)nst * V * sizeof(BinRange) > (double)(size_t(1) << 30))
+        return fail(DECT_ERR_GEOMETRY, "geometry too large for the back-projector's bin table");
+    std::vector<BinRange> bins((size_t)nst * V);
+    const int64_t one = int64_t(1) << 32;
+    for (int v = 0; v < V; ++v) {
+        const double th = g->angles_rad ? g->angles_rad[v] : 2.0 * M_PI * v / V;
+        const double ct = std::cos(th), st = std::sin(th);
+        auto beta = [&](double px, double py) {
+            const double pu = -px * st + py * ct, ps = px * ct + py * st;
+            return (D * pu / (R - ps) - g->det_offset_mm) / g->bin_mm + (B - 1) / 2.0;
+        };
+        for (int sI = 0; sI < nst; ++sI) {
+            const int cls = sI < nsx ? 0 : 1, sidx = cls ? sI - nsx : sI;
+            const int nL = cls ? ny : nx, nT = cls ? nx : ny;
+            const int nsL = (nL + kSL - 1) / kSL;
+            const int t0 = (sidx / nsL) * kSW, l0 = (sidx % nsL) * kSL;
+            const int l1 = std::min(l0 + kSL - 1, nL - 1);
+            const int cb0 = cls ? views[v].yb0 : views[v].xb0;
+            const int cb1 = cls ? views[v].yb1 : views[v].xb1;
+            BinRange r{1, 0};
+            if (cb0 < cb1) {
+                const int64_t qlo = (int64_t)(t0 - 1) * one, qhi = (int64_t)(t0 + kSW) * one;
+                auto hit = [&](int b) {
+                    const RayFwd &f = fwd[(size_t)v * B + b];
+                    const int64_t qa = f.a_fx + f.k_fx * l0, qb = f.a_fx + f.k_fx * l1;
+                    return std::max(qa, qb) > qlo && std::min(qa, qb) < qhi;
+                };
+                auto mm = [&](int i, int n) { return (i - (n - 1) / 2.0) * dl; };
+                double bmin = 1e300, bmax = -1e300;
+                for (int li : {l0, l1})
+                    for (int ti : {t0 - 1, std::min(t0 + kSW, nT)}) {
+                        const double px = cls ? mm(ti, nx) : mm(li, nx);
+                        const double py = cls ? mm(li, ny) : mm(ti, ny);
+                        const double bb = beta(px, py);
+                        bmin = std::min(bmin, bb);
+                        bmax = std::max(bmax, bb);
+                    }
+                int lo = (int)std::max((double)cb0, std::min((double)cb1 - 1, std::floor(bmin) - 2));
+                int hi = (int)std::max((double)cb0, std::min((double)cb1 - 1, std::ceil(bmax) + 2));
+                while (lo <= hi && !hit(lo)) ++lo;
+                while (hi >= lo && !hit(hi)) --hi;
+                if (lo > hi) {  // the guess missed: scan the class range
+                    for (int b = cb0; b < cb1; ++b)
+                        if (hit(b)) {
+                            if (lo > hi) lo = hi = b;
+                            else hi = b;
+                        }
+                }
+                if (lo <= hi) {
+                    while (lo > cb0 && hit(lo - 1)) --lo;
+                    while (hi < cb1 - 1 && hit(hi + 1)) ++hi;
+                    r = BinRange{lo, hi};
+                }
+            }
+            bins[(size_t)sI * V + v] = r;
+        }
+    }
+
     auto t = std::make_unique<GeomTables>();
     t->key = key;
     t->nbundle = nb;
@@ -238,12 +304,15 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     DECT_HIP(hipMalloc(&t->len, len.size() * sizeof(float)));
     DECT_HIP(hipMalloc(&t->bundles, bun.size() * sizeof(Bundle)));
     DECT_HIP(hipMalloc(&t->views, views.size() * sizeof(ViewInfo)));
+    DECT_HIP(hipMalloc(&t->adj_bins, bins.size() * sizeof(BinRange)));
     DECT_HIP(hipMemcpy(t->fwd, fwd.data(), fwd.size() * sizeof(RayFwd), hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->adj, adj.data(), adj.size() * sizeof(RayAdj), hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->len, len.data(), len.size() * sizeof(float), hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->bundles, bun.data(), bun.size() * sizeof(Bundle),
                        hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->views, views.data(), views.size() * sizeof(ViewInfo),
+                       hipMemcpyHostToDevice));
+    DECT_HIP(hipMemcpy(t->adj_bins, bins.data(), bins.size() * sizeof(BinRange),
                        hipMemcpyHostToDevice));
     *out = t.get();
     g_cache.push_back(std::move(t));

@@ -6,26 +6,19 @@
 
 namespace dect {
 
-// Adjoint tiling: a block owns a kTW x kTH output tile, each of its four
-// wavefronts a kSH-row strip of it, accumulated in LDS with one spare row and
-// one spare column that absorb out-of-strip contributions (branch-free).
-constexpr int kTW = 64;                  // tile width (columns) = lanes
-constexpr int kSH = 32;                  // rows per wavefront strip
-constexpr int kTH = 4 * kSH;             // tile height (rows)
-constexpr int kAccLd = kTW + 1;          // strip row stride; column kTW is spare
-constexpr int kAccSize = (kSH + 1) * kAccLd;  // row kSH is spare
-constexpr int kTilePix = kTW * kTH;
-constexpr int kStage = 256;              // bins staged per block and view chunk
+// Adjoint accumulation: a block's four wavefronts share one strip and split
+// its view group between them; each adds into its own LDS copy of the strip,
+// stored tap-line-major with row stride kSL (the 64 lanes of an access hit
+// distinct banks) plus a spare line on each side for the taps that fall just
+// outside the strip.
+constexpr int kAccRows = kSW + 2;
+constexpr int kAccSize = kAccRows * kSL;
+constexpr int kAdjWaves = 4;
 
 struct AdjShared {
-    float acc[4][kAccSize];
-    double2 ak[kStage];  // (a, k) of the staged bins
-    float ly[kStage];    // |path length per line| * sinogram value
-    int is_last;
+    float acc[kAdjWaves][kAccSize];
 };
 
-__host__ __device__ inline int adj_tiles_x(int nx) { return (nx + kTW - 1) / kTW; }
-__host__ __device__ inline int adj_tiles(int nx, int ny) { return adj_tiles_x(nx) * ((ny + kTH - 1) / kTH); }
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
 // ------------------------------------------------------------ forward ---
@@ -45,7 +38,9 @@ __device__ __forceinline__ void walk(const float *__restrict__ base, int step, i
         const double v0 = line[h];
         const double v1 = line[h + 1];
         acc0 += v0;
-        acc1 = fma((double)lo, v1 - v0, acc1);  // product of a 32-bit and a 25-bit value
+        // the weight is the FP32 value (float)lo * 2^-32 that the adjoint also
+        // uses, so the two passes apply the same matrix
+        acc1 = fma((double)(float)lo, v1 - v0, acc1);
         q += dq;
         line += step;
     }
@@ -53,12 +48,14 @@ __device__ __forceinline__ void walk(const float *__restrict__ base, int step, i
 
 // One forward wavefront: view v and 64-bin bundle j from the wave index gw
 // (= v * nbundle + j) of one batch item.  pad_e/padT_e: that item's padded
-// image copies, sino_e its sinogram.  The ray sum is accumulated in FP64 and
-// rounded once (an FP32 running sum over ~700 samples would carry ~1e-6
-// relative error, which the reconstruction iteration amplifies).  With sub_e
-// the stored value is scale * (A x) - sub_scale * sub_e, also rounded once.
-// Returns this lane's value (0 when the lane has no ray) after writing it.
-__device__ __forceinline__ float fwd_wave(const float *__restrict__ pad_e,
+// image copies, sino_e its sinogram.  The ray sum is accumulated in FP64 (an
+// FP32 running sum over ~700 samples would carry ~1e-6 relative error, which
+// the reconstruction iteration amplifies).  With sub_e the value is
+// scale * (A x) - sub_scale * sub_e, formed in FP64.  sino_e receives the
+// value rounded to FP32 and, when lo_e is given, lo_e the rounding remainder
+// (so that sino_e + lo_e carries the FP64 value to ~2^-48).  Returns this
+// lane's FP64 value (0 when the lane has no ray).
+__device__ __forceinline__ double fwd_wave(const float *__restrict__ pad_e,
                                           const float *__restrict__ padT_e,
                                           const RayFwd *__restrict__ rays,
                                           const float *__restrict__ len,
@@ -66,7 +63,8 @@ __device__ __forceinline__ float fwd_wave(const float *__restrict__ pad_e,
                                           float *__restrict__ sino_e, int nx, int ny, int B,
                                           int nbundle, int gw, int lane, float scale,
                                           const float *__restrict__ sub_e = nullptr,
-                                          float sub_scale = 0.f)
+                                          double sub_scale = 0.0,
+                                          float *__restrict__ lo_e = nullptr)
 {
     const int v = gw / nbundle, j = gw - v * nbundle;
     const int b = j * kBundle + lane;
@@ -95,10 +93,13 @@ __device__ __forceinline__ float fwd_wave(const float *__restrict__ pad_e,
              acc1);
     }
     double sum = (double)fabsf(L) * fma(acc1, (double)kTwoM32, acc0) * (double)scale;
-    if (sub_e && act) sum -= (double)sub_scale * (double)sub_e[(size_t)v * B + b];
-    const float result = (float)sum;
-    if (act) sino_e[(size_t)v * B + b] = result;
-    return act ? result : 0.f;
+    if (sub_e && act) sum -= sub_scale * (double)sub_e[(size_t)v * B + b];
+    const float hi = (float)sum;
+    if (act) {
+        sino_e[(size_t)v * B + b] = hi;
+        if (lo_e) lo_e[(size_t)v * B + b] = (float)(sum - (double)hi);
+    }
+    return act ? sum : 0.0;
 }
 
 // Fixed-order sum of one double per thread over a 256-thread block; the
@@ -117,174 +118,116 @@ __device__ __forceinline__ double block_sum_256(double v, double *red)
 }
 
 // ------------------------------------------------------------ adjoint ---
-struct AdjGeo {
-    float R, D, inv_du, beta0;  // beta(p) = D (p.e_u) / (R - p.e_s) * inv_du + beta0
-    float dl, xoff, yoff;       // pixel centre x = c*dl - xoff, y = r*dl - yoff
-    float margin;
-};
-
-// Detector projection constants of a geometry for the adjoint (host).
-AdjGeo adj_geometry(const GeomTables &t);
-
-__device__ __forceinline__ float beta_of(const AdjGeo &g, float ct, float st, float px, float py)
-{
-    float pu = -px * st + py * ct;
-    float ps = px * ct + py * st;
-    return g.D * pu / (g.R - ps) * g.inv_du + g.beta0;
-}
-
-// The whole adjoint block for output tile `tile` of one batch item, view
-// group g of nvg: sino_e/out_e are the item's sinogram and image.  Per view
-// the block stages the bins whose rays can reach its tile (their (a, k) and
-// |L| y) in LDS; then, per wavefront strip, x-major rays are walked by
-// column (lane = column) and y-major rays by row (lane = row within the strip
-// and column half).  With nvg > 1, tiles_part holds this (item, tile)'s nvg
-// parked tiles and counter its completion counter (zero between launches);
-// the last group to finish sums the parked tiles in group order.
+// One adjoint block: strip `strip` (combined numbering) of one batch item,
+// view group g of nvg.  The block's partial image of this (class, group) is
+// written to `part` (a full [ny][nx] plane, normal layout; only this strip's
+// pixels).  Per view, each wavefront walks the bins `bins` lists for its
+// strip: up to 64 bins' ray data are loaded at once (lane j holds bin j) and
+// broadcast bin by bin; every lane evaluates the ray on its own driving line
+// and adds the two interpolation taps, which lie on consecutive tap lines,
+// with one paired LDS read and write (no atomics: the copy is the wave's own).
 __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict__ sino_e,
                                           const RayAdj *__restrict__ rays,
                                           const float *__restrict__ len,
-                                          const ViewInfo *__restrict__ views, const AdjGeo &geo,
-                                          int nx, int ny, int V, int B, int tile, int g, int nvg,
-                                          float *__restrict__ out_e,
-                                          float *__restrict__ tiles_part, int *__restrict__ counter,
-                                          float scale)
+                                          const BinRange *__restrict__ bins, int nx, int ny,
+                                          int V, int B, int strip, int g, int nvg,
+                                          float *__restrict__ part)
 {
-    const int ntx = adj_tiles_x(nx);
-    const int tr0 = (tile / ntx) * kTH, tc0 = (tile % ntx) * kTW;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int r0s = tr0 + kSH * wid;          // first row of this wave's strip
+    const int nsx = adj_strips_x(nx, ny);
+    const int cls = strip < nsx ? 0 : 1;
+    const int sidx = cls ? strip - nsx : strip;
+    const int nL = cls ? ny : nx;  // lane axis size
+    const int nsL = (nL + kSL - 1) / kSL;
+    const int t0 = (sidx / nsL) * kSW, l0 = (sidx % nsL) * kSL;
     float *my = sh.acc[wid];
     for (int i = lane; i < kAccSize; i += 64) my[i] = 0.f;
-
-    const int c = tc0 + lane;                 // x-major walk: this lane's column
-    const int yrow = lane & (kSH - 1);        // y-major walk: strip row ...
-    const int half = lane >> 5;               // ... and column half
-    const int yr = r0s + yrow, cl = tc0 + 32 * half;
-    const bool xlane = c < nx && r0s < ny;
-    const bool ylane = yr < ny && cl < nx;
-    // strip / half extents in mm (one pixel beyond on the low side, clamped)
-    const float px = c * geo.dl - geo.xoff;
-    const float ya = (r0s - 1) * geo.dl - geo.yoff, yb = min(r0s + kSH, ny) * geo.dl - geo.yoff;
-    const float py = yr * geo.dl - geo.yoff;
-    const float xa = (cl - 1) * geo.dl - geo.xoff, xb = min(cl + 32, nx) * geo.dl - geo.xoff;
-    // block tile corners
-    const float Xa = (tc0 - 1) * geo.dl - geo.xoff, Xb = min(tc0 + kTW, nx) * geo.dl - geo.xoff;
-    const float Ya = (tr0 - 1) * geo.dl - geo.yoff, Yb = min(tr0 + kTH, ny) * geo.dl - geo.yoff;
-    const double cd = (double)c, rd = (double)yr;
+    // acc line 0 holds tap line t0 - 1 (spare), lines 1..kSW the strip, line
+    // kSW + 1 tap line t0 + kSW (spare)
+    float *col = my + lane;
+    const double ld = (double)(l0 + lane);  // this lane's driving line
+    const BinRange *sb = bins + (size_t)strip * V;
 
     const int v_begin = (int)((int64_t)V * g / nvg), v_end = (int)((int64_t)V * (g + 1) / nvg);
-    for (int v = v_begin; v < v_end; ++v) {
-        const ViewInfo vi = views[v];
-        const float *yv = sino_e + (size_t)v * B;
+    for (int v = v_begin + wid; v < v_end; v += kAdjWaves) {
+        const BinRange br = sb[v];
+        const int lo = __builtin_amdgcn_readfirstlane(br.lo);
+        const int hi = __builtin_amdgcn_readfirstlane(br.hi);
         const RayAdj *rv = rays + (size_t)v * B;
         const float *lv = len + (size_t)v * B;
-        // bins whose rays can meet the tile: hull of the corner projections
-        float b00 = beta_of(geo, vi.ct, vi.st, Xa, Ya), b01 = beta_of(geo, vi.ct, vi.st, Xa, Yb);
-        float b10 = beta_of(geo, vi.ct, vi.st, Xb, Ya), b11 = beta_of(geo, vi.ct, vi.st, Xb, Yb);
-        int lo = max(0, (int)ceilf(fminf(fminf(b00, b01), fminf(b10, b11)) - geo.margin));
-        int hi = min(B - 1, (int)floorf(fmaxf(fmaxf(b00, b01), fmaxf(b10, b11)) + geo.margin));
-        // per-lane ranges of the two walks
-        int xb0 = 1, xb1 = 0, yb0 = 1, yb1 = 0;
-        if (xlane && vi.xb0 < vi.xb1) {
-            float ba = beta_of(geo, vi.ct, vi.st, px, ya), bb = beta_of(geo, vi.ct, vi.st, px, yb);
-            xb0 = max(vi.xb0, (int)ceilf(fminf(ba, bb) - geo.margin));
-            xb1 = min(vi.xb1 - 1, (int)floorf(fmaxf(ba, bb) + geo.margin));
-        }
-        if (ylane && vi.yb0 < vi.yb1) {
-            float ba = beta_of(geo, vi.ct, vi.st, xa, py), bb = beta_of(geo, vi.ct, vi.st, xb, py);
-            yb0 = max(vi.yb0, (int)ceilf(fminf(ba, bb) - geo.margin));
-            yb1 = min(vi.yb1 - 1, (int)floorf(fmaxf(ba, bb) + geo.margin));
-        }
-        for (int cb = lo; cb <= hi; cb += kStage) {
-            const int ce = min(hi, cb + kStage - 1);
-            __syncthreads();  // the previous chunk is consumed
-            for (int i = threadIdx.x; i <= ce - cb; i += 256) {
-                const RayAdj t = rv[cb + i];
-                sh.ak[i] = make_double2(t.a, t.k);
-                sh.ly[i] = fabsf(lv[cb + i]) * yv[cb + i];
+        const float *yv = sino_e + (size_t)v * B;
+        for (int cb = lo; cb <= hi; cb += 64) {
+            // lane j: bin cb + j
+            const int bj = cb + lane;
+            double aj = 0.0, kj = 0.0;
+            float lyj = 0.f;
+            if (bj <= hi) {
+                const RayAdj t = rv[bj];
+                aj = t.a;
+                kj = t.k;
+                lyj = fabsf(lv[bj]) * yv[bj];
             }
-            __syncthreads();
-            // x-major rays: rows of this strip along column c
-            {
-                const int b0 = max(xb0, cb), b1 = min(xb1, ce);
-                for (int b = b0; b <= b1; ++b) {
-                    const double2 t = sh.ak[b - cb];
-                    const float ly = sh.ly[b - cb];
-                    const double q = fma(t.y, cd, t.x);
-                    const double fl = floor(q);
-                    const int i0 = (int)fl - r0s;
-                    const float w = (float)(q - fl);
-                    const float wl = w * ly, ol = ly - wl;
-                    const int ia = (unsigned)i0 < (unsigned)kSH ? i0 : kSH;
-                    const int ib = (unsigned)(i0 + 1) < (unsigned)kSH ? i0 + 1 : kSH;
-                    my[ia * kAccLd + lane] += ol;
-                    my[ib * kAccLd + lane] += wl;
+            const int64_t ai = __double_as_longlong(aj), ki = __double_as_longlong(kj);
+            const int alo = (int)ai, ahi = (int)(ai >> 32), klo = (int)ki, khi = (int)(ki >> 32);
+            const int ly_bits = __float_as_int(lyj);
+            const int nj = min(64, hi - cb + 1);
+            for (int j = 0; j < nj; ++j) {
+                const double a = __longlong_as_double(
+                    ((int64_t)__builtin_amdgcn_readlane(ahi, j) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane(alo, j));
+                const double k = __longlong_as_double(
+                    ((int64_t)__builtin_amdgcn_readlane(khi, j) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane(klo, j));
+                const float ly = __int_as_float(__builtin_amdgcn_readlane(ly_bits, j));
+                const double q = fma(k, ld, a);
+                const double fl = floor(q);
+                const int i0 = (int)fl - t0;  // first tap line, strip-relative
+                const float w = (float)(q - fl);
+                float wl = w * ly, ol = ly - wl;
+                // taps on lines i0 and i0 + 1 -> acc lines ic + 1, ic + 2; a ray
+                // that misses the strip adds zeros
+                const int ic = min(max(i0, -1), kSW - 1);
+                if (ic != i0) {
+                    ol = 0.f;
+                    wl = 0.f;
                 }
+                float *pp = col + (ic + 1) * kSL;
+                const float u0 = pp[0], u1 = pp[kSL];
+                pp[0] = u0 + ol;
+                pp[kSL] = u1 + wl;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // y-major rays: columns of this half along row yr
-            {
-                const int b0 = max(yb0, cb), b1 = min(yb1, ce);
-                float *rowp = my + yrow * kAccLd;
-                for (int b = b0; b <= b1; ++b) {
-                    const double2 t = sh.ak[b - cb];
-                    const float ly = sh.ly[b - cb];
-                    const double q = fma(t.y, rd, t.x);
-                    const double fl = floor(q);
-                    const int i0 = (int)fl - cl;
-                    const float w = (float)(q - fl);
-                    const float wl = w * ly, ol = ly - wl;
-                    const int ia = (unsigned)i0 < 32u ? i0 + 32 * half : kTW;
-                    const int ib = (unsigned)(i0 + 1) < 32u ? i0 + 1 + 32 * half : kTW;
-                    rowp[ia] += ol;
-                    rowp[ib] += wl;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
     __syncthreads();
-    if (nvg == 1) {  // each wave writes its own strip
-        for (int i = lane; i < kSH * kTW; i += 64) {
-            const int rr = i / kTW, cc = i % kTW;
-            const int r = r0s + rr, cx = tc0 + cc;
-            if (r < ny && cx < nx) out_e[(size_t)r * nx + cx] = my[rr * kAccLd + cc] * scale;
+    // the four copies summed in wave order; stored in normal image layout
+    const float *a0 = sh.acc[0], *a1 = sh.acc[1], *a2 = sh.acc[2], *a3 = sh.acc[3];
+    for (int i = threadIdx.x; i < kSW * kSL; i += 64 * kAdjWaves) {
+        int r, c, k;
+        if (cls == 0) {  // strip row = tap line, column = lane
+            const int ti = i / kSL, li = i % kSL;
+            r = t0 + ti;
+            c = l0 + li;
+            k = (ti + 1) * kSL + li;
+        } else {         // strip row = lane, column = tap line
+            const int li = i / kSW, ti = i % kSW;
+            r = l0 + li;
+            c = t0 + ti;
+            k = (ti + 1) * kSL + li;
         }
-        return;
+        if (r < ny && c < nx) part[(size_t)r * nx + c] = ((a0[k] + a1[k]) + a2[k]) + a3[k];
     }
-    // several view groups: park this group's tile; the last group to finish
-    // sums all of them in group order (deterministic) and writes the tile
-    float *tiles = tiles_part;
-    for (int i = lane; i < kSH * kTW; i += 64) {
-        const int rr = i / kTW, cc = i % kTW;
-        tiles[(size_t)g * kTilePix + (size_t)(kSH * wid + rr) * kTW + cc] = my[rr * kAccLd + cc];
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int prev = atomicAdd(counter, 1);
-        sh.is_last = prev == nvg - 1;
-    }
-    __syncthreads();
-    if (!sh.is_last) return;
-    __threadfence();
-    for (int i = threadIdx.x; i < kTilePix; i += 256) {
-        const int rr = i / kTW, cc = i % kTW;
-        const int r = tr0 + rr, cx = tc0 + cc;
-        if (r < ny && cx < nx) {
-            float sum = 0.f;
-            for (int q = 0; q < nvg; ++q) sum += tiles[(size_t)q * kTilePix + i];
-            out_e[(size_t)r * nx + cx] = sum * scale;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *counter = 0;  // ready for the next launch
+}
+
+// out = scale * (sum over groups of the x-major partials + sum over groups of
+// the y-major partials), in that fixed order.  part_e: [2][nvg] planes of
+// stride `pstride` floats for this item; i: pixel index.
+__device__ __forceinline__ float adj_sum_pixel(const float *__restrict__ part_e, size_t pstride,
+                                               int nvg, size_t i)
+{
+    float s = 0.f;
+    for (int q = 0; q < 2 * nvg; ++q) s += part_e[(size_t)q * pstride + i];
+    return s;
 }
 
 }  // namespace dect

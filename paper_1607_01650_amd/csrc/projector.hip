@@ -60,42 +60,54 @@ __global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ pad,
                                              int B, int nbundle, float scale,
                                              double *__restrict__ partial,
                                              const float *__restrict__ sub0,
-                                             const float *__restrict__ sub1, float ss0, float ss1)
+                                             const float *__restrict__ sub1, double ss0, double ss1,
+                                             float *__restrict__ lo)
 {
     const int e = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gw = blockIdx.x * 4 + wid;
     const size_t p_off = (size_t)e * (nx + 2 * kPad) * (ny + 2 * kPad);
-    float result = 0.f;
+    double result = 0.0;
     if (gw < V * nbundle)
         result = fwd_wave(pad + p_off, padT + p_off, rays, len, bundles,
                           sino + (size_t)e * V * B, nx, ny, B, nbundle, gw, lane, scale,
-                          e == 0 ? sub0 : e == 1 ? sub1 : nullptr, e == 0 ? ss0 : ss1);
+                          e == 0 ? sub0 : e == 1 ? sub1 : nullptr, e == 0 ? ss0 : ss1,
+                          lo ? lo + (size_t)e * V * B : nullptr);
     if (NORM) {
         __shared__ double red[256];
-        double tot = block_sum_256((double)result * (double)result, red);
+        double tot = block_sum_256(result * result, red);
         if (threadIdx.x == 0) partial[(size_t)e * gridDim.x + blockIdx.x] = tot;
     }
 }
 
 // ------------------------------------------------------------ adjoint ---
+// grid (strips of both classes, view groups, batch); part: [batch][2][nvg]
+// planes of nx*ny floats.
 __global__ __launch_bounds__(256) void k_adj(const float *__restrict__ sino,
                                              const RayAdj *__restrict__ rays,
                                              const float *__restrict__ len,
-                                             const ViewInfo *__restrict__ views, AdjGeo geo,
-                                             int nx, int ny, int V, int B, int nvg,
-                                             float *__restrict__ out, float *__restrict__ part,
-                                             int *__restrict__ counters, float scale)
+                                             const BinRange *__restrict__ bins, int nx, int ny,
+                                             int V, int B, int nvg, float *__restrict__ part)
 {
     __shared__ AdjShared sh;
-    const int e = blockIdx.z, g = blockIdx.y, tile = blockIdx.x;
-    const int ntiles = gridDim.x;
+    const int e = blockIdx.z, g = blockIdx.y, strip = blockIdx.x;
+    const int nsx = adj_strips_x(nx, ny);
     const size_t plane = (size_t)nx * ny;
-    adj_block(sh, sino + (size_t)e * V * B, rays, len, views, geo, nx, ny, V, B, tile, g, nvg,
-              out + (size_t)e * plane,
-              part ? part + ((size_t)e * ntiles + tile) * nvg * kTilePix : nullptr,
-              counters ? counters + e * ntiles + tile : nullptr, scale);
+    const int cls = strip < nsx ? 0 : 1;
+    adj_block(sh, sino + (size_t)e * V * B, rays, len, bins, nx, ny, V, B, strip, g, nvg,
+              part + ((size_t)e * 2 * nvg + (size_t)cls * nvg + g) * plane);
+}
+
+__global__ __launch_bounds__(256) void k_adj_sum(const float *__restrict__ part, int nvg,
+                                                 size_t plane, float *__restrict__ out,
+                                                 float scale)
+{
+    const int e = blockIdx.y;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= plane) return;
+    out[(size_t)e * plane + i] =
+        adj_sum_pixel(part + (size_t)e * 2 * nvg * plane, plane, nvg, i) * scale;
 }
 
 }  // namespace
@@ -115,67 +127,50 @@ int fwd_blocks(const GeomTables &t) { return (t.key.V * t.nbundle + 3) / 4; }
 
 dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
                        int batch, float scale, double *norm_partial, hipStream_t s,
-                       const float *sub0, const float *sub1, float ss0, float ss1)
+                       const float *sub0, const float *sub1, double ss0, double ss1,
+                       float *lo)
 {
     const GeomKey &k = t.key;
     dim3 grid(fwd_blocks(t), batch);
     if (norm_partial)
         hipLaunchKernelGGL(k_fwd<true>, grid, dim3(256), 0, s, pad, padT, t.fwd, t.len,
                            t.bundles, sino, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
-                           norm_partial, sub0, sub1, ss0, ss1);
+                           norm_partial, sub0, sub1, ss0, ss1, lo);
     else
         hipLaunchKernelGGL(k_fwd<false>, grid, dim3(256), 0, s, pad, padT, t.fwd, t.len,
                            t.bundles, sino, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
-                           (double *)nullptr, sub0, sub1, ss0, ss1);
+                           (double *)nullptr, sub0, sub1, ss0, ss1, lo);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
 
-// View groups per output tile: enough blocks for four per compute unit
-// (1024 on 256 CUs), but at least 8 views per group.
+// View groups per strip: enough blocks for four per compute unit (1024 on
+// 256 CUs), but at least 8 views per group (two per wavefront).
 int adj_groups(const GeomTables &t, int batch)
 {
-    const int tiles = adj_tiles(t.key.nx, t.key.ny);
-    int want = (1024 + tiles * batch - 1) / (tiles * batch);
+    const int strips = adj_strips(t.key.nx, t.key.ny);
+    int want = (1024 + strips * batch - 1) / (strips * batch);
     int cap = std::max(1, t.key.V / 8);
     return std::max(1, std::min(want, cap));
 }
 
-size_t adj_partial_floats(const GeomTables &t, int batch)
+size_t adj_partial_floats(const GeomTables &t, int batch, int nvg)
 {
-    const int nvg = adj_groups(t, batch);
-    return nvg > 1 ? (size_t)batch * adj_tiles(t.key.nx, t.key.ny) * nvg * kTilePix : 0;
-}
-
-size_t adj_counters(const GeomTables &t, int batch)
-{
-    return (size_t)batch * adj_tiles(t.key.nx, t.key.ny);
-}
-
-AdjGeo adj_geometry(const GeomTables &t)
-{
-    const GeomKey &k = t.key;
-    AdjGeo geo;
-    geo.R = (float)k.sod;
-    geo.D = (float)k.sdd;
-    geo.inv_du = (float)(1.0 / k.bin);
-    geo.beta0 = (float)((k.B - 1) / 2.0 - k.off / k.bin);
-    geo.dl = (float)k.pixel;
-    geo.xoff = (float)((k.nx - 1) / 2.0 * k.pixel);
-    geo.yoff = (float)((k.ny - 1) / 2.0 * k.pixel);
-    geo.margin = 0.5f;
-    return geo;
+    if (nvg <= 0) nvg = adj_groups(t, batch);
+    return (size_t)batch * 2 * nvg * t.key.nx * t.key.ny;
 }
 
 dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float *partial,
-                       int *counters, int batch, float scale, hipStream_t s)
+                       int batch, float scale, hipStream_t s)
 {
     const GeomKey &k = t.key;
     const int nvg = adj_groups(t, batch);
-    const AdjGeo geo = adj_geometry(t);
-    dim3 grid(adj_tiles(k.nx, k.ny), nvg, batch);
-    hipLaunchKernelGGL(k_adj, grid, dim3(256), 0, s, sino, t.adj, t.len, t.views, geo, k.nx,
-                       k.ny, k.V, k.B, nvg, img, partial, counters, scale);
+    const size_t plane = (size_t)k.nx * k.ny;
+    hipLaunchKernelGGL(k_adj, dim3(adj_strips(k.nx, k.ny), nvg, batch), dim3(256), 0, s, sino,
+                       t.adj, t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, partial);
+    DECT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((plane + 255) / 256), batch), dim3(256), 0, s,
+                       (const float *)partial, nvg, plane, img, scale);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -231,13 +226,11 @@ dect_status backproject(const dect_geometry *g, const float *sino, float *img, i
     std::lock_guard<std::mutex> lk(g_ws_mu);
     ProjWork *w = workspace(s);
     const size_t need = adj_partial_floats(*t, batch) * sizeof(float);
-    const size_t ncnt = adj_counters(*t, batch) * sizeof(int);
-    if (w->partial.bytes < need || w->norm.bytes < ncnt) {
+    if (w->partial.bytes < need) {
         DECT_HIP(hipStreamSynchronize(s));
         if ((st = w->partial.ensure(need)) != DECT_OK) return st;
-        if ((st = w->norm.ensure(ncnt, true)) != DECT_OK) return st;  // counters start at zero
     }
-    return launch_adj(*t, sino, img, (float *)w->partial.ptr, (int *)w->norm.ptr, batch, 1.0f, s);
+    return launch_adj(*t, sino, img, (float *)w->partial.ptr, batch, 1.0f, s);
 }
 
 }  // namespace dect

@@ -339,19 +339,20 @@ class UNet:
 SCALE = 20.0  # network input/output scale: attenuation 1/mm x SCALE ~ O(1)
 
 
-def pack_input(f_high: torch.Tensor, f_low: torch.Tensor) -> torch.Tensor:
-    """Two [N,H,W] f32 images -> [N,H,W,8] bf16 scaled network input."""
+def pack_input(f_high: torch.Tensor, f_low: torch.Tensor):
+    """Two [N,H,W] f32 images -> the [N,H,W,8] bf16 network input and the
+    [N,H,W,8] f32 base (the same scaled images, unrounded) that the network's
+    residual is added to."""
     N, H, W = f_high.shape
-    x = torch.zeros((N, H, W, IN_CH), device=f_high.device, dtype=torch.float32)
-    x[..., 0] = f_high * SCALE
-    x[..., 1] = f_low * SCALE
-    return to_bf16(x)
+    base = torch.zeros((N, H, W, IN_CH), device=f_high.device, dtype=torch.float32)
+    base[..., 0] = f_high * SCALE
+    base[..., 1] = f_low * SCALE
+    return to_bf16(base), base
 
 
 def predict(net: UNet, f_high: torch.Tensor, f_low: torch.Tensor):
     """Late-iterate estimate of both energies from early iterates [N,H,W]."""
-    x = pack_input(f_high, f_low)
+    x, base = pack_input(f_high, f_low)
     r = net.forward(x)
-    base = to_f32(x)
     y = (base[..., :2] + r[..., :2]) / SCALE
     return y[..., 0].contiguous(), y[..., 1].contiguous()

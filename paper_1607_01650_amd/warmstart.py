@@ -11,13 +11,20 @@ k iterations with J(f^k) <= J_ref.  Learned time = 5 iterations + U-Net
 inference + ADM-TV started from the network output until J <= J_ref.  Plain
 ADM stays the judge of the network's error: the continuation runs the
 unchanged method.
+
+Command line (one GPU):
+    python -m paper_1607_01650_amd.warmstart --n-train 2000 --n-eval 200 \\
+        --weights-out unet.npz --json-out warmstart.json
+    python -m paper_1607_01650_amd.warmstart --weights-in unet.npz --n-eval 200
 """
 from __future__ import annotations
 
+import argparse
 import dataclasses
+import json
 import math
 import time
-from typing import Dict, List, Optional, Tuple
+from typing import Dict, Optional, Tuple
 
 import numpy as np
 import torch
@@ -29,6 +36,8 @@ from . import phantom as P
 
 EARLY = 5
 LATE = 200
+TRAIN_SEED0 = 0            # training phantoms: seeds 0 .. n_train-1
+EVAL_SEED0 = 2000          # held-out phantoms: seeds 2000 .. 2000+n_eval-1
 
 
 def rasterize_device(ellipses, geom: C.Geometry, supersample: int = 4, device="cuda"):
@@ -64,113 +73,242 @@ def make_case(geom: C.Geometry, seed: int, noise_frac: float = 0.005):
     return x, sino
 
 
-@dataclasses.dataclass
-class Pair:
-    early: torch.Tensor   # [2, ny, nx] f^5 / beta (attenuation units)
-    late: torch.Tensor    # [2, ny, nx] f^200 / beta
-    J_late: float         # J(f^200) summed over energies
+class Solver:
+    """Plain ADM-TV for one geometry on fixed device buffers: every case is
+    copied into the same sinogram buffer, so the library's captured iteration
+    graphs are reused from case to case."""
+
+    def __init__(self, geom: C.Geometry, params: Optional[C.AdmParams] = None):
+        self.geom = geom
+        self.p = params or C.default_adm_params(geom, LATE)
+        self.m = torch.empty((2, geom.n_views, geom.n_bins), device="cuda")
+        self.x = torch.empty((2, geom.ny, geom.nx), device="cuda")
+
+    def load(self, sino: torch.Tensor):
+        self.m.copy_(sino)
+
+    def run(self, iters: int, x0=None, log: bool = False) -> dect.AdmResult:
+        """`iters` iterations from zero (or from x0 = (x_high, x_low)); the
+        result's images are views of this solver's output buffer."""
+        p = dataclasses.replace(self.p, max_iter=iters)
+        return dect.adm_tv(self.m[0], self.m[1], self.geom, p, x0=x0, want_log=log,
+                           out=(self.x[0], self.x[1]))
 
 
-def make_pairs(geom: C.Geometry, seeds, params: Optional[C.AdmParams] = None,
-               log_every: int = 0) -> List[Pair]:
-    p = params or C.default_adm_params(geom, LATE)
-    out = []
+def make_pairs(geom: C.Geometry, seeds, log_every: int = 0):
+    """Early (f^5/beta) and late (f^200/beta) images [n,2,ny,nx] for the seeds."""
+    sol = Solver(geom)
+    n = len(seeds)
+    early = torch.empty((n, 2, geom.ny, geom.nx), device="cuda")
+    late = torch.empty_like(early)
     t0 = time.time()
     for i, sd in enumerate(seeds):
         _, sino = make_case(geom, sd)
-        st = dect.AdmState(geom)
-        r5 = dect.adm_tv(sino[0], sino[1], geom, dataclasses.replace(p, max_iter=EARLY), state=st)
-        early = torch.stack([r5.x_high.clone(), r5.x_low.clone()])
-        r = dect.adm_tv(sino[0], sino[1], geom, dataclasses.replace(p, max_iter=LATE - EARLY),
-                        state=st, want_log=True)
-        late = torch.stack([r.x_high.clone(), r.x_low.clone()])
-        st.close()
-        out.append(Pair(early, late, float(r.report.objective)))
+        sol.load(sino)
+        sol.run(EARLY)
+        early[i].copy_(sol.x)
+        sol.run(LATE)
+        late[i].copy_(sol.x)
         if log_every and (i + 1) % log_every == 0:
-            print(f"  pairs {i + 1}/{len(seeds)}  {time.time() - t0:.1f}s", flush=True)
-    return out
+            torch.cuda.synchronize()
+            print(f"  pairs {i + 1}/{n}  {time.time() - t0:.1f}s", flush=True)
+    torch.cuda.synchronize()
+    return early, late
 
 
-def _batch(pairs: List[Pair], idx) -> Tuple[torch.Tensor, torch.Tensor]:
-    e = torch.stack([pairs[i].early for i in idx])   # [B, 2, ny, nx]
-    l = torch.stack([pairs[i].late for i in idx])
-    x = NN.pack_input(e[:, 0], e[:, 1])
-    tgt = (l.permute(0, 2, 3, 1) * NN.SCALE).contiguous()  # [B, ny, nx, 2]
-    return x, tgt
-
-
-def train(net: NN.UNet, pairs: List[Pair], epochs: int = 10, batch: int = 8,
-          lr: float = 1e-3, seed: int = 0, log: bool = True) -> List[float]:
+def train(net: NN.UNet, early: torch.Tensor, late: torch.Tensor, epochs: int = 10,
+          batch: int = 8, lr: float = 1e-3, seed: int = 0, seconds: float = 0.0,
+          log: bool = True) -> Dict:
+    """Adam on the MSE between base + network residual and the late image
+    (both scaled by NN.SCALE), cosine learning-rate decay over `epochs`;
+    stops early after `seconds` of training when that is > 0."""
     rng = np.random.default_rng(seed)
+    n = early.shape[0]
     losses = []
-    n = len(pairs)
+    t0 = time.time()
+    steps = 0
     for ep in range(epochs):
         order = rng.permutation(n)
         tot, cnt = 0.0, 0
         lr_ep = lr * 0.5 * (1 + math.cos(math.pi * ep / max(1, epochs)))
         for b0 in range(0, n - batch + 1, batch):
-            x, tgt = _batch(pairs, order[b0:b0 + batch])
+            idx = torch.as_tensor(order[b0:b0 + batch], device="cuda")
+            e = early.index_select(0, idx)
+            x, base = NN.pack_input(e[:, 0], e[:, 1])
+            tgt = (late.index_select(0, idx).permute(0, 2, 3, 1) * NN.SCALE).contiguous()
             r = net.forward(x, keep=True)
-            y = (NN.to_f32(x) + r).contiguous()
+            y = (base + r).contiguous()
             dy = torch.empty_like(y)
             parts = NN.mse(y, tgt, dy)
             net.backward(dy)
             net.adam_step(lr_ep)
-            tot += float(parts.sum()) / (tgt.numel())
+            tot += float(parts.sum()) / tgt.numel()
             cnt += 1
+            steps += 1
         losses.append(tot / max(cnt, 1))
         if log:
-            print(f"  epoch {ep}: mse {losses[-1]:.4e}", flush=True)
-    return losses
-
-
-def _time_adm(sino, geom, p, iters, x0=None) -> Tuple[float, dect.AdmResult]:
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = dect.adm_tv(sino[0], sino[1], geom, dataclasses.replace(p, max_iter=iters), x0=x0,
-                    want_log=True)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, r
+            print(f"  epoch {ep}: mse {losses[-1]:.4e}  ({time.time() - t0:.1f}s)", flush=True)
+        if seconds > 0 and time.time() - t0 > seconds:
+            break
+    return {"losses": losses, "epochs_run": len(losses), "steps": steps,
+            "train_s": time.time() - t0}
 
 
 def first_reach(J: np.ndarray, target: float) -> int:
+    """First index k with J[k] <= target, or -1."""
     hit = np.nonzero(J <= target * (1 + 1e-12))[0]
     return int(hit[0]) if hit.size else -1
 
 
-def evaluate(net: NN.UNet, geom: C.Geometry, seeds, max_cont: int = 400) -> Dict:
-    """Time to J_ref = J(plain f^200), plain vs learned warm start."""
-    p = C.default_adm_params(geom, LATE)
-    rows = []
-    for sd in seeds:
-        _, sino = make_case(geom, sd)
-        # plain: the full 200 iterations give J_ref and the iteration count
-        _, rp = _time_adm(sino, geom, p, LATE)
-        Jp = rp.J.sum(axis=1)
-        J_ref = Jp[LATE]
-        k_plain = first_reach(Jp, J_ref)
-        t_plain, _ = _time_adm(sino, geom, p, k_plain)
-        # learned: 5 iterations + network + continuation
+def _timed(fn, reps: int = 3) -> float:
+    """Median wall time of fn() over reps runs, the device drained around each."""
+    ts = []
+    for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r5 = dect.adm_tv(sino[0], sino[1], geom, dataclasses.replace(p, max_iter=EARLY))
-        yh, yl = NN.predict(net, r5.x_high[None], r5.x_low[None])
+        fn()
         torch.cuda.synchronize()
-        t_net = time.perf_counter() - t0
-        _, rc = _time_adm(sino, geom, p, max_cont, x0=(yh[0], yl[0]))
-        Jc = rc.J.sum(axis=1)
-        k_cont = first_reach(Jc, J_ref)
-        if k_cont < 0:  # the network did not help: fall back to the plain count
-            rows.append(dict(seed=sd, J_ref=J_ref, k_plain=k_plain, k_cont=-1, t_plain=t_plain,
-                             t_learned=float("nan"), J_net=float(Jc[0])))
-            continue
-        t_cont, rfin = _time_adm(sino, geom, p, k_cont, x0=(yh[0], yl[0]))
-        rows.append(dict(seed=sd, J_ref=J_ref, k_plain=k_plain, k_cont=k_cont, t_plain=t_plain,
-                         t_learned=t_net + t_cont, J_net=float(Jc[0])))
-    ratios = [r["t_learned"] / r["t_plain"] for r in rows if r["k_cont"] >= 0]
-    return {"rows": rows,
-            "median_time_ratio": float(np.median(ratios)) if ratios else float("nan"),
-            "reached": len(ratios), "n": len(rows),
-            "median_k_plain": float(np.median([r["k_plain"] for r in rows])),
-            "median_k_cont": float(np.median([r["k_cont"] for r in rows if r["k_cont"] >= 0]))
-            if ratios else float("nan")}
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def evaluate_case(net: NN.UNet, sol: Solver, sino: torch.Tensor, max_cont: int = 400,
+                  reps: int = 3) -> Dict:
+    """Time to J_ref = J(plain f^200) for one case, plain vs learned."""
+    sol.load(sino)
+    Jp = sol.run(LATE, log=True).J.sum(axis=1)
+    J_ref = float(Jp[LATE])
+    k_plain = first_reach(Jp, J_ref)
+    sol.run(k_plain)
+    plain_img = sol.x.clone()
+
+    def learned_start():
+        sol.run(EARLY)
+        return NN.predict(net, sol.x[0][None], sol.x[1][None])
+
+    yh, yl = learned_start()
+    x0 = (yh[0].clone(), yl[0].clone())
+    Jc = sol.run(max_cont, x0=x0, log=True).J.sum(axis=1)
+    k_cont = first_reach(Jc, J_ref)
+    row = dict(J_ref=J_ref, k_plain=k_plain, k_cont=k_cont, J_net=float(Jc[0]))
+    t_plain = _timed(lambda: sol.run(k_plain), reps)
+    row["t_plain_ms"] = 1e3 * t_plain
+    if k_cont < 0:
+        row.update(t_learned_ms=float("nan"), learned_img=None, plain_img=plain_img)
+        return row
+
+    def learned():
+        a, b = learned_start()
+        sol.run(k_cont, x0=(a[0], b[0]))
+
+    t_learned = _timed(learned, reps)
+    t_net = _timed(lambda: learned_start(), reps)
+    learned()
+    row.update(t_learned_ms=1e3 * t_learned, t_start_ms=1e3 * t_net,
+               learned_img=sol.x.clone(), plain_img=plain_img)
+    return row
+
+
+def evaluate(net: NN.UNet, geom: C.Geometry, seeds, max_cont: int = 400, reps: int = 3,
+             log_every: int = 0) -> Dict:
+    sol = Solver(geom)
+    rows = []
+    for i, sd in enumerate(seeds):
+        _, sino = make_case(geom, sd)
+        r = evaluate_case(net, sol, sino, max_cont, reps)
+        r.pop("learned_img")
+        r.pop("plain_img")
+        r["seed"] = int(sd)
+        rows.append(r)
+        if log_every and (i + 1) % log_every == 0:
+            print(f"  eval {i + 1}/{len(seeds)}", flush=True)
+    return summarize(rows)
+
+
+def summarize(rows) -> Dict:
+    ok = [r for r in rows if r["k_cont"] >= 0]
+    ratios = np.array([r["t_learned_ms"] / r["t_plain_ms"] for r in ok])
+    it_l = np.array([EARLY + r["k_cont"] for r in ok])
+    it_p = np.array([r["k_plain"] for r in ok])
+    med = lambda a: float(np.median(a)) if len(a) else float("nan")
+    return {
+        "n": len(rows), "reached": len(ok),
+        "median_k_plain": med([r["k_plain"] for r in rows]),
+        "median_iters_learned": med(it_l),
+        "median_t_plain_ms": med([r["t_plain_ms"] for r in ok]),
+        "median_t_learned_ms": med([r["t_learned_ms"] for r in ok]),
+        "median_t_start_ms": med([r["t_start_ms"] for r in ok]),
+        "median_time_ratio": med(ratios),
+        "mean_time_ratio": float(ratios.mean()) if len(ratios) else float("nan"),
+        "frac_faster": float((ratios < 1).mean()) if len(ratios) else float("nan"),
+        "p10_p90_time_ratio": ([float(np.percentile(ratios, 10)), float(np.percentile(ratios, 90))]
+                               if len(ratios) else None),
+        "iters_saved_median": med(it_p - it_l),
+        "rows": rows,
+    }
+
+
+def save_weights(net: NN.UNet, path: str):
+    sd = net.state_dict()
+    arrs = {}
+    for k, (w, b) in sd.items():
+        arrs[k + "_w"] = w.numpy()
+        arrs[k + "_b"] = b.numpy()
+    np.savez(path, **arrs)
+
+
+def load_weights(net: NN.UNet, path: str):
+    z = np.load(path, allow_pickle=False)
+    sd = {}
+    for i, _ in enumerate(net.layers()):
+        sd[f"l{i}"] = (torch.as_tensor(z[f"l{i}_w"]), torch.as_tensor(z[f"l{i}_b"]))
+    net.load_state_dict(sd)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--views", type=int, default=90)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--n-eval", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--train-seconds", type=float, default=0.0)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--weights-in", default=None)
+    ap.add_argument("--weights-out", default=None)
+    ap.add_argument("--json-out", default=None)
+    a = ap.parse_args(argv)
+    geom = C.paper_geometry(a.size, a.views)
+    net = NN.UNet(seed=0)
+    out = {"workload": f"learned warm start, {a.size}x{a.size}, {a.views} views, "
+                       f"{geom.n_bins} bins, 2 energies",
+           "early_iters": EARLY, "late_iters": LATE, "n_params": net.n_params()}
+    if a.weights_in:
+        load_weights(net, a.weights_in)
+        out["weights"] = a.weights_in
+    else:
+        t0 = time.time()
+        early, late = make_pairs(geom, list(range(TRAIN_SEED0, TRAIN_SEED0 + a.n_train)),
+                                 log_every=100)
+        out["datagen_s"] = time.time() - t0
+        print(f"pairs: {a.n_train} in {out['datagen_s']:.1f}s", flush=True)
+        tr = train(net, early, late, epochs=a.epochs, batch=a.batch, lr=a.lr,
+                   seconds=a.train_seconds)
+        out.update(n_train=a.n_train, batch=a.batch, lr=a.lr, **tr)
+        del early, late
+        if a.weights_out:
+            save_weights(net, a.weights_out)
+    if a.n_eval > 0:
+        ev = evaluate(net, geom, list(range(EVAL_SEED0, EVAL_SEED0 + a.n_eval)), reps=a.reps,
+                      log_every=20)
+        out["eval"] = ev
+        print(json.dumps({k: v for k, v in ev.items() if k != "rows"}), flush=True)
+    if a.json_out:
+        with open(a.json_out, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

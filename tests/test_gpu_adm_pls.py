@@ -1,7 +1,8 @@
 """GPU parity of ADM-TV (dect_adm_tv) and the PLS decomposition.
 
-ADM images after K iterations vs the FP64 oracle: rel-L2 <= 1e-4; the logged
-objective per iteration within 1e-5 relative.  PLS on shared FP32 inputs and
+ADM images after K iterations vs the FP64 oracle: rel-L2 <= 1e-4 (3e-4 for the
+sparsest paper-scale case, whose derivation is given at that test); the logged
+objective within 1e-5 relative over the first iterations.  PLS on shared FP32 inputs and
 weights: rel-L2 <= 1e-5; the edge map is bit-exact (its threshold decision
 is taken in FP32 on both sides).
 """
@@ -161,15 +162,18 @@ def test_pls_maxiter_warning(torch, tiny):
 @pytest.mark.parametrize("views", [90, 360, 720])
 def test_adm_paper_scale_parity_200(torch, views):
     """512x512, 736 bins, both energies, 200 iterations vs the stored FP64 oracle
-    run (tests/golden/make_golden.py): rel-L2 <= 1e-4 per energy image.
+    run (tests/golden/make_golden.py): image rel-L2 <= 1e-4 per energy at 360 and
+    720 views, <= 3e-4 at 90 views.
 
-    The iteration amplifies rounding: the FP64 oracle itself, with only its
-    image rounded to FP32 after every step, ends 1.4e-4 (90 views), 5.6e-5
-    (360) and ~4e-6 (720) away from its unrounded run, and its objective
-    J(f^200) up to 7e-5 away.  The 1e-4 image bound is therefore tight at
-    90 views by nature, and J(f^200) is held to the same 1e-4.  Systematic
-    errors (a wrong term or scale) show in the first iterations, before the
-    rounding has grown: J(f^k), k <= 10, within 1e-5.
+    The iteration amplifies rounding, and at 90 views (the sparsest case) it
+    does so to the 1e-4 level for any FP32 evaluation: the FP64 oracle itself,
+    with only its image rounded to FP32 after every step, ends 1.4e-4 away
+    from its unrounded run at 90 views (5.6e-5 at 360, ~4e-6 at 720); with only
+    its back-projection accumulated in FP32, 1.2e-5.  The 90-view bound is
+    twice that floor.  The objective J(f^200) is held to 1e-4 (the oracle's
+    own FP32-image run moves it by up to 7e-5).  Systematic errors (a wrong
+    term or scale) show in the first iterations, before the rounding has
+    grown: J(f^k), k <= 10, within 1e-5.
     """
     import os
     dect = _dect()
@@ -185,6 +189,6 @@ def test_adm_paper_scale_parity_200(torch, views):
         jrel = np.abs(r.J[:, e] - gold["J"][e]) / gold["J"][e]
         print(f"V={views} energy {e}: image rel-L2 {err:.3e}  J200 rel err {jrel[200]:.2e}  "
               f"max J rel err k<=10 {jrel[:11].max():.2e}", flush=True)
-        assert err <= 1e-4
+        assert err <= (3e-4 if views == 90 else 1e-4)
         assert jrel[200] <= 1e-4
         assert jrel[:11].max() <= 1e-5
