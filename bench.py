@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes as ct
+import dataclasses
 import json
 import os
 import sys
@@ -98,6 +99,11 @@ def main():
     ap.add_argument("--pmc-dir", default="gpurun_out/pmc")
     ap.add_argument("--warm-cases", type=int, default=4,
                     help="held-out cases for the learned-warm-start time-to-tol entry")
+    ap.add_argument("--batch-slices", type=int, default=64,
+                    help="slices of the batched multi-slice entry (0: skip)")
+    ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--unrolled-steps", type=int, default=3,
+                    help="timed training steps of the unrolled-ADM entry (0: skip)")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -128,7 +134,6 @@ def main():
     ev = HipEvents()
 
     state = dect.AdmState(g)
-    import dataclasses
     dect.adm_tv(mh, ml, g, dataclasses.replace(p, max_iter=args.warmup), state=state,
                 out=(xh, xl))
     timed = dataclasses.replace(p, max_iter=args.steps)
@@ -182,6 +187,8 @@ def main():
     pls_ms = (time.perf_counter() - q0) * 1e3
 
     warm = warm_start_extra(args.warm_cases)
+    batched = batched_extra(args.batch_slices, args.batch_iters) if args.batch_slices > 0 else None
+    unrolled = unrolled_extra(args.unrolled_steps) if args.unrolled_steps > 0 else None
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -220,7 +227,7 @@ def main():
                   "ray_updates_per_s": round(4 * S * iters_per_s, 1),
                   "wall_s_timed": round(wall, 4),
                   "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
-                  "warm_start": warm},
+                  "warm_start": warm, "batched": batched, "unrolled": unrolled},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
@@ -256,6 +263,90 @@ def warm_start_extra(n: int):
             "median_ms_plain": med([r["t_plain_ms"] for r in ok]),
             "median_ms_learned": med([r["t_learned_ms"] for r in ok]),
             "median_time_ratio": med([r["t_learned_ms"] / r["t_plain_ms"] for r in ok])}
+
+
+def batched_extra(n_slices: int, iters: int):
+    """Many slices of uneven size and view count (sizes {256, 384, 512}^2, views
+    {60, 90, 180, 360}, seed 0), both energies, advanced together by the
+    batched ADM (one persistent launch per phase, graph replay, autotuned view
+    grouping): slice-iterations/s, beside the same slices run one after
+    another through dect_adm_tv."""
+    import numpy as np
+    import torch
+    from paper_1607_01650_amd import configs as C, dect, warmstart as W
+    rng = np.random.default_rng(0)
+    sizes = rng.choice([256, 384, 512], n_slices)
+    views = rng.choice([60, 90, 180, 360], n_slices)
+    geoms = [C.paper_geometry(int(n), int(v)) for n, v in zip(sizes, views)]
+    params = [C.default_adm_params(g, iters) for g in geoms]
+    mh, ml = [], []
+    for i, g in enumerate(geoms):
+        _, sino = W.make_case(g, 3000 + i)
+        mh.append(sino[0].contiguous())
+        ml.append(sino[1].contiguous())
+    b = dect.AdmBatch(geoms, params)
+    groups, _ = b.tune(mh, ml, iters=4)
+    b.run(mh, ml, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(mh, ml, iters)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    for i, g in enumerate(geoms):  # set-up (tables, states, graphs) outside the timing
+        dect.adm_tv(mh[i], ml[i], g, dataclasses.replace(params[i], max_iter=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, g in enumerate(geoms):
+        dect.adm_tv(mh[i], ml[i], g, params[i])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    samples = sum(2 * 2 * dect.count_samples(g) for g in geoms)  # fwd + adj, 2 energies
+    return {"workload": f"{n_slices} slices x 2 energies, sizes {{256,384,512}}^2, views "
+                        "{60,90,180,360}, seed 0",
+            "iters": iters, "tuned_view_groups": groups,
+            "slice_iters_per_s": round(n_slices * iters / t_batch, 1),
+            "ray_updates_per_s": round(samples * iters / t_batch, 1),
+            "ms_per_iteration_all_slices": round(1e3 * t_batch / iters, 3),
+            "sequential_slice_iters_per_s": round(n_slices * iters / t_seq, 1),
+            "speedup_vs_sequential": round(t_seq / t_batch, 3)}
+
+
+def unrolled_extra(steps: int, batch: int = 8):
+    """One training step of 10 unrolled ADM-TV iterations with learnable
+    per-step parameters (batch 8, 512^2, 180 views, checkpoint every 2): the
+    projector and its adjoint run in the library, the image-domain steps are
+    device tensor ops; milliseconds per forward + backward + Adam step."""
+    import torch
+    from paper_1607_01650_amd import configs as C, unrolled as U, warmstart as W
+    g = C.paper_geometry(512, 180)
+    gd, xt = [], []
+    for i in range(batch):
+        x, sino = W.make_case(g, 4000 + i)
+        gd.append(sino[0])
+        xt.append(x[0])
+    gdata, target = torch.stack(gd).contiguous(), torch.stack(xt).contiguous()
+    model = U.UnrolledADM(g, n_steps=10, mu=45.0 / 180, rho=1024.0, xi=256.0,
+                          alphas=[2e-4] * 10, checkpoint_every=2).cuda()
+    opt = torch.optim.Adam(model.parameters(), lr=1e-2)
+
+    def step():
+        opt.zero_grad()
+        f = model(gdata)
+        loss = ((f - target) ** 2).mean()
+        loss.backward()
+        opt.step()
+        return float(loss)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        last = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"workload": f"batch {batch} x 512x512, 180 views, 10 unrolled steps, checkpoint 2",
+            "ms_per_train_step": round(ms, 2), "loss": last}
 
 
 def _kernel_hash() -> str:

@@ -9,9 +9,10 @@ namespace dect {
 // Adjoint accumulation: a block's four wavefronts share one strip and split
 // its view group between them; each adds into its own LDS copy of the strip,
 // stored tap-line-major with row stride kSL (the 64 lanes of an access hit
-// distinct banks) plus a spare line on each side for the taps that fall just
-// outside the strip.
-constexpr int kAccRows = kSW + 2;
+// distinct banks) plus two spare lines on each side: a tap pair whose first
+// line is clamped to [-2, kSW] then always lands on real lines only when it
+// belongs there, and on spare lines otherwise.
+constexpr int kAccRows = kSW + 4;
 constexpr int kAccSize = kAccRows * kSL;
 constexpr int kAdjWaves = 4;
 
@@ -22,28 +23,53 @@ struct AdjShared {
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
 // ------------------------------------------------------------ forward ---
-// One driving-line loop over `line` in [l0, l1] for the lanes of one class.
-// base: padded line l0 at offset kPad (the element of index 0 of the line);
-// step: floats between consecutive lines.  q: this lane's 32.32 coordinate
-// at l0 (a sentinel far below -2 for lanes of the other class), dq its step.
-__device__ __forceinline__ void walk(const float *__restrict__ base, int step, int l0, int l1,
-                                     int64_t q, int64_t dq, int nq, double &acc0, double &acc1)
+// One driving-line loop over lines [l0, l1] for the lanes of one class, on
+// the padded plane `rs` (a buffer resource over the whole plane).  soff: byte
+// offset of line l0's element -2 (the plane's line start) and bstep the line
+// stride in bytes, both the same for every lane.  q: this lane's 32.32
+// coordinate at l0 (a sentinel far below -2 for lanes of the other class),
+// dq its step.  The taps h, h + 1 (h clamped to [-2, nq], so outside the grid
+// both read zero padding) are addressed by a 32-bit per-lane byte offset.
+// Groups of four samples are summed in FP32 and the group sums added in FP64
+// (acc0: first taps, acc1: weight x tap difference, the weight being the FP32
+// value (float)lo, scaled by 2^-32 at the end).
+__device__ __forceinline__ void walk(__amdgpu_buffer_rsrc_t rs, unsigned soff, unsigned bstep,
+                                     int l0, int l1, int64_t q, int64_t dq, int nq,
+                                     double &acc0, double &acc1)
 {
-    const float *line = base;
-#pragma unroll 4
-    for (int i = l0; i <= l1; ++i) {
-        int h = (int)(q >> 32);
-        unsigned lo = (unsigned)q;
-        h = min(max(h, -2), nq);  // outside [-1, nq-1]: both taps read zero padding
-        const double v0 = line[h];
-        const double v1 = line[h + 1];
-        acc0 += v0;
-        // the weight is the FP32 value (float)lo * 2^-32 that the adjoint also
-        // uses, so the two passes apply the same matrix
-        acc1 = fma((double)(float)lo, v1 - v0, acc1);
+    auto sample = [&](float &s0, float &s1) {
+        const int h = min(max((int)(q >> 32), -2), nq);
+        const unsigned lo = (unsigned)q;
+        const unsigned vo = (unsigned)(h + 2) * 4u;
+        const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, soff, 0));
+        const float v1 =
+            __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4u, soff, 0));
+        s0 += v0;
+        s1 = fmaf((float)lo, v1 - v0, s1);
         q += dq;
-        line += step;
+        soff += bstep;
+    };
+    int i = l0;
+    for (; i + 3 <= l1; i += 4) {
+        float s0 = 0.f, s1 = 0.f;
+        sample(s0, s1);
+        sample(s0, s1);
+        sample(s0, s1);
+        sample(s0, s1);
+        acc0 += (double)s0;
+        acc1 += (double)s1;
     }
+    float s0 = 0.f, s1 = 0.f;
+    for (; i <= l1; ++i) sample(s0, s1);
+    acc0 += (double)s0;
+    acc1 += (double)s1;
+}
+
+// Raw buffer resource over n_bytes at p (word 3 as for gfx9-family raw
+// buffers).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *p, unsigned n_bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)n_bytes, 0x00020000);
 }
 
 // One forward wavefront: view v and 64-bin bundle j from the wave index gw
@@ -80,17 +106,18 @@ __device__ __forceinline__ double fwd_wave(const float *__restrict__ pad_e,
     // the sign of the stored path length marks the ray class (+ x-major)
     const bool is_x = act && L > 0.f;
     const bool is_y = act && L < 0.f;
-    if (bu.x0 <= bu.x1) {
+    const unsigned plane_bytes = (unsigned)((size_t)pnx * pny * sizeof(float));
+    if (bu.x0 <= bu.x1) {  // x-major: lines are columns of the transposed copy
         int64_t q = is_x ? a + k * (int64_t)bu.x0 : far;
         int64_t dq = is_x ? k : 0;
-        walk(padT_e + (size_t)(bu.x0 + kPad) * pny + kPad, pny, bu.x0, bu.x1, q, dq, ny, acc0,
-             acc1);
+        walk(plane_rsrc(padT_e, plane_bytes), (unsigned)((bu.x0 + kPad) * pny * 4),
+             (unsigned)(pny * 4), bu.x0, bu.x1, q, dq, ny, acc0, acc1);
     }
-    if (bu.y0 <= bu.y1) {
+    if (bu.y0 <= bu.y1) {  // y-major: lines are rows of the padded image
         int64_t q = is_y ? a + k * (int64_t)bu.y0 : far;
         int64_t dq = is_y ? k : 0;
-        walk(pad_e + (size_t)(bu.y0 + kPad) * pnx + kPad, pnx, bu.y0, bu.y1, q, dq, nx, acc0,
-             acc1);
+        walk(plane_rsrc(pad_e, plane_bytes), (unsigned)((bu.y0 + kPad) * pnx * 4),
+             (unsigned)(pnx * 4), bu.y0, bu.y1, q, dq, nx, acc0, acc1);
     }
     double sum = (double)fabsf(L) * fma(acc1, (double)kTwoM32, acc0) * (double)scale;
     if (sub_e && act) sum -= sub_scale * (double)sub_e[(size_t)v * B + b];
@@ -143,10 +170,10 @@ __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict
     const int t0 = (sidx / nsL) * kSW, l0 = (sidx % nsL) * kSL;
     float *my = sh.acc[wid];
     for (int i = lane; i < kAccSize; i += 64) my[i] = 0.f;
-    // acc line 0 holds tap line t0 - 1 (spare), lines 1..kSW the strip, line
-    // kSW + 1 tap line t0 + kSW (spare)
+    // acc line j holds tap line t0 + j - 2: lines 0, 1 and kSW + 2, kSW + 3
+    // are spare
     float *col = my + lane;
-    const double ld = (double)(l0 + lane);  // this lane's driving line
+    const double ld = (double)lane;  // this lane's driving line, relative to l0
     const BinRange *sb = bins + (size_t)strip * V;
 
     const int v_begin = (int)((int64_t)V * g / nvg), v_end = (int)((int64_t)V * (g + 1) / nvg);
@@ -158,13 +185,15 @@ __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict
         const float *lv = len + (size_t)v * B;
         const float *yv = sino_e + (size_t)v * B;
         for (int cb = lo; cb <= hi; cb += 64) {
-            // lane j: bin cb + j
+            // lane j: bin cb + j, its line coordinate moved to the strip
+            // origin, q' = (a + k l0 - t0) + k lane (exact: all terms are
+            // multiples of 2^-32 below 2^21)
             const int bj = cb + lane;
             double aj = 0.0, kj = 0.0;
             float lyj = 0.f;
             if (bj <= hi) {
                 const RayAdj t = rv[bj];
-                aj = t.a;
+                aj = fma(t.k, (double)l0, t.a) - (double)t0;
                 kj = t.k;
                 lyj = fabsf(lv[bj]) * yv[bj];
             }
@@ -172,7 +201,8 @@ __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict
             const int alo = (int)ai, ahi = (int)(ai >> 32), klo = (int)ki, khi = (int)(ki >> 32);
             const int ly_bits = __float_as_int(lyj);
             const int nj = min(64, hi - cb + 1);
-            for (int j = 0; j < nj; ++j) {
+            // one bin: this lane's tap pair, added in bin order
+            auto tap = [&](int j) {
                 const double a = __longlong_as_double(
                     ((int64_t)__builtin_amdgcn_readlane(ahi, j) << 32) |
                     (uint32_t)__builtin_amdgcn_readlane(alo, j));
@@ -182,21 +212,20 @@ __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict
                 const float ly = __int_as_float(__builtin_amdgcn_readlane(ly_bits, j));
                 const double q = fma(k, ld, a);
                 const double fl = floor(q);
-                const int i0 = (int)fl - t0;  // first tap line, strip-relative
+                const int i0 = min(max((int)fl, -2), kSW);  // first tap line, strip-relative
                 const float w = (float)(q - fl);
-                float wl = w * ly, ol = ly - wl;
-                // taps on lines i0 and i0 + 1 -> acc lines ic + 1, ic + 2; a ray
-                // that misses the strip adds zeros
-                const int ic = min(max(i0, -1), kSW - 1);
-                if (ic != i0) {
-                    ol = 0.f;
-                    wl = 0.f;
-                }
-                float *pp = col + (ic + 1) * kSL;
+                const float wl = w * ly, ol = ly - wl;
+                float *pp = col + (i0 + 2) * kSL;
                 const float u0 = pp[0], u1 = pp[kSL];
                 pp[0] = u0 + ol;
                 pp[kSL] = u1 + wl;
+            };
+            int j = 0;
+            for (; j + 1 < nj; j += 2) {
+                tap(j);
+                tap(j + 1);
             }
+            if (j < nj) tap(j);
         }
     }
     __syncthreads();
@@ -208,12 +237,12 @@ __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict
             const int ti = i / kSL, li = i % kSL;
             r = t0 + ti;
             c = l0 + li;
-            k = (ti + 1) * kSL + li;
+            k = (ti + 2) * kSL + li;
         } else {         // strip row = lane, column = tap line
             const int li = i / kSW, ti = i % kSW;
             r = l0 + li;
             c = t0 + ti;
-            k = (ti + 1) * kSL + li;
+            k = (ti + 2) * kSL + li;
         }
         if (r < ny && c < nx) part[(size_t)r * nx + c] = ((a0[k] + a1[k]) + a2[k]) + a3[k];
     }
