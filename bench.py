@@ -318,7 +318,7 @@ def unrolled_extra(steps: int, batch: int = 8):
     projector and its adjoint run in the library, the image-domain steps are
     device tensor ops; milliseconds per forward + backward + Adam step."""
     import torch
-    from paper_1607_01650_amd import configs as C, unrolled as U, warmstart as W
+    from paper_1607_01650_amd import configs as C, dect, unrolled as U, warmstart as W
     g = C.paper_geometry(512, 180)
     gd, xt = [], []
     for i in range(batch):
@@ -326,8 +326,11 @@ def unrolled_extra(steps: int, batch: int = 8):
         gd.append(sino[0])
         xt.append(x[0])
     gdata, target = torch.stack(gd).contiguous(), torch.stack(xt).contiguous()
-    model = U.UnrolledADM(g, n_steps=10, mu=45.0 / 180, rho=1024.0, xi=256.0,
-                          alphas=[2e-4] * 10, checkpoint_every=2).cuda()
+    # initial per-step sizes: the plain method's first ten BB steps on case 0
+    p = C.default_adm_params(g, 10)
+    log = dect.adm_tv(gdata[0], gdata[0], g, p, want_log=True).alpha[:10, 0]
+    model = U.UnrolledADM(g, n_steps=10, mu=p.mu, rho=p.rho, xi=p.xi,
+                          alphas=[float(a) for a in log], checkpoint_every=2).cuda()
     opt = torch.optim.Adam(model.parameters(), lr=1e-2)
 
     def step():
@@ -346,7 +349,7 @@ def unrolled_extra(steps: int, batch: int = 8):
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / steps
     return {"workload": f"batch {batch} x 512x512, 180 views, 10 unrolled steps, checkpoint 2",
-            "ms_per_train_step": round(ms, 2), "loss": last}
+            "ms_per_train_step": round(ms, 2), "loss_mse": last}
 
 
 def _kernel_hash() -> str:
@@ -360,7 +363,8 @@ def _kernel_hash() -> str:
 
 
 def projector_launches(k: int):
-    """The roofline entry's projector launches alone (for counter runs)."""
+    """The roofline entry's projector launches alone (for counter runs), with
+    their average HIP-event time per launch."""
     import torch
     from paper_1607_01650_amd import configs as C, dect
     g = C.METRIC
@@ -369,14 +373,25 @@ def projector_launches(k: int):
     img = torch.empty((2, g.ny, g.nx), device="cuda")
     x = torch.randn((2, g.ny, g.nx), device="cuda", generator=gen)
     sino = torch.empty((2, g.n_views, g.n_bins), device="cuda")
+    ev = HipEvents()
+    sp = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dect.backproject(r, g, out=img)
+    dect.project(x, g, out=sino)
+    a0, a1, f0, f1 = ev.event(), ev.event(), ev.event(), ev.event()
+    ev.record(a0, sp)
     for _ in range(k):
         dect.backproject(r, g, out=img)
+    ev.record(a1, sp)
+    ev.record(f0, sp)
     for _ in range(k):
         dect.project(x, g, out=sino)
+    ev.record(f1, sp)
     torch.cuda.synchronize()
     S = dect.count_samples(g)
     M, N = g.n_views * g.n_bins, g.nx * g.ny
     print(json.dumps({"mode": "projectors", "launches": k, "samples": S,
+                      "backproject_us": round(1e3 * ev.ms(a0, a1) / k, 2),
+                      "project_us": round(1e3 * ev.ms(f0, f1) / k, 2),
                       "algorithmic_bytes_per_launch": 2 * (8 * S + 4 * M + 4 * N),
                       "kernel_hash": _kernel_hash()}), flush=True)
 

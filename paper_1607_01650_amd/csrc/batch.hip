@@ -59,25 +59,22 @@ __global__ __launch_bounds__(256) void kb_tv(const SliceDev *__restrict__ S,
     }
 }
 
-// item = (slice, energy, block of 4 wavefronts)
+// item = (slice, energy, (view, bundle) block)
 __global__ __launch_bounds__(256) void kb_fwd(const SliceDev *__restrict__ S,
                                               const int4 *__restrict__ items, int n)
 {
     __shared__ double red[256];
-    const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ FwdShared sh;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
         const int e = w.y, blk = w.z;
         if (!d.P.sc[e].stopped) {
             const size_t Pp = (size_t)(d.nx + 2 * kPad) * (d.ny + 2 * kPad);
-            const int gw = blk * 4 + wid;
-            double result = 0.0;
-            if (gw < d.V * d.nbundle)
-                result = fwd_wave(d.P.gpad + e * Pp, d.P.gpadT + e * Pp, d.fwd, d.len, d.bundles,
-                                  d.P.p + (size_t)e * d.M, d.nx, d.ny, d.B, d.nbundle, gw, lane,
-                                  1.0f, nullptr, 0.0, d.P.plo + (size_t)e * d.M);
+            const double result =
+                fwd_block(sh, d.P.gpad + e * Pp, d.P.gpadT + e * Pp, d.fwd, d.len, d.bundles,
+                          d.P.p + (size_t)e * d.M, d.nx, d.ny, d.B, d.nbundle, blk, 1.0f, nullptr,
+                          0.0, d.P.plo + (size_t)e * d.M);
             double tot = block_sum_256(result * result, red);
             if (threadIdx.x == 0) d.P.p_fwd[(size_t)e * d.P.nb_fwd + blk] = tot;
         }
@@ -131,7 +128,7 @@ __global__ __launch_bounds__(256) void kb_rr(const SliceDev *__restrict__ S,
 }
 
 // item = (slice, energy, strip of either ray class, view group)
-__global__ __launch_bounds__(256) void kb_adj(const SliceDev *__restrict__ S,
+__global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict__ S,
                                               const int4 *__restrict__ items, int n)
 {
     __shared__ AdjShared sh;
@@ -245,9 +242,10 @@ dect_status build_work(dect_batch *b)
     int dev = 0, cus = 0;
     DECT_HIP(hipGetDevice(&dev));
     DECT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    auto grid = [&](const void *fn, int items) {
+    auto grid = [&](const void *fn, int items, int threads = 256) {
         int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, 0) != hipSuccess ||
+            per < 1)
             per = 1;
         return std::max(1, std::min(items, per * cus));
     };
@@ -255,7 +253,7 @@ dect_status build_work(dect_batch *b)
     b->g_fwd = grid((const void *)kb_fwd, b->n_fwd);
     b->g_se = std::max(1, b->n_se);
     b->g_upd = grid((const void *)kb_update, b->n_upd);
-    b->g_adj = grid((const void *)kb_adj, b->n_adj);
+    b->g_adj = grid((const void *)kb_adj, b->n_adj, kAdjThreads);
     b->g_sum = grid((const void *)kb_adj_sum, b->n_sum);
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
@@ -282,7 +280,8 @@ dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
     hipLaunchKernelGGL(kb_rr, dim3(b->g_se), dim3(256), 0, s, S, (const int4 *)b->w_se.ptr,
                        b->n_se);
     DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_adj, dim3(b->g_adj), dim3(256), 0, s, S, (const int4 *)b->w_adj.ptr,
+    hipLaunchKernelGGL(kb_adj, dim3(b->g_adj), dim3(kAdjThreads), 0, s, S,
+                       (const int4 *)b->w_adj.ptr,
                        b->n_adj);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(kb_adj_sum, dim3(b->g_sum), dim3(256), 0, s, S, (const int4 *)b->w_sum.ptr,

@@ -61,8 +61,20 @@ constexpr int kPad = 2;       // zero border of the padded image copies
 // rows), y-major rays on strips of kSW columns x kSL rows (lane = row, taps
 // along the columns) -- the same walk on the transposed image.  Strips are
 // numbered x-major first: strip = ts * ceil(n_lane / kSL) + ls within a class.
-constexpr int kSL = 64;  // strip length along the lane axis (one wavefront)
-constexpr int kSW = 32;  // strip width along the tap axis
+#ifndef DECT_ADJ_STRIP_WIDTH
+#define DECT_ADJ_STRIP_WIDTH 32
+#endif
+#ifndef DECT_ADJ_WAVES
+#define DECT_ADJ_WAVES 4
+#endif
+#ifndef DECT_ADJ_BLOCKS
+#define DECT_ADJ_BLOCKS 1024
+#endif
+constexpr int kSL = 64;                    // strip length along the lane axis (one wavefront)
+constexpr int kSW = DECT_ADJ_STRIP_WIDTH;  // strip width along the tap axis
+constexpr int kAdjWaves = DECT_ADJ_WAVES;  // wavefronts per block (sharing one strip)
+constexpr int kAdjThreads = 64 * kAdjWaves;
+constexpr int kAdjBlocks = DECT_ADJ_BLOCKS;  // launch size the view grouping aims for
 __host__ __device__ inline int adj_strips_cls(int n_lane, int n_tap)
 {
     return ((n_lane + kSL - 1) / kSL) * ((n_tap + kSW - 1) / kSW);

@@ -6,7 +6,7 @@
 
 namespace dect {
 
-// Adjoint accumulation: a block's four wavefronts share one strip and split
+// Adjoint accumulation: a block's kAdjWaves wavefronts share one strip and split
 // its view group between them; each adds into its own LDS copy of the strip,
 // stored tap-line-major with row stride kSL (the 64 lanes of an access hit
 // distinct banks) plus two spare lines on each side: a tap pair whose first
@@ -14,7 +14,6 @@ namespace dect {
 // belongs there, and on spare lines otherwise.
 constexpr int kAccRows = kSW + 4;
 constexpr int kAccSize = kAccRows * kSL;
-constexpr int kAdjWaves = 4;
 
 struct AdjShared {
     float acc[kAdjWaves][kAccSize];
@@ -72,27 +71,37 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *p, uns
     return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)n_bytes, 0x00020000);
 }
 
-// One forward wavefront: view v and 64-bin bundle j from the wave index gw
-// (= v * nbundle + j) of one batch item.  pad_e/padT_e: that item's padded
-// image copies, sino_e its sinogram.  The ray sum is accumulated in FP64 (an
-// FP32 running sum over ~700 samples would carry ~1e-6 relative error, which
-// the reconstruction iteration amplifies).  With sub_e the value is
+// One forward block: view v and 64-bin bundle j from the index vb (= v *
+// nbundle + j) of one batch item; lane = bin.  Wavefront `part` (of 4) walks
+// the part-th quarter of each of the bundle's line ranges, so every
+// wavefront of the launch carries about the same work, and the four partial
+// sums are combined in part order.  pad_e/padT_e: that item's padded image
+// copies, sino_e its sinogram.  The ray sum is accumulated in FP64 (an FP32
+// running sum over ~700 samples would carry ~1e-6 relative error, which the
+// reconstruction iteration amplifies).  With sub_e the value is
 // scale * (A x) - sub_scale * sub_e, formed in FP64.  sino_e receives the
 // value rounded to FP32 and, when lo_e is given, lo_e the rounding remainder
-// (so that sino_e + lo_e carries the FP64 value to ~2^-48).  Returns this
-// lane's FP64 value (0 when the lane has no ray).
-__device__ __forceinline__ double fwd_wave(const float *__restrict__ pad_e,
-                                          const float *__restrict__ padT_e,
-                                          const RayFwd *__restrict__ rays,
-                                          const float *__restrict__ len,
-                                          const Bundle *__restrict__ bundles,
-                                          float *__restrict__ sino_e, int nx, int ny, int B,
-                                          int nbundle, int gw, int lane, float scale,
-                                          const float *__restrict__ sub_e = nullptr,
-                                          double sub_scale = 0.0,
-                                          float *__restrict__ lo_e = nullptr)
+// (so that sino_e + lo_e carries the FP64 value to ~2^-48).  Returns, in
+// wavefront 0, this lane's FP64 value (0 when the lane has no ray); 0 in the
+// other wavefronts.
+struct FwdShared {
+    double acc[4][2][64];
+};
+
+__device__ __forceinline__ double fwd_block(FwdShared &sh, const float *__restrict__ pad_e,
+                                           const float *__restrict__ padT_e,
+                                           const RayFwd *__restrict__ rays,
+                                           const float *__restrict__ len,
+                                           const Bundle *__restrict__ bundles,
+                                           float *__restrict__ sino_e, int nx, int ny, int B,
+                                           int nbundle, int vb, float scale,
+                                           const float *__restrict__ sub_e = nullptr,
+                                           double sub_scale = 0.0,
+                                           float *__restrict__ lo_e = nullptr)
 {
-    const int v = gw / nbundle, j = gw - v * nbundle;
+    const int lane = threadIdx.x & 63;
+    const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int v = vb / nbundle, j = vb - v * nbundle;
     const int b = j * kBundle + lane;
     const bool act = b < B;
     const size_t ray = (size_t)v * B + (act ? b : 0);
@@ -107,26 +116,50 @@ __device__ __forceinline__ double fwd_wave(const float *__restrict__ pad_e,
     const bool is_x = act && L > 0.f;
     const bool is_y = act && L < 0.f;
     const unsigned plane_bytes = (unsigned)((size_t)pnx * pny * sizeof(float));
+    auto quarter = [&](int l0, int l1, int &s0, int &s1) {
+        const int n = l1 - l0 + 1;
+        s0 = l0 + n * part / 4;
+        s1 = l0 + n * (part + 1) / 4 - 1;
+    };
     if (bu.x0 <= bu.x1) {  // x-major: lines are columns of the transposed copy
-        int64_t q = is_x ? a + k * (int64_t)bu.x0 : far;
-        int64_t dq = is_x ? k : 0;
-        walk(plane_rsrc(padT_e, plane_bytes), (unsigned)((bu.x0 + kPad) * pny * 4),
-             (unsigned)(pny * 4), bu.x0, bu.x1, q, dq, ny, acc0, acc1);
+        int s0, s1;
+        quarter(bu.x0, bu.x1, s0, s1);
+        if (s0 <= s1) {
+            int64_t q = is_x ? a + k * (int64_t)s0 : far;
+            int64_t dq = is_x ? k : 0;
+            walk(plane_rsrc(padT_e, plane_bytes), (unsigned)((s0 + kPad) * pny * 4),
+                 (unsigned)(pny * 4), s0, s1, q, dq, ny, acc0, acc1);
+        }
     }
     if (bu.y0 <= bu.y1) {  // y-major: lines are rows of the padded image
-        int64_t q = is_y ? a + k * (int64_t)bu.y0 : far;
-        int64_t dq = is_y ? k : 0;
-        walk(plane_rsrc(pad_e, plane_bytes), (unsigned)((bu.y0 + kPad) * pnx * 4),
-             (unsigned)(pnx * 4), bu.y0, bu.y1, q, dq, nx, acc0, acc1);
+        int s0, s1;
+        quarter(bu.y0, bu.y1, s0, s1);
+        if (s0 <= s1) {
+            int64_t q = is_y ? a + k * (int64_t)s0 : far;
+            int64_t dq = is_y ? k : 0;
+            walk(plane_rsrc(pad_e, plane_bytes), (unsigned)((s0 + kPad) * pnx * 4),
+                 (unsigned)(pnx * 4), s0, s1, q, dq, nx, acc0, acc1);
+        }
     }
-    double sum = (double)fabsf(L) * fma(acc1, (double)kTwoM32, acc0) * (double)scale;
-    if (sub_e && act) sum -= sub_scale * (double)sub_e[(size_t)v * B + b];
-    const float hi = (float)sum;
-    if (act) {
-        sino_e[(size_t)v * B + b] = hi;
-        if (lo_e) lo_e[(size_t)v * B + b] = (float)(sum - (double)hi);
+    sh.acc[part][0][lane] = acc0;
+    sh.acc[part][1][lane] = acc1;
+    __syncthreads();
+    double sum = 0.0;
+    if (part == 0) {
+        acc0 = ((sh.acc[0][0][lane] + sh.acc[1][0][lane]) + sh.acc[2][0][lane]) + sh.acc[3][0][lane];
+        acc1 = ((sh.acc[0][1][lane] + sh.acc[1][1][lane]) + sh.acc[2][1][lane]) + sh.acc[3][1][lane];
+        sum = (double)fabsf(L) * fma(acc1, (double)kTwoM32, acc0) * (double)scale;
+        if (sub_e && act) sum -= sub_scale * (double)sub_e[(size_t)v * B + b];
+        const float hi = (float)sum;
+        if (act) {
+            sino_e[(size_t)v * B + b] = hi;
+            if (lo_e) lo_e[(size_t)v * B + b] = (float)(sum - (double)hi);
+        } else {
+            sum = 0.0;
+        }
     }
-    return act ? sum : 0.0;
+    __syncthreads();  // the partials are consumed (persistent callers reuse them)
+    return sum;
 }
 
 // Fixed-order sum of one double per thread over a 256-thread block; the
@@ -229,9 +262,8 @@ __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict
         }
     }
     __syncthreads();
-    // the four copies summed in wave order; stored in normal image layout
-    const float *a0 = sh.acc[0], *a1 = sh.acc[1], *a2 = sh.acc[2], *a3 = sh.acc[3];
-    for (int i = threadIdx.x; i < kSW * kSL; i += 64 * kAdjWaves) {
+    // the copies summed in wave order; stored in normal image layout
+    for (int i = threadIdx.x; i < kSW * kSL; i += kAdjThreads) {
         int r, c, k;
         if (cls == 0) {  // strip row = tap line, column = lane
             const int ti = i / kSL, li = i % kSL;
@@ -244,7 +276,12 @@ __device__ __forceinline__ void adj_block(AdjShared &sh, const float *__restrict
             c = t0 + ti;
             k = (ti + 2) * kSL + li;
         }
-        if (r < ny && c < nx) part[(size_t)r * nx + c] = ((a0[k] + a1[k]) + a2[k]) + a3[k];
+        if (r < ny && c < nx) {
+            float sum = sh.acc[0][k];
+#pragma unroll
+            for (int w = 1; w < kAdjWaves; ++w) sum += sh.acc[w][k];
+            part[(size_t)r * nx + c] = sum;
+        }
     }
 }
 

@@ -63,17 +63,13 @@ __global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ pad,
                                              const float *__restrict__ sub1, double ss0, double ss1,
                                              float *__restrict__ lo)
 {
+    __shared__ FwdShared sh;
     const int e = blockIdx.y;
-    const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int gw = blockIdx.x * 4 + wid;
     const size_t p_off = (size_t)e * (nx + 2 * kPad) * (ny + 2 * kPad);
-    double result = 0.0;
-    if (gw < V * nbundle)
-        result = fwd_wave(pad + p_off, padT + p_off, rays, len, bundles,
-                          sino + (size_t)e * V * B, nx, ny, B, nbundle, gw, lane, scale,
-                          e == 0 ? sub0 : e == 1 ? sub1 : nullptr, e == 0 ? ss0 : ss1,
-                          lo ? lo + (size_t)e * V * B : nullptr);
+    const double result =
+        fwd_block(sh, pad + p_off, padT + p_off, rays, len, bundles, sino + (size_t)e * V * B, nx,
+                  ny, B, nbundle, blockIdx.x, scale, e == 0 ? sub0 : e == 1 ? sub1 : nullptr,
+                  e == 0 ? ss0 : ss1, lo ? lo + (size_t)e * V * B : nullptr);
     if (NORM) {
         __shared__ double red[256];
         double tot = block_sum_256(result * result, red);
@@ -84,7 +80,7 @@ __global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ pad,
 // ------------------------------------------------------------ adjoint ---
 // grid (strips of both classes, view groups, batch); part: [batch][2][nvg]
 // planes of nx*ny floats.
-__global__ __launch_bounds__(256) void k_adj(const float *__restrict__ sino,
+__global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ sino,
                                              const RayAdj *__restrict__ rays,
                                              const float *__restrict__ len,
                                              const BinRange *__restrict__ bins, int nx, int ny,
@@ -123,7 +119,7 @@ dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float 
     return DECT_OK;
 }
 
-int fwd_blocks(const GeomTables &t) { return (t.key.V * t.nbundle + 3) / 4; }
+int fwd_blocks(const GeomTables &t) { return t.key.V * t.nbundle; }
 
 dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
                        int batch, float scale, double *norm_partial, hipStream_t s,
@@ -144,12 +140,12 @@ dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT,
     return DECT_OK;
 }
 
-// View groups per strip: enough blocks for four per compute unit (1024 on
-// 256 CUs), but at least 8 views per group (two per wavefront).
+// View groups per strip: enough blocks to fill the chip (kAdjBlocks), but
+// at least 8 views per group.
 int adj_groups(const GeomTables &t, int batch)
 {
     const int strips = adj_strips(t.key.nx, t.key.ny);
-    int want = (1024 + strips * batch - 1) / (strips * batch);
+    int want = (kAdjBlocks + strips * batch - 1) / (strips * batch);
     int cap = std::max(1, t.key.V / 8);
     return std::max(1, std::min(want, cap));
 }
@@ -166,7 +162,8 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
     const GeomKey &k = t.key;
     const int nvg = adj_groups(t, batch);
     const size_t plane = (size_t)k.nx * k.ny;
-    hipLaunchKernelGGL(k_adj, dim3(adj_strips(k.nx, k.ny), nvg, batch), dim3(256), 0, s, sino,
+    hipLaunchKernelGGL(k_adj, dim3(adj_strips(k.nx, k.ny), nvg, batch), dim3(kAdjThreads), 0, s,
+                       sino,
                        t.adj, t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, partial);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((plane + 255) / 256), batch), dim3(256), 0, s,
