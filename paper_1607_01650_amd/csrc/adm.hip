@@ -23,6 +23,7 @@
 #include <cstring>
 
 #include "adm_device.h"
+#include "xcd.h"
 
 namespace dect {
 namespace {
@@ -34,7 +35,11 @@ __global__ __launch_bounds__(256) void k_tv_fused(
     float *__restrict__ gpad, float *__restrict__ gpadT, double *__restrict__ partial,
     const AdmScalars *__restrict__ sc, int nx, int ny, float rho, float xi)
 {
-    const int e = blockIdx.z;
+    // tiles in XCD order: each XCD takes a band of tile rows (shared halos)
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned tile = xcd_order(block_linear(), grid_blocks());
+    const int e = (int)(tile / (gx * gy));
+    const int ty = (int)(tile / gx % gy), tx = (int)(tile % gx);
     if (sc[e].stopped) return;
     const size_t N = (size_t)nx * ny, P = (size_t)(nx + 2 * kPad) * (ny + 2 * kPad);
     AdmImg m{f + e * N,
@@ -50,9 +55,7 @@ __global__ __launch_bounds__(256) void k_tv_fused(
              gpad + e * P,
              gpadT + e * P,
              f + 2 * N + e * N};
-    const size_t blk = (size_t)e * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x;
-    tv_tile(blockIdx.y * kT, blockIdx.x * kT, m, partial + blk * 5, sc[e].pending != 0, nx, ny,
-            rho, xi);
+    tv_tile(ty * kT, tx * kT, m, partial + (size_t)tile * 5, sc[e].pending != 0, nx, ny, rho, xi);
 }
 
 // One block per energy.  nb_tv/nb_fwd: partial counts per energy.

@@ -192,10 +192,28 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
     const bool run = !s.stopped;
     double v[6] = {0, 0, 0, 0, 0, 0};
     if (run) {
-        for (int i = threadIdx.x; i < nb_tv; i += 256)
+        // thread t adds entries t, t + 256, ... in that order; eight loads are
+        // issued together
+        for (int i0 = threadIdx.x; i0 < nb_tv; i0 += 256 * 4) {
+            double t[4][5];
 #pragma unroll
-            for (int j = 0; j < 5; ++j) v[j] += pt[(size_t)i * 5 + j];
-        for (int i = threadIdx.x; i < nb_fwd; i += 256) v[5] += pf[i];
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 256 * u;
+#pragma unroll
+                for (int j = 0; j < 5; ++j) t[u][j] = i < nb_tv ? pt[(size_t)i * 5 + j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int j = 0; j < 5; ++j) v[j] += t[u][j];
+        }
+        for (int i0 = threadIdx.x; i0 < nb_fwd; i0 += 256 * 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = i0 + 256 * u < nb_fwd ? pf[i0 + 256 * u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[5] += t[u];
+        }
     }
     block_sum<6>(v, tot);
     if (run && threadIdx.x == 0) {

@@ -14,6 +14,7 @@
 // is the exact transpose of the forward matrix.  No atomics: each pixel's sum
 // runs in a fixed order (views of a wave, waves of a block, view groups).
 #include "proj_device.h"
+#include "xcd.h"
 
 namespace dect {
 
@@ -64,16 +65,19 @@ __global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ pad,
                                              float *__restrict__ lo)
 {
     __shared__ FwdShared sh;
-    const int e = blockIdx.y;
+    // (view, bundle) blocks in XCD order: each XCD works on one energy's
+    // image, which then fits its L2
+    const unsigned item = xcd_order(block_linear(), grid_blocks());
+    const int e = (int)(item / gridDim.x), vb = (int)(item % gridDim.x);
     const size_t p_off = (size_t)e * (nx + 2 * kPad) * (ny + 2 * kPad);
     const double result =
         fwd_block(sh, pad + p_off, padT + p_off, rays, len, bundles, sino + (size_t)e * V * B, nx,
-                  ny, B, nbundle, blockIdx.x, scale, e == 0 ? sub0 : e == 1 ? sub1 : nullptr,
+                  ny, B, nbundle, vb, scale, e == 0 ? sub0 : e == 1 ? sub1 : nullptr,
                   e == 0 ? ss0 : ss1, lo ? lo + (size_t)e * V * B : nullptr);
     if (NORM) {
         __shared__ double red[256];
         double tot = block_sum_256(result * result, red);
-        if (threadIdx.x == 0) partial[(size_t)e * gridDim.x + blockIdx.x] = tot;
+        if (threadIdx.x == 0) partial[(size_t)e * gridDim.x + vb] = tot;
     }
 }
 
@@ -87,7 +91,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
                                              int V, int B, int nvg, float *__restrict__ part)
 {
     __shared__ AdjShared sh;
-    const int e = blockIdx.z, g = blockIdx.y, strip = blockIdx.x;
+    // (strip, view group, item) blocks in XCD order: the blocks of one XCD
+    // share a view group's rays and sinogram rows
+    const unsigned item = xcd_order(block_linear(), grid_blocks());
+    const int strip = (int)(item % gridDim.x), g = (int)(item / gridDim.x % gridDim.y);
+    const int e = (int)(item / (gridDim.x * gridDim.y));
     const int nsx = adj_strips_x(nx, ny);
     const size_t plane = (size_t)nx * ny;
     const int cls = strip < nsx ? 0 : 1;
