@@ -30,7 +30,8 @@ namespace {
 
 // ------------------------------------------------------------- kernels ---
 __global__ __launch_bounds__(256) void k_tv_fused(
-    const float *__restrict__ f, const float *__restrict__ h, const float *__restrict__ lam_in,
+    const float *__restrict__ f, const float *__restrict__ hpart, int nvg, float mu,
+    const float *__restrict__ lam_in,
     const float *__restrict__ z_in, float *__restrict__ lam_out, float *__restrict__ z_out,
     float *__restrict__ gpad, float *__restrict__ gpadT, double *__restrict__ partial,
     const AdmScalars *__restrict__ sc, int nx, int ny, float rho, float xi)
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void k_tv_fused(
     if (sc[e].stopped) return;
     const size_t N = (size_t)nx * ny, P = (size_t)(nx + 2 * kPad) * (ny + 2 * kPad);
     AdmImg m{f + e * N,
-             h + e * N,
+             hpart + (size_t)e * 2 * nvg * N,
              lam_in + (2 * e) * N,
              lam_in + (2 * e + 1) * N,
              z_in + (2 * e) * N,
@@ -54,7 +55,9 @@ __global__ __launch_bounds__(256) void k_tv_fused(
              z_out + (2 * e + 1) * N,
              gpad + e * P,
              gpadT + e * P,
-             f + 2 * N + e * N};
+             f + 2 * N + e * N,
+             2 * nvg,
+             mu};
     tv_tile(ty * kT, tx * kT, m, partial + (size_t)tile * 5, sc[e].pending != 0, nx, ny, rho, xi);
 }
 
@@ -202,7 +205,7 @@ struct dect_adm_state {
     bool started = false;
     double mu = 0, rho = 0, xi = 0, bh = 1, bl = 1;
     int nvg = 1, nb_tv = 0, nb_fwd = 0, nbi = 0, nbs = 0, nb_img = 0;
-    dect::DevBuf f, h, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, sc, logbuf,
+    dect::DevBuf f, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, sc, logbuf,
         p_tvo;
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
@@ -221,9 +224,9 @@ namespace dect {
 
 // Set-up of a run on raw state pointers: f = beta x0 (or 0), lambda = z = 0,
 // r = A f - beta m, h = mu A^T r, scalars reset.
-dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
-                     double mu, double bh, double bl, const float *x0h, const float *x0l,
-                     hipStream_t s)
+dect_status adm_init(const GeomTables &t, const AdmPtrs &P, int nvg, const float *mh,
+                     const float *ml, double mu, double bh, double bl, const float *x0h,
+                     const float *x0l, hipStream_t s)
 {
     const size_t N = (size_t)t.key.nx * t.key.ny;
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, P.sc, bh, bl);
@@ -240,7 +243,7 @@ dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, con
     hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_fwd, P.nb_fwd,
                        0, 0.0);
     DECT_HIP(hipGetLastError());
-    return launch_adj(t, P.r, P.h, P.adjpart, 2, (float)mu, s);
+    return launch_adj(t, P.r, nullptr, P.adjpart, 2, (float)mu, s, nvg);
 }
 
 // Marks the start of a call's log (row 0 = the next iteration).
@@ -273,7 +276,6 @@ static AdmPtrs ptrs_of(dect_adm_state *S)
     AdmPtrs P;
     P.f = (float *)S->f.ptr;
     P.flo = P.f + 2 * (size_t)S->t->key.nx * S->t->key.ny;
-    P.h = (float *)S->h.ptr;
     const size_t M = (size_t)S->t->key.V * S->t->key.B;
     P.r = (float *)S->r.ptr;
     P.rlo = P.r + 2 * M;
@@ -312,7 +314,7 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
     S->nbi = (int)((N + 1023) / 1024);
     S->nbs = (int)((M + 1023) / 1024);
     S->nb_img = S->nbi;
-    if ((st = S->f.ensure(4 * N * 4)) || (st = S->h.ensure(2 * N * 4)) ||
+    if ((st = S->f.ensure(4 * N * 4)) ||
         (st = S->r.ensure(4 * M * 4)) || (st = S->p.ensure(4 * M * 4)) ||
         (st = S->lam.ensure(8 * N * 4)) || (st = S->z.ensure(8 * N * 4)) ||
         (st = S->gpad.ensure(2 * P * 4, true)) || (st = S->gpadT.ensure(2 * P * 4, true)) ||
@@ -340,7 +342,8 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     AdmScalars *sc = (AdmScalars *)S->sc.ptr;
     dim3 gtv((nx + kT - 1) / kT, (ny + kT - 1) / kT, 2);
     hipLaunchKernelGGL(k_tv_fused, gtv, dim3(256), 0, s, (const float *)S->f.ptr,
-                       (const float *)S->h.ptr, lam_in, z_in, lam_out, z_out,
+                       (const float *)S->adjpart.ptr, S->nvg, (float)S->mu, lam_in, z_in,
+                       lam_out, z_out,
                        (float *)S->gpad.ptr, (float *)S->gpadT.ptr, (double *)S->p_tv.ptr, sc,
                        nx, ny, (float)S->rho, (float)S->xi);
     DECT_HIP(hipGetLastError());
@@ -360,8 +363,8 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_rr.ptr, S->nbs, 1,
                        tol);
     DECT_HIP(hipGetLastError());
-    return launch_adj(t, (const float *)S->r.ptr, (float *)S->h.ptr, (float *)S->adjpart.ptr, 2,
-                      (float)S->mu, s);
+    return launch_adj(t, (const float *)S->r.ptr, nullptr, (float *)S->adjpart.ptr, 2,
+                      (float)S->mu, s, S->nvg);
 }
 
 static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const float *mh,
@@ -373,7 +376,8 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     S->bh = P->beta_high;
     S->bl = P->beta_low;
     S->parity = 0;
-    dect_status st = adm_init(*S->t, ptrs_of(S), mh, ml, S->mu, S->bh, S->bl, x0h, x0l, s);
+    dect_status st =
+        adm_init(*S->t, ptrs_of(S), S->nvg, mh, ml, S->mu, S->bh, S->bl, x0h, x0l, s);
     if (st) return st;
     S->started = true;
     return DECT_OK;

@@ -48,10 +48,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
     __syncthreads();
 }
 
-// Device pointers of one slice's ADM state (both energies).  Layouts: f, flo,
-// h [2][N]; r, rlo, p, plo [2][M]; lambda, z [parity][energy][comp][N];
+// Device pointers of one slice's ADM state (both energies).  Layouts: f, flo
+// [2][N]; r, rlo, p, plo [2][M]; lambda, z [parity][energy][comp][N];
 // gpad, gpadT [2][(ny+4)(nx+4)] / [2][(nx+4)(ny+4)]; partials per energy
-// and block.  The image and the residual r = A f - beta m are carried as
+// and block; adjpart the back-projector's partial planes of h = mu A^T r
+// ([energy][class][view group][N]).  The image and the residual r = A f - beta m are carried as
 // unevaluated sums of two FP32 values (f + flo, r + rlo, |lo| <= half an ulp
 // of the first part), and A G arrives as p + plo from the projector's FP64
 // sum; both updates are formed in FP64.  The iterates then take no FP32
@@ -59,25 +60,29 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
 // the back-projector and the finite differences read FP32 values (f, r and
 // f + flo respectively).
 struct AdmPtrs {
-    float *f, *flo, *h, *r, *rlo, *p, *plo, *lam, *z, *gpad, *gpadT, *adjpart;
+    float *f, *flo, *r, *rlo, *p, *plo, *lam, *z, *gpad, *gpadT, *adjpart;
     double *p_tv, *p_fwd, *p_rr, *p_tvo, *log;
     int log_rows;
     AdmScalars *sc;
     int nb_tv, nb_fwd, nbi, nbs;
 };
 
-dect_status adm_init(const GeomTables &t, const AdmPtrs &P, const float *mh, const float *ml,
-                     double mu, double bh, double bl, const float *x0h, const float *x0l,
-                     hipStream_t s);
+dect_status adm_init(const GeomTables &t, const AdmPtrs &P, int nvg, const float *mh,
+                     const float *ml, double mu, double bh, double bl, const float *x0h,
+                     const float *x0l, hipStream_t s);
 dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s);
 dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
                        double bh, double bl, hipStream_t s);
 
-// Pointers of one energy image's ADM state.
+// Pointers of one energy image's ADM state.  h: hq partial planes whose sum
+// times hmu is mu A^T r (summed here in plane order, as the back-projector's
+// own summation kernel does).
 struct AdmImg {
     const float *f, *h, *lxi, *lyi, *zxi, *zyi;
     float *lxo, *lyo, *zxo, *zyo, *gpad, *gpadT;
     const float *flo;
+    int hq;
+    float hmu;
 };
 
 // ------------------------------------------------------------- tv_fused ---
@@ -145,7 +150,10 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
         int r = r0 - 1 + rr, c = c0 - 1 + cc;
         float gv = 0.f;
         if (r >= 0 && r < ny && c >= 0 && c < nx) {
-            float s = m.h[(size_t)r * nx + c];
+            const size_t o = (size_t)r * nx + c, N = (size_t)nx * ny;
+            float s = 0.f;
+            for (int q = 0; q < m.hq; ++q) s += m.h[(size_t)q * N + o];
+            s *= m.hmu;
             if (c >= 1) s += swx[rr][cc];
             if (c + 1 <= nx - 1) s -= swx[rr][cc + 1];
             if (r >= 1) s += swy[rr][cc];

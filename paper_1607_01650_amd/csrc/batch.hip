@@ -34,11 +34,21 @@ __device__ __forceinline__ AdmImg img_of(const SliceDev &d, int e, int par)
     const size_t N = (size_t)d.nx * d.ny, Pp = (size_t)(d.nx + 2 * kPad) * (d.ny + 2 * kPad);
     const float *lin = d.P.lam + (size_t)par * 4 * N, *zin = d.P.z + (size_t)par * 4 * N;
     float *lout = d.P.lam + (size_t)(1 - par) * 4 * N, *zout = d.P.z + (size_t)(1 - par) * 4 * N;
-    return AdmImg{d.P.f + e * N,          d.P.h + e * N,           lin + (2 * e) * N,
-                  lin + (2 * e + 1) * N,  zin + (2 * e) * N,       zin + (2 * e + 1) * N,
-                  lout + (2 * e) * N,     lout + (2 * e + 1) * N,  zout + (2 * e) * N,
-                  zout + (2 * e + 1) * N, d.P.gpad + e * Pp,       d.P.gpadT + e * Pp,
-                  d.P.flo + e * N};
+    return AdmImg{d.P.f + e * N,
+                  d.P.adjpart + (size_t)e * 2 * d.nvg * N,
+                  lin + (2 * e) * N,
+                  lin + (2 * e + 1) * N,
+                  zin + (2 * e) * N,
+                  zin + (2 * e + 1) * N,
+                  lout + (2 * e) * N,
+                  lout + (2 * e + 1) * N,
+                  zout + (2 * e) * N,
+                  zout + (2 * e + 1) * N,
+                  d.P.gpad + e * Pp,
+                  d.P.gpadT + e * Pp,
+                  d.P.flo + e * N,
+                  2 * d.nvg,
+                  d.muf};
 }
 
 // item = (slice, energy, tile row, tile column)
@@ -146,24 +156,6 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
     }
 }
 
-// item = (slice, energy, chunk of 1024 pixels): h = mu * (sum of the partials)
-__global__ __launch_bounds__(256) void kb_adj_sum(const SliceDev *__restrict__ S,
-                                                  const int4 *__restrict__ items, int n)
-{
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int4 w = items[it];
-        const SliceDev &d = S[w.x];
-        const int e = w.y;
-        if (d.P.sc[e].stopped) continue;
-        const size_t plane = (size_t)d.nx * d.ny;
-        const float *pe = d.P.adjpart + (size_t)e * 2 * d.nvg * plane;
-        for (int j = 0; j < 4; ++j) {
-            const size_t i = (size_t)w.z * 1024 + j * 256 + threadIdx.x;
-            if (i < plane) d.P.h[(size_t)e * plane + i] = adj_sum_pixel(pe, plane, d.nvg, i) * d.muf;
-        }
-    }
-}
-
 }  // namespace
 }  // namespace dect
 
@@ -173,9 +165,9 @@ struct dect_batch {
     std::vector<dect_adm_params> prm;
     std::vector<dect::SliceDev> host;
     std::vector<size_t> off;  // arena offsets per slice
-    dect::DevBuf arena, slices, w_tv, w_fwd, w_se, w_upd, w_adj, w_sum;
-    int n_tv = 0, n_fwd = 0, n_se = 0, n_upd = 0, n_adj = 0, n_sum = 0;
-    int g_tv = 0, g_fwd = 0, g_se = 0, g_upd = 0, g_adj = 0, g_sum = 0;
+    dect::DevBuf arena, slices, w_tv, w_fwd, w_se, w_upd, w_adj;
+    int n_tv = 0, n_fwd = 0, n_se = 0, n_upd = 0, n_adj = 0;
+    int g_tv = 0, g_fwd = 0, g_se = 0, g_upd = 0, g_adj = 0;
     int nvg_max = 16, group_choice = 0;  // 0: per-slice heuristic, else fixed
     hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;
@@ -196,7 +188,7 @@ int heuristic_groups(const GeomTables &t) { return adj_groups(t, 2); }
 // Work lists and persistent grid sizes for the current view-group choice.
 dect_status build_work(dect_batch *b)
 {
-    std::vector<std::pair<double, int4>> tv, fwd, se, upd, adj, sum;
+    std::vector<std::pair<double, int4>> tv, fwd, se, upd, adj;
     for (int s = 0; s < b->n; ++s) {
         SliceDev &d = b->host[s];
         const GeomTables &t = *b->t[s];
@@ -207,7 +199,6 @@ dect_status build_work(dect_batch *b)
         d.nvg = nvg;
         const int gx = (d.nx + kT - 1) / kT, gy = (d.ny + kT - 1) / kT;
         const int nstrips = adj_strips(d.nx, d.ny);
-        const int nchunks = (d.nx * d.ny + 1023) / 1024;
         for (int e = 0; e < 2; ++e) {
             for (int ty = 0; ty < gy; ++ty)
                 for (int tx = 0; tx < gx; ++tx) tv.push_back({1.0, make_int4(s, e, ty, tx)});
@@ -218,7 +209,6 @@ dect_status build_work(dect_batch *b)
             for (int strip = 0; strip < nstrips; ++strip)
                 for (int g = 0; g < nvg; ++g)
                     adj.push_back({(double)d.V / nvg, make_int4(s, e, strip, g)});
-            for (int k = 0; k < nchunks; ++k) sum.push_back({(double)nvg, make_int4(s, e, k, 0)});
         }
     }
     auto upload = [&](std::vector<std::pair<double, int4>> &v, DevBuf &buf, int &count) {
@@ -235,7 +225,7 @@ dect_status build_work(dect_batch *b)
     dect_status st;
     if ((st = upload(tv, b->w_tv, b->n_tv)) || (st = upload(fwd, b->w_fwd, b->n_fwd)) ||
         (st = upload(se, b->w_se, b->n_se)) || (st = upload(upd, b->w_upd, b->n_upd)) ||
-        (st = upload(adj, b->w_adj, b->n_adj)) || (st = upload(sum, b->w_sum, b->n_sum)))
+        (st = upload(adj, b->w_adj, b->n_adj)))
         return st;
     DECT_HIP(hipMemcpy(b->slices.ptr, b->host.data(), b->host.size() * sizeof(SliceDev),
                        hipMemcpyHostToDevice));
@@ -254,7 +244,6 @@ dect_status build_work(dect_batch *b)
     b->g_se = std::max(1, b->n_se);
     b->g_upd = grid((const void *)kb_update, b->n_upd);
     b->g_adj = grid((const void *)kb_adj, b->n_adj, kAdjThreads);
-    b->g_sum = grid((const void *)kb_adj_sum, b->n_sum);
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
@@ -283,9 +272,6 @@ dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
     hipLaunchKernelGGL(kb_adj, dim3(b->g_adj), dim3(kAdjThreads), 0, s, S,
                        (const int4 *)b->w_adj.ptr,
                        b->n_adj);
-    DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_adj_sum, dim3(b->g_sum), dim3(256), 0, s, S, (const int4 *)b->w_sum.ptr,
-                       b->n_sum);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -319,8 +305,8 @@ dect_status batch_run(dect_batch *b, const float *const *mh, const float *const 
     dect_status st;
     for (int i = 0; i < b->n; ++i) {
         const dect_adm_params &p = b->prm[i];
-        if ((st = adm_init(*b->t[i], b->host[i].P, mh[i], ml[i], p.mu, p.beta_high, p.beta_low,
-                           nullptr, nullptr, s)))
+        if ((st = adm_init(*b->t[i], b->host[i].P, b->host[i].nvg, mh[i], ml[i], p.mu,
+                           p.beta_high, p.beta_low, nullptr, nullptr, s)))
             return st;
         if ((st = adm_mark_log(b->host[i].P, s))) return st;
     }
@@ -364,7 +350,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         z.nbs = (z.M + 1023) / 1024;
         z.part = adj_partial_floats(t, 2, std::max(b->nvg_max, adj_groups(t, 2)));
         size_t bytes = 0;
-        bytes += align256(4 * z.N * 4) + align256(2 * z.N * 4);  // f (+ flo), h
+        bytes += align256(4 * z.N * 4);             // f (+ flo)
         bytes += align256(4 * z.M * 4) * 2;         // r (+ rlo), p (+ plo)
         bytes += align256(8 * z.N * 4) * 2;         // lam, z
         bytes += align256(2 * z.Pp * 4) * 2;        // gpad, gpadT
@@ -391,7 +377,6 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         std::memset(&d, 0, sizeof(d));
         d.P.f = (float *)take(4 * z.N * 4);
         d.P.flo = d.P.f + 2 * z.N;
-        d.P.h = (float *)take(2 * z.N * 4);
         d.P.r = (float *)take(4 * z.M * 4);
         d.P.rlo = d.P.r + 2 * z.M;
         d.P.p = (float *)take(4 * z.M * 4);

@@ -149,11 +149,14 @@ dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT,
                        double ss0 = 0.0, double ss1 = 0.0, float *lo = nullptr);
 int fwd_blocks(const GeomTables &t);
 // img[e] = scale * A^T sino[e], through `partial`: adj_partial_floats()
-// floats of scratch (per item, both ray classes and every view group).
+// floats of scratch (per item, both ray classes and every view group).  With
+// img == NULL only the partial planes are formed ([item][class][group][N];
+// img[e] = scale * their sum in that order).  nvg: view groups, <= 0 for
+// adj_groups(t, batch).
 int adj_groups(const GeomTables &t, int batch);
 size_t adj_partial_floats(const GeomTables &t, int batch, int nvg = 0);
 dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float *partial,
-                       int batch, float scale, hipStream_t s);
+                       int batch, float scale, hipStream_t s, int nvg = 0);
 
 dect_status project(const dect_geometry *g, const float *img, float *sino, int batch,
                     hipStream_t s);

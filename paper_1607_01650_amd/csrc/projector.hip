@@ -165,15 +165,16 @@ size_t adj_partial_floats(const GeomTables &t, int batch, int nvg)
 }
 
 dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float *partial,
-                       int batch, float scale, hipStream_t s)
+                       int batch, float scale, hipStream_t s, int nvg)
 {
     const GeomKey &k = t.key;
-    const int nvg = adj_groups(t, batch);
+    if (nvg <= 0) nvg = adj_groups(t, batch);
     const size_t plane = (size_t)k.nx * k.ny;
     hipLaunchKernelGGL(k_adj, dim3(adj_strips(k.nx, k.ny), nvg, batch), dim3(kAdjThreads), 0, s,
                        sino,
                        t.adj, t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, partial);
     DECT_HIP(hipGetLastError());
+    if (!img) return DECT_OK;  // the caller consumes the partial planes itself
     hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((plane + 255) / 256), batch), dim3(256), 0, s,
                        (const float *)partial, nvg, plane, img, scale);
     DECT_HIP(hipGetLastError());
