@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_tv_fused(
     const int e = (int)(tile / (gx * gy));
     const int ty = (int)(tile / gx % gy), tx = (int)(tile % gx);
     if (sc[e].stopped) return;
-    const size_t N = (size_t)nx * ny, P = (size_t)(nx + 2 * kPad) * (ny + 2 * kPad);
+    const size_t N = (size_t)nx * ny;
     AdmImg m{f + e * N,
              hpart + (size_t)e * 2 * nvg * N,
              lam_in + (2 * e) * N,
@@ -53,8 +53,8 @@ __global__ __launch_bounds__(256) void k_tv_fused(
              lam_out + (2 * e + 1) * N,
              z_out + (2 * e) * N,
              z_out + (2 * e + 1) * N,
-             gpad + e * P,
-             gpadT + e * P,
+             gpad + e,
+             gpadT + e,
              f + 2 * N + e * N,
              2 * nvg,
              mu};
@@ -84,9 +84,9 @@ __global__ __launch_bounds__(256) void k_update(float *__restrict__ f,
 {
     const int e = blockIdx.y;
     if (sc[e].stopped) return;
-    const size_t N = (size_t)nx * ny, P = (size_t)(nx + 2 * kPad) * (ny + 2 * kPad);
+    const size_t N = (size_t)nx * ny;
     const size_t Ms = (size_t)M;
-    update_chunk(blockIdx.x, f + e * N, f + 2 * N + e * N, gpad + e * P, r + e * Ms,
+    update_chunk(blockIdx.x, f + e * N, f + 2 * N + e * N, gpad + e, r + e * Ms,
                  r + 2 * Ms + e * Ms, p + e * Ms, p + 2 * Ms + e * Ms, p_rr + (size_t)e * nbs,
                  sc[e].alpha, nx, ny, M, nbi);
 }
@@ -447,7 +447,6 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
                            S->bh != P->beta_high || S->bl != P->beta_low))
             return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: parameters differ from the state's run");
     }
-    const size_t N = (size_t)g->nx * g->ny;
     const int K = P->max_iter;
     const size_t log_rows = (size_t)K + 1;
     // the device log keeps at least 4096 rows so that calls of different

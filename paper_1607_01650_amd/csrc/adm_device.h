@@ -50,7 +50,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
 
 // Device pointers of one slice's ADM state (both energies).  Layouts: f, flo
 // [2][N]; r, rlo, p, plo [2][M]; lambda, z [parity][energy][comp][N];
-// gpad, gpadT [2][(ny+4)(nx+4)] / [2][(nx+4)(ny+4)]; partials per energy
+// gpad, gpadT [(ny+4)(nx+4)][2] / [(nx+4)(ny+4)][2] (the projector's
+// interleaved padded layouts, both energies of a pixel side by side); partials per energy
 // and block; adjpart the back-projector's partial planes of h = mu A^T r
 // ([energy][class][view group][N]).  The image and the residual r = A f - beta m are carried as
 // unevaluated sums of two FP32 values (f + flo, r + rlo, |lo| <= half an ulp
@@ -76,7 +77,8 @@ dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *
 
 // Pointers of one energy image's ADM state.  h: hq partial planes whose sum
 // times hmu is mu A^T r (summed here in plane order, as the back-projector's
-// own summation kernel does).
+// own summation kernel does).  gpad/gpadT point at this energy's first
+// element of the interleaved padded layouts (element stride 2).
 struct AdmImg {
     const float *f, *h, *lxi, *lyi, *zxi, *zyi;
     float *lxo, *lyo, *zxo, *zyo, *gpad, *gpadT;
@@ -175,11 +177,12 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             float gy = r >= 1 ? gv - sg[rr][cc + 1] : 0.f;
             gg = (double)gv * gv;
             gradg = (double)gx * gx + (double)gy * gy;
-            m.gpad[(size_t)(r + kPad) * pnx + c + kPad] = gv;
+            m.gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad)] = gv;
         }
         // transposed write: thread (rr, cc) writes element (cc, rr) of the tile
         int rt = r0 + cc, ct = c0 + rr;
-        if (rt < ny && ct < nx) m.gpadT[(size_t)(ct + kPad) * pny + rt + kPad] = sg[cc + 1][rr + 1];
+        if (rt < ny && ct < nx)
+            m.gpadT[2 * ((size_t)(ct + kPad) * pny + rt + kPad)] = sg[cc + 1][rr + 1];
     }
     double v[5] = {tv, gg, gradg, pres, ff};
     block_sum<5>(v, outv);
@@ -255,6 +258,7 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
 // Chunk bx of 1024 elements: bx < nbi updates the image (f + flo) -= alpha G
 // in FP64, split again into f + flo; otherwise sinogram chunk bx - nbi:
 // (r + rlo) -= alpha (p + plo) likewise, partial |r|^2 into p_rr[bx - nbi].
+// gpad_e: this energy's first element of the interleaved padded G.
 __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
                                              float *__restrict__ fle,
                                              const float *__restrict__ gpad_e,
@@ -272,7 +276,7 @@ __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
             size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
             if (i < N) {
                 int rr = (int)(i / nx), cc = (int)(i % nx);
-                const double g = gpad_e[(size_t)(rr + kPad) * pnx + cc + kPad];
+                const double g = gpad_e[2 * ((size_t)(rr + kPad) * pnx + cc + kPad)];
                 const double d = ((double)fe[i] + (double)fle[i]) - alpha * g;
                 const float hi = (float)d;
                 fe[i] = hi;

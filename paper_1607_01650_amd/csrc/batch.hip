@@ -1,8 +1,9 @@
 // Batched ADM-TV: many slices of uneven size and view count, both energies,
 // advanced together.  Each phase of an iteration (tv stencil, forward
 // projection, step, update, residual norm, back-projection) is ONE
-// persistent launch over a work list that spans every slice and energy;
-// a captured hipGraph replays an even/odd pair of iterations.  Items are
+// persistent launch over a work list that spans every slice (and energy,
+// for the image-domain phases; a projector item carries both energies of its
+// slice); a captured hipGraph replays an even/odd pair of iterations.  Items are
 // sorted by estimated cost (longest first) and handed to the persistent
 // blocks round-robin; the adjoint's view-group depth (how many blocks share
 // one output tile) is chosen per batch by a timing autotuner.
@@ -31,7 +32,7 @@ namespace {
 
 __device__ __forceinline__ AdmImg img_of(const SliceDev &d, int e, int par)
 {
-    const size_t N = (size_t)d.nx * d.ny, Pp = (size_t)(d.nx + 2 * kPad) * (d.ny + 2 * kPad);
+    const size_t N = (size_t)d.nx * d.ny;
     const float *lin = d.P.lam + (size_t)par * 4 * N, *zin = d.P.z + (size_t)par * 4 * N;
     float *lout = d.P.lam + (size_t)(1 - par) * 4 * N, *zout = d.P.z + (size_t)(1 - par) * 4 * N;
     return AdmImg{d.P.f + e * N,
@@ -44,8 +45,8 @@ __device__ __forceinline__ AdmImg img_of(const SliceDev &d, int e, int par)
                   lout + (2 * e + 1) * N,
                   zout + (2 * e) * N,
                   zout + (2 * e + 1) * N,
-                  d.P.gpad + e * Pp,
-                  d.P.gpadT + e * Pp,
+                  d.P.gpad + e,
+                  d.P.gpadT + e,
                   d.P.flo + e * N,
                   2 * d.nvg,
                   d.muf};
@@ -69,24 +70,34 @@ __global__ __launch_bounds__(256) void kb_tv(const SliceDev *__restrict__ S,
     }
 }
 
-// item = (slice, energy, (view, bundle) block)
-__global__ __launch_bounds__(256) void kb_fwd(const SliceDev *__restrict__ S,
-                                              const int4 *__restrict__ items, int n)
+// item = (slice, (view, bundle) block): both energies
+__global__ __launch_bounds__(kFwdThreads) void kb_fwd(const SliceDev *__restrict__ S,
+                                                      const int4 *__restrict__ items, int n)
 {
-    __shared__ double red[256];
     __shared__ FwdShared sh;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
-        const int e = w.y, blk = w.z;
-        if (!d.P.sc[e].stopped) {
-            const size_t Pp = (size_t)(d.nx + 2 * kPad) * (d.ny + 2 * kPad);
-            const double result =
-                fwd_block(sh, d.P.gpad + e * Pp, d.P.gpadT + e * Pp, d.fwd, d.len, d.bundles,
-                          d.P.p + (size_t)e * d.M, d.nx, d.ny, d.B, d.nbundle, blk, 1.0f, nullptr,
-                          0.0, d.P.plo + (size_t)e * d.M);
-            double tot = block_sum_256(result * result, red);
-            if (threadIdx.x == 0) d.P.p_fwd[(size_t)e * d.P.nb_fwd + blk] = tot;
+        const int blk = w.y;
+        if (!(d.P.sc[0].stopped && d.P.sc[1].stopped)) {
+            FwdOut o;
+            for (int e = 0; e < 2; ++e) {
+                o.sino[e] = d.P.p + (size_t)e * d.M;
+                o.lo[e] = d.P.plo + (size_t)e * d.M;
+                o.sub[e] = nullptr;
+                o.sub_scale[e] = 0.0;
+            }
+            double res[2];
+            fwd_block(sh, d.P.gpad, d.P.gpadT, d.fwd, d.len, d.bundles, o, d.nx, d.ny, d.B,
+                      d.nbundle, blk, 1.0f, res);
+            if (threadIdx.x < 64) {  // the values live in wavefront 0
+                const double t0 = lane_sum(res[0] * res[0]);
+                const double t1 = lane_sum(res[1] * res[1]);
+                if (threadIdx.x == 0) {
+                    d.P.p_fwd[blk] = t0;
+                    d.P.p_fwd[(size_t)d.P.nb_fwd + blk] = t1;
+                }
+            }
         }
         __syncthreads();
     }
@@ -115,8 +126,8 @@ __global__ __launch_bounds__(256) void kb_update(const SliceDev *__restrict__ S,
         const SliceDev &d = S[w.x];
         const int e = w.y;
         if (!d.P.sc[e].stopped) {
-            const size_t N = (size_t)d.nx * d.ny, Pp = (size_t)(d.nx + 2 * kPad) * (d.ny + 2 * kPad);
-            update_chunk(w.z, d.P.f + e * N, d.P.flo + e * N, d.P.gpad + e * Pp,
+            const size_t N = (size_t)d.nx * d.ny;
+            update_chunk(w.z, d.P.f + e * N, d.P.flo + e * N, d.P.gpad + e,
                          d.P.r + (size_t)e * d.M, d.P.rlo + (size_t)e * d.M,
                          d.P.p + (size_t)e * d.M, d.P.plo + (size_t)e * d.M,
                          d.P.p_rr + (size_t)e * d.P.nbs, d.P.sc[e].alpha, d.nx, d.ny, d.M,
@@ -137,21 +148,24 @@ __global__ __launch_bounds__(256) void kb_rr(const SliceDev *__restrict__ S,
     }
 }
 
-// item = (slice, energy, strip of either ray class, view group)
+// item = (slice, strip of either ray class, view group): both energies
 __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict__ S,
                                               const int4 *__restrict__ items, int n)
 {
-    __shared__ AdjShared sh;
+    __shared__ AdjShared<2> sh;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
-        const int e = w.y, strip = w.z, g = w.w;
+        const int strip = w.y, g = w.z;
         const size_t plane = (size_t)d.nx * d.ny;
         const int cls = strip < adj_strips_x(d.nx, d.ny) ? 0 : 1;
-        if (!d.P.sc[e].stopped)
-            adj_block(sh, d.P.r + (size_t)e * d.M, d.adj, d.len, d.bins, d.nx, d.ny, d.V, d.B,
-                      strip, g, d.nvg,
-                      d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane);
+        if (!(d.P.sc[0].stopped && d.P.sc[1].stopped)) {
+            const float *s[2] = {d.P.r, d.P.r + d.M};
+            float *p[2];
+            for (int e = 0; e < 2; ++e)
+                p[e] = d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
+            adj_block<2>(sh, s, d.adj, d.len, d.bins, d.nx, d.ny, d.V, d.B, strip, g, d.nvg, p);
+        }
         __syncthreads();
     }
 }
@@ -202,14 +216,15 @@ dect_status build_work(dect_batch *b)
         for (int e = 0; e < 2; ++e) {
             for (int ty = 0; ty < gy; ++ty)
                 for (int tx = 0; tx < gx; ++tx) tv.push_back({1.0, make_int4(s, e, ty, tx)});
-            for (int k = 0; k < d.P.nb_fwd; ++k)
-                fwd.push_back({(double)std::max(d.nx, d.ny), make_int4(s, e, k, 0)});
             se.push_back({1.0, make_int4(s, e, 0, 0)});
             for (int k = 0; k < d.P.nbi + d.P.nbs; ++k) upd.push_back({1.0, make_int4(s, e, k, 0)});
-            for (int strip = 0; strip < nstrips; ++strip)
-                for (int g = 0; g < nvg; ++g)
-                    adj.push_back({(double)d.V / nvg, make_int4(s, e, strip, g)});
         }
+        // the projectors carry both energies per item
+        for (int k = 0; k < d.P.nb_fwd; ++k)
+            fwd.push_back({(double)std::max(d.nx, d.ny), make_int4(s, k, 0, 0)});
+        for (int strip = 0; strip < nstrips; ++strip)
+            for (int g = 0; g < nvg; ++g)
+                adj.push_back({(double)d.V / nvg, make_int4(s, strip, g, 0)});
     }
     auto upload = [&](std::vector<std::pair<double, int4>> &v, DevBuf &buf, int &count) {
         std::stable_sort(v.begin(), v.end(),
@@ -240,7 +255,7 @@ dect_status build_work(dect_batch *b)
         return std::max(1, std::min(items, per * cus));
     };
     b->g_tv = grid((const void *)kb_tv, b->n_tv);
-    b->g_fwd = grid((const void *)kb_fwd, b->n_fwd);
+    b->g_fwd = grid((const void *)kb_fwd, b->n_fwd, kFwdThreads);
     b->g_se = std::max(1, b->n_se);
     b->g_upd = grid((const void *)kb_update, b->n_upd);
     b->g_adj = grid((const void *)kb_adj, b->n_adj, kAdjThreads);
@@ -257,7 +272,7 @@ dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
     hipLaunchKernelGGL(kb_tv, dim3(b->g_tv), dim3(256), 0, s, S, (const int4 *)b->w_tv.ptr, b->n_tv,
                        par);
     DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_fwd, dim3(b->g_fwd), dim3(256), 0, s, S, (const int4 *)b->w_fwd.ptr,
+    hipLaunchKernelGGL(kb_fwd, dim3(b->g_fwd), dim3(kFwdThreads), 0, s, S, (const int4 *)b->w_fwd.ptr,
                        b->n_fwd);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(kb_scalar, dim3(b->g_se), dim3(256), 0, s, S, (const int4 *)b->w_se.ptr,

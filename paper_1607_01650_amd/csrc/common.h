@@ -70,6 +70,11 @@ constexpr int kPad = 2;       // zero border of the padded image copies
 #ifndef DECT_ADJ_BLOCKS
 #define DECT_ADJ_BLOCKS 1024
 #endif
+#ifndef DECT_FWD_WAVES
+#define DECT_FWD_WAVES 8
+#endif
+constexpr int kFwdWaves = DECT_FWD_WAVES;  // forward: wavefronts per (view, bundle) block
+constexpr int kFwdThreads = 64 * kFwdWaves;
 constexpr int kSL = 64;                    // strip length along the lane axis (one wavefront)
 constexpr int kSW = DECT_ADJ_STRIP_WIDTH;  // strip width along the tap axis
 constexpr int kAdjWaves = DECT_ADJ_WAVES;  // wavefronts per block (sharing one strip)
@@ -130,20 +135,25 @@ struct DevBuf {
 
 // ------------------------------------------------------------ projector ---
 struct ProjWork {
-    // padded copies [batch][ny+4][nx+4] and transposed [batch][nx+4][ny+4];
-    // adjoint partial images (per ray class and view group)
+    // interleaved padded copies of item pairs, [pair][ny+4][nx+4][2] and
+    // transposed [pair][nx+4][ny+4][2]; adjoint partial images (per item, ray
+    // class and view group)
     DevBuf pad, padT, partial;
 };
 
-// img [batch][ny][nx] -> both padded layouts (borders stay zero).
-dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float *padT, int batch,
+// Pairs of items (2p, 2p + 1) that the projectors process together.
+int pairs_of(int batch);
+// img [batch][ny][nx] -> both interleaved padded layouts of every pair
+// (borders zero; the second image of an odd batch's last pair is zero).
+dect_status launch_pad(const GeomTables &t, const float *img, float *pad2, float *padT2, int batch,
                        hipStream_t s);
-// sino[e] = scale * A img[e] from the padded layouts.  norm_partial (may be
-// NULL) receives per-block sums of squares (double) for a later reduction.
-// With sub0/sub1 (items 0 and 1), sino[e] = scale * A img[e] - ss_e * sub_e,
-// formed in FP64 and rounded once; with lo, lo[e] receives the rounding
-// remainder of every value (same layout as sino).
-dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
+// sino[e] = scale * A img[e] from the interleaved padded layouts.
+// norm_partial (may be NULL) receives per-block sums of squares (double),
+// [item][fwd_blocks], for a later reduction.  With sub0/sub1 (items 0 and
+// 1), sino[e] = scale * A img[e] - ss_e * sub_e, formed in FP64 and rounded
+// once; with lo, lo[e] receives the rounding remainder of every value (same
+// layout as sino).
+dect_status launch_fwd(const GeomTables &t, const float *pad2, const float *padT2, float *sino,
                        int batch, float scale, double *norm_partial, hipStream_t s,
                        const float *sub0 = nullptr, const float *sub1 = nullptr,
                        double ss0 = 0.0, double ss1 = 0.0, float *lo = nullptr);

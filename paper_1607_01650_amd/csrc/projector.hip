@@ -1,18 +1,25 @@
 // Joseph fan-beam projector pair for gfx950.
 //
-// Forward (A x): one lane per ray; a wavefront holds 64 adjacent bins of one
-// view and steps through the driving lines in lockstep, so the two taps of
-// all lanes land in one short run of a padded image line (the transposed
-// copy for x-major rays): coalesced reads, coalesced sinogram writes.  The
-// line coordinate is advanced in exact 32.32 fixed point.
+// Both directions work on pairs of images with one geometry (the two
+// energies of a slice, or consecutive batch items).  The padded images are
+// stored interleaved, both images' values of a pixel side by side, so one
+// load fetches the two taps of both images.
 //
-// Adjoint (A^T y): output-stationary gather.  A wavefront owns a 64x64 pixel
-// tile held in LDS; for x-major rays lane l owns tile column l and walks the
-// bins whose rays cross that column inside the tile, for y-major rays lane l
-// owns tile row l.  Every weight is recomputed from the same fixed-point line
-// coordinate as the forward pass (evaluated exactly in FP64), so the adjoint
-// is the exact transpose of the forward matrix.  No atomics: each pixel's sum
-// runs in a fixed order (views of a wave, waves of a block, view groups).
+// Forward (A x): one lane per ray; a block holds 64 adjacent bins of one
+// view and its four wavefronts step through quarters of the driving lines in
+// lockstep, so the taps of all lanes land in one short run of a padded image
+// line (the transposed copy for x-major rays): coalesced reads, coalesced
+// sinogram writes.  The line coordinate is advanced in exact 32.32 fixed
+// point.
+//
+// Adjoint (A^T y): output-stationary gather on strips.  x-major rays are
+// gathered on strips of kSW rows x 64 columns (lane = column), y-major rays
+// on strips of kSW columns x 64 rows (lane = row); each wavefront holds the
+// strip in LDS and walks, view by view, the bins whose rays put a tap in it.
+// Every weight is recomputed from the same fixed-point line coordinate as the
+// forward pass (evaluated exactly in FP64), so the adjoint is the exact
+// transpose of the forward matrix.  No atomics: each pixel's sum runs in a
+// fixed order (views of a wave, waves of a block, view groups).
 #include "proj_device.h"
 #include "xcd.h"
 
@@ -21,86 +28,117 @@ namespace dect {
 namespace {
 
 // ------------------------------------------------------------ padding ---
-// In: img [batch][ny][nx].  Out: pad [batch][ny+4][nx+4] and padT
-// [batch][nx+4][ny+4], written whole (zero border of kPad included), so a
+// In: img [batch][ny][nx].  Out, per pair p of items (2p, 2p + 1; the second
+// reads as zero when batch is odd): pad2 [p][ny+4][nx+4][2] and padT2
+// [p][nx+4][ny+4][2], written whole (zero border of kPad included), so a
 // reused buffer never carries another geometry's values.  The grid covers the
-// padded domain in 32x32 tiles; padT goes through an LDS transpose.
-__global__ __launch_bounds__(256) void k_pad(const float *__restrict__ img,
-                                             float *__restrict__ pad,
-                                             float *__restrict__ padT, int nx, int ny)
+// padded domain in 32x32 tiles; padT2 goes through an LDS transpose.
+__global__ __launch_bounds__(256) void k_pad(const float *__restrict__ img, int batch,
+                                             f2v *__restrict__ pad2, f2v *__restrict__ padT2,
+                                             int nx, int ny)
 {
-    __shared__ float tile[32][33];
-    const int e = blockIdx.z;
+    __shared__ f2v tile[32][33];
+    const int pr = blockIdx.z;
     const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;  // padded coordinates
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    const size_t in_off = (size_t)e * nx * ny;
+    const size_t N = (size_t)nx * ny;
+    const float *im0 = img + (size_t)(2 * pr) * N;
+    const float *im1 = 2 * pr + 1 < batch ? im0 + N : nullptr;
     const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
-    const size_t p_off = (size_t)e * pnx * pny;
+    const size_t p_off = (size_t)pr * pnx * pny;
     for (int j = ty; j < 32; j += 8) {
         int rp = r0 + j, cp = c0 + tx;
         int r = rp - kPad, c = cp - kPad;
-        float v = (r >= 0 && r < ny && c >= 0 && c < nx) ? img[in_off + (size_t)r * nx + c] : 0.f;
-        if (rp < pny && cp < pnx) pad[p_off + (size_t)rp * pnx + cp] = v;
+        f2v v = f2v(0.f);
+        if (r >= 0 && r < ny && c >= 0 && c < nx) {
+            const size_t i = (size_t)r * nx + c;
+            v.x = im0[i];
+            v.y = im1 ? im1[i] : 0.f;
+        }
+        if (rp < pny && cp < pnx) pad2[p_off + (size_t)rp * pnx + cp] = v;
         tile[j][tx] = v;
     }
     __syncthreads();
     for (int j = ty; j < 32; j += 8) {
         int cp = c0 + j, rp = r0 + tx;
-        if (rp < pny && cp < pnx) padT[p_off + (size_t)cp * pny + rp] = tile[tx][j];
+        if (rp < pny && cp < pnx) padT2[p_off + (size_t)cp * pny + rp] = tile[tx][j];
     }
 }
 
 // ------------------------------------------------------------ forward ---
+// grid ((view, bundle) blocks, pairs); items 2p, 2p + 1 of `batch`.
 template <bool NORM>
-__global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ pad,
-                                             const float *__restrict__ padT,
+__global__ __launch_bounds__(kFwdThreads) void k_fwd(const float *__restrict__ pad2,
+                                             const float *__restrict__ padT2,
                                              const RayFwd *__restrict__ rays,
                                              const float *__restrict__ len,
                                              const Bundle *__restrict__ bundles,
-                                             float *__restrict__ sino, int nx, int ny, int V,
-                                             int B, int nbundle, float scale,
+                                             float *__restrict__ sino, int batch, int nx, int ny,
+                                             int V, int B, int nbundle, float scale,
                                              double *__restrict__ partial,
                                              const float *__restrict__ sub0,
                                              const float *__restrict__ sub1, double ss0, double ss1,
                                              float *__restrict__ lo)
 {
     __shared__ FwdShared sh;
-    // (view, bundle) blocks in XCD order: each XCD works on one energy's
-    // image, which then fits its L2
+    // (view, bundle) blocks in XCD order: neighbouring views and bundles,
+    // which read the same image lines, share an XCD's L2
     const unsigned item = xcd_order(block_linear(), grid_blocks());
-    const int e = (int)(item / gridDim.x), vb = (int)(item % gridDim.x);
-    const size_t p_off = (size_t)e * (nx + 2 * kPad) * (ny + 2 * kPad);
-    const double result =
-        fwd_block(sh, pad + p_off, padT + p_off, rays, len, bundles, sino + (size_t)e * V * B, nx,
-                  ny, B, nbundle, vb, scale, e == 0 ? sub0 : e == 1 ? sub1 : nullptr,
-                  e == 0 ? ss0 : ss1, lo ? lo + (size_t)e * V * B : nullptr);
-    if (NORM) {
-        __shared__ double red[256];
-        double tot = block_sum_256(result * result, red);
-        if (threadIdx.x == 0) partial[(size_t)e * gridDim.x + vb] = tot;
+    const int pr = (int)(item / gridDim.x), vb = (int)(item % gridDim.x);
+    const size_t p_off = (size_t)pr * 2 * (nx + 2 * kPad) * (ny + 2 * kPad);
+    const size_t M = (size_t)V * B;
+    const int e0 = 2 * pr;
+    const bool two = e0 + 1 < batch;
+    FwdOut o;
+    o.sino[0] = sino + e0 * M;
+    o.sino[1] = two ? sino + (e0 + 1) * M : nullptr;
+    o.lo[0] = lo ? lo + e0 * M : nullptr;
+    o.lo[1] = lo && two ? lo + (e0 + 1) * M : nullptr;
+    o.sub[0] = e0 == 0 ? sub0 : nullptr;  // the subtrahends belong to items 0 and 1
+    o.sub[1] = e0 == 0 ? sub1 : nullptr;
+    o.sub_scale[0] = ss0;
+    o.sub_scale[1] = ss1;
+    double res[2];
+    fwd_block(sh, pad2 + p_off, padT2 + p_off, rays, len, bundles, o, nx, ny, B, nbundle, vb,
+              scale, res);
+    if (NORM && threadIdx.x < 64) {  // the values live in wavefront 0
+        const double t0 = lane_sum(res[0] * res[0]);
+        const double t1 = lane_sum(res[1] * res[1]);
+        if (threadIdx.x == 0) {
+            partial[(size_t)e0 * gridDim.x + vb] = t0;
+            if (two) partial[(size_t)(e0 + 1) * gridDim.x + vb] = t1;
+        }
     }
 }
 
 // ------------------------------------------------------------ adjoint ---
-// grid (strips of both classes, view groups, batch); part: [batch][2][nvg]
-// planes of nx*ny floats.
+// grid (strips of both classes, view groups, groups of NE items starting at
+// item0); part: [batch][2][nvg] planes of nx*ny floats.
+template <int NE>
 __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ sino,
-                                             const RayAdj *__restrict__ rays,
-                                             const float *__restrict__ len,
-                                             const BinRange *__restrict__ bins, int nx, int ny,
-                                             int V, int B, int nvg, float *__restrict__ part)
+                                                     const RayAdj *__restrict__ rays,
+                                                     const float *__restrict__ len,
+                                                     const BinRange *__restrict__ bins, int nx,
+                                                     int ny, int V, int B, int nvg, int item0,
+                                                     float *__restrict__ part)
 {
-    __shared__ AdjShared sh;
-    // (strip, view group, item) blocks in XCD order: the blocks of one XCD
+    __shared__ AdjShared<NE> sh;
+    // (strip, view group, items) blocks in XCD order: the blocks of one XCD
     // share a view group's rays and sinogram rows
     const unsigned item = xcd_order(block_linear(), grid_blocks());
     const int strip = (int)(item % gridDim.x), g = (int)(item / gridDim.x % gridDim.y);
-    const int e = (int)(item / (gridDim.x * gridDim.y));
+    const int e0 = item0 + NE * (int)(item / (gridDim.x * gridDim.y));
     const int nsx = adj_strips_x(nx, ny);
-    const size_t plane = (size_t)nx * ny;
+    const size_t plane = (size_t)nx * ny, M = (size_t)V * B;
     const int cls = strip < nsx ? 0 : 1;
-    adj_block(sh, sino + (size_t)e * V * B, rays, len, bins, nx, ny, V, B, strip, g, nvg,
-              part + ((size_t)e * 2 * nvg + (size_t)cls * nvg + g) * plane);
+    const float *s[NE];
+    float *p[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        s[i] = sino + (size_t)(e0 + i) * M;
+        p[i] = part + ((size_t)(e0 + i) * 2 * nvg + (size_t)cls * nvg + g) * plane;
+    }
+    adj_block<NE>(sh, s, rays, len, bins, nx, ny, V, B, strip, g, nvg, p);
 }
 
 __global__ __launch_bounds__(256) void k_adj_sum(const float *__restrict__ part, int nvg,
@@ -117,43 +155,47 @@ __global__ __launch_bounds__(256) void k_adj_sum(const float *__restrict__ part,
 }  // namespace
 
 // ---------------------------------------------------------- launchers ---
-dect_status launch_pad(const GeomTables &t, const float *img, float *pad, float *padT, int batch,
+int pairs_of(int batch) { return (batch + 1) / 2; }
+
+dect_status launch_pad(const GeomTables &t, const float *img, float *pad2, float *padT2, int batch,
                        hipStream_t s)
 {
     const int nx = t.key.nx, ny = t.key.ny;
-    dim3 grid((nx + 2 * kPad + 31) / 32, (ny + 2 * kPad + 31) / 32, batch);
-    hipLaunchKernelGGL(k_pad, grid, dim3(256), 0, s, img, pad, padT, nx, ny);
+    dim3 grid((nx + 2 * kPad + 31) / 32, (ny + 2 * kPad + 31) / 32, pairs_of(batch));
+    hipLaunchKernelGGL(k_pad, grid, dim3(256), 0, s, img, batch, (f2v *)pad2, (f2v *)padT2, nx,
+                       ny);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
 
 int fwd_blocks(const GeomTables &t) { return t.key.V * t.nbundle; }
 
-dect_status launch_fwd(const GeomTables &t, const float *pad, const float *padT, float *sino,
+dect_status launch_fwd(const GeomTables &t, const float *pad2, const float *padT2, float *sino,
                        int batch, float scale, double *norm_partial, hipStream_t s,
                        const float *sub0, const float *sub1, double ss0, double ss1,
                        float *lo)
 {
     const GeomKey &k = t.key;
-    dim3 grid(fwd_blocks(t), batch);
+    dim3 grid(fwd_blocks(t), pairs_of(batch));
     if (norm_partial)
-        hipLaunchKernelGGL(k_fwd<true>, grid, dim3(256), 0, s, pad, padT, t.fwd, t.len,
-                           t.bundles, sino, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
+        hipLaunchKernelGGL(k_fwd<true>, grid, dim3(kFwdThreads), 0, s, pad2, padT2, t.fwd, t.len,
+                           t.bundles, sino, batch, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
                            norm_partial, sub0, sub1, ss0, ss1, lo);
     else
-        hipLaunchKernelGGL(k_fwd<false>, grid, dim3(256), 0, s, pad, padT, t.fwd, t.len,
-                           t.bundles, sino, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
+        hipLaunchKernelGGL(k_fwd<false>, grid, dim3(kFwdThreads), 0, s, pad2, padT2, t.fwd, t.len,
+                           t.bundles, sino, batch, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
                            (double *)nullptr, sub0, sub1, ss0, ss1, lo);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
 
 // View groups per strip: enough blocks to fill the chip (kAdjBlocks), but
-// at least 8 views per group.
+// at least 8 views per group.  A block carries a pair of items.
 int adj_groups(const GeomTables &t, int batch)
 {
     const int strips = adj_strips(t.key.nx, t.key.ny);
-    int want = (kAdjBlocks + strips * batch - 1) / (strips * batch);
+    const int units = strips * pairs_of(batch);
+    int want = (kAdjBlocks + units - 1) / units;
     int cap = std::max(1, t.key.V / 8);
     return std::max(1, std::min(want, cap));
 }
@@ -170,9 +212,13 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
     const GeomKey &k = t.key;
     if (nvg <= 0) nvg = adj_groups(t, batch);
     const size_t plane = (size_t)k.nx * k.ny;
-    hipLaunchKernelGGL(k_adj, dim3(adj_strips(k.nx, k.ny), nvg, batch), dim3(kAdjThreads), 0, s,
-                       sino,
-                       t.adj, t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, partial);
+    const unsigned strips = (unsigned)adj_strips(k.nx, k.ny);
+    if (batch >= 2)
+        hipLaunchKernelGGL(k_adj<2>, dim3(strips, nvg, batch / 2), dim3(kAdjThreads), 0, s, sino,
+                           t.adj, t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, 0, partial);
+    if (batch % 2)  // the last item of an odd batch on its own
+        hipLaunchKernelGGL(k_adj<1>, dim3(strips, nvg, 1), dim3(kAdjThreads), 0, s, sino, t.adj,
+                           t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, batch - 1, partial);
     DECT_HIP(hipGetLastError());
     if (!img) return DECT_OK;  // the caller consumes the partial planes itself
     hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((plane + 255) / 256), batch), dim3(256), 0, s,
@@ -207,7 +253,8 @@ dect_status project(const dect_geometry *g, const float *img, float *sino, int b
     if (st != DECT_OK) return st;
     std::lock_guard<std::mutex> lk(g_ws_mu);
     ProjWork *w = workspace(s);
-    const size_t padn = (size_t)(g->nx + 2 * kPad) * (g->ny + 2 * kPad) * batch * sizeof(float);
+    const size_t padn =
+        (size_t)(g->nx + 2 * kPad) * (g->ny + 2 * kPad) * 2 * pairs_of(batch) * sizeof(float);
     // the padded copies are reused across calls and geometries; k_pad writes
     // them whole, border included
     if (w->pad.bytes < padn) {
