@@ -24,6 +24,7 @@ import argparse
 import ctypes as ct
 import dataclasses
 import json
+import re
 import os
 import sys
 import time
@@ -449,8 +450,9 @@ def traffic_summary(pmc_dir: str):
         proj_rows = load(f"proj_{tag}")
         is_copy = lambda n: "copy" in n.lower() or "elementwise" in n.lower()
         ck, nc = per_dispatch(copy_rows, is_copy, counter)
-        adj, na = per_dispatch(proj_rows, lambda n: "k_adj(" in n or "k_adjE" in n or
-                               n.split("(")[0].endswith("k_adj"), counter)
+        # k_adj (any template instance), not k_adj_sum; demangled or mangled
+        is_adj = lambda n: re.search(r"k_adj(<\d+>)?\(|\d+k_adj[IE]", n) is not None
+        adj, na = per_dispatch(proj_rows, is_adj, counter)
         asum, ns = per_dispatch(proj_rows, lambda n: "k_adj_sum" in n, counter)
         meta = json.load(open(os.path.join(pmc_dir, "copy_meta.json")))
         true_bytes = meta["bytes_read"] if counter == "FETCH_SIZE" else meta["bytes_written"]

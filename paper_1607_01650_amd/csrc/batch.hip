@@ -164,7 +164,8 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
             float *p[2];
             for (int e = 0; e < 2; ++e)
                 p[e] = d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
-            adj_block<2>(sh, s, d.adj, d.len, d.bins, d.nx, d.ny, d.V, d.B, strip, g, d.nvg, p);
+            adj_block<2>(sh, s, d.adj, d.fwd, d.len, d.bins, d.nx, d.ny, d.V, d.B, strip, g,
+                         d.nvg, p);
         }
         __syncthreads();
     }

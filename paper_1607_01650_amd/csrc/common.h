@@ -75,6 +75,10 @@ constexpr int kPad = 2;       // zero border of the padded image copies
 #endif
 constexpr int kFwdWaves = DECT_FWD_WAVES;  // forward: wavefronts per (view, bundle) block
 constexpr int kFwdThreads = 64 * kFwdWaves;
+#ifndef DECT_FWD_GROUP
+#define DECT_FWD_GROUP 4
+#endif
+constexpr int kFwdGroup = DECT_FWD_GROUP;  // forward: samples per FP32 partial sum
 constexpr int kSL = 64;                    // strip length along the lane axis (one wavefront)
 constexpr int kSW = DECT_ADJ_STRIP_WIDTH;  // strip width along the tap axis
 constexpr int kAdjWaves = DECT_ADJ_WAVES;  // wavefronts per block (sharing one strip)

@@ -34,6 +34,14 @@ struct AdjShared {
     typename AdjElem<NE>::T acc[kAdjWaves][kAccSize];
 };
 
+// The back-projector evaluates the line coordinate of a bin at a lane either
+// in FP64 (DECT_ADJ_INT 0: the exact doubles a + k * lane) or in 32.32
+// fixed point (1: one 32 x 32 -> 64-bit multiply-add); both give the same
+// tap line and the same FP32 weight as the forward pass.
+#ifndef DECT_ADJ_INT
+#define DECT_ADJ_INT 1
+#endif
+
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
 // ------------------------------------------------------------ forward ---
@@ -43,7 +51,7 @@ constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 // l0 (a sentinel far below -2 for lanes of the other class), dq its step.
 // The taps h, h + 1 (h clamped to [-2, nq], so outside the grid both read
 // zero padding) of both images are one 16-byte load at a 32-bit per-lane
-// byte offset.  Groups of four samples are summed in FP32 and the group sums
+// byte offset.  Groups of kFwdGroup samples are summed in FP32 and the group sums
 // added in FP64; per image i, acc[2i] sums the first taps and acc[2i + 1] the
 // weight times the tap difference, the weight being the FP32 value (float)lo,
 // scaled by 2^-32 at the end.
@@ -69,12 +77,10 @@ __device__ __forceinline__ void walk(const char *line, unsigned bstep, int l0, i
         line += bstep;
     };
     int i = l0;
-    for (; i + 3 <= l1; i += 4) {
+    for (; i + kFwdGroup - 1 <= l1; i += kFwdGroup) {
         float s[4] = {0.f, 0.f, 0.f, 0.f};
-        sample(s);
-        sample(s);
-        sample(s);
-        sample(s);
+#pragma unroll
+        for (int u = 0; u < kFwdGroup; ++u) sample(s);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += (double)s[c];
     }
@@ -205,6 +211,7 @@ __device__ __forceinline__ double lane_sum(double v)
 template <int NE>
 __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const (&sino)[NE],
                                           const RayAdj *__restrict__ rays,
+                                          const RayFwd *__restrict__ rays_fx,
                                           const float *__restrict__ len,
                                           const BinRange *__restrict__ bins, int nx, int ny,
                                           int V, int B, int strip, int g, int nvg,
@@ -224,7 +231,9 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
     // acc line j holds tap line t0 + j - 2: lines 0, 1 and kSW + 2, kSW + 3
     // are spare
     E *col = my + lane;
+#if !DECT_ADJ_INT
     const double ld = (double)lane;  // this lane's driving line, relative to l0
+#endif
     const BinRange *sb = bins + (size_t)strip * V;
 
     const int v_begin = (int)((int64_t)V * g / nvg), v_end = (int)((int64_t)V * (g + 1) / nvg);
@@ -233,56 +242,92 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
         const int lo = __builtin_amdgcn_readfirstlane(br.lo);
         const int hi = __builtin_amdgcn_readfirstlane(br.hi);
         const RayAdj *rv = rays + (size_t)v * B;
+        const RayFwd *rfv = rays_fx + (size_t)v * B;
         const float *lv = len + (size_t)v * B;
         for (int cb = lo; cb <= hi; cb += 64) {
             // lane j: bin cb + j, its line coordinate moved to the strip
             // origin, q' = (a + k l0 - t0) + k lane (exact: all terms are
             // multiples of 2^-32 below 2^21)
             const int bj = cb + lane;
-            double aj = 0.0, kj = 0.0;
             float lyj[NE];
 #pragma unroll
             for (int i = 0; i < NE; ++i) lyj[i] = 0.f;
+#if DECT_ADJ_INT
+            int64_t aj = 0, kj = 0;
+#else
+            double ajd = 0.0, kjd = 0.0;
+#endif
             if (bj <= hi) {
+#if DECT_ADJ_INT
+                const RayFwd t = rfv[bj];
+                aj = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
+                kj = t.k_fx;
+#else
                 const RayAdj t = rv[bj];
-                aj = fma(t.k, (double)l0, t.a) - (double)t0;
-                kj = t.k;
+                ajd = fma(t.k, (double)l0, t.a) - (double)t0;
+                kjd = t.k;
+#endif
                 const float L = fabsf(lv[bj]);
 #pragma unroll
                 for (int i = 0; i < NE; ++i) lyj[i] = L * sino[i][(size_t)v * B + bj];
             }
-            const int64_t ai = __double_as_longlong(aj), ki = __double_as_longlong(kj);
-            const int alo = (int)ai, ahi = (int)(ai >> 32), klo = (int)ki, khi = (int)(ki >> 32);
+#if !DECT_ADJ_INT
+            const int64_t aj = __double_as_longlong(ajd), kj = __double_as_longlong(kjd);
+#endif
+            const int alo = (int)aj, ahi = (int)(aj >> 32), klo = (int)kj, khi = (int)(kj >> 32);
             int ly_bits[NE];
 #pragma unroll
             for (int i = 0; i < NE; ++i) ly_bits[i] = __float_as_int(lyj[i]);
             const int nj = min(64, hi - cb + 1);
-            // one bin: this lane's tap pair of every image, added in bin order
-            auto tap = [&](int j) {
-                const double a = __longlong_as_double(
-                    ((int64_t)__builtin_amdgcn_readlane(ahi, j) << 32) |
-                    (uint32_t)__builtin_amdgcn_readlane(alo, j));
-                const double k = __longlong_as_double(
-                    ((int64_t)__builtin_amdgcn_readlane(khi, j) << 32) |
-                    (uint32_t)__builtin_amdgcn_readlane(klo, j));
+            // bin j's first tap line (strip-relative, clamped) and weight at
+            // this lane
+            auto pos = [&](int j, int &i0, float &w) {
+                const uint32_t a_lo = (uint32_t)__builtin_amdgcn_readlane(alo, j);
+                const uint32_t a_hi = (uint32_t)__builtin_amdgcn_readlane(ahi, j);
+                const uint32_t k_lo = (uint32_t)__builtin_amdgcn_readlane(klo, j);
+                const uint32_t k_hi = (uint32_t)__builtin_amdgcn_readlane(khi, j);
+#if DECT_ADJ_INT
+                // q = a + (k_hi 2^32 + k_lo) lane; k_hi is -1, 0 or 1
+                const uint64_t p = (uint64_t)k_lo * (uint32_t)lane + (((uint64_t)a_hi << 32) | a_lo);
+                const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)k_hi, lane);
+                i0 = min(max(qh, -2), kSW);
+                w = (float)(uint32_t)p * kTwoM32;
+#else
+                const double a = __longlong_as_double((int64_t)(((uint64_t)a_hi << 32) | a_lo));
+                const double k = __longlong_as_double((int64_t)(((uint64_t)k_hi << 32) | k_lo));
                 const double q = fma(k, ld, a);
                 const double fl = floor(q);
-                const int i0 = min(max((int)fl, -2), kSW);  // first tap line, strip-relative
-                const float w = (float)(q - fl);
-                E *pp = col + (i0 + 2) * kSL;
-                E u0 = pp[0], u1 = pp[kSL];
+                i0 = min(max((int)fl, -2), kSW);
+                w = (float)(q - fl);
+#endif
+            };
+            auto bin_y = [&](int j, int i) {
+                return __int_as_float(__builtin_amdgcn_readlane(ly_bits[i], j));
+            };
+            // bin j's contributions added to the values of its two tap lines
+            auto add = [&](E &u0, E &u1, float w, int j) {
                 if constexpr (NE == 1) {
-                    const float ly = __int_as_float(__builtin_amdgcn_readlane(ly_bits[0], j));
+                    const float ly = bin_y(j, 0);
                     u0 += fmaf(-w, ly, ly);
                     u1 = fmaf(w, ly, u1);
                 } else {
-                    const float y0 = __int_as_float(__builtin_amdgcn_readlane(ly_bits[0], j));
-                    const float y1 = __int_as_float(__builtin_amdgcn_readlane(ly_bits[1], j));
+                    const float y0 = bin_y(j, 0);
+                    const float y1 = bin_y(j, 1);
                     u0.x += fmaf(-w, y0, y0);
                     u0.y += fmaf(-w, y1, y1);
                     u1.x = fmaf(w, y0, u1.x);
                     u1.y = fmaf(w, y1, u1.y);
                 }
+            };
+            // one bin after the other, in bin order: this lane's tap pair of
+            // every image, one paired LDS read and write
+            auto tap = [&](int j) {
+                int i0;
+                float w;
+                pos(j, i0, w);
+                E *pp = col + (i0 + 2) * kSL;
+                E u0 = pp[0], u1 = pp[kSL];
+                add(u0, u1, w, j);
                 pp[0] = u0;
                 pp[kSL] = u1;
             };
