@@ -100,6 +100,53 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     __shared__ double outv[5];
     const float inv_rho = 1.0f / rho;
 
+    // h = hmu * (sum of the partial planes, in plane order) on the G region
+    // (rows/cols -1..15; a thread holds at most two of its 289 pixels).  It
+    // depends on nothing else here, so its loads go out first, eight planes
+    // at a time, and overlap the tile loads below.
+    float hsum[2] = {0.f, 0.f};
+    {
+        const size_t N = (size_t)nx * ny;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            const int rr = i / 17, cc = i % 17;
+            const int r = r0 - 1 + rr, c = c0 - 1 + cc;
+            if (i < 17 * 17 && r >= 0 && r < ny && c >= 0 && c < nx) {
+                const float *hp = m.h + (size_t)r * nx + c;
+                float acc = 0.f;
+                for (int q0 = 0; q0 < m.hq; q0 += 8) {
+                    float t[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) t[u] = q0 + u < m.hq ? hp[(size_t)(q0 + u) * N] : 0.f;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (q0 + u < m.hq) acc += t[u];
+                }
+                hsum[k] = acc * m.hmu;
+            }
+        }
+    }
+
+    // lambda (and z for the deferred multiplier step) on the w region (rows/
+    // cols -1..16; at most two of its 324 pixels per thread), loaded ahead too
+    float lxv[2] = {0.f, 0.f}, lyv[2] = {0.f, 0.f}, zxv[2] = {0.f, 0.f}, zyv[2] = {0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        const int rr = i / 18, cc = i % 18;
+        const int r = r0 - 1 + rr, c = c0 - 1 + cc;
+        if (i < 18 * 18 && r >= 0 && r < ny && c >= 0 && c < nx) {
+            const size_t o = (size_t)r * nx + c;
+            lxv[k] = m.lxi[o];
+            lyv[k] = m.lyi[o];
+            if (pending) {
+                zxv[k] = m.zxi[o];
+                zyv[k] = m.zyi[o];
+            }
+        }
+    }
+
     for (int i = threadIdx.x; i < 19 * 19; i += 256) {
         int rr = i / 19, cc = i % 19;
         int r = r0 - 2 + rr, c = c0 - 2 + cc;
@@ -110,7 +157,10 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     __syncthreads();
 
     double tv = 0.0, pres = 0.0, ff = 0.0;
-    for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i >= 18 * 18) break;
         int rr = i / 18, cc = i % 18;
         int r = r0 - 1 + rr, c = c0 - 1 + cc;
         float wx = 0.f, wy = 0.f;
@@ -119,10 +169,10 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             float fc = sf[rr + 1][cc + 1], lc = sl[rr + 1][cc + 1];
             float dx = c >= 1 ? (fc - sf[rr + 1][cc]) + (lc - sl[rr + 1][cc]) : 0.f;
             float dy = r >= 1 ? (fc - sf[rr][cc + 1]) + (lc - sl[rr][cc + 1]) : 0.f;
-            float lx = m.lxi[o], ly = m.lyi[o];
+            float lx = lxv[k], ly = lyv[k];
             if (pending) {
-                lx -= xi * (dx - m.zxi[o]);
-                ly -= xi * (dy - m.zyi[o]);
+                lx -= xi * (dx - zxv[k]);
+                ly -= xi * (dy - zyv[k]);
             }
             float vx = dx - lx / rho, vy = dy - ly / rho;
             float n = sqrtf(vx * vx + vy * vy);
@@ -147,15 +197,15 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     __syncthreads();
 
     // G = h + grad^T w on rows/cols -1..15
-    for (int i = threadIdx.x; i < 17 * 17; i += 256) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i >= 17 * 17) break;
         int rr = i / 17, cc = i % 17;
         int r = r0 - 1 + rr, c = c0 - 1 + cc;
         float gv = 0.f;
         if (r >= 0 && r < ny && c >= 0 && c < nx) {
-            const size_t o = (size_t)r * nx + c, N = (size_t)nx * ny;
-            float s = 0.f;
-            for (int q = 0; q < m.hq; ++q) s += m.h[(size_t)q * N + o];
-            s *= m.hmu;
+            float s = hsum[k];
             if (c >= 1) s += swx[rr][cc];
             if (c + 1 <= nx - 1) s -= swx[rr][cc + 1];
             if (r >= 1) s += swy[rr][cc];
