@@ -23,6 +23,7 @@ struct SliceDev {
     const float *len;
     const Bundle *bundles;
     const BinRange *bins;
+    const LaneRange *lanes;
     float rho, xi, muf;
     double mu, rhod, tol;
     AdmPtrs P;
@@ -153,6 +154,7 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
                                               const int4 *__restrict__ items, int n)
 {
     __shared__ AdjShared<2> sh;
+    __shared__ AdjStage stage[kAdjWaves * 64];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
@@ -164,8 +166,8 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
             float *p[2];
             for (int e = 0; e < 2; ++e)
                 p[e] = d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
-            adj_block<2>(sh, s, d.adj, d.fwd, d.len, d.bins, d.nx, d.ny, d.V, d.B, strip, g,
-                         d.nvg, p);
+            adj_block<2>(sh, s, d.adj, d.fwd, d.len, d.bins, d.lanes, d.nx, d.ny, d.V, d.B, strip,
+                         g, d.nvg, p, stage);
         }
         __syncthreads();
     }
@@ -424,6 +426,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         d.len = t.len;
         d.bundles = t.bundles;
         d.bins = t.adj_bins;
+        d.lanes = t.adj_lanes;
         d.rho = (float)prm[i].rho;
         d.xi = (float)prm[i].xi;
         d.muf = (float)prm[i].mu;

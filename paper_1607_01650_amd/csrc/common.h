@@ -98,6 +98,12 @@ __host__ __device__ inline int adj_strips(int nx, int ny)
 struct BinRange {
     int32_t lo, hi;
 };
+// Bins [lo + first, lo + last] of one view that put a tap inside one strip at
+// one lane (its driving line); empty: first > last.  Exact, from the
+// fixed-point ray table, relative to the strip's BinRange lo.
+struct LaneRange {
+    uint16_t first, last;
+};
 
 struct GeomKey {
     int32_t nx, ny, V, B;
@@ -117,6 +123,7 @@ struct GeomTables {
     Bundle *bundles = nullptr; // [V*nbundle]
     ViewInfo *views = nullptr; // [V]
     BinRange *adj_bins = nullptr;  // [adj_strips][V]
+    LaneRange *adj_lanes = nullptr;  // [adj_strips][V][kSL]
     int64_t samples = 0;       // Joseph samples with q in (-1, n)
     ~GeomTables();
 };

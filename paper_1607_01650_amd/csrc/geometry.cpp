@@ -59,6 +59,7 @@ GeomTables::~GeomTables()
     if (bundles) (void)hipFree(bundles);
     if (views) (void)hipFree(views);
     if (adj_bins) (void)hipFree(adj_bins);
+    if (adj_lanes) (void)hipFree(adj_lanes);
 }
 
 dect_status validate_geometry(const dect_geometry *g)
@@ -295,6 +296,60 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
         }
     }
 
+    // Per-lane bin ranges inside each strip range.  At a fixed driving line
+    // the rays of one view are ordered (they meet only at the source, outside
+    // the image), so the line coordinate q is monotone in the bin index and
+    // the bins with t0 - 1 < q < t0 + kSW form one interval: two binary
+    // searches per lane.  A bin outside it adds nothing to the strip's lines
+    // at that lane (q exactly t0 - 1 gives the line t0 weight zero).
+    if ((double)nst * V * kSL * sizeof(LaneRange) > (double)(size_t(1) << 30))
+        return fail(DECT_ERR_GEOMETRY, "geometry too large for the back-projector's lane table");
+    std::vector<LaneRange> lanes((size_t)nst * V * kSL, LaneRange{1, 0});
+    for (int sI = 0; sI < nst; ++sI) {
+        const int cls = sI < nsx ? 0 : 1, sidx = cls ? sI - nsx : sI;
+        const int nL = cls ? ny : nx;
+        const int nsL = (nL + kSL - 1) / kSL;
+        const int t0 = (sidx / nsL) * kSW, l0 = (sidx % nsL) * kSL;
+        const int64_t qlo = (int64_t)(t0 - 1) * one, qhi = (int64_t)(t0 + kSW) * one;
+        for (int v = 0; v < V; ++v) {
+            const BinRange r = bins[(size_t)sI * V + v];
+            if (r.lo > r.hi) continue;
+            if (r.hi - r.lo >= 0xffff)
+                return fail(DECT_ERR_GEOMETRY, "too many bins per strip for the lane table");
+            LaneRange *out = &lanes[((size_t)sI * V + v) * kSL];
+            for (int l = 0; l < kSL && l0 + l < nL; ++l) {
+                const int64_t c = l0 + l;
+                auto q = [&](int b) {
+                    const RayFwd &f = fwd[(size_t)v * B + b];
+                    return f.a_fx + f.k_fx * c;
+                };
+                const bool up = q(r.hi) >= q(r.lo);
+                // first bin past the lower edge and last bin before the upper
+                // one, in the direction q grows
+                auto below_hi = [&](int b) { return q(b) < qhi; };
+                auto above_lo = [&](int b) { return q(b) > qlo; };
+                int first, last;
+                if (up) {
+                    int a = r.lo, z = r.hi + 1;  // first b with q(b) > qlo
+                    while (a < z) { const int m = (a + z) / 2; if (above_lo(m)) z = m; else a = m + 1; }
+                    first = a;
+                    a = r.lo - 1; z = r.hi;  // last b with q(b) < qhi
+                    while (a < z) { const int m = (a + z + 1) / 2; if (below_hi(m)) a = m; else z = m - 1; }
+                    last = a;
+                } else {
+                    int a = r.lo, z = r.hi + 1;  // first b with q(b) < qhi
+                    while (a < z) { const int m = (a + z) / 2; if (below_hi(m)) z = m; else a = m + 1; }
+                    first = a;
+                    a = r.lo - 1; z = r.hi;  // last b with q(b) > qlo
+                    while (a < z) { const int m = (a + z + 1) / 2; if (above_lo(m)) a = m; else z = m - 1; }
+                    last = a;
+                }
+                if (first <= last)
+                    out[l] = LaneRange{(uint16_t)(first - r.lo), (uint16_t)(last - r.lo)};
+            }
+        }
+    }
+
     auto t = std::make_unique<GeomTables>();
     t->key = key;
     t->nbundle = nb;
@@ -305,6 +360,7 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     DECT_HIP(hipMalloc(&t->bundles, bun.size() * sizeof(Bundle)));
     DECT_HIP(hipMalloc(&t->views, views.size() * sizeof(ViewInfo)));
     DECT_HIP(hipMalloc(&t->adj_bins, bins.size() * sizeof(BinRange)));
+    DECT_HIP(hipMalloc(&t->adj_lanes, lanes.size() * sizeof(LaneRange)));
     DECT_HIP(hipMemcpy(t->fwd, fwd.data(), fwd.size() * sizeof(RayFwd), hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->adj, adj.data(), adj.size() * sizeof(RayAdj), hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->len, len.data(), len.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -313,6 +369,8 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     DECT_HIP(hipMemcpy(t->views, views.data(), views.size() * sizeof(ViewInfo),
                        hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->adj_bins, bins.data(), bins.size() * sizeof(BinRange),
+                       hipMemcpyHostToDevice));
+    DECT_HIP(hipMemcpy(t->adj_lanes, lanes.data(), lanes.size() * sizeof(LaneRange),
                        hipMemcpyHostToDevice));
     *out = t.get();
     g_cache.push_back(std::move(t));

@@ -34,6 +34,20 @@ struct AdjShared {
     typename AdjElem<NE>::T acc[kAdjWaves][kAccSize];
 };
 
+// Back-projector bin walk.  DECT_ADJ_LANES 1: every lane walks only the bins
+// that hit its own driving line inside the strip (exact per-lane ranges from
+// the host), reading their ray data from a per-wavefront LDS stage; 0: all
+// lanes take every bin of the strip's range together (ray data broadcast
+// with v_readlane).  Each accumulator element receives the same contributions
+// in the same order either way, so both give bitwise the same result.
+#ifndef DECT_ADJ_LANES
+#define DECT_ADJ_LANES 1
+#endif
+struct AdjStage {
+    int64_t a, k;  // strip-relative 32.32 line coordinate at lane 0, slope
+    float ly[2];   // |path length| x sinogram value of each image
+};
+
 // The back-projector evaluates the line coordinate of a bin at a lane either
 // in FP64 (DECT_ADJ_INT 0: the exact doubles a + k * lane) or in 32.32
 // fixed point (1: one 32 x 32 -> 64-bit multiply-add); both give the same
@@ -213,9 +227,11 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                                           const RayAdj *__restrict__ rays,
                                           const RayFwd *__restrict__ rays_fx,
                                           const float *__restrict__ len,
-                                          const BinRange *__restrict__ bins, int nx, int ny,
+                                          const BinRange *__restrict__ bins,
+                                          const LaneRange *__restrict__ lanes, int nx, int ny,
                                           int V, int B, int strip, int g, int nvg,
-                                          float *const (&part)[NE])
+                                          float *const (&part)[NE],
+                                          AdjStage (&stage)[kAdjWaves * 64])
 {
     typedef typename AdjElem<NE>::T E;
     const int lane = threadIdx.x & 63;
@@ -244,6 +260,73 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
         const RayAdj *rv = rays + (size_t)v * B;
         const RayFwd *rfv = rays_fx + (size_t)v * B;
         const float *lv = len + (size_t)v * B;
+#if DECT_ADJ_LANES && DECT_ADJ_INT
+        (void)rv;
+        if (lo > hi) continue;
+        const LaneRange lr = lanes[((size_t)strip * V + v) * kSL + lane];
+        const int sbase = wid * 64;
+        for (int cb = lo; cb <= hi; cb += 64) {
+            // stage: lane j holds bin cb + j (strip-relative line coordinate)
+            const int bj = cb + lane;
+            AdjStage me;
+            me.a = 0;
+            me.k = 0;
+            me.ly[0] = me.ly[1] = 0.f;
+            if (bj <= hi) {
+                const RayFwd t = rfv[bj];
+                me.a = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
+                me.k = t.k_fx;
+                const float L = fabsf(lv[bj]);
+#pragma unroll
+                for (int i = 0; i < NE; ++i) me.ly[i] = L * sino[i][(size_t)v * B + bj];
+            }
+            stage[sbase + lane] = me;
+            // this lane's bins in the chunk: [f, e], chunk-relative
+            const int rel = cb - lo;
+            const int f = max((int)lr.first, rel) - rel;
+            const int e = min((int)lr.last, rel + 63) - rel;
+            const int n = e - f + 1;
+            int m = n;
+            for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+            const int steps = __builtin_amdgcn_readfirstlane(m);
+            // one step: bin b (staged) at this lane; a lane past its last bin
+            // sends its taps to a spare line
+            auto step = [&](const AdjStage &b, bool ok) {
+                const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
+                const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
+                const int i0 = ok ? min(max(qh, -2), kSW) : -2;
+                const float w = (float)(uint32_t)p * kTwoM32;
+                E *pp = col + (i0 + 2) * kSL;
+                E u0 = pp[0], u1 = pp[kSL];
+                if constexpr (NE == 1) {
+                    u0 += fmaf(-w, b.ly[0], b.ly[0]);
+                    u1 = fmaf(w, b.ly[0], u1);
+                } else {
+                    u0.x += fmaf(-w, b.ly[0], b.ly[0]);
+                    u0.y += fmaf(-w, b.ly[1], b.ly[1]);
+                    u1.x = fmaf(w, b.ly[0], u1.x);
+                    u1.y = fmaf(w, b.ly[1], u1.y);
+                }
+                pp[0] = u0;
+                pp[kSL] = u1;
+            };
+            // two steps at a time, both bins' stage reads issued first
+            int t = 0;
+            for (; t + 1 < steps; t += 2) {
+                const bool ok0 = t < n, ok1 = t + 1 < n;
+                const AdjStage b0 = stage[sbase + (ok0 ? f + t : 0)];
+                const AdjStage b1 = stage[sbase + (ok1 ? f + t + 1 : 0)];
+                step(b0, ok0);
+                step(b1, ok1);
+            }
+            if (t < steps) {
+                const bool ok = t < n;
+                step(stage[sbase + (ok ? f + t : 0)], ok);
+            }
+        }
+#else
+        (void)lanes;
+        (void)stage;
         for (int cb = lo; cb <= hi; cb += 64) {
             // lane j: bin cb + j, its line coordinate moved to the strip
             // origin, q' = (a + k l0 - t0) + k lane (exact: all terms are
@@ -338,6 +421,7 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             }
             if (j < nj) tap(j);
         }
+#endif
     }
     __syncthreads();
     // the copies summed in wave order; stored in normal image layout

@@ -119,11 +119,13 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
                                                      const RayAdj *__restrict__ rays,
                                                      const RayFwd *__restrict__ rays_fx,
                                                      const float *__restrict__ len,
-                                                     const BinRange *__restrict__ bins, int nx,
+                                                     const BinRange *__restrict__ bins,
+                                                     const LaneRange *__restrict__ lanes, int nx,
                                                      int ny, int V, int B, int nvg, int item0,
                                                      float *__restrict__ part)
 {
     __shared__ AdjShared<NE> sh;
+    __shared__ AdjStage stage[kAdjWaves * 64];
     // (strip, view group, items) blocks in XCD order: the blocks of one XCD
     // share a view group's rays and sinogram rows
     const unsigned item = xcd_order(block_linear(), grid_blocks());
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
         s[i] = sino + (size_t)(e0 + i) * M;
         p[i] = part + ((size_t)(e0 + i) * 2 * nvg + (size_t)cls * nvg + g) * plane;
     }
-    adj_block<NE>(sh, s, rays, rays_fx, len, bins, nx, ny, V, B, strip, g, nvg, p);
+    adj_block<NE>(sh, s, rays, rays_fx, len, bins, lanes, nx, ny, V, B, strip, g, nvg, p, stage);
 }
 
 __global__ __launch_bounds__(256) void k_adj_sum(const float *__restrict__ part, int nvg,
@@ -216,10 +218,12 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
     const unsigned strips = (unsigned)adj_strips(k.nx, k.ny);
     if (batch >= 2)
         hipLaunchKernelGGL(k_adj<2>, dim3(strips, nvg, batch / 2), dim3(kAdjThreads), 0, s, sino,
-                           t.adj, t.fwd, t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, 0, partial);
+                           t.adj, t.fwd, t.len, t.adj_bins, t.adj_lanes, k.nx, k.ny, k.V, k.B, nvg, 0,
+                           partial);
     if (batch % 2)  // the last item of an odd batch on its own
         hipLaunchKernelGGL(k_adj<1>, dim3(strips, nvg, 1), dim3(kAdjThreads), 0, s, sino, t.adj,
-                           t.fwd, t.len, t.adj_bins, k.nx, k.ny, k.V, k.B, nvg, batch - 1, partial);
+                           t.fwd, t.len, t.adj_bins, t.adj_lanes, k.nx, k.ny, k.V, k.B, nvg, batch - 1,
+                           partial);
     DECT_HIP(hipGetLastError());
     if (!img) return DECT_OK;  // the caller consumes the partial planes itself
     hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((plane + 255) / 256), batch), dim3(256), 0, s,
