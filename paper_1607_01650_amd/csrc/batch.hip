@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
                                               const int4 *__restrict__ items, int n)
 {
     __shared__ AdjShared<2> sh;
-    __shared__ AdjStage stage[kAdjWaves * 64];
+    __shared__ AdjStage stage;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];

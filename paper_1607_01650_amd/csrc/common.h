@@ -62,13 +62,13 @@ constexpr int kPad = 2;       // zero border of the padded image copies
 // along the columns) -- the same walk on the transposed image.  Strips are
 // numbered x-major first: strip = ts * ceil(n_lane / kSL) + ls within a class.
 #ifndef DECT_ADJ_STRIP_WIDTH
-#define DECT_ADJ_STRIP_WIDTH 32
+#define DECT_ADJ_STRIP_WIDTH 8
 #endif
 #ifndef DECT_ADJ_WAVES
 #define DECT_ADJ_WAVES 4
 #endif
 #ifndef DECT_ADJ_BLOCKS
-#define DECT_ADJ_BLOCKS 1024
+#define DECT_ADJ_BLOCKS 4096
 #endif
 #ifndef DECT_FWD_WAVES
 #define DECT_FWD_WAVES 8
@@ -100,10 +100,12 @@ struct BinRange {
 };
 // Bins [lo + first, lo + last] of one view that put a tap inside one strip at
 // one lane (its driving line); empty: first > last.  Exact, from the
-// fixed-point ray table, relative to the strip's BinRange lo.
+// fixed-point ray table, relative to the strip's BinRange lo.  A strip range
+// of more than 256 bins keeps no lane ranges: its lanes take the whole range.
 struct LaneRange {
-    uint16_t first, last;
+    uint8_t first, last;
 };
+constexpr int kLaneRangeMax = 255;
 
 struct GeomKey {
     int32_t nx, ny, V, B;

@@ -299,9 +299,12 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     // Per-lane bin ranges inside each strip range.  At a fixed driving line
     // the rays of one view are ordered (they meet only at the source, outside
     // the image), so the line coordinate q is monotone in the bin index and
-    // the bins with t0 - 1 < q < t0 + kSW form one interval: two binary
-    // searches per lane.  A bin outside it adds nothing to the strip's lines
-    // at that lane (q exactly t0 - 1 gives the line t0 weight zero).
+    // the bins with t0 - 1 < q < t0 + kSW form one interval, whose ends are
+    // walked from the previous lane's.  A bin outside it adds nothing to the
+    // strip's lines at that lane (q exactly t0 - 1 gives the line t0 weight
+    // zero).  Ranges are stored relative to the strip's lo as bytes; a strip
+    // range of more than 256 bins stores none (the kernel then gives every
+    // lane the whole range, a superset, which changes no result).
     if ((double)nst * V * kSL * sizeof(LaneRange) > (double)(size_t(1) << 30))
         return fail(DECT_ERR_GEOMETRY, "geometry too large for the back-projector's lane table");
     std::vector<LaneRange> lanes((size_t)nst * V * kSL, LaneRange{1, 0});
@@ -314,9 +317,11 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
         for (int v = 0; v < V; ++v) {
             const BinRange r = bins[(size_t)sI * V + v];
             if (r.lo > r.hi) continue;
-            if (r.hi - r.lo >= 0xffff)
-                return fail(DECT_ERR_GEOMETRY, "too many bins per strip for the lane table");
+            if (r.hi - r.lo > kLaneRangeMax) continue;  // the kernel takes the whole range
             LaneRange *out = &lanes[((size_t)sI * V + v) * kSL];
+            // boundaries of monotone predicates over [lo, hi], walked from the
+            // previous lane's (they move by a few bins from lane to lane)
+            int gf = r.lo, gl = r.hi;
             for (int l = 0; l < kSL && l0 + l < nL; ++l) {
                 const int64_t c = l0 + l;
                 auto q = [&](int b) {
@@ -324,28 +329,30 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
                     return f.a_fx + f.k_fx * c;
                 };
                 const bool up = q(r.hi) >= q(r.lo);
-                // first bin past the lower edge and last bin before the upper
-                // one, in the direction q grows
                 auto below_hi = [&](int b) { return q(b) < qhi; };
                 auto above_lo = [&](int b) { return q(b) > qlo; };
-                int first, last;
-                if (up) {
-                    int a = r.lo, z = r.hi + 1;  // first b with q(b) > qlo
-                    while (a < z) { const int m = (a + z) / 2; if (above_lo(m)) z = m; else a = m + 1; }
-                    first = a;
-                    a = r.lo - 1; z = r.hi;  // last b with q(b) < qhi
-                    while (a < z) { const int m = (a + z + 1) / 2; if (below_hi(m)) a = m; else z = m - 1; }
-                    last = a;
-                } else {
-                    int a = r.lo, z = r.hi + 1;  // first b with q(b) < qhi
-                    while (a < z) { const int m = (a + z) / 2; if (below_hi(m)) z = m; else a = m + 1; }
-                    first = a;
-                    a = r.lo - 1; z = r.hi;  // last b with q(b) > qlo
-                    while (a < z) { const int m = (a + z + 1) / 2; if (above_lo(m)) a = m; else z = m - 1; }
-                    last = a;
-                }
+                // smallest b in [lo, hi + 1] where pred (false ... true) holds
+                auto first_true = [&](auto pred, int g) {
+                    g = std::min(std::max(g, r.lo), r.hi + 1);
+                    while (g > r.lo && pred(g - 1)) --g;
+                    while (g <= r.hi && !pred(g)) ++g;
+                    return g;
+                };
+                // largest b in [lo - 1, hi] where pred (true ... false) holds
+                auto last_true = [&](auto pred, int g) {
+                    g = std::min(std::max(g, r.lo - 1), r.hi);
+                    while (g < r.hi && pred(g + 1)) ++g;
+                    while (g >= r.lo && !pred(g)) --g;
+                    return g;
+                };
+                // in the direction q grows: the first bin past the lower
+                // edge, the last before the upper one
+                const int first = up ? first_true(above_lo, gf) : first_true(below_hi, gf);
+                const int last = up ? last_true(below_hi, gl) : last_true(above_lo, gl);
+                gf = first;
+                gl = last;
                 if (first <= last)
-                    out[l] = LaneRange{(uint16_t)(first - r.lo), (uint16_t)(last - r.lo)};
+                    out[l] = LaneRange{(uint8_t)(first - r.lo), (uint8_t)(last - r.lo)};
             }
         }
     }

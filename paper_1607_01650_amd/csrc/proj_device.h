@@ -43,9 +43,12 @@ struct AdjShared {
 #ifndef DECT_ADJ_LANES
 #define DECT_ADJ_LANES 1
 #endif
-struct AdjStage {
+struct alignas(16) AdjRay {
     int64_t a, k;  // strip-relative 32.32 line coordinate at lane 0, slope
-    float ly[2];   // |path length| x sinogram value of each image
+};
+struct AdjStage {  // one 64-bin chunk per wavefront
+    AdjRay ray[kAdjWaves * 64];
+    f2v ly[kAdjWaves * 64];  // |path length| x sinogram value of each image
 };
 
 // The back-projector evaluates the line coordinate of a bin at a lane either
@@ -231,7 +234,7 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                                           const LaneRange *__restrict__ lanes, int nx, int ny,
                                           int V, int B, int strip, int g, int nvg,
                                           float *const (&part)[NE],
-                                          AdjStage (&stage)[kAdjWaves * 64])
+                                          AdjStage &stage)
 {
     typedef typename AdjElem<NE>::T E;
     const int lane = threadIdx.x & 63;
@@ -264,34 +267,36 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
         (void)rv;
         if (lo > hi) continue;
         const LaneRange lr = lanes[((size_t)strip * V + v) * kSL + lane];
+        // a strip range too long for the table: every lane takes all of it
+        const bool whole = hi - lo > kLaneRangeMax;
+        const int lfirst = whole ? 0 : (int)lr.first, llast = whole ? hi - lo : (int)lr.last;
         const int sbase = wid * 64;
         for (int cb = lo; cb <= hi; cb += 64) {
             // stage: lane j holds bin cb + j (strip-relative line coordinate)
             const int bj = cb + lane;
-            AdjStage me;
-            me.a = 0;
-            me.k = 0;
-            me.ly[0] = me.ly[1] = 0.f;
+            AdjRay me{0, 0};
+            f2v my_ly = f2v(0.f);
             if (bj <= hi) {
                 const RayFwd t = rfv[bj];
                 me.a = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
                 me.k = t.k_fx;
                 const float L = fabsf(lv[bj]);
-#pragma unroll
-                for (int i = 0; i < NE; ++i) me.ly[i] = L * sino[i][(size_t)v * B + bj];
+                my_ly.x = L * sino[0][(size_t)v * B + bj];
+                if constexpr (NE > 1) my_ly.y = L * sino[NE - 1][(size_t)v * B + bj];
             }
-            stage[sbase + lane] = me;
+            stage.ray[sbase + lane] = me;
+            stage.ly[sbase + lane] = my_ly;
             // this lane's bins in the chunk: [f, e], chunk-relative
             const int rel = cb - lo;
-            const int f = max((int)lr.first, rel) - rel;
-            const int e = min((int)lr.last, rel + 63) - rel;
+            const int f = max(lfirst, rel) - rel;
+            const int e = min(llast, rel + 63) - rel;
             const int n = e - f + 1;
             int m = n;
             for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
             const int steps = __builtin_amdgcn_readfirstlane(m);
             // one step: bin b (staged) at this lane; a lane past its last bin
             // sends its taps to a spare line
-            auto step = [&](const AdjStage &b, bool ok) {
+            auto step = [&](const AdjRay &b, f2v y, bool ok) {
                 const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
                 const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
                 const int i0 = ok ? min(max(qh, -2), kSW) : -2;
@@ -299,13 +304,13 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 E *pp = col + (i0 + 2) * kSL;
                 E u0 = pp[0], u1 = pp[kSL];
                 if constexpr (NE == 1) {
-                    u0 += fmaf(-w, b.ly[0], b.ly[0]);
-                    u1 = fmaf(w, b.ly[0], u1);
+                    u0 += fmaf(-w, y.x, y.x);
+                    u1 = fmaf(w, y.x, u1);
                 } else {
-                    u0.x += fmaf(-w, b.ly[0], b.ly[0]);
-                    u0.y += fmaf(-w, b.ly[1], b.ly[1]);
-                    u1.x = fmaf(w, b.ly[0], u1.x);
-                    u1.y = fmaf(w, b.ly[1], u1.y);
+                    u0.x += fmaf(-w, y.x, y.x);
+                    u0.y += fmaf(-w, y.y, y.y);
+                    u1.x = fmaf(w, y.x, u1.x);
+                    u1.y = fmaf(w, y.y, u1.y);
                 }
                 pp[0] = u0;
                 pp[kSL] = u1;
@@ -314,14 +319,16 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             int t = 0;
             for (; t + 1 < steps; t += 2) {
                 const bool ok0 = t < n, ok1 = t + 1 < n;
-                const AdjStage b0 = stage[sbase + (ok0 ? f + t : 0)];
-                const AdjStage b1 = stage[sbase + (ok1 ? f + t + 1 : 0)];
-                step(b0, ok0);
-                step(b1, ok1);
+                const int j0 = sbase + (ok0 ? f + t : 0), j1 = sbase + (ok1 ? f + t + 1 : 0);
+                const AdjRay b0 = stage.ray[j0], b1 = stage.ray[j1];
+                const f2v y0 = stage.ly[j0], y1 = stage.ly[j1];
+                step(b0, y0, ok0);
+                step(b1, y1, ok1);
             }
             if (t < steps) {
                 const bool ok = t < n;
-                step(stage[sbase + (ok ? f + t : 0)], ok);
+                const int j = sbase + (ok ? f + t : 0);
+                step(stage.ray[j], stage.ly[j], ok);
             }
         }
 #else

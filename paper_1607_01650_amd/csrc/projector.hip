@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
                                                      float *__restrict__ part)
 {
     __shared__ AdjShared<NE> sh;
-    __shared__ AdjStage stage[kAdjWaves * 64];
+    __shared__ AdjStage stage;
     // (strip, view group, items) blocks in XCD order: the blocks of one XCD
     // share a view group's rays and sinogram rows
     const unsigned item = xcd_order(block_linear(), grid_blocks());

@@ -7,6 +7,7 @@
   size of a zero gradient is defined as 0 on both sides);
 * a single view: projector parity and the adjoint identity;
 * an image smaller than one back-projection strip (9 x 5 pixels);
+* detector bins so fine that a strip sees hundreds of bins per view;
 * PLS on a ragged image;
 * a batch of one slice reproduces the single-slice path bit for bit.
 """
@@ -29,6 +30,10 @@ ONE_VIEW = C.Geometry(nx=40, ny=40, pixel_mm=1.0, n_views=1, n_bins=70, bin_mm=1
                       sod_mm=200.0, sdd_mm=400.0)
 SMALL = C.Geometry(nx=9, ny=5, pixel_mm=1.0, n_views=7, n_bins=15, bin_mm=1.1,
                    sod_mm=40.0, sdd_mm=80.0)
+# detector bins of 0.06 px at the isocentre: a back-projection strip is hit by
+# hundreds of bins per view (more than the per-lane range table holds)
+FINE_BINS = C.Geometry(nx=64, ny=64, pixel_mm=1.0, n_views=12, n_bins=1200, bin_mm=0.12,
+                       sod_mm=200.0, sdd_mm=400.0)
 
 
 @pytest.fixture(scope="module")
@@ -73,7 +78,7 @@ def test_adm_zero_data_stays_zero(torch):
     assert np.all(ref.x == 0.0) and np.all(ref.J == 0.0)
 
 
-@pytest.mark.parametrize("geom", [ONE_VIEW, SMALL], ids=["one_view", "9x5"])
+@pytest.mark.parametrize("geom", [ONE_VIEW, SMALL, FINE_BINS], ids=["one_view", "9x5", "fine_bins"])
 def test_projectors_degenerate_geometries(torch, geom):
     dect = _dect()
     g = geom
