@@ -97,6 +97,8 @@ __host__ __device__ inline int adj_strips(int nx, int ny)
 // lo > hi); exact, from the fixed-point ray table.
 struct BinRange {
     int32_t lo, hi;
+    int32_t steps;  // longest per-lane range (below), at most 64: bin steps per 64-bin chunk
+    int32_t pad;
 };
 // Bins [lo + first, lo + last] of one view that put a tap inside one strip at
 // one lane (its driving line); empty: first > last.  Exact, from the

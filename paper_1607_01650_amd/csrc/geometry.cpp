@@ -257,7 +257,7 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
             const int l1 = std::min(l0 + kSL - 1, nL - 1);
             const int cb0 = cls ? views[v].yb0 : views[v].xb0;
             const int cb1 = cls ? views[v].yb1 : views[v].xb1;
-            BinRange r{1, 0};
+            BinRange r{1, 0, 0, 0};
             if (cb0 < cb1) {
                 const int64_t qlo = (int64_t)(t0 - 1) * one, qhi = (int64_t)(t0 + kSW) * one;
                 auto hit = [&](int b) {
@@ -289,7 +289,7 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
                 if (lo <= hi) {
                     while (lo > cb0 && hit(lo - 1)) --lo;
                     while (hi < cb1 - 1 && hit(hi + 1)) ++hi;
-                    r = BinRange{lo, hi};
+                    r = BinRange{lo, hi, 64, 0};
                 }
             }
             bins[(size_t)sI * V + v] = r;
@@ -315,9 +315,10 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
         const int t0 = (sidx / nsL) * kSW, l0 = (sidx % nsL) * kSL;
         const int64_t qlo = (int64_t)(t0 - 1) * one, qhi = (int64_t)(t0 + kSW) * one;
         for (int v = 0; v < V; ++v) {
-            const BinRange r = bins[(size_t)sI * V + v];
+            BinRange &r = bins[(size_t)sI * V + v];
             if (r.lo > r.hi) continue;
             if (r.hi - r.lo > kLaneRangeMax) continue;  // the kernel takes the whole range
+            int longest = 0;
             LaneRange *out = &lanes[((size_t)sI * V + v) * kSL];
             // boundaries of monotone predicates over [lo, hi], walked from the
             // previous lane's (they move by a few bins from lane to lane)
@@ -351,9 +352,12 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
                 const int last = up ? last_true(below_hi, gl) : last_true(above_lo, gl);
                 gf = first;
                 gl = last;
-                if (first <= last)
+                if (first <= last) {
                     out[l] = LaneRange{(uint8_t)(first - r.lo), (uint8_t)(last - r.lo)};
+                    longest = std::max(longest, last - first + 1);
+                }
             }
+            r.steps = std::min(longest, 64);
         }
     }
 

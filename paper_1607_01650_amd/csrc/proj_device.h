@@ -291,9 +291,8 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             const int f = max(lfirst, rel) - rel;
             const int e = min(llast, rel + 63) - rel;
             const int n = e - f + 1;
-            int m = n;
-            for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
-            const int steps = __builtin_amdgcn_readfirstlane(m);
+            // no lane has more bins in a chunk than its whole range holds
+            const int steps = __builtin_amdgcn_readfirstlane(br.steps);
             // one step: bin b (staged) at this lane; a lane past its last bin
             // sends its taps to a spare line
             auto step = [&](const AdjRay &b, f2v y, bool ok) {
