@@ -15,14 +15,28 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 // pair in the interleaved padded layout
 typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
 
+// Back-projector bin walk.  DECT_ADJ_LANES 1: every lane walks only the bins
+// that hit its own driving line inside the strip (exact per-lane ranges from
+// the host), reading their ray data from a per-wavefront LDS stage; 0: all
+// lanes take every bin of the strip's range together (ray data broadcast
+// with v_readlane).  Each accumulator element receives the same contributions
+// in the same order either way, so both give bitwise the same result.
+#ifndef DECT_ADJ_LANES
+#define DECT_ADJ_LANES 1
+#endif
+
 // Adjoint accumulation: a block's kAdjWaves wavefronts share one strip and split
 // its view group between them; each adds into its own LDS copy of the strip,
 // stored tap-line-major with row stride kSL (the 64 lanes of an access hit
-// distinct banks) plus two spare lines on each side: a tap pair whose first
-// line is clamped to [-2, kSW] then always lands on real lines only when it
-// belongs there, and on spare lines otherwise.  For a pair of images each
-// element holds both images' values side by side.
-constexpr int kAccRows = kSW + 4;
+// distinct banks) plus kAccOff spare lines on each side.  With per-lane ranges
+// every bin a lane takes has its first tap on lines -1 .. kSW - 1, so one
+// spare line per side suffices (a lane with no bin left adds zero to lines -1
+// and 0, which leaves them as they are); the shared walk clamps the first
+// tap line to [-2, kSW], so that every tap outside the strip lands on one of
+// two spare lines per side.  For a pair of images each element holds both
+// images' values side by side.
+constexpr int kAccOff = DECT_ADJ_LANES ? 1 : 2;
+constexpr int kAccRows = kSW + 2 * kAccOff;
 constexpr int kAccSize = kAccRows * kSL;
 
 template <int NE> struct AdjElem;
@@ -34,15 +48,6 @@ struct AdjShared {
     typename AdjElem<NE>::T acc[kAdjWaves][kAccSize];
 };
 
-// Back-projector bin walk.  DECT_ADJ_LANES 1: every lane walks only the bins
-// that hit its own driving line inside the strip (exact per-lane ranges from
-// the host), reading their ray data from a per-wavefront LDS stage; 0: all
-// lanes take every bin of the strip's range together (ray data broadcast
-// with v_readlane).  Each accumulator element receives the same contributions
-// in the same order either way, so both give bitwise the same result.
-#ifndef DECT_ADJ_LANES
-#define DECT_ADJ_LANES 1
-#endif
 struct alignas(16) AdjRay {
     int64_t a, k;  // strip-relative 32.32 line coordinate at lane 0, slope
 };
@@ -247,8 +252,7 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
     const int t0 = (sidx / nsL) * kSW, l0 = (sidx % nsL) * kSL;
     E *my = sh.acc[wid];
     for (int i = lane; i < kAccSize; i += 64) my[i] = E(0.f);
-    // acc line j holds tap line t0 + j - 2: lines 0, 1 and kSW + 2, kSW + 3
-    // are spare
+    // acc line j holds tap line t0 + j - kAccOff
     E *col = my + lane;
 #if !DECT_ADJ_INT
     const double ld = (double)lane;  // this lane's driving line, relative to l0
@@ -293,14 +297,17 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             const int n = e - f + 1;
             // no lane has more bins in a chunk than its whole range holds
             const int steps = __builtin_amdgcn_readfirstlane(br.steps);
-            // one step: bin b (staged) at this lane; a lane past its last bin
-            // sends its taps to a spare line
+            // one step: bin b (staged) at this lane.  A lane past its last bin,
+            // or taking a bin that misses its line (a strip range without
+            // lane ranges), adds zero to lines -1 and 0
             auto step = [&](const AdjRay &b, f2v y, bool ok) {
                 const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
                 const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
-                const int i0 = ok ? min(max(qh, -2), kSW) : -2;
+                ok = ok && qh >= -1 && qh <= kSW - 1;
+                const int i0 = ok ? qh : -1;
+                if (!ok) y = f2v(0.f);
                 const float w = (float)(uint32_t)p * kTwoM32;
-                E *pp = col + (i0 + 2) * kSL;
+                E *pp = col + (i0 + kAccOff) * kSL;
                 E u0 = pp[0], u1 = pp[kSL];
                 if constexpr (NE == 1) {
                     u0 += fmaf(-w, y.x, y.x);
@@ -414,7 +421,7 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 int i0;
                 float w;
                 pos(j, i0, w);
-                E *pp = col + (i0 + 2) * kSL;
+                E *pp = col + (i0 + kAccOff) * kSL;
                 E u0 = pp[0], u1 = pp[kSL];
                 add(u0, u1, w, j);
                 pp[0] = u0;
@@ -437,12 +444,12 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             const int ti = i / kSL, li = i % kSL;
             r = t0 + ti;
             c = l0 + li;
-            k = (ti + 2) * kSL + li;
+            k = (ti + kAccOff) * kSL + li;
         } else {         // strip row = lane, column = tap line
             const int li = i / kSW, ti = i % kSW;
             r = l0 + li;
             c = t0 + ti;
-            k = (ti + 2) * kSL + li;
+            k = (ti + kAccOff) * kSL + li;
         }
         if (r < ny && c < nx) {
             E sum = sh.acc[0][k];
