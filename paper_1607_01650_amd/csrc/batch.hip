@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kFwdThreads) void kb_fwd(const SliceDev *__restrict
                 o.sub_scale[e] = 0.0;
             }
             double res[2];
-            fwd_block(sh, d.P.gpad, d.P.gpadT, d.fwd, d.len, d.bundles, o, d.nx, d.ny, d.B,
+            fwd_block(sh, d.P.gpad, d.P.gpadT, d.fwd, d.len, d.bundles, o, d.nx, d.ny, d.V, d.B,
                       d.nbundle, blk, 1.0f, res);
             if (threadIdx.x < 64) {  // the values live in wavefront 0
                 const double t0 = lane_sum(res[0] * res[0]);

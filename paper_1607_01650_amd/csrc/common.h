@@ -53,7 +53,14 @@ struct ViewInfo {
     int32_t pad0, pad1;
 };
 
-constexpr int kBundle = 64;   // bins per forward wavefront
+// A forward wavefront holds kFwdViews adjacent views x kBundle adjacent bins
+// (lane = view offset * kBundle + bin offset): their rays cross each image
+// line close together, so a wavefront's tap loads touch few cache lines.
+#ifndef DECT_FWD_VIEWS
+#define DECT_FWD_VIEWS 4
+#endif
+constexpr int kFwdViews = DECT_FWD_VIEWS;
+constexpr int kBundle = 64 / kFwdViews;  // bins per forward wavefront and view
 constexpr int kPad = 2;       // zero border of the padded image copies
 
 // Adjoint strips.  The two ray classes are gathered separately: x-major rays
@@ -124,7 +131,7 @@ struct GeomTables {
     RayFwd *fwd = nullptr;     // [V*B]
     RayAdj *adj = nullptr;     // [V*B]
     float *len = nullptr;      // [V*B] path length per driving line (pixel/|cos|)
-    Bundle *bundles = nullptr; // [V*nbundle]
+    Bundle *bundles = nullptr; // [ceil(V / kFwdViews) * nbundle]
     ViewInfo *views = nullptr; // [V]
     BinRange *adj_bins = nullptr;  // [adj_strips][V]
     LaneRange *adj_lanes = nullptr;  // [adj_strips][V][kSL]

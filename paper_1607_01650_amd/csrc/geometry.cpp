@@ -160,7 +160,10 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     std::vector<RayFwd> fwd((size_t)V * B);
     std::vector<RayAdj> adj((size_t)V * B);
     std::vector<float> len((size_t)V * B);
-    std::vector<Bundle> bun((size_t)V * nb);
+    const int nvgrp = (V + kFwdViews - 1) / kFwdViews;
+    std::vector<Bundle> bun((size_t)nvgrp * nb);
+    // per ray: class and valid driving-line range
+    std::vector<int> r_major((size_t)V * B), r_lo((size_t)V * B), r_hi((size_t)V * B);
     std::vector<ViewInfo> views(V);
     int64_t samples = 0;
 
@@ -218,18 +221,28 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
         vi.yb0 = first_y < 0 ? 0 : first_y;
         vi.yb1 = first_y < 0 ? 0 : last_y + 1;
         views[v] = vi;
-        for (int j = 0; j < nb; ++j) {
-            Bundle bb{1 << 30, -(1 << 30), 1 << 30, -(1 << 30)};
-            for (int b = j * kBundle; b < std::min(B, (j + 1) * kBundle); ++b) {
-                if (lo[b] > hi[b]) continue;
-                if (major[b]) { bb.x0 = std::min(bb.x0, lo[b]); bb.x1 = std::max(bb.x1, hi[b]); }
-                else { bb.y0 = std::min(bb.y0, lo[b]); bb.y1 = std::max(bb.y1, hi[b]); }
-            }
-            if (bb.x0 > bb.x1) { bb.x0 = 1; bb.x1 = 0; }
-            if (bb.y0 > bb.y1) { bb.y0 = 1; bb.y1 = 0; }
-            bun[(size_t)v * nb + j] = bb;
+        for (int b = 0; b < B; ++b) {
+            r_major[(size_t)v * B + b] = major[b];
+            r_lo[(size_t)v * B + b] = lo[b];
+            r_hi[(size_t)v * B + b] = hi[b];
         }
     }
+    // forward bundles: per (group of kFwdViews views, kBundle bins), the union
+    // of the rays' valid line ranges per class
+    for (int gi = 0; gi < nvgrp; ++gi)
+        for (int j = 0; j < nb; ++j) {
+            Bundle bb{1 << 30, -(1 << 30), 1 << 30, -(1 << 30)};
+            for (int v = gi * kFwdViews; v < std::min(V, (gi + 1) * kFwdViews); ++v)
+                for (int b = j * kBundle; b < std::min(B, (j + 1) * kBundle); ++b) {
+                    const size_t i = (size_t)v * B + b;
+                    if (r_lo[i] > r_hi[i]) continue;
+                    if (r_major[i]) { bb.x0 = std::min(bb.x0, r_lo[i]); bb.x1 = std::max(bb.x1, r_hi[i]); }
+                    else { bb.y0 = std::min(bb.y0, r_lo[i]); bb.y1 = std::max(bb.y1, r_hi[i]); }
+                }
+            if (bb.x0 > bb.x1) { bb.x0 = 1; bb.x1 = 0; }
+            if (bb.y0 > bb.y1) { bb.y0 = 1; bb.y1 = 0; }
+            bun[(size_t)gi * nb + j] = bb;
+        }
 
     // Adjoint bin ranges: for every strip and view, the bins of the strip's
     // ray class whose rays put a tap inside the strip.  A first guess comes

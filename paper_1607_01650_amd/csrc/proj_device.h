@@ -124,8 +124,9 @@ struct FwdOut {
     double sub_scale[2];
 };
 
-// One forward block: view v and 64-bin bundle j from the index vb (= v *
-// nbundle + j) of one pair; lane = bin.  Wavefront `part` (of kFwdWaves)
+// One forward block: views [kFwdViews g, kFwdViews (g + 1)) and kBundle-bin
+// bundle j from the index vb (= g * nbundle + j) of one pair; lane = (view
+// offset, bin offset).  Wavefront `part` (of kFwdWaves)
 // walks the part-th share of each of the bundle's line ranges, so every
 // wavefront of the launch carries about the same work, and the partial sums
 // are combined in part order.  pad2/padT2: the pair's interleaved padded planes.
@@ -143,18 +144,19 @@ __device__ __forceinline__ void fwd_block(FwdShared &sh, const float *__restrict
                                           const RayFwd *__restrict__ rays,
                                           const float *__restrict__ len,
                                           const Bundle *__restrict__ bundles, const FwdOut &o,
-                                          int nx, int ny, int B, int nbundle, int vb, float scale,
-                                          double (&res)[2])
+                                          int nx, int ny, int V, int B, int nbundle, int vb,
+                                          float scale, double (&res)[2])
 {
     const int lane = threadIdx.x & 63;
     const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int v = vb / nbundle, j = vb - v * nbundle;
-    const int b = j * kBundle + lane;
-    const bool act = b < B;
-    const size_t ray = (size_t)v * B + (act ? b : 0);
+    const int vg = vb / nbundle, j = vb - vg * nbundle;
+    const int v = vg * kFwdViews + lane / kBundle;
+    const int b = j * kBundle + lane % kBundle;
+    const bool act = v < V && b < B;
+    const size_t ray = act ? (size_t)v * B + b : 0;
     const RayFwd rf = rays[ray];
     const float L = len[ray];
-    const Bundle bu = bundles[(size_t)v * nbundle + j];
+    const Bundle bu = bundles[vb];
     const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t far = -(int64_t(1000000) << 32);

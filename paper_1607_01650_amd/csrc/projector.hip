@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(const float *__restrict__ p
     o.sub_scale[0] = ss0;
     o.sub_scale[1] = ss1;
     double res[2];
-    fwd_block(sh, pad2 + p_off, padT2 + p_off, rays, len, bundles, o, nx, ny, B, nbundle, vb,
+    fwd_block(sh, pad2 + p_off, padT2 + p_off, rays, len, bundles, o, nx, ny, V, B, nbundle, vb,
               scale, res);
     if (NORM && threadIdx.x < 64) {  // the values live in wavefront 0
         const double t0 = lane_sum(res[0] * res[0]);
@@ -171,7 +171,10 @@ dect_status launch_pad(const GeomTables &t, const float *img, float *pad2, float
     return DECT_OK;
 }
 
-int fwd_blocks(const GeomTables &t) { return t.key.V * t.nbundle; }
+int fwd_blocks(const GeomTables &t)
+{
+    return (t.key.V + kFwdViews - 1) / kFwdViews * t.nbundle;
+}
 
 dect_status launch_fwd(const GeomTables &t, const float *pad2, const float *padT2, float *sino,
                        int batch, float scale, double *norm_partial, hipStream_t s,
