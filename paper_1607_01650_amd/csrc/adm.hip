@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_tv_fused(
              f + 2 * N + e * N,
              2 * nvg,
              mu};
-    tv_tile(ty * kT, tx * kT, m, partial + (size_t)tile * 5, sc[e].pending != 0, nx, ny, rho, xi);
+    tv_tile(ty * kTY, tx * kTX, m, partial + (size_t)tile * 5, sc[e].pending != 0, nx, ny, rho, xi);
 }
 
 // One block per energy.  nb_tv/nb_fwd: partial counts per energy.
@@ -309,7 +309,7 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
     const size_t N = (size_t)g->nx * g->ny, M = (size_t)g->n_views * g->n_bins;
     const size_t P = (size_t)(g->nx + 2 * kPad) * (g->ny + 2 * kPad);
     S->nvg = adj_groups(t, 2);
-    S->nb_tv = ((g->nx + kT - 1) / kT) * ((g->ny + kT - 1) / kT);
+    S->nb_tv = ((g->nx + kTX - 1) / kTX) * ((g->ny + kTY - 1) / kTY);
     S->nb_fwd = fwd_blocks(t);
     S->nbi = (int)((N + 1023) / 1024);
     S->nbs = (int)((M + 1023) / 1024);
@@ -340,7 +340,7 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     float *lam_in = lam + (size_t)par * 4 * N, *lam_out = lam + (size_t)(1 - par) * 4 * N;
     float *z_in = z + (size_t)par * 4 * N, *z_out = z + (size_t)(1 - par) * 4 * N;
     AdmScalars *sc = (AdmScalars *)S->sc.ptr;
-    dim3 gtv((nx + kT - 1) / kT, (ny + kT - 1) / kT, 2);
+    dim3 gtv((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY, 2);
     hipLaunchKernelGGL(k_tv_fused, gtv, dim3(256), 0, s, (const float *)S->f.ptr,
                        (const float *)S->adjpart.ptr, S->nvg, (float)S->mu, lam_in, z_in,
                        lam_out, z_out,

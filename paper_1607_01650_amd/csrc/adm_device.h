@@ -8,7 +8,18 @@
 
 namespace dect {
 
-constexpr int kT = 16;  // tv tile side
+// TV stencil tile: kTX columns x kTY rows, one pixel per thread of a 256-thread
+// block (wide tiles read longer row segments of every plane)
+#ifndef DECT_TV_TX
+#define DECT_TV_TX 32
+#endif
+constexpr int kTX = DECT_TV_TX;
+constexpr int kTY = 256 / kTX;
+static_assert(kTX * kTY == 256 && kTX >= 8 && kTY >= 4, "tv tile must hold 256 pixels");
+constexpr int kGW = kTX + 1, kGH = kTY + 1;  // G region (rows/cols -1 .. tile - 1)
+constexpr int kWW = kTX + 2, kWH = kTY + 2;  // w region (rows/cols -1 .. tile)
+constexpr int kFW = kTX + 3, kFH = kTY + 3;  // f region (rows/cols -2 .. tile)
+static_assert(kGW * kGH <= 512 && kWW * kWH <= 512, "two pixels per thread at most");
 
 struct AdmScalars {
     double alpha;   // step used by the next update
@@ -88,20 +99,20 @@ struct AdmImg {
 };
 
 // ------------------------------------------------------------- tv_fused ---
-// Tile origin (r0, c0).  Regions relative to it: f on rows/cols -2..16 (19),
-// w on -1..16 (18), G on -1..15 (17), grad G on the 16x16 tile.  part5
+// Tile origin (r0, c0).  Regions relative to it: f on rows/cols -2 .. tile,
+// w on -1 .. tile, G on -1 .. tile - 1, grad G on the kTX x kTY tile.  part5
 // receives (TV(f), |G|^2, |grad G|^2, |grad f - z|^2, |f|^2) of the tile.
 __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part5,
                                         bool pending, int nx, int ny, float rho, float xi)
 {
-    __shared__ float sf[19][20], sl[19][20];
-    __shared__ float swx[18][19], swy[18][19];
-    __shared__ float sg[17][18];
+    __shared__ float sf[kFH][kFW + 1], sl[kFH][kFW + 1];
+    __shared__ float swx[kWH][kWW + 1], swy[kWH][kWW + 1];
+    __shared__ float sg[kGH][kGW + 1];
     __shared__ double outv[5];
     const float inv_rho = 1.0f / rho;
 
     // h = hmu * (sum of the partial planes, in plane order) on the G region
-    // (rows/cols -1..15; a thread holds at most two of its 289 pixels).  It
+    // (a thread holds at most two of its pixels).  It
     // depends on nothing else here, so its loads go out first, eight planes
     // at a time, and overlap the tile loads below.
     float hsum[2] = {0.f, 0.f};
@@ -110,9 +121,9 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int i = threadIdx.x + 256 * k;
-            const int rr = i / 17, cc = i % 17;
+            const int rr = i / kGW, cc = i % kGW;
             const int r = r0 - 1 + rr, c = c0 - 1 + cc;
-            if (i < 17 * 17 && r >= 0 && r < ny && c >= 0 && c < nx) {
+            if (i < kGW * kGH && r >= 0 && r < ny && c >= 0 && c < nx) {
                 const float *hp = m.h + (size_t)r * nx + c;
                 float acc = 0.f;
                 for (int q0 = 0; q0 < m.hq; q0 += 8) {
@@ -128,15 +139,15 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
         }
     }
 
-    // lambda (and z for the deferred multiplier step) on the w region (rows/
-    // cols -1..16; at most two of its 324 pixels per thread), loaded ahead too
+    // lambda (and z for the deferred multiplier step) on the w region (at
+    // most two of its pixels per thread), loaded ahead too
     float lxv[2] = {0.f, 0.f}, lyv[2] = {0.f, 0.f}, zxv[2] = {0.f, 0.f}, zyv[2] = {0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int i = threadIdx.x + 256 * k;
-        const int rr = i / 18, cc = i % 18;
+        const int rr = i / kWW, cc = i % kWW;
         const int r = r0 - 1 + rr, c = c0 - 1 + cc;
-        if (i < 18 * 18 && r >= 0 && r < ny && c >= 0 && c < nx) {
+        if (i < kWW * kWH && r >= 0 && r < ny && c >= 0 && c < nx) {
             const size_t o = (size_t)r * nx + c;
             lxv[k] = m.lxi[o];
             lyv[k] = m.lyi[o];
@@ -147,8 +158,8 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
         }
     }
 
-    for (int i = threadIdx.x; i < 19 * 19; i += 256) {
-        int rr = i / 19, cc = i % 19;
+    for (int i = threadIdx.x; i < kFW * kFH; i += 256) {
+        int rr = i / kFW, cc = i % kFW;
         int r = r0 - 2 + rr, c = c0 - 2 + cc;
         const bool in = r >= 0 && r < ny && c >= 0 && c < nx;
         sf[rr][cc] = in ? m.f[(size_t)r * nx + c] : 0.f;
@@ -160,8 +171,8 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int i = threadIdx.x + 256 * k;
-        if (i >= 18 * 18) break;
-        int rr = i / 18, cc = i % 18;
+        if (i >= kWW * kWH) break;
+        int rr = i / kWW, cc = i % kWW;
         int r = r0 - 1 + rr, c = c0 - 1 + cc;
         float wx = 0.f, wy = 0.f;
         if (r >= 0 && r < ny && c >= 0 && c < nx) {
@@ -180,7 +191,7 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             float zx = s * vx, zy = s * vy;
             wx = rho * (dx - zx) - lx;
             wy = rho * (dy - zy) - ly;
-            if (rr >= 1 && rr <= kT && cc >= 1 && cc <= kT) {
+            if (rr >= 1 && rr <= kTY && cc >= 1 && cc <= kTX) {
                 m.lxo[o] = lx;
                 m.lyo[o] = ly;
                 m.zxo[o] = zx;
@@ -196,12 +207,12 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     }
     __syncthreads();
 
-    // G = h + grad^T w on rows/cols -1..15
+    // G = h + grad^T w on the G region
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int i = threadIdx.x + 256 * k;
-        if (i >= 17 * 17) break;
-        int rr = i / 17, cc = i % 17;
+        if (i >= kGW * kGH) break;
+        int rr = i / kGW, cc = i % kGW;
         int r = r0 - 1 + rr, c = c0 - 1 + cc;
         float gv = 0.f;
         if (r >= 0 && r < ny && c >= 0 && c < nx) {
@@ -219,7 +230,7 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     double gg = 0.0, gradg = 0.0;
     const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
     {
-        int rr = threadIdx.x / kT, cc = threadIdx.x % kT;
+        int rr = threadIdx.x / kTX, cc = threadIdx.x % kTX;
         int r = r0 + rr, c = c0 + cc;
         if (r < ny && c < nx) {
             float gv = sg[rr + 1][cc + 1];
@@ -229,10 +240,12 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             gradg = (double)gx * gx + (double)gy * gy;
             m.gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad)] = gv;
         }
-        // transposed write: thread (rr, cc) writes element (cc, rr) of the tile
-        int rt = r0 + cc, ct = c0 + rr;
+        // transposed write: consecutive threads take consecutive rows of one
+        // column, i.e. consecutive elements of a line of the transposed copy
+        const int cl = threadIdx.x / kTY, rl = threadIdx.x % kTY;
+        int rt = r0 + rl, ct = c0 + cl;
         if (rt < ny && ct < nx)
-            m.gpadT[2 * ((size_t)(ct + kPad) * pny + rt + kPad)] = sg[cc + 1][rr + 1];
+            m.gpadT[2 * ((size_t)(ct + kPad) * pny + rt + kPad)] = sg[rl + 1][cl + 1];
     }
     double v[5] = {tv, gg, gradg, pres, ff};
     block_sum<5>(v, outv);

@@ -62,9 +62,9 @@ __global__ __launch_bounds__(256) void kb_tv(const SliceDev *__restrict__ S,
         const SliceDev &d = S[w.x];
         const int e = w.y;
         if (!d.P.sc[e].stopped) {
-            const int gx = (d.nx + kT - 1) / kT, gy = (d.ny + kT - 1) / kT;
+            const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
             const size_t blk = (size_t)e * gx * gy + (size_t)w.z * gx + w.w;
-            tv_tile(w.z * kT, w.w * kT, img_of(d, e, par), d.P.p_tv + blk * 5,
+            tv_tile(w.z * kTY, w.w * kTX, img_of(d, e, par), d.P.p_tv + blk * 5,
                     d.P.sc[e].pending != 0, d.nx, d.ny, d.rho, d.xi);
         }
         __syncthreads();
@@ -214,7 +214,7 @@ dect_status build_work(dect_batch *b)
         int nvg = b->group_choice ? std::min(b->group_choice, std::max(1, d.V / 8))
                                   : heuristic_groups(t);
         d.nvg = nvg;
-        const int gx = (d.nx + kT - 1) / kT, gy = (d.ny + kT - 1) / kT;
+        const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
         const int nstrips = adj_strips(d.nx, d.ny);
         for (int e = 0; e < 2; ++e) {
             for (int ty = 0; ty < gy; ++ty)
@@ -362,7 +362,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         z.N = (size_t)t.key.nx * t.key.ny;
         z.M = (size_t)t.key.V * t.key.B;
         z.Pp = (size_t)(t.key.nx + 2 * kPad) * (t.key.ny + 2 * kPad);
-        z.nb_tv = (size_t)((t.key.nx + kT - 1) / kT) * ((t.key.ny + kT - 1) / kT);
+        z.nb_tv = (size_t)((t.key.nx + kTX - 1) / kTX) * ((t.key.ny + kTY - 1) / kTY);
         z.nb_fwd = (size_t)fwd_blocks(t);
         z.nbi = (z.N + 1023) / 1024;
         z.nbs = (z.M + 1023) / 1024;

@@ -5,21 +5,21 @@
 // stored interleaved, both images' values of a pixel side by side, so one
 // load fetches the two taps of both images.
 //
-// Forward (A x): one lane per ray; a block holds 64 adjacent bins of one
-// view and its four wavefronts step through quarters of the driving lines in
-// lockstep, so the taps of all lanes land in one short run of a padded image
-// line (the transposed copy for x-major rays): coalesced reads, coalesced
-// sinogram writes.  The line coordinate is advanced in exact 32.32 fixed
-// point.
+// Forward (A x): one lane per ray; a wavefront holds 16 adjacent bins of 4
+// adjacent views and the block's wavefronts step through shares of the
+// driving lines in lockstep, so the taps of all lanes land in one short run
+// of a padded image line (the transposed copy for x-major rays).  The line
+// coordinate is advanced in exact 32.32 fixed point.
 //
 // Adjoint (A^T y): output-stationary gather on strips.  x-major rays are
 // gathered on strips of kSW rows x 64 columns (lane = column), y-major rays
 // on strips of kSW columns x 64 rows (lane = row); each wavefront holds the
-// strip in LDS and walks, view by view, the bins whose rays put a tap in it.
-// Every weight is recomputed from the same fixed-point line coordinate as the
-// forward pass (evaluated exactly in FP64), so the adjoint is the exact
-// transpose of the forward matrix.  No atomics: each pixel's sum runs in a
-// fixed order (views of a wave, waves of a block, view groups).
+// strip in LDS and walks, view by view, the bins whose rays put a tap on its
+// lanes' lines (each lane its own bins, from exact per-lane ranges).  Every
+// weight is recomputed from the same fixed-point line coordinate as the
+// forward pass, so the adjoint is the exact transpose of the forward matrix.
+// No atomics: each pixel's sum runs in a fixed order (bins and views of a
+// wave, waves of a block, view groups).
 #include "proj_device.h"
 #include "xcd.h"
 
