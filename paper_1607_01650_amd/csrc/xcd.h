@@ -4,7 +4,8 @@
 // a work index such that each XCD receives one contiguous 1/kXcds of the
 // work range, so work items that share input lines (neighbouring tiles, one
 // energy's image, one view group's rays) share an L2.  It is a permutation
-// of [0, n) for any n; the grouping applies when n is a multiple of kXcds.
+// of [0, n) for any n: the first kXcds * floor(n / kXcds) blocks are grouped,
+// the last n mod kXcds keep their index.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,8 +16,9 @@ constexpr unsigned kXcds = 8;
 
 __device__ __forceinline__ unsigned xcd_order(unsigned linear, unsigned n)
 {
-    if (n % kXcds) return linear;
-    return (linear % kXcds) * (n / kXcds) + linear / kXcds;
+    const unsigned q = n / kXcds;
+    if (linear >= q * kXcds) return linear;
+    return (linear % kXcds) * q + linear / kXcds;
 }
 
 // Linear index of this block in a 3-D grid (x fastest) and the grid's size.
