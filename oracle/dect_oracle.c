@@ -8,9 +8,12 @@
  * Decomposition for Dual-energy CT") in the most direct form, slowly.
  *
  * Contents and the passage each follows:
- *   or_project / or_backproject  Joseph ray-driven line integrals of the image
- *                                and their literal transpose (the linear model
- *                                A x = m of Eq. 1; A^T of the gradient G_f, Eq. 9)
+ *   or_project / or_backproject  line integrals of the image and their literal
+ *                                transpose (the linear model A x = m of Eq. 1;
+ *                                A^T of the gradient G_f, Eq. 9), with either
+ *                                Joseph's interpolating ray model or Siddon's
+ *                                exact pixel intersection lengths, the model
+ *                                Sec. 2.1 names
  *   or_grad / or_gradT           backward differences of the TV norm (Eq. 2)
  *                                and their exact adjoint
  *   or_shrink                    the z-subproblem's closed form (Eq. 8, read as
@@ -56,6 +59,7 @@ typedef struct {
     const double *angles; /* NULL: theta_v = 2*pi*v/n_views */
     int32_t n_bins;
     double bin, det_offset, sod, sdd;
+    int32_t model; /* 0: Joseph, 1: Siddon */
 } or_geom;
 
 int or_num_threads(void)
@@ -139,6 +143,89 @@ static double joseph_walk(const or_geom *g, int v, int b, double *X, double y, i
     return acc;
 }
 
+/*
+ * Walk one Siddon ray: the segment from the source to the bin centre, and
+ * the exact length of its part inside every pixel (pixels are squares of side
+ * `pixel` tiling the grid, which is centred on the isocentre).  Points on the
+ * segment are s + t d, t in [0, 1].  The segment enters and leaves the grid
+ * at t0 < t1 (slab clipping against the grid's four sides).  Its crossings
+ * with the nx + 1 vertical and ny + 1 horizontal grid lines inside (t0, t1),
+ * merged in increasing t together with t0 and t1, cut it into pieces that
+ * each lie in one pixel, the pixel that contains the piece's midpoint; the
+ * piece's length is its parameter interval times |d|.
+ * mode 0: return sum over pieces of length * X.  mode 1: X += length * y.
+ */
+static double siddon_walk(const or_geom *g, int v, int b, double *X, double y, int mode)
+{
+    const int nx = g->nx, ny = g->ny;
+    const double dl = g->pixel;
+    double sx, sy, dx, dy;
+    ray_of(g, v, b, &sx, &sy, &dx, &dy);
+    const double len = sqrt(dx * dx + dy * dy);
+    const double xmin = -0.5 * nx * dl, ymin = -0.5 * ny * dl;
+    const double xmax = 0.5 * nx * dl, ymax = 0.5 * ny * dl;
+    double t0 = 0.0, t1 = 1.0;
+    if (dx != 0.0) {
+        double ta = (xmin - sx) / dx, tb = (xmax - sx) / dx;
+        t0 = fmax(t0, fmin(ta, tb));
+        t1 = fmin(t1, fmax(ta, tb));
+    } else if (!(sx > xmin && sx < xmax)) {
+        return 0.0;
+    }
+    if (dy != 0.0) {
+        double ta = (ymin - sy) / dy, tb = (ymax - sy) / dy;
+        t0 = fmax(t0, fmin(ta, tb));
+        t1 = fmin(t1, fmax(ta, tb));
+    } else if (!(sy > ymin && sy < ymax)) {
+        return 0.0;
+    }
+    if (!(t1 > t0)) return 0.0;
+    /* grid-line crossings of each family in increasing t */
+    double *tx = (double *)malloc((size_t)(nx + 1) * sizeof(double));
+    double *ty = (double *)malloc((size_t)(ny + 1) * sizeof(double));
+    int nxc = 0, nyc = 0;
+    if (dx != 0.0)
+        for (int j = 0; j <= nx; ++j) {
+            int i = dx > 0.0 ? j : nx - j;
+            double t = (xmin + i * dl - sx) / dx;
+            if (t > t0 && t < t1) tx[nxc++] = t;
+        }
+    if (dy != 0.0)
+        for (int j = 0; j <= ny; ++j) {
+            int i = dy > 0.0 ? j : ny - j;
+            double t = (ymin + i * dl - sy) / dy;
+            if (t > t0 && t < t1) ty[nyc++] = t;
+        }
+    double acc = 0.0, prev = t0;
+    int ix = 0, iy = 0;
+    for (;;) {
+        double next;
+        if (ix < nxc && (iy >= nyc || tx[ix] <= ty[iy])) next = tx[ix++];
+        else if (iy < nyc) next = ty[iy++];
+        else next = t1;
+        if (next > prev) {
+            double tm = 0.5 * (prev + next);
+            int c = (int)floor((sx + tm * dx - xmin) / dl);
+            int r = (int)floor((sy + tm * dy - ymin) / dl);
+            if (c >= 0 && c < nx && r >= 0 && r < ny) {
+                double l = (next - prev) * len;
+                if (mode == 0) acc += l * X[(size_t)r * nx + c];
+                else X[(size_t)r * nx + c] += l * y;
+            }
+        }
+        prev = next;
+        if (next == t1 && ix >= nxc && iy >= nyc) break;
+    }
+    free(tx);
+    free(ty);
+    return acc;
+}
+
+static double ray_walk(const or_geom *g, int v, int b, double *X, double y, int mode)
+{
+    return g->model == 1 ? siddon_walk(g, v, b, X, y, mode) : joseph_walk(g, v, b, X, y, mode);
+}
+
 /* Number of (ray, driving line) samples whose crossing lies in (-1, n). */
 int64_t or_count_samples(const or_geom *g)
 {
@@ -171,7 +258,7 @@ void or_project(const or_geom *g, const double *img, double *sino)
 #pragma omp parallel for schedule(static)
     for (int v = 0; v < V; ++v)
         for (int b = 0; b < B; ++b)
-            sino[(size_t)v * B + b] = joseph_walk(g, v, b, (double *)img, 0.0, 0);
+            sino[(size_t)v * B + b] = ray_walk(g, v, b, (double *)img, 0.0, 0);
 }
 
 /* img = A^T sino: every ray scatters its weights back.  Views are split into
@@ -191,7 +278,7 @@ void or_backproject(const or_geom *g, const double *sino, double *img)
         double *mine = buf + (size_t)t * N;
         for (int v = v0; v < v1; ++v)
             for (int b = 0; b < B; ++b)
-                joseph_walk(g, v, b, mine, sino[(size_t)v * B + b], 1);
+                ray_walk(g, v, b, mine, sino[(size_t)v * B + b], 1);
     }
     for (size_t i = 0; i < N; ++i) {
         double s = 0.0;

@@ -34,7 +34,7 @@ class _Geom(ct.Structure):
     _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("pixel", ct.c_double),
                 ("n_views", ct.c_int32), ("angles", ct.POINTER(ct.c_double)),
                 ("n_bins", ct.c_int32), ("bin", ct.c_double), ("det_offset", ct.c_double),
-                ("sod", ct.c_double), ("sdd", ct.c_double)]
+                ("sod", ct.c_double), ("sdd", ct.c_double), ("model", ct.c_int32)]
 
 
 _lib = None
@@ -90,18 +90,20 @@ class OGeom:
     """Geometry in the oracle's own struct; keeps the angle array alive."""
 
     def __init__(self, nx, ny, pixel_mm, n_views, n_bins, bin_mm, sod_mm, sdd_mm,
-                 det_offset_mm=0.0, angles_rad: Optional[Sequence[float]] = None):
+                 det_offset_mm=0.0, angles_rad: Optional[Sequence[float]] = None,
+                 model: int = 0):
         self.nx, self.ny, self.n_views, self.n_bins = int(nx), int(ny), int(n_views), int(n_bins)
         self._angles = None if angles_rad is None else _f64(angles_rad)
         self.s = _Geom(self.nx, self.ny, float(pixel_mm), self.n_views,
                        _p(self._angles), self.n_bins, float(bin_mm), float(det_offset_mm),
-                       float(sod_mm), float(sdd_mm))
+                       float(sod_mm), float(sdd_mm), int(model))
 
     @classmethod
     def of(cls, g) -> "OGeom":
-        """From any object with the Geometry field names."""
+        """From any object with the Geometry field names (model: 0 Joseph,
+        1 Siddon; absent means Joseph)."""
         return cls(g.nx, g.ny, g.pixel_mm, g.n_views, g.n_bins, g.bin_mm, g.sod_mm, g.sdd_mm,
-                   g.det_offset_mm, g.angles_rad)
+                   g.det_offset_mm, g.angles_rad, getattr(g, "model", 0))
 
 
 def _og(g) -> OGeom:

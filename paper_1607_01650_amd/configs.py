@@ -45,6 +45,7 @@ class Geometry:
     sdd_mm: float
     det_offset_mm: float = 0.0
     angles_rad: Optional[Sequence[float]] = None
+    model: int = 0  # ray model of A: 0 Joseph (interpolating), 1 Siddon (pixel intersection lengths)
 
     @property
     def n_pixels(self) -> int:
