@@ -49,6 +49,18 @@ typedef enum {
     DECT_WARN_MAXITER = 5     /* PCG stopped at max_iter above tolerance */
 } dect_status;
 
+/* Ray model of the system matrix A (Eq. 1).
+ * DECT_JOSEPH: each ray steps along the image axis it is more aligned with
+ *   and interpolates linearly between the two nearest pixel centres of every
+ *   line it crosses; samples are scaled by the path length per line.
+ * DECT_SIDDON: A[ray, pixel] is the exact length of the source-to-bin-centre
+ *   segment inside the pixel square (the model Sec. 2.1 names).  Along a
+ *   line of the driving axis the ray crosses at most two adjacent pixels, so
+ *   it is evaluated as two taps per line like Joseph, with the path length
+ *   per line split at the pixel boundary (the boundary's position is rounded
+ *   to 2^-32 pixel). */
+enum { DECT_JOSEPH = 0, DECT_SIDDON = 1 };
+
 /* 2-D fan-beam geometry with a flat detector line (Sec. 2.1 and Sec. 3:
  * SOD, SDD, views and detector bins define the system matrix A of Eq. 1). */
 typedef struct {
@@ -61,6 +73,7 @@ typedef struct {
     double det_offset_mm;     /* shift of the detector centre along its axis */
     double sod_mm;            /* source to isocentre */
     double sdd_mm;            /* source to detector */
+    int32_t model;            /* DECT_JOSEPH or DECT_SIDDON (else DECT_ERR_INVALID_ARG) */
 } dect_geometry;
 
 /* ADM-TV parameters (Eqs. 3-10 and Sec. 2.4). */
@@ -106,11 +119,7 @@ typedef struct dect_adm_state dect_adm_state;
 
 /*
  * Forward projection d_sino = A d_img (Eq. 1; Sec. 2.4's forward projector),
- * with A the Joseph ray-driven linear-interpolation model: each ray steps
- * along the image axis it is more aligned with and interpolates linearly
- * between the two nearest pixel centres of every line it crosses; samples are
- * scaled by the path length per line.  The paper's own A uses Siddon's
- * intersection lengths; Joseph is the model implemented here.
+ * with A the ray model geom->model selects (Joseph or Siddon, see above).
  * batch images [batch][ny][nx] -> [batch][n_views][n_bins].
  */
 dect_status dect_project(const dect_geometry *geom, const float *d_img, float *d_sino,
@@ -178,7 +187,8 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  * size, view count and parameters, both energies each, advanced together;
  * every phase of an iteration is one persistent launch over a work list that
  * spans all slices, replayed from a hipGraph.  Starts from zero images.
- * geoms/params: host arrays [n] (params[i].max_iter and flags are ignored).
+ * geoms/params: host arrays [n] (params[i].max_iter and flags are ignored);
+ *   every geometry must use DECT_JOSEPH (else DECT_ERR_INVALID_ARG).
  * d_m_high, d_m_low, d_x_high, d_x_low: host arrays [n] of device pointers
  *   to slice i's sinograms [V_i][B_i] and output images [ny_i][nx_i].
  * objective: NULL or host [n], filled after synchronising the stream with

@@ -89,8 +89,8 @@ __global__ __launch_bounds__(kFwdThreads) void kb_fwd(const SliceDev *__restrict
                 o.sub_scale[e] = 0.0;
             }
             double res[2];
-            fwd_block(sh, d.P.gpad, d.P.gpadT, d.fwd, d.len, d.bundles, o, d.nx, d.ny, d.V, d.B,
-                      d.nbundle, blk, 1.0f, res);
+            fwd_block<false>(sh, d.P.gpad, d.P.gpadT, d.fwd, d.len, nullptr, d.bundles, o, d.nx,
+                             d.ny, d.V, d.B, d.nbundle, blk, 1.0f, res);
             if (threadIdx.x < 64) {  // the values live in wavefront 0
                 const double t0 = lane_sum(res[0] * res[0]);
                 const double t1 = lane_sum(res[1] * res[1]);
@@ -166,8 +166,8 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
             float *p[2];
             for (int e = 0; e < 2; ++e)
                 p[e] = d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
-            adj_block<2>(sh, s, d.adj, d.fwd, d.len, d.bins, d.lanes, d.nx, d.ny, d.V, d.B, strip,
-                         g, d.nvg, p, stage);
+            adj_block<2, false>(sh, s, d.adj, d.fwd, d.len, nullptr, d.bins, d.lanes, d.nx, d.ny,
+                                d.V, d.B, strip, g, d.nvg, p, stage, nullptr);
         }
         __syncthreads();
     }
@@ -356,6 +356,8 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         const dect_adm_params &p = prm[i];
         if (!(p.mu > 0) || !(p.rho > 0) || !(p.xi >= 0) || !(p.beta_high > 0) || !(p.beta_low > 0))
             return fail(DECT_ERR_INVALID_ARG, "dect_batch_create: invalid ADM parameters");
+        if (geoms[i].model != DECT_JOSEPH)
+            return fail(DECT_ERR_INVALID_ARG, "batched ADM runs the Joseph model only");
         if ((st = get_tables(&geoms[i], &b->t[i]))) return st;
         const GeomTables &t = *b->t[i];
         Sizes &z = sz[i];

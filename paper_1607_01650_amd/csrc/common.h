@@ -36,6 +36,17 @@ struct RayFwd {
     int64_t a_fx;
     int64_t k_fx;
 };
+// Siddon model: a_fx above is the coordinate q' = q - |k|/2 + 1/2 of the
+// ray's lower end within the driving line, shifted by half a pixel, so that
+// h = floor(q') is the first of the (at most two) pixels the ray crosses on
+// that line.  Its share of the line's path length that falls in pixel h + 1
+// is (frac(q') - (1 - |k|)) / |k| when positive, else 0; with frac(q') as
+// the 32-bit word lo, that is (lo - c) * inv * 2^-32 for lo > c, where
+// c = 2^32 - |k_fx| and inv = 1 / |k| (c = 2^32 - 1, inv = 0 when k = 0).
+struct SidW {
+    uint32_t c;
+    float inv;
+};
 struct RayAdj {  // the same two numbers as doubles (exact: |values| < 2^53)
     double a;
     double k;
@@ -117,7 +128,7 @@ struct LaneRange {
 constexpr int kLaneRangeMax = 255;
 
 struct GeomKey {
-    int32_t nx, ny, V, B;
+    int32_t nx, ny, V, B, model;
     double pixel, bin, off, sod, sdd;
     std::vector<double> angles;
     int device;
@@ -135,6 +146,7 @@ struct GeomTables {
     ViewInfo *views = nullptr; // [V]
     BinRange *adj_bins = nullptr;  // [adj_strips][V]
     LaneRange *adj_lanes = nullptr;  // [adj_strips][V][kSL]
+    SidW *sid = nullptr;       // [V*B] Siddon weight terms (null for Joseph)
     int64_t samples = 0;       // Joseph samples with q in (-1, n)
     ~GeomTables();
 };

@@ -46,7 +46,7 @@ DevBuf::~DevBuf()
 // ---------------------------------------------------------- geometry ---
 bool GeomKey::operator==(const GeomKey &o) const
 {
-    return nx == o.nx && ny == o.ny && V == o.V && B == o.B && pixel == o.pixel &&
+    return nx == o.nx && ny == o.ny && V == o.V && B == o.B && model == o.model && pixel == o.pixel &&
            bin == o.bin && off == o.off && sod == o.sod && sdd == o.sdd && angles == o.angles &&
            device == o.device;
 }
@@ -60,6 +60,7 @@ GeomTables::~GeomTables()
     if (views) (void)hipFree(views);
     if (adj_bins) (void)hipFree(adj_bins);
     if (adj_lanes) (void)hipFree(adj_lanes);
+    if (sid) (void)hipFree(sid);
 }
 
 dect_status validate_geometry(const dect_geometry *g)
@@ -67,6 +68,8 @@ dect_status validate_geometry(const dect_geometry *g)
     if (!g) return fail(DECT_ERR_INVALID_ARG, "geometry is NULL");
     if (g->nx <= 0 || g->ny <= 0 || g->n_views <= 0 || g->n_bins <= 0)
         return fail(DECT_ERR_INVALID_ARG, "geometry sizes must be positive");
+    if (g->model != DECT_JOSEPH && g->model != DECT_SIDDON)
+        return fail(DECT_ERR_INVALID_ARG, "geometry model must be DECT_JOSEPH or DECT_SIDDON");
     if (g->nx > 16384 || g->ny > 16384 || g->n_bins > (1 << 20) || g->n_views > (1 << 20))
         return fail(DECT_ERR_INVALID_ARG, "geometry sizes exceed the supported maximum");
     if (!(g->pixel_mm > 0.0) || !(g->bin_mm > 0.0) || !std::isfinite(g->pixel_mm) ||
@@ -143,7 +146,7 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     if (st != DECT_OK) return st;
     int dev = 0;
     DECT_HIP(hipGetDevice(&dev));
-    GeomKey key{g->nx, g->ny, g->n_views, g->n_bins, g->pixel_mm, g->bin_mm,
+    GeomKey key{g->nx, g->ny, g->n_views, g->n_bins, g->model, g->pixel_mm, g->bin_mm,
                 g->det_offset_mm, g->sod_mm, g->sdd_mm, {}, dev};
     if (g->angles_rad) key.angles.assign(g->angles_rad, g->angles_rad + g->n_views);
 
@@ -160,6 +163,8 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     std::vector<RayFwd> fwd((size_t)V * B);
     std::vector<RayAdj> adj((size_t)V * B);
     std::vector<float> len((size_t)V * B);
+    const bool siddon = g->model == DECT_SIDDON;
+    std::vector<SidW> sid(siddon ? (size_t)V * B : 0);
     const int nvgrp = (V + kFwdViews - 1) / kFwdViews;
     std::vector<Bundle> bun((size_t)nvgrp * nb);
     // per ray: class and valid driving-line range
@@ -194,6 +199,13 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
             int64_t afx = (int64_t)std::llround(a * kTwo32);
             int64_t kfx = (int64_t)std::llround(k * kTwo32);
             size_t i = (size_t)v * B + b;
+            if (siddon) {
+                // |k| <= 1 on the driving axis, so |k_fx| <= 2^32
+                const int64_t kabs = kfx < 0 ? -kfx : kfx;
+                afx += (int64_t(1) << 31) - (kabs >> 1);
+                sid[i].c = kabs ? (uint32_t)((int64_t(1) << 32) - kabs) : 0xFFFFFFFFu;
+                sid[i].inv = kabs ? (float)(kTwo32 / (double)kabs) : 0.0f;
+            }
             fwd[i] = {afx, kfx};
             adj[i] = {(double)afx / kTwo32, (double)kfx / kTwo32};
             len[i] = xm ? (float)L : -(float)L;  // sign marks the class
@@ -385,6 +397,10 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     DECT_HIP(hipMalloc(&t->views, views.size() * sizeof(ViewInfo)));
     DECT_HIP(hipMalloc(&t->adj_bins, bins.size() * sizeof(BinRange)));
     DECT_HIP(hipMalloc(&t->adj_lanes, lanes.size() * sizeof(LaneRange)));
+    if (siddon) {
+        DECT_HIP(hipMalloc(&t->sid, sid.size() * sizeof(SidW)));
+        DECT_HIP(hipMemcpy(t->sid, sid.data(), sid.size() * sizeof(SidW), hipMemcpyHostToDevice));
+    }
     DECT_HIP(hipMemcpy(t->fwd, fwd.data(), fwd.size() * sizeof(RayFwd), hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->adj, adj.data(), adj.size() * sizeof(RayAdj), hipMemcpyHostToDevice));
     DECT_HIP(hipMemcpy(t->len, len.data(), len.size() * sizeof(float), hipMemcpyHostToDevice));

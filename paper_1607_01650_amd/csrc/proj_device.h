@@ -75,10 +75,12 @@ constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 // zero padding) of both images are one 16-byte load at a 32-bit per-lane
 // byte offset.  Groups of kFwdGroup samples are summed in FP32 and the group sums
 // added in FP64; per image i, acc[2i] sums the first taps and acc[2i + 1] the
-// weight times the tap difference, the weight being the FP32 value (float)lo,
-// scaled by 2^-32 at the end.
+// weight times the tap difference, the weight being the FP32 value (float)lo
+// (Joseph) or (float)(lo - c) * inv for lo > c, else 0 (Siddon, sw = (c,
+// inv)), scaled by 2^-32 at the end.
+template <bool SID>
 __device__ __forceinline__ void walk(const char *line, unsigned bstep, int l0, int l1, int64_t q,
-                                     int64_t dq, int nq, double (&acc)[4])
+                                     int64_t dq, int nq, SidW sw, double (&acc)[4])
 {
     // q as (signed whole part, fraction) stepped with an explicit carry
     int qh = (int)(q >> 32);
@@ -87,7 +89,9 @@ __device__ __forceinline__ void walk(const char *line, unsigned bstep, int l0, i
     const unsigned dl = (unsigned)dq;
     auto sample = [&](float (&s)[4]) {
         const int h = min(max(qh, -2), nq);
-        const float wq = (float)ql;
+        float wq;
+        if constexpr (SID) wq = ql > sw.c ? (float)(ql - sw.c) * sw.inv : 0.f;
+        else wq = (float)ql;
         const f4a8 v = *(const f4a8 *)(line + (unsigned)(h + 2) * 8u);
         s[0] += v.x;
         s[1] = fmaf(wq, v.z - v.x, s[1]);
@@ -139,10 +143,12 @@ struct FwdShared {
     double acc[kFwdWaves][4][64];
 };
 
+template <bool SID>
 __device__ __forceinline__ void fwd_block(FwdShared &sh, const float *__restrict__ pad2,
                                           const float *__restrict__ padT2,
                                           const RayFwd *__restrict__ rays,
                                           const float *__restrict__ len,
+                                          const SidW *__restrict__ sid,
                                           const Bundle *__restrict__ bundles, const FwdOut &o,
                                           int nx, int ny, int V, int B, int nbundle, int vb,
                                           float scale, double (&res)[2])
@@ -156,6 +162,8 @@ __device__ __forceinline__ void fwd_block(FwdShared &sh, const float *__restrict
     const size_t ray = act ? (size_t)v * B + b : 0;
     const RayFwd rf = rays[ray];
     const float L = len[ray];
+    SidW sw{0xFFFFFFFFu, 0.f};
+    if constexpr (SID) sw = sid[ray];
     const Bundle bu = bundles[vb];
     const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -174,8 +182,8 @@ __device__ __forceinline__ void fwd_block(FwdShared &sh, const float *__restrict
         share(bu.x0, bu.x1, s0, s1);
         if (s0 <= s1) {
             const int64_t q = is_x ? a + k * (int64_t)s0 : far;
-            walk((const char *)padT2 + (size_t)(s0 + kPad) * pny * 8, (unsigned)(pny * 8), s0, s1,
-                 q, is_x ? k : 0, ny, acc);
+            walk<SID>((const char *)padT2 + (size_t)(s0 + kPad) * pny * 8, (unsigned)(pny * 8), s0,
+                      s1, q, is_x ? k : 0, ny, sw, acc);
         }
     }
     if (bu.y0 <= bu.y1) {  // y-major: lines are rows of the padded image
@@ -183,8 +191,8 @@ __device__ __forceinline__ void fwd_block(FwdShared &sh, const float *__restrict
         share(bu.y0, bu.y1, s0, s1);
         if (s0 <= s1) {
             const int64_t q = is_y ? a + k * (int64_t)s0 : far;
-            walk((const char *)pad2 + (size_t)(s0 + kPad) * pnx * 8, (unsigned)(pnx * 8), s0, s1,
-                 q, is_y ? k : 0, nx, acc);
+            walk<SID>((const char *)pad2 + (size_t)(s0 + kPad) * pnx * 8, (unsigned)(pnx * 8), s0,
+                      s1, q, is_y ? k : 0, nx, sw, acc);
         }
     }
 #pragma unroll
@@ -232,16 +240,17 @@ __device__ __forceinline__ double lane_sum(double v)
 // evaluates the ray on its own driving line and adds the two interpolation
 // taps of every image, which lie on consecutive tap lines, with one paired
 // LDS read and write (no atomics: the copy is the wave's own).
-template <int NE>
+template <int NE, bool SID>
 __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const (&sino)[NE],
                                           const RayAdj *__restrict__ rays,
                                           const RayFwd *__restrict__ rays_fx,
                                           const float *__restrict__ len,
+                                          const SidW *__restrict__ sid,
                                           const BinRange *__restrict__ bins,
                                           const LaneRange *__restrict__ lanes, int nx, int ny,
                                           int V, int B, int strip, int g, int nvg,
                                           float *const (&part)[NE],
-                                          AdjStage &stage)
+                                          AdjStage &stage, SidW *sid_stage)
 {
     typedef typename AdjElem<NE>::T E;
     const int lane = threadIdx.x & 63;
@@ -282,6 +291,7 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             const int bj = cb + lane;
             AdjRay me{0, 0};
             f2v my_ly = f2v(0.f);
+            SidW my_sw{0xFFFFFFFFu, 0.f};
             if (bj <= hi) {
                 const RayFwd t = rfv[bj];
                 me.a = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
@@ -289,9 +299,11 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 const float L = fabsf(lv[bj]);
                 my_ly.x = L * sino[0][(size_t)v * B + bj];
                 if constexpr (NE > 1) my_ly.y = L * sino[NE - 1][(size_t)v * B + bj];
+                if constexpr (SID) my_sw = sid[(size_t)v * B + bj];
             }
             stage.ray[sbase + lane] = me;
             stage.ly[sbase + lane] = my_ly;
+            if constexpr (SID) sid_stage[sbase + lane] = my_sw;
             // this lane's bins in the chunk: [f, e], chunk-relative
             const int rel = cb - lo;
             const int f = max(lfirst, rel) - rel;
@@ -302,13 +314,16 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             // one step: bin b (staged) at this lane.  A lane past its last bin,
             // or taking a bin that misses its line (a strip range without
             // lane ranges), adds zero to lines -1 and 0
-            auto step = [&](const AdjRay &b, f2v y, bool ok) {
+            auto step = [&](const AdjRay &b, f2v y, SidW sw, bool ok) {
                 const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
                 const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
                 ok = ok && qh >= -1 && qh <= kSW - 1;
                 const int i0 = ok ? qh : -1;
                 if (!ok) y = f2v(0.f);
-                const float w = (float)(uint32_t)p * kTwoM32;
+                const uint32_t lo = (uint32_t)p;
+                float w;
+                if constexpr (SID) w = (lo > sw.c ? (float)(lo - sw.c) * sw.inv : 0.f) * kTwoM32;
+                else w = (float)lo * kTwoM32;
                 E *pp = col + (i0 + kAccOff) * kSL;
                 E u0 = pp[0], u1 = pp[kSL];
                 if constexpr (NE == 1) {
@@ -330,18 +345,27 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 const int j0 = sbase + (ok0 ? f + t : 0), j1 = sbase + (ok1 ? f + t + 1 : 0);
                 const AdjRay b0 = stage.ray[j0], b1 = stage.ray[j1];
                 const f2v y0 = stage.ly[j0], y1 = stage.ly[j1];
-                step(b0, y0, ok0);
-                step(b1, y1, ok1);
+                SidW s0{0u, 0.f}, s1{0u, 0.f};
+                if constexpr (SID) {
+                    s0 = sid_stage[j0];
+                    s1 = sid_stage[j1];
+                }
+                step(b0, y0, s0, ok0);
+                step(b1, y1, s1, ok1);
             }
             if (t < steps) {
                 const bool ok = t < n;
                 const int j = sbase + (ok ? f + t : 0);
-                step(stage.ray[j], stage.ly[j], ok);
+                SidW sj{0u, 0.f};
+                if constexpr (SID) sj = sid_stage[j];
+                step(stage.ray[j], stage.ly[j], sj, ok);
             }
         }
 #else
         (void)lanes;
         (void)stage;
+        (void)sid_stage;
+        static_assert(!SID || DECT_ADJ_INT, "the Siddon weight needs the fixed-point position");
         for (int cb = lo; cb <= hi; cb += 64) {
             // lane j: bin cb + j, its line coordinate moved to the strip
             // origin, q' = (a + k l0 - t0) + k lane (exact: all terms are
@@ -355,6 +379,7 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
 #else
             double ajd = 0.0, kjd = 0.0;
 #endif
+            SidW sw_j{0xFFFFFFFFu, 0.f};
             if (bj <= hi) {
 #if DECT_ADJ_INT
                 const RayFwd t = rfv[bj];
@@ -368,6 +393,7 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 const float L = fabsf(lv[bj]);
 #pragma unroll
                 for (int i = 0; i < NE; ++i) lyj[i] = L * sino[i][(size_t)v * B + bj];
+                if constexpr (SID) sw_j = sid[(size_t)v * B + bj];
             }
 #if !DECT_ADJ_INT
             const int64_t aj = __double_as_longlong(ajd), kj = __double_as_longlong(kjd);
@@ -389,7 +415,15 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 const uint64_t p = (uint64_t)k_lo * (uint32_t)lane + (((uint64_t)a_hi << 32) | a_lo);
                 const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)k_hi, lane);
                 i0 = min(max(qh, -2), kSW);
-                w = (float)(uint32_t)p * kTwoM32;
+                const uint32_t lo = (uint32_t)p;
+                if constexpr (SID) {
+                    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)sw_j.c, j);
+                    const float inv =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sw_j.inv), j));
+                    w = (lo > c ? (float)(lo - c) * inv : 0.f) * kTwoM32;
+                } else {
+                    w = (float)lo * kTwoM32;
+                }
 #else
                 const double a = __longlong_as_double((int64_t)(((uint64_t)a_hi << 32) | a_lo));
                 const double k = __longlong_as_double((int64_t)(((uint64_t)k_hi << 32) | k_lo));

@@ -67,11 +67,12 @@ __global__ __launch_bounds__(256) void k_pad(const float *__restrict__ img, int 
 
 // ------------------------------------------------------------ forward ---
 // grid ((view, bundle) blocks, pairs); items 2p, 2p + 1 of `batch`.
-template <bool NORM>
+template <bool NORM, bool SID>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd(const float *__restrict__ pad2,
                                              const float *__restrict__ padT2,
                                              const RayFwd *__restrict__ rays,
                                              const float *__restrict__ len,
+                                             const SidW *__restrict__ sid,
                                              const Bundle *__restrict__ bundles,
                                              float *__restrict__ sino, int batch, int nx, int ny,
                                              int V, int B, int nbundle, float scale,
@@ -99,8 +100,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(const float *__restrict__ p
     o.sub_scale[0] = ss0;
     o.sub_scale[1] = ss1;
     double res[2];
-    fwd_block(sh, pad2 + p_off, padT2 + p_off, rays, len, bundles, o, nx, ny, V, B, nbundle, vb,
-              scale, res);
+    fwd_block<SID>(sh, pad2 + p_off, padT2 + p_off, rays, len, sid, bundles, o, nx, ny, V, B,
+                   nbundle, vb, scale, res);
     if (NORM && threadIdx.x < 64) {  // the values live in wavefront 0
         const double t0 = lane_sum(res[0] * res[0]);
         const double t1 = lane_sum(res[1] * res[1]);
@@ -114,11 +115,12 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(const float *__restrict__ p
 // ------------------------------------------------------------ adjoint ---
 // grid (strips of both classes, view groups, groups of NE items starting at
 // item0); part: [batch][2][nvg] planes of nx*ny floats.
-template <int NE>
+template <int NE, bool SID>
 __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ sino,
                                                      const RayAdj *__restrict__ rays,
                                                      const RayFwd *__restrict__ rays_fx,
                                                      const float *__restrict__ len,
+                                                     const SidW *__restrict__ sid,
                                                      const BinRange *__restrict__ bins,
                                                      const LaneRange *__restrict__ lanes, int nx,
                                                      int ny, int V, int B, int nvg, int item0,
@@ -126,6 +128,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
 {
     __shared__ AdjShared<NE> sh;
     __shared__ AdjStage stage;
+    __shared__ SidW sid_stage[SID ? kAdjWaves * 64 : 1];
     // (strip, view group, items) blocks in XCD order: the blocks of one XCD
     // share a view group's rays and sinogram rows
     const unsigned item = xcd_order(block_linear(), grid_blocks());
@@ -141,7 +144,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
         s[i] = sino + (size_t)(e0 + i) * M;
         p[i] = part + ((size_t)(e0 + i) * 2 * nvg + (size_t)cls * nvg + g) * plane;
     }
-    adj_block<NE>(sh, s, rays, rays_fx, len, bins, lanes, nx, ny, V, B, strip, g, nvg, p, stage);
+    adj_block<NE, SID>(sh, s, rays, rays_fx, len, sid, bins, lanes, nx, ny, V, B, strip, g, nvg, p,
+                       stage, sid_stage);
 }
 
 __global__ __launch_bounds__(256) void k_adj_sum(const float *__restrict__ part, int nvg,
@@ -183,14 +187,19 @@ dect_status launch_fwd(const GeomTables &t, const float *pad2, const float *padT
 {
     const GeomKey &k = t.key;
     dim3 grid(fwd_blocks(t), pairs_of(batch));
-    if (norm_partial)
-        hipLaunchKernelGGL(k_fwd<true>, grid, dim3(kFwdThreads), 0, s, pad2, padT2, t.fwd, t.len,
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(kFwdThreads), 0, s, pad2, padT2, t.fwd, t.len, t.sid,
                            t.bundles, sino, batch, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
                            norm_partial, sub0, sub1, ss0, ss1, lo);
-    else
-        hipLaunchKernelGGL(k_fwd<false>, grid, dim3(kFwdThreads), 0, s, pad2, padT2, t.fwd, t.len,
-                           t.bundles, sino, batch, k.nx, k.ny, k.V, k.B, t.nbundle, scale,
-                           (double *)nullptr, sub0, sub1, ss0, ss1, lo);
+    };
+    const bool sid = k.model == DECT_SIDDON;
+    if (norm_partial) {
+        if (sid) go(k_fwd<true, true>);
+        else go(k_fwd<true, false>);
+    } else {
+        if (sid) go(k_fwd<false, true>);
+        else go(k_fwd<false, false>);
+    }
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -219,14 +228,20 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
     if (nvg <= 0) nvg = adj_groups(t, batch);
     const size_t plane = (size_t)k.nx * k.ny;
     const unsigned strips = (unsigned)adj_strips(k.nx, k.ny);
-    if (batch >= 2)
-        hipLaunchKernelGGL(k_adj<2>, dim3(strips, nvg, batch / 2), dim3(kAdjThreads), 0, s, sino,
-                           t.adj, t.fwd, t.len, t.adj_bins, t.adj_lanes, k.nx, k.ny, k.V, k.B, nvg, 0,
-                           partial);
-    if (batch % 2)  // the last item of an odd batch on its own
-        hipLaunchKernelGGL(k_adj<1>, dim3(strips, nvg, 1), dim3(kAdjThreads), 0, s, sino, t.adj,
-                           t.fwd, t.len, t.adj_bins, t.adj_lanes, k.nx, k.ny, k.V, k.B, nvg, batch - 1,
-                           partial);
+    auto go = [&](auto kern, unsigned items, int item0) {
+        hipLaunchKernelGGL(kern, dim3(strips, nvg, items), dim3(kAdjThreads), 0, s, sino, t.adj,
+                           t.fwd, t.len, t.sid, t.adj_bins, t.adj_lanes, k.nx, k.ny, k.V, k.B, nvg,
+                           item0, partial);
+    };
+    const bool sid = k.model == DECT_SIDDON;
+    if (batch >= 2) {
+        if (sid) go(k_adj<2, true>, batch / 2, 0);
+        else go(k_adj<2, false>, batch / 2, 0);
+    }
+    if (batch % 2) {  // the last item of an odd batch on its own
+        if (sid) go(k_adj<1, true>, 1, batch - 1);
+        else go(k_adj<1, false>, 1, batch - 1);
+    }
     DECT_HIP(hipGetLastError());
     if (!img) return DECT_OK;  // the caller consumes the partial planes itself
     hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((plane + 255) / 256), batch), dim3(256), 0, s,

@@ -39,7 +39,7 @@ class dect_geometry(ct.Structure):
     _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("pixel_mm", ct.c_double),
                 ("n_views", ct.c_int32), ("angles_rad", ct.POINTER(ct.c_double)),
                 ("n_bins", ct.c_int32), ("bin_mm", ct.c_double), ("det_offset_mm", ct.c_double),
-                ("sod_mm", ct.c_double), ("sdd_mm", ct.c_double)]
+                ("sod_mm", ct.c_double), ("sdd_mm", ct.c_double), ("model", ct.c_int32)]
 
 
 class dect_adm_params(ct.Structure):
@@ -128,7 +128,7 @@ class GeomArg:
             self._angles = np.ascontiguousarray(g.angles_rad, dtype=np.float64)
             ap = self._angles.ctypes.data_as(ct.POINTER(ct.c_double))
         self.s = dect_geometry(g.nx, g.ny, g.pixel_mm, g.n_views, ap, g.n_bins, g.bin_mm,
-                               g.det_offset_mm, g.sod_mm, g.sdd_mm)
+                               g.det_offset_mm, g.sod_mm, g.sdd_mm, int(g.model))
 
     @property
     def ref(self):
