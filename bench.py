@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--unrolled-steps", type=int, default=3,
                     help="timed training steps of the unrolled-ADM entry (0: skip)")
+    ap.add_argument("--siddon-steps", type=int, default=100,
+                    help="timed ADM iterations of the Siddon-model entry (0: skip)")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -190,6 +192,8 @@ def main():
     warm = warm_start_extra(args.warm_cases)
     batched = batched_extra(args.batch_slices, args.batch_iters) if args.batch_slices > 0 else None
     unrolled = unrolled_extra(args.unrolled_steps) if args.unrolled_steps > 0 else None
+    siddon = (siddon_extra(args.siddon_steps, args.kernel_launches)
+              if args.siddon_steps > 0 else None)
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -228,11 +232,61 @@ def main():
                   "ray_updates_per_s": round(4 * S * iters_per_s, 1),
                   "wall_s_timed": round(wall, 4),
                   "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
-                  "warm_start": warm, "batched": batched, "unrolled": unrolled},
+                  "warm_start": warm, "batched": batched, "unrolled": unrolled,
+                  "siddon": siddon},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
     print(json.dumps(out), flush=True)
+
+
+def siddon_extra(steps: int, launches: int):
+    """The metric workload on the Siddon ray model (pixel intersection
+    lengths): ADM iterations/s and both projectors' launch times."""
+    import torch
+
+    from paper_1607_01650_amd import configs as C, dect, phantom as P
+
+    g = dataclasses.replace(C.METRIC, model=1)
+    s = P.make_slice(C.METRIC, 0)
+    p = C.default_adm_params(C.METRIC, steps)
+    mh = torch.as_tensor(s.sino[0], dtype=torch.float32).cuda()
+    ml = torch.as_tensor(s.sino[1], dtype=torch.float32).cuda()
+    xh = torch.empty((g.ny, g.nx), device="cuda")
+    xl = torch.empty_like(xh)
+    sp = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ev = HipEvents()
+    state = dect.AdmState(g)
+    dect.adm_tv(mh, ml, g, dataclasses.replace(p, max_iter=5), state=state, out=(xh, xl))
+    torch.cuda.synchronize()
+    e0, e1 = ev.event(), ev.event()
+    ev.record(e0, sp)
+    dect.adm_tv(mh, ml, g, p, state=state, out=(xh, xl))
+    ev.record(e1, sp)
+    torch.cuda.synchronize()
+    adm_ms = ev.ms(e0, e1) / steps
+
+    def per_launch(fn):
+        for _ in range(3):
+            fn()
+        a0, a1 = ev.event(), ev.event()
+        ev.record(a0, sp)
+        for _ in range(launches):
+            fn()
+        ev.record(a1, sp)
+        torch.cuda.synchronize()
+        return ev.ms(a0, a1) / launches
+
+    r = torch.randn((2, g.n_views, g.n_bins), device="cuda")
+    img = torch.empty((2, g.ny, g.nx), device="cuda")
+    x = torch.randn((2, g.ny, g.nx), device="cuda")
+    sino = torch.empty((2, g.n_views, g.n_bins), device="cuda")
+    adj_ms = per_launch(lambda: dect.backproject(r, g, out=img))
+    fwd_ms = per_launch(lambda: dect.project(x, g, out=sino))
+    return {"workload": "adm_tv_512x512_360views_736bins_2energies, Siddon model",
+            "iters_per_s": round(1e3 / adm_ms, 2), "ms_per_iteration": round(adm_ms, 4),
+            "steps": steps, "backprojection_us_2energies": round(adj_ms * 1e3, 2),
+            "fwd_projection_us_2energies": round(fwd_ms * 1e3, 2)}
 
 
 def warm_start_extra(n: int):

@@ -11,7 +11,8 @@ Sec. 2.1) against the FP64 oracle's Siddon walk.
 * a batch of three (a pair and a single instance) equals single calls bit
   for bit;
 * ADM-TV of both energies on the Siddon model, 50 iterations on the tiny
-  workload: image rel-L2 <= 1e-4, objective within 1e-5;
+  workload: image rel-L2 <= 1e-4, objective within 1e-5; 200 iterations at
+  512 x 512 x 360 views against the stored oracle run;
 * the batched ADM and an unknown model value are refused.
 """
 import math
@@ -141,3 +142,29 @@ def test_refusals(torch):
     bad = C.Geometry(**{**C.TINY.__dict__, "model": 2})
     with pytest.raises(dect.DectError):
         dect.project(torch.zeros((C.TINY.ny, C.TINY.nx), device="cuda"), bad)
+
+
+def test_adm_paper_scale_parity_200(torch):
+    """512x512, 360 views, 736 bins, both energies, 200 iterations on the
+    Siddon model vs the stored FP64 oracle run (tests/golden/make_golden.py
+    360 siddon): the same bounds as the Joseph model at 360 views (image
+    rel-L2 <= 1e-4 per energy, J(f^200) within 1e-4, J(f^k) for k <= 10
+    within 1e-5), whose FP32 rounding floor is derived there."""
+    import dataclasses
+    import os
+    dect = _dect()
+    path = os.path.join(os.path.dirname(__file__), "golden", "adm512_v360_k200_siddon.npz")
+    gold = np.load(path)
+    g = dataclasses.replace(C.paper_geometry(512, 360), model=1)
+    s = P.make_slice(g, 0)
+    p = C.default_adm_params(g, 200)
+    assert float(gold["mu"]) == p.mu and float(gold["xi"]) == p.xi
+    r = dect.adm_tv(to_dev(torch, s.sino[0]), to_dev(torch, s.sino[1]), g, p, want_log=True)
+    for e, xe in enumerate((r.x_high, r.x_low)):
+        err = rel_l2(to_np(xe), gold["x"][e])
+        jrel = np.abs(r.J[:, e] - gold["J"][e]) / gold["J"][e]
+        print(f"siddon V=360 energy {e}: image rel-L2 {err:.3e}  J200 rel err {jrel[200]:.2e}  "
+              f"max J rel err k<=10 {jrel[:11].max():.2e}", flush=True)
+        assert err <= 1e-4
+        assert jrel[200] <= 1e-4
+        assert jrel[:11].max() <= 1e-5

@@ -170,3 +170,19 @@ def test_adm_fixed_point():
     m = O.project(g, x0)
     r = O.adm(g, m, 0.9, 1.0, 64.0, 64.0, 8, x0=x0)
     assert np.abs(r.x - x0).max() <= 1e-12
+
+
+def test_linearity_and_half_turn_symmetry():
+    """A(ax + by) = aAx + bAy; rotating the image by 180 degrees shifts the
+    sinogram by half the views (full-circle scan, even view count)."""
+    g = C.Geometry(nx=48, ny=48, pixel_mm=1.0, n_views=20, n_bins=70, bin_mm=1.4, sod_mm=120.0,
+                   sdd_mm=240.0, model=1)
+    x, y = P.random_image(g, 5), P.random_image(g, 6)
+    lhs = O.project(g, 2.5 * x - 0.75 * y)
+    rhs = 2.5 * O.project(g, x) - 0.75 * O.project(g, y)
+    assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(rhs).max()
+    Sx = O.project(g, x)
+    Sr = O.project(g, x[::-1, ::-1].copy())
+    V = g.n_views
+    shifted = np.concatenate([Sx[V // 2:], Sx[: V // 2]])
+    assert np.abs(Sr - shifted).max() <= 1e-12 * np.abs(Sx).max()
