@@ -55,6 +55,7 @@ def lib():
         L.or_count_samples.restype = ct.c_int64
         L.or_project.argtypes = [P(_Geom), pd, pd]
         L.or_backproject.argtypes = [P(_Geom), pd, pd]
+        L.or_fbp.argtypes = [P(_Geom), pd, pd]
         L.or_grad.argtypes = [ct.c_int, ct.c_int, pd, pd, pd]
         L.or_gradT.argtypes = [ct.c_int, ct.c_int, pd, pd, pd]
         L.or_shrink.argtypes = [sz, pd, pd, d, pd, pd]
@@ -128,6 +129,15 @@ def backproject(g, sino: np.ndarray) -> np.ndarray:
     y = _f64(sino).reshape(og.n_views, og.n_bins)
     out = np.empty((og.ny, og.nx))
     lib().or_backproject(ct.byref(og.s), _p(y), _p(out))
+    return out
+
+
+def fbp(g, sino: np.ndarray) -> np.ndarray:
+    """Fan-beam filtered back-projection (full turn, ramp filter)."""
+    og = _og(g)
+    y = _f64(sino).reshape(og.n_views, og.n_bins)
+    out = np.empty((og.ny, og.nx))
+    lib().or_fbp(ct.byref(og.s), _p(y), _p(out))
     return out
 
 
