@@ -194,6 +194,7 @@ def main():
     unrolled = unrolled_extra(args.unrolled_steps) if args.unrolled_steps > 0 else None
     siddon = (siddon_extra(args.siddon_steps, args.kernel_launches)
               if args.siddon_steps > 0 else None)
+    fbp = fbp_extra(args.kernel_launches) if args.kernel_launches > 0 else None
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -233,7 +234,7 @@ def main():
                   "wall_s_timed": round(wall, 4),
                   "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
                   "warm_start": warm, "batched": batched, "unrolled": unrolled,
-                  "siddon": siddon},
+                  "siddon": siddon, "fbp": fbp},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
@@ -289,6 +290,47 @@ def siddon_extra(steps: int, launches: int):
             "fwd_projection_us_2energies": round(fwd_ms * 1e3, 2)}
 
 
+def fbp_extra(launches: int):
+    """Filtered back-projection, the paper's analytic comparator, on the
+    metric workload: time per call for both energies, and the image and
+    material errors against the phantom truth beside those of ADM-TV (200
+    iterations) + PLS."""
+    import numpy as np
+    import torch
+
+    from paper_1607_01650_amd import configs as C, dect, phantom as P
+
+    g = C.METRIC
+    s = P.make_slice(g, 0)
+    y = torch.as_tensor(s.sino, dtype=torch.float32).cuda()
+    out = torch.empty((2, g.ny, g.nx), device="cuda")
+    sp = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ev = HipEvents()
+    for _ in range(3):
+        dect.fbp(y, g, out=out)
+    a0, a1 = ev.event(), ev.event()
+    ev.record(a0, sp)
+    for _ in range(launches):
+        dect.fbp(y, g, out=out)
+    ev.record(a1, sp)
+    torch.cuda.synchronize()
+    fbp_us = ev.ms(a0, a1) / launches * 1e3
+    r = dect.adm_tv(y[0], y[1], g, C.default_adm_params(g, 200))
+    u_fbp = dect.pls_decompose(out[0], out[1], C.PlsParams(gamma=0.0, tol=1e-6))
+    u_adm = dect.pls_decompose(r.x_high, r.x_low, C.PlsParams(gamma=1.0, tol=1e-6))
+
+    def rel(a, b):
+        a = a.detach().cpu().numpy().astype(np.float64)
+        return round(float(np.linalg.norm(a - b) / np.linalg.norm(b)), 5)
+
+    return {"workload": "adm_tv_512x512_360views_736bins_2energies, slice 0",
+            "fbp_us_2energies": round(fbp_us, 2),
+            "x_rel_err_fbp": [rel(out[e], s.x_true[e]) for e in (0, 1)],
+            "x_rel_err_adm200": [rel(r.x_high, s.x_true[0]), rel(r.x_low, s.x_true[1])],
+            "u_rel_err_fbp_direct": [rel(u_fbp[m], s.u_true[m]) for m in (0, 1)],
+            "u_rel_err_adm200_pls": [rel(u_adm[m], s.u_true[m]) for m in (0, 1)]}
+
+
 def warm_start_extra(n: int):
     """Time to the plain method's objective J(f^200), learned warm start vs
     plain ADM, on the first n held-out phantoms (512x512, 90 views) with the
@@ -317,7 +359,12 @@ def warm_start_extra(n: int):
             "median_iters_learned": med([W.EARLY + r["k_cont"] for r in ok]),
             "median_ms_plain": med([r["t_plain_ms"] for r in ok]),
             "median_ms_learned": med([r["t_learned_ms"] for r in ok]),
-            "median_time_ratio": med([r["t_learned_ms"] / r["t_plain_ms"] for r in ok])}
+            "median_time_ratio": med([r["t_learned_ms"] / r["t_plain_ms"] for r in ok]),
+            "fbp_start": {"reached": sum(r["k_fbp"] >= 0 for r in rows),
+                          "median_iters": med([r["k_fbp"] for r in rows if r["k_fbp"] >= 0]),
+                          "median_ms": med([r["t_fbp_ms"] for r in rows if r["k_fbp"] >= 0]),
+                          "median_time_ratio": med([r["t_fbp_ms"] / r["t_plain_ms"]
+                                                    for r in rows if r["k_fbp"] >= 0])}}
 
 
 def batched_extra(n_slices: int, iters: int):

@@ -135,6 +135,23 @@ dect_status dect_backproject(const dect_geometry *geom, const float *d_sino, flo
                              int32_t batch, void *stream);
 
 /*
+ * Fan-beam filtered back-projection d_img = FBP(d_sino): the analytic
+ * reconstruction the paper compares with (Sec. 3, FBP rows of its tables),
+ * usable as the start image of dect_adm_tv (DECT_WARM_START).  Textbook form
+ * for an equally spaced flat detector over a full turn: each view is
+ * weighted by R / sqrt(R^2 + s^2) (s the bin position scaled to the
+ * isocentre, R = SOD), convolved with the band-limited ramp kernel and
+ * halved, then back-projected pixel by pixel with linear interpolation and
+ * the weight R^2 / (R - p . e_s)^2 (e_s towards the source), times 2 pi / V.
+ * Independent of geom->model.  batch sinograms [batch][n_views][n_bins] ->
+ * images [batch][ny][nx].  DECT_ERR_INVALID_ARG when geom->angles_rad is not
+ * NULL (the views must be the equally spaced full turn) or n_bins > 6144.
+ * Uses a library-owned workspace per (device, stream).
+ */
+dect_status dect_fbp(const dect_geometry *geom, const float *d_sino, float *d_img, int32_t batch,
+                     void *stream);
+
+/*
  * TV-regularised ADM reconstruction of both energies (Eq. 10): the stacked
  * system of Eq. 3 with f = (beta_1 x_h; beta_2 x_l), g = (beta_1 m_h;
  * beta_2 m_l), minimising |grad f| + mu/2 |W f - g|^2 (Eq. 4) by the

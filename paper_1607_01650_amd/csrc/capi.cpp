@@ -75,6 +75,13 @@ dect_status dect_backproject(const dect_geometry *geom, const float *d_sino, flo
     return dect::backproject(geom, d_sino, d_img, batch, (hipStream_t)stream);
 }
 
+dect_status dect_fbp(const dect_geometry *geom, const float *d_sino, float *d_img, int32_t batch,
+                     void *stream)
+{
+    dect::set_error("");
+    return dect::fbp(geom, d_sino, d_img, batch, (hipStream_t)stream);
+}
+
 dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
                         const dect_adm_params *params, float *d_x_high, float *d_x_low,
                         dect_adm_state *state, dect_report *rep, void *stream)

@@ -67,6 +67,7 @@ SIGNATURES = {
                                 ct.c_void_p]),
     "dect_backproject": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, ct.c_int32,
                                     ct.c_void_p]),
+    "dect_fbp": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p]),
     "dect_adm_tv": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, _P(dect_adm_params),
                                ct.c_void_p, ct.c_void_p, ct.c_void_p, _P(dect_report),
                                ct.c_void_p]),
@@ -201,6 +202,23 @@ def backproject(sino, geom: C.Geometry, out=None):
         return out
     _check(lib().dect_backproject(GeomArg(geom).ref, ct.c_void_p(sino.data_ptr()),
                                   ct.c_void_p(out.data_ptr()), b, _stream()), "dect_backproject")
+    return out
+
+
+def fbp(sino, geom: C.Geometry, out=None):
+    """Fan-beam filtered back-projection of sinograms [..., V, B] -> images
+    [..., ny, nx] (dect_fbp; equally spaced full turn)."""
+    torch = _torch()
+    _dev(sino, "sino", (geom.n_views, geom.n_bins))
+    lead = tuple(sino.shape[:-2])
+    if out is None:
+        out = torch.empty(lead + (geom.ny, geom.nx), device=sino.device, dtype=torch.float32)
+    _dev(out, "out", (geom.ny, geom.nx))
+    b = _batch(sino, 2)
+    if b == 0:
+        return out
+    _check(lib().dect_fbp(GeomArg(geom).ref, ct.c_void_p(sino.data_ptr()),
+                          ct.c_void_p(out.data_ptr()), b, _stream()), "dect_fbp")
     return out
 
 

@@ -186,13 +186,30 @@ def evaluate_case(net: NN.UNet, sol: Solver, sino: torch.Tensor, max_cont: int =
         sol.run(EARLY)
         return NN.predict(net, sol.x[0][None], sol.x[1][None])
 
+    # filtered back-projection start (the paper's analytic reconstruction)
+    def fbp_start():
+        return dect.fbp(sol.m, sol.geom)
+
+    xf = fbp_start()
+    Jf = sol.run(max_cont, x0=(xf[0].clone(), xf[1].clone()), log=True).J.sum(axis=1)
+    k_fbp = first_reach(Jf, J_ref)
+
     yh, yl = learned_start()
     x0 = (yh[0].clone(), yl[0].clone())
     Jc = sol.run(max_cont, x0=x0, log=True).J.sum(axis=1)
     k_cont = first_reach(Jc, J_ref)
-    row = dict(J_ref=J_ref, k_plain=k_plain, k_cont=k_cont, J_net=float(Jc[0]))
+    row = dict(J_ref=J_ref, k_plain=k_plain, k_cont=k_cont, J_net=float(Jc[0]), k_fbp=k_fbp,
+               J_fbp=float(Jf[0]))
     t_plain = _timed(lambda: sol.run(k_plain), reps)
     row["t_plain_ms"] = 1e3 * t_plain
+    if k_fbp >= 0:
+        def fbp_run():
+            a = fbp_start()
+            sol.run(k_fbp, x0=(a[0], a[1]))
+
+        row["t_fbp_ms"] = 1e3 * _timed(fbp_run, reps)
+    else:
+        row["t_fbp_ms"] = float("nan")
     if k_cont < 0:
         row.update(t_learned_ms=float("nan"), learned_img=None, plain_img=plain_img)
         return row
