@@ -107,6 +107,8 @@ def main():
                     help="timed training steps of the unrolled-ADM entry (0: skip)")
     ap.add_argument("--siddon-steps", type=int, default=100,
                     help="timed ADM iterations of the Siddon-model entry (0: skip)")
+    ap.add_argument("--no-fbp", action="store_true",
+                    help="skip the filtered back-projection comparator entry")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -194,7 +196,7 @@ def main():
     unrolled = unrolled_extra(args.unrolled_steps) if args.unrolled_steps > 0 else None
     siddon = (siddon_extra(args.siddon_steps, args.kernel_launches)
               if args.siddon_steps > 0 else None)
-    fbp = fbp_extra(args.kernel_launches) if args.kernel_launches > 0 else None
+    fbp = None if args.no_fbp else fbp_extra(max(1, args.kernel_launches))
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -552,7 +554,7 @@ def traffic_summary(pmc_dir: str):
         is_copy = lambda n: "copy" in n.lower() or "elementwise" in n.lower()
         ck, nc = per_dispatch(copy_rows, is_copy, counter)
         # k_adj (any template instance), not k_adj_sum; demangled or mangled
-        is_adj = lambda n: re.search(r"k_adj(<\d+>)?\(|\d+k_adj[IE]", n) is not None
+        is_adj = lambda n: re.search(r"k_adj(<[^>]*>)?\(|\d+k_adj[IE]", n) is not None
         adj, na = per_dispatch(proj_rows, is_adj, counter)
         asum, ns = per_dispatch(proj_rows, lambda n: "k_adj_sum" in n, counter)
         meta = json.load(open(os.path.join(pmc_dir, "copy_meta.json")))
