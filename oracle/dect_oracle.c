@@ -30,6 +30,8 @@
  *                                turns floats into a binary map
  *   or_laplacian                 the Hessian of R(u) (Eq. 14), halved
  *   or_pcg                       Jacobi-preconditioned CG for Eq. 15
+ *   or_pcg_att                   the attenuation-space variant |x - Du|^2 +
+ *                                gamma R(u), both materials coupled
  *
  * Readings of the paper taken here (each is also listed in the design notes):
  *   - separable TV per energy block, zero difference on the first row/column;
@@ -671,5 +673,94 @@ int or_pcg(int nx, int ny, const double *er, const double *ed, double gamma, con
     }
     if (relres) *relres = rn / bn;
     free(res); free(z); free(p); free(q); free(dinv);
+    return it;
+}
+
+/*
+ * Attenuation-space PLS: u = (u1, u2) minimising |x - D u|^2 + gamma R(u)
+ * (D applied per pixel, Eq. 12; R of Eq. 14 per material, Hessian 2L), i.e.
+ * the linear system (D^T D (x) I + gamma I (x) L) u = D^T x, solved by
+ * conjugate gradients preconditioned with the 2 x 2 per-pixel diagonal block
+ * D^T D + gamma diag(L), from u = D^{-1} x, until |res| <= tol |D^T x| (joint
+ * norms over both materials) or max_iter iterations.  Returns the iterations.
+ */
+int or_pcg_att(int nx, int ny, const double *er, const double *ed, double e1h, double e2h,
+               double e1l, double e2l, double gamma, const double *xh, const double *xl,
+               double *u1, double *u2, int max_iter, double tol, double *relres)
+{
+    const size_t N = (size_t)nx * ny;
+    /* D^T D = [[g11, g12], [g12, g22]] */
+    const double g11 = e1h * e1h + e1l * e1l, g12 = e1h * e2h + e1l * e2l;
+    const double g22 = e2h * e2h + e2l * e2l;
+    double *c = malloc(2 * N * sizeof(double)), *u = malloc(2 * N * sizeof(double));
+    double *res = malloc(2 * N * sizeof(double)), *z = malloc(2 * N * sizeof(double));
+    double *p = malloc(2 * N * sizeof(double)), *q = malloc(2 * N * sizeof(double));
+    double *lap = malloc(N * sizeof(double)), *dg = malloc(N * sizeof(double));
+    double det = e1h * e2l - e2h * e1l;
+    for (size_t i = 0; i < N; ++i) {
+        c[i] = e1h * xh[i] + e1l * xl[i];
+        c[N + i] = e2h * xh[i] + e2l * xl[i];
+        u[i] = (e2l * xh[i] - e2h * xl[i]) / det;
+        u[N + i] = (e1h * xl[i] - e1l * xh[i]) / det;
+    }
+    for (int r = 0; r < ny; ++r)
+        for (int cc = 0; cc < nx; ++cc) {
+            size_t i = (size_t)r * nx + cc;
+            double d = 0.0;
+            if (cc + 1 < nx) d += er[i];
+            if (cc >= 1) d += er[i - 1];
+            if (r + 1 < ny) d += ed[i];
+            if (r >= 1) d += ed[i - nx];
+            dg[i] = d;
+        }
+    /* q = A v for the two-material vector v */
+    #define APPLY(v, out)                                                         \
+        for (int m = 0; m < 2; ++m) {                                             \
+            or_laplacian(nx, ny, er, ed, (v) + m * N, lap);                       \
+            for (size_t i = 0; i < N; ++i) {                                      \
+                double dd = m == 0 ? g11 * (v)[i] + g12 * (v)[N + i]              \
+                                   : g12 * (v)[i] + g22 * (v)[N + i];             \
+                (out)[m * N + i] = dd + gamma * lap[i];                           \
+            }                                                                     \
+        }
+    /* z = P^{-1} res with the per-pixel block P = D^T D + gamma diag(L) I */
+    #define PRECOND()                                                             \
+        for (size_t i = 0; i < N; ++i) {                                          \
+            double a11 = g11 + gamma * dg[i], a22 = g22 + gamma * dg[i];          \
+            double dt = a11 * a22 - g12 * g12;                                    \
+            z[i] = (a22 * res[i] - g12 * res[N + i]) / dt;                        \
+            z[N + i] = (a11 * res[N + i] - g12 * res[i]) / dt;                    \
+        }
+    APPLY(u, q);
+    for (size_t i = 0; i < 2 * N; ++i) res[i] = c[i] - q[i];
+    double cn = sqrt(dot(2 * N, c, c)), rn = sqrt(dot(2 * N, res, res));
+    if (cn == 0.0) cn = 1.0;
+    PRECOND();
+    memcpy(p, z, 2 * N * sizeof(double));
+    double rz = dot(2 * N, res, z);
+    int it = 0;
+    while (it < max_iter && rn > tol * cn) {
+        APPLY(p, q);
+        double pq = dot(2 * N, p, q);
+        if (pq <= 0.0) break;
+        double a = rz / pq;
+        for (size_t i = 0; i < 2 * N; ++i) {
+            u[i] += a * p[i];
+            res[i] -= a * q[i];
+        }
+        ++it;
+        rn = sqrt(dot(2 * N, res, res));
+        PRECOND();
+        double rz2 = dot(2 * N, res, z);
+        double beta = rz2 / rz;
+        rz = rz2;
+        for (size_t i = 0; i < 2 * N; ++i) p[i] = z[i] + beta * p[i];
+    }
+    #undef APPLY
+    #undef PRECOND
+    memcpy(u1, u, N * sizeof(double));
+    memcpy(u2, u + N, N * sizeof(double));
+    if (relres) *relres = rn / cn;
+    free(c); free(u); free(res); free(z); free(p); free(q); free(lap); free(dg);
     return it;
 }

@@ -69,6 +69,9 @@ def lib():
         L.or_laplacian.argtypes = [ct.c_int, ct.c_int, pd, pd, pd, pd]
         L.or_pcg.argtypes = [ct.c_int, ct.c_int, pd, pd, d, pd, pd, ct.c_int, d, pd]
         L.or_pcg.restype = ct.c_int
+        L.or_pcg_att.argtypes = [ct.c_int, ct.c_int, pd, pd, d, d, d, d, d, pd, pd, pd, pd,
+                                 ct.c_int, d, pd]
+        L.or_pcg_att.restype = ct.c_int
         _lib = L
     return _lib
 
@@ -236,6 +239,19 @@ def pcg(er, ed, gamma: float, b, max_iter: int = 500, tol: float = 1e-12):
     return u, int(it), float(rr.value)
 
 
+def pcg_att(er, ed, eta, gamma: float, xh, xl, max_iter: int = 500, tol: float = 1e-12):
+    """Attenuation-space PLS system (D^T D + gamma L) u = D^T x, both materials
+    coupled; eta = (eta_water_high, eta_bone_high, eta_water_low, eta_bone_low)."""
+    er, ed, xh, xl = _f64(er), _f64(ed), _f64(xh), _f64(xl)
+    ny, nx = xh.shape
+    u1, u2 = np.empty_like(xh), np.empty_like(xh)
+    rr = ct.c_double(0.0)
+    it = lib().or_pcg_att(nx, ny, _p(er), _p(ed), *[float(e) for e in eta], float(gamma),
+                          _p(xh), _p(xl), _p(u1), _p(u2), int(max_iter), float(tol),
+                          ct.byref(rr))
+    return u1, u2, int(it), float(rr.value)
+
+
 def pls(xh, xl, p, edge_w=None, tol: float = 1e-12):
     """Full decomposition: D^{-1} x, edge weights on x_l (FP32 decision), PCG.
 
@@ -247,6 +263,10 @@ def pls(xh, xl, p, edge_w=None, tol: float = 1e-12):
         er, ed, _ = edges_f32(xl, p.edge_tau, p.edge_eps)
     else:
         er, ed = edge_w[0], edge_w[1]
+    if getattr(p, "mode", 0) == 1:  # attenuation space
+        eta = (p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
+        u1, u2, it, r = pcg_att(er, ed, eta, p.gamma, xh, xl, p.max_iter, tol)
+        return u1, u2, (it, it), (r, r)
     u1, it1, r1 = pcg(er, ed, p.gamma, b1, p.max_iter, tol)
     u2, it2, r2 = pcg(er, ed, p.gamma, b2, p.max_iter, tol)
     return u1, u2, (it1, it2), (r1, r2)
