@@ -102,7 +102,17 @@ typedef struct {
     double edge_tau;                      /* edge if |Prewitt| > tau * max |Prewitt| */
     int32_t max_iter;                     /* PCG iteration cap (paper: 500) */
     double tol;                           /* PCG stop: |res| <= tol * |rhs| */
+    int32_t mode;                         /* DECT_PLS_IMAGE or DECT_PLS_ATTENUATION */
 } dect_pls_params;
+
+/* PLS objective.  DECT_PLS_IMAGE: Eqs. 13 and 15 as printed, |u - D^{-1} x|^2
+ * + gamma R(u), i.e. (I + gamma L) u_m = (D^{-1} x)_m per material.
+ * DECT_PLS_ATTENUATION: |x - D u|^2 + gamma R(u) (the data term in the
+ * measured attenuation space, for which the gamma range of Sec. 2.4 is
+ * scaled), i.e. (D^T D (x) I + gamma I (x) L) u = D^T x with both materials
+ * coupled per pixel; solved by block-Jacobi CG in FP64 (D^T D is
+ * ill-conditioned), joint tolerance over both materials. */
+enum { DECT_PLS_IMAGE = 0, DECT_PLS_ATTENUATION = 1 };
 
 typedef struct {
     int32_t iters;       /* ADM iterations run, or the larger PCG count */

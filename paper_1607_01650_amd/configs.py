@@ -100,6 +100,7 @@ class PlsParams:
     edge_tau: float = 0.25
     max_iter: int = 500
     tol: float = 1e-6
+    mode: int = 0  # 0: Eq. 15 as printed (image space), 1: |x - Du|^2 + gamma R (attenuation space)
 
 
 # --- Workload geometries -----------------------------------------------------

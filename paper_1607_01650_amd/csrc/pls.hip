@@ -319,8 +319,231 @@ __global__ __launch_bounds__(256) void k_pcg_final(const double *__restrict__ p_
     stat[m].done = rn <= tol * bn ? 1 : 3;  // 3: stopped at the cap
 }
 
+// ---------------------------------------------- attenuation-space PLS ---
+// (D^T D (x) I + gamma I (x) L) u = D^T x (|x - Du|^2 + gamma R(u)): both
+// materials of a pixel in one thread, so the per-pixel 2 x 2 coupling D^T D
+// and the block-Jacobi preconditioner (D^T D + gamma diag(L)) apply in place;
+// joint scalars over both materials.  D^T D has the condition number of D
+// squared (~740 for water and bone), so vectors and arithmetic are FP64.
+struct AttCoef {
+    double g11, g12, g22;       // D^T D
+    double e1h, e2h, e1l, e2l;  // D
+};
+
+// (A v)_m at pixel i for the two-material FP64 vector v ([2][N]).
+__device__ __forceinline__ void att_apply(const double *__restrict__ v,
+                                          const float *__restrict__ er,
+                                          const float *__restrict__ ed, const AttCoef &k,
+                                          double gamma, size_t i, int r, int c, int nx, int ny,
+                                          size_t N, double (&out)[2])
+{
+    double lv[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const double *vm = v + m * N;
+        const double vi = vm[i];
+        double l = 0.0;
+        if (c + 1 < nx) l += (double)er[i] * (vi - vm[i + 1]);
+        if (c >= 1) l += (double)er[i - 1] * (vi - vm[i - 1]);
+        if (r + 1 < ny) l += (double)ed[i] * (vi - vm[i + nx]);
+        if (r >= 1) l += (double)ed[i - nx] * (vi - vm[i - nx]);
+        lv[m] = l;
+    }
+    const double a = v[i], b = v[N + i];
+    out[0] = k.g11 * a + k.g12 * b + gamma * lv[0];
+    out[1] = k.g12 * a + k.g22 * b + gamma * lv[1];
+}
+
+// z = P^{-1} res at one pixel, P = D^T D + gamma diag(L) I.
+__device__ __forceinline__ void att_precond(const AttCoef &k, double gamma, double d,
+                                            const double (&rs)[2], double (&z)[2])
+{
+    const double a11 = k.g11 + gamma * d, a22 = k.g22 + gamma * d;
+    const double dt = a11 * a22 - k.g12 * k.g12;
+    z[0] = (a22 * rs[0] - k.g12 * rs[1]) / dt;
+    z[1] = (a11 * rs[1] - k.g12 * rs[0]) / dt;
+}
+
+// Setup from u = D^{-1} x (u1, u2): u64 = u, res = D^T x - A u, z = P^{-1} res,
+// p_old = 0; partials <res, z>, |res|^2, |D^T x|^2 in slot 0.
+__global__ __launch_bounds__(256) void k_apcg_setup(
+    const float *__restrict__ xh, const float *__restrict__ xl, const float *__restrict__ u1,
+    const float *__restrict__ u2, const float *__restrict__ w, double gamma, AttCoef k,
+    double *__restrict__ u, double *__restrict__ res, double *__restrict__ z,
+    double *__restrict__ pold, double *__restrict__ p_rz, double *__restrict__ p_rr,
+    double *__restrict__ p_bb, PcgStatus *__restrict__ stat, int nx, int ny)
+{
+    const size_t N = (size_t)nx * ny;
+    const float *er = w, *ed = w + N;
+    // u64 first, block by block: the stencil below reads neighbours' values
+    // from the float inputs, so no ordering between blocks is needed
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < kPix; ++j) {
+        size_t i = ((size_t)blockIdx.x * kPix + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            double lu[2];
+            const float *um[2] = {u1, u2};
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const double ui = um[m][i];
+                double l = 0.0;
+                if (c + 1 < nx) l += (double)er[i] * (ui - (double)um[m][i + 1]);
+                if (c >= 1) l += (double)er[i - 1] * (ui - (double)um[m][i - 1]);
+                if (r + 1 < ny) l += (double)ed[i] * (ui - (double)um[m][i + nx]);
+                if (r >= 1) l += (double)ed[i - nx] * (ui - (double)um[m][i - nx]);
+                lu[m] = l;
+            }
+            const double a = u1[i], b = u2[i];
+            const double h = xh[i], l = xl[i];
+            const double c0 = k.e1h * h + k.e1l * l, c1 = k.e2h * h + k.e2l * l;
+            double rs[2] = {c0 - (k.g11 * a + k.g12 * b + gamma * lu[0]),
+                            c1 - (k.g12 * a + k.g22 * b + gamma * lu[1])};
+            double zz[2];
+            att_precond(k, gamma, (double)lap_diag(er, ed, i, r, c, nx, ny), rs, zz);
+            u[i] = a;
+            u[N + i] = b;
+            res[i] = rs[0];
+            res[N + i] = rs[1];
+            z[i] = zz[0];
+            z[N + i] = zz[1];
+            pold[i] = 0.0;
+            pold[N + i] = 0.0;
+            v[0] += rs[0] * zz[0] + rs[1] * zz[1];
+            v[1] += rs[0] * rs[0] + rs[1] * rs[1];
+            v[2] += c0 * c0 + c1 * c1;
+        }
+    }
+    __shared__ double out[3];
+    bsum<3>(v, out);
+    if (threadIdx.x == 0) {
+        p_rz[blockIdx.x] = out[0];
+        p_rr[blockIdx.x] = out[1];
+        p_bb[blockIdx.x] = out[2];
+        if (blockIdx.x == 0) {
+            stat[0].done = 0;
+            stat[0].iters = 0;
+            stat[0].relres = 0.0;
+        }
+    }
+}
+
+// Part A: convergence test, beta, p_new = z + beta p_old, q = A p_new,
+// partial <p_new, q>.  p_new is formed first by every block for its own
+// pixels in a separate pass (k_apcg_p) so that q's stencil can read it.
+__global__ __launch_bounds__(256) void k_apcg_p(
+    const double *__restrict__ z, const double *__restrict__ pold, double *__restrict__ pnew,
+    const double *__restrict__ rz_cur, const double *__restrict__ rz_prev,
+    const double *__restrict__ p_rr, const double *__restrict__ p_bb,
+    PcgStatus *__restrict__ stat, int it, double tol, int nx, int ny, int nblk)
+{
+    if (stat[0].done) return;
+    const double rr = reduce_array(p_rr, nblk);
+    const double bb = reduce_array(p_bb, nblk);
+    const double bn = bb > 0.0 ? sqrt(bb) : 1.0;
+    const double rn = bb > 0.0 ? sqrt(rr) : 0.0;
+    if (rn <= tol * bn) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            stat[0].done = 1;
+            stat[0].iters = it;
+            stat[0].relres = rn / bn;
+        }
+        return;
+    }
+    double beta = 0.0;
+    if (it > 0) beta = reduce_array(rz_cur, nblk) / reduce_array(rz_prev, nblk);
+    const size_t N = (size_t)nx * ny;
+    for (int j = 0; j < kPix; ++j) {
+        size_t i = ((size_t)blockIdx.x * kPix + j) * 256 + threadIdx.x;
+        if (i < N) {
+            pnew[i] = z[i] + beta * pold[i];
+            pnew[N + i] = z[N + i] + beta * pold[N + i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_apcg_q(
+    const double *__restrict__ pnew, double *__restrict__ q, const float *__restrict__ w,
+    double gamma, AttCoef k, double *__restrict__ p_pq, PcgStatus *__restrict__ stat, int nx,
+    int ny)
+{
+    if (stat[0].done) return;
+    const size_t N = (size_t)nx * ny;
+    const float *er = w, *ed = w + N;
+    double v[1] = {0.0};
+    for (int j = 0; j < kPix; ++j) {
+        size_t i = ((size_t)blockIdx.x * kPix + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            double qq[2];
+            att_apply(pnew, er, ed, k, gamma, i, r, c, nx, ny, N, qq);
+            q[i] = qq[0];
+            q[N + i] = qq[1];
+            v[0] += pnew[i] * qq[0] + pnew[N + i] * qq[1];
+        }
+    }
+    __shared__ double out[1];
+    bsum<1>(v, out);
+    if (threadIdx.x == 0) p_pq[blockIdx.x] = out[0];
+}
+
+// Part B: a = rz / <p, q>, u += a p, res -= a q, z = P^{-1} res; partials of
+// the next <res, z> and |res|^2.
+__global__ __launch_bounds__(256) void k_apcg_b(
+    double *__restrict__ u, double *__restrict__ res, double *__restrict__ z,
+    const double *__restrict__ pnew, const double *__restrict__ q, const float *__restrict__ w,
+    double gamma, AttCoef k, const double *__restrict__ rz_cur, const double *__restrict__ p_pq,
+    double *__restrict__ rz_next, double *__restrict__ p_rr, PcgStatus *__restrict__ stat,
+    int nx, int ny, int nblk)
+{
+    if (stat[0].done) return;
+    const double pq = reduce_array(p_pq, nblk);
+    const double rz = reduce_array(rz_cur, nblk);
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) stat[0].done = 2;
+        return;
+    }
+    const double a = rz / pq;
+    const size_t N = (size_t)nx * ny;
+    const float *er = w, *ed = w + N;
+    double v[2] = {0.0, 0.0};
+    for (int j = 0; j < kPix; ++j) {
+        size_t i = ((size_t)blockIdx.x * kPix + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            u[i] += a * pnew[i];
+            u[N + i] += a * pnew[N + i];
+            double rs[2] = {res[i] - a * q[i], res[N + i] - a * q[N + i]};
+            double zz[2];
+            att_precond(k, gamma, (double)lap_diag(er, ed, i, r, c, nx, ny), rs, zz);
+            res[i] = rs[0];
+            res[N + i] = rs[1];
+            z[i] = zz[0];
+            z[N + i] = zz[1];
+            v[0] += rs[0] * zz[0] + rs[1] * zz[1];
+            v[1] += rs[0] * rs[0] + rs[1] * rs[1];
+        }
+    }
+    __shared__ double out[2];
+    bsum<2>(v, out);
+    if (threadIdx.x == 0) {
+        rz_next[blockIdx.x] = out[0];
+        p_rr[blockIdx.x] = out[1];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_apcg_out(const double *__restrict__ u,
+                                                  float *__restrict__ u1, float *__restrict__ u2,
+                                                  size_t N)
+{
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    u1[i] = (float)u[i];
+    u2[i] = (float)u[N + i];
+}
+
 struct PlsWork {
-    DevBuf b, res, z, p0, p1, q, minv, w, m2, pmax, prz0, prz1, prr, pbb, ppq, stat;
+    DevBuf b, res, z, p0, p1, q, minv, w, m2, pmax, prz0, prz1, prr, pbb, ppq, stat, u64;
 };
 
 std::mutex g_pls_mu;
@@ -366,6 +589,86 @@ dect_status pls_edge_weights(int nx, int ny, const float *x, double tau, double 
     return edges_into(nx, ny, x, tau, eps, w, pls_work(), s);
 }
 
+// The attenuation-space system, from u = D^{-1} x already in u1, u2.
+dect_status pls_attenuation(int nx, int ny, const float *xh, const float *xl,
+                            const dect_pls_params *P, const float *w, float *u1, float *u2,
+                            dect_report *rep, PlsWork *W, int nblk, hipStream_t s)
+{
+    const size_t N = (size_t)nx * ny;
+    dect_status st;
+    if ((st = W->u64.ensure(2 * N * 8)) || (st = W->res.ensure(2 * N * 8)) ||
+        (st = W->z.ensure(2 * N * 8)) || (st = W->p0.ensure(2 * N * 8)) ||
+        (st = W->p1.ensure(2 * N * 8)) || (st = W->q.ensure(2 * N * 8)))
+        return st;
+    AttCoef k;
+    k.e1h = P->eta_water_high;
+    k.e2h = P->eta_bone_high;
+    k.e1l = P->eta_water_low;
+    k.e2l = P->eta_bone_low;
+    k.g11 = k.e1h * k.e1h + k.e1l * k.e1l;
+    k.g12 = k.e1h * k.e2h + k.e1l * k.e2l;
+    k.g22 = k.e2h * k.e2h + k.e2l * k.e2l;
+    const double gamma = P->gamma;
+    PcgStatus *stat = (PcgStatus *)W->stat.ptr;
+    double *u = (double *)W->u64.ptr, *res = (double *)W->res.ptr, *z = (double *)W->z.ptr;
+    double *q = (double *)W->q.ptr;
+    double *pbuf[2] = {(double *)W->p0.ptr, (double *)W->p1.ptr};
+    double *rzb[2] = {(double *)W->prz0.ptr, (double *)W->prz1.ptr};
+    hipLaunchKernelGGL(k_apcg_setup, dim3(nblk), dim3(256), 0, s, xh, xl, (const float *)u1,
+                       (const float *)u2, w, gamma, k, u, res, z, pbuf[0], rzb[0],
+                       (double *)W->prr.ptr, (double *)W->pbb.ptr, stat, nx, ny);
+    DECT_HIP(hipGetLastError());
+    int it = 0;
+    const int check_every = 16;
+    for (; it < P->max_iter; ++it) {
+        const double *pold = pbuf[it & 1];
+        double *pnew = pbuf[(it + 1) & 1];
+        hipLaunchKernelGGL(k_apcg_p, dim3(nblk), dim3(256), 0, s, (const double *)z, pold, pnew,
+                           (const double *)rzb[it & 1], (const double *)rzb[(it + 1) & 1],
+                           (const double *)W->prr.ptr, (const double *)W->pbb.ptr, stat, it,
+                           P->tol, nx, ny, nblk);
+        DECT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_apcg_q, dim3(nblk), dim3(256), 0, s, (const double *)pnew, q, w,
+                           gamma, k, (double *)W->ppq.ptr, stat, nx, ny);
+        DECT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_apcg_b, dim3(nblk), dim3(256), 0, s, u, res, z, (const double *)pnew,
+                           (const double *)q, w, gamma, k, (const double *)rzb[it & 1],
+                           (const double *)W->ppq.ptr, rzb[(it + 1) & 1], (double *)W->prr.ptr,
+                           stat, nx, ny, nblk);
+        DECT_HIP(hipGetLastError());
+        if ((it + 1) % check_every == 0) {
+            PcgStatus hs;
+            DECT_HIP(hipMemcpyAsync(&hs, stat, sizeof(hs), hipMemcpyDeviceToHost, s));
+            DECT_HIP(hipStreamSynchronize(s));
+            if (hs.done) {
+                ++it;
+                break;
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_pcg_final, dim3(1), dim3(256), 0, s, (const double *)W->prr.ptr,
+                       (const double *)W->pbb.ptr, stat, it, P->tol, nblk);
+    DECT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_apcg_out, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                       (const double *)u, u1, u2, N);
+    DECT_HIP(hipGetLastError());
+    if (rep) {
+        PcgStatus hs;
+        DECT_HIP(hipMemcpyAsync(&hs, stat, sizeof(hs), hipMemcpyDeviceToHost, s));
+        DECT_HIP(hipStreamSynchronize(s));
+        rep->iters = hs.iters;
+        rep->pcg_residual = hs.relres;
+        rep->objective = 0.0;
+        rep->rel_change = 0.0;
+        rep->status = hs.done == 3 ? DECT_WARN_MAXITER : DECT_OK;
+        if (rep->status == DECT_WARN_MAXITER) {
+            set_error("dect_pls_decompose: PCG reached max_iter above tolerance");
+            return DECT_WARN_MAXITER;
+        }
+    }
+    return DECT_OK;
+}
+
 dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
                           const dect_pls_params *P, const float *ew, float *u1, float *u2,
                           dect_report *rep, hipStream_t s)
@@ -377,6 +680,8 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
         return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose: singular decomposition matrix");
     if (!(P->gamma >= 0.0) || !std::isfinite(P->gamma) || P->max_iter < 0 || !(P->tol >= 0.0))
         return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose: bad gamma/max_iter/tol");
+    if (P->mode != DECT_PLS_IMAGE && P->mode != DECT_PLS_ATTENUATION)
+        return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose: unknown mode");
     std::lock_guard<std::mutex> lk(g_pls_mu);
     PlsWork *W = pls_work();
     const size_t N = (size_t)nx * ny;
@@ -406,6 +711,8 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
         w = (const float *)W->w.ptr;
     }
     PcgStatus *stat = (PcgStatus *)W->stat.ptr;
+    if (P->mode == DECT_PLS_ATTENUATION)
+        return pls_attenuation(nx, ny, xh, xl, P, w, u1, u2, rep, W, nblk, s);
     const float gamma = (float)P->gamma;
     float *pbuf[2] = {(float *)W->p0.ptr, (float *)W->p1.ptr};
     double *rzb[2] = {(double *)W->prz0.ptr, (double *)W->prz1.ptr};

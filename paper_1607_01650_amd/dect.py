@@ -52,7 +52,7 @@ class dect_pls_params(ct.Structure):
     _fields_ = [("eta_water_high", ct.c_double), ("eta_bone_high", ct.c_double),
                 ("eta_water_low", ct.c_double), ("eta_bone_low", ct.c_double),
                 ("gamma", ct.c_double), ("edge_eps", ct.c_double), ("edge_tau", ct.c_double),
-                ("max_iter", ct.c_int32), ("tol", ct.c_double)]
+                ("max_iter", ct.c_int32), ("tol", ct.c_double), ("mode", ct.c_int32)]
 
 
 class dect_report(ct.Structure):
@@ -361,7 +361,7 @@ class AdmBatch:
 
 def pls_params(p: C.PlsParams) -> dect_pls_params:
     return dect_pls_params(p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low,
-                           p.gamma, p.edge_eps, p.edge_tau, p.max_iter, p.tol)
+                           p.gamma, p.edge_eps, p.edge_tau, p.max_iter, p.tol, int(p.mode))
 
 
 def pls_decompose(x_high, x_low, p: C.PlsParams, edge_w=None, report: bool = True):
