@@ -431,12 +431,15 @@ double or_tv(int nx, int ny, const double *x)
  * Out: x_out = f / beta after the last iteration; optional lam_out, z_out
  *      [2][ny][nx]; log [(K+1)][5] rows (J(f^k), alpha^k, |grad f^k - z^k|,
  *      |f^k - f^{k-1}|/|f^{k-1}|, |G^k|) -- the last row holds J(f^K).
+ * nonneg != 0: every f-step is followed by the projection f = max(f, 0)
+ * (images are attenuation maps, non-negative); the BB step is then taken
+ * from the projected step s.
  * Returns the number of iterations run (stops early when tol > 0 and the
  * relative image change drops below tol).
  */
 int or_adm(const or_geom *g, const double *m, double beta, double mu, double rho, double xi,
            int K, double tol, const double *x0, double *x_out, double *lam_out, double *z_out,
-           double *log)
+           double *log, int nonneg)
 {
     const int nx = g->nx, ny = g->ny;
     const size_t N = (size_t)nx * ny, M = (size_t)g->n_views * g->n_bins;
@@ -500,6 +503,8 @@ int or_adm(const or_geom *g, const double *m, double beta, double mu, double rho
         memcpy(fo, f, N * sizeof(double));
         memcpy(ho, h, N * sizeof(double));
         for (size_t i = 0; i < N; ++i) f[i] -= alpha * G[i];
+        if (nonneg)  /* projection onto the non-negative images */
+            for (size_t i = 0; i < N; ++i) f[i] = f[i] > 0.0 ? f[i] : 0.0;
         or_project(g, f, r);
         for (size_t j = 0; j < M; ++j) r[j] -= gs[j];
         or_backproject(g, r, h);
