@@ -85,6 +85,7 @@ class AdmParams:
     beta_low: float = 1.0
     max_iter: int = 50
     tol: float = 0.0
+    nonneg: bool = False  # project every f-step onto f >= 0
 
 
 @dataclasses.dataclass(frozen=True)

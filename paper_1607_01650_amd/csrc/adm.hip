@@ -66,11 +66,156 @@ __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
                                                 const double *__restrict__ p_tv, int nb_tv,
                                                 const double *__restrict__ p_fwd, int nb_fwd,
                                                 double *__restrict__ log, int log_rows,
-                                                double mu, double rho)
+                                                double mu, double rho, int nonneg)
 {
     const int e = blockIdx.x;
     scalar_energy(sc[e], p_tv + (size_t)e * nb_tv * 5, nb_tv, p_fwd + (size_t)e * nb_fwd, nb_fwd,
-                  log, log_rows, e, mu, rho);
+                  log, log_rows, e, mu, rho, nonneg != 0);
+}
+
+// ------------------------------------------------ non-negative variant ---
+// Projected f-step: t = (f + flo) - alpha G, f' = max(t, 0).  The step s =
+// f' - f is kept in FP32 (rounded toward zero where the projection clips, so
+// f + s >= 0) and f advances by exactly that s, so that r + A s stays the
+// residual of f.  s goes to the transposed padded layout (G, in the other
+// layout, is still read by neighbouring threads); partials <s,s>, |f|^2.
+__global__ __launch_bounds__(256) void k_nn_step(float *__restrict__ f,
+                                                 const float *__restrict__ gpad,
+                                                 float *__restrict__ gpadT,
+                                                 const AdmScalars *__restrict__ sc,
+                                                 double *__restrict__ p_ss,
+                                                 double *__restrict__ p_ff, int nx, int ny,
+                                                 int nbi)
+{
+    const int e = blockIdx.y;
+    if (sc[e].stopped) return;
+    const double alpha = sc[e].alpha;
+    const size_t N = (size_t)nx * ny;
+    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
+    float *fe = f + e * N, *fle = f + 2 * N + e * N;
+    double v[2] = {0.0, 0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            const double g = gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e];
+            const double fo = (double)fe[i] + (double)fle[i];
+            const double t = fo - alpha * g;
+            float s32 = t > 0.0 ? (float)(t - fo) : __double2float_rz(-fo);
+            if (fo + (double)s32 < 0.0) s32 = __double2float_rz(-fo);
+            const double fn = fo + (double)s32;
+            const float hi = (float)fn;
+            fe[i] = hi;
+            fle[i] = (float)(fn - (double)hi);
+            gpadT[2 * ((size_t)(c + kPad) * pny + r + kPad) + e] = s32;
+            v[0] += (double)s32 * (double)s32;
+            v[1] += fo * fo;
+        }
+    }
+    __shared__ double tot[2];
+    block_sum<2>(v, tot);
+    if (threadIdx.x == 0) {
+        p_ss[(size_t)e * nbi + blockIdx.x] = tot[0];
+        p_ff[(size_t)e * nbi + blockIdx.x] = tot[1];
+    }
+}
+
+// |grad s|^2 partials (backward differences of Eq. 2) and s copied into the
+// normal padded layout, so that the forward projector reads s in both.
+__global__ __launch_bounds__(256) void k_nn_grad(float *__restrict__ gpad,
+                                                 const float *__restrict__ gpadT,
+                                                 const AdmScalars *__restrict__ sc,
+                                                 double *__restrict__ p_gs, int nx, int ny,
+                                                 int nbi)
+{
+    const int e = blockIdx.y;
+    if (sc[e].stopped) return;
+    const size_t N = (size_t)nx * ny;
+    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
+    auto sT = [&](int r, int c) {
+        return gpadT[2 * ((size_t)(c + kPad) * pny + r + kPad) + e];
+    };
+    double v[1] = {0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            const float si = sT(r, c);
+            const double gx = c >= 1 ? (double)si - (double)sT(r, c - 1) : 0.0;
+            const double gy = r >= 1 ? (double)si - (double)sT(r - 1, c) : 0.0;
+            gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e] = si;
+            v[0] += gx * gx + gy * gy;
+        }
+    }
+    __shared__ double tot[1];
+    block_sum<1>(v, tot);
+    if (threadIdx.x == 0) p_gs[(size_t)e * nbi + blockIdx.x] = tot[0];
+}
+
+// (r + rlo) += (p + plo) = A s in FP64; partial |r|^2.
+__global__ __launch_bounds__(256) void k_nn_resid(float *__restrict__ r,
+                                                  const float *__restrict__ p,
+                                                  const AdmScalars *__restrict__ sc,
+                                                  double *__restrict__ p_rr, int M, int nbs)
+{
+    const int e = blockIdx.y;
+    if (sc[e].stopped) return;
+    const size_t Ms = (size_t)M;
+    float *re = r + e * Ms, *rle = r + 2 * Ms + e * Ms;
+    const float *pe = p + e * Ms, *ple = p + 2 * Ms + e * Ms;
+    double v[1] = {0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
+        if (i < Ms) {
+            const double d = ((double)re[i] + (double)rle[i]) + ((double)pe[i] + (double)ple[i]);
+            const float hi = (float)d;
+            re[i] = hi;
+            rle[i] = (float)(d - (double)hi);
+            v[0] += d * d;
+        }
+    }
+    __shared__ double tot[1];
+    block_sum<1>(v, tot);
+    if (threadIdx.x == 0) p_rr[(size_t)e * nbs + blockIdx.x] = tot[0];
+}
+
+// |r|^2, <s,s>, <s,y> = mu |A s|^2 + rho |grad s|^2 and |s| / |f| from the
+// partials; counts the iteration, marks the deferred multiplier step and
+// applies the relative-change stop rule.
+__global__ __launch_bounds__(256) void k_nn_rr(AdmScalars *__restrict__ sc,
+                                               const double *__restrict__ p_rr, int nbs,
+                                               const double *__restrict__ p_ss,
+                                               const double *__restrict__ p_ff,
+                                               const double *__restrict__ p_gs, int nbi,
+                                               const double *__restrict__ p_as, int nb_fwd,
+                                               double mu, double rho, double tol)
+{
+    const int e = blockIdx.x;
+    AdmScalars &s = sc[e];
+    const bool run = !s.stopped;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (run) {
+        for (int i = threadIdx.x; i < nbs; i += 256) v[0] += p_rr[(size_t)e * nbs + i];
+        for (int i = threadIdx.x; i < nbi; i += 256) {
+            v[1] += p_ss[(size_t)e * nbi + i];
+            v[2] += p_ff[(size_t)e * nbi + i];
+            v[3] += p_gs[(size_t)e * nbi + i];
+        }
+        for (int i = threadIdx.x; i < nb_fwd; i += 256) v[4] += p_as[(size_t)e * nb_fwd + i];
+    }
+    __shared__ double tot[5];
+    block_sum<5>(v, tot);
+    if (run && threadIdx.x == 0) {
+        const double ss = tot[1], ff = tot[2];
+        s.rr = tot[0];
+        s.ss = ss;
+        s.sy = mu * tot[4] + rho * tot[3];
+        s.relchg = ff > 0.0 ? sqrt(ss) / sqrt(ff) : (ss > 0.0 ? INFINITY : 0.0);
+        s.pending = 1;
+        s.iter += 1;
+        if (tol > 0.0 && s.relchg < tol) s.stopped = 1;
+    }
+    __syncthreads();
 }
 
 // blocks [0, nbi): f -= alpha G (image); blocks [nbi, nbi+nbs): r -= alpha p
@@ -206,7 +351,9 @@ struct dect_adm_state {
     double mu = 0, rho = 0, xi = 0, bh = 1, bl = 1;
     int nvg = 1, nb_tv = 0, nb_fwd = 0, nbi = 0, nbs = 0, nb_img = 0;
     dect::DevBuf f, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, sc, logbuf,
-        p_tvo;
+        p_tvo, p_ss, p_ff, p_gs;
+    bool nonneg = false;        // the run projects every f-step onto f >= 0
+    int graph_nonneg = -1;
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
     double graph_tol = -1.0;
@@ -290,6 +437,9 @@ static AdmPtrs ptrs_of(dect_adm_state *S)
     P.p_fwd = (double *)S->p_fwd.ptr;
     P.p_rr = (double *)S->p_rr.ptr;
     P.p_tvo = (double *)S->p_tvo.ptr;
+    P.p_ss = (double *)S->p_ss.ptr;
+    P.p_ff = (double *)S->p_ff.ptr;
+    P.p_gs = (double *)S->p_gs.ptr;
     P.log = (double *)S->logbuf.ptr;
     P.log_rows = (int)(S->logbuf.bytes / 32);
     P.sc = (AdmScalars *)S->sc.ptr;
@@ -322,6 +472,9 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
         (st = S->p_fwd.ensure((size_t)2 * S->nb_fwd * 8)) ||
         (st = S->p_rr.ensure((size_t)2 * S->nbs * 8)) ||
         (st = S->p_tvo.ensure((size_t)2 * S->nbi * 8)) ||
+        (st = S->p_ss.ensure((size_t)2 * S->nbi * 8)) ||
+        (st = S->p_ff.ensure((size_t)2 * S->nbi * 8)) ||
+        (st = S->p_gs.ensure((size_t)2 * S->nbi * 8)) ||
         (st = S->adjpart.ensure(std::max<size_t>(1, adj_partial_floats(t, 2)) * 4)) ||
         (st = S->sc.ensure(2 * sizeof(AdmScalars))))
         return st;
@@ -354,8 +507,36 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     if (st) return st;
     hipLaunchKernelGGL(k_scalar, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_tv.ptr,
                        S->nb_tv, (const double *)S->p_fwd.ptr, S->nb_fwd,
-                       (double *)S->logbuf.ptr, (int)(S->logbuf.bytes / 32), S->mu, S->rho);
+                       (double *)S->logbuf.ptr, (int)(S->logbuf.bytes / 32), S->mu, S->rho,
+                       S->nonneg ? 1 : 0);
     DECT_HIP(hipGetLastError());
+    if (S->nonneg) {
+        // projected step s, |grad s|^2, p = A s, r += p, then the step's sums
+        hipLaunchKernelGGL(k_nn_step, dim3(S->nbi, 2), dim3(256), 0, s, (float *)S->f.ptr,
+                           (const float *)S->gpad.ptr, (float *)S->gpadT.ptr,
+                           (const AdmScalars *)sc, (double *)S->p_ss.ptr, (double *)S->p_ff.ptr,
+                           nx, ny, S->nbi);
+        DECT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_nn_grad, dim3(S->nbi, 2), dim3(256), 0, s, (float *)S->gpad.ptr,
+                           (const float *)S->gpadT.ptr, (const AdmScalars *)sc,
+                           (double *)S->p_gs.ptr, nx, ny, S->nbi);
+        DECT_HIP(hipGetLastError());
+        if ((st = launch_fwd(t, (const float *)S->gpad.ptr, (const float *)S->gpadT.ptr, p, 2,
+                             1.0f, (double *)S->p_fwd.ptr, s, nullptr, nullptr, 0.0, 0.0,
+                             p + 2 * (size_t)M)))
+            return st;
+        hipLaunchKernelGGL(k_nn_resid, dim3(S->nbs, 2), dim3(256), 0, s, (float *)S->r.ptr,
+                           (const float *)p, (const AdmScalars *)sc, (double *)S->p_rr.ptr, M,
+                           S->nbs);
+        DECT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_nn_rr, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_rr.ptr,
+                           S->nbs, (const double *)S->p_ss.ptr, (const double *)S->p_ff.ptr,
+                           (const double *)S->p_gs.ptr, S->nbi, (const double *)S->p_fwd.ptr,
+                           S->nb_fwd, S->mu, S->rho, tol);
+        DECT_HIP(hipGetLastError());
+        return launch_adj(t, (const float *)S->r.ptr, nullptr, (float *)S->adjpart.ptr, 2,
+                          (float)S->mu, s, S->nvg);
+    }
     hipLaunchKernelGGL(k_update, dim3(S->nbi + S->nbs, 2), dim3(256), 0, s, (float *)S->f.ptr,
                        (const float *)S->gpad.ptr, (float *)S->r.ptr, (const float *)S->p.ptr,
                        (double *)S->p_rr.ptr, sc, nx, ny, M, S->nbi, S->nbs);
@@ -375,6 +556,7 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     S->xi = P->xi;
     S->bh = P->beta_high;
     S->bl = P->beta_low;
+    S->nonneg = (P->flags & DECT_NONNEG) != 0;
     S->parity = 0;
     dect_status st =
         adm_init(*S->t, ptrs_of(S), S->nvg, mh, ml, S->mu, S->bh, S->bl, x0h, x0l, s);
@@ -444,7 +626,8 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         if ((st = get_tables(g, &t))) return st;
         if (t != S->t) return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: state was made for another geometry");
         if (S->started && (S->mu != P->mu || S->rho != P->rho || S->xi != P->xi ||
-                           S->bh != P->beta_high || S->bl != P->beta_low))
+                           S->bh != P->beta_high || S->bl != P->beta_low ||
+                           S->nonneg != ((P->flags & DECT_NONNEG) != 0)))
             return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: parameters differ from the state's run");
     }
     const int K = P->max_iter;
@@ -460,11 +643,13 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     // the log buffer and tol are baked into the graph's kernel arguments:
     // rebuild only when they change
     if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
-                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol)) {
+                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol ||
+                   S->graph_nonneg != (int)S->nonneg)) {
         if ((st = build_graph(S, P->tol))) return st;
         S->graph_log = S->logbuf.ptr;
         S->graph_log_bytes = S->logbuf.bytes;
         S->graph_tol = P->tol;
+        S->graph_nonneg = (int)S->nonneg;
     }
     int k = 0;
     if (S->parity == 1 && K > 0) {  // realign so the graph starts on parity 0

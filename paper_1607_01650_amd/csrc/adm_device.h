@@ -28,6 +28,7 @@ struct AdmScalars {
     double J;       // last logged objective
     double relchg;  // last relative image change
     double beta;    // Eq. 3 weight of this energy
+    double ss, sy;  // non-negative variant: <s,s> and <s,y> of the last projected step
     int32_t has_prev, stopped, nonfinite_iter, pending;
     int64_t iter;      // iterations completed
     int64_t log_base;  // iteration index of log row 0 for this call
@@ -74,6 +75,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
 struct AdmPtrs {
     float *f, *flo, *r, *rlo, *p, *plo, *lam, *z, *gpad, *gpadT, *adjpart;
     double *p_tv, *p_fwd, *p_rr, *p_tvo, *log;
+    double *p_ss, *p_ff, *p_gs;  // non-negative variant: [2][nbi] step partials
     int log_rows;
     AdmScalars *sc;
     int nb_tv, nb_fwd, nbi, nbs;
@@ -260,7 +262,7 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
 __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__restrict__ pt,
                                               int nb_tv, const double *__restrict__ pf, int nb_fwd,
                                               double *__restrict__ log, int log_rows, int col,
-                                              double mu, double rho)
+                                              double mu, double rho, bool nonneg = false)
 {
     __shared__ double tot[6];
     const bool run = !s.stopped;
@@ -295,6 +297,8 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
         const double den = mu * pp + rho * gradg;
         double c = den > 0.0 ? gg / den : (s.has_prev ? s.c_prev : 0.0);
         double alpha = s.has_prev ? s.c_prev : c;
+        // projected steps: BB1 <s,s>/<s,y> of the last step (kept when <s,y> <= 0)
+        if (nonneg && s.has_prev) alpha = s.sy > 0.0 ? s.ss / s.sy : s.alpha;
         const double J = tvf + 0.5 * mu * s.rr;
         const double relchg = ff > 0.0 ? alpha * sqrt(gg) / sqrt(ff) : (gg > 0.0 ? INFINITY : 0.0);
         const int64_t k = s.iter;
@@ -307,7 +311,7 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
         s.alpha = alpha;
         s.c_prev = c;
         s.has_prev = 1;
-        s.relchg = relchg;
+        if (!nonneg) s.relchg = relchg;  // else set from the projected step
         if (!isfinite(J) || !isfinite(alpha) || !isfinite(gg) || !isfinite(pp)) {
             s.nonfinite_iter = (int32_t)(k + 1);
             s.stopped = 1;

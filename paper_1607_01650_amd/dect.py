@@ -25,6 +25,7 @@ DECT_ERR_HIP = 3
 DECT_ERR_NONFINITE = 4
 DECT_WARN_MAXITER = 5
 DECT_WARM_START = 1
+DECT_NONNEG = 2
 
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "GEOMETRY", 3: "HIP", 4: "NONFINITE", 5: "WARN_MAXITER"}
 
@@ -280,6 +281,8 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
         xh.copy_(x0[0])
         xl.copy_(x0[1])
         flags |= DECT_WARM_START
+    if getattr(p, "nonneg", False):
+        flags |= DECT_NONNEG
     _dev(xh, "x_high", (geom.ny, geom.nx))
     _dev(xl, "x_low", (geom.ny, geom.nx))
     log = None
@@ -309,7 +312,9 @@ class AdmBatch:
         self._g = [GeomArg(g) for g in geoms]
         garr = (dect_geometry * n)(*[a.s for a in self._g])
         parr = (dect_adm_params * n)(*[dect_adm_params(p.mu, p.rho, p.xi, p.beta_high,
-                                                       p.beta_low, p.max_iter, p.tol, 0, None)
+                                                       p.beta_low, p.max_iter, p.tol,
+                                                       DECT_NONNEG if getattr(p, "nonneg", False)
+                                                       else 0, None)
                                        for p in params])
         h = ct.c_void_p(None)
         _check(lib().dect_batch_create(garr, parr, n, ct.byref(h)), "dect_batch_create")
