@@ -109,6 +109,8 @@ def main():
                     help="timed ADM iterations of the Siddon-model entry (0: skip)")
     ap.add_argument("--no-fbp", action="store_true",
                     help="skip the filtered back-projection comparator entry")
+    ap.add_argument("--nonneg-steps", type=int, default=100,
+                    help="timed ADM iterations of the non-negative variant entry (0: skip)")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -205,6 +207,7 @@ def main():
     siddon = (siddon_extra(args.siddon_steps, args.kernel_launches)
               if args.siddon_steps > 0 else None)
     fbp = None if args.no_fbp else fbp_extra(max(1, args.kernel_launches))
+    nonneg = nonneg_extra(args.nonneg_steps) if args.nonneg_steps > 0 else None
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -245,7 +248,7 @@ def main():
                   "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
                   "pls_attenuation_ms": round(pls_att_ms, 3), "pls_attenuation_iters": arep.iters,
                   "warm_start": warm, "batched": batched, "unrolled": unrolled,
-                  "siddon": siddon, "fbp": fbp},
+                  "siddon": siddon, "fbp": fbp, "nonneg": nonneg},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
@@ -299,6 +302,37 @@ def siddon_extra(steps: int, launches: int):
             "iters_per_s": round(1e3 / adm_ms, 2), "ms_per_iteration": round(adm_ms, 4),
             "steps": steps, "backprojection_us_2energies": round(adj_ms * 1e3, 2),
             "fwd_projection_us_2energies": round(fwd_ms * 1e3, 2)}
+
+
+def nonneg_extra(steps: int):
+    """The metric workload with every f-step projected onto f >= 0
+    (DECT_NONNEG): ADM iterations/s (one more projection per iteration)."""
+    import torch
+
+    from paper_1607_01650_amd import configs as C, dect, phantom as P
+
+    g = C.METRIC
+    s = P.make_slice(g, 0)
+    p = dataclasses.replace(C.default_adm_params(g, steps), nonneg=True)
+    mh = torch.as_tensor(s.sino[0], dtype=torch.float32).cuda()
+    ml = torch.as_tensor(s.sino[1], dtype=torch.float32).cuda()
+    xh = torch.empty((g.ny, g.nx), device="cuda")
+    xl = torch.empty_like(xh)
+    sp = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ev = HipEvents()
+    state = dect.AdmState(g)
+    dect.adm_tv(mh, ml, g, dataclasses.replace(p, max_iter=5), state=state, out=(xh, xl))
+    torch.cuda.synchronize()
+    e0, e1 = ev.event(), ev.event()
+    ev.record(e0, sp)
+    dect.adm_tv(mh, ml, g, p, state=state, out=(xh, xl))
+    ev.record(e1, sp)
+    torch.cuda.synchronize()
+    ms = ev.ms(e0, e1) / steps
+    state.close()
+    return {"workload": "adm_tv_512x512_360views_736bins_2energies, f >= 0",
+            "iters_per_s": round(1e3 / ms, 2), "ms_per_iteration": round(ms, 4),
+            "steps": steps, "zero_pixels": int((xh == 0).sum().item() + (xl == 0).sum().item())}
 
 
 def fbp_extra(launches: int):
