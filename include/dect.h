@@ -82,8 +82,9 @@ enum {
     DECT_NONNEG = 2      /* project every f-step onto f >= 0 (attenuation maps are
                             non-negative); the BB1 step is then taken from the
                             projected step s: <s,s> / (mu |A s|^2 + rho |grad s|^2),
-                            kept when the denominator is not positive.  One more
-                            projection per iteration. */
+                            kept when the denominator is not positive.  The
+                            step's own projection A s replaces A G after the
+                            first iteration. */
 };
 typedef struct {
     double mu;        /* data-fidelity weight of Eq. 4 */

@@ -353,6 +353,7 @@ struct dect_adm_state {
     dect::DevBuf f, r, p, lam, z, gpad, gpadT, p_tv, p_fwd, p_rr, adjpart, sc, logbuf,
         p_tvo, p_ss, p_ff, p_gs;
     bool nonneg = false;        // the run projects every f-step onto f >= 0
+    bool fresh = false;         // no iteration launched since the run's set-up
     int graph_nonneg = -1;
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
@@ -483,7 +484,8 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
 
 // Launch one iteration; `par` selects the lambda/z buffers holding the
 // current values.
-static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream_t s)
+static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream_t s,
+                               bool first = false)
 {
     const GeomTables &t = *S->t;
     const int nx = t.key.nx, ny = t.key.ny;
@@ -501,10 +503,15 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
                        nx, ny, (float)S->rho, (float)S->xi);
     DECT_HIP(hipGetLastError());
     float *p = (float *)S->p.ptr;
-    dect_status st = launch_fwd(t, (const float *)S->gpad.ptr, (const float *)S->gpadT.ptr, p, 2,
-                                1.0f, (double *)S->p_fwd.ptr, s, nullptr, nullptr, 0.0, 0.0,
-                                p + 2 * (size_t)M);
-    if (st) return st;
+    dect_status st = DECT_OK;
+    // A G: the step and the residual update of the plain iteration; with the
+    // projection only the first (Cauchy) step needs it
+    if (!S->nonneg || first) {
+        st = launch_fwd(t, (const float *)S->gpad.ptr, (const float *)S->gpadT.ptr, p, 2, 1.0f,
+                        (double *)S->p_fwd.ptr, s, nullptr, nullptr, 0.0, 0.0,
+                        p + 2 * (size_t)M);
+        if (st) return st;
+    }
     hipLaunchKernelGGL(k_scalar, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_tv.ptr,
                        S->nb_tv, (const double *)S->p_fwd.ptr, S->nb_fwd,
                        (double *)S->logbuf.ptr, (int)(S->logbuf.bytes / 32), S->mu, S->rho,
@@ -557,6 +564,7 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     S->bh = P->beta_high;
     S->bl = P->beta_low;
     S->nonneg = (P->flags & DECT_NONNEG) != 0;
+    S->fresh = true;
     S->parity = 0;
     dect_status st =
         adm_init(*S->t, ptrs_of(S), S->nvg, mh, ml, S->mu, S->bh, S->bl, x0h, x0l, s);
@@ -652,7 +660,13 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         S->graph_nonneg = (int)S->nonneg;
     }
     int k = 0;
-    if (S->parity == 1 && K > 0) {  // realign so the graph starts on parity 0
+    if (S->fresh && S->nonneg && K > 0) {  // the first projected step starts from A G
+        if ((st = launch_iter(S, S->parity, P->tol, s, true))) return st;
+        S->parity ^= 1;
+        ++k;
+    }
+    if (k > 0 || K > 0) S->fresh = false;
+    if (S->parity == 1 && k < K) {  // realign so the graph starts on parity 0
         if ((st = launch_iter(S, 1, P->tol, s))) return st;
         S->parity = 0;
         ++k;
