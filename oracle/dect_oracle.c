@@ -769,3 +769,114 @@ int or_pcg_att(int nx, int ny, const double *er, const double *ed, double e1h, d
     free(c); free(u); free(res); free(z); free(p); free(q); free(lap); free(dg);
     return it;
 }
+
+/*
+ * ADM-TV of both energies with the TV coupled across them: the norm of
+ * Eq. 2 taken over the 4-vector (grad f_high, grad f_low) at every pixel,
+ * so the z-step (Eq. 8) shrinks the two energies' 2-vectors together:
+ * z_e = max(|v| - 1/rho, 0) v_e / |v| with |v|^2 = |v_high|^2 + |v_low|^2.
+ * Given z and lambda the f-subproblem still separates by energy, so each
+ * energy keeps its own gradient step (Eq. 9), BB step and multiplier
+ * (Eq. 7), exactly as in or_adm.  Fixed iteration count.
+ * In:  m [2][V][B], beta[2], x0 [2][ny][nx] or NULL.
+ * Out: x_out [2][ny][nx]; log [2][(K+1)][2] rows (J part, alpha^k) per
+ *      energy: energy 0 carries the joint TV, energy 1 none, each its own
+ *      mu/2 |r_e|^2, so that the two columns sum to the objective.
+ */
+void or_adm_coupled(const or_geom *g, const double *m, const double *beta, double mu, double rho,
+                    double xi, int K, const double *x0, double *x_out, double *log, int nonneg)
+{
+    const int nx = g->nx, ny = g->ny;
+    const size_t N = (size_t)nx * ny, M = (size_t)g->n_views * g->n_bins;
+    double *f[2], *fo[2], *G[2], *h[2], *ho[2], *lx[2], *ly[2], *zx[2], *zy[2], *dx[2], *dy[2];
+    double *wx = calloc(N, sizeof(double)), *wy = calloc(N, sizeof(double));
+    double *t1 = calloc(N, sizeof(double)), *s = calloc(N, sizeof(double));
+    double *y = calloc(N, sizeof(double)), *p = calloc(M, sizeof(double));
+    double *gs[2], *r[2], alpha[2] = {0.0, 0.0};
+    for (int e = 0; e < 2; ++e) {
+        f[e] = calloc(N, sizeof(double)); fo[e] = calloc(N, sizeof(double));
+        G[e] = calloc(N, sizeof(double)); h[e] = calloc(N, sizeof(double));
+        ho[e] = calloc(N, sizeof(double)); lx[e] = calloc(N, sizeof(double));
+        ly[e] = calloc(N, sizeof(double)); zx[e] = calloc(N, sizeof(double));
+        zy[e] = calloc(N, sizeof(double)); dx[e] = calloc(N, sizeof(double));
+        dy[e] = calloc(N, sizeof(double)); gs[e] = calloc(M, sizeof(double));
+        r[e] = calloc(M, sizeof(double));
+        for (size_t j = 0; j < M; ++j) gs[e][j] = beta[e] * m[e * M + j];
+        if (x0)
+            for (size_t i = 0; i < N; ++i) f[e][i] = beta[e] * x0[e * N + i];
+        or_project(g, f[e], r[e]);
+        for (size_t j = 0; j < M; ++j) r[e][j] -= gs[e][j];
+        or_backproject(g, r[e], h[e]);
+        for (size_t i = 0; i < N; ++i) h[e][i] *= mu;
+    }
+    int k;
+    for (k = 0; k <= K; ++k) {
+        for (int e = 0; e < 2; ++e) or_grad(nx, ny, f[e], dx[e], dy[e]);
+        double tvj = 0.0;
+        for (size_t i = 0; i < N; ++i)
+            tvj += sqrt(dx[0][i] * dx[0][i] + dy[0][i] * dy[0][i] + dx[1][i] * dx[1][i] +
+                        dy[1][i] * dy[1][i]);
+        for (int e = 0; e < 2; ++e) {
+            double *row = log + ((size_t)e * (K + 1) + k) * 2;
+            row[0] = (e == 0 ? tvj : 0.0) + 0.5 * mu * dot(M, r[e], r[e]);
+            row[1] = alpha[e];
+        }
+        if (k == K) break;
+        /* joint z-step */
+        for (size_t i = 0; i < N; ++i) {
+            double v[4] = {dx[0][i] - lx[0][i] / rho, dy[0][i] - ly[0][i] / rho,
+                           dx[1][i] - lx[1][i] / rho, dy[1][i] - ly[1][i] / rho};
+            double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
+            double sh = n > 1.0 / rho ? (n - 1.0 / rho) / n : 0.0;
+            zx[0][i] = sh * v[0];
+            zy[0][i] = sh * v[1];
+            zx[1][i] = sh * v[2];
+            zy[1][i] = sh * v[3];
+        }
+        for (int e = 0; e < 2; ++e) {
+            /* G (Eq. 9) */
+            for (size_t i = 0; i < N; ++i) {
+                wx[i] = rho * (dx[e][i] - zx[e][i]) - lx[e][i];
+                wy[i] = rho * (dy[e][i] - zy[e][i]) - ly[e][i];
+            }
+            or_gradT(nx, ny, wx, wy, G[e]);
+            for (size_t i = 0; i < N; ++i) G[e][i] += h[e][i];
+            if (k == 0) {
+                or_project(g, G[e], p);
+                or_grad(nx, ny, G[e], wx, wy);
+                double gg = dot(N, G[e], G[e]);
+                double den = mu * dot(M, p, p) + rho * (dot(N, wx, wx) + dot(N, wy, wy));
+                alpha[e] = den > 0.0 ? gg / den : 0.0;
+                log[((size_t)e * (K + 1) + k) * 2 + 1] = alpha[e];
+            }
+            memcpy(fo[e], f[e], N * sizeof(double));
+            memcpy(ho[e], h[e], N * sizeof(double));
+            for (size_t i = 0; i < N; ++i) f[e][i] -= alpha[e] * G[e][i];
+            if (nonneg)
+                for (size_t i = 0; i < N; ++i) f[e][i] = f[e][i] > 0.0 ? f[e][i] : 0.0;
+            or_project(g, f[e], r[e]);
+            for (size_t j = 0; j < M; ++j) r[e][j] -= gs[e][j];
+            or_backproject(g, r[e], h[e]);
+            for (size_t i = 0; i < N; ++i) h[e][i] *= mu;
+            for (size_t i = 0; i < N; ++i) s[i] = f[e][i] - fo[e][i];
+            or_grad(nx, ny, s, wx, wy);
+            or_gradT(nx, ny, wx, wy, t1);
+            for (size_t i = 0; i < N; ++i) y[i] = (h[e][i] - ho[e][i]) + rho * t1[i];
+            double ss = dot(N, s, s), sy = dot(N, s, y);
+            if (sy > 0.0) alpha[e] = ss / sy;
+            /* multiplier step (Eq. 7) */
+            or_grad(nx, ny, f[e], wx, wy);
+            for (size_t i = 0; i < N; ++i) {
+                lx[e][i] -= xi * (wx[i] - zx[e][i]);
+                ly[e][i] -= xi * (wy[i] - zy[e][i]);
+            }
+        }
+    }
+    for (int e = 0; e < 2; ++e)
+        for (size_t i = 0; i < N; ++i) x_out[e * N + i] = f[e][i] / beta[e];
+    for (int e = 0; e < 2; ++e) {
+        free(f[e]); free(fo[e]); free(G[e]); free(h[e]); free(ho[e]); free(lx[e]); free(ly[e]);
+        free(zx[e]); free(zy[e]); free(dx[e]); free(dy[e]); free(gs[e]); free(r[e]);
+    }
+    free(wx); free(wy); free(t1); free(s); free(y); free(p);
+}

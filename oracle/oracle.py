@@ -72,6 +72,7 @@ def lib():
         L.or_pcg_att.argtypes = [ct.c_int, ct.c_int, pd, pd, d, d, d, d, d, pd, pd, pd, pd,
                                  ct.c_int, d, pd]
         L.or_pcg_att.restype = ct.c_int
+        L.or_adm_coupled.argtypes = [P(_Geom), pd, pd, d, d, d, ct.c_int, pd, pd, pd, ct.c_int]
         _lib = L
     return _lib
 
@@ -200,6 +201,23 @@ def adm(g, m: np.ndarray, beta: float, mu: float, rho: float, xi: float, iters: 
                      int(iters), float(tol), _p(x0c), _p(x), _p(lam), _p(z), _p(log),
                      1 if nonneg else 0)
     return AdmResult(x, lam, z, log, int(k))
+
+
+def adm_coupled(g, m_high, m_low, beta_high: float, beta_low: float, mu: float, rho: float,
+                xi: float, iters: int, x0=None, nonneg: bool = False):
+    """ADM-TV of both energies with the TV coupled across them (joint z-step).
+    Returns (x [2][ny][nx], J [iters+1][2], alpha [iters+1][2]); energy 0's J
+    column carries the joint TV, so the columns sum to the objective."""
+    og = _og(g)
+    m = np.ascontiguousarray(np.stack([_f64(m_high).reshape(og.n_views, og.n_bins),
+                                       _f64(m_low).reshape(og.n_views, og.n_bins)]))
+    beta = np.array([beta_high, beta_low], dtype=np.float64)
+    x0c = None if x0 is None else np.ascontiguousarray(np.stack([_f64(x0[0]), _f64(x0[1])]))
+    x = np.empty((2, og.ny, og.nx))
+    log = np.zeros((2, iters + 1, 2))
+    lib().or_adm_coupled(ct.byref(og.s), _p(m), _p(beta), float(mu), float(rho), float(xi),
+                         int(iters), _p(x0c), _p(x), _p(log), 1 if nonneg else 0)
+    return x, log[:, :, 0].T.copy(), log[:, :, 1].T.copy()
 
 
 def dinv(xh, xl, eta_water_high, eta_bone_high, eta_water_low, eta_bone_low):
