@@ -79,12 +79,17 @@ typedef struct {
 /* ADM-TV parameters (Eqs. 3-10 and Sec. 2.4). */
 enum {
     DECT_WARM_START = 1, /* start from d_x_* instead of zero images */
-    DECT_NONNEG = 2      /* project every f-step onto f >= 0 (attenuation maps are
+    DECT_NONNEG = 2,     /* project every f-step onto f >= 0 (attenuation maps are
                             non-negative); the BB1 step is then taken from the
                             projected step s: <s,s> / (mu |A s|^2 + rho |grad s|^2),
                             kept when the denominator is not positive.  The
                             step's own projection A s replaces A G after the
                             first iteration. */
+    DECT_COUPLED_TV = 4  /* the TV norm of Eq. 2 over the 4-vector of both energies'
+                            gradients (one joint z-step; each energy keeps its own
+                            f-step and BB step); log column J_high then holds the
+                            joint TV and J_low none, so the two sum to the
+                            objective.  Needs tol = 0 (fixed iteration count). */
 };
 typedef struct {
     double mu;        /* data-fidelity weight of Eq. 4 */
@@ -95,7 +100,7 @@ typedef struct {
     int32_t max_iter; /* iterations to run (>= 0) */
     double tol;       /* stop once |f^{k+1}-f^k| / |f^k| < tol for both
                          energies (0 = run max_iter iterations) */
-    int32_t flags;    /* DECT_WARM_START, DECT_NONNEG */
+    int32_t flags;    /* DECT_WARM_START, DECT_NONNEG, DECT_COUPLED_TV */
     double *log;      /* host [max_iter+1][4] or NULL: per energy-pair row
                          {J_high(f^k), J_low(f^k), alpha_high^k, alpha_low^k};
                          filling it synchronises the stream */
@@ -224,7 +229,7 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  * spans all slices, replayed from a hipGraph.  Starts from zero images.
  * geoms/params: host arrays [n] (params[i].max_iter and DECT_WARM_START are ignored);
  *   every geometry must use DECT_JOSEPH and no params[i].flags may hold
- *   DECT_NONNEG (else DECT_ERR_INVALID_ARG).
+ *   DECT_NONNEG or DECT_COUPLED_TV (else DECT_ERR_INVALID_ARG).
  * d_m_high, d_m_low, d_x_high, d_x_low: host arrays [n] of device pointers
  *   to slice i's sinograms [V_i][B_i] and output images [ny_i][nx_i].
  * objective: NULL or host [n], filled after synchronising the stream with

@@ -86,6 +86,7 @@ class AdmParams:
     max_iter: int = 50
     tol: float = 0.0
     nonneg: bool = False  # project every f-step onto f >= 0
+    coupled_tv: bool = False  # TV over both energies' gradients jointly (tol must be 0)
 
 
 @dataclasses.dataclass(frozen=True)

@@ -29,6 +29,7 @@ namespace dect {
 namespace {
 
 // ------------------------------------------------------------- kernels ---
+template <bool COUPLED>
 __global__ __launch_bounds__(256) void k_tv_fused(
     const float *__restrict__ f, const float *__restrict__ hpart, int nvg, float mu,
     const float *__restrict__ lam_in,
@@ -58,7 +59,19 @@ __global__ __launch_bounds__(256) void k_tv_fused(
              f + 2 * N + e * N,
              2 * nvg,
              mu};
-    tv_tile(ty * kTY, tx * kTX, m, partial + (size_t)tile * 5, sc[e].pending != 0, nx, ny, rho, xi);
+    if constexpr (COUPLED) {
+        const int o = 1 - e;
+        m.f2 = f + o * N;
+        m.flo2 = f + 2 * N + o * N;
+        m.lxi2 = lam_in + (2 * o) * N;
+        m.lyi2 = lam_in + (2 * o + 1) * N;
+        m.zxi2 = z_in + (2 * o) * N;
+        m.zyi2 = z_in + (2 * o + 1) * N;
+        m.pending2 = sc[o].pending != 0;
+        m.record_tv = e == 0;
+    }
+    tv_tile<COUPLED>(ty * kTY, tx * kTX, m, partial + (size_t)tile * 5, sc[e].pending != 0, nx,
+                     ny, rho, xi);
 }
 
 // One block per energy.  nb_tv/nb_fwd: partial counts per energy.
@@ -283,21 +296,35 @@ __global__ void k_set_log_base(AdmScalars *__restrict__ sc)
 }
 
 // TV(f) per block for the final objective.
+// (coupled: the joint TV of both energies in energy 0's partials, none in
+// energy 1's)
 __global__ __launch_bounds__(256) void k_tv_only(const float *__restrict__ f,
-                                                 double *__restrict__ partial, int nx, int ny)
+                                                 double *__restrict__ partial, int nx, int ny,
+                                                 int coupled)
 {
     const int e = blockIdx.y;
     const size_t N = (size_t)nx * ny;
     double v[1] = {0.0};
+    const float *fl = f + 2 * N;
+    auto grad = [&](int q, size_t i, int r, int c, float &dx, float &dy) {
+        float fc = f[q * N + i], lc = fl[q * N + i];
+        dx = c >= 1 ? (fc - f[q * N + i - 1]) + (lc - fl[q * N + i - 1]) : 0.f;
+        dy = r >= 1 ? (fc - f[q * N + i - nx]) + (lc - fl[q * N + i - nx]) : 0.f;
+    };
     for (int j = 0; j < 4; ++j) {
         size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
         if (i < N) {
             int r = (int)(i / nx), c = (int)(i % nx);
-            const float *fl = f + 2 * N;
-            float fc = f[e * N + i], lc = fl[e * N + i];
-            float dx = c >= 1 ? (fc - f[e * N + i - 1]) + (lc - fl[e * N + i - 1]) : 0.f;
-            float dy = r >= 1 ? (fc - f[e * N + i - nx]) + (lc - fl[e * N + i - nx]) : 0.f;
-            v[0] += (double)sqrtf(dx * dx + dy * dy);
+            float dx, dy;
+            grad(e, i, r, c, dx, dy);
+            if (!coupled) {
+                v[0] += (double)sqrtf(dx * dx + dy * dy);
+            } else if (e == 0) {
+                float dx2, dy2;
+                grad(1, i, r, c, dx2, dy2);
+                const float ta = dx * dx + dy * dy, tb = dx2 * dx2 + dy2 * dy2;
+                v[0] += (double)sqrtf(ta + tb);
+            }
         }
     }
     __shared__ double tot[1];
@@ -354,6 +381,8 @@ struct dect_adm_state {
         p_tvo, p_ss, p_ff, p_gs;
     bool nonneg = false;        // the run projects every f-step onto f >= 0
     bool fresh = false;         // no iteration launched since the run's set-up
+    bool coupled = false;       // the run couples the TV of the two energies
+    int graph_coupled = -1;
     int graph_nonneg = -1;
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
@@ -404,14 +433,14 @@ dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s)
 
 // x = f / beta and the final objective J(f^K) into the scalars and the log.
 dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
-                       double bh, double bl, hipStream_t s)
+                       double bh, double bl, hipStream_t s, bool coupled)
 {
     const size_t N = (size_t)t.key.nx * t.key.ny;
     dim3 go((unsigned)((N + 255) / 256), 2);
     hipLaunchKernelGGL(k_output, go, dim3(256), 0, s, (const float *)P.f, xh, xl, bh, bl, N);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_tv_only, dim3(P.nbi, 2), dim3(256), 0, s, (const float *)P.f, P.p_tvo,
-                       t.key.nx, t.key.ny);
+                       t.key.nx, t.key.ny, coupled ? 1 : 0);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_final_J, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_tvo, P.nbi,
                        P.log, P.log_rows, mu);
@@ -496,11 +525,11 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     float *z_in = z + (size_t)par * 4 * N, *z_out = z + (size_t)(1 - par) * 4 * N;
     AdmScalars *sc = (AdmScalars *)S->sc.ptr;
     dim3 gtv((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY, 2);
-    hipLaunchKernelGGL(k_tv_fused, gtv, dim3(256), 0, s, (const float *)S->f.ptr,
-                       (const float *)S->adjpart.ptr, S->nvg, (float)S->mu, lam_in, z_in,
-                       lam_out, z_out,
-                       (float *)S->gpad.ptr, (float *)S->gpadT.ptr, (double *)S->p_tv.ptr, sc,
-                       nx, ny, (float)S->rho, (float)S->xi);
+    hipLaunchKernelGGL(S->coupled ? k_tv_fused<true> : k_tv_fused<false>, gtv, dim3(256), 0, s,
+                       (const float *)S->f.ptr, (const float *)S->adjpart.ptr, S->nvg,
+                       (float)S->mu, lam_in, z_in, lam_out, z_out, (float *)S->gpad.ptr,
+                       (float *)S->gpadT.ptr, (double *)S->p_tv.ptr, sc, nx, ny, (float)S->rho,
+                       (float)S->xi);
     DECT_HIP(hipGetLastError());
     float *p = (float *)S->p.ptr;
     dect_status st = DECT_OK;
@@ -564,6 +593,7 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     S->bh = P->beta_high;
     S->bl = P->beta_low;
     S->nonneg = (P->flags & DECT_NONNEG) != 0;
+    S->coupled = (P->flags & DECT_COUPLED_TV) != 0;
     S->fresh = true;
     S->parity = 0;
     dect_status st =
@@ -610,6 +640,8 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         !(P->beta_low > 0) || P->max_iter < 0 || !(P->tol >= 0) || !std::isfinite(P->mu) ||
         !std::isfinite(P->rho) || !std::isfinite(P->xi))
         return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: invalid parameters");
+    if ((P->flags & DECT_COUPLED_TV) && P->tol > 0.0)
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: coupled TV runs a fixed iteration count (tol 0)");
     dect_status st = validate_geometry(g);
     if (st) return st;
     std::lock_guard<std::mutex> lk(g_adm_mu);
@@ -635,7 +667,8 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         if (t != S->t) return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: state was made for another geometry");
         if (S->started && (S->mu != P->mu || S->rho != P->rho || S->xi != P->xi ||
                            S->bh != P->beta_high || S->bl != P->beta_low ||
-                           S->nonneg != ((P->flags & DECT_NONNEG) != 0)))
+                           S->nonneg != ((P->flags & DECT_NONNEG) != 0) ||
+                           S->coupled != ((P->flags & DECT_COUPLED_TV) != 0)))
             return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: parameters differ from the state's run");
     }
     const int K = P->max_iter;
@@ -652,12 +685,13 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     // rebuild only when they change
     if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
                    S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol ||
-                   S->graph_nonneg != (int)S->nonneg)) {
+                   S->graph_nonneg != (int)S->nonneg || S->graph_coupled != (int)S->coupled)) {
         if ((st = build_graph(S, P->tol))) return st;
         S->graph_log = S->logbuf.ptr;
         S->graph_log_bytes = S->logbuf.bytes;
         S->graph_tol = P->tol;
         S->graph_nonneg = (int)S->nonneg;
+        S->graph_coupled = (int)S->coupled;
     }
     int k = 0;
     if (S->fresh && S->nonneg && K > 0) {  // the first projected step starts from A G
@@ -678,7 +712,8 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         ++k;
     }
     // outputs and the final objective
-    if ((st = adm_finish(*S->t, ptrs_of(S), xh, xl, S->mu, S->bh, S->bl, s))) return st;
+    if ((st = adm_finish(*S->t, ptrs_of(S), xh, xl, S->mu, S->bh, S->bl, s, S->coupled)))
+        return st;
     if (rep || P->log) {
         DECT_HIP(hipStreamSynchronize(s));
         AdmScalars hs[2];

@@ -86,7 +86,8 @@ dect_status adm_init(const GeomTables &t, const AdmPtrs &P, int nvg, const float
                      const float *x0l, hipStream_t s);
 dect_status adm_mark_log(const AdmPtrs &P, hipStream_t s);
 dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *xl, double mu,
-                       double bh, double bl, hipStream_t s);
+                       double bh, double bl, hipStream_t s,
+                       bool coupled = false);
 
 // Pointers of one energy image's ADM state.  h: hq partial planes whose sum
 // times hmu is mu A^T r (summed here in plane order, as the back-projector's
@@ -98,16 +99,25 @@ struct AdmImg {
     const float *flo;
     int hq;
     float hmu;
+    // coupled TV: the other energy's f, f_lo, lambda and z (the z-step
+    // shrinks both energies' gradients together), whether its deferred
+    // multiplier step is pending, and whether this block records the joint
+    // TV (energy 0 does, energy 1 records none)
+    const float *f2, *flo2, *lxi2, *lyi2, *zxi2, *zyi2;
+    int pending2, record_tv;
 };
 
 // ------------------------------------------------------------- tv_fused ---
 // Tile origin (r0, c0).  Regions relative to it: f on rows/cols -2 .. tile,
 // w on -1 .. tile, G on -1 .. tile - 1, grad G on the kTX x kTY tile.  part5
 // receives (TV(f), |G|^2, |grad G|^2, |grad f - z|^2, |f|^2) of the tile.
+template <bool COUPLED = false>
 __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part5,
                                         bool pending, int nx, int ny, float rho, float xi)
 {
     __shared__ float sf[kFH][kFW + 1], sl[kFH][kFW + 1];
+    __shared__ float sf2[COUPLED ? kFH : 1][COUPLED ? kFW + 1 : 1];
+    __shared__ float sl2[COUPLED ? kFH : 1][COUPLED ? kFW + 1 : 1];
     __shared__ float swx[kWH][kWW + 1], swy[kWH][kWW + 1];
     __shared__ float sg[kGH][kGW + 1];
     __shared__ double outv[5];
@@ -144,6 +154,7 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     // lambda (and z for the deferred multiplier step) on the w region (at
     // most two of its pixels per thread), loaded ahead too
     float lxv[2] = {0.f, 0.f}, lyv[2] = {0.f, 0.f}, zxv[2] = {0.f, 0.f}, zyv[2] = {0.f, 0.f};
+    float lx2v[2] = {0.f, 0.f}, ly2v[2] = {0.f, 0.f}, zx2v[2] = {0.f, 0.f}, zy2v[2] = {0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int i = threadIdx.x + 256 * k;
@@ -157,6 +168,14 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
                 zxv[k] = m.zxi[o];
                 zyv[k] = m.zyi[o];
             }
+            if constexpr (COUPLED) {
+                lx2v[k] = m.lxi2[o];
+                ly2v[k] = m.lyi2[o];
+                if (m.pending2) {
+                    zx2v[k] = m.zxi2[o];
+                    zy2v[k] = m.zyi2[o];
+                }
+            }
         }
     }
 
@@ -166,6 +185,10 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
         const bool in = r >= 0 && r < ny && c >= 0 && c < nx;
         sf[rr][cc] = in ? m.f[(size_t)r * nx + c] : 0.f;
         sl[rr][cc] = in ? m.flo[(size_t)r * nx + c] : 0.f;
+        if constexpr (COUPLED) {
+            sf2[rr][cc] = in ? m.f2[(size_t)r * nx + c] : 0.f;
+            sl2[rr][cc] = in ? m.flo2[(size_t)r * nx + c] : 0.f;
+        }
     }
     __syncthreads();
 
@@ -188,7 +211,28 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
                 ly -= xi * (dy - zyv[k]);
             }
             float vx = dx - lx / rho, vy = dy - ly / rho;
-            float n = sqrtf(vx * vx + vy * vy);
+            float n, tvi;
+            if constexpr (COUPLED) {
+                // the other energy's gradient and multiplier at this pixel, as
+                // its own block computes them; the joint norms are summed in
+                // energy order (own pair first in energy 0's block)
+                float f2c = sf2[rr + 1][cc + 1], l2c = sl2[rr + 1][cc + 1];
+                float dx2 = c >= 1 ? (f2c - sf2[rr + 1][cc]) + (l2c - sl2[rr + 1][cc]) : 0.f;
+                float dy2 = r >= 1 ? (f2c - sf2[rr][cc + 1]) + (l2c - sl2[rr][cc + 1]) : 0.f;
+                float lx2 = lx2v[k], ly2 = ly2v[k];
+                if (m.pending2) {
+                    lx2 -= xi * (dx2 - zx2v[k]);
+                    ly2 -= xi * (dy2 - zy2v[k]);
+                }
+                float vx2 = dx2 - lx2 / rho, vy2 = dy2 - ly2 / rho;
+                const float a = vx * vx + vy * vy, b = vx2 * vx2 + vy2 * vy2;
+                n = sqrtf(m.record_tv ? a + b : b + a);
+                const float ta = dx * dx + dy * dy, tb = dx2 * dx2 + dy2 * dy2;
+                tvi = m.record_tv ? sqrtf(ta + tb) : 0.f;
+            } else {
+                n = sqrtf(vx * vx + vy * vy);
+                tvi = sqrtf(dx * dx + dy * dy);
+            }
             float s = n > inv_rho ? (n - inv_rho) / n : 0.f;
             float zx = s * vx, zy = s * vy;
             wx = rho * (dx - zx) - lx;
@@ -198,7 +242,7 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
                 m.lyo[o] = ly;
                 m.zxo[o] = zx;
                 m.zyo[o] = zy;
-                tv += (double)sqrtf(dx * dx + dy * dy);
+                tv += (double)tvi;
                 double ex = (double)dx - zx, ey = (double)dy - zy;
                 pres += ex * ex + ey * ey;
                 ff += (double)fc * fc;

@@ -26,6 +26,7 @@ DECT_ERR_NONFINITE = 4
 DECT_WARN_MAXITER = 5
 DECT_WARM_START = 1
 DECT_NONNEG = 2
+DECT_COUPLED_TV = 4
 
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "GEOMETRY", 3: "HIP", 4: "NONFINITE", 5: "WARN_MAXITER"}
 
@@ -283,6 +284,8 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
         flags |= DECT_WARM_START
     if getattr(p, "nonneg", False):
         flags |= DECT_NONNEG
+    if getattr(p, "coupled_tv", False):
+        flags |= DECT_COUPLED_TV
     _dev(xh, "x_high", (geom.ny, geom.nx))
     _dev(xl, "x_low", (geom.ny, geom.nx))
     log = None
@@ -313,8 +316,11 @@ class AdmBatch:
         garr = (dect_geometry * n)(*[a.s for a in self._g])
         parr = (dect_adm_params * n)(*[dect_adm_params(p.mu, p.rho, p.xi, p.beta_high,
                                                        p.beta_low, p.max_iter, p.tol,
-                                                       DECT_NONNEG if getattr(p, "nonneg", False)
-                                                       else 0, None)
+                                                       (DECT_NONNEG if getattr(p, "nonneg", False)
+                                                        else 0) |
+                                                       (DECT_COUPLED_TV
+                                                        if getattr(p, "coupled_tv", False) else 0),
+                                                       None)
                                        for p in params])
         h = ct.c_void_p(None)
         _check(lib().dect_batch_create(garr, parr, n, ct.byref(h)), "dect_batch_create")
