@@ -110,7 +110,8 @@ def main():
     ap.add_argument("--no-fbp", action="store_true",
                     help="skip the filtered back-projection comparator entry")
     ap.add_argument("--nonneg-steps", type=int, default=100,
-                    help="timed ADM iterations of the non-negative variant entry (0: skip)")
+                    help="timed ADM iterations of the non-negative and coupled-TV variant "
+                         "entries (0: skip)")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -208,6 +209,7 @@ def main():
               if args.siddon_steps > 0 else None)
     fbp = None if args.no_fbp else fbp_extra(max(1, args.kernel_launches))
     nonneg = nonneg_extra(args.nonneg_steps) if args.nonneg_steps > 0 else None
+    coupled = nonneg_extra(args.nonneg_steps, coupled=True) if args.nonneg_steps > 0 else None
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -248,7 +250,7 @@ def main():
                   "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
                   "pls_attenuation_ms": round(pls_att_ms, 3), "pls_attenuation_iters": arep.iters,
                   "warm_start": warm, "batched": batched, "unrolled": unrolled,
-                  "siddon": siddon, "fbp": fbp, "nonneg": nonneg},
+                  "siddon": siddon, "fbp": fbp, "nonneg": nonneg, "coupled_tv": coupled},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
@@ -304,16 +306,18 @@ def siddon_extra(steps: int, launches: int):
             "fwd_projection_us_2energies": round(fwd_ms * 1e3, 2)}
 
 
-def nonneg_extra(steps: int):
+def nonneg_extra(steps: int, coupled: bool = False):
     """The metric workload with every f-step projected onto f >= 0
-    (DECT_NONNEG): ADM iterations/s (one more projection per iteration)."""
+    (DECT_NONNEG), or with the TV coupled across the energies
+    (DECT_COUPLED_TV): ADM iterations/s."""
     import torch
 
     from paper_1607_01650_amd import configs as C, dect, phantom as P
 
     g = C.METRIC
     s = P.make_slice(g, 0)
-    p = dataclasses.replace(C.default_adm_params(g, steps), nonneg=True)
+    p = dataclasses.replace(C.default_adm_params(g, steps), nonneg=not coupled,
+                            coupled_tv=coupled)
     mh = torch.as_tensor(s.sino[0], dtype=torch.float32).cuda()
     ml = torch.as_tensor(s.sino[1], dtype=torch.float32).cuda()
     xh = torch.empty((g.ny, g.nx), device="cuda")
@@ -330,9 +334,12 @@ def nonneg_extra(steps: int):
     torch.cuda.synchronize()
     ms = ev.ms(e0, e1) / steps
     state.close()
-    return {"workload": "adm_tv_512x512_360views_736bins_2energies, f >= 0",
-            "iters_per_s": round(1e3 / ms, 2), "ms_per_iteration": round(ms, 4),
-            "steps": steps, "zero_pixels": int((xh == 0).sum().item() + (xl == 0).sum().item())}
+    out = {"workload": "adm_tv_512x512_360views_736bins_2energies, "
+                       + ("TV coupled across energies" if coupled else "f >= 0"),
+           "iters_per_s": round(1e3 / ms, 2), "ms_per_iteration": round(ms, 4), "steps": steps}
+    if not coupled:
+        out["zero_pixels"] = int((xh == 0).sum().item() + (xl == 0).sum().item())
+    return out
 
 
 def fbp_extra(launches: int):
