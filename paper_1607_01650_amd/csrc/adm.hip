@@ -9,12 +9,14 @@
 //              |grad f - z|^2 and |f|^2.  G is written straight into the two
 //              zero-padded layouts the forward projector reads.
 //   fwd      : p = A G^k, |p|^2.
-//   scalar   : c^k = |G^k|^2 / (mu |A G^k|^2 + rho |grad G^k|^2).  The BB1
-//              step <s,s>/<s,y> of s = -alpha G^k, y = (mu A^T A + rho
-//              grad^T grad) s equals c^k, so alpha^{k+1} = c^k and
-//              alpha^0 = c^0 (the exact line-search step); logs J^k.
+//   scalar   : |r^k|^2 from the previous update's partials; c^k = |G^k|^2 /
+//              (mu |A G^k|^2 + rho |grad G^k|^2).  The BB1 step <s,s>/<s,y>
+//              of s = -alpha G^k, y = (mu A^T A + rho grad^T grad) s equals
+//              c^k, so alpha^{k+1} = c^k and alpha^0 = c^0 (the exact
+//              line-search step); logs J^k, counts the iteration and applies
+//              the relative-change stop rule (effective after this update).
 //   update   : f^{k+1} = f^k - alpha^k G^k, r^{k+1} = r^k - alpha^k p (so r
-//              stays A f - g without projecting f), |r^{k+1}|^2.
+//              stays A f - g without projecting f), partials of |r^{k+1}|^2.
 //   adj      : h^{k+1} = mu A^T r^{k+1}.
 // Every reduction is a fixed-order tree in FP64: reruns are bitwise equal.
 // lambda and z alternate between two buffers (the stencil reads neighbours'
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void k_tv_fused(
     const unsigned tile = xcd_order(block_linear(), grid_blocks());
     const int e = (int)(tile / (gx * gy));
     const int ty = (int)(tile / gx % gy), tx = (int)(tile % gx);
-    if (sc[e].stopped) return;
+    if (sc[e].stopped || sc[e].stop_next) return;
     const size_t N = (size_t)nx * ny;
     AdmImg m{f + e * N,
              hpart + (size_t)e * 2 * nvg * N,
@@ -79,11 +81,14 @@ __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
                                                 const double *__restrict__ p_tv, int nb_tv,
                                                 const double *__restrict__ p_fwd, int nb_fwd,
                                                 double *__restrict__ log, int log_rows,
-                                                double mu, double rho, int nonneg)
+                                                double mu, double rho, int nonneg,
+                                                const double *__restrict__ p_rr, int nbs,
+                                                double tol)
 {
     const int e = blockIdx.x;
     scalar_energy(sc[e], p_tv + (size_t)e * nb_tv * 5, nb_tv, p_fwd + (size_t)e * nb_fwd, nb_fwd,
-                  log, log_rows, e, mu, rho, nonneg != 0);
+                  log, log_rows, e, mu, rho, nonneg != 0, nonneg == 0,
+                  p_rr + (size_t)e * nbs, nbs, tol);
 }
 
 // ------------------------------------------------ non-negative variant ---
@@ -333,18 +338,25 @@ __global__ __launch_bounds__(256) void k_tv_only(const float *__restrict__ f,
     if (threadIdx.x == 0) partial[(size_t)e * gridDim.x + blockIdx.x] = tot[0];
 }
 
+// J(f^K): TV from the partials, |r|^2 from the last update's partials (once
+// an update has run; else the set-up's value).
 __global__ __launch_bounds__(256) void k_final_J(AdmScalars *__restrict__ sc,
                                                  const double *__restrict__ p_tv, int nb,
+                                                 const double *__restrict__ p_rr, int nbs,
                                                  double *__restrict__ log, int log_rows, double mu)
 {
     const int e = blockIdx.x;
-    double v[1] = {0.0};
+    const bool fresh_rr = sc[e].pending != 0;
+    double v[2] = {0.0, 0.0};
     for (int i = threadIdx.x; i < nb; i += 256) v[0] += p_tv[(size_t)e * nb + i];
-    __shared__ double tot[1];
-    block_sum<1>(v, tot);
+    if (fresh_rr)
+        for (int i = threadIdx.x; i < nbs; i += 256) v[1] += p_rr[(size_t)e * nbs + i];
+    __shared__ double tot[2];
+    block_sum<2>(v, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
     AdmScalars &s = sc[e];
+    if (fresh_rr) s.rr = tot[1];
     double J = tot[0] + 0.5 * mu * s.rr;
     int64_t row = s.iter - s.log_base;
     if (log && row >= 0 && row < log_rows) {
@@ -443,7 +455,7 @@ dect_status adm_finish(const GeomTables &t, const AdmPtrs &P, float *xh, float *
                        t.key.nx, t.key.ny, coupled ? 1 : 0);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_final_J, dim3(2), dim3(256), 0, s, P.sc, (const double *)P.p_tvo, P.nbi,
-                       P.log, P.log_rows, mu);
+                       (const double *)P.p_rr, P.nbs, P.log, P.log_rows, mu);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -544,7 +556,7 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     hipLaunchKernelGGL(k_scalar, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_tv.ptr,
                        S->nb_tv, (const double *)S->p_fwd.ptr, S->nb_fwd,
                        (double *)S->logbuf.ptr, (int)(S->logbuf.bytes / 32), S->mu, S->rho,
-                       S->nonneg ? 1 : 0);
+                       S->nonneg ? 1 : 0, (const double *)S->p_rr.ptr, S->nbs, tol);
     DECT_HIP(hipGetLastError());
     if (S->nonneg) {
         // projected step s, |grad s|^2, p = A s, r += p, then the step's sums
@@ -577,9 +589,7 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
                        (const float *)S->gpad.ptr, (float *)S->r.ptr, (const float *)S->p.ptr,
                        (double *)S->p_rr.ptr, sc, nx, ny, M, S->nbi, S->nbs);
     DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_rr, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_rr.ptr, S->nbs, 1,
-                       tol);
-    DECT_HIP(hipGetLastError());
+    // |r|^2 of this update is summed by the next iteration's scalar kernel
     return launch_adj(t, (const float *)S->r.ptr, nullptr, (float *)S->adjpart.ptr, 2,
                       (float)S->mu, s, S->nvg);
 }

@@ -30,6 +30,7 @@ struct AdmScalars {
     double beta;    // Eq. 3 weight of this energy
     double ss, sy;  // non-negative variant: <s,s> and <s,y> of the last projected step
     int32_t has_prev, stopped, nonfinite_iter, pending;
+    int32_t stop_next;  // the stop rule held: stop once this iteration's update is done
     int64_t iter;      // iterations completed
     int64_t log_base;  // iteration index of log row 0 for this call
 };
@@ -303,15 +304,28 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
 // c^k = |G|^2 / (mu |A G|^2 + rho |grad G|^2) from the partials of one
 // energy; alpha^k = c^{k-1} (c^0 at the first step); J^k logged in column
 // `col` (and the step in column col + 2) of a [rows][4] log.
+// fold: also take over the bookkeeping of the previous update (the plain
+// iteration has no separate kernel for it): |r|^2 of the residual it left,
+// from its per-block partials p_rr (once an update has run), then, for the
+// update about to run, the iteration count, the pending multiplier step and
+// the relative-change stop rule (stop_next, turned into stopped here one
+// iteration later, so that this iteration's update still runs).
 __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__restrict__ pt,
                                               int nb_tv, const double *__restrict__ pf, int nb_fwd,
                                               double *__restrict__ log, int log_rows, int col,
-                                              double mu, double rho, bool nonneg = false)
+                                              double mu, double rho, bool nonneg = false,
+                                              bool fold = false,
+                                              const double *__restrict__ p_rr = nullptr,
+                                              int nbs = 0, double tol = 0.0)
 {
-    __shared__ double tot[6];
-    const bool run = !s.stopped;
-    double v[6] = {0, 0, 0, 0, 0, 0};
+    __shared__ double tot[7];
+    const bool stop_now = fold && s.stop_next;
+    const bool run = !s.stopped && !stop_now;
+    const bool fresh_rr = fold && s.pending;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (run) {
+        if (fresh_rr)
+            for (int i = threadIdx.x; i < nbs; i += 256) v[6] += p_rr[i];
         // thread t adds entries t, t + 256, ... in that order; eight loads are
         // issued together
         for (int i0 = threadIdx.x; i0 < nb_tv; i0 += 256 * 4) {
@@ -335,8 +349,13 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
             for (int u = 0; u < 8; ++u) v[5] += t[u];
         }
     }
-    block_sum<6>(v, tot);
+    block_sum<7>(v, tot);
+    if (stop_now && threadIdx.x == 0) {
+        s.stopped = 1;
+        s.stop_next = 0;
+    }
     if (run && threadIdx.x == 0) {
+        if (fresh_rr) s.rr = tot[6];
         const double tvf = tot[0], gg = tot[1], gradg = tot[2], ff = tot[4], pp = tot[5];
         const double den = mu * pp + rho * gradg;
         double c = den > 0.0 ? gg / den : (s.has_prev ? s.c_prev : 0.0);
@@ -360,6 +379,11 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
             s.nonfinite_iter = (int32_t)(k + 1);
             s.stopped = 1;
             s.alpha = 0.0;
+        }
+        if (fold && !s.stopped) {  // this iteration's update runs
+            s.pending = 1;
+            s.iter += 1;
+            if (tol > 0.0 && s.relchg < tol) s.stop_next = 1;
         }
     }
     __syncthreads();

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void kb_tv(const SliceDev *__restrict__ S,
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
         const int e = w.y;
-        if (!d.P.sc[e].stopped) {
+        if (!d.P.sc[e].stopped && !d.P.sc[e].stop_next) {
             const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
             const size_t blk = (size_t)e * gx * gy + (size_t)w.z * gx + w.w;
             tv_tile(w.z * kTY, w.w * kTX, img_of(d, e, par), d.P.p_tv + blk * 5,
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void kb_scalar(const SliceDev *__restrict__ S,
         const int e = w.y;
         scalar_energy(d.P.sc[e], d.P.p_tv + (size_t)e * d.P.nb_tv * 5, d.P.nb_tv,
                       d.P.p_fwd + (size_t)e * d.P.nb_fwd, d.P.nb_fwd, d.P.log, d.P.log_rows, e,
-                      d.mu, d.rhod);
+                      d.mu, d.rhod, false, true, d.P.p_rr + (size_t)e * d.P.nbs, d.P.nbs, d.tol);
     }
 }
 
@@ -135,17 +135,6 @@ __global__ __launch_bounds__(256) void kb_update(const SliceDev *__restrict__ S,
                          d.P.nbi);
         }
         __syncthreads();
-    }
-}
-
-// item = (slice, energy)
-__global__ __launch_bounds__(256) void kb_rr(const SliceDev *__restrict__ S,
-                                             const int4 *__restrict__ items, int n)
-{
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int4 w = items[it];
-        const SliceDev &d = S[w.x];
-        rr_energy(d.P.sc[w.y], d.P.p_rr + (size_t)w.y * d.P.nbs, d.P.nbs, 1, d.tol);
     }
 }
 
@@ -283,9 +272,6 @@ dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(kb_update, dim3(b->g_upd), dim3(256), 0, s, S, (const int4 *)b->w_upd.ptr,
                        b->n_upd);
-    DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_rr, dim3(b->g_se), dim3(256), 0, s, S, (const int4 *)b->w_se.ptr,
-                       b->n_se);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(kb_adj, dim3(b->g_adj), dim3(kAdjThreads), 0, s, S,
                        (const int4 *)b->w_adj.ptr,
