@@ -434,12 +434,14 @@ double or_tv(int nx, int ny, const double *x)
  * nonneg != 0: every f-step is followed by the projection f = max(f, 0)
  * (images are attenuation maps, non-negative); the BB step is then taken
  * from the projected step s.
+ * step_rule: 0 BB1 <s,s>/<s,y>; 1 BB2 <s,y>/<y,y>; 2 adaptive (BB2 where
+ * BB2/BB1 < 1/2, else BB1).  A non-positive <s,y> keeps the step.
  * Returns the number of iterations run (stops early when tol > 0 and the
  * relative image change drops below tol).
  */
 int or_adm(const or_geom *g, const double *m, double beta, double mu, double rho, double xi,
            int K, double tol, const double *x0, double *x_out, double *lam_out, double *z_out,
-           double *log, int nonneg)
+           double *log, int nonneg, int step_rule)
 {
     const int nx = g->nx, ny = g->ny;
     const size_t N = (size_t)nx * ny, M = (size_t)g->n_views * g->n_bins;
@@ -514,8 +516,13 @@ int or_adm(const or_geom *g, const double *m, double beta, double mu, double rho
         or_grad(nx, ny, s, wx, wy);
         or_gradT(nx, ny, wx, wy, t1);
         for (size_t i = 0; i < N; ++i) y[i] = (h[i] - ho[i]) + rho * t1[i];
-        double ss = dot(N, s, s), sy = dot(N, s, y);
-        if (sy > 0.0) alpha = ss / sy;
+        double ss = dot(N, s, s), sy = dot(N, s, y), yy = dot(N, y, y);
+        if (sy > 0.0) {
+            const double bb1 = ss / sy, bb2 = yy > 0.0 ? sy / yy : bb1;
+            if (step_rule == 1) alpha = bb2;
+            else if (step_rule == 2) alpha = bb2 / bb1 < 0.5 ? bb2 : bb1;  /* adaptive */
+            else alpha = bb1;
+        }
         double fn = sqrt(dot(N, fo, fo));
         relchg = fn > 0.0 ? sqrt(ss) / fn : (ss > 0.0 ? INFINITY : 0.0);
         /* multiplier step (Eq. 7) */

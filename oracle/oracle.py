@@ -61,7 +61,8 @@ def lib():
         L.or_shrink.argtypes = [sz, pd, pd, d, pd, pd]
         L.or_tv.argtypes = [ct.c_int, ct.c_int, pd]
         L.or_tv.restype = d
-        L.or_adm.argtypes = [P(_Geom), pd, d, d, d, d, ct.c_int, d, pd, pd, pd, pd, pd, ct.c_int]
+        L.or_adm.argtypes = [P(_Geom), pd, d, d, d, d, ct.c_int, d, pd, pd, pd, pd, pd, ct.c_int,
+                             ct.c_int]
         L.or_adm.restype = ct.c_int
         L.or_dinv.argtypes = [sz, d, d, d, d, pd, pd, pd, pd]
         L.or_edges_f32.argtypes = [ct.c_int, ct.c_int, pf, ct.c_float, ct.c_float, pf, pf,
@@ -187,9 +188,11 @@ class AdmResult:
 
 
 def adm(g, m: np.ndarray, beta: float, mu: float, rho: float, xi: float, iters: int,
-        tol: float = 0.0, x0: Optional[np.ndarray] = None, nonneg: bool = False) -> AdmResult:
+        tol: float = 0.0, x0: Optional[np.ndarray] = None, nonneg: bool = False,
+        step: str = "bb1") -> AdmResult:
     """ADM-TV (Eq. 10) for one energy; returns x = f / beta and the log.
-    nonneg: project every f-step onto f >= 0."""
+    nonneg: project every f-step onto f >= 0.  step: "bb1", "bb2" or "abb"
+    (adaptive: BB2 where BB2/BB1 < 1/2, else BB1)."""
     og = _og(g)
     mm = _f64(m).reshape(og.n_views, og.n_bins)
     x0c = None if x0 is None else _f64(x0).reshape(og.ny, og.nx)
@@ -199,7 +202,7 @@ def adm(g, m: np.ndarray, beta: float, mu: float, rho: float, xi: float, iters: 
     log = np.zeros((iters + 1, 5))
     k = lib().or_adm(ct.byref(og.s), _p(mm), float(beta), float(mu), float(rho), float(xi),
                      int(iters), float(tol), _p(x0c), _p(x), _p(lam), _p(z), _p(log),
-                     1 if nonneg else 0)
+                     1 if nonneg else 0, {"bb1": 0, "bb2": 1, "abb": 2}[step])
     return AdmResult(x, lam, z, log, int(k))
 
 

@@ -207,3 +207,69 @@ def test_beta_scaling_identity():
     r2 = O.adm(g, m, 1.0, 2.0 * beta, 8.0 * beta, 8.0 * beta, 40)
     assert np.abs(r1.x - r2.x).max() <= 1e-10 * np.abs(r2.x).max()
     assert np.allclose(r1.J, beta * r2.J, rtol=1e-10, atol=0)
+
+
+def _g_and_parts(g, m, beta, p, k):
+    """G^k rebuilt from the oracle's primitives and its state after k
+    iterations, with A G and grad G."""
+    if k == 0:
+        f = np.zeros((g.ny, g.nx))
+        lam = np.zeros((2, g.ny, g.nx))
+    else:
+        run_k = O.adm(g, m, beta, p.mu, p.rho, p.xi, k)
+        f, lam = beta * run_k.x, run_k.lam
+    d = O.grad(f)
+    zx, zy = O.shrink(d[0] - lam[0] / p.rho, d[1] - lam[1] / p.rho, 1.0 / p.rho)
+    h = p.mu * O.backproject(g, O.project(g, f) - beta * m)
+    G = h + O.gradT(p.rho * (d[0] - zx) - lam[0], p.rho * (d[1] - zy) - lam[1])
+    AG = O.project(g, G)
+    gx, gy = O.grad(G)
+    return G, AG, gx, gy
+
+
+def test_bb2_and_adaptive_steps():
+    """The BB2 step <s,y>/<y,y> after step k, for s = -alpha G^k and y = (mu
+    A^T A + rho grad^T grad) s, equals (mu |A G|^2 + rho |grad G|^2) / |mu A^T
+    A G + rho grad^T grad G|^2; the adaptive rule takes it where it is below
+    half the BB1 (Cauchy) step and the BB1 step otherwise."""
+    g = C.TINY
+    s = P.make_slice(g, 0)
+    p = C.default_adm_params(g, 1)
+    beta = p.beta_low
+    m = s.sino[1]
+    for k in (0, 3, 17):
+        G, AG, gx, gy = _g_and_parts(g, m, beta, p, k)
+        den = p.mu * np.sum(AG * AG) + p.rho * (np.sum(gx * gx) + np.sum(gy * gy))
+        ytil = p.mu * O.backproject(g, AG) + p.rho * O.gradT(gx, gy)
+        bb1, bb2 = np.sum(G * G) / den, den / np.sum(ytil * ytil)
+        assert bb2 <= bb1 * (1 + 1e-12)  # Cauchy-Schwarz
+        for step, want in (("bb2", bb2), ("abb", bb2 if bb2 / bb1 < 0.5 else bb1)):
+            run_k = O.adm(g, m, beta, p.mu, p.rho, p.xi, k, step=step) if k > 0 else None
+            if k > 0:
+                # the state after k steps of this rule differs from the BB1 one:
+                # rebuild G^k from the rule's own run
+                f, lam = beta * run_k.x, run_k.lam
+                d = O.grad(f)
+                zx, zy = O.shrink(d[0] - lam[0] / p.rho, d[1] - lam[1] / p.rho, 1.0 / p.rho)
+                h = p.mu * O.backproject(g, O.project(g, f) - beta * m)
+                G = h + O.gradT(p.rho * (d[0] - zx) - lam[0], p.rho * (d[1] - zy) - lam[1])
+                AG = O.project(g, G)
+                gx, gy = O.grad(G)
+                den = p.mu * np.sum(AG * AG) + p.rho * (np.sum(gx * gx) + np.sum(gy * gy))
+                ytil = p.mu * O.backproject(g, AG) + p.rho * O.gradT(gx, gy)
+                b1, b2 = np.sum(G * G) / den, den / np.sum(ytil * ytil)
+                want = b2 if step == "bb2" else (b2 if b2 / b1 < 0.5 else b1)
+            run_next = O.adm(g, m, beta, p.mu, p.rho, p.xi, k + 2, step=step)
+            assert abs(run_next.log[k + 1, 1] - want) <= 1e-9 * want, (step, k)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("step", ["bb2", "abb"])
+def test_bb2_and_adaptive_reach_the_minimum(step):
+    """With either step rule ADM still reaches the minimum J* of Eq. 4 found
+    by Chambolle-Pock, within 1e-6."""
+    g, A, m = _dense_problem()
+    mu = 0.5
+    Jstar = _chambolle_pock(A, m, mu, 16, 100000)
+    r = O.adm(g, m.reshape(g.n_views, g.n_bins), 1.0, mu, 16.0, 4.0, 20000, step=step)
+    assert abs(r.J[-1] - Jstar) <= 1e-6 * Jstar, (r.J[-1], Jstar)
