@@ -85,11 +85,16 @@ enum {
                             kept when the denominator is not positive.  The
                             step's own projection A s replaces A G after the
                             first iteration. */
-    DECT_COUPLED_TV = 4  /* the TV norm of Eq. 2 over the 4-vector of both energies'
+    DECT_COUPLED_TV = 4, /* the TV norm of Eq. 2 over the 4-vector of both energies'
                             gradients (one joint z-step; each energy keeps its own
                             f-step and BB step); log column J_high then holds the
                             joint TV and J_low none, so the two sum to the
                             objective.  Needs tol = 0 (fixed iteration count). */
+    DECT_STEP_BB2 = 8,   /* BB2 step <s,y>/<y,y> instead of BB1 <s,s>/<s,y> (Eq. 9
+                            names a BB step without its variant); one more back-projection per
+                            iteration (A^T A G for |y|^2) */
+    DECT_STEP_ABB = 16   /* adaptive: BB2 where BB2/BB1 < 1/2, else BB1; same cost.
+                            Neither step flag combines with DECT_NONNEG. */
 };
 typedef struct {
     double mu;        /* data-fidelity weight of Eq. 4 */
@@ -100,7 +105,8 @@ typedef struct {
     int32_t max_iter; /* iterations to run (>= 0) */
     double tol;       /* stop once |f^{k+1}-f^k| / |f^k| < tol for both
                          energies (0 = run max_iter iterations) */
-    int32_t flags;    /* DECT_WARM_START, DECT_NONNEG, DECT_COUPLED_TV */
+    int32_t flags;    /* DECT_WARM_START, DECT_NONNEG, DECT_COUPLED_TV, DECT_STEP_BB2 or
+                         DECT_STEP_ABB */
     double *log;      /* host [max_iter+1][4] or NULL: per energy-pair row
                          {J_high(f^k), J_low(f^k), alpha_high^k, alpha_low^k};
                          filling it synchronises the stream */
@@ -229,7 +235,8 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  * spans all slices, replayed from a hipGraph.  Starts from zero images.
  * geoms/params: host arrays [n] (params[i].max_iter and DECT_WARM_START are ignored);
  *   every geometry must use DECT_JOSEPH and no params[i].flags may hold
- *   DECT_NONNEG or DECT_COUPLED_TV (else DECT_ERR_INVALID_ARG).
+ *   DECT_NONNEG, DECT_COUPLED_TV, DECT_STEP_BB2 or DECT_STEP_ABB (else
+ *   DECT_ERR_INVALID_ARG).
  * d_m_high, d_m_low, d_x_high, d_x_low: host arrays [n] of device pointers
  *   to slice i's sinograms [V_i][B_i] and output images [ny_i][nx_i].
  * objective: NULL or host [n], filled after synchronising the stream with

@@ -87,6 +87,7 @@ class AdmParams:
     tol: float = 0.0
     nonneg: bool = False  # project every f-step onto f >= 0
     coupled_tv: bool = False  # TV over both energies' gradients jointly (tol must be 0)
+    step: str = "bb1"  # Barzilai-Borwein rule: "bb1", "bb2" or "abb" (adaptive)
 
 
 @dataclasses.dataclass(frozen=True)

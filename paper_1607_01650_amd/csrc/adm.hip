@@ -83,12 +83,13 @@ __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
                                                 double *__restrict__ log, int log_rows,
                                                 double mu, double rho, int nonneg,
                                                 const double *__restrict__ p_rr, int nbs,
-                                                double tol)
+                                                double tol, int step_rule,
+                                                const double *__restrict__ p_yy, int nbi)
 {
     const int e = blockIdx.x;
     scalar_energy(sc[e], p_tv + (size_t)e * nb_tv * 5, nb_tv, p_fwd + (size_t)e * nb_fwd, nb_fwd,
                   log, log_rows, e, mu, rho, nonneg != 0, nonneg == 0,
-                  p_rr + (size_t)e * nbs, nbs, tol);
+                  p_rr + (size_t)e * nbs, nbs, tol, step_rule, p_yy + (size_t)e * nbi, nbi);
 }
 
 // ------------------------------------------------ non-negative variant ---
@@ -262,6 +263,44 @@ __global__ __launch_bounds__(256) void k_rr(AdmScalars *__restrict__ sc,
     rr_energy(sc[e], p_rr + (size_t)e * nbs, nbs, step, tol);
 }
 
+// BB2 / adaptive steps: partials of |mu A^T A G + rho grad^T grad G|^2 per
+// block of 1024 pixels, from the partial planes of A^T (A G) (summed in plane
+// order) and G in the padded layout (still this iteration's G).
+__global__ __launch_bounds__(256) void k_yy(const float *__restrict__ apart, int nplanes,
+                                            float mu, const float *__restrict__ gpad, float rho,
+                                            const AdmScalars *__restrict__ sc,
+                                            double *__restrict__ p_yy, int nx, int ny, int nbi)
+{
+    const int e = blockIdx.y;
+    if (sc[e].stopped) return;
+    const size_t N = (size_t)nx * ny;
+    const int pnx = nx + 2 * kPad;
+    const float *ap = apart + (size_t)e * nplanes * N;
+    auto G = [&](int r, int c) { return gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e]; };
+    // backward difference along x / y at (r, c) (zero on the first column / row)
+    auto gx = [&](int r, int c) { return c >= 1 ? G(r, c) - G(r, c - 1) : 0.f; };
+    auto gy = [&](int r, int c) { return r >= 1 ? G(r, c) - G(r - 1, c) : 0.f; };
+    double v[1] = {0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            float a = 0.f;
+            for (int q = 0; q < nplanes; ++q) a += ap[(size_t)q * N + i];
+            float lt = 0.f;  // (grad^T grad G) at (r, c)
+            if (c >= 1) lt += gx(r, c);
+            if (c + 1 <= nx - 1) lt -= gx(r, c + 1);
+            if (r >= 1) lt += gy(r, c);
+            if (r + 1 <= ny - 1) lt -= gy(r + 1, c);
+            const double y = (double)mu * a + (double)rho * lt;
+            v[0] += y * y;
+        }
+    }
+    __shared__ double tot[1];
+    block_sum<1>(v, tot);
+    if (threadIdx.x == 0) p_yy[(size_t)e * nbi + blockIdx.x] = tot[0];
+}
+
 // ------------------------------------------------------------- set-up ---
 // f = beta x0 (or 0), lambda = z = 0 for both parities.
 __global__ __launch_bounds__(256) void k_init_image(float *__restrict__ f,
@@ -395,6 +434,9 @@ struct dect_adm_state {
     bool fresh = false;         // no iteration launched since the run's set-up
     bool coupled = false;       // the run couples the TV of the two energies
     int graph_coupled = -1;
+    int step_rule = 0;          // 0 BB1, 1 BB2, 2 adaptive
+    int graph_step = -1;
+    dect::DevBuf apart, p_yy;   // BB2 / adaptive: A^T (A G) partial planes, |y|^2 partials
     int graph_nonneg = -1;
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
@@ -556,7 +598,8 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     hipLaunchKernelGGL(k_scalar, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_tv.ptr,
                        S->nb_tv, (const double *)S->p_fwd.ptr, S->nb_fwd,
                        (double *)S->logbuf.ptr, (int)(S->logbuf.bytes / 32), S->mu, S->rho,
-                       S->nonneg ? 1 : 0, (const double *)S->p_rr.ptr, S->nbs, tol);
+                       S->nonneg ? 1 : 0, (const double *)S->p_rr.ptr, S->nbs, tol,
+                       S->step_rule, (const double *)S->p_yy.ptr, S->nbi);
     DECT_HIP(hipGetLastError());
     if (S->nonneg) {
         // projected step s, |grad s|^2, p = A s, r += p, then the step's sums
@@ -590,6 +633,15 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
                        (double *)S->p_rr.ptr, sc, nx, ny, M, S->nbi, S->nbs);
     DECT_HIP(hipGetLastError());
     // |r|^2 of this update is summed by the next iteration's scalar kernel
+    if (S->step_rule) {  // |mu A^T A G + rho grad^T grad G|^2 for the next step
+        if ((st = launch_adj(t, (const float *)p, nullptr, (float *)S->apart.ptr, 2, 1.0f, s,
+                             S->nvg)))
+            return st;
+        hipLaunchKernelGGL(k_yy, dim3(S->nbi, 2), dim3(256), 0, s, (const float *)S->apart.ptr,
+                           2 * S->nvg, (float)S->mu, (const float *)S->gpad.ptr, (float)S->rho,
+                           (const AdmScalars *)sc, (double *)S->p_yy.ptr, nx, ny, S->nbi);
+        DECT_HIP(hipGetLastError());
+    }
     return launch_adj(t, (const float *)S->r.ptr, nullptr, (float *)S->adjpart.ptr, 2,
                       (float)S->mu, s, S->nvg);
 }
@@ -604,6 +656,13 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     S->bl = P->beta_low;
     S->nonneg = (P->flags & DECT_NONNEG) != 0;
     S->coupled = (P->flags & DECT_COUPLED_TV) != 0;
+    S->step_rule = (P->flags & DECT_STEP_BB2) ? 1 : (P->flags & DECT_STEP_ABB) ? 2 : 0;
+    if (S->step_rule) {
+        dect_status st = DECT_OK;
+        if ((st = S->apart.ensure(std::max<size_t>(1, adj_partial_floats(*S->t, 2, S->nvg)) * 4)) ||
+            (st = S->p_yy.ensure((size_t)2 * S->nbi * 8)))
+            return st;
+    }
     S->fresh = true;
     S->parity = 0;
     dect_status st =
@@ -652,6 +711,10 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: invalid parameters");
     if ((P->flags & DECT_COUPLED_TV) && P->tol > 0.0)
         return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: coupled TV runs a fixed iteration count (tol 0)");
+    if ((P->flags & DECT_STEP_BB2) && (P->flags & DECT_STEP_ABB))
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: DECT_STEP_BB2 and DECT_STEP_ABB exclude each other");
+    if ((P->flags & (DECT_STEP_BB2 | DECT_STEP_ABB)) && (P->flags & DECT_NONNEG))
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: the BB2 / adaptive steps have no non-negative variant");
     dect_status st = validate_geometry(g);
     if (st) return st;
     std::lock_guard<std::mutex> lk(g_adm_mu);
@@ -678,7 +741,9 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         if (S->started && (S->mu != P->mu || S->rho != P->rho || S->xi != P->xi ||
                            S->bh != P->beta_high || S->bl != P->beta_low ||
                            S->nonneg != ((P->flags & DECT_NONNEG) != 0) ||
-                           S->coupled != ((P->flags & DECT_COUPLED_TV) != 0)))
+                           S->coupled != ((P->flags & DECT_COUPLED_TV) != 0) ||
+                           S->step_rule != ((P->flags & DECT_STEP_BB2) ? 1
+                                            : (P->flags & DECT_STEP_ABB) ? 2 : 0)))
             return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv: parameters differ from the state's run");
     }
     const int K = P->max_iter;
@@ -695,13 +760,15 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     // rebuild only when they change
     if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
                    S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol ||
-                   S->graph_nonneg != (int)S->nonneg || S->graph_coupled != (int)S->coupled)) {
+                   S->graph_nonneg != (int)S->nonneg || S->graph_coupled != (int)S->coupled ||
+                   S->graph_step != S->step_rule)) {
         if ((st = build_graph(S, P->tol))) return st;
         S->graph_log = S->logbuf.ptr;
         S->graph_log_bytes = S->logbuf.bytes;
         S->graph_tol = P->tol;
         S->graph_nonneg = (int)S->nonneg;
         S->graph_coupled = (int)S->coupled;
+        S->graph_step = S->step_rule;
     }
     int k = 0;
     if (S->fresh && S->nonneg && K > 0) {  // the first projected step starts from A G

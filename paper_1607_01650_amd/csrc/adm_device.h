@@ -29,6 +29,7 @@ struct AdmScalars {
     double relchg;  // last relative image change
     double beta;    // Eq. 3 weight of this energy
     double ss, sy;  // non-negative variant: <s,s> and <s,y> of the last projected step
+    double den_prev;  // mu |A G|^2 + rho |grad G|^2 of the previous G (BB2 numerator)
     int32_t has_prev, stopped, nonfinite_iter, pending;
     int32_t stop_next;  // the stop rule held: stop once this iteration's update is done
     int64_t iter;      // iterations completed
@@ -316,16 +317,21 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
                                               double mu, double rho, bool nonneg = false,
                                               bool fold = false,
                                               const double *__restrict__ p_rr = nullptr,
-                                              int nbs = 0, double tol = 0.0)
+                                              int nbs = 0, double tol = 0.0, int step_rule = 0,
+                                              const double *__restrict__ p_yy = nullptr,
+                                              int nyy = 0)
 {
-    __shared__ double tot[7];
+    __shared__ double tot[8];
     const bool stop_now = fold && s.stop_next;
     const bool run = !s.stopped && !stop_now;
     const bool fresh_rr = fold && s.pending;
-    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    const bool want_yy = step_rule != 0 && s.has_prev;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (run) {
         if (fresh_rr)
             for (int i = threadIdx.x; i < nbs; i += 256) v[6] += p_rr[i];
+        if (want_yy)
+            for (int i = threadIdx.x; i < nyy; i += 256) v[7] += p_yy[i];
         // thread t adds entries t, t + 256, ... in that order; eight loads are
         // issued together
         for (int i0 = threadIdx.x; i0 < nb_tv; i0 += 256 * 4) {
@@ -349,7 +355,7 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
             for (int u = 0; u < 8; ++u) v[5] += t[u];
         }
     }
-    block_sum<7>(v, tot);
+    block_sum<8>(v, tot);
     if (stop_now && threadIdx.x == 0) {
         s.stopped = 1;
         s.stop_next = 0;
@@ -360,6 +366,19 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
         const double den = mu * pp + rho * gradg;
         double c = den > 0.0 ? gg / den : (s.has_prev ? s.c_prev : 0.0);
         double alpha = s.has_prev ? s.c_prev : c;
+        // BB2 <s,y>/<y,y> of s = -alpha G_prev: den_prev / |mu A^T A G + rho
+        // grad^T grad G|^2 (step_rule 1), or the adaptive choice (2): BB2
+        // where it is below half the BB1 step; a non-positive <s,y> keeps alpha
+        if (want_yy) {
+            if (s.den_prev > 0.0) {
+                const double bb1 = s.c_prev, yy = tot[7];
+                const double bb2 = yy > 0.0 ? s.den_prev / yy : bb1;
+                alpha = step_rule == 1 ? bb2 : (bb2 / bb1 < 0.5 ? bb2 : bb1);
+            } else {
+                alpha = s.alpha;
+            }
+        }
+        s.den_prev = den;
         // projected steps: BB1 <s,s>/<s,y> of the last step (kept when <s,y> <= 0)
         if (nonneg && s.has_prev) alpha = s.sy > 0.0 ? s.ss / s.sy : s.alpha;
         const double J = tvf + 0.5 * mu * s.rr;

@@ -344,9 +344,9 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
             return fail(DECT_ERR_INVALID_ARG, "dect_batch_create: invalid ADM parameters");
         if (geoms[i].model != DECT_JOSEPH)
             return fail(DECT_ERR_INVALID_ARG, "batched ADM runs the Joseph model only");
-        if (p.flags & (DECT_NONNEG | DECT_COUPLED_TV))
+        if (p.flags & (DECT_NONNEG | DECT_COUPLED_TV | DECT_STEP_BB2 | DECT_STEP_ABB))
             return fail(DECT_ERR_INVALID_ARG,
-                        "batched ADM has no non-negative or coupled-TV variant");
+                        "batched ADM has no non-negative, coupled-TV or BB2 variant");
         if ((st = get_tables(&geoms[i], &b->t[i]))) return st;
         const GeomTables &t = *b->t[i];
         Sizes &z = sz[i];

@@ -27,6 +27,9 @@ DECT_WARN_MAXITER = 5
 DECT_WARM_START = 1
 DECT_NONNEG = 2
 DECT_COUPLED_TV = 4
+DECT_STEP_BB2 = 8
+DECT_STEP_ABB = 16
+_STEP_FLAGS = {"bb1": 0, "bb2": DECT_STEP_BB2, "abb": DECT_STEP_ABB}
 
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "GEOMETRY", 3: "HIP", 4: "NONFINITE", 5: "WARN_MAXITER"}
 
@@ -286,6 +289,7 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
         flags |= DECT_NONNEG
     if getattr(p, "coupled_tv", False):
         flags |= DECT_COUPLED_TV
+    flags |= _STEP_FLAGS[getattr(p, "step", "bb1")]
     _dev(xh, "x_high", (geom.ny, geom.nx))
     _dev(xl, "x_low", (geom.ny, geom.nx))
     log = None
@@ -319,7 +323,8 @@ class AdmBatch:
                                                        (DECT_NONNEG if getattr(p, "nonneg", False)
                                                         else 0) |
                                                        (DECT_COUPLED_TV
-                                                        if getattr(p, "coupled_tv", False) else 0),
+                                                        if getattr(p, "coupled_tv", False) else 0) |
+                                                       _STEP_FLAGS[getattr(p, "step", "bb1")],
                                                        None)
                                        for p in params])
         h = ct.c_void_p(None)
