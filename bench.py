@@ -110,8 +110,8 @@ def main():
     ap.add_argument("--no-fbp", action="store_true",
                     help="skip the filtered back-projection comparator entry")
     ap.add_argument("--nonneg-steps", type=int, default=100,
-                    help="timed ADM iterations of the non-negative and coupled-TV variant "
-                         "entries (0: skip)")
+                    help="timed ADM iterations of the non-negative, coupled-TV and "
+                         "adaptive-step variant entries (0: skip)")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -210,6 +210,7 @@ def main():
     fbp = None if args.no_fbp else fbp_extra(max(1, args.kernel_launches))
     nonneg = nonneg_extra(args.nonneg_steps) if args.nonneg_steps > 0 else None
     coupled = nonneg_extra(args.nonneg_steps, coupled=True) if args.nonneg_steps > 0 else None
+    abb = nonneg_extra(args.nonneg_steps, step="abb") if args.nonneg_steps > 0 else None
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -250,7 +251,8 @@ def main():
                   "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
                   "pls_attenuation_ms": round(pls_att_ms, 3), "pls_attenuation_iters": arep.iters,
                   "warm_start": warm, "batched": batched, "unrolled": unrolled,
-                  "siddon": siddon, "fbp": fbp, "nonneg": nonneg, "coupled_tv": coupled},
+                  "siddon": siddon, "fbp": fbp, "nonneg": nonneg, "coupled_tv": coupled,
+                  "abb_step": abb},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
@@ -306,18 +308,20 @@ def siddon_extra(steps: int, launches: int):
             "fwd_projection_us_2energies": round(fwd_ms * 1e3, 2)}
 
 
-def nonneg_extra(steps: int, coupled: bool = False):
+def nonneg_extra(steps: int, coupled: bool = False, step: str = "bb1"):
     """The metric workload with every f-step projected onto f >= 0
-    (DECT_NONNEG), or with the TV coupled across the energies
-    (DECT_COUPLED_TV): ADM iterations/s."""
+    (DECT_NONNEG), with the TV coupled across the energies (DECT_COUPLED_TV),
+    or with another BB step rule (DECT_STEP_BB2 / DECT_STEP_ABB): ADM
+    iterations/s."""
     import torch
 
     from paper_1607_01650_amd import configs as C, dect, phantom as P
 
     g = C.METRIC
     s = P.make_slice(g, 0)
-    p = dataclasses.replace(C.default_adm_params(g, steps), nonneg=not coupled,
-                            coupled_tv=coupled)
+    plain_step = step == "bb1"
+    p = dataclasses.replace(C.default_adm_params(g, steps), nonneg=not coupled and plain_step,
+                            coupled_tv=coupled, step=step)
     mh = torch.as_tensor(s.sino[0], dtype=torch.float32).cuda()
     ml = torch.as_tensor(s.sino[1], dtype=torch.float32).cuda()
     xh = torch.empty((g.ny, g.nx), device="cuda")
@@ -334,10 +338,11 @@ def nonneg_extra(steps: int, coupled: bool = False):
     torch.cuda.synchronize()
     ms = ev.ms(e0, e1) / steps
     state.close()
-    out = {"workload": "adm_tv_512x512_360views_736bins_2energies, "
-                       + ("TV coupled across energies" if coupled else "f >= 0"),
+    what = ("TV coupled across energies" if coupled else
+            "f >= 0" if plain_step else step + " step")
+    out = {"workload": "adm_tv_512x512_360views_736bins_2energies, " + what,
            "iters_per_s": round(1e3 / ms, 2), "ms_per_iteration": round(ms, 4), "steps": steps}
-    if not coupled:
+    if not coupled and plain_step:
         out["zero_pixels"] = int((xh == 0).sum().item() + (xl == 0).sum().item())
     return out
 
