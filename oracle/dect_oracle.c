@@ -887,3 +887,103 @@ void or_adm_coupled(const or_geom *g, const double *m, const double *beta, doubl
     }
     free(wx); free(wy); free(t1); free(s); free(y); free(p);
 }
+
+/* ----------------------------------------------------------- cone beam ---
+ * 3-D circular cone beam (the scanner geometry of Sec. 3; the slice model
+ * above is its central plane).  Source s = R (cos t, sin t, 0); flat detector
+ * centred at -(D - R)(cos t, sin t, 0) with axes e_u = (-sin t, cos t, 0) and
+ * e_v = (0, 0, 1); bin b of row j at u_b = (b - (B-1)/2) du + offset,
+ * v_j = (j - (J-1)/2) dv.  Volume nx x ny x nz cubic voxels of side `voxel`,
+ * centred on the isocentre, stored [z][y][x].  Joseph's model in 3-D: the ray
+ * steps along the in-plane axis it is more aligned with and, on each plane of
+ * that axis, interpolates bilinearly between the four nearest voxel centres
+ * (the other in-plane axis and z); samples are scaled by the path length per
+ * plane, voxel / |cos| of the angle to the driving axis; voxels outside the
+ * volume are zero.  Projections are [V][J][B].
+ */
+typedef struct {
+    int32_t nx, ny, nz;
+    double voxel;
+    int32_t n_views;
+    const double *angles;
+    int32_t n_bins, n_rows;
+    double bin, row, det_offset, sod, sdd;
+} or_geom3;
+
+static double cone_walk(const or_geom3 *g, int v, int j, int b, double *X, double y, int mode)
+{
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const double dl = g->voxel;
+    const double th = g->angles ? g->angles[v] : 2.0 * M_PI * v / g->n_views;
+    const double ct = cos(th), st = sin(th);
+    const double u = (b - (g->n_bins - 1) / 2.0) * g->bin + g->det_offset;
+    const double w = (j - (g->n_rows - 1) / 2.0) * g->row;
+    const double sx = g->sod * ct, sy = g->sod * st, sz = 0.0;
+    const double px = -(g->sdd - g->sod) * ct - u * st, py = -(g->sdd - g->sod) * st + u * ct;
+    const double pz = w;
+    const double dx = px - sx, dy = py - sy, dz = pz - sz;
+    const double len = sqrt(dx * dx + dy * dy + dz * dz);
+    const size_t plane = (size_t)nx * ny;
+    double acc = 0.0;
+    const int xmaj = fabs(dx) >= fabs(dy);
+    const int nl = xmaj ? nx : ny, nq = xmaj ? ny : nx;
+    const double L = dl * len / (xmaj ? fabs(dx) : fabs(dy));
+    for (int i = 0; i < nl; ++i) {
+        double t;  /* ray parameter at the plane's centre */
+        if (xmaj) t = ((i - (nx - 1) / 2.0) * dl - sx) / dx;
+        else t = ((i - (ny - 1) / 2.0) * dl - sy) / dy;
+        const double qa = (xmaj ? sy + t * dy : sx + t * dx) / dl + (nq - 1) / 2.0;
+        const double qz = (sz + t * dz) / dl + (nz - 1) / 2.0;
+        const double fa = floor(qa), fz = floor(qz);
+        const int a0 = (int)fa, z0 = (int)fz;
+        const double wa = qa - fa, wz = qz - fz;
+        for (int da = 0; da <= 1; ++da)
+            for (int dz2 = 0; dz2 <= 1; ++dz2) {
+                const int a = a0 + da, zz = z0 + dz2;
+                if (fa < -1.0 || fa > nq - 1.0 || fz < -1.0 || fz > nz - 1.0) continue;
+                if (a < 0 || a >= nq || zz < 0 || zz >= nz) continue;
+                const double wt = (da ? wa : 1.0 - wa) * (dz2 ? wz : 1.0 - wz);
+                const size_t idx = (size_t)zz * plane + (xmaj ? (size_t)a * nx + i : (size_t)i * nx + a);
+                if (mode == 0) acc += L * wt * X[idx];
+                else X[idx] += L * wt * y;
+            }
+    }
+    return acc;
+}
+
+/* proj[v][j][b] = (A vol) */
+void or_project3(const or_geom3 *g, const double *vol, double *proj)
+{
+    const int V = g->n_views, J = g->n_rows, B = g->n_bins;
+#pragma omp parallel for schedule(static)
+    for (int v = 0; v < V; ++v)
+        for (int j = 0; j < J; ++j)
+            for (int b = 0; b < B; ++b)
+                proj[((size_t)v * J + j) * B + b] = cone_walk(g, v, j, b, (double *)vol, 0.0, 0);
+}
+
+/* vol = A^T proj, views in fixed chunks with private volumes summed in order. */
+void or_backproject3(const or_geom3 *g, const double *proj, double *vol)
+{
+    const int V = g->n_views, J = g->n_rows, B = g->n_bins;
+    const size_t N = (size_t)g->nx * g->ny * g->nz;
+    int T = or_num_threads();
+    if (T > V) T = V;
+    if (T < 1) T = 1;
+    double *buf = (double *)calloc((size_t)T * N, sizeof(double));
+#pragma omp parallel for schedule(static, 1) num_threads(T)
+    for (int t = 0; t < T; ++t) {
+        int v0 = (int)((int64_t)V * t / T), v1 = (int)((int64_t)V * (t + 1) / T);
+        double *mine = buf + (size_t)t * N;
+        for (int v = v0; v < v1; ++v)
+            for (int j = 0; j < J; ++j)
+                for (int b = 0; b < B; ++b)
+                    cone_walk(g, v, j, b, mine, proj[((size_t)v * J + j) * B + b], 1);
+    }
+    for (size_t i = 0; i < N; ++i) {
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += buf[(size_t)t * N + i];
+        vol[i] = s;
+    }
+    free(buf);
+}

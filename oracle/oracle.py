@@ -37,6 +37,14 @@ class _Geom(ct.Structure):
                 ("sod", ct.c_double), ("sdd", ct.c_double), ("model", ct.c_int32)]
 
 
+class _Geom3(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("voxel", ct.c_double), ("n_views", ct.c_int32),
+                ("angles", ct.POINTER(ct.c_double)), ("n_bins", ct.c_int32),
+                ("n_rows", ct.c_int32), ("bin", ct.c_double), ("row", ct.c_double),
+                ("det_offset", ct.c_double), ("sod", ct.c_double), ("sdd", ct.c_double)]
+
+
 _lib = None
 
 
@@ -74,6 +82,8 @@ def lib():
                                  ct.c_int, d, pd]
         L.or_pcg_att.restype = ct.c_int
         L.or_adm_coupled.argtypes = [P(_Geom), pd, pd, d, d, d, ct.c_int, pd, pd, pd, ct.c_int]
+        L.or_project3.argtypes = [P(_Geom3), pd, pd]
+        L.or_backproject3.argtypes = [P(_Geom3), pd, pd]
         _lib = L
     return _lib
 
@@ -143,6 +153,37 @@ def fbp(g, sino: np.ndarray) -> np.ndarray:
     y = _f64(sino).reshape(og.n_views, og.n_bins)
     out = np.empty((og.ny, og.nx))
     lib().or_fbp(ct.byref(og.s), _p(y), _p(out))
+    return out
+
+
+class OGeom3:
+    """Cone-beam geometry in the oracle's struct (any object with the
+    ConeGeometry field names)."""
+
+    def __init__(self, g):
+        self.nx, self.ny, self.nz = int(g.nx), int(g.ny), int(g.nz)
+        self.n_views, self.n_bins, self.n_rows = int(g.n_views), int(g.n_bins), int(g.n_rows)
+        self._angles = None if g.angles_rad is None else _f64(g.angles_rad)
+        self.s = _Geom3(self.nx, self.ny, self.nz, float(g.voxel_mm), self.n_views,
+                        _p(self._angles), self.n_bins, self.n_rows, float(g.bin_mm),
+                        float(g.row_mm), float(g.det_offset_mm), float(g.sod_mm),
+                        float(g.sdd_mm))
+
+
+def project3(g, vol: np.ndarray) -> np.ndarray:
+    """Cone-beam Joseph projection of vol [nz][ny][nx] -> [V][rows][bins]."""
+    og = OGeom3(g)
+    x = _f64(vol).reshape(og.nz, og.ny, og.nx)
+    out = np.empty((og.n_views, og.n_rows, og.n_bins))
+    lib().or_project3(ct.byref(og.s), _p(x), _p(out))
+    return out
+
+
+def backproject3(g, proj: np.ndarray) -> np.ndarray:
+    og = OGeom3(g)
+    y = _f64(proj).reshape(og.n_views, og.n_rows, og.n_bins)
+    out = np.empty((og.nz, og.ny, og.nx))
+    lib().or_backproject3(ct.byref(og.s), _p(y), _p(out))
     return out
 
 

@@ -70,6 +70,35 @@ class Geometry:
 
 
 @dataclasses.dataclass(frozen=True)
+class ConeGeometry:
+    """3-D circular cone beam with a flat detector panel (the scanner of Sec. 3;
+    Geometry is its central plane).  Volume [nz][ny][nx] of cubic voxels
+    centred on the isocentre; projections [n_views][n_rows][n_bins]; detector
+    rows along z, row j at (j - (n_rows-1)/2) * row_mm."""
+
+    nx: int
+    ny: int
+    nz: int
+    voxel_mm: float
+    n_views: int
+    n_bins: int
+    n_rows: int
+    bin_mm: float
+    row_mm: float
+    sod_mm: float
+    sdd_mm: float
+    det_offset_mm: float = 0.0
+    angles_rad: Optional[Sequence[float]] = None
+
+    def central_plane(self) -> "Geometry":
+        """The 2-D fan-beam geometry of the source's plane (z = 0)."""
+        return Geometry(nx=self.nx, ny=self.ny, pixel_mm=self.voxel_mm, n_views=self.n_views,
+                        n_bins=self.n_bins, bin_mm=self.bin_mm, sod_mm=self.sod_mm,
+                        sdd_mm=self.sdd_mm, det_offset_mm=self.det_offset_mm,
+                        angles_rad=self.angles_rad)
+
+
+@dataclasses.dataclass(frozen=True)
 class AdmParams:
     """Parameters of the TV-regularised ADM reconstruction (Eqs. 3-10, Sec. 2.4).
 
