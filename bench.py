@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--nonneg-steps", type=int, default=100,
                     help="timed ADM iterations of the non-negative, coupled-TV and "
                          "adaptive-step variant entries (0: skip)")
+    ap.add_argument("--cone-launches", type=int, default=3,
+                    help="timed calls of each cone-beam projector (0: skip)")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -211,6 +213,7 @@ def main():
     nonneg = nonneg_extra(args.nonneg_steps) if args.nonneg_steps > 0 else None
     coupled = nonneg_extra(args.nonneg_steps, coupled=True) if args.nonneg_steps > 0 else None
     abb = nonneg_extra(args.nonneg_steps, step="abb") if args.nonneg_steps > 0 else None
+    cone = cone_extra(args.cone_launches) if args.cone_launches > 0 else None
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -252,7 +255,7 @@ def main():
                   "pls_attenuation_ms": round(pls_att_ms, 3), "pls_attenuation_iters": arep.iters,
                   "warm_start": warm, "batched": batched, "unrolled": unrolled,
                   "siddon": siddon, "fbp": fbp, "nonneg": nonneg, "coupled_tv": coupled,
-                  "abb_step": abb},
+                  "abb_step": abb, "cone": cone},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
@@ -345,6 +348,45 @@ def nonneg_extra(steps: int, coupled: bool = False, step: str = "bb1"):
     if not coupled and plain_step:
         out["zero_pixels"] = int((xh == 0).sum().item() + (xl == 0).sum().item())
     return out
+
+
+def cone_extra(launches: int):
+    """Cone-beam projector pair on a 512 x 512 x 64 volume, 360 views, 64 x 736
+    detector (the metric fan with 64 rows): time per forward and per
+    back-projection call, Joseph samples (ray, plane) per second, and the
+    rate of the algorithmic bytes (volume read once, projections written
+    once, or the reverse) against HBM."""
+    import torch
+
+    from paper_1607_01650_amd import configs as C, dect, phantom as P
+
+    g = C.CONE
+    vol = torch.as_tensor(P.cone_volume(g, 0, supersample=2), dtype=torch.float32).cuda()
+    proj = torch.empty((g.n_views, g.n_rows, g.n_bins), device="cuda")
+    back = torch.empty_like(vol)
+    sp = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ev = HipEvents()
+    dect.cone_project(vol, g, out=proj)
+    dect.cone_backproject(proj, g, out=back)
+    a0, a1, a2 = ev.event(), ev.event(), ev.event()
+    ev.record(a0, sp)
+    for _ in range(launches):
+        dect.cone_project(vol, g, out=proj)
+    ev.record(a1, sp)
+    for _ in range(launches):
+        dect.cone_backproject(proj, g, out=back)
+    ev.record(a2, sp)
+    torch.cuda.synchronize()
+    fwd_ms, adj_ms = ev.ms(a0, a1) / launches, ev.ms(a1, a2) / launches
+    rays = g.n_views * g.n_rows * g.n_bins
+    samples = rays * g.nx  # every ray steps over all planes of its driving axis (nx == ny)
+    nbytes = 4 * (g.nx * g.ny * g.nz + rays)
+    return {"workload": "cone_512x512x64_360views_64x736det", "launches": launches,
+            "fwd_ms": round(fwd_ms, 3), "back_ms": round(adj_ms, 3),
+            "fwd_gsamples_per_s": round(samples / fwd_ms / 1e6, 2),
+            "back_gsamples_per_s": round(samples / adj_ms / 1e6, 2),
+            "fwd_algorithmic_gbs": round(nbytes / fwd_ms / 1e6, 1),
+            "back_algorithmic_gbs": round(nbytes / adj_ms / 1e6, 1)}
 
 
 def fbp_extra(launches: int):

@@ -258,6 +258,52 @@ dect_status dect_batch_tune(dect_batch *batch, const float *const *d_m_high,
                             double *ms_per_iter, void *stream);
 dect_status dect_batch_set_groups(dect_batch *batch, int32_t groups);
 
+/*
+ * 3-D circular cone beam with a flat panel (the scanner of Sec. 3, of which
+ * dect_geometry is the central plane z = 0).  Source at SOD (cos t, sin t,
+ * 0); panel centred at -(SDD - SOD)(cos t, sin t, 0), bin b of row j at
+ * u_b = (b - (n_bins-1)/2) bin_mm + det_offset_mm along (-sin t, cos t, 0)
+ * and v_j = (j - (n_rows-1)/2) row_mm along z.  Volume [nz][ny][nx] of cubic
+ * voxels of side voxel_mm centred on the isocentre; projections
+ * [n_views][n_rows][n_bins].  angles_rad: NULL for 2 pi v / n_views, else
+ * n_views host values.  Checked: sizes positive (nx, ny, nz <= 4096, bins and
+ * rows <= 16384, views <= 65536), the orbit outside the volume, SDD > SOD,
+ * fan angle below 90 degrees and cone half-angle below atan(1/2) (so the
+ * height never drives a ray).
+ */
+typedef struct {
+    int32_t nx, ny, nz;
+    double voxel_mm;
+    int32_t n_views;
+    const double *angles_rad;
+    int32_t n_bins, n_rows;
+    double bin_mm, row_mm, det_offset_mm, sod_mm, sdd_mm;
+} dect_cone_geometry;
+
+/*
+ * Cone-beam forward projection d_proj = A3 d_vol: Joseph's model (Sec. 2.4's
+ * projector) carried to 3-D -- each ray steps along the in-plane axis it is
+ * more aligned with and, on every plane of that axis, interpolates
+ * bilinearly between the four nearest voxel centres (other in-plane axis and
+ * height), scaled by the path length per plane; outside the volume is zero.
+ * Device buffers: d_vol [nz][ny][nx], d_proj [n_views][n_rows][n_bins]
+ * (caller-owned, not aliased).  Uses a library-owned workspace per (device,
+ * stream) holding two padded copies of the volume.  Asynchronous on
+ * `stream` except when the view table changes (then the stream is
+ * synchronised once).
+ */
+dect_status dect_cone_project(const dect_cone_geometry *geom, const float *d_vol, float *d_proj,
+                              void *stream);
+
+/*
+ * Cone-beam back-projection d_vol = A3^T d_proj with the forward pass's
+ * weights, scattered with float atomics: the transpose of dect_cone_project's
+ * matrix up to FP32 rounding, whose summation order (and so the last bits)
+ * varies from run to run.  d_vol is overwritten.
+ */
+dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d_proj,
+                                  float *d_vol, void *stream);
+
 /* Number of Joseph samples (ray, line) with the crossing inside (-1, n)
  * for a geometry: the unit of projector work. */
 dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);

@@ -163,10 +163,21 @@ def object_radius_mm(geom: Geometry) -> float:
     return 230.0 * geom.nx / 512.0
 
 
+def paper_cone_geometry(n: int = 512, nz: int = 64, n_views: int = 360,
+                        n_rows: int = 64) -> ConeGeometry:
+    """Multi-row version of paper_geometry: the same fan (SOD 1000 mm, SDD
+    2000 mm, 2.4 mm bins, 1 mm voxels) with n_rows rows of 2.4 mm, which
+    cover n_rows * 1.2 mm of height at the isocentre, and nz slices."""
+    return ConeGeometry(nx=n, ny=n, nz=nz, voxel_mm=1.0, n_views=n_views,
+                        n_bins=int(round(1.4375 * n)), n_rows=n_rows, bin_mm=2.4, row_mm=2.4,
+                        sod_mm=1000.0, sdd_mm=2000.0)
+
+
 METRIC = paper_geometry(512, 360)          # ADM-TV iterations/s are quoted here
 PAPER_SPARSE = paper_geometry(512, 90)
 PAPER_FULL = paper_geometry(512, 720)
 UNROLLED = paper_geometry(512, 180)
+CONE = paper_cone_geometry(512, 64, 360, 64)  # cone-beam projector pair timings
 
 BATCH_SIZES = (256, 384, 512)
 BATCH_VIEWS = (60, 90, 180, 360)

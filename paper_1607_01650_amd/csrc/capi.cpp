@@ -82,6 +82,20 @@ dect_status dect_fbp(const dect_geometry *geom, const float *d_sino, float *d_im
     return dect::fbp(geom, d_sino, d_img, batch, (hipStream_t)stream);
 }
 
+dect_status dect_cone_project(const dect_cone_geometry *geom, const float *d_vol, float *d_proj,
+                              void *stream)
+{
+    dect::set_error("");
+    return dect::cone_project(geom, d_vol, d_proj, (hipStream_t)stream);
+}
+
+dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d_proj,
+                                  float *d_vol, void *stream)
+{
+    dect::set_error("");
+    return dect::cone_backproject(geom, d_proj, d_vol, (hipStream_t)stream);
+}
+
 dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
                         const dect_adm_params *params, float *d_x_high, float *d_x_low,
                         dect_adm_state *state, dect_report *rep, void *stream)

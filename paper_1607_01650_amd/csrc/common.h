@@ -205,6 +205,10 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
 dect_status project(const dect_geometry *g, const float *img, float *sino, int batch,
                     hipStream_t s);
 dect_status fbp(const dect_geometry *g, const float *sino, float *img, int batch, hipStream_t s);
+dect_status cone_project(const dect_cone_geometry *g, const float *vol, float *proj,
+                         hipStream_t s);
+dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, float *vol,
+                             hipStream_t s);
 dect_status backproject(const dect_geometry *g, const float *sino, float *img, int batch,
                         hipStream_t s);
 

@@ -1,0 +1,299 @@
+// Cone-beam Joseph projector pair for the 3-D circular scan (the scanner of
+// Sec. 3; the fan-beam path is its central plane) on gfx950.
+//
+// Source s = R (cos t, sin t, 0); flat panel centred at -(D - R)(cos t, sin t,
+// 0), bin b of row j at u_b = (b - (B-1)/2) du + offset along (-sin t, cos t,
+// 0) and v_j = (j - (J-1)/2) dv along z.  Volume [nz][ny][nx] of cubic voxels,
+// projections [V][J][B].  Each ray steps along the in-plane axis it is more
+// aligned with; on every plane of that axis its crossing (in-plane coordinate
+// and height) is interpolated bilinearly between the four nearest voxel
+// centres, and the samples are scaled by the path length per plane.
+//
+//   k_cone_pad : two zero-padded permuted copies of the volume, [x][z][y] for
+//                x-major rays and [y][z][x] for y-major rays, so that a
+//                sample's two in-plane taps are adjacent (borders written as
+//                zeros by the same kernel: no memset in the path).
+//   k_cone_fwd : one thread per ray (64 adjacent bins of one row per
+//                wavefront); the ray's constants are formed in FP64 from the
+//                view's cos/sin and turned into 32.32 fixed point (in-plane
+//                coordinate and height per plane), stepped by integer adds;
+//                FP32 bilinear samples summed in FP64.
+//   k_cone_adj : the same walk with the same FP32 weights, every weighted
+//                sample added to its voxels with hardware float atomics
+//                (the transpose of the forward matrix; the summation order,
+//                and so the last bits, vary from run to run).
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace dect {
+namespace {
+
+constexpr int kCPad = 2;  // zero lines on each side of the padded copies
+constexpr double kTwo32c = 4294967296.0;
+constexpr float kTwoM32c = 2.3283064365386963e-10f;
+
+struct ConeDev {
+    int nx, ny, nz, V, J, B;
+    double voxel, bin, row, off, sod, sdd;
+    const double *cs;  // [V][2] cos, sin of the view angle
+};
+
+struct ConeRay {
+    int64_t a, k, az, kz;  // 32.32 in-plane coordinate and height at plane 0, steps
+    float L;               // path length per plane
+    int xmaj;
+};
+
+__device__ __forceinline__ ConeRay cone_ray(const ConeDev &g, int v, int j, int b)
+{
+    const double ct = g.cs[2 * v], st = g.cs[2 * v + 1];
+    const double u = (b - (g.B - 1) / 2.0) * g.bin + g.off;
+    const double w = (j - (g.J - 1) / 2.0) * g.row;
+    const double sx = g.sod * ct, sy = g.sod * st;
+    const double px = -(g.sdd - g.sod) * ct - u * st, py = -(g.sdd - g.sod) * st + u * ct;
+    const double dx = px - sx, dy = py - sy, dz = w;
+    const double len = sqrt(dx * dx + dy * dy + dz * dz);
+    ConeRay r;
+    r.xmaj = fabs(dx) >= fabs(dy);
+    double a, k, kz, az;
+    if (r.xmaj) {
+        k = dy / dx;
+        kz = dz / dx;
+        const double x0 = (0 - (g.nx - 1) / 2.0) * g.voxel;
+        a = (sy + (x0 - sx) * k) / g.voxel + (g.ny - 1) / 2.0;
+        az = ((x0 - sx) * kz) / g.voxel + (g.nz - 1) / 2.0;
+        r.L = (float)(g.voxel * len / fabs(dx));
+    } else {
+        k = dx / dy;
+        kz = dz / dy;
+        const double y0 = (0 - (g.ny - 1) / 2.0) * g.voxel;
+        a = (sx + (y0 - sy) * k) / g.voxel + (g.nx - 1) / 2.0;
+        az = ((y0 - sy) * kz) / g.voxel + (g.nz - 1) / 2.0;
+        r.L = (float)(g.voxel * len / fabs(dy));
+    }
+    // |a|, |az| stay far below 2^31 for validated geometries (rays outside
+    // the volume are clamped to a far coordinate and contribute zero)
+    a = fmin(fmax(a, -1.0e6), 1.0e6);
+    az = fmin(fmax(az, -1.0e6), 1.0e6);
+    r.a = __double2ll_rn(a * kTwo32c);
+    r.k = __double2ll_rn(k * kTwo32c);
+    r.az = __double2ll_rn(az * kTwo32c);
+    r.kz = __double2ll_rn(kz * kTwo32c);
+    return r;
+}
+
+// vol [nz][ny][nx] -> vx [nx][nz+4][ny+4] and vy [ny][nz+4][nx+4], written
+// whole (zero borders included), one thread per element of the larger copy.
+__global__ __launch_bounds__(256) void k_cone_pad(const float *__restrict__ vol, int nx, int ny,
+                                                  int nz, float *__restrict__ vx,
+                                                  float *__restrict__ vy)
+{
+    const int pz = nz + 2 * kCPad, py = ny + 2 * kCPad, px = nx + 2 * kCPad;
+    const size_t nvx = (size_t)nx * pz * py, nvy = (size_t)ny * pz * px;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < nvx) {  // vx: y fastest
+        const int yy = (int)(i % py) - kCPad, zz = (int)(i / py % pz) - kCPad;
+        const int x = (int)(i / ((size_t)py * pz));
+        vx[i] = (yy >= 0 && yy < ny && zz >= 0 && zz < nz)
+                    ? vol[((size_t)zz * ny + yy) * nx + x] : 0.f;
+    }
+    if (i < nvy) {  // vy: x fastest
+        const int xx = (int)(i % px) - kCPad, zz = (int)(i / px % pz) - kCPad;
+        const int y = (int)(i / ((size_t)px * pz));
+        vy[i] = (xx >= 0 && xx < nx && zz >= 0 && zz < nz)
+                    ? vol[((size_t)zz * ny + y) * nx + xx] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cone_zero(float *__restrict__ p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ vx,
+                                                  const float *__restrict__ vy,
+                                                  float *__restrict__ proj)
+{
+    const size_t nray = (size_t)g.V * g.J * g.B;
+    const size_t rid = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (rid >= nray) return;
+    const int b = (int)(rid % g.B), j = (int)(rid / g.B % g.J), v = (int)(rid / ((size_t)g.B * g.J));
+    const ConeRay r = cone_ray(g, v, j, b);
+    const int nl = r.xmaj ? g.nx : g.ny, nq = r.xmaj ? g.ny : g.nx;
+    const int pq = nq + 2 * kCPad, pz = g.nz + 2 * kCPad;
+    const float *base = r.xmaj ? vx : vy;
+    int64_t q = r.a, qz = r.az;
+    double acc = 0.0;
+    for (int i0 = 0; i0 < nl; i0 += 4) {
+        float s = 0.f;
+        const int i1 = min(nl, i0 + 4);
+        for (int i = i0; i < i1; ++i) {
+            const int h = min(max((int)(q >> 32), -2), nq);
+            const int hz = min(max((int)(qz >> 32), -2), g.nz);
+            const float wa = (float)(uint32_t)q * kTwoM32c;
+            const float wz = (float)(uint32_t)qz * kTwoM32c;
+            const float *p0 = base + ((size_t)i * pz + hz + kCPad) * pq + h + kCPad;
+            const float *p1 = p0 + pq;
+            const float lo = fmaf(wa, p0[1] - p0[0], p0[0]);
+            const float hi = fmaf(wa, p1[1] - p1[0], p1[0]);
+            s += fmaf(wz, hi - lo, lo);
+            q += r.k;
+            qz += r.kz;
+        }
+        acc += (double)s;
+    }
+    proj[rid] = (float)(acc * (double)r.L);
+}
+
+__global__ __launch_bounds__(256) void k_cone_adj(ConeDev g, const float *__restrict__ proj,
+                                                  float *__restrict__ vol)
+{
+    const size_t nray = (size_t)g.V * g.J * g.B;
+    const size_t rid = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (rid >= nray) return;
+    const float yv = proj[rid];
+    if (yv == 0.f) return;
+    const int b = (int)(rid % g.B), j = (int)(rid / g.B % g.J), v = (int)(rid / ((size_t)g.B * g.J));
+    const ConeRay r = cone_ray(g, v, j, b);
+    const int nl = r.xmaj ? g.nx : g.ny, nq = r.xmaj ? g.ny : g.nx;
+    const float ly = r.L * yv;
+    int64_t q = r.a, qz = r.az;
+    for (int i = 0; i < nl; ++i) {
+        const int h = (int)(q >> 32), hz = (int)(qz >> 32);
+        if (h >= -1 && h <= nq - 1 && hz >= -1 && hz <= g.nz - 1) {
+            const float wa = (float)(uint32_t)q * kTwoM32c;
+            const float wz = (float)(uint32_t)qz * kTwoM32c;
+            const float w[2][2] = {{(1.f - wa) * (1.f - wz), wa * (1.f - wz)},
+                                   {(1.f - wa) * wz, wa * wz}};
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int da = 0; da < 2; ++da) {
+                    const int aa = h + da, zz = hz + dz;
+                    if (aa < 0 || aa >= nq || zz < 0 || zz >= g.nz) continue;
+                    const size_t idx = (size_t)zz * g.nx * g.ny +
+                                       (r.xmaj ? (size_t)aa * g.nx + i : (size_t)i * g.nx + aa);
+                    unsafeAtomicAdd(vol + idx, ly * w[dz][da]);
+                }
+        }
+        q += r.k;
+        qz += r.kz;
+    }
+}
+
+struct ConeWork {
+    DevBuf vx, vy, cs;
+    std::vector<double> cs_host;  // what cs holds
+};
+
+std::mutex g_cone_mu;
+std::vector<std::pair<std::pair<int, hipStream_t>, std::unique_ptr<ConeWork>>> g_cone_ws;
+
+ConeWork *cone_workspace(hipStream_t s)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (auto &p : g_cone_ws)
+        if (p.first.first == dev && p.first.second == s) return p.second.get();
+    g_cone_ws.emplace_back(std::make_pair(dev, s), std::make_unique<ConeWork>());
+    return g_cone_ws.back().second.get();
+}
+
+dect_status cone_setup(const dect_cone_geometry *g, ConeDev &d, ConeWork *w, hipStream_t s)
+{
+    if (!g) return fail(DECT_ERR_INVALID_ARG, "cone geometry is NULL");
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || g->n_views <= 0 || g->n_bins <= 0 ||
+        g->n_rows <= 0)
+        return fail(DECT_ERR_INVALID_ARG, "cone geometry sizes must be positive");
+    if (g->nx > 4096 || g->ny > 4096 || g->nz > 4096 || g->n_bins > 16384 || g->n_rows > 16384 ||
+        g->n_views > 65536)
+        return fail(DECT_ERR_INVALID_ARG, "cone geometry sizes exceed the supported maximum");
+    if (!(g->voxel_mm > 0.0) || !(g->bin_mm > 0.0) || !(g->row_mm > 0.0) ||
+        !std::isfinite(g->det_offset_mm))
+        return fail(DECT_ERR_INVALID_ARG, "voxel, bin and row sizes must be positive");
+    const double hx = 0.5 * g->nx * g->voxel_mm, hy = 0.5 * g->ny * g->voxel_mm;
+    if (!(g->sod_mm > std::sqrt(hx * hx + hy * hy)) || !std::isfinite(g->sod_mm))
+        return fail(DECT_ERR_GEOMETRY, "source orbit (SOD) must lie outside the volume");
+    if (!(g->sdd_mm > g->sod_mm) || !std::isfinite(g->sdd_mm))
+        return fail(DECT_ERR_GEOMETRY, "SDD must exceed SOD");
+    const double hu = 0.5 * g->n_bins * g->bin_mm + std::fabs(g->det_offset_mm);
+    const double hv = 0.5 * g->n_rows * g->row_mm;
+    if (!(std::atan(hu / g->sdd_mm) < 0.25 * M_PI))
+        return fail(DECT_ERR_GEOMETRY, "fan angle must be below 90 degrees");
+    // the height never becomes the driving axis: |dz| < |d_in-plane| on every ray
+    if (!(hv < 0.5 * g->sdd_mm))
+        return fail(DECT_ERR_GEOMETRY, "cone half-angle must be below atan(1/2)");
+    std::vector<double> cs(2 * (size_t)g->n_views);
+    for (int v = 0; v < g->n_views; ++v) {
+        const double th = g->angles_rad ? g->angles_rad[v] : 2.0 * M_PI * v / g->n_views;
+        if (!std::isfinite(th)) return fail(DECT_ERR_INVALID_ARG, "view angles must be finite");
+        cs[2 * v] = std::cos(th);
+        cs[2 * v + 1] = std::sin(th);
+    }
+    if (cs != w->cs_host) {
+        // kernels in flight on this stream may still read the old table
+        DECT_HIP(hipStreamSynchronize(s));
+        dect_status st = w->cs.ensure(cs.size() * 8);
+        if (st) return st;
+        DECT_HIP(hipMemcpy(w->cs.ptr, cs.data(), cs.size() * 8, hipMemcpyHostToDevice));
+        w->cs_host = cs;
+    }
+    d = ConeDev{g->nx, g->ny, g->nz, g->n_views, g->n_rows, g->n_bins, g->voxel_mm, g->bin_mm,
+                g->row_mm, g->det_offset_mm, g->sod_mm, g->sdd_mm, (const double *)w->cs.ptr};
+    return DECT_OK;
+}
+
+}  // namespace
+
+dect_status cone_project(const dect_cone_geometry *g, const float *vol, float *proj,
+                         hipStream_t s)
+{
+    if (!vol || !proj) return fail(DECT_ERR_INVALID_ARG, "dect_cone_project: null buffer");
+    std::lock_guard<std::mutex> lk(g_cone_mu);
+    ConeWork *w = cone_workspace(s);
+    ConeDev d;
+    dect_status st = cone_setup(g, d, w, s);
+    if (st) return st;
+    const size_t pz = d.nz + 2 * kCPad;
+    const size_t nxb = (size_t)d.nx * pz * (d.ny + 2 * kCPad) * 4;
+    const size_t nyb = (size_t)d.ny * pz * (d.nx + 2 * kCPad) * 4;
+    if (w->vx.bytes < nxb || w->vy.bytes < nyb) {
+        DECT_HIP(hipStreamSynchronize(s));
+        if ((st = w->vx.ensure(nxb)) || (st = w->vy.ensure(nyb))) return st;
+    }
+    const size_t npad = std::max(nxb, nyb) / 4;
+    hipLaunchKernelGGL(k_cone_pad, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, vol,
+                       d.nx, d.ny, d.nz, (float *)w->vx.ptr, (float *)w->vy.ptr);
+    DECT_HIP(hipGetLastError());
+    const size_t nray = (size_t)d.V * d.J * d.B;
+    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
+                       (const float *)w->vx.ptr, (const float *)w->vy.ptr, proj);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, float *vol,
+                             hipStream_t s)
+{
+    if (!vol || !proj) return fail(DECT_ERR_INVALID_ARG, "dect_cone_backproject: null buffer");
+    std::lock_guard<std::mutex> lk(g_cone_mu);
+    ConeWork *w = cone_workspace(s);
+    ConeDev d;
+    dect_status st = cone_setup(g, d, w, s);
+    if (st) return st;
+    const size_t N = (size_t)d.nx * d.ny * d.nz;
+    hipLaunchKernelGGL(k_cone_zero, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, vol, N);
+    DECT_HIP(hipGetLastError());
+    const size_t nray = (size_t)d.V * d.J * d.B;
+    hipLaunchKernelGGL(k_cone_adj, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d, proj,
+                       vol);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+}  // namespace dect

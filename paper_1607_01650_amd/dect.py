@@ -47,6 +47,14 @@ class dect_geometry(ct.Structure):
                 ("sod_mm", ct.c_double), ("sdd_mm", ct.c_double), ("model", ct.c_int32)]
 
 
+class dect_cone_geometry(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("voxel_mm", ct.c_double), ("n_views", ct.c_int32),
+                ("angles_rad", ct.POINTER(ct.c_double)), ("n_bins", ct.c_int32),
+                ("n_rows", ct.c_int32), ("bin_mm", ct.c_double), ("row_mm", ct.c_double),
+                ("det_offset_mm", ct.c_double), ("sod_mm", ct.c_double), ("sdd_mm", ct.c_double)]
+
+
 class dect_adm_params(ct.Structure):
     _fields_ = [("mu", ct.c_double), ("rho", ct.c_double), ("xi", ct.c_double),
                 ("beta_high", ct.c_double), ("beta_low", ct.c_double), ("max_iter", ct.c_int32),
@@ -73,6 +81,10 @@ SIGNATURES = {
     "dect_backproject": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, ct.c_int32,
                                     ct.c_void_p]),
     "dect_fbp": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p]),
+    "dect_cone_project": (ct.c_int, [_P(dect_cone_geometry), ct.c_void_p, ct.c_void_p,
+                                     ct.c_void_p]),
+    "dect_cone_backproject": (ct.c_int, [_P(dect_cone_geometry), ct.c_void_p, ct.c_void_p,
+                                         ct.c_void_p]),
     "dect_adm_tv": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, _P(dect_adm_params),
                                ct.c_void_p, ct.c_void_p, ct.c_void_p, _P(dect_report),
                                ct.c_void_p]),
@@ -224,6 +236,56 @@ def fbp(sino, geom: C.Geometry, out=None):
         return out
     _check(lib().dect_fbp(GeomArg(geom).ref, ct.c_void_p(sino.data_ptr()),
                           ct.c_void_p(out.data_ptr()), b, _stream()), "dect_fbp")
+    return out
+
+
+class ConeArg:
+    """A dect_cone_geometry struct plus the angle array it points to."""
+
+    def __init__(self, g: C.ConeGeometry):
+        self._angles = None
+        ap = None
+        if g.angles_rad is not None:
+            self._angles = np.ascontiguousarray(g.angles_rad, dtype=np.float64)
+            ap = self._angles.ctypes.data_as(ct.POINTER(ct.c_double))
+        self.s = dect_cone_geometry(g.nx, g.ny, g.nz, g.voxel_mm, g.n_views, ap, g.n_bins,
+                                    g.n_rows, g.bin_mm, g.row_mm, g.det_offset_mm, g.sod_mm,
+                                    g.sdd_mm)
+
+    @property
+    def ref(self):
+        return ct.byref(self.s)
+
+
+def cone_project(vol, geom: C.ConeGeometry, out=None):
+    """Cone-beam projection of a volume [nz, ny, nx] -> [V, rows, bins]
+    (dect_cone_project)."""
+    torch = _torch()
+    _dev(vol, "vol", (geom.nz, geom.ny, geom.nx))
+    if vol.dim() != 3:
+        raise ValueError("vol must be [nz, ny, nx]")
+    if out is None:
+        out = torch.empty((geom.n_views, geom.n_rows, geom.n_bins), device=vol.device,
+                          dtype=torch.float32)
+    _dev(out, "out", (geom.n_views, geom.n_rows, geom.n_bins))
+    _check(lib().dect_cone_project(ConeArg(geom).ref, ct.c_void_p(vol.data_ptr()),
+                                   ct.c_void_p(out.data_ptr()), _stream()), "dect_cone_project")
+    return out
+
+
+def cone_backproject(proj, geom: C.ConeGeometry, out=None):
+    """Cone-beam back-projection [V, rows, bins] -> [nz, ny, nx]
+    (dect_cone_backproject; float atomics, last bits vary run to run)."""
+    torch = _torch()
+    _dev(proj, "proj", (geom.n_views, geom.n_rows, geom.n_bins))
+    if proj.dim() != 3:
+        raise ValueError("proj must be [V, rows, bins]")
+    if out is None:
+        out = torch.empty((geom.nz, geom.ny, geom.nx), device=proj.device, dtype=torch.float32)
+    _dev(out, "out", (geom.nz, geom.ny, geom.nx))
+    _check(lib().dect_cone_backproject(ConeArg(geom).ref, ct.c_void_p(proj.data_ptr()),
+                                       ct.c_void_p(out.data_ptr()), _stream()),
+           "dect_cone_backproject")
     return out
 
 

@@ -232,3 +232,14 @@ def random_image(geom: C.Geometry, seed: int, dtype=np.float64) -> np.ndarray:
 def random_sino(geom: C.Geometry, seed: int, dtype=np.float64) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.standard_normal((geom.n_views, geom.n_bins)).astype(dtype)
+
+
+def cone_volume(geom: C.ConeGeometry, seed: int, supersample: int = 4) -> np.ndarray:
+    """Seeded 3-D test object [nz][ny][nx] (high-energy attenuation, 1/mm):
+    the in-plane phantom of make_phantom, extruded over the central 70% of
+    the volume's height (flat ends), zero above and below."""
+    g2 = geom.central_plane()
+    img = rasterize(make_phantom(seed, C.object_radius_mm(g2)), g2, 0, supersample)
+    z = (np.arange(geom.nz) - (geom.nz - 1) / 2.0) * geom.voxel_mm
+    on = (np.abs(z) <= 0.35 * geom.nz * geom.voxel_mm).astype(np.float64)
+    return on[:, None, None] * img[None]
