@@ -296,10 +296,12 @@ dect_status dect_cone_project(const dect_cone_geometry *geom, const float *d_vol
                               void *stream);
 
 /*
- * Cone-beam back-projection d_vol = A3^T d_proj with the forward pass's
- * weights, scattered with float atomics: the transpose of dect_cone_project's
- * matrix up to FP32 rounding, whose summation order (and so the last bits)
- * varies from run to run.  d_vol is overwritten.
+ * Cone-beam back-projection d_vol = A3^T d_proj: the transpose of
+ * dect_cone_project's matrix in gather form -- every voxel sums over the
+ * rays that reach it, with the forward pass's in-plane interpolation weight
+ * (the same 32.32 coordinate) and its height weight evaluated in FP64; no
+ * atomics, so repeated calls agree bit for bit.  d_vol is overwritten.
+ * Uses the workspace of dect_cone_project plus a scaled copy of d_proj.
  */
 dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d_proj,
                                   float *d_vol, void *stream);

@@ -18,10 +18,11 @@
 //                view's cos/sin and turned into 32.32 fixed point (in-plane
 //                coordinate and height per plane), stepped by integer adds;
 //                FP32 bilinear samples summed in FP64.
-//   k_cone_adj : the same walk with the same FP32 weights, every weighted
-//                sample added to its voxels with hardware float atomics
-//                (the transpose of the forward matrix; the summation order,
-//                and so the last bits, vary from run to run).
+//   k_cone_tab, k_cone_scale, k_cone_gather : the transpose in gather form
+//                (no atomics, the same result on every run): per-(view, bin)
+//                ray constants, projections times each ray's path length,
+//                then one thread per voxel column and 8 slices sums over
+//                the rays that reach it (see k_cone_gather).
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -109,12 +110,6 @@ __global__ __launch_bounds__(256) void k_cone_pad(const float *__restrict__ vol,
     }
 }
 
-__global__ __launch_bounds__(256) void k_cone_zero(float *__restrict__ p, size_t n)
-{
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = 0.f;
-}
-
 __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ vx,
                                                   const float *__restrict__ vy,
                                                   float *__restrict__ proj)
@@ -150,44 +145,140 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
     proj[rid] = (float)(acc * (double)r.L);
 }
 
-__global__ __launch_bounds__(256) void k_cone_adj(ConeDev g, const float *__restrict__ proj,
-                                                  float *__restrict__ vol)
+// Per (view, bin): the ray's 32.32 in-plane coordinate at plane 0 and its
+// step (as in the forward walk), its class, and the height coefficients:
+// at plane p the ray's height is qz = w * (g0 + g1 p) + (nz - 1)/2 voxels,
+// w the row's height on the panel.
+struct ConeTab {
+    int64_t a, k;
+    double g0, g1;
+    int32_t xmaj, pad;
+};
+
+__global__ __launch_bounds__(256) void k_cone_tab(ConeDev g, ConeTab *__restrict__ tab)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.V * g.B) return;
+    const int v = i / g.B, b = i % g.B;
+    const ConeRay r = cone_ray(g, v, 0, b);  // in-plane terms do not depend on the row
+    const double ct = g.cs[2 * v], st = g.cs[2 * v + 1];
+    const double u = (b - (g.B - 1) / 2.0) * g.bin + g.off;
+    const double sx = g.sod * ct, sy = g.sod * st;
+    const double dx = -(g.sdd - g.sod) * ct - u * st - sx;
+    const double dy = -(g.sdd - g.sod) * st + u * ct - sy;
+    const double dp = r.xmaj ? dx : dy, sp = r.xmaj ? sx : sy;
+    const int np = r.xmaj ? g.nx : g.ny;
+    ConeTab t;
+    t.a = r.a;
+    t.k = r.k;
+    t.g0 = ((0 - (np - 1) / 2.0) * g.voxel - sp) / (dp * g.voxel);
+    t.g1 = 1.0 / dp;
+    t.xmaj = r.xmaj;
+    t.pad = 0;
+    tab[i] = t;
+}
+
+// yl = L * proj, L the forward walk's path length per plane of each ray.
+__global__ __launch_bounds__(256) void k_cone_scale(ConeDev g, const float *__restrict__ proj,
+                                                    float *__restrict__ yl)
 {
     const size_t nray = (size_t)g.V * g.J * g.B;
     const size_t rid = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (rid >= nray) return;
-    const float yv = proj[rid];
-    if (yv == 0.f) return;
     const int b = (int)(rid % g.B), j = (int)(rid / g.B % g.J), v = (int)(rid / ((size_t)g.B * g.J));
-    const ConeRay r = cone_ray(g, v, j, b);
-    const int nl = r.xmaj ? g.nx : g.ny, nq = r.xmaj ? g.ny : g.nx;
-    const float ly = r.L * yv;
-    int64_t q = r.a, qz = r.az;
-    for (int i = 0; i < nl; ++i) {
-        const int h = (int)(q >> 32), hz = (int)(qz >> 32);
-        if (h >= -1 && h <= nq - 1 && hz >= -1 && hz <= g.nz - 1) {
+    yl[rid] = proj[rid] * cone_ray(g, v, j, b).L;
+}
+
+constexpr int kZC = 8;  // slices per gather thread
+
+// vol = A3^T proj in gather form.  Thread: voxel column (x, y), slices
+// [z0, z0 + kZC); lanes along x.  Per view, the rays that can reach the
+// column cross the segments (x, y -+ 1) (x-major rays, on plane x) or
+// (x -+ 1, y) (y-major rays, on plane y); their bins lie between the
+// panel positions of those four points.  Every candidate is checked against
+// its exact 32.32 in-plane coordinate (the forward's interpolation weight);
+// the rows reaching slice z are those whose height on the ray's plane lies
+// in [z - 1, z + 1), evaluated in FP64.  Per-view sums in FP32, accumulated
+// over views in FP64.
+__global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *__restrict__ tab,
+                                                     const float *__restrict__ yl,
+                                                     float *__restrict__ vol)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y;
+    const int z0 = (blockIdx.z * 4 + (threadIdx.x >> 6)) * kZC;
+    if (x >= g.nx || z0 >= g.nz) return;
+    const float vox = (float)g.voxel;
+    const float px = (x - (g.nx - 1) * 0.5f) * vox, py = (y - (g.ny - 1) * 0.5f) * vox;
+    const float R = (float)g.sod, D = (float)g.sdd;
+    const float ibin = (float)(1.0 / g.bin), bc = (float)((g.B - 1) / 2.0 - g.off / g.bin);
+    const double cz = (g.nz - 1) / 2.0, jc = (g.J - 1) / 2.0;
+    const size_t JB = (size_t)g.J * g.B;
+    double acc[kZC];
+#pragma unroll
+    for (int t = 0; t < kZC; ++t) acc[t] = 0.0;
+    for (int v = 0; v < g.V; ++v) {
+        const float ct = (float)g.cs[2 * v], st = (float)g.cs[2 * v + 1];
+        const float sx = R * ct, sy = R * st;
+        // continuous bin of the ray through (qx, qy)
+        auto bin_of = [&](float qx, float qy) {
+            const float rx = qx - sx, ry = qy - sy;
+            return -D * (ry * ct - rx * st) / (rx * ct + ry * st) * ibin + bc;
+        };
+        const float b1 = bin_of(px, py - vox), b2 = bin_of(px, py + vox);
+        const float b3 = bin_of(px - vox, py), b4 = bin_of(px + vox, py);
+        const float bmin = fminf(fminf(b1, b2), fminf(b3, b4));
+        const float bmax = fmaxf(fmaxf(b1, b2), fmaxf(b3, b4));
+        // clamped before conversion (bounds only; the exact test below decides)
+        const int bl = max(0, (int)ceilf(fminf(fmaxf(bmin - 1e-3f, -1.f), (float)g.B)));
+        const int bh = min(g.B - 1, (int)floorf(fminf(fmaxf(bmax + 1e-3f, -1.f), (float)g.B)));
+        float part[kZC];
+#pragma unroll
+        for (int t = 0; t < kZC; ++t) part[t] = 0.f;
+        const ConeTab *tv = tab + (size_t)v * g.B;
+        const float *yv = yl + (size_t)v * JB;
+        for (int b = bl; b <= bh; ++b) {
+            const ConeTab tb = tv[b];
+            const int pl = tb.xmaj ? x : y, c = tb.xmaj ? y : x;
+            const int64_t q = tb.a + tb.k * pl;
+            const int h = (int)(q >> 32);
+            if (h != c && h != c - 1) continue;
             const float wa = (float)(uint32_t)q * kTwoM32c;
-            const float wz = (float)(uint32_t)qz * kTwoM32c;
-            const float w[2][2] = {{(1.f - wa) * (1.f - wz), wa * (1.f - wz)},
-                                   {(1.f - wa) * wz, wa * wz}};
+            const float wi = (h == c) ? 1.f - wa : wa;
+            const double sb = (tb.g0 + tb.g1 * pl) * g.row;  // height step per row (> 0)
+            const double qz0 = cz - jc * sb;                  // height of row 0
+            const float isb = (float)(1.0 / sb);
+            const float lo0 = (float)(z0 - 1 - qz0) * isb;
+            const float *yb = yv + b;
 #pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-                for (int da = 0; da < 2; ++da) {
-                    const int aa = h + da, zz = hz + dz;
-                    if (aa < 0 || aa >= nq || zz < 0 || zz >= g.nz) continue;
-                    const size_t idx = (size_t)zz * g.nx * g.ny +
-                                       (r.xmaj ? (size_t)aa * g.nx + i : (size_t)i * g.nx + aa);
-                    unsafeAtomicAdd(vol + idx, ly * w[dz][da]);
+            for (int t = 0; t < kZC; ++t) {
+                const int z = z0 + t;
+                const float lo = lo0 + t * isb, hi = lo + 2.f * isb;
+                const int j0 = max(0, (int)floorf(fminf(fmaxf(lo, -1.f), (float)g.J)));
+                const int j1 = min(g.J - 1, (int)floorf(fminf(fmaxf(hi, -1.f), (float)g.J)));
+                float s = 0.f;
+                for (int j = j0; j <= j1; ++j) {
+                    const double qz = qz0 + j * sb;
+                    const double fz = floor(qz);
+                    const int hz = (int)fz;
+                    const float wz = (float)(qz - fz);
+                    const float w = (hz == z) ? 1.f - wz : ((hz == z - 1) ? wz : 0.f);
+                    s = fmaf(w, yb[(size_t)j * g.B], s);
                 }
+                part[t] = fmaf(wi, s, part[t]);
+            }
         }
-        q += r.k;
-        qz += r.kz;
+#pragma unroll
+        for (int t = 0; t < kZC; ++t) acc[t] += (double)part[t];
     }
+    const size_t plane = (size_t)g.nx * g.ny;
+#pragma unroll
+    for (int t = 0; t < kZC; ++t)
+        if (z0 + t < g.nz) vol[(size_t)(z0 + t) * plane + (size_t)y * g.nx + x] = (float)acc[t];
 }
 
 struct ConeWork {
-    DevBuf vx, vy, cs;
+    DevBuf vx, vy, cs, yl, tab;
     std::vector<double> cs_host;  // what cs holds
 };
 
@@ -286,11 +377,23 @@ dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, flo
     ConeDev d;
     dect_status st = cone_setup(g, d, w, s);
     if (st) return st;
-    const size_t N = (size_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL(k_cone_zero, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, vol, N);
-    DECT_HIP(hipGetLastError());
     const size_t nray = (size_t)d.V * d.J * d.B;
-    hipLaunchKernelGGL(k_cone_adj, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d, proj,
+    const size_t ntab = (size_t)d.V * d.B;
+    if (w->yl.bytes < nray * 4 || w->tab.bytes < ntab * sizeof(ConeTab)) {
+        DECT_HIP(hipStreamSynchronize(s));
+        if ((st = w->yl.ensure(nray * 4)) || (st = w->tab.ensure(ntab * sizeof(ConeTab))))
+            return st;
+    }
+    hipLaunchKernelGGL(k_cone_tab, dim3((unsigned)((ntab + 255) / 256)), dim3(256), 0, s, d,
+                       (ConeTab *)w->tab.ptr);
+    DECT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cone_scale, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
+                       proj, (float *)w->yl.ptr);
+    DECT_HIP(hipGetLastError());
+    const int nzc = (d.nz + kZC - 1) / kZC;
+    hipLaunchKernelGGL(k_cone_gather, dim3((unsigned)((d.nx + 63) / 64), (unsigned)d.ny,
+                                           (unsigned)((nzc + 3) / 4)),
+                       dim3(256), 0, s, d, (const ConeTab *)w->tab.ptr, (const float *)w->yl.ptr,
                        vol);
     DECT_HIP(hipGetLastError());
     return DECT_OK;

@@ -275,7 +275,7 @@ def cone_project(vol, geom: C.ConeGeometry, out=None):
 
 def cone_backproject(proj, geom: C.ConeGeometry, out=None):
     """Cone-beam back-projection [V, rows, bins] -> [nz, ny, nx]
-    (dect_cone_backproject; float atomics, last bits vary run to run)."""
+    (dect_cone_backproject; gather form, reproducible bit for bit)."""
     torch = _torch()
     _dev(proj, "proj", (geom.n_views, geom.n_rows, geom.n_bins))
     if proj.dim() != 3:

@@ -6,13 +6,15 @@ Sec. 3, Joseph's model of Sec. 2.4 with bilinear taps in the driving plane).
   counts, detector offset, irregular view angles): forward and back
   projection within 1e-5 of the oracle's largest value.  The GPU steps each
   ray's in-plane coordinate and height in 32.32 fixed point and interpolates
-  in FP32 (summed in FP64 per four planes); the back-projection adds FP32
-  products with float atomics;
+  in FP32 (summed in FP64 per four planes); the gather back-projection
+  uses the same in-plane coordinate, the height in FP64, per-view FP32 sums
+  accumulated in FP64;
 * the 512 x 512 x 64 volume, 360 views, 64 x 736 detector: eight views
   against the oracle run on those views alone, and the adjoint identity of
   the GPU pair at full size;
 * the central row of an odd-row detector equals the fan-beam GPU projector
-  of the central slice; two forward calls agree bit for bit;
+  of the central slice; repeated forward and back-projection calls agree
+  bit for bit;
 * geometries the kernels do not support are refused.
 """
 import dataclasses
@@ -111,6 +113,9 @@ def test_central_row_equals_fan_beam(torch):
     assert _maxrel(p3[:, g.n_rows // 2, :], p2) <= 1e-5
     again = to_np(dect.cone_project(to_dev(torch, vol), g))
     assert np.array_equal(p3, again)
+    y = to_dev(torch, p3)
+    b1 = to_np(dect.cone_backproject(y, g))
+    assert np.array_equal(b1, to_np(dect.cone_backproject(y, g)))
 
 
 @pytest.mark.parametrize("change", [
