@@ -189,17 +189,21 @@ __global__ __launch_bounds__(256) void k_cone_scale(ConeDev g, const float *__re
     yl[rid] = proj[rid] * cone_ray(g, v, j, b).L;
 }
 
-constexpr int kZC = 8;  // slices per gather thread
+#ifndef DECT_CONE_ZC
+#define DECT_CONE_ZC 8
+#endif
+constexpr int kZC = DECT_CONE_ZC;  // slices per gather thread
 
 // vol = A3^T proj in gather form.  Thread: voxel column (x, y), slices
 // [z0, z0 + kZC); lanes along x.  Per view, the rays that can reach the
 // column cross the segments (x, y -+ 1) (x-major rays, on plane x) or
 // (x -+ 1, y) (y-major rays, on plane y); their bins lie between the
-// panel positions of those four points.  Every candidate is checked against
-// its exact 32.32 in-plane coordinate (the forward's interpolation weight);
-// the rows reaching slice z are those whose height on the ray's plane lies
-// in [z - 1, z + 1), evaluated in FP64.  Per-view sums in FP32, accumulated
-// over views in FP64.
+// panel positions of those four points.  Every candidate's in-plane weight
+// comes from its exact 32.32 coordinate (the forward's interpolation
+// weight); the rows reaching slice z are those whose height on the ray's
+// plane lies within one voxel of z, the height taken in FP64 at the first
+// such row and stepped in FP32 (a few rows).  Per-view sums in FP32,
+// accumulated over views in FP64.
 __global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *__restrict__ tab,
                                                      const float *__restrict__ yl,
                                                      float *__restrict__ vol)
@@ -240,29 +244,27 @@ __global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *_
         for (int b = bl; b <= bh; ++b) {
             const ConeTab tb = tv[b];
             const int pl = tb.xmaj ? x : y, c = tb.xmaj ? y : x;
-            const int64_t q = tb.a + tb.k * pl;
-            const int h = (int)(q >> 32);
-            if (h != c && h != c - 1) continue;
-            const float wa = (float)(uint32_t)q * kTwoM32c;
-            const float wi = (h == c) ? 1.f - wa : wa;
+            // bilinear weights are the tent 1 - |q - c| (in-plane, exact in
+            // 32.32 as in the forward walk) times 1 - |qz - z| (height)
+            const int64_t dq = tb.a + tb.k * pl - ((int64_t)c << 32);
+            const uint64_t adq = (uint64_t)(dq < 0 ? -dq : dq);
+            if (adq >= (1ull << 32)) continue;
+            const float wi = 1.f - (float)(uint32_t)adq * kTwoM32c;
             const double sb = (tb.g0 + tb.g1 * pl) * g.row;  // height step per row (> 0)
             const double qz0 = cz - jc * sb;                  // height of row 0
-            const float isb = (float)(1.0 / sb);
+            const float sbf = (float)sb, isb = 1.f / sbf;
             const float lo0 = (float)(z0 - 1 - qz0) * isb;
             const float *yb = yv + b;
 #pragma unroll
             for (int t = 0; t < kZC; ++t) {
-                const int z = z0 + t;
+                // rows with |qz - z| < 1: j in (lo, lo + 2/sb)
                 const float lo = lo0 + t * isb, hi = lo + 2.f * isb;
-                const int j0 = max(0, (int)floorf(fminf(fmaxf(lo, -1.f), (float)g.J)));
-                const int j1 = min(g.J - 1, (int)floorf(fminf(fmaxf(hi, -1.f), (float)g.J)));
+                const int j0 = max(0, (int)floorf(fminf(fmaxf(lo, -1.f), (float)g.J)) + 1);
+                const int j1 = min(g.J - 1, (int)ceilf(fminf(fmaxf(hi, -1.f), (float)g.J)) - 1);
+                const float e0 = (float)(qz0 + j0 * sb - (z0 + t));  // qz - z at row j0
                 float s = 0.f;
                 for (int j = j0; j <= j1; ++j) {
-                    const double qz = qz0 + j * sb;
-                    const double fz = floor(qz);
-                    const int hz = (int)fz;
-                    const float wz = (float)(qz - fz);
-                    const float w = (hz == z) ? 1.f - wz : ((hz == z - 1) ? wz : 0.f);
+                    const float w = fmaxf(0.f, 1.f - fabsf(fmaf((float)(j - j0), sbf, e0)));
                     s = fmaf(w, yb[(size_t)j * g.B], s);
                 }
                 part[t] = fmaf(wi, s, part[t]);
