@@ -94,7 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-launches", type=int, default=50)
-    ap.add_argument("--mode", choices=["metric", "projectors", "copy", "traffic"],
+    ap.add_argument("--mode", choices=["metric", "projectors", "copy", "traffic", "cone"],
                     default="metric")
     ap.add_argument("--copy-mb", type=int, default=512)
     ap.add_argument("--pmc-dir", default="gpurun_out/pmc")
@@ -132,6 +132,9 @@ def main():
         return copy_probe(args.copy_mb, args.kernel_launches)
     if args.mode == "projectors":
         return projector_launches(args.kernel_launches)
+    if args.mode == "cone":  # the cone-beam projector pair alone
+        print(json.dumps(cone_extra(max(1, args.cone_launches))), flush=True)
+        return
     g = C.METRIC
     s = P.make_slice(g, 0)
     p = C.default_adm_params(g, args.steps)

@@ -21,7 +21,7 @@
 //   k_cone_tab, k_cone_scale, k_cone_gather : the transpose in gather form
 //                (no atomics, the same result on every run): per-(view, bin)
 //                ray constants, projections times each ray's path length,
-//                then one thread per voxel column and 8 slices sums over
+//                then one thread per voxel column and 4 slices sums over
 //                the rays that reach it (see k_cone_gather).
 #include <algorithm>
 #include <cmath>
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_cone_scale(ConeDev g, const float *__re
 }
 
 #ifndef DECT_CONE_ZC
-#define DECT_CONE_ZC 8
+#define DECT_CONE_ZC 4
 #endif
 constexpr int kZC = DECT_CONE_ZC;  // slices per gather thread
 
