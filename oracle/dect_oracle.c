@@ -987,3 +987,153 @@ void or_backproject3(const or_geom3 *g, const double *proj, double *vol)
     }
     free(buf);
 }
+
+/* ------------------------------------------------------- 3-D ADM-TV ---
+ * The reconstruction of Eq. 10 on a volume: Eq. 2's TV with backward
+ * differences along x, y and z (zero on the first column, row and slice),
+ * the isotropic shrinkage of Eq. 8 on the 3-vector, and the cone-beam
+ * projector pair above in place of W.  Same steps, order, BB1 step and log
+ * as or_adm (no projection, fixed iteration count).
+ */
+static void grad3(int nx, int ny, int nz, const double *x, double *gx, double *gy, double *gz)
+{
+    const size_t P = (size_t)nx * ny;
+    for (int zz = 0; zz < nz; ++zz)
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)zz * P + (size_t)r * nx + c;
+                gx[i] = c >= 1 ? x[i] - x[i - 1] : 0.0;
+                gy[i] = r >= 1 ? x[i] - x[i - nx] : 0.0;
+                gz[i] = zz >= 1 ? x[i] - x[i - P] : 0.0;
+            }
+}
+
+/* Exact adjoint of grad3. */
+static void gradT3(int nx, int ny, int nz, const double *px, const double *py, const double *pz,
+                   double *out)
+{
+    const size_t P = (size_t)nx * ny;
+    for (int zz = 0; zz < nz; ++zz)
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)zz * P + (size_t)r * nx + c;
+                double s = 0.0;
+                if (c >= 1) s += px[i];
+                if (c + 1 <= nx - 1) s -= px[i + 1];
+                if (r >= 1) s += py[i];
+                if (r + 1 <= ny - 1) s -= py[i + nx];
+                if (zz >= 1) s += pz[i];
+                if (zz + 1 <= nz - 1) s -= pz[i + P];
+                out[i] = s;
+            }
+}
+
+void or_grad3(int nx, int ny, int nz, const double *x, double *g3)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    grad3(nx, ny, nz, x, g3, g3 + N, g3 + 2 * N);
+}
+
+void or_gradT3(int nx, int ny, int nz, const double *g3, double *out)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    gradT3(nx, ny, nz, g3, g3 + N, g3 + 2 * N, out);
+}
+
+/* m [V][J][B] projections of one energy; x_out [nz][ny][nx] = f / beta;
+ * log [(K+1)][5] as in or_adm. */
+int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double rho, double xi,
+            int K, double *x_out, double *log)
+{
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t M = (size_t)g->n_views * g->n_rows * g->n_bins;
+    double *f = calloc(N, 8), *fo = calloc(N, 8), *G = calloc(N, 8), *h = calloc(N, 8),
+           *ho = calloc(N, 8), *t1 = calloc(N, 8), *sv = calloc(N, 8), *y = calloc(N, 8);
+    double *l[3], *z[3], *d[3], *w[3];
+    for (int a = 0; a < 3; ++a) {
+        l[a] = calloc(N, 8); z[a] = calloc(N, 8); d[a] = calloc(N, 8); w[a] = calloc(N, 8);
+    }
+    double *gs = calloc(M, 8), *r = calloc(M, 8), *p = calloc(M, 8);
+    for (size_t j = 0; j < M; ++j) gs[j] = beta * m[j];
+    or_project3(g, f, r);
+    for (size_t j = 0; j < M; ++j) r[j] -= gs[j];
+    or_backproject3(g, r, h);
+    for (size_t i = 0; i < N; ++i) h[i] *= mu;
+    double alpha = 0.0, relchg = 0.0;
+    int k;
+    for (k = 0; k < K; ++k) {
+        /* z-step (Eq. 8) */
+        grad3(nx, ny, nz, f, d[0], d[1], d[2]);
+        double tvf = 0.0, pres = 0.0;
+        for (size_t i = 0; i < N; ++i) {
+            tvf += sqrt(d[0][i] * d[0][i] + d[1][i] * d[1][i] + d[2][i] * d[2][i]);
+            double v0 = d[0][i] - l[0][i] / rho, v1 = d[1][i] - l[1][i] / rho,
+                   v2 = d[2][i] - l[2][i] / rho;
+            double mag = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+            double sh = mag > 1.0 / rho ? (mag - 1.0 / rho) / mag : 0.0;
+            z[0][i] = sh * v0; z[1][i] = sh * v1; z[2][i] = sh * v2;
+        }
+        /* G (Eq. 9) */
+        for (int a = 0; a < 3; ++a)
+            for (size_t i = 0; i < N; ++i) {
+                w[a][i] = rho * (d[a][i] - z[a][i]) - l[a][i];
+                pres += (d[a][i] - z[a][i]) * (d[a][i] - z[a][i]);
+            }
+        gradT3(nx, ny, nz, w[0], w[1], w[2], G);
+        for (size_t i = 0; i < N; ++i) G[i] += h[i];
+        if (k == 0) {  /* exact minimiser of the f-subproblem along -G */
+            or_project3(g, G, p);
+            grad3(nx, ny, nz, G, w[0], w[1], w[2]);
+            double den = mu * dot(M, p, p) + rho * (dot(N, w[0], w[0]) + dot(N, w[1], w[1]) +
+                                                   dot(N, w[2], w[2]));
+            double gg = dot(N, G, G);
+            alpha = den > 0.0 ? gg / den : 0.0;
+        }
+        if (log) {
+            double *row = log + (size_t)k * 5;
+            row[0] = tvf + 0.5 * mu * dot(M, r, r);
+            row[1] = alpha;
+            row[2] = sqrt(pres);
+            row[3] = relchg;
+            row[4] = sqrt(dot(N, G, G));
+        }
+        memcpy(fo, f, N * 8);
+        memcpy(ho, h, N * 8);
+        for (size_t i = 0; i < N; ++i) f[i] -= alpha * G[i];
+        or_project3(g, f, r);
+        for (size_t j = 0; j < M; ++j) r[j] -= gs[j];
+        or_backproject3(g, r, h);
+        for (size_t i = 0; i < N; ++i) h[i] *= mu;
+        /* BB1 step from s = f^{k+1} - f^k and the change of the f-gradient */
+        for (size_t i = 0; i < N; ++i) sv[i] = f[i] - fo[i];
+        grad3(nx, ny, nz, sv, w[0], w[1], w[2]);
+        gradT3(nx, ny, nz, w[0], w[1], w[2], t1);
+        for (size_t i = 0; i < N; ++i) y[i] = (h[i] - ho[i]) + rho * t1[i];
+        double ss = dot(N, sv, sv), sy = dot(N, sv, y);
+        if (sy > 0.0) alpha = ss / sy;
+        double fn = sqrt(dot(N, fo, fo));
+        relchg = fn > 0.0 ? sqrt(ss) / fn : (ss > 0.0 ? INFINITY : 0.0);
+        /* multiplier step (Eq. 7) */
+        grad3(nx, ny, nz, f, d[0], d[1], d[2]);
+        for (int a = 0; a < 3; ++a)
+            for (size_t i = 0; i < N; ++i) l[a][i] -= xi * (d[a][i] - z[a][i]);
+    }
+    if (log) {
+        grad3(nx, ny, nz, f, d[0], d[1], d[2]);
+        double tvf = 0.0;
+        for (size_t i = 0; i < N; ++i)
+            tvf += sqrt(d[0][i] * d[0][i] + d[1][i] * d[1][i] + d[2][i] * d[2][i]);
+        double *row = log + (size_t)k * 5;
+        row[0] = tvf + 0.5 * mu * dot(M, r, r);
+        row[1] = alpha;
+        row[2] = 0.0;
+        row[3] = relchg;
+        row[4] = 0.0;
+    }
+    for (size_t i = 0; i < N; ++i) x_out[i] = f[i] / beta;
+    for (int a = 0; a < 3; ++a) { free(l[a]); free(z[a]); free(d[a]); free(w[a]); }
+    free(f); free(fo); free(G); free(h); free(ho); free(t1); free(sv); free(y);
+    free(gs); free(r); free(p);
+    return k;
+}

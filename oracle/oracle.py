@@ -84,6 +84,10 @@ def lib():
         L.or_adm_coupled.argtypes = [P(_Geom), pd, pd, d, d, d, ct.c_int, pd, pd, pd, ct.c_int]
         L.or_project3.argtypes = [P(_Geom3), pd, pd]
         L.or_backproject3.argtypes = [P(_Geom3), pd, pd]
+        L.or_adm3.argtypes = [P(_Geom3), pd, d, d, d, d, ct.c_int, pd, pd]
+        L.or_adm3.restype = ct.c_int
+        L.or_grad3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
+        L.or_gradT3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
         _lib = L
     return _lib
 
@@ -184,6 +188,35 @@ def backproject3(g, proj: np.ndarray) -> np.ndarray:
     y = _f64(proj).reshape(og.n_views, og.n_rows, og.n_bins)
     out = np.empty((og.nz, og.ny, og.nx))
     lib().or_backproject3(ct.byref(og.s), _p(y), _p(out))
+    return out
+
+
+def adm3(g, m: np.ndarray, beta: float, mu: float, rho: float, xi: float, iters: int):
+    """ADM-TV (Eq. 10) of one energy on a volume with the cone-beam pair and
+    the 3-D TV; returns (x = f / beta [nz][ny][nx], log [(iters+1)][5])."""
+    og = OGeom3(g)
+    mm = _f64(m).reshape(og.n_views, og.n_rows, og.n_bins)
+    x = np.empty((og.nz, og.ny, og.nx))
+    log = np.zeros((iters + 1, 5))
+    lib().or_adm3(ct.byref(og.s), _p(mm), float(beta), float(mu), float(rho), float(xi),
+                  int(iters), _p(x), _p(log))
+    return x, log
+
+
+def grad3(x: np.ndarray) -> np.ndarray:
+    """Backward differences along x, y, z of a volume: [3][nz][ny][nx]."""
+    x = _f64(x)
+    nz, ny, nx = x.shape
+    out = np.empty((3, nz, ny, nx))
+    lib().or_grad3(nx, ny, nz, _p(x), _p(out))
+    return out
+
+
+def gradT3(p3: np.ndarray) -> np.ndarray:
+    p3 = _f64(p3)
+    _, nz, ny, nx = p3.shape
+    out = np.empty((nz, ny, nx))
+    lib().or_gradT3(nx, ny, nz, _p(p3), _p(out))
     return out
 
 
