@@ -306,6 +306,24 @@ dect_status dect_cone_project(const dect_cone_geometry *geom, const float *d_vol
 dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d_proj,
                                   float *d_vol, void *stream);
 
+/*
+ * ADM-TV of both energies on a volume (Eq. 10 with the TV of Eq. 2 taken
+ * over backward differences along x, y and z -- the six-neighbour form --
+ * and the isotropic shrinkage of Eq. 8 on the 3-vector), with A the
+ * cone-beam pair above.  d_m_* [n_views][n_rows][n_bins] device, d_x_*
+ * [nz][ny][nx] device outputs (x = f / beta).  params as for dect_adm_tv
+ * except: flags must be 0 (zero start, BB1 step; else DECT_ERR_INVALID_ARG)
+ * and tol must be 0 (fixed iteration count); params->log, when not NULL,
+ * receives the [max_iter+1][4] rows {J_high, J_low, alpha_high, alpha_low}.
+ * The energies run one after the other; state in FP32, reductions in FP64.
+ * Allocates its work buffers per call (about 12 volumes and 2 projection
+ * sets) and synchronises the stream before returning.  DECT_ERR_NONFINITE
+ * when a logged objective or step is not finite.
+ */
+dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
+                         const float *d_m_low, const dect_adm_params *params, float *d_x_high,
+                         float *d_x_low, dect_report *rep, void *stream);
+
 /* Number of Joseph samples (ray, line) with the crossing inside (-1, n)
  * for a geometry: the unit of projector work. */
 dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);

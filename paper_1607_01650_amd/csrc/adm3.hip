@@ -1,0 +1,449 @@
+// ADM-TV on a volume (Eq. 10 with Eq. 2's TV over backward differences in
+// x, y and z, the isotropic shrinkage of Eq. 8 on the 3-vector, the
+// deferred multiplier step of Eq. 7 and the BB1 step of Eq. 9), with the
+// cone-beam projector pair as A.  Energies run one after the other, each
+// with the iteration below; state in FP32, every reduction in FP64 from
+// per-block partial sums reduced in a fixed order by one block, scalars and
+// the log kept on the device.
+//
+// Iteration k (N-voxel kernels, one thread per voxel):
+//   k3_tv     lambda -= xi (grad f - z) (k > 0: the previous iteration's
+//             multiplier step, grad f being the new image's), z = shrink(
+//             grad f - lambda / rho, 1 / rho), W = rho (grad f - z) - lambda;
+//             partials TV(f), |grad f - z|^2
+//   k3_g      G = grad^T W + h; partial |G|^2   (k = 0 also |grad G|^2, and
+//             A G through the cone projector for the exact first step)
+//   k3_scalar log row k
+//   k3_step   s = -alpha G, f += s; partial |f^k|^2
+//   A f       r = A f - beta m; partial |r|^2
+//   A^T r     h' = mu A^T r, y = h' - h + rho grad^T grad s, h = h';
+//             partials <s,s>, <s,y>
+//   k3_scalar alpha = <s,s>/<s,y> when <s,y> > 0, relative change
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace dect {
+namespace {
+
+enum { Q_TV, Q_PRES, Q_GG, Q_GRADG, Q_PP, Q_FF, Q_RR, Q_SS, Q_SY, Q_COUNT };
+
+struct Dims {
+    int nx, ny, nz;
+    size_t N;
+};
+
+__device__ __forceinline__ void block_sum(double v, double *out)
+{
+    __shared__ double red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__device__ __forceinline__ void grad_at(const Dims &d, const float *__restrict__ f, size_t i,
+                                        int c, int r, int z, float &gx, float &gy, float &gz)
+{
+    const float fi = f[i];
+    const size_t P = (size_t)d.nx * d.ny;
+    gx = c >= 1 ? fi - f[i - 1] : 0.f;
+    gy = r >= 1 ? fi - f[i - d.nx] : 0.f;
+    gz = z >= 1 ? fi - f[i - P] : 0.f;
+}
+
+__device__ __forceinline__ void coords(const Dims &d, size_t i, int &c, int &r, int &z)
+{
+    c = (int)(i % d.nx);
+    r = (int)(i / d.nx % d.ny);
+    z = (int)(i / ((size_t)d.nx * d.ny));
+}
+
+__global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f,
+                                             float *__restrict__ lam, float *__restrict__ zz,
+                                             float *__restrict__ W, int first, float xi, float rho,
+                                             double *__restrict__ part, size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double tv = 0.0, pres = 0.0;
+    if (i < d.N) {
+        int c, r, z;
+        coords(d, i, c, r, z);
+        float g[3];
+        grad_at(d, f, i, c, r, z, g[0], g[1], g[2]);
+        float l[3], v[3];
+        for (int a = 0; a < 3; ++a) {
+            l[a] = lam[a * d.N + i];
+            if (!first) l[a] -= xi * (g[a] - zz[a * d.N + i]);
+            v[a] = g[a] - l[a] / rho;
+        }
+        const float mag = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const float t = 1.f / rho;
+        const float sh = mag > t ? (mag - t) / mag : 0.f;
+        for (int a = 0; a < 3; ++a) {
+            const float za = sh * v[a];
+            lam[a * d.N + i] = l[a];
+            zz[a * d.N + i] = za;
+            W[a * d.N + i] = rho * (g[a] - za) - l[a];
+            pres += (double)(g[a] - za) * (g[a] - za);
+        }
+        tv = sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
+    }
+    block_sum(tv, part + Q_TV * stride + blockIdx.x);
+    block_sum(pres, part + Q_PRES * stride + blockIdx.x);
+}
+
+// TV(f) alone (the last log row).
+__global__ __launch_bounds__(256) void k3_tvonly(Dims d, const float *__restrict__ f,
+                                                 double *__restrict__ part, size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double tv = 0.0;
+    if (i < d.N) {
+        int c, r, z;
+        coords(d, i, c, r, z);
+        float g[3];
+        grad_at(d, f, i, c, r, z, g[0], g[1], g[2]);
+        tv = sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
+    }
+    block_sum(tv, part + Q_TV * stride + blockIdx.x);
+}
+
+// grad^T of a 3-component field at voxel i (exact adjoint of grad_at).
+__device__ __forceinline__ float gradT_at(const Dims &d, const float *__restrict__ W, size_t i,
+                                          int c, int r, int z)
+{
+    const size_t P = (size_t)d.nx * d.ny, N = d.N;
+    float s = 0.f;
+    if (c >= 1) s += W[i];
+    if (c + 1 <= d.nx - 1) s -= W[i + 1];
+    if (r >= 1) s += W[N + i];
+    if (r + 1 <= d.ny - 1) s -= W[N + i + d.nx];
+    if (z >= 1) s += W[2 * N + i];
+    if (z + 1 <= d.nz - 1) s -= W[2 * N + i + P];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k3_g(Dims d, const float *__restrict__ W,
+                                            const float *__restrict__ h, float *__restrict__ G,
+                                            double *__restrict__ part, size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double gg = 0.0;
+    if (i < d.N) {
+        int c, r, z;
+        coords(d, i, c, r, z);
+        const float g = gradT_at(d, W, i, c, r, z) + h[i];
+        G[i] = g;
+        gg = (double)g * g;
+    }
+    block_sum(gg, part + Q_GG * stride + blockIdx.x);
+}
+
+// |grad G|^2 (first step's exact line search).
+__global__ __launch_bounds__(256) void k3_gradnorm(Dims d, const float *__restrict__ G,
+                                                   double *__restrict__ part, size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+    if (i < d.N) {
+        int c, r, z;
+        coords(d, i, c, r, z);
+        float g[3];
+        grad_at(d, G, i, c, r, z, g[0], g[1], g[2]);
+        s = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+    }
+    block_sum(s, part + Q_GRADG * stride + blockIdx.x);
+}
+
+// sum of squares of a length-n vector into quantity q.
+__global__ __launch_bounds__(256) void k3_sumsq(const float *__restrict__ p, size_t n, int q,
+                                                double *__restrict__ part, size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const double v = i < n ? (double)p[i] : 0.0;
+    block_sum(v * v, part + q * stride + blockIdx.x);
+}
+
+struct Scal3 {
+    double alpha, relchg, rr;
+};
+
+__global__ __launch_bounds__(256) void k3_step(Dims d, const float *__restrict__ G,
+                                               float *__restrict__ f, float *__restrict__ s,
+                                               const Scal3 *__restrict__ sc,
+                                               double *__restrict__ part, size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double ff = 0.0;
+    if (i < d.N) {
+        const float fo = f[i];
+        const float fn = fo - (float)sc->alpha * G[i];
+        s[i] = fn - fo;
+        f[i] = fn;
+        ff = (double)fo * fo;
+    }
+    block_sum(ff, part + Q_FF * stride + blockIdx.x);
+}
+
+// r = p - gs over the projections (in place in p); partial |r|^2.
+__global__ __launch_bounds__(256) void k3_resid(float *__restrict__ p, const float *__restrict__ gs,
+                                                size_t M, double *__restrict__ part, size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double rr = 0.0;
+    if (i < M) {
+        const float r = p[i] - gs[i];
+        p[i] = r;
+        rr = (double)r * r;
+    }
+    block_sum(rr, part + Q_RR * stride + blockIdx.x);
+}
+
+// gs = beta m
+__global__ __launch_bounds__(256) void k3_scale(const float *__restrict__ m, float beta, size_t M,
+                                                float *__restrict__ gs)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < M) gs[i] = beta * m[i];
+}
+
+// h' = mu hb; y = h' - h + rho grad^T grad s; h = h'.  With s == NULL only h
+// is formed (the start).
+__global__ __launch_bounds__(256) void k3_y(Dims d, const float *__restrict__ hb,
+                                            float *__restrict__ h, const float *__restrict__ s,
+                                            float mu, float rho, double *__restrict__ part,
+                                            size_t stride)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double ss = 0.0, sy = 0.0;
+    if (i < d.N) {
+        const float hn = mu * hb[i];
+        if (s) {
+            int c, r, z;
+            coords(d, i, c, r, z);
+            // grad^T grad s at i: per axis, (s_i - s_prev) when i has a
+            // predecessor minus (s_next - s_i) when it has a successor
+            const size_t P = (size_t)d.nx * d.ny;
+            const float si = s[i];
+            float l = 0.f;
+            if (c >= 1) l += si - s[i - 1];
+            if (c + 1 <= d.nx - 1) l -= s[i + 1] - si;
+            if (r >= 1) l += si - s[i - d.nx];
+            if (r + 1 <= d.ny - 1) l -= s[i + d.nx] - si;
+            if (z >= 1) l += si - s[i - P];
+            if (z + 1 <= d.nz - 1) l -= s[i + P] - si;
+            const float y = (hn - h[i]) + rho * l;
+            ss = (double)si * si;
+            sy = (double)si * y;
+        }
+        h[i] = hn;
+    }
+    block_sum(ss, part + Q_SS * stride + blockIdx.x);
+    block_sum(sy, part + Q_SY * stride + blockIdx.x);
+}
+
+__device__ double reduce_q(const double *__restrict__ part, size_t stride, int q, int nb)
+{
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += part[q * stride + b];
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// phase 0: first step's line search (alpha = |G|^2 / (mu |A G|^2 + rho |grad G|^2))
+// phase 1: log row k (J, alpha, ...) before the f-step
+// phase 2: BB1 step and relative change after the f-step
+// phase 3: last log row
+__global__ __launch_bounds__(256) void k3_scalar(Scal3 *sc, const double *__restrict__ part,
+                                                 size_t stride, int nbN, int nbM, int phase,
+                                                 double mu, double rho, double *log_row)
+{
+    if (phase == 0) {
+        const double gg = reduce_q(part, stride, Q_GG, nbN);
+        const double pp = reduce_q(part, stride, Q_PP, nbM);
+        const double gd = reduce_q(part, stride, Q_GRADG, nbN);
+        if (threadIdx.x == 0) {
+            const double den = mu * pp + rho * gd;
+            sc->alpha = den > 0.0 ? gg / den : 0.0;
+        }
+    } else if (phase == 1 || phase == 3) {
+        const double tv = reduce_q(part, stride, Q_TV, nbN);
+        const double gg = phase == 1 ? reduce_q(part, stride, Q_GG, nbN) : 0.0;
+        const double pr = phase == 1 ? reduce_q(part, stride, Q_PRES, nbN) : 0.0;
+        if (threadIdx.x == 0 && log_row) {
+            log_row[0] = tv + 0.5 * mu * sc->rr;
+            log_row[1] = sc->alpha;
+            log_row[2] = sqrt(pr);
+            log_row[3] = sc->relchg;
+            log_row[4] = sqrt(gg);
+        }
+    } else {
+        const double rr = reduce_q(part, stride, Q_RR, nbM);
+        const double ss = reduce_q(part, stride, Q_SS, nbN);
+        const double sy = reduce_q(part, stride, Q_SY, nbN);
+        const double ff = reduce_q(part, stride, Q_FF, nbN);
+        if (threadIdx.x == 0) {
+            sc->rr = rr;
+            if (sy > 0.0) sc->alpha = ss / sy;
+            const double fn = sqrt(ff);
+            sc->relchg = fn > 0.0 ? sqrt(ss) / fn : (ss > 0.0 ? INFINITY : 0.0);
+        }
+    }
+}
+
+__global__ void k3_init(Scal3 *sc, const double *__restrict__ part, size_t stride, int nbM)
+{
+    const double rr = reduce_q(part, stride, Q_RR, nbM);
+    if (threadIdx.x == 0) {
+        sc->alpha = 0.0;
+        sc->relchg = 0.0;
+        sc->rr = rr;
+    }
+}
+
+__global__ __launch_bounds__(256) void k3_zero(float *__restrict__ p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+__global__ __launch_bounds__(256) void k3_out(const float *__restrict__ f, float inv_beta, size_t n,
+                                              float *__restrict__ x)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = f[i] * inv_beta;
+}
+
+unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const float *m_low,
+                    const dect_adm_params *p, float *x_high, float *x_low, dect_report *rep,
+                    hipStream_t s)
+{
+    if (!g || !p || !m_high || !m_low || !x_high || !x_low)
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: null argument");
+    if (p->flags != 0)
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3 takes no flags (zero start, BB1 step)");
+    if (p->tol != 0.0)
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3 runs a fixed iteration count (tol = 0)");
+    if (p->max_iter < 0 || p->max_iter > 1000000)
+        return fail(DECT_ERR_INVALID_ARG, "max_iter out of range");
+    if (!(p->mu > 0.0) || !(p->rho > 0.0) || !(p->xi >= 0.0) || !(p->beta_high > 0.0) ||
+        !(p->beta_low > 0.0))
+        return fail(DECT_ERR_INVALID_ARG, "mu, rho, beta must be positive and xi >= 0");
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || g->n_views <= 0 || g->n_rows <= 0 ||
+        g->n_bins <= 0)
+        return fail(DECT_ERR_INVALID_ARG, "cone geometry sizes must be positive");
+    const Dims d{g->nx, g->ny, g->nz, (size_t)g->nx * g->ny * g->nz};
+    const size_t M = (size_t)g->n_views * g->n_rows * g->n_bins;
+    const int K = p->max_iter;
+    const int nbN = (int)nblk(d.N), nbM = (int)nblk(M);
+    const size_t stride = (size_t)std::max(nbN, nbM);
+
+    // library-owned work buffers of this call (sized to the problem)
+    DevBuf bf, bs, bG, bh, bhb, blam, bz, bW, bgs, bp, bpart, bsc, blog;
+    dect_status st;
+    if ((st = bf.ensure(d.N * 4)) || (st = bs.ensure(d.N * 4)) || (st = bG.ensure(d.N * 4)) ||
+        (st = bh.ensure(d.N * 4)) || (st = bhb.ensure(d.N * 4)) || (st = blam.ensure(3 * d.N * 4)) ||
+        (st = bz.ensure(3 * d.N * 4)) || (st = bW.ensure(3 * d.N * 4)) || (st = bgs.ensure(M * 4)) ||
+        (st = bp.ensure(M * 4)) || (st = bpart.ensure(Q_COUNT * stride * 8)) ||
+        (st = bsc.ensure(sizeof(Scal3))) || (st = blog.ensure((size_t)(K + 1) * 5 * 8 * 2)))
+        return st;
+    float *f = (float *)bf.ptr, *sv = (float *)bs.ptr, *G = (float *)bG.ptr, *h = (float *)bh.ptr,
+          *hb = (float *)bhb.ptr, *lam = (float *)blam.ptr, *zz = (float *)bz.ptr,
+          *W = (float *)bW.ptr, *gs = (float *)bgs.ptr, *pr = (float *)bp.ptr;
+    double *part = (double *)bpart.ptr, *dlog = (double *)blog.ptr;
+    Scal3 *sc = (Scal3 *)bsc.ptr;
+    const float mu = (float)p->mu, rho = (float)p->rho, xi = (float)p->xi;
+    const float *ms[2] = {m_high, m_low};
+    float *xs[2] = {x_high, x_low};
+    const double betas[2] = {p->beta_high, p->beta_low};
+
+    for (int e = 0; e < 2; ++e) {
+        hipLaunchKernelGGL(k3_zero, dim3(nblk(d.N)), dim3(256), 0, s, f, d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nblk(3 * d.N)), dim3(256), 0, s, lam, 3 * d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nblk(3 * d.N)), dim3(256), 0, s, zz, 3 * d.N);
+        hipLaunchKernelGGL(k3_scale, dim3(nbM), dim3(256), 0, s, ms[e], (float)betas[e], M, gs);
+        // r = A 0 - gs, h = mu A^T r
+        if ((st = cone_project(g, f, pr, s))) return st;
+        hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr, gs, M, part, stride);
+        if ((st = cone_backproject(g, pr, hb, s))) return st;
+        hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb, h, (const float *)nullptr, mu,
+                           rho, part, stride);
+        hipLaunchKernelGGL(k3_init, dim3(1), dim3(256), 0, s, sc, part, stride, nbM);
+        DECT_HIP(hipGetLastError());
+        double *elog = dlog + (size_t)e * (K + 1) * 5;
+        for (int k = 0; k < K; ++k) {
+            hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, f, lam, zz, W, k == 0 ? 1 : 0,
+                               xi, rho, part, stride);
+            hipLaunchKernelGGL(k3_g, dim3(nbN), dim3(256), 0, s, d, W, h, G, part, stride);
+            if (k == 0) {
+                if ((st = cone_project(g, G, pr, s))) return st;
+                hipLaunchKernelGGL(k3_sumsq, dim3(nbM), dim3(256), 0, s, pr, M, (int)Q_PP, part,
+                                   stride);
+                hipLaunchKernelGGL(k3_gradnorm, dim3(nbN), dim3(256), 0, s, d, G, part, stride);
+                hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM,
+                                   0, p->mu, p->rho, (double *)nullptr);
+            }
+            hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM, 1,
+                               p->mu, p->rho, elog + (size_t)k * 5);
+            hipLaunchKernelGGL(k3_step, dim3(nbN), dim3(256), 0, s, d, G, f, sv, sc, part, stride);
+            if ((st = cone_project(g, f, pr, s))) return st;
+            hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr, gs, M, part, stride);
+            if ((st = cone_backproject(g, pr, hb, s))) return st;
+            hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb, h, (const float *)sv, mu,
+                               rho, part, stride);
+            hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM, 2,
+                               p->mu, p->rho, (double *)nullptr);
+            DECT_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, f, part, stride);
+        hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM, 3,
+                           p->mu, p->rho, elog + (size_t)K * 5);
+        hipLaunchKernelGGL(k3_out, dim3(nbN), dim3(256), 0, s, f, (float)(1.0 / betas[e]), d.N,
+                           xs[e]);
+        DECT_HIP(hipGetLastError());
+    }
+    // the work buffers are freed at return: wait for the stream first
+    std::vector<double> hlog((size_t)(K + 1) * 5 * 2);
+    DECT_HIP(hipMemcpyAsync(hlog.data(), dlog, hlog.size() * 8, hipMemcpyDeviceToHost, s));
+    DECT_HIP(hipStreamSynchronize(s));
+    // J and the step must stay finite (the relative change after the first
+    // step of a zero start is infinite by definition)
+    bool finite = true;
+    for (size_t r = 0; r < hlog.size() / 5; ++r)
+        finite = finite && std::isfinite(hlog[r * 5]) && std::isfinite(hlog[r * 5 + 1]);
+    if (p->log)
+        for (int k = 0; k <= K; ++k) {
+            p->log[k * 4 + 0] = hlog[(size_t)k * 5];
+            p->log[k * 4 + 1] = hlog[(size_t)(K + 1) * 5 + (size_t)k * 5];
+            p->log[k * 4 + 2] = hlog[(size_t)k * 5 + 1];
+            p->log[k * 4 + 3] = hlog[(size_t)(K + 1) * 5 + (size_t)k * 5 + 1];
+        }
+    if (rep) {
+        rep->iters = K;
+        rep->objective = hlog[(size_t)K * 5] + hlog[(size_t)(K + 1) * 5 + (size_t)K * 5];
+        rep->rel_change = std::max(hlog[(size_t)K * 5 + 3],
+                                   hlog[(size_t)(K + 1) * 5 + (size_t)K * 5 + 3]);
+        rep->pcg_residual = 0.0;
+        rep->status = finite ? DECT_OK : DECT_ERR_NONFINITE;
+    }
+    if (!finite) return fail(DECT_ERR_NONFINITE, "non-finite objective or step");
+    return DECT_OK;
+}
+
+}  // namespace dect

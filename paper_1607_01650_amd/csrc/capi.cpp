@@ -96,6 +96,15 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
     return dect::cone_backproject(geom, d_proj, d_vol, (hipStream_t)stream);
 }
 
+dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
+                         const float *d_m_low, const dect_adm_params *params, float *d_x_high,
+                         float *d_x_low, dect_report *rep, void *stream)
+{
+    dect::set_error("");
+    return dect::adm_tv3(geom, d_m_high, d_m_low, params, d_x_high, d_x_low, rep,
+                         (hipStream_t)stream);
+}
+
 dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
                         const dect_adm_params *params, float *d_x_high, float *d_x_low,
                         dect_adm_state *state, dect_report *rep, void *stream)

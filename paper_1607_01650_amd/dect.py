@@ -85,6 +85,9 @@ SIGNATURES = {
                                      ct.c_void_p]),
     "dect_cone_backproject": (ct.c_int, [_P(dect_cone_geometry), ct.c_void_p, ct.c_void_p,
                                          ct.c_void_p]),
+    "dect_adm_tv3": (ct.c_int, [_P(dect_cone_geometry), ct.c_void_p, ct.c_void_p,
+                                _P(dect_adm_params), ct.c_void_p, ct.c_void_p, _P(dect_report),
+                                ct.c_void_p]),
     "dect_adm_tv": (ct.c_int, [_P(dect_geometry), ct.c_void_p, ct.c_void_p, _P(dect_adm_params),
                                ct.c_void_p, ct.c_void_p, ct.c_void_p, _P(dect_report),
                                ct.c_void_p]),
@@ -368,6 +371,42 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
                            state.handle if state is not None else None,
                            ct.byref(rep) if want_log else None, _stream())
     _check(st, "dect_adm_tv")
+    return AdmResult(xh, xl, rep if want_log else None, log)
+
+
+def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool = False,
+            out: Optional[Tuple] = None) -> AdmResult:
+    """ADM-TV of both energies on a volume with the cone-beam pair
+    (dect_adm_tv3): m_* [V, rows, bins] device projections -> x_high, x_low
+    [nz, ny, nx]; zero start, BB1 step, fixed iteration count.  With
+    want_log, the log [max_iter+1, 4] = (J_high, J_low, alpha_high,
+    alpha_low) and the report."""
+    torch = _torch()
+    shp = (geom.n_views, geom.n_rows, geom.n_bins)
+    _dev(m_high, "m_high", shp)
+    _dev(m_low, "m_low", shp)
+    if out is not None:
+        xh, xl = out
+    else:
+        xh = torch.empty((geom.nz, geom.ny, geom.nx), device=m_high.device, dtype=torch.float32)
+        xl = torch.empty_like(xh)
+    _dev(xh, "x_high", (geom.nz, geom.ny, geom.nx))
+    _dev(xl, "x_low", (geom.nz, geom.ny, geom.nx))
+    flags = (DECT_NONNEG if getattr(p, "nonneg", False) else 0) | \
+        (DECT_COUPLED_TV if getattr(p, "coupled_tv", False) else 0) | \
+        _STEP_FLAGS[getattr(p, "step", "bb1")]
+    log = None
+    logp = None
+    if want_log:
+        log = np.zeros((p.max_iter + 1, 4))
+        logp = log.ctypes.data_as(ct.POINTER(ct.c_double))
+    prm = dect_adm_params(p.mu, p.rho, p.xi, p.beta_high, p.beta_low, p.max_iter, p.tol, flags,
+                          logp)
+    rep = dect_report()
+    _check(lib().dect_adm_tv3(ConeArg(geom).ref, ct.c_void_p(m_high.data_ptr()),
+                              ct.c_void_p(m_low.data_ptr()), ct.byref(prm),
+                              ct.c_void_p(xh.data_ptr()), ct.c_void_p(xl.data_ptr()),
+                              ct.byref(rep), _stream()), "dect_adm_tv3")
     return AdmResult(xh, xl, rep if want_log else None, log)
 
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "dect.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dect_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(dect_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,82 @@
+"""GPU parity of the 3-D ADM-TV (dect_adm_tv3: Eq. 10 on a volume with the
+3-D TV and the cone-beam pair) against the FP64 oracle's run (or_adm3) of
+each energy on the same FP32 inputs: a 32 x 28 x 12 volume (30 views, 10 x 48
+panel, 30 iterations) and a ragged one (37 x 29 x 9, detector offset, 25
+iterations): image rel-L2 <= 1e-4, the logged objective within 1e-5 over
+the first 10 iterations (where a wrong term or scale would show) and 1e-4
+over the run; the BB step within 1e-4 over the first 10 iterations and 1e-3
+over the run (a ratio of differences of nearly equal iterates, which
+amplifies FP32 rounding as the run converges: measured 1.4e-4 late in the
+run while the images agree to 2e-6; a wrong term would be O(1) from the
+start).  The state is FP32 and the back-projection's in-plane weights are
+the forward's, so the differences are FP32 rounding amplified by the
+iteration.  Flags and a tolerance stop
+are refused.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1607_01650_amd import configs as C
+from paper_1607_01650_amd import phantom as P
+
+from helpers import f32, need_gpu, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+VOL = C.ConeGeometry(nx=32, ny=28, nz=12, voxel_mm=1.0, n_views=30, n_bins=48, n_rows=10,
+                     bin_mm=1.5, row_mm=1.5, sod_mm=100.0, sdd_mm=200.0)
+RAGGED = C.ConeGeometry(nx=37, ny=29, nz=9, voxel_mm=1.0, n_views=23, n_bins=53, n_rows=7,
+                        bin_mm=1.4, row_mm=1.7, sod_mm=90.0, sdd_mm=170.0, det_offset_mm=0.6)
+PARAMS = C.AdmParams(mu=1.0, rho=64.0, xi=16.0, beta_high=1.0, beta_low=0.79, max_iter=30)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return need_gpu()
+
+
+def _data(g, seed):
+    """Two energies' projections of the extruded phantom (low energy 1.3x
+    the attenuation) with 0.5%-of-max Gaussian noise, rounded to FP32."""
+    vol = P.cone_volume(g, seed, supersample=2) * 10.0
+    rng = np.random.default_rng(100 + seed)
+    out = []
+    for e, scale in enumerate((1.0, 1.3)):
+        p = O.project3(g, scale * vol)
+        out.append(f32(p + rng.normal(0.0, 0.005 * p.max(), size=p.shape)))
+    return out
+
+
+@pytest.mark.parametrize("geom,iters,seed", [(VOL, 30, 0), (RAGGED, 25, 1)],
+                         ids=["volume", "ragged"])
+def test_parity(torch, geom, iters, seed):
+    from paper_1607_01650_amd import dect
+    m = _data(geom, seed)
+    p = dataclasses.replace(PARAMS, max_iter=iters)
+    r = dect.adm_tv3(to_dev(torch, m[0]), to_dev(torch, m[1]), geom, p, want_log=True)
+    for e, (xe, beta) in enumerate(((r.x_high, p.beta_high), (r.x_low, p.beta_low))):
+        x, log = O.adm3(geom, m[e], beta, p.mu, p.rho, p.xi, iters)
+        err = rel_l2(to_np(xe), x)
+        jrel = np.abs(r.log[:, e] - log[:, 0]) / np.abs(log[:, 0])
+        arel = np.abs(r.log[1:, 2 + e] - log[1:, 1]) / np.abs(log[1:, 1])
+        print(f"3-D ADM {geom.nx}x{geom.ny}x{geom.nz} energy {e}: image rel-L2 {err:.2e}, "
+              f"J rel err k<=10 {jrel[:11].max():.2e}, all {jrel.max():.2e}, "
+              f"alpha k<=10 {arel[:10].max():.2e}, all {arel.max():.2e}", flush=True)
+        assert err <= 1e-4
+        assert jrel[:11].max() <= 1e-5
+        assert jrel.max() <= 1e-4
+        assert arel[:10].max() <= 1e-4
+        assert arel.max() <= 1e-3
+    assert r.report.iters == iters
+
+
+def test_refusals(torch):
+    from paper_1607_01650_amd import dect
+    g = VOL
+    z = torch.zeros((g.n_views, g.n_rows, g.n_bins), device="cuda")
+    for change in ({"nonneg": True}, {"tol": 1e-3}, {"step": "bb2"}):
+        with pytest.raises(dect.DectError):
+            dect.adm_tv3(z, z, g, dataclasses.replace(PARAMS, max_iter=2, **change))
