@@ -114,6 +114,8 @@ def main():
                          "adaptive-step variant entries (0: skip)")
     ap.add_argument("--cone-launches", type=int, default=3,
                     help="timed calls of each cone-beam projector (0: skip)")
+    ap.add_argument("--adm3-iters", type=int, default=6,
+                    help="iterations of the 3-D ADM entry (0: skip; at least 2)")
     args = ap.parse_args()
     if args.mode == "traffic":
         return traffic_summary(args.pmc_dir)
@@ -132,8 +134,9 @@ def main():
         return copy_probe(args.copy_mb, args.kernel_launches)
     if args.mode == "projectors":
         return projector_launches(args.kernel_launches)
-    if args.mode == "cone":  # the cone-beam projector pair alone
-        print(json.dumps(cone_extra(max(1, args.cone_launches))), flush=True)
+    if args.mode == "cone":  # the cone-beam projector pair and the 3-D ADM alone
+        print(json.dumps({"cone": cone_extra(max(1, args.cone_launches)),
+                          "adm3": adm3_extra(max(2, args.adm3_iters))}), flush=True)
         return
     g = C.METRIC
     s = P.make_slice(g, 0)
@@ -217,6 +220,7 @@ def main():
     coupled = nonneg_extra(args.nonneg_steps, coupled=True) if args.nonneg_steps > 0 else None
     abb = nonneg_extra(args.nonneg_steps, step="abb") if args.nonneg_steps > 0 else None
     cone = cone_extra(args.cone_launches) if args.cone_launches > 0 else None
+    adm3 = adm3_extra(max(2, args.adm3_iters)) if args.adm3_iters > 0 else None
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
@@ -258,7 +262,7 @@ def main():
                   "pls_attenuation_ms": round(pls_att_ms, 3), "pls_attenuation_iters": arep.iters,
                   "warm_start": warm, "batched": batched, "unrolled": unrolled,
                   "siddon": siddon, "fbp": fbp, "nonneg": nonneg, "coupled_tv": coupled,
-                  "abb_step": abb, "cone": cone},
+                  "abb_step": abb, "cone": cone, "adm3": adm3},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
@@ -390,6 +394,38 @@ def cone_extra(launches: int):
             "back_gsamples_per_s": round(samples / adj_ms / 1e6, 2),
             "fwd_algorithmic_gbs": round(nbytes / fwd_ms / 1e6, 1),
             "back_algorithmic_gbs": round(nbytes / adj_ms / 1e6, 1)}
+
+
+def adm3_extra(iters: int):
+    """3-D ADM-TV of both energies on the cone workload (512 x 512 x 64, 360
+    views, 64 x 736 panel): wall time per iteration of the call (both
+    energies, the stream synchronised at its end), from the difference of an
+    iters-long and a 1-iteration run so that set-up is excluded."""
+    import torch
+
+    from paper_1607_01650_amd import configs as C, dect, phantom as P
+
+    g = C.CONE
+    vol = torch.as_tensor(P.cone_volume(g, 0, supersample=2), dtype=torch.float32).cuda()
+    mh = dect.cone_project(vol, g)
+    ml = dect.cone_project(vol * 1.3, g)
+    p = C.AdmParams(mu=45.0 / g.n_views, rho=1024.0, xi=256.0, beta_high=1.0, beta_low=0.79,
+                    max_iter=1)
+    dect.adm_tv3(mh, ml, g, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dect.adm_tv3(mh, ml, g, p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = dect.adm_tv3(mh, ml, g, dataclasses.replace(p, max_iter=iters), want_log=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    per_it = ((t2 - t1) - (t1 - t0)) / (iters - 1)
+    return {"workload": "adm_tv3_cone_512x512x64_360views_64x736det_2energies", "iters": iters,
+            "ms_per_iteration_2energies": round(per_it * 1e3, 2),
+            "iters_per_s": round(1.0 / per_it, 2),
+            "J_first_last": [round(float(r.log[0, 0] + r.log[0, 1]), 1),
+                             round(float(r.log[-1, 0] + r.log[-1, 1]), 1)]}
 
 
 def fbp_extra(launches: int):
