@@ -1137,3 +1137,134 @@ int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double r
     free(gs); free(r); free(p);
     return k;
 }
+
+/* ------------------------------------------------------------ 3-D PLS ---
+ * Eqs. 13-15 on a volume: R of Eq. 14 over the six face neighbours, edges
+ * from the 3-D Prewitt operator (per axis, the sum over the 3 x 3 face at
+ * +1 minus the sum at -1, borders replicated), in FP32 with a fixed order:
+ * each face sum runs over the face's first index, then its second, from -1
+ * to +1, added one at a time; m2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz)); an
+ * edge where m2 > tau2 * max(m2).  Pair weights e_x[i] couple i and i + 1,
+ * e_y[i] i and i + nx, e_z[i] i and i + nx ny: eps if either voxel is an
+ * edge, else 1; pairs that leave the volume get 0.
+ */
+void or_edges3_f32(int nx, int ny, int nz, const float *x, float tau2, float eps, float *ex,
+                   float *ey, float *ez, uint8_t *edge)
+{
+    const size_t P = (size_t)nx * ny, N = P * nz;
+    float *m2 = malloc(N * sizeof(float));
+    float mx = 0.0f;
+#define CL(v, n) ((v) < 0 ? 0 : ((v) > (n) - 1 ? (n) - 1 : (v)))
+#define V3(zz, rr, cc) x[(size_t)CL(zz, nz) * P + (size_t)CL(rr, ny) * nx + CL(cc, nx)]
+    for (int z = 0; z < nz; ++z)
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                float xp = 0.f, xm = 0.f, yp = 0.f, ym = 0.f, zp = 0.f, zm = 0.f;
+                int first = 1;
+                for (int a = -1; a <= 1; ++a)
+                    for (int b = -1; b <= 1; ++b) {
+                        /* x faces: (z + a, r + b); y faces: (z + a, c + b); z faces: (r + a, c + b) */
+                        float vxp = V3(z + a, r + b, c + 1), vxm = V3(z + a, r + b, c - 1);
+                        float vyp = V3(z + a, r + 1, c + b), vym = V3(z + a, r - 1, c + b);
+                        float vzp = V3(z + 1, r + a, c + b), vzm = V3(z - 1, r + a, c + b);
+                        if (first) {
+                            xp = vxp; xm = vxm; yp = vyp; ym = vym; zp = vzp; zm = vzm;
+                            first = 0;
+                        } else {
+                            xp += vxp; xm += vxm; yp += vyp; ym += vym; zp += vzp; zm += vzm;
+                        }
+                    }
+                float gx = xp - xm, gy = yp - ym, gz = zp - zm;
+                float v = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+                m2[(size_t)z * P + (size_t)r * nx + c] = v;
+                if (v > mx) mx = v;
+            }
+#undef V3
+#undef CL
+    float thr = tau2 * mx;
+    for (size_t i = 0; i < N; ++i) edge[i] = m2[i] > thr;
+    for (int z = 0; z < nz; ++z)
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)z * P + (size_t)r * nx + c;
+                ex[i] = c + 1 < nx ? ((edge[i] || edge[i + 1]) ? eps : 1.0f) : 0.0f;
+                ey[i] = r + 1 < ny ? ((edge[i] || edge[i + nx]) ? eps : 1.0f) : 0.0f;
+                ez[i] = z + 1 < nz ? ((edge[i] || edge[i + P]) ? eps : 1.0f) : 0.0f;
+            }
+    free(m2);
+}
+
+/* (L u)_i = sum over the six face neighbours k of e_ik (u_i - u_k) (Eq. 14). */
+void or_laplacian3(int nx, int ny, int nz, const double *ex, const double *ey, const double *ez,
+                   const double *u, double *out)
+{
+    const size_t P = (size_t)nx * ny;
+    for (int z = 0; z < nz; ++z)
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)z * P + (size_t)r * nx + c;
+                double s = 0.0;
+                if (c + 1 < nx) s += ex[i] * (u[i] - u[i + 1]);
+                if (c >= 1) s += ex[i - 1] * (u[i] - u[i - 1]);
+                if (r + 1 < ny) s += ey[i] * (u[i] - u[i + nx]);
+                if (r >= 1) s += ey[i - nx] * (u[i] - u[i - nx]);
+                if (z + 1 < nz) s += ez[i] * (u[i] - u[i + P]);
+                if (z >= 1) s += ez[i - P] * (u[i] - u[i - P]);
+                out[i] = s;
+            }
+}
+
+/* Jacobi-PCG for (I + gamma L) u = b on a volume, from u = b; as or_pcg. */
+int or_pcg3(int nx, int ny, int nz, const double *ex, const double *ey, const double *ez,
+            double gamma, const double *b, double *u, int max_iter, double tol, double *relres)
+{
+    const size_t P = (size_t)nx * ny, N = P * nz;
+    double *res = malloc(N * 8), *zv = malloc(N * 8), *p = malloc(N * 8), *q = malloc(N * 8),
+           *dinv = malloc(N * 8);
+    for (int z = 0; z < nz; ++z)
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)z * P + (size_t)r * nx + c;
+                double d = 0.0;
+                if (c + 1 < nx) d += ex[i];
+                if (c >= 1) d += ex[i - 1];
+                if (r + 1 < ny) d += ey[i];
+                if (r >= 1) d += ey[i - nx];
+                if (z + 1 < nz) d += ez[i];
+                if (z >= 1) d += ez[i - P];
+                dinv[i] = 1.0 / (1.0 + gamma * d);
+            }
+    memcpy(u, b, N * 8);
+    or_laplacian3(nx, ny, nz, ex, ey, ez, u, q);
+    for (size_t i = 0; i < N; ++i) res[i] = b[i] - (u[i] + gamma * q[i]);
+    double bn = sqrt(dot(N, b, b)), rn = sqrt(dot(N, res, res));
+    int it = 0;
+    if (bn == 0.0) {
+        memset(u, 0, N * 8);
+        rn = 0.0;
+        bn = 1.0;
+    }
+    for (size_t i = 0; i < N; ++i) zv[i] = dinv[i] * res[i];
+    memcpy(p, zv, N * 8);
+    double rz = dot(N, res, zv);
+    while (it < max_iter && rn > tol * bn) {
+        or_laplacian3(nx, ny, nz, ex, ey, ez, p, q);
+        for (size_t i = 0; i < N; ++i) q[i] = p[i] + gamma * q[i];
+        double pq = dot(N, p, q);
+        if (pq <= 0.0) break;
+        double a = rz / pq;
+        for (size_t i = 0; i < N; ++i) {
+            u[i] += a * p[i];
+            res[i] -= a * q[i];
+        }
+        ++it;
+        rn = sqrt(dot(N, res, res));
+        for (size_t i = 0; i < N; ++i) zv[i] = dinv[i] * res[i];
+        double rz2 = dot(N, res, zv), beta = rz2 / rz;
+        rz = rz2;
+        for (size_t i = 0; i < N; ++i) p[i] = zv[i] + beta * p[i];
+    }
+    if (relres) *relres = rn / bn;
+    free(res); free(zv); free(p); free(q); free(dinv);
+    return it;
+}

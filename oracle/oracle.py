@@ -85,6 +85,12 @@ def lib():
         L.or_project3.argtypes = [P(_Geom3), pd, pd]
         L.or_backproject3.argtypes = [P(_Geom3), pd, pd]
         L.or_adm3.argtypes = [P(_Geom3), pd, d, d, d, d, ct.c_int, pd, pd]
+        L.or_edges3_f32.argtypes = [ct.c_int, ct.c_int, ct.c_int, pf, ct.c_float, ct.c_float,
+                                    pf, pf, pf, P(ct.c_uint8)]
+        L.or_laplacian3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, pd, pd]
+        L.or_pcg3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, d, pd, pd, ct.c_int, d,
+                              pd]
+        L.or_pcg3.restype = ct.c_int
         L.or_adm3.restype = ct.c_int
         L.or_grad3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
         L.or_gradT3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
@@ -347,6 +353,47 @@ def pcg_att(er, ed, eta, gamma: float, xh, xl, max_iter: int = 500, tol: float =
                           _p(xh), _p(xl), _p(u1), _p(u2), int(max_iter), float(tol),
                           ct.byref(rr))
     return u1, u2, int(it), float(rr.value)
+
+
+def edges3_f32(xl: np.ndarray, tau: float, eps: float):
+    """3-D Prewitt edge weights of a volume [nz][ny][nx]: (e_x, e_y, e_z, edge);
+    the decision is taken in FP32 (tau2 = fp32(tau*tau))."""
+    x = np.ascontiguousarray(xl, dtype=np.float32)
+    nz, ny, nx = x.shape
+    ex, ey, ez = np.empty_like(x), np.empty_like(x), np.empty_like(x)
+    e = np.empty(x.shape, dtype=np.uint8)
+    lib().or_edges3_f32(nx, ny, nz, _p(x, ct.c_float), ct.c_float(np.float32(tau * tau)),
+                        ct.c_float(np.float32(eps)), _p(ex, ct.c_float), _p(ey, ct.c_float),
+                        _p(ez, ct.c_float), e.ctypes.data_as(ct.POINTER(ct.c_uint8)))
+    return ex, ey, ez, e
+
+
+def laplacian3(ex, ey, ez, u):
+    ex, ey, ez, u = _f64(ex), _f64(ey), _f64(ez), _f64(u)
+    nz, ny, nx = u.shape
+    out = np.empty_like(u)
+    lib().or_laplacian3(nx, ny, nz, _p(ex), _p(ey), _p(ez), _p(u), _p(out))
+    return out
+
+
+def pcg3(ex, ey, ez, gamma: float, b, max_iter: int = 500, tol: float = 1e-12):
+    ex, ey, ez, b = _f64(ex), _f64(ey), _f64(ez), _f64(b)
+    nz, ny, nx = b.shape
+    u = np.empty_like(b)
+    rr = ct.c_double(0.0)
+    it = lib().or_pcg3(nx, ny, nz, _p(ex), _p(ey), _p(ez), float(gamma), _p(b), _p(u),
+                       int(max_iter), float(tol), ct.byref(rr))
+    return u, int(it), float(rr.value)
+
+
+def pls3(xh, xl, p, tol: float = 1e-12):
+    """3-D decomposition of volumes [nz][ny][nx]: D^{-1} x per voxel, 3-D
+    Prewitt edge weights on x_l, PCG per material with the six-neighbour L."""
+    b1, b2 = dinv(xh, xl, p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
+    ex, ey, ez, _ = edges3_f32(xl, p.edge_tau, p.edge_eps)
+    u1, i1, _ = pcg3(ex, ey, ez, p.gamma, b1, p.max_iter, tol)
+    u2, i2, _ = pcg3(ex, ey, ez, p.gamma, b2, p.max_iter, tol)
+    return u1, u2, max(i1, i2)
 
 
 def pls(xh, xl, p, edge_w=None, tol: float = 1e-12):

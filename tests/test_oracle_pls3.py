@@ -1,0 +1,90 @@
+"""Pins of the oracle's 3-D PLS pieces (Eqs. 13-15 on a volume, R of Eq. 14
+over the six face neighbours, edges from the 3-D Prewitt operator):
+
+* a step along z (constant in-plane) marks exactly the two slices beside the
+  step; a step along x marks exactly the two columns beside it in every row
+  and slice; a constant volume has no edges;
+* the six-neighbour Laplacian's quadratic form equals R(u) of Eq. 14 summed
+  pair by pair over the face neighbours; L 1 = 0; on a one-slice volume it is
+  the 2-D Laplacian, bit for bit;
+* PCG solves (I + gamma L) u = b as numpy.linalg.solve does on the dense
+  matrix assembled pair by pair.
+"""
+import numpy as np
+
+from oracle import oracle as O
+
+
+def test_z_step_marks_two_slices():
+    x = np.zeros((9, 7, 8), dtype=np.float32)
+    x[4:] = 1.0
+    ex, ey, ez, e = O.edges3_f32(x, 0.25, 0.1)
+    want = np.zeros_like(e)
+    want[3:5] = 1
+    assert np.array_equal(e, want)
+    assert np.all(ez[2:5] == np.float32(0.1)) and np.all(ez[5:8] == 1.0) and np.all(ez[8] == 0.0)
+    assert np.all(ez[:2] == 1.0)
+
+
+def test_x_step_marks_two_columns():
+    x = np.zeros((5, 6, 10), dtype=np.float32)
+    x[:, :, 6:] = 2.0
+    _, _, _, e = O.edges3_f32(x, 0.25, 0.1)
+    want = np.zeros_like(e)
+    want[:, :, 5:7] = 1
+    assert np.array_equal(e, want)
+    _, _, _, e0 = O.edges3_f32(np.full((4, 5, 6), 3.0, dtype=np.float32), 0.25, 0.1)
+    assert not e0.any()
+
+
+def _pairs(nx, ny, nz):
+    P = nx * ny
+    for z in range(nz):
+        for r in range(ny):
+            for c in range(nx):
+                i = z * P + r * nx + c
+                if c + 1 < nx:
+                    yield 0, i, i + 1
+                if r + 1 < ny:
+                    yield 1, i, i + nx
+                if z + 1 < nz:
+                    yield 2, i, i + P
+
+
+def test_laplacian_is_eq14_pairwise():
+    rng = np.random.default_rng(0)
+    nz, ny, nx = 4, 5, 6
+    w = [rng.random((nz, ny, nx)) for _ in range(3)]
+    for a, idx in ((0, np.s_[:, :, -1]), (1, np.s_[:, -1, :]), (2, np.s_[-1, :, :])):
+        w[a][idx] = 0.0
+    u = rng.random((nz, ny, nx))
+    Lu = O.laplacian3(w[0], w[1], w[2], u)
+    uf, wf = u.reshape(-1), [a.reshape(-1) for a in w]
+    R = sum(wf[a][i] * (uf[i] - uf[k]) ** 2 for a, i, k in _pairs(nx, ny, nz))
+    assert abs(np.sum(u * Lu) - R) <= 1e-12 * R
+    assert np.abs(O.laplacian3(w[0], w[1], w[2], np.ones_like(u))).max() <= 1e-14
+    one = [a[:1] for a in w]
+    assert np.array_equal(O.laplacian3(one[0], one[1], np.zeros_like(one[2]), u[:1])[0],
+                          O.laplacian(one[0][0], one[1][0], u[0]))
+
+
+def test_pcg3_matches_dense_solve():
+    rng = np.random.default_rng(1)
+    nz, ny, nx = 4, 5, 6
+    N = nx * ny * nz
+    w = [np.where(rng.random((nz, ny, nx)) < 0.2, 0.1, 1.0) for _ in range(3)]
+    w[0][:, :, -1] = 0.0
+    w[1][:, -1, :] = 0.0
+    w[2][-1] = 0.0
+    gamma = 0.7
+    A = np.eye(N)
+    wf = [a.reshape(-1) for a in w]
+    for a, i, k in _pairs(nx, ny, nz):
+        A[i, i] += gamma * wf[a][i]
+        A[k, k] += gamma * wf[a][i]
+        A[i, k] -= gamma * wf[a][i]
+        A[k, i] -= gamma * wf[a][i]
+    b = rng.standard_normal((nz, ny, nx))
+    u, it, rr = O.pcg3(w[0], w[1], w[2], gamma, b, 500, 1e-13)
+    ref = np.linalg.solve(A, b.reshape(-1)).reshape(nz, ny, nx)
+    assert np.abs(u - ref).max() <= 1e-11 * np.abs(ref).max() and rr <= 1e-13 and it < 500
