@@ -324,6 +324,26 @@ dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
                          const float *d_m_low, const dect_adm_params *params, float *d_x_high,
                          float *d_x_low, dect_report *rep, void *stream);
 
+/*
+ * PLS decomposition of volumes (Eqs. 11-15 with R of Eq. 14 over the six
+ * face neighbours): u = D^{-1} x per voxel (Eq. 12), then (I + gamma L) u_m
+ * = (D^{-1} x)_m per material by Jacobi-PCG from u = D^{-1} x, L the
+ * six-neighbour Laplacian with pair weights edge_eps where either voxel is
+ * an edge of x_low, else 1.  Edges come from the 3-D Prewitt operator (per
+ * axis, the 3 x 3 face sum at +1 minus the one at -1, borders replicated),
+ * an edge where its squared magnitude exceeds edge_tau^2 times the largest;
+ * that decision is taken in FP32 in a fixed order.  Device buffers
+ * d_x_* [nz][ny][nx] in, d_u_water / d_u_bone [nz][ny][nx] out.  params as
+ * for dect_pls_decompose with mode DECT_PLS_IMAGE only (else
+ * DECT_ERR_INVALID_ARG); stops when |res| <= tol |b| or after max_iter
+ * iterations per material.  Allocates its work buffers per call (about 11
+ * volumes) and synchronises the stream.  rep: iters (the larger of the two
+ * materials) and pcg_residual.
+ */
+dect_status dect_pls_decompose3(int32_t nx, int32_t ny, int32_t nz, const float *d_x_high,
+                                const float *d_x_low, const dect_pls_params *params,
+                                float *d_u_water, float *d_u_bone, dect_report *rep, void *stream);
+
 /* Number of Joseph samples (ray, line) with the crossing inside (-1, n)
  * for a geometry: the unit of projector work. */
 dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);

@@ -105,6 +105,15 @@ dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
                          (hipStream_t)stream);
 }
 
+dect_status dect_pls_decompose3(int32_t nx, int32_t ny, int32_t nz, const float *d_x_high,
+                                const float *d_x_low, const dect_pls_params *params,
+                                float *d_u_water, float *d_u_bone, dect_report *rep, void *stream)
+{
+    dect::set_error("");
+    return dect::pls_decompose3(nx, ny, nz, d_x_high, d_x_low, params, d_u_water, d_u_bone, rep,
+                                (hipStream_t)stream);
+}
+
 dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
                         const dect_adm_params *params, float *d_x_high, float *d_x_low,
                         dect_adm_state *state, dect_report *rep, void *stream)

@@ -85,6 +85,9 @@ SIGNATURES = {
                                      ct.c_void_p]),
     "dect_cone_backproject": (ct.c_int, [_P(dect_cone_geometry), ct.c_void_p, ct.c_void_p,
                                          ct.c_void_p]),
+    "dect_pls_decompose3": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                       ct.c_void_p, _P(dect_pls_params), ct.c_void_p,
+                                       ct.c_void_p, _P(dect_report), ct.c_void_p]),
     "dect_adm_tv3": (ct.c_int, [_P(dect_cone_geometry), ct.c_void_p, ct.c_void_p,
                                 _P(dect_adm_params), ct.c_void_p, ct.c_void_p, _P(dect_report),
                                 ct.c_void_p]),
@@ -408,6 +411,32 @@ def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool 
                               ct.c_void_p(xh.data_ptr()), ct.c_void_p(xl.data_ptr()),
                               ct.byref(rep), _stream()), "dect_adm_tv3")
     return AdmResult(xh, xl, rep if want_log else None, log)
+
+
+def pls_decompose3(x_high, x_low, p: C.PlsParams, out: Optional[Tuple] = None):
+    """PLS decomposition of volumes [nz, ny, nx] (dect_pls_decompose3, image-space
+    system, six-neighbour R): returns (u_water, u_bone, report)."""
+    torch = _torch()
+    if x_high.dim() != 3:
+        raise ValueError("x_high must be [nz, ny, nx]")
+    nz, ny, nx = (int(v) for v in x_high.shape)
+    _dev(x_high, "x_high", (nz, ny, nx))
+    _dev(x_low, "x_low", (nz, ny, nx))
+    if out is None:
+        u1, u2 = torch.empty_like(x_high), torch.empty_like(x_high)
+    else:
+        u1, u2 = out
+    _dev(u1, "u_water", (nz, ny, nx))
+    _dev(u2, "u_bone", (nz, ny, nx))
+    prm = dect_pls_params(p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low,
+                          p.gamma, p.edge_eps, p.edge_tau, p.max_iter, p.tol,
+                          int(getattr(p, "mode", 0)))
+    rep = dect_report()
+    _check(lib().dect_pls_decompose3(nx, ny, nz, ct.c_void_p(x_high.data_ptr()),
+                                     ct.c_void_p(x_low.data_ptr()), ct.byref(prm),
+                                     ct.c_void_p(u1.data_ptr()), ct.c_void_p(u2.data_ptr()),
+                                     ct.byref(rep), _stream()), "dect_pls_decompose3")
+    return u1, u2, rep
 
 
 class AdmBatch:
