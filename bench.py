@@ -421,9 +421,19 @@ def adm3_extra(iters: int):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     per_it = ((t2 - t1) - (t1 - t0)) / (iters - 1)
+    # 3-D PLS of the result (six-neighbour R), gamma 1e-3 and 1
+    pls = {}
+    for gamma in (1e-3, 1.0):
+        dect.pls_decompose3(r.x_high, r.x_low, C.PlsParams(gamma=gamma))
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        _, _, prep = dect.pls_decompose3(r.x_high, r.x_low, C.PlsParams(gamma=gamma))
+        torch.cuda.synchronize()
+        pls[f"gamma_{gamma:g}"] = {"ms": round((time.perf_counter() - q0) * 1e3, 2),
+                                   "pcg_iters": prep.iters}
     return {"workload": "adm_tv3_cone_512x512x64_360views_64x736det_2energies", "iters": iters,
             "ms_per_iteration_2energies": round(per_it * 1e3, 2),
-            "iters_per_s": round(1.0 / per_it, 2),
+            "iters_per_s": round(1.0 / per_it, 2), "pls3": pls,
             "J_first_last": [round(float(r.log[0, 0] + r.log[0, 1]), 1),
                              round(float(r.log[-1, 0] + r.log[-1, 1]), 1)]}
 
