@@ -6,7 +6,8 @@
 // per-block partial sums reduced in a fixed order by one block, scalars and
 // the log kept on the device.
 //
-// Iteration k (N-voxel kernels, one thread per voxel):
+// Iteration k (element-wise kernels: grid-stride loops over at most 2048
+// blocks, so the one-block reductions read few partial sums):
 //   k3_tv     lambda -= xi (grad f - z) (k > 0: the previous iteration's
 //             multiplier step, grad f being the new image's), z = shrink(
 //             grad f - lambda / rho, 1 / rho), W = rho (grad f - z) - lambda;
@@ -22,7 +23,7 @@
 #include <cmath>
 #include <vector>
 
-#include "common.h"
+#include "volume.h"
 
 namespace dect {
 namespace {
@@ -63,14 +64,15 @@ __device__ __forceinline__ void coords(const Dims &d, size_t i, int &c, int &r, 
     z = (int)(i / ((size_t)d.nx * d.ny));
 }
 
+constexpr int kMaxBlk = 2048;  // grid of the element-wise kernels (grid-stride loops)
+
 __global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f,
                                              float *__restrict__ lam, float *__restrict__ zz,
                                              float *__restrict__ W, int first, float xi, float rho,
                                              double *__restrict__ part, size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     double tv = 0.0, pres = 0.0;
-    if (i < d.N) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         int c, r, z;
         coords(d, i, c, r, z);
         float g[3];
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f
             W[a * d.N + i] = rho * (g[a] - za) - l[a];
             pres += (double)(g[a] - za) * (g[a] - za);
         }
-        tv = sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
+        tv += sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
     }
     block_sum(tv, part + Q_TV * stride + blockIdx.x);
     block_sum(pres, part + Q_PRES * stride + blockIdx.x);
@@ -101,14 +103,13 @@ __global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f
 __global__ __launch_bounds__(256) void k3_tvonly(Dims d, const float *__restrict__ f,
                                                  double *__restrict__ part, size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     double tv = 0.0;
-    if (i < d.N) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         int c, r, z;
         coords(d, i, c, r, z);
         float g[3];
         grad_at(d, f, i, c, r, z, g[0], g[1], g[2]);
-        tv = sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
+        tv += sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
     }
     block_sum(tv, part + Q_TV * stride + blockIdx.x);
 }
@@ -132,14 +133,13 @@ __global__ __launch_bounds__(256) void k3_g(Dims d, const float *__restrict__ W,
                                             const float *__restrict__ h, float *__restrict__ G,
                                             double *__restrict__ part, size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     double gg = 0.0;
-    if (i < d.N) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         int c, r, z;
         coords(d, i, c, r, z);
         const float g = gradT_at(d, W, i, c, r, z) + h[i];
         G[i] = g;
-        gg = (double)g * g;
+        gg += (double)g * g;
     }
     block_sum(gg, part + Q_GG * stride + blockIdx.x);
 }
@@ -148,14 +148,13 @@ __global__ __launch_bounds__(256) void k3_g(Dims d, const float *__restrict__ W,
 __global__ __launch_bounds__(256) void k3_gradnorm(Dims d, const float *__restrict__ G,
                                                    double *__restrict__ part, size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     double s = 0.0;
-    if (i < d.N) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         int c, r, z;
         coords(d, i, c, r, z);
         float g[3];
         grad_at(d, G, i, c, r, z, g[0], g[1], g[2]);
-        s = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+        s += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
     }
     block_sum(s, part + Q_GRADG * stride + blockIdx.x);
 }
@@ -164,9 +163,10 @@ __global__ __launch_bounds__(256) void k3_gradnorm(Dims d, const float *__restri
 __global__ __launch_bounds__(256) void k3_sumsq(const float *__restrict__ p, size_t n, int q,
                                                 double *__restrict__ part, size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const double v = i < n ? (double)p[i] : 0.0;
-    block_sum(v * v, part + q * stride + blockIdx.x);
+    double ss = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        ss += (double)p[i] * p[i];
+    block_sum(ss, part + q * stride + blockIdx.x);
 }
 
 struct Scal3 {
@@ -178,14 +178,13 @@ __global__ __launch_bounds__(256) void k3_step(Dims d, const float *__restrict__
                                                const Scal3 *__restrict__ sc,
                                                double *__restrict__ part, size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     double ff = 0.0;
-    if (i < d.N) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         const float fo = f[i];
         const float fn = fo - (float)sc->alpha * G[i];
         s[i] = fn - fo;
         f[i] = fn;
-        ff = (double)fo * fo;
+        ff += (double)fo * fo;
     }
     block_sum(ff, part + Q_FF * stride + blockIdx.x);
 }
@@ -194,12 +193,11 @@ __global__ __launch_bounds__(256) void k3_step(Dims d, const float *__restrict__
 __global__ __launch_bounds__(256) void k3_resid(float *__restrict__ p, const float *__restrict__ gs,
                                                 size_t M, double *__restrict__ part, size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     double rr = 0.0;
-    if (i < M) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (size_t)gridDim.x * 256) {
         const float r = p[i] - gs[i];
         p[i] = r;
-        rr = (double)r * r;
+        rr += (double)r * r;
     }
     block_sum(rr, part + Q_RR * stride + blockIdx.x);
 }
@@ -208,8 +206,8 @@ __global__ __launch_bounds__(256) void k3_resid(float *__restrict__ p, const flo
 __global__ __launch_bounds__(256) void k3_scale(const float *__restrict__ m, float beta, size_t M,
                                                 float *__restrict__ gs)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < M) gs[i] = beta * m[i];
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (size_t)gridDim.x * 256)
+        gs[i] = beta * m[i];
 }
 
 // h' = mu hb; y = h' - h + rho grad^T grad s; h = h'.  With s == NULL only h
@@ -219,9 +217,8 @@ __global__ __launch_bounds__(256) void k3_y(Dims d, const float *__restrict__ hb
                                             float mu, float rho, double *__restrict__ part,
                                             size_t stride)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     double ss = 0.0, sy = 0.0;
-    if (i < d.N) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         const float hn = mu * hb[i];
         if (s) {
             int c, r, z;
@@ -238,8 +235,8 @@ __global__ __launch_bounds__(256) void k3_y(Dims d, const float *__restrict__ hb
             if (z >= 1) l += si - s[i - P];
             if (z + 1 <= d.nz - 1) l -= s[i + P] - si;
             const float y = (hn - h[i]) + rho * l;
-            ss = (double)si * si;
-            sy = (double)si * y;
+            ss += (double)si * si;
+            sy += (double)si * y;
         }
         h[i] = hn;
     }
@@ -315,15 +312,15 @@ __global__ void k3_init(Scal3 *sc, const double *__restrict__ part, size_t strid
 
 __global__ __launch_bounds__(256) void k3_zero(float *__restrict__ p, size_t n)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = 0.f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        p[i] = 0.f;
 }
 
 __global__ __launch_bounds__(256) void k3_out(const float *__restrict__ f, float inv_beta, size_t n,
                                               float *__restrict__ x)
 {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) x[i] = f[i] * inv_beta;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        x[i] = f[i] * inv_beta;
 }
 
 unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
@@ -351,7 +348,8 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const Dims d{g->nx, g->ny, g->nz, (size_t)g->nx * g->ny * g->nz};
     const size_t M = (size_t)g->n_views * g->n_rows * g->n_bins;
     const int K = p->max_iter;
-    const int nbN = (int)nblk(d.N), nbM = (int)nblk(M);
+    const int nbN = (int)std::min<size_t>(kMaxBlk, nblk(d.N));
+    const int nbM = (int)std::min<size_t>(kMaxBlk, nblk(M));
     const size_t stride = (size_t)std::max(nbN, nbM);
 
     // library-owned work buffers of this call (sized to the problem)
@@ -374,9 +372,9 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const double betas[2] = {p->beta_high, p->beta_low};
 
     for (int e = 0; e < 2; ++e) {
-        hipLaunchKernelGGL(k3_zero, dim3(nblk(d.N)), dim3(256), 0, s, f, d.N);
-        hipLaunchKernelGGL(k3_zero, dim3(nblk(3 * d.N)), dim3(256), 0, s, lam, 3 * d.N);
-        hipLaunchKernelGGL(k3_zero, dim3(nblk(3 * d.N)), dim3(256), 0, s, zz, 3 * d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, f, d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, lam, 3 * d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, zz, 3 * d.N);
         hipLaunchKernelGGL(k3_scale, dim3(nbM), dim3(256), 0, s, ms[e], (float)betas[e], M, gs);
         // r = A 0 - gs, h = mu A^T r
         if ((st = cone_project(g, f, pr, s))) return st;

@@ -1,5 +1,6 @@
 // extern "C" entry points of libdect (declared in include/dect.h).
 #include "common.h"
+#include "volume.h"
 
 namespace dect {
 const char *last_error();

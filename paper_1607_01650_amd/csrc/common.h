@@ -209,12 +209,6 @@ dect_status cone_project(const dect_cone_geometry *g, const float *vol, float *p
                          hipStream_t s);
 dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, float *vol,
                              hipStream_t s);
-dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const float *m_low,
-                    const dect_adm_params *p, float *x_high, float *x_low, dect_report *rep,
-                    hipStream_t s);
-dect_status pls_decompose3(int nx, int ny, int nz, const float *xh, const float *xl,
-                           const dect_pls_params *p, float *u1, float *u2, dect_report *rep,
-                           hipStream_t s);
 dect_status backproject(const dect_geometry *g, const float *sino, float *img, int batch,
                         hipStream_t s);
 

@@ -11,7 +11,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "common.h"
+#include "volume.h"
 
 namespace dect {
 namespace {
