@@ -79,3 +79,34 @@ def test_calls_fail_loudly_without_a_device(lib):
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         dect.project(torch.zeros((C.TINY.ny, C.TINY.nx)), C.TINY)
+
+
+def test_volume_entry_points_validate_first(lib):
+    """The cone-beam pair, the 3-D ADM and the 3-D PLS reject bad arguments
+    on the host before any device work."""
+    import dataclasses
+    buf = ct.c_void_p(16)  # never dereferenced: validation fails first
+    g = C.ConeGeometry(nx=40, ny=36, nz=21, voxel_mm=1.0, n_views=24, n_bins=70, n_rows=9,
+                       bin_mm=1.3, row_mm=1.1, sod_mm=150.0, sdd_mm=300.0)
+    cases = [
+        (dataclasses.replace(g, n_rows=200, row_mm=2.0), dect.DECT_ERR_GEOMETRY),  # steep cone
+        (dataclasses.replace(g, sod_mm=20.0), dect.DECT_ERR_GEOMETRY),            # orbit inside
+        (dataclasses.replace(g, sdd_mm=140.0), dect.DECT_ERR_GEOMETRY),           # SDD < SOD
+        (dataclasses.replace(g, nz=0), dect.DECT_ERR_INVALID_ARG),
+        (dataclasses.replace(g, row_mm=-1.0), dect.DECT_ERR_INVALID_ARG),
+    ]
+    for gg, want in cases:
+        assert lib.dect_cone_project(dect.ConeArg(gg).ref, buf, buf, None) == want, gg
+        assert lib.dect_cone_backproject(dect.ConeArg(gg).ref, buf, buf, None) == want, gg
+    assert lib.dect_cone_project(None, buf, buf, None) == dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_cone_project(dect.ConeArg(g).ref, None, buf, None) == dect.DECT_ERR_INVALID_ARG
+    for flags, tol in ((dect.DECT_NONNEG, 0.0), (0, 1e-3), (dect.DECT_STEP_BB2, 0.0)):
+        prm = dect.dect_adm_params(1.0, 16.0, 4.0, 1.0, 0.8, 5, tol, flags, None)
+        assert lib.dect_adm_tv3(dect.ConeArg(g).ref, buf, buf, ct.byref(prm), buf, buf, None,
+                                None) == dect.DECT_ERR_INVALID_ARG
+    p = dect.pls_params(C.PlsParams())
+    att = dect.pls_params(C.PlsParams(mode=1))
+    sing = dect.dect_pls_params(1.0, 2.0, 2.0, 4.0, 1.0, 0.1, 0.25, 10, 1e-6, 0)
+    for nz, prm in ((4, att), (4, sing), (0, p)):
+        assert lib.dect_pls_decompose3(8, 8, nz, buf, buf, ct.byref(prm), buf, buf, None,
+                                       None) == dect.DECT_ERR_INVALID_ARG

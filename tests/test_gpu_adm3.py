@@ -80,3 +80,36 @@ def test_refusals(torch):
     for change in ({"nonneg": True}, {"tol": 1e-3}, {"step": "bb2"}):
         with pytest.raises(dect.DectError):
             dect.adm_tv3(z, z, g, dataclasses.replace(PARAMS, max_iter=2, **change))
+
+
+def test_full_size_first_iteration(torch):
+    """512 x 512 x 64, 360 views, 64 x 736 panel (the bench configuration):
+    from f = 0 (lambda = z = 0, so W = 0) the first gradient is
+    G = -mu beta A^T m and the first step the exact line search along it, so
+    x^1 = alpha0 mu A^T m with alpha0 = |G|^2 / (mu |A G|^2 + rho |grad G|^2);
+    and J^0 = mu/2 |beta m|^2.  A, A^T are the GPU pair (its own parity tests
+    hold it to the oracle); the rest is formed on the host in FP64."""
+    from paper_1607_01650_amd import dect
+    g = C.CONE
+    vol = to_dev(torch, P.cone_volume(g, 0, supersample=2))
+    mh = dect.cone_project(vol, g)
+    ml = dect.cone_project(vol * 1.3, g)
+    p = C.AdmParams(mu=45.0 / g.n_views, rho=1024.0, xi=256.0, beta_high=1.0, beta_low=0.79,
+                    max_iter=1)
+    r = dect.adm_tv3(mh, ml, g, p, want_log=True)
+    for e, (m, beta, xe) in enumerate(((mh, p.beta_high, r.x_high), (ml, p.beta_low, r.x_low))):
+        atm = to_np(dect.cone_backproject(m, g))
+        G = -p.mu * beta * atm
+        ag = to_np(dect.cone_project(to_dev(torch, G), g))
+        gd = O.grad3(G)
+        alpha0 = np.sum(G * G) / (p.mu * np.sum(ag * ag) + p.rho * np.sum(gd * gd))
+        want = alpha0 * p.mu * atm
+        err = rel_l2(to_np(xe), want)
+        gs = np.float32(beta) * to_np(m).astype(np.float32)
+        j0 = 0.5 * p.mu * np.sum(gs.astype(np.float64) ** 2)
+        print(f"3-D ADM 512x512x64 energy {e}: first iterate rel-L2 {err:.2e}, J0 rel err "
+              f"{abs(r.log[0, e] - j0) / j0:.2e}, alpha0 rel err "
+              f"{abs(r.log[0, 2 + e] - alpha0) / alpha0:.2e}", flush=True)
+        assert err <= 1e-5
+        assert abs(r.log[0, e] - j0) <= 1e-9 * j0
+        assert abs(r.log[0, 2 + e] - alpha0) <= 1e-5 * alpha0
