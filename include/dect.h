@@ -315,10 +315,11 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
  * except: flags must be 0 (zero start, BB1 step; else DECT_ERR_INVALID_ARG)
  * and tol must be 0 (fixed iteration count); params->log, when not NULL,
  * receives the [max_iter+1][4] rows {J_high, J_low, alpha_high, alpha_low}.
- * The energies run one after the other; state in FP32, reductions in FP64.
- * Allocates its work buffers per call (about 12 volumes and 2 projection
- * sets) and synchronises the stream before returning.  DECT_ERR_NONFINITE
- * when a logged objective or step is not finite.
+ * The two energies advance together (each with its own step), every
+ * projector call walking both volumes at once; state in FP32, reductions in
+ * FP64.  Allocates its work buffers per call (per energy about 12 volumes
+ * and 2 projection sets) and synchronises the stream before returning.
+ * DECT_ERR_NONFINITE when a logged objective or step is not finite.
  */
 dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
                          const float *d_m_low, const dect_adm_params *params, float *d_x_high,

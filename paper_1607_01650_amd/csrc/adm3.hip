@@ -1,8 +1,9 @@
 // ADM-TV on a volume (Eq. 10 with Eq. 2's TV over backward differences in
 // x, y and z, the isotropic shrinkage of Eq. 8 on the 3-vector, the
 // deferred multiplier step of Eq. 7 and the BB1 step of Eq. 9), with the
-// cone-beam projector pair as A.  Energies run one after the other, each
-// with the iteration below; state in FP32, every reduction in FP64 from
+// cone-beam projector pair as A.  The two energies advance together (each
+// with its own state, step and partial sums) so that every projector call
+// walks both volumes at once; state in FP32, every reduction in FP64 from
 // per-block partial sums reduced in a fixed order by one block, scalars and
 // the log kept on the device.
 //
@@ -352,70 +353,97 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const int nbM = (int)std::min<size_t>(kMaxBlk, nblk(M));
     const size_t stride = (size_t)std::max(nbN, nbM);
 
-    // library-owned work buffers of this call (sized to the problem)
-    DevBuf bf, bs, bG, bh, bhb, blam, bz, bW, bgs, bp, bpart, bsc, blog;
+    // library-owned work buffers of this call (sized to the problem), one
+    // set per energy; the two energies advance together so that every
+    // projector call walks both volumes at once
+    DevBuf buf[2][10], bpart[2], bsc, blog;
+    const size_t vsz[10] = {d.N, d.N, d.N, d.N, d.N, 3 * d.N, 3 * d.N, 3 * d.N, M, M};
     dect_status st;
-    if ((st = bf.ensure(d.N * 4)) || (st = bs.ensure(d.N * 4)) || (st = bG.ensure(d.N * 4)) ||
-        (st = bh.ensure(d.N * 4)) || (st = bhb.ensure(d.N * 4)) || (st = blam.ensure(3 * d.N * 4)) ||
-        (st = bz.ensure(3 * d.N * 4)) || (st = bW.ensure(3 * d.N * 4)) || (st = bgs.ensure(M * 4)) ||
-        (st = bp.ensure(M * 4)) || (st = bpart.ensure(Q_COUNT * stride * 8)) ||
-        (st = bsc.ensure(sizeof(Scal3))) || (st = blog.ensure((size_t)(K + 1) * 5 * 8 * 2)))
+    for (int e = 0; e < 2; ++e) {
+        for (int a = 0; a < 10; ++a)
+            if ((st = buf[e][a].ensure(vsz[a] * 4))) return st;
+        if ((st = bpart[e].ensure(Q_COUNT * stride * 8))) return st;
+    }
+    if ((st = bsc.ensure(2 * sizeof(Scal3))) || (st = blog.ensure((size_t)(K + 1) * 5 * 8 * 2)))
         return st;
-    float *f = (float *)bf.ptr, *sv = (float *)bs.ptr, *G = (float *)bG.ptr, *h = (float *)bh.ptr,
-          *hb = (float *)bhb.ptr, *lam = (float *)blam.ptr, *zz = (float *)bz.ptr,
-          *W = (float *)bW.ptr, *gs = (float *)bgs.ptr, *pr = (float *)bp.ptr;
-    double *part = (double *)bpart.ptr, *dlog = (double *)blog.ptr;
+    float *f[2], *sv[2], *G[2], *h[2], *hb[2], *lam[2], *zz[2], *W[2], *gs[2], *pr[2];
+    double *part[2];
+    for (int e = 0; e < 2; ++e) {
+        float **dst[10] = {&f[e], &sv[e], &G[e], &h[e], &hb[e], &lam[e], &zz[e], &W[e], &gs[e],
+                           &pr[e]};
+        for (int a = 0; a < 10; ++a) *dst[a] = (float *)buf[e][a].ptr;
+        part[e] = (double *)bpart[e].ptr;
+    }
+    double *dlog = (double *)blog.ptr;
     Scal3 *sc = (Scal3 *)bsc.ptr;
     const float mu = (float)p->mu, rho = (float)p->rho, xi = (float)p->xi;
     const float *ms[2] = {m_high, m_low};
     float *xs[2] = {x_high, x_low};
     const double betas[2] = {p->beta_high, p->beta_low};
+    const float *cf[2] = {f[0], f[1]}, *cG[2] = {G[0], G[1]}, *cpr[2] = {pr[0], pr[1]};
 
     for (int e = 0; e < 2; ++e) {
-        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, f, d.N);
-        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, lam, 3 * d.N);
-        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, zz, 3 * d.N);
-        hipLaunchKernelGGL(k3_scale, dim3(nbM), dim3(256), 0, s, ms[e], (float)betas[e], M, gs);
-        // r = A 0 - gs, h = mu A^T r
-        if ((st = cone_project(g, f, pr, s))) return st;
-        hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr, gs, M, part, stride);
-        if ((st = cone_backproject(g, pr, hb, s))) return st;
-        hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb, h, (const float *)nullptr, mu,
-                           rho, part, stride);
-        hipLaunchKernelGGL(k3_init, dim3(1), dim3(256), 0, s, sc, part, stride, nbM);
-        DECT_HIP(hipGetLastError());
-        double *elog = dlog + (size_t)e * (K + 1) * 5;
-        for (int k = 0; k < K; ++k) {
-            hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, f, lam, zz, W, k == 0 ? 1 : 0,
-                               xi, rho, part, stride);
-            hipLaunchKernelGGL(k3_g, dim3(nbN), dim3(256), 0, s, d, W, h, G, part, stride);
-            if (k == 0) {
-                if ((st = cone_project(g, G, pr, s))) return st;
-                hipLaunchKernelGGL(k3_sumsq, dim3(nbM), dim3(256), 0, s, pr, M, (int)Q_PP, part,
-                                   stride);
-                hipLaunchKernelGGL(k3_gradnorm, dim3(nbN), dim3(256), 0, s, d, G, part, stride);
-                hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM,
-                                   0, p->mu, p->rho, (double *)nullptr);
-            }
-            hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM, 1,
-                               p->mu, p->rho, elog + (size_t)k * 5);
-            hipLaunchKernelGGL(k3_step, dim3(nbN), dim3(256), 0, s, d, G, f, sv, sc, part, stride);
-            if ((st = cone_project(g, f, pr, s))) return st;
-            hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr, gs, M, part, stride);
-            if ((st = cone_backproject(g, pr, hb, s))) return st;
-            hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb, h, (const float *)sv, mu,
-                               rho, part, stride);
-            hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM, 2,
-                               p->mu, p->rho, (double *)nullptr);
-            DECT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, f[e], d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, lam[e], 3 * d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, zz[e], 3 * d.N);
+        hipLaunchKernelGGL(k3_scale, dim3(nbM), dim3(256), 0, s, ms[e], (float)betas[e], M, gs[e]);
+    }
+    // r = A 0 - gs, h = mu A^T r
+    if ((st = cone_project2(g, cf, pr, s))) return st;
+    for (int e = 0; e < 2; ++e)
+        hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr[e], gs[e], M, part[e], stride);
+    if ((st = cone_backproject2(g, cpr, hb, s))) return st;
+    for (int e = 0; e < 2; ++e) {
+        hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb[e], h[e], (const float *)nullptr,
+                           mu, rho, part[e], stride);
+        hipLaunchKernelGGL(k3_init, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbM);
+    }
+    DECT_HIP(hipGetLastError());
+    for (int k = 0; k < K; ++k) {
+        for (int e = 0; e < 2; ++e) {
+            hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, f[e], lam[e], zz[e], W[e],
+                               k == 0 ? 1 : 0, xi, rho, part[e], stride);
+            hipLaunchKernelGGL(k3_g, dim3(nbN), dim3(256), 0, s, d, W[e], h[e], G[e], part[e],
+                               stride);
         }
-        hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, f, part, stride);
-        hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc, part, stride, nbN, nbM, 3,
-                           p->mu, p->rho, elog + (size_t)K * 5);
-        hipLaunchKernelGGL(k3_out, dim3(nbN), dim3(256), 0, s, f, (float)(1.0 / betas[e]), d.N,
-                           xs[e]);
+        if (k == 0) {
+            if ((st = cone_project2(g, cG, pr, s))) return st;
+            for (int e = 0; e < 2; ++e) {
+                hipLaunchKernelGGL(k3_sumsq, dim3(nbM), dim3(256), 0, s, pr[e], M, (int)Q_PP,
+                                   part[e], stride);
+                hipLaunchKernelGGL(k3_gradnorm, dim3(nbN), dim3(256), 0, s, d, G[e], part[e],
+                                   stride);
+                hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride,
+                                   nbN, nbM, 0, p->mu, p->rho, (double *)nullptr);
+            }
+        }
+        for (int e = 0; e < 2; ++e) {
+            hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN,
+                               nbM, 1, p->mu, p->rho, dlog + ((size_t)e * (K + 1) + k) * 5);
+            hipLaunchKernelGGL(k3_step, dim3(nbN), dim3(256), 0, s, d, G[e], f[e], sv[e], sc + e,
+                               part[e], stride);
+        }
+        if ((st = cone_project2(g, cf, pr, s))) return st;
+        for (int e = 0; e < 2; ++e)
+            hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr[e], gs[e], M, part[e],
+                               stride);
+        if ((st = cone_backproject2(g, cpr, hb, s))) return st;
+        for (int e = 0; e < 2; ++e) {
+            hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb[e], h[e],
+                               (const float *)sv[e], mu, rho, part[e], stride);
+            hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN,
+                               nbM, 2, p->mu, p->rho, (double *)nullptr);
+        }
         DECT_HIP(hipGetLastError());
     }
+    for (int e = 0; e < 2; ++e) {
+        hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, f[e], part[e], stride);
+        hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN, nbM,
+                           3, p->mu, p->rho, dlog + ((size_t)e * (K + 1) + K) * 5);
+        hipLaunchKernelGGL(k3_out, dim3(nbN), dim3(256), 0, s, f[e], (float)(1.0 / betas[e]), d.N,
+                           xs[e]);
+    }
+    DECT_HIP(hipGetLastError());
     // the work buffers are freed at return: wait for the stream first
     std::vector<double> hlog((size_t)(K + 1) * 5 * 2);
     DECT_HIP(hipMemcpyAsync(hlog.data(), dlog, hlog.size() * 8, hipMemcpyDeviceToHost, s));

@@ -28,7 +28,7 @@
 #include <mutex>
 #include <vector>
 
-#include "common.h"
+#include "volume.h"
 
 namespace dect {
 namespace {
@@ -89,30 +89,45 @@ __device__ __forceinline__ ConeRay cone_ray(const ConeDev &g, int v, int j, int 
 
 // vol [nz][ny][nx] -> vx [nx][nz+4][ny+4] and vy [ny][nz+4][nx+4], written
 // whole (zero borders included), one thread per element of the larger copy.
-__global__ __launch_bounds__(256) void k_cone_pad(const float *__restrict__ vol, int nx, int ny,
+// NE = 2: the two volumes interleaved ([..][2]), so that one load carries a
+// tap of both.
+template <int NE>
+__global__ __launch_bounds__(256) void k_cone_pad(const float *__restrict__ vol0,
+                                                  const float *__restrict__ vol1, int nx, int ny,
                                                   int nz, float *__restrict__ vx,
                                                   float *__restrict__ vy)
 {
     const int pz = nz + 2 * kCPad, py = ny + 2 * kCPad, px = nx + 2 * kCPad;
     const size_t nvx = (size_t)nx * pz * py, nvy = (size_t)ny * pz * px;
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const float *vol[2] = {vol0, vol1};
     if (i < nvx) {  // vx: y fastest
         const int yy = (int)(i % py) - kCPad, zz = (int)(i / py % pz) - kCPad;
         const int x = (int)(i / ((size_t)py * pz));
-        vx[i] = (yy >= 0 && yy < ny && zz >= 0 && zz < nz)
-                    ? vol[((size_t)zz * ny + yy) * nx + x] : 0.f;
+        const bool in = yy >= 0 && yy < ny && zz >= 0 && zz < nz;
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            vx[i * NE + e] = in ? vol[e][((size_t)zz * ny + yy) * nx + x] : 0.f;
     }
     if (i < nvy) {  // vy: x fastest
         const int xx = (int)(i % px) - kCPad, zz = (int)(i / px % pz) - kCPad;
         const int y = (int)(i / ((size_t)px * pz));
-        vy[i] = (xx >= 0 && xx < nx && zz >= 0 && zz < nz)
-                    ? vol[((size_t)zz * ny + y) * nx + xx] : 0.f;
+        const bool in = xx >= 0 && xx < nx && zz >= 0 && zz < nz;
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            vy[i * NE + e] = in ? vol[e][((size_t)zz * ny + y) * nx + xx] : 0.f;
     }
 }
 
+// four floats at 8-byte alignment: taps h and h + 1 of both volumes
+typedef float c4a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef float c2 __attribute__((ext_vector_type(2)));
+
+template <int NE>
 __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ vx,
                                                   const float *__restrict__ vy,
-                                                  float *__restrict__ proj)
+                                                  float *__restrict__ proj0,
+                                                  float *__restrict__ proj1)
 {
     const size_t nray = (size_t)g.V * g.J * g.B;
     const size_t rid = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -123,26 +138,42 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
     const int pq = nq + 2 * kCPad, pz = g.nz + 2 * kCPad;
     const float *base = r.xmaj ? vx : vy;
     int64_t q = r.a, qz = r.az;
-    double acc = 0.0;
+    double acc[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) acc[e] = 0.0;
     for (int i0 = 0; i0 < nl; i0 += 4) {
-        float s = 0.f;
+        float s[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) s[e] = 0.f;
         const int i1 = min(nl, i0 + 4);
         for (int i = i0; i < i1; ++i) {
             const int h = min(max((int)(q >> 32), -2), nq);
             const int hz = min(max((int)(qz >> 32), -2), g.nz);
             const float wa = (float)(uint32_t)q * kTwoM32c;
             const float wz = (float)(uint32_t)qz * kTwoM32c;
-            const float *p0 = base + ((size_t)i * pz + hz + kCPad) * pq + h + kCPad;
-            const float *p1 = p0 + pq;
-            const float lo = fmaf(wa, p0[1] - p0[0], p0[0]);
-            const float hi = fmaf(wa, p1[1] - p1[0], p1[0]);
-            s += fmaf(wz, hi - lo, lo);
+            const size_t o0 = ((size_t)i * pz + hz + kCPad) * pq + h + kCPad;
+            if constexpr (NE == 1) {
+                const float *p0 = base + o0;
+                const float *p1 = p0 + pq;
+                const float lo = fmaf(wa, p0[1] - p0[0], p0[0]);
+                const float hi = fmaf(wa, p1[1] - p1[0], p1[0]);
+                s[0] += fmaf(wz, hi - lo, lo);
+            } else {
+                const c4a8 a0 = *(const c4a8 *)(base + 2 * o0);
+                const c4a8 a1 = *(const c4a8 *)(base + 2 * (o0 + pq));
+                const float lo0 = fmaf(wa, a0.z - a0.x, a0.x), hi0 = fmaf(wa, a1.z - a1.x, a1.x);
+                const float lo1 = fmaf(wa, a0.w - a0.y, a0.y), hi1 = fmaf(wa, a1.w - a1.y, a1.y);
+                s[0] += fmaf(wz, hi0 - lo0, lo0);
+                s[1] += fmaf(wz, hi1 - lo1, lo1);
+            }
             q += r.k;
             qz += r.kz;
         }
-        acc += (double)s;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) acc[e] += (double)s[e];
     }
-    proj[rid] = (float)(acc * (double)r.L);
+    proj0[rid] = (float)(acc[0] * (double)r.L);
+    if constexpr (NE == 2) proj1[rid] = (float)(acc[1] * (double)r.L);
 }
 
 // Per (view, bin): the ray's 32.32 in-plane coordinate at plane 0 and its
@@ -178,15 +209,20 @@ __global__ __launch_bounds__(256) void k_cone_tab(ConeDev g, ConeTab *__restrict
     tab[i] = t;
 }
 
-// yl = L * proj, L the forward walk's path length per plane of each ray.
-__global__ __launch_bounds__(256) void k_cone_scale(ConeDev g, const float *__restrict__ proj,
+// yl = L * proj (NE = 2: both projections interleaved), L the forward
+// walk's path length per plane of each ray.
+template <int NE>
+__global__ __launch_bounds__(256) void k_cone_scale(ConeDev g, const float *__restrict__ proj0,
+                                                    const float *__restrict__ proj1,
                                                     float *__restrict__ yl)
 {
     const size_t nray = (size_t)g.V * g.J * g.B;
     const size_t rid = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (rid >= nray) return;
     const int b = (int)(rid % g.B), j = (int)(rid / g.B % g.J), v = (int)(rid / ((size_t)g.B * g.J));
-    yl[rid] = proj[rid] * cone_ray(g, v, j, b).L;
+    const float L = cone_ray(g, v, j, b).L;
+    yl[rid * NE] = proj0[rid] * L;
+    if constexpr (NE == 2) yl[rid * 2 + 1] = proj1[rid] * L;
 }
 
 #ifndef DECT_CONE_ZC
@@ -204,9 +240,11 @@ constexpr int kZC = DECT_CONE_ZC;  // slices per gather thread
 // plane lies within one voxel of z, the height taken in FP64 at the first
 // such row and stepped in FP32 (a few rows).  Per-view sums in FP32,
 // accumulated over views in FP64.
+template <int NE>
 __global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *__restrict__ tab,
                                                      const float *__restrict__ yl,
-                                                     float *__restrict__ vol)
+                                                     float *__restrict__ vol0,
+                                                     float *__restrict__ vol1)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y;
@@ -218,9 +256,11 @@ __global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *_
     const float ibin = (float)(1.0 / g.bin), bc = (float)((g.B - 1) / 2.0 - g.off / g.bin);
     const double cz = (g.nz - 1) / 2.0, jc = (g.J - 1) / 2.0;
     const size_t JB = (size_t)g.J * g.B;
-    double acc[kZC];
+    double acc[kZC][NE];
 #pragma unroll
-    for (int t = 0; t < kZC; ++t) acc[t] = 0.0;
+    for (int t = 0; t < kZC; ++t)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) acc[t][e] = 0.0;
     for (int v = 0; v < g.V; ++v) {
         const float ct = (float)g.cs[2 * v], st = (float)g.cs[2 * v + 1];
         const float sx = R * ct, sy = R * st;
@@ -236,11 +276,13 @@ __global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *_
         // clamped before conversion (bounds only; the exact test below decides)
         const int bl = max(0, (int)ceilf(fminf(fmaxf(bmin - 1e-3f, -1.f), (float)g.B)));
         const int bh = min(g.B - 1, (int)floorf(fminf(fmaxf(bmax + 1e-3f, -1.f), (float)g.B)));
-        float part[kZC];
+        float part[kZC][NE];
 #pragma unroll
-        for (int t = 0; t < kZC; ++t) part[t] = 0.f;
+        for (int t = 0; t < kZC; ++t)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) part[t][e] = 0.f;
         const ConeTab *tv = tab + (size_t)v * g.B;
-        const float *yv = yl + (size_t)v * JB;
+        const float *yv = yl + (size_t)v * JB * NE;
         for (int b = bl; b <= bh; ++b) {
             const ConeTab tb = tv[b];
             const int pl = tb.xmaj ? x : y, c = tb.xmaj ? y : x;
@@ -254,7 +296,7 @@ __global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *_
             const double qz0 = cz - jc * sb;                  // height of row 0
             const float sbf = (float)sb, isb = 1.f / sbf;
             const float lo0 = (float)(z0 - 1 - qz0) * isb;
-            const float *yb = yv + b;
+            const float *yb = yv + (size_t)b * NE;
 #pragma unroll
             for (int t = 0; t < kZC; ++t) {
                 // rows with |qz - z| < 1: j in (lo, lo + 2/sb)
@@ -262,21 +304,36 @@ __global__ __launch_bounds__(256) void k_cone_gather(ConeDev g, const ConeTab *_
                 const int j0 = max(0, (int)floorf(fminf(fmaxf(lo, -1.f), (float)g.J)) + 1);
                 const int j1 = min(g.J - 1, (int)ceilf(fminf(fmaxf(hi, -1.f), (float)g.J)) - 1);
                 const float e0 = (float)(qz0 + j0 * sb - (z0 + t));  // qz - z at row j0
-                float s = 0.f;
+                float s[NE];
+#pragma unroll
+                for (int e = 0; e < NE; ++e) s[e] = 0.f;
                 for (int j = j0; j <= j1; ++j) {
                     const float w = fmaxf(0.f, 1.f - fabsf(fmaf((float)(j - j0), sbf, e0)));
-                    s = fmaf(w, yb[(size_t)j * g.B], s);
+                    if constexpr (NE == 1) {
+                        s[0] = fmaf(w, yb[(size_t)j * g.B], s[0]);
+                    } else {
+                        const c2 yy = *(const c2 *)(yb + (size_t)j * g.B * 2);
+                        s[0] = fmaf(w, yy.x, s[0]);
+                        s[1] = fmaf(w, yy.y, s[1]);
+                    }
                 }
-                part[t] = fmaf(wi, s, part[t]);
+#pragma unroll
+                for (int e = 0; e < NE; ++e) part[t][e] = fmaf(wi, s[e], part[t][e]);
             }
         }
 #pragma unroll
-        for (int t = 0; t < kZC; ++t) acc[t] += (double)part[t];
+        for (int t = 0; t < kZC; ++t)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) acc[t][e] += (double)part[t][e];
     }
     const size_t plane = (size_t)g.nx * g.ny;
 #pragma unroll
     for (int t = 0; t < kZC; ++t)
-        if (z0 + t < g.nz) vol[(size_t)(z0 + t) * plane + (size_t)y * g.nx + x] = (float)acc[t];
+        if (z0 + t < g.nz) {
+            const size_t o = (size_t)(z0 + t) * plane + (size_t)y * g.nx + x;
+            vol0[o] = (float)acc[t][0];
+            if constexpr (NE == 2) vol1[o] = (float)acc[t][1];
+        }
 }
 
 struct ConeWork {
@@ -341,12 +398,13 @@ dect_status cone_setup(const dect_cone_geometry *g, ConeDev &d, ConeWork *w, hip
     return DECT_OK;
 }
 
-}  // namespace
-
-dect_status cone_project(const dect_cone_geometry *g, const float *vol, float *proj,
-                         hipStream_t s)
+// Both projectors for NE volumes (1 or 2) sharing one geometry.
+template <int NE>
+dect_status cone_project_n(const dect_cone_geometry *g, const float *const *vol,
+                           float *const *proj, hipStream_t s)
 {
-    if (!vol || !proj) return fail(DECT_ERR_INVALID_ARG, "dect_cone_project: null buffer");
+    for (int e = 0; e < NE; ++e)
+        if (!vol[e] || !proj[e]) return fail(DECT_ERR_INVALID_ARG, "dect_cone_project: null buffer");
     std::lock_guard<std::mutex> lk(g_cone_mu);
     ConeWork *w = cone_workspace(s);
     ConeDev d;
@@ -355,25 +413,29 @@ dect_status cone_project(const dect_cone_geometry *g, const float *vol, float *p
     const size_t pz = d.nz + 2 * kCPad;
     const size_t nxb = (size_t)d.nx * pz * (d.ny + 2 * kCPad) * 4;
     const size_t nyb = (size_t)d.ny * pz * (d.nx + 2 * kCPad) * 4;
-    if (w->vx.bytes < nxb || w->vy.bytes < nyb) {
+    if (w->vx.bytes < nxb * NE || w->vy.bytes < nyb * NE) {
         DECT_HIP(hipStreamSynchronize(s));
-        if ((st = w->vx.ensure(nxb)) || (st = w->vy.ensure(nyb))) return st;
+        if ((st = w->vx.ensure(nxb * NE)) || (st = w->vy.ensure(nyb * NE))) return st;
     }
     const size_t npad = std::max(nxb, nyb) / 4;
-    hipLaunchKernelGGL(k_cone_pad, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, vol,
-                       d.nx, d.ny, d.nz, (float *)w->vx.ptr, (float *)w->vy.ptr);
+    hipLaunchKernelGGL(k_cone_pad<NE>, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s,
+                       vol[0], vol[NE - 1], d.nx, d.ny, d.nz, (float *)w->vx.ptr,
+                       (float *)w->vy.ptr);
     DECT_HIP(hipGetLastError());
     const size_t nray = (size_t)d.V * d.J * d.B;
-    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
-                       (const float *)w->vx.ptr, (const float *)w->vy.ptr, proj);
+    hipLaunchKernelGGL(k_cone_fwd<NE>, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
+                       (const float *)w->vx.ptr, (const float *)w->vy.ptr, proj[0], proj[NE - 1]);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
 
-dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, float *vol,
-                             hipStream_t s)
+template <int NE>
+dect_status cone_backproject_n(const dect_cone_geometry *g, const float *const *proj,
+                               float *const *vol, hipStream_t s)
 {
-    if (!vol || !proj) return fail(DECT_ERR_INVALID_ARG, "dect_cone_backproject: null buffer");
+    for (int e = 0; e < NE; ++e)
+        if (!vol[e] || !proj[e])
+            return fail(DECT_ERR_INVALID_ARG, "dect_cone_backproject: null buffer");
     std::lock_guard<std::mutex> lk(g_cone_mu);
     ConeWork *w = cone_workspace(s);
     ConeDev d;
@@ -381,24 +443,50 @@ dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, flo
     if (st) return st;
     const size_t nray = (size_t)d.V * d.J * d.B;
     const size_t ntab = (size_t)d.V * d.B;
-    if (w->yl.bytes < nray * 4 || w->tab.bytes < ntab * sizeof(ConeTab)) {
+    if (w->yl.bytes < nray * 4 * NE || w->tab.bytes < ntab * sizeof(ConeTab)) {
         DECT_HIP(hipStreamSynchronize(s));
-        if ((st = w->yl.ensure(nray * 4)) || (st = w->tab.ensure(ntab * sizeof(ConeTab))))
+        if ((st = w->yl.ensure(nray * 4 * NE)) || (st = w->tab.ensure(ntab * sizeof(ConeTab))))
             return st;
     }
     hipLaunchKernelGGL(k_cone_tab, dim3((unsigned)((ntab + 255) / 256)), dim3(256), 0, s, d,
                        (ConeTab *)w->tab.ptr);
     DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_cone_scale, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
-                       proj, (float *)w->yl.ptr);
+    hipLaunchKernelGGL(k_cone_scale<NE>, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
+                       proj[0], proj[NE - 1], (float *)w->yl.ptr);
     DECT_HIP(hipGetLastError());
     const int nzc = (d.nz + kZC - 1) / kZC;
-    hipLaunchKernelGGL(k_cone_gather, dim3((unsigned)((d.nx + 63) / 64), (unsigned)d.ny,
-                                           (unsigned)((nzc + 3) / 4)),
+    hipLaunchKernelGGL(k_cone_gather<NE>, dim3((unsigned)((d.nx + 63) / 64), (unsigned)d.ny,
+                                               (unsigned)((nzc + 3) / 4)),
                        dim3(256), 0, s, d, (const ConeTab *)w->tab.ptr, (const float *)w->yl.ptr,
-                       vol);
+                       vol[0], vol[NE - 1]);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
+}
+
+}  // namespace
+
+dect_status cone_project(const dect_cone_geometry *g, const float *vol, float *proj,
+                         hipStream_t s)
+{
+    return cone_project_n<1>(g, &vol, &proj, s);
+}
+
+dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, float *vol,
+                             hipStream_t s)
+{
+    return cone_backproject_n<1>(g, &proj, &vol, s);
+}
+
+dect_status cone_project2(const dect_cone_geometry *g, const float *const vol[2],
+                          float *const proj[2], hipStream_t s)
+{
+    return cone_project_n<2>(g, vol, proj, s);
+}
+
+dect_status cone_backproject2(const dect_cone_geometry *g, const float *const proj[2],
+                              float *const vol[2], hipStream_t s)
+{
+    return cone_backproject_n<2>(g, proj, vol, s);
 }
 
 }  // namespace dect

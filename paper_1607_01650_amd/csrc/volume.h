@@ -5,6 +5,13 @@
 
 namespace dect {
 
+// The cone-beam pair on two volumes sharing one geometry (both walked
+// together, interleaved; each result equal to the single-volume call's).
+dect_status cone_project2(const dect_cone_geometry *g, const float *const vol[2],
+                          float *const proj[2], hipStream_t s);
+dect_status cone_backproject2(const dect_cone_geometry *g, const float *const proj[2],
+                              float *const vol[2], hipStream_t s);
+
 dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const float *m_low,
                     const dect_adm_params *p, float *x_high, float *x_low, dect_report *rep,
                     hipStream_t s);
