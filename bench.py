@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--mode", choices=["metric", "projectors", "copy", "traffic", "cone"],
                     default="metric")
     ap.add_argument("--copy-mb", type=int, default=512)
-    ap.add_argument("--pmc-dir", default="gpurun_out/pmc")
+    ap.add_argument("--pmc-dir", default="pmc", help="directory of the FETCH_SIZE / WRITE_SIZE runs")
     ap.add_argument("--warm-cases", type=int, default=4,
                     help="held-out cases for the learned-warm-start time-to-tol entry")
     ap.add_argument("--batch-slices", type=int, default=64,
