@@ -1,17 +1,27 @@
 """GPU parity of the 3-D ADM-TV (dect_adm_tv3: Eq. 10 on a volume with the
 3-D TV and the cone-beam pair) against the FP64 oracle's run (or_adm3) of
 each energy on the same FP32 inputs: a 32 x 28 x 12 volume (30 views, 10 x 48
-panel, 30 iterations) and a ragged one (37 x 29 x 9, detector offset, 25
-iterations): image rel-L2 <= 1e-4, the logged objective within 1e-5 over
-the first 10 iterations (where a wrong term or scale would show) and 1e-4
-over the run; the BB step within 1e-4 over the first 10 iterations and 1e-3
-over the run (a ratio of differences of nearly equal iterates, which
-amplifies FP32 rounding as the run converges: measured 1.4e-4 late in the
-run while the images agree to 2e-6; a wrong term would be O(1) from the
-start).  The state is FP32 and the back-projection's in-plane weights are
-the forward's, so the differences are FP32 rounding amplified by the
-iteration.  Flags and a tolerance stop
-are refused.
+panel, 30 iterations), a ragged one (37 x 29 x 9, detector offset, 25
+iterations) and a 128 x 128 x 16 one (90 views, 16 x 192 panel, 40
+iterations).
+
+* Images: rel-L2 <= 1e-4.
+* The logged objective of Eq. 4: within 1e-5 over the first 10 iterations,
+  where a wrong term or scale would show.  Over the run the bound is
+  1e-5 sqrt(J^0 / J^k), at least 1e-4.  The 3-D path forms the residual
+  r = A f - beta m in FP32, whose absolute error is ~eps32 |beta m|, so the
+  relative error of |r|^2 grows as the residual falls below the data.
+  Measured: 1.3e-4 at J^0 / J^k = 2400 on the 128 x 128 x 16 case, where the
+  images agree to 1e-6.
+* The BB step: within 1e-4 over the first 10 iterations and 1e-3 over the
+  run.  It is a ratio of differences of nearly equal iterates, which
+  amplifies FP32 rounding as the run converges (measured 1.4e-4 late in the
+  run while the images agree to 2e-6); a wrong term would be O(1) from the
+  start.
+
+The state is FP32 and the back-projection's in-plane weights are the
+forward's, so the differences are FP32 rounding amplified by the iteration.
+Flags and a tolerance stop are refused.
 """
 import dataclasses
 
@@ -30,6 +40,8 @@ VOL = C.ConeGeometry(nx=32, ny=28, nz=12, voxel_mm=1.0, n_views=30, n_bins=48, n
                      bin_mm=1.5, row_mm=1.5, sod_mm=100.0, sdd_mm=200.0)
 RAGGED = C.ConeGeometry(nx=37, ny=29, nz=9, voxel_mm=1.0, n_views=23, n_bins=53, n_rows=7,
                         bin_mm=1.4, row_mm=1.7, sod_mm=90.0, sdd_mm=170.0, det_offset_mm=0.6)
+MID = C.ConeGeometry(nx=128, ny=128, nz=16, voxel_mm=1.0, n_views=90, n_bins=192, n_rows=16,
+                     bin_mm=1.2, row_mm=1.2, sod_mm=500.0, sdd_mm=1000.0)
 PARAMS = C.AdmParams(mu=1.0, rho=64.0, xi=16.0, beta_high=1.0, beta_low=0.79, max_iter=30)
 
 
@@ -50,8 +62,8 @@ def _data(g, seed):
     return out
 
 
-@pytest.mark.parametrize("geom,iters,seed", [(VOL, 30, 0), (RAGGED, 25, 1)],
-                         ids=["volume", "ragged"])
+@pytest.mark.parametrize("geom,iters,seed", [(VOL, 30, 0), (RAGGED, 25, 1), (MID, 40, 2)],
+                         ids=["volume", "ragged", "128x128x16"])
 def test_parity(torch, geom, iters, seed):
     from paper_1607_01650_amd import dect
     m = _data(geom, seed)
@@ -67,7 +79,11 @@ def test_parity(torch, geom, iters, seed):
               f"alpha k<=10 {arel[:10].max():.2e}, all {arel.max():.2e}", flush=True)
         assert err <= 1e-4
         assert jrel[:11].max() <= 1e-5
-        assert jrel.max() <= 1e-4
+        # late in the run J is formed from an FP32 residual r = A f - beta m
+        # whose error is ~eps32 |beta m| absolute, so its relative error
+        # grows like |beta m| / |r| ~ sqrt(J^0 / J^k)
+        jbound = 1e-5 * np.maximum(10.0, np.sqrt(log[0, 0] / log[:, 0]))
+        assert np.all(jrel <= jbound)
         assert arel[:10].max() <= 1e-4
         assert arel.max() <= 1e-3
     assert r.report.iters == iters
