@@ -3,7 +3,8 @@ dect_cone_backproject) against the FP64 oracle's pair (the 3-D scanner of
 Sec. 3, Joseph's model of Sec. 2.4 with bilinear taps in the driving plane).
 
 * ragged volumes (several 64-bin wavefronts plus a tail, odd slice and row
-  counts, detector offset, irregular view angles): forward and back
+  counts, detector offset, irregular view angles, and views at multiples of
+  45 degrees whose central rays lie on the x-major / y-major boundary): forward and back
   projection within 1e-5 of the oracle's largest value.  The GPU steps each
   ray's in-plane coordinate and height in 32.32 fixed point and interpolates
   in FP32 (summed in FP64 per four planes); the gather back-projection
@@ -35,6 +36,10 @@ RAGGED = C.ConeGeometry(nx=64, ny=56, nz=33, voxel_mm=1.0, n_views=40, n_bins=97
                         bin_mm=1.4, row_mm=1.6, sod_mm=150.0, sdd_mm=300.0, det_offset_mm=0.6)
 SMALL = C.ConeGeometry(nx=40, ny=36, nz=21, voxel_mm=1.0, n_views=24, n_bins=70, n_rows=9,
                        bin_mm=1.3, row_mm=1.1, sod_mm=150.0, sdd_mm=300.0, det_offset_mm=0.4)
+# views at multiples of 45 degrees with an odd bin count and no offset: the
+# central ray of the diagonal views lies on the x-major / y-major boundary
+DIAG = C.ConeGeometry(nx=33, ny=33, nz=9, voxel_mm=1.0, n_views=8, n_bins=61, n_rows=5,
+                      bin_mm=1.2, row_mm=1.3, sod_mm=120.0, sdd_mm=240.0)
 IRREG = dataclasses.replace(
     SMALL, n_views=17,
     angles_rad=tuple(0.37 * v + 0.05 * math.sin(3.0 * v) for v in range(17)))
@@ -54,7 +59,8 @@ def _maxrel(a, ref):
     return float(np.abs(a - ref).max() / np.abs(ref).max())
 
 
-@pytest.mark.parametrize("geom", [RAGGED, SMALL, IRREG], ids=["ragged", "small", "irregular"])
+@pytest.mark.parametrize("geom", [RAGGED, SMALL, IRREG, DIAG],
+                         ids=["ragged", "small", "irregular", "diagonal"])
 def test_pair_parity(torch, geom):
     dect = _dect()
     rng = np.random.default_rng(5)
