@@ -9,10 +9,11 @@
 // and height) is interpolated bilinearly between the four nearest voxel
 // centres, and the samples are scaled by the path length per plane.
 //
-//   k_cone_pad : two zero-padded permuted copies of the volume, [x][z][y] for
-//                x-major rays and [y][z][x] for y-major rays, so that a
-//                sample's two in-plane taps are adjacent (borders written as
-//                zeros by the same kernel: no memset in the path).
+//   k_cone_pad_x, k_cone_pad_y : two zero-padded permuted copies of the
+//                volume, [x][z][y] for x-major rays and [y][z][x] for
+//                y-major rays, so that a sample's two in-plane taps are
+//                adjacent (borders written as zeros by the same kernels: no
+//                memset in the path).
 //   k_cone_fwd : one thread per ray (64 adjacent bins of one row per
 //                wavefront); the ray's constants are formed in FP64 from the
 //                view's cos/sin and turned into 32.32 fixed point (in-plane
@@ -88,27 +89,52 @@ __device__ __forceinline__ ConeRay cone_ray(const ConeDev &g, int v, int j, int 
 }
 
 // vol [nz][ny][nx] -> vx [nx][nz+4][ny+4] and vy [ny][nz+4][nx+4], written
-// whole (zero borders included), one thread per element of the larger copy.
-// NE = 2: the two volumes interleaved ([..][2]), so that one load carries a
-// tap of both.
+// whole (zero borders included).  NE = 2: the two volumes interleaved
+// ([..][2]), so that one load carries a tap of both.
+//
+// k_cone_pad_x: vx is a transpose (y fastest), staged through a 32 x 32
+// LDS tile per (x block, padded-y block, padded slice): read along x, write
+// along y.  k_cone_pad_y: vy keeps x fastest, one thread per element.
 template <int NE>
-__global__ __launch_bounds__(256) void k_cone_pad(const float *__restrict__ vol0,
-                                                  const float *__restrict__ vol1, int nx, int ny,
-                                                  int nz, float *__restrict__ vx,
-                                                  float *__restrict__ vy)
+__global__ __launch_bounds__(256) void k_cone_pad_x(const float *__restrict__ vol0,
+                                                    const float *__restrict__ vol1, int nx, int ny,
+                                                    int nz, float *__restrict__ vx)
 {
-    const int pz = nz + 2 * kCPad, py = ny + 2 * kCPad, px = nx + 2 * kCPad;
-    const size_t nvx = (size_t)nx * pz * py, nvy = (size_t)ny * pz * px;
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ float tile[NE][32][33];
+    const int pz = nz + 2 * kCPad, py = ny + 2 * kCPad;
+    const int x0 = blockIdx.x * 32, yp0 = blockIdx.y * 32, zp = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int z = zp - kCPad;
     const float *vol[2] = {vol0, vol1};
-    if (i < nvx) {  // vx: y fastest
-        const int yy = (int)(i % py) - kCPad, zz = (int)(i / py % pz) - kCPad;
-        const int x = (int)(i / ((size_t)py * pz));
-        const bool in = yy >= 0 && yy < ny && zz >= 0 && zz < nz;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int y = yp0 + ty + 8 * r - kCPad, x = x0 + tx;
+        const bool in = x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            vx[i * NE + e] = in ? vol[e][((size_t)zz * ny + yy) * nx + x] : 0.f;
+            tile[e][ty + 8 * r][tx] = in ? vol[e][((size_t)z * ny + y) * nx + x] : 0.f;
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int x = x0 + ty + 8 * r, yp = yp0 + tx;
+        if (x < nx && yp < py) {
+            const size_t o = ((size_t)x * pz + zp) * py + yp;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) vx[o * NE + e] = tile[e][tx][ty + 8 * r];
+        }
+    }
+}
+
+template <int NE>
+__global__ __launch_bounds__(256) void k_cone_pad_y(const float *__restrict__ vol0,
+                                                    const float *__restrict__ vol1, int nx, int ny,
+                                                    int nz, float *__restrict__ vy)
+{
+    const int pz = nz + 2 * kCPad, px = nx + 2 * kCPad;
+    const size_t nvy = (size_t)ny * pz * px;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const float *vol[2] = {vol0, vol1};
     if (i < nvy) {  // vy: x fastest
         const int xx = (int)(i % px) - kCPad, zz = (int)(i / px % pz) - kCPad;
         const int y = (int)(i / ((size_t)px * pz));
@@ -417,10 +443,12 @@ dect_status cone_project_n(const dect_cone_geometry *g, const float *const *vol,
         DECT_HIP(hipStreamSynchronize(s));
         if ((st = w->vx.ensure(nxb * NE)) || (st = w->vy.ensure(nyb * NE))) return st;
     }
-    const size_t npad = std::max(nxb, nyb) / 4;
-    hipLaunchKernelGGL(k_cone_pad<NE>, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s,
-                       vol[0], vol[NE - 1], d.nx, d.ny, d.nz, (float *)w->vx.ptr,
-                       (float *)w->vy.ptr);
+    hipLaunchKernelGGL(k_cone_pad_x<NE>,
+                       dim3((unsigned)((d.nx + 31) / 32), (unsigned)((d.ny + 2 * kCPad + 31) / 32),
+                            (unsigned)pz),
+                       dim3(256), 0, s, vol[0], vol[NE - 1], d.nx, d.ny, d.nz, (float *)w->vx.ptr);
+    hipLaunchKernelGGL(k_cone_pad_y<NE>, dim3((unsigned)((nyb / 4 + 255) / 256)), dim3(256), 0, s,
+                       vol[0], vol[NE - 1], d.nx, d.ny, d.nz, (float *)w->vy.ptr);
     DECT_HIP(hipGetLastError());
     const size_t nray = (size_t)d.V * d.J * d.B;
     hipLaunchKernelGGL(k_cone_fwd<NE>, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
