@@ -182,6 +182,15 @@ def _dev(t, name: str, shape_tail: Tuple[int, ...]):
     return t
 
 
+def _out(t, name: str, shape: Tuple[int, ...]):
+    """A caller-supplied output: a float32 contiguous device tensor of exactly
+    `shape` (the kernels write as many items as the input holds)."""
+    _dev(t, name, shape[-2:])
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
 def _batch(t, tail: int) -> int:
     n = 1
     for s in t.shape[:-tail]:
@@ -203,7 +212,7 @@ def project(img, geom: C.Geometry, out=None):
     if out is None:
         out = torch.empty(lead + (geom.n_views, geom.n_bins), device=img.device,
                           dtype=torch.float32)
-    _dev(out, "out", (geom.n_views, geom.n_bins))
+    _out(out, "out", lead + (geom.n_views, geom.n_bins))
     b = _batch(img, 2)
     if b == 0:
         return out
@@ -219,7 +228,7 @@ def backproject(sino, geom: C.Geometry, out=None):
     lead = tuple(sino.shape[:-2])
     if out is None:
         out = torch.empty(lead + (geom.ny, geom.nx), device=sino.device, dtype=torch.float32)
-    _dev(out, "out", (geom.ny, geom.nx))
+    _out(out, "out", lead + (geom.ny, geom.nx))
     b = _batch(sino, 2)
     if b == 0:
         return out
@@ -236,7 +245,7 @@ def fbp(sino, geom: C.Geometry, out=None):
     lead = tuple(sino.shape[:-2])
     if out is None:
         out = torch.empty(lead + (geom.ny, geom.nx), device=sino.device, dtype=torch.float32)
-    _dev(out, "out", (geom.ny, geom.nx))
+    _out(out, "out", lead + (geom.ny, geom.nx))
     b = _batch(sino, 2)
     if b == 0:
         return out
@@ -273,7 +282,7 @@ def cone_project(vol, geom: C.ConeGeometry, out=None):
     if out is None:
         out = torch.empty((geom.n_views, geom.n_rows, geom.n_bins), device=vol.device,
                           dtype=torch.float32)
-    _dev(out, "out", (geom.n_views, geom.n_rows, geom.n_bins))
+    _out(out, "out", (geom.n_views, geom.n_rows, geom.n_bins))
     _check(lib().dect_cone_project(ConeArg(geom).ref, ct.c_void_p(vol.data_ptr()),
                                    ct.c_void_p(out.data_ptr()), _stream()), "dect_cone_project")
     return out
@@ -288,7 +297,7 @@ def cone_backproject(proj, geom: C.ConeGeometry, out=None):
         raise ValueError("proj must be [V, rows, bins]")
     if out is None:
         out = torch.empty((geom.nz, geom.ny, geom.nx), device=proj.device, dtype=torch.float32)
-    _dev(out, "out", (geom.nz, geom.ny, geom.nx))
+    _out(out, "out", (geom.nz, geom.ny, geom.nx))
     _check(lib().dect_cone_backproject(ConeArg(geom).ref, ct.c_void_p(proj.data_ptr()),
                                        ct.c_void_p(out.data_ptr()), _stream()),
            "dect_cone_backproject")

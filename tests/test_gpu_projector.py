@@ -125,6 +125,13 @@ def test_empty_batch_and_errors(torch):
     with pytest.raises(dect.DectError) as ei:
         dect.project(torch.zeros((g.ny, g.nx), device="cuda"), bad)
     assert ei.value.status == dect.DECT_ERR_GEOMETRY
+    # a caller-supplied output must hold exactly the input's items
+    x3 = torch.zeros((3, g.ny, g.nx), device="cuda")
+    for fn, shape in ((dect.project, (2, g.n_views, g.n_bins)),
+                      (dect.backproject, (2, g.ny, g.nx)), (dect.fbp, (2, g.ny, g.nx))):
+        src = x3 if fn is dect.project else torch.zeros((3, g.n_views, g.n_bins), device="cuda")
+        with pytest.raises(ValueError):
+            fn(src, g, out=torch.empty(shape, device="cuda"))
 
 
 def test_sample_count_matches_oracle(torch):
