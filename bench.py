@@ -508,6 +508,7 @@ def warm_start_extra(n: int):
             "median_ms_plain": med([r["t_plain_ms"] for r in ok]),
             "median_ms_learned": med([r["t_learned_ms"] for r in ok]),
             "median_time_ratio": med([r["t_learned_ms"] / r["t_plain_ms"] for r in ok]),
+            "fallbacks": sum(r["start"] != "net" for r in rows),
             "fbp_start": {"reached": sum(r["k_fbp"] >= 0 for r in rows),
                           "median_iters": med([r["k_fbp"] for r in rows if r["k_fbp"] >= 0]),
                           "median_ms": med([r["t_fbp_ms"] for r in rows if r["k_fbp"] >= 0]),

@@ -193,6 +193,11 @@ dect_status dect_fbp(const dect_geometry *geom, const float *d_sino, float *d_im
  * state: NULL, or a state from dect_adm_state_create for this geometry;
  *   an empty state starts a run, a used one continues it (x inputs ignored).
  * rep: NULL, or filled after synchronising the stream.
+ * Non-finite values: the iteration records the first iteration at which a
+ *   sum turned non-finite in a device flag.  The flag is read, and
+ *   DECT_ERR_NONFINITE returned, only by a call that synchronises (rep or
+ *   params->log not NULL); a call with neither returns DECT_OK without
+ *   looking, and the next synchronising call on the same state reports it.
  */
 dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
                         const dect_adm_params *params, float *d_x_high, float *d_x_low,
@@ -200,6 +205,15 @@ dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const 
 
 dect_status dect_adm_state_create(const dect_geometry *geom, dect_adm_state **out);
 dect_status dect_adm_state_destroy(dect_adm_state *state);
+
+/*
+ * Empty a state, so that the next dect_adm_tv call on it starts a new run
+ * (from zero, or from its x inputs with DECT_WARM_START).  The state keeps its
+ * buffers and captured iteration graphs.  Asynchronous work already queued on
+ * the state must be on the stream the next call uses.  DECT_ERR_INVALID_ARG
+ * for a NULL state.
+ */
+dect_status dect_adm_state_reset(dect_adm_state *state);
 
 /*
  * Image-domain decomposition by penalised least squares (Eqs. 11-15): the
@@ -329,21 +343,35 @@ dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
  * PLS decomposition of volumes (Eqs. 11-15 with R of Eq. 14 over the six
  * face neighbours): u = D^{-1} x per voxel (Eq. 12), then (I + gamma L) u_m
  * = (D^{-1} x)_m per material by Jacobi-PCG from u = D^{-1} x, L the
- * six-neighbour Laplacian with pair weights edge_eps where either voxel is
- * an edge of x_low, else 1.  Edges come from the 3-D Prewitt operator (per
- * axis, the 3 x 3 face sum at +1 minus the one at -1, borders replicated),
- * an edge where its squared magnitude exceeds edge_tau^2 times the largest;
- * that decision is taken in FP32 in a fixed order.  Device buffers
- * d_x_* [nz][ny][nx] in, d_u_water / d_u_bone [nz][ny][nx] out.  params as
- * for dect_pls_decompose with mode DECT_PLS_IMAGE only (else
+ * six-neighbour Laplacian with pair weights from d_edge_w.  Device buffers
+ * d_x_* [nz][ny][nx] in, d_u_water / d_u_bone [nz][ny][nx] out.
+ * d_edge_w: NULL to detect edges on d_x_low (dect_pls_edge_weights3), or a
+ *   [3][nz][ny][nx] map of pair weights (x, y and z pairs as there).
+ * params as for dect_pls_decompose with mode DECT_PLS_IMAGE only (else
  * DECT_ERR_INVALID_ARG); stops when |res| <= tol |b| or after max_iter
- * iterations per material.  Allocates its work buffers per call (about 11
- * volumes) and synchronises the stream.  rep: iters (the larger of the two
- * materials) and pcg_residual.
+ * iterations per material.  Work buffers (about 10 volumes) are
+ * library-owned per device and kept between calls; the call synchronises
+ * the stream.  rep: iters (the larger of the two materials) and
+ * pcg_residual.
  */
 dect_status dect_pls_decompose3(int32_t nx, int32_t ny, int32_t nz, const float *d_x_high,
                                 const float *d_x_low, const dect_pls_params *params,
-                                float *d_u_water, float *d_u_bone, dect_report *rep, void *stream);
+                                const float *d_edge_w, float *d_u_water, float *d_u_bone,
+                                dect_report *rep, void *stream);
+
+/*
+ * Pair weights e_ik of Eq. 14 over the six face neighbours from the 3-D
+ * Prewitt edge map of d_x (per axis, the 3 x 3 face sum at +1 minus the one
+ * at -1, borders replicated): an edge where the squared magnitude exceeds
+ * tau^2 times the largest (evaluated in FP32 as
+ * fmaf(gx, gx, fmaf(gy, gy, gz*gz)) against fp32(tau^2) * max).  d_w[0]
+ * couples i and i + 1 (x), d_w[1] i and i + nx (y), d_w[2] i and i + nx ny
+ * (z): eps if either voxel is an edge, 1 otherwise, 0 for pairs leaving the
+ * volume.  d_x [nz][ny][nx], d_w [3][nz][ny][nx] float32, both device
+ * memory of the caller.  DECT_ERR_INVALID_ARG for bad sizes, tau or eps.
+ */
+dect_status dect_pls_edge_weights3(int32_t nx, int32_t ny, int32_t nz, const float *d_x,
+                                   double tau, double eps, float *d_w, void *stream);
 
 /* Number of Joseph samples (ray, line) with the crossing inside (-1, n)
  * for a geometry: the unit of projector work. */

@@ -25,9 +25,8 @@
  *                                energy block of Eq. 3, with the f-gradient of
  *                                Eq. 9 and a Barzilai-Borwein step
  *   or_dinv                      direct decomposition u = D^{-1} x (Eqs. 11-12)
- *   or_edges_f32                 Prewitt edge weights e_ik (after Eq. 14); the
- *                                threshold decision is taken in FP32 because it
- *                                turns floats into a binary map
+ *   or_edges / or_edges3         Prewitt edge weights e_ik (after Eq. 14), the
+ *                                gradient magnitude and threshold in FP64
  *   or_laplacian                 the Hessian of R(u) (Eq. 14), halved
  *   or_pcg                       Jacobi-preconditioned CG for Eq. 15
  *   or_pcg_att                   the attenuation-space variant |x - Du|^2 +
@@ -574,43 +573,44 @@ void or_dinv(size_t n, double e1h, double e2h, double e1l, double e2l, const dou
 }
 
 /*
- * Prewitt edge map and pair weights, in FP32 with a fixed operation order
- * (the map is a threshold decision, so it is taken in the precision of the
- * GPU kernel).  gx = right column sum - left column sum, gy = lower row sum -
- * upper row sum, borders replicate; m2 = fmaf(gx, gx, gy*gy); edge where
- * m2 > tau2 * max(m2).  e_right[r][c] couples (r,c)-(r,c+1), e_down[r][c]
+ * Edge map and pair weights of the penalty (the edge-weighted R after Eq. 14),
+ * in FP64.  The Prewitt operator with replicated borders: gx = (sum of the
+ * column to the right over rows r-1..r+1) - (sum of the column to the left),
+ * gy = (sum of the row below over columns c-1..c+1) - (sum of the row above);
+ * m2 = gx^2 + gy^2; a pixel is an edge where m2 > tau^2 max(m2), i.e.
+ * |grad| > tau max |grad|.  e_right[r][c] couples (r,c)-(r,c+1), e_down[r][c]
  * couples (r,c)-(r+1,c): eps if either pixel is an edge, else 1; pairs that
- * leave the image get 0.
+ * leave the image get 0.  m2_out (optional) receives m2, *thr_out (optional)
+ * the threshold tau^2 max(m2).
  */
-void or_edges_f32(int nx, int ny, const float *x, float tau2, float eps, float *e_right,
-                  float *e_down, uint8_t *edge)
+void or_edges(int nx, int ny, const double *x, double tau, double eps, double *e_right,
+              double *e_down, uint8_t *edge, double *m2_out, double *thr_out)
 {
     size_t N = (size_t)nx * ny;
-    float *m2 = malloc(N * sizeof(float));
-    float mx = 0.0f;
+    double *m2 = malloc(N * sizeof(double));
+    double mx = 0.0;
     for (int r = 0; r < ny; ++r)
         for (int c = 0; c < nx; ++c) {
             int ru = r > 0 ? r - 1 : 0, rd = r < ny - 1 ? r + 1 : ny - 1;
             int cl = c > 0 ? c - 1 : 0, cr = c < nx - 1 ? c + 1 : nx - 1;
 #define X(rr, cc) x[(size_t)(rr) * nx + (cc)]
-            float right = (X(ru, cr) + X(r, cr)) + X(rd, cr);
-            float left = (X(ru, cl) + X(r, cl)) + X(rd, cl);
-            float down = (X(rd, cl) + X(rd, c)) + X(rd, cr);
-            float up = (X(ru, cl) + X(ru, c)) + X(ru, cr);
+            double gx = (X(ru, cr) + X(r, cr) + X(rd, cr)) - (X(ru, cl) + X(r, cl) + X(rd, cl));
+            double gy = (X(rd, cl) + X(rd, c) + X(rd, cr)) - (X(ru, cl) + X(ru, c) + X(ru, cr));
 #undef X
-            float gx = right - left, gy = down - up;
-            float v = fmaf(gx, gx, gy * gy);
+            double v = gx * gx + gy * gy;
             m2[(size_t)r * nx + c] = v;
             if (v > mx) mx = v;
         }
-    float thr = tau2 * mx;
+    double thr = tau * tau * mx;
     for (size_t i = 0; i < N; ++i) edge[i] = m2[i] > thr;
     for (int r = 0; r < ny; ++r)
         for (int c = 0; c < nx; ++c) {
             size_t i = (size_t)r * nx + c;
-            e_right[i] = c + 1 < nx ? ((edge[i] || edge[i + 1]) ? eps : 1.0f) : 0.0f;
-            e_down[i] = r + 1 < ny ? ((edge[i] || edge[i + nx]) ? eps : 1.0f) : 0.0f;
+            e_right[i] = c + 1 < nx ? ((edge[i] || edge[i + 1]) ? eps : 1.0) : 0.0;
+            e_down[i] = r + 1 < ny ? ((edge[i] || edge[i + nx]) ? eps : 1.0) : 0.0;
         }
+    if (m2_out) memcpy(m2_out, m2, N * sizeof(double));
+    if (thr_out) *thr_out = thr;
     free(m2);
 }
 
@@ -1140,57 +1140,49 @@ int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double r
 
 /* ------------------------------------------------------------ 3-D PLS ---
  * Eqs. 13-15 on a volume: R of Eq. 14 over the six face neighbours, edges
- * from the 3-D Prewitt operator (per axis, the sum over the 3 x 3 face at
- * +1 minus the sum at -1, borders replicated), in FP32 with a fixed order:
- * each face sum runs over the face's first index, then its second, from -1
- * to +1, added one at a time; m2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz)); an
- * edge where m2 > tau2 * max(m2).  Pair weights e_x[i] couple i and i + 1,
- * e_y[i] i and i + nx, e_z[i] i and i + nx ny: eps if either voxel is an
- * edge, else 1; pairs that leave the volume get 0.
+ * from the 3-D Prewitt operator in FP64: per axis, the sum over the 3 x 3
+ * face at +1 minus the sum over the face at -1, borders replicated;
+ * m2 = gx^2 + gy^2 + gz^2; an edge where m2 > tau^2 max(m2).  Pair weights
+ * e_x[i] couple i and i + 1, e_y[i] i and i + nx, e_z[i] i and i + nx ny: eps
+ * if either voxel is an edge, else 1; pairs that leave the volume get 0.
+ * m2_out / thr_out (optional) as in or_edges.
  */
-void or_edges3_f32(int nx, int ny, int nz, const float *x, float tau2, float eps, float *ex,
-                   float *ey, float *ez, uint8_t *edge)
+void or_edges3(int nx, int ny, int nz, const double *x, double tau, double eps, double *ex,
+               double *ey, double *ez, uint8_t *edge, double *m2_out, double *thr_out)
 {
     const size_t P = (size_t)nx * ny, N = P * nz;
-    float *m2 = malloc(N * sizeof(float));
-    float mx = 0.0f;
+    double *m2 = malloc(N * sizeof(double));
+    double mx = 0.0;
 #define CL(v, n) ((v) < 0 ? 0 : ((v) > (n) - 1 ? (n) - 1 : (v)))
 #define V3(zz, rr, cc) x[(size_t)CL(zz, nz) * P + (size_t)CL(rr, ny) * nx + CL(cc, nx)]
     for (int z = 0; z < nz; ++z)
         for (int r = 0; r < ny; ++r)
             for (int c = 0; c < nx; ++c) {
-                float xp = 0.f, xm = 0.f, yp = 0.f, ym = 0.f, zp = 0.f, zm = 0.f;
-                int first = 1;
+                double gx = 0.0, gy = 0.0, gz = 0.0;
                 for (int a = -1; a <= 1; ++a)
                     for (int b = -1; b <= 1; ++b) {
-                        /* x faces: (z + a, r + b); y faces: (z + a, c + b); z faces: (r + a, c + b) */
-                        float vxp = V3(z + a, r + b, c + 1), vxm = V3(z + a, r + b, c - 1);
-                        float vyp = V3(z + a, r + 1, c + b), vym = V3(z + a, r - 1, c + b);
-                        float vzp = V3(z + 1, r + a, c + b), vzm = V3(z - 1, r + a, c + b);
-                        if (first) {
-                            xp = vxp; xm = vxm; yp = vyp; ym = vym; zp = vzp; zm = vzm;
-                            first = 0;
-                        } else {
-                            xp += vxp; xm += vxm; yp += vyp; ym += vym; zp += vzp; zm += vzm;
-                        }
+                        gx += V3(z + a, r + b, c + 1) - V3(z + a, r + b, c - 1);
+                        gy += V3(z + a, r + 1, c + b) - V3(z + a, r - 1, c + b);
+                        gz += V3(z + 1, r + a, c + b) - V3(z - 1, r + a, c + b);
                     }
-                float gx = xp - xm, gy = yp - ym, gz = zp - zm;
-                float v = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+                double v = gx * gx + gy * gy + gz * gz;
                 m2[(size_t)z * P + (size_t)r * nx + c] = v;
                 if (v > mx) mx = v;
             }
 #undef V3
 #undef CL
-    float thr = tau2 * mx;
+    double thr = tau * tau * mx;
     for (size_t i = 0; i < N; ++i) edge[i] = m2[i] > thr;
     for (int z = 0; z < nz; ++z)
         for (int r = 0; r < ny; ++r)
             for (int c = 0; c < nx; ++c) {
                 size_t i = (size_t)z * P + (size_t)r * nx + c;
-                ex[i] = c + 1 < nx ? ((edge[i] || edge[i + 1]) ? eps : 1.0f) : 0.0f;
-                ey[i] = r + 1 < ny ? ((edge[i] || edge[i + nx]) ? eps : 1.0f) : 0.0f;
-                ez[i] = z + 1 < nz ? ((edge[i] || edge[i + P]) ? eps : 1.0f) : 0.0f;
+                ex[i] = c + 1 < nx ? ((edge[i] || edge[i + 1]) ? eps : 1.0) : 0.0;
+                ey[i] = r + 1 < ny ? ((edge[i] || edge[i + nx]) ? eps : 1.0) : 0.0;
+                ez[i] = z + 1 < nz ? ((edge[i] || edge[i + P]) ? eps : 1.0) : 0.0;
             }
+    if (m2_out) memcpy(m2_out, m2, N * sizeof(double));
+    if (thr_out) *thr_out = thr;
     free(m2);
 }
 

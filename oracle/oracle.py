@@ -73,8 +73,7 @@ def lib():
                              ct.c_int]
         L.or_adm.restype = ct.c_int
         L.or_dinv.argtypes = [sz, d, d, d, d, pd, pd, pd, pd]
-        L.or_edges_f32.argtypes = [ct.c_int, ct.c_int, pf, ct.c_float, ct.c_float, pf, pf,
-                                   P(ct.c_uint8)]
+        L.or_edges.argtypes = [ct.c_int, ct.c_int, pd, d, d, pd, pd, P(ct.c_uint8), pd, pd]
         L.or_laplacian.argtypes = [ct.c_int, ct.c_int, pd, pd, pd, pd]
         L.or_pcg.argtypes = [ct.c_int, ct.c_int, pd, pd, d, pd, pd, ct.c_int, d, pd]
         L.or_pcg.restype = ct.c_int
@@ -85,8 +84,8 @@ def lib():
         L.or_project3.argtypes = [P(_Geom3), pd, pd]
         L.or_backproject3.argtypes = [P(_Geom3), pd, pd]
         L.or_adm3.argtypes = [P(_Geom3), pd, d, d, d, d, ct.c_int, pd, pd]
-        L.or_edges3_f32.argtypes = [ct.c_int, ct.c_int, ct.c_int, pf, ct.c_float, ct.c_float,
-                                    pf, pf, pf, P(ct.c_uint8)]
+        L.or_edges3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, d, d, pd, pd, pd,
+                                P(ct.c_uint8), pd, pd]
         L.or_laplacian3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, pd, pd]
         L.or_pcg3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, d, pd, pd, ct.c_int, d,
                               pd]
@@ -311,17 +310,31 @@ def dinv(xh, xl, eta_water_high, eta_bone_high, eta_water_low, eta_bone_low):
     return u1, u2
 
 
-def edges_f32(xl: np.ndarray, tau: float, eps: float):
-    """Prewitt edge weights; the decision is taken in FP32 (tau2 = fp32(tau*tau))."""
-    x = np.ascontiguousarray(xl, dtype=np.float32)
+class EdgeMap:
+    """Edge weights of the penalty and what decided them (FP64): pair weights,
+    the edge flags, m2 = |Prewitt gradient|^2 per pixel and the threshold
+    tau^2 max(m2)."""
+
+    def __init__(self, weights, edge, m2, thr):
+        self.weights, self.edge, self.m2, self.thr = weights, edge, m2, thr
+
+    def near_threshold(self, rel: float) -> np.ndarray:
+        """Pixels whose m2 lies within rel * thr of the threshold, where an
+        evaluation in another precision may decide the other way."""
+        return np.abs(self.m2 - self.thr) <= rel * self.thr
+
+
+def edges(xl: np.ndarray, tau: float, eps: float) -> EdgeMap:
+    """Prewitt edge weights of an image [ny][nx] in FP64: weights (e_right,
+    e_down)."""
+    x = _f64(xl)
     ny, nx = x.shape
-    er = np.empty_like(x)
-    ed = np.empty_like(x)
+    er, ed, m2 = np.empty_like(x), np.empty_like(x), np.empty_like(x)
     e = np.empty(x.shape, dtype=np.uint8)
-    lib().or_edges_f32(nx, ny, _p(x, ct.c_float), ct.c_float(np.float32(tau * tau)),
-                       ct.c_float(np.float32(eps)), _p(er, ct.c_float), _p(ed, ct.c_float),
-                       e.ctypes.data_as(ct.POINTER(ct.c_uint8)))
-    return er, ed, e
+    thr = ct.c_double(0.0)
+    lib().or_edges(nx, ny, _p(x), float(tau), float(eps), _p(er), _p(ed),
+                   e.ctypes.data_as(ct.POINTER(ct.c_uint8)), _p(m2), ct.byref(thr))
+    return EdgeMap((er, ed), e, m2, float(thr.value))
 
 
 def laplacian(er, ed, u):
@@ -355,17 +368,17 @@ def pcg_att(er, ed, eta, gamma: float, xh, xl, max_iter: int = 500, tol: float =
     return u1, u2, int(it), float(rr.value)
 
 
-def edges3_f32(xl: np.ndarray, tau: float, eps: float):
-    """3-D Prewitt edge weights of a volume [nz][ny][nx]: (e_x, e_y, e_z, edge);
-    the decision is taken in FP32 (tau2 = fp32(tau*tau))."""
-    x = np.ascontiguousarray(xl, dtype=np.float32)
+def edges3(xl: np.ndarray, tau: float, eps: float) -> EdgeMap:
+    """3-D Prewitt edge weights of a volume [nz][ny][nx] in FP64: weights
+    (e_x, e_y, e_z)."""
+    x = _f64(xl)
     nz, ny, nx = x.shape
-    ex, ey, ez = np.empty_like(x), np.empty_like(x), np.empty_like(x)
+    ex, ey, ez, m2 = np.empty_like(x), np.empty_like(x), np.empty_like(x), np.empty_like(x)
     e = np.empty(x.shape, dtype=np.uint8)
-    lib().or_edges3_f32(nx, ny, nz, _p(x, ct.c_float), ct.c_float(np.float32(tau * tau)),
-                        ct.c_float(np.float32(eps)), _p(ex, ct.c_float), _p(ey, ct.c_float),
-                        _p(ez, ct.c_float), e.ctypes.data_as(ct.POINTER(ct.c_uint8)))
-    return ex, ey, ez, e
+    thr = ct.c_double(0.0)
+    lib().or_edges3(nx, ny, nz, _p(x), float(tau), float(eps), _p(ex), _p(ey), _p(ez),
+                    e.ctypes.data_as(ct.POINTER(ct.c_uint8)), _p(m2), ct.byref(thr))
+    return EdgeMap((ex, ey, ez), e, m2, float(thr.value))
 
 
 def laplacian3(ex, ey, ez, u):
@@ -390,7 +403,7 @@ def pls3(xh, xl, p, tol: float = 1e-12):
     """3-D decomposition of volumes [nz][ny][nx]: D^{-1} x per voxel, 3-D
     Prewitt edge weights on x_l, PCG per material with the six-neighbour L."""
     b1, b2 = dinv(xh, xl, p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
-    ex, ey, ez, _ = edges3_f32(xl, p.edge_tau, p.edge_eps)
+    ex, ey, ez = edges3(xl, p.edge_tau, p.edge_eps).weights
     u1, i1, _ = pcg3(ex, ey, ez, p.gamma, b1, p.max_iter, tol)
     u2, i2, _ = pcg3(ex, ey, ez, p.gamma, b2, p.max_iter, tol)
     return u1, u2, max(i1, i2)
@@ -404,7 +417,7 @@ def pls(xh, xl, p, edge_w=None, tol: float = 1e-12):
     """
     b1, b2 = dinv(xh, xl, p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
     if edge_w is None:
-        er, ed, _ = edges_f32(xl, p.edge_tau, p.edge_eps)
+        er, ed = edges(xl, p.edge_tau, p.edge_eps).weights
     else:
         er, ed = edge_w[0], edge_w[1]
     if getattr(p, "mode", 0) == 1:  # attenuation space

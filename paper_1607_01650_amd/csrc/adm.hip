@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_tv_fused(
         m.pending2 = sc[o].pending != 0;
         m.record_tv = e == 0;
     }
-    tv_tile<COUPLED>(ty * kTY, tx * kTX, m, partial + (size_t)tile * 5, sc[e].pending != 0, nx,
+    tv_tile<COUPLED>(ty * kTY, tx * kTX, m, partial + (size_t)tile * kTvParts, sc[e].pending != 0, nx,
                      ny, rho, xi);
 }
 
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
                                                 const double *__restrict__ p_yy, int nbi)
 {
     const int e = blockIdx.x;
-    scalar_energy(sc[e], p_tv + (size_t)e * nb_tv * 5, nb_tv, p_fwd + (size_t)e * nb_fwd, nb_fwd,
+    scalar_energy(sc[e], p_tv + (size_t)e * nb_tv * kTvParts, nb_tv, p_fwd + (size_t)e * nb_fwd, nb_fwd,
                   log, log_rows, e, mu, rho, nonneg != 0, nonneg == 0,
                   p_rr + (size_t)e * nbs, nbs, tol, step_rule, p_yy + (size_t)e * nbi, nbi);
 }
@@ -552,7 +552,7 @@ static dect_status state_alloc(dect_adm_state *S, const dect_geometry *g)
         (st = S->r.ensure(4 * M * 4)) || (st = S->p.ensure(4 * M * 4)) ||
         (st = S->lam.ensure(8 * N * 4)) || (st = S->z.ensure(8 * N * 4)) ||
         (st = S->gpad.ensure(2 * P * 4, true)) || (st = S->gpadT.ensure(2 * P * 4, true)) ||
-        (st = S->p_tv.ensure((size_t)2 * S->nb_tv * 5 * 8)) ||
+        (st = S->p_tv.ensure((size_t)2 * S->nb_tv * kTvParts * 8)) ||
         (st = S->p_fwd.ensure((size_t)2 * S->nb_fwd * 8)) ||
         (st = S->p_rr.ensure((size_t)2 * S->nbs * 8)) ||
         (st = S->p_tvo.ensure((size_t)2 * S->nbi * 8)) ||
@@ -828,6 +828,14 @@ dect_status adm_state_create(const dect_geometry *g, dect_adm_state **out)
 dect_status adm_state_destroy(dect_adm_state *S)
 {
     delete S;
+    return DECT_OK;
+}
+
+dect_status adm_state_reset(dect_adm_state *S)
+{
+    if (!S) return fail(DECT_ERR_INVALID_ARG, "dect_adm_state_reset: state is NULL");
+    std::lock_guard<std::mutex> lk(g_adm_mu);
+    S->started = false;
     return DECT_OK;
 }
 

@@ -20,6 +20,9 @@ constexpr int kGW = kTX + 1, kGH = kTY + 1;  // G region (rows/cols -1 .. tile -
 constexpr int kWW = kTX + 2, kWH = kTY + 2;  // w region (rows/cols -1 .. tile)
 constexpr int kFW = kTX + 3, kFH = kTY + 3;  // f region (rows/cols -2 .. tile)
 static_assert(kGW * kGH <= 512 && kWW * kWH <= 512, "two pixels per thread at most");
+// FP64 partial sums one TV tile leaves per energy: TV(f), |G|^2, |grad G|^2,
+// |grad f - z|^2, |f|^2, <G_prev, h>, <G, h>
+constexpr int kTvParts = 7;
 
 struct AdmScalars {
     double alpha;   // step used by the next update
@@ -30,6 +33,7 @@ struct AdmScalars {
     double beta;    // Eq. 3 weight of this energy
     double ss, sy;  // non-negative variant: <s,s> and <s,y> of the last projected step
     double den_prev;  // mu |A G|^2 + rho |grad G|^2 of the previous G (BB2 numerator)
+    double gg_prev, gh_prev, gradg_prev;  // |G|^2, <G, h>, |grad G|^2 of the previous G
     int32_t has_prev, stopped, nonfinite_iter, pending;
     int32_t stop_next;  // the stop rule held: stop once this iteration's update is done
     int64_t iter;      // iterations completed
@@ -111,18 +115,21 @@ struct AdmImg {
 
 // ------------------------------------------------------------- tv_fused ---
 // Tile origin (r0, c0).  Regions relative to it: f on rows/cols -2 .. tile,
-// w on -1 .. tile, G on -1 .. tile - 1, grad G on the kTX x kTY tile.  part5
-// receives (TV(f), |G|^2, |grad G|^2, |grad f - z|^2, |f|^2) of the tile.
+// w on -1 .. tile, G on -1 .. tile - 1, grad G on the kTX x kTY tile.  part
+// receives the kTvParts sums (TV(f), |G|^2, |grad G|^2, |grad f - z|^2, |f|^2,
+// <G_prev, h>, <G, h>) of the tile, where G_prev is the value the padded G
+// buffer holds at the tile's pixels before this tile overwrites it (the
+// previous iteration's G) and h = mu A^T r the data term of this G.
 template <bool COUPLED = false>
-__device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part5,
+__device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part,
                                         bool pending, int nx, int ny, float rho, float xi)
 {
     __shared__ float sf[kFH][kFW + 1], sl[kFH][kFW + 1];
     __shared__ float sf2[COUPLED ? kFH : 1][COUPLED ? kFW + 1 : 1];
     __shared__ float sl2[COUPLED ? kFH : 1][COUPLED ? kFW + 1 : 1];
     __shared__ float swx[kWH][kWW + 1], swy[kWH][kWW + 1];
-    __shared__ float sg[kGH][kGW + 1];
-    __shared__ double outv[5];
+    __shared__ float sg[kGH][kGW + 1], sh[kGH][kGW + 1];
+    __shared__ double outv[kTvParts];
     const float inv_rho = 1.0f / rho;
 
     // h = hmu * (sum of the partial planes, in plane order) on the G region
@@ -272,21 +279,29 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             gv = s;
         }
         sg[rr][cc] = gv;
+        sh[rr][cc] = hsum[k];
     }
     __syncthreads();
 
-    double gg = 0.0, gradg = 0.0;
+    double gg = 0.0, gradg = 0.0, gh_old = 0.0, gh = 0.0;
     const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
     {
         int rr = threadIdx.x / kTX, cc = threadIdx.x % kTX;
         int r = r0 + rr, c = c0 + cc;
         if (r < ny && c < nx) {
             float gv = sg[rr + 1][cc + 1];
+            float hv = sh[rr + 1][cc + 1];
             float gx = c >= 1 ? gv - sg[rr + 1][cc] : 0.f;
             float gy = r >= 1 ? gv - sg[rr][cc + 1] : 0.f;
             gg = (double)gv * gv;
             gradg = (double)gx * gx + (double)gy * gy;
-            m.gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad)] = gv;
+            // this pixel's previous G is read by this thread alone, before it
+            // is replaced
+            float* gp = m.gpad + 2 * ((size_t)(r + kPad) * pnx + c + kPad);
+            const float gprev = *gp;
+            gh_old = (double)gprev * hv;
+            gh = (double)gv * hv;
+            *gp = gv;
         }
         // transposed write: consecutive threads take consecutive rows of one
         // column, i.e. consecutive elements of a line of the transposed copy
@@ -295,9 +310,9 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
         if (rt < ny && ct < nx)
             m.gpadT[2 * ((size_t)(ct + kPad) * pny + rt + kPad)] = sg[rl + 1][cl + 1];
     }
-    double v[5] = {tv, gg, gradg, pres, ff};
-    block_sum<5>(v, outv);
-    if (threadIdx.x < 5) part5[threadIdx.x] = outv[threadIdx.x];
+    double v[kTvParts] = {tv, gg, gradg, pres, ff, gh_old, gh};
+    block_sum<kTvParts>(v, outv);
+    if (threadIdx.x < kTvParts) part[threadIdx.x] = outv[threadIdx.x];
     __syncthreads();
 }
 
@@ -321,57 +336,72 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
                                               const double *__restrict__ p_yy = nullptr,
                                               int nyy = 0)
 {
-    __shared__ double tot[8];
+    constexpr int kP = kTvParts, kFwd = kP, kRR = kP + 1, kYY = kP + 2, kNV = kP + 3;
+    __shared__ double tot[kNV];
     const bool stop_now = fold && s.stop_next;
     const bool run = !s.stopped && !stop_now;
     const bool fresh_rr = fold && s.pending;
     const bool want_yy = step_rule != 0 && s.has_prev;
-    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double v[kNV];
+#pragma unroll
+    for (int j = 0; j < kNV; ++j) v[j] = 0.0;
     if (run) {
         if (fresh_rr)
-            for (int i = threadIdx.x; i < nbs; i += 256) v[6] += p_rr[i];
+            for (int i = threadIdx.x; i < nbs; i += 256) v[kRR] += p_rr[i];
         if (want_yy)
-            for (int i = threadIdx.x; i < nyy; i += 256) v[7] += p_yy[i];
-        // thread t adds entries t, t + 256, ... in that order; eight loads are
-        // issued together
+            for (int i = threadIdx.x; i < nyy; i += 256) v[kYY] += p_yy[i];
+        // thread t adds entries t, t + 256, ... in that order; several loads
+        // are issued together
         for (int i0 = threadIdx.x; i0 < nb_tv; i0 += 256 * 4) {
-            double t[4][5];
+            double t[4][kP];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + 256 * u;
 #pragma unroll
-                for (int j = 0; j < 5; ++j) t[u][j] = i < nb_tv ? pt[(size_t)i * 5 + j] : 0.0;
+                for (int j = 0; j < kP; ++j) t[u][j] = i < nb_tv ? pt[(size_t)i * kP + j] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int j = 0; j < 5; ++j) v[j] += t[u][j];
+                for (int j = 0; j < kP; ++j) v[j] += t[u][j];
         }
         for (int i0 = threadIdx.x; i0 < nb_fwd; i0 += 256 * 8) {
             double t[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) t[u] = i0 + 256 * u < nb_fwd ? pf[i0 + 256 * u] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[5] += t[u];
+            for (int u = 0; u < 8; ++u) v[kFwd] += t[u];
         }
     }
-    block_sum<8>(v, tot);
+    block_sum<kNV>(v, tot);
     if (stop_now && threadIdx.x == 0) {
         s.stopped = 1;
         s.stop_next = 0;
     }
     if (run && threadIdx.x == 0) {
-        if (fresh_rr) s.rr = tot[6];
-        const double tvf = tot[0], gg = tot[1], gradg = tot[2], ff = tot[4], pp = tot[5];
+        if (fresh_rr) s.rr = tot[kRR];
+        const double tvf = tot[0], gg = tot[1], gradg = tot[2], ff = tot[4], pp = tot[kFwd];
+        const double gh_old = tot[5], gh = tot[6];
         const double den = mu * pp + rho * gradg;
         double c = den > 0.0 ? gg / den : (s.has_prev ? s.c_prev : 0.0);
-        double alpha = s.has_prev ? s.c_prev : c;
+        // BB1 <s,s>/<s,y> of the last step s = -alpha G_prev, with y the change
+        // of the f-gradient at fixed z and lambda, (h - h_prev) + rho grad^T
+        // grad s: <s,s> = alpha^2 |G_prev|^2 and <s,y> = alpha (<G_prev, h_prev>
+        // - <G_prev, h> + alpha rho |grad G_prev|^2), from this iteration's h;
+        // a non-positive <s,y> keeps alpha.  The first step is the exact line
+        // search along -G (c).
+        double bb1 = s.alpha;
+        if (s.has_prev) {
+            const double sy = (s.gh_prev - gh_old) + s.alpha * rho * s.gradg_prev;
+            if (sy > 0.0) bb1 = s.alpha * s.gg_prev / sy;
+        }
+        double alpha = s.has_prev ? bb1 : c;
         // BB2 <s,y>/<y,y> of s = -alpha G_prev: den_prev / |mu A^T A G + rho
         // grad^T grad G|^2 (step_rule 1), or the adaptive choice (2): BB2
         // where it is below half the BB1 step; a non-positive <s,y> keeps alpha
         if (want_yy) {
             if (s.den_prev > 0.0) {
-                const double bb1 = s.c_prev, yy = tot[7];
+                const double yy = tot[kYY];
                 const double bb2 = yy > 0.0 ? s.den_prev / yy : bb1;
                 alpha = step_rule == 1 ? bb2 : (bb2 / bb1 < 0.5 ? bb2 : bb1);
             } else {
@@ -379,6 +409,9 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
             }
         }
         s.den_prev = den;
+        s.gg_prev = gg;
+        s.gh_prev = gh;
+        s.gradg_prev = gradg;
         // projected steps: BB1 <s,s>/<s,y> of the last step (kept when <s,y> <= 0)
         if (nonneg && s.has_prev) alpha = s.sy > 0.0 ? s.ss / s.sy : s.alpha;
         const double J = tvf + 0.5 * mu * s.rr;

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void kb_tv(const SliceDev *__restrict__ S,
         if (!d.P.sc[e].stopped && !d.P.sc[e].stop_next) {
             const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
             const size_t blk = (size_t)e * gx * gy + (size_t)w.z * gx + w.w;
-            tv_tile(w.z * kTY, w.w * kTX, img_of(d, e, par), d.P.p_tv + blk * 5,
+            tv_tile(w.z * kTY, w.w * kTX, img_of(d, e, par), d.P.p_tv + blk * kTvParts,
                     d.P.sc[e].pending != 0, d.nx, d.ny, d.rho, d.xi);
         }
         __syncthreads();
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void kb_scalar(const SliceDev *__restrict__ S,
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
         const int e = w.y;
-        scalar_energy(d.P.sc[e], d.P.p_tv + (size_t)e * d.P.nb_tv * 5, d.P.nb_tv,
+        scalar_energy(d.P.sc[e], d.P.p_tv + (size_t)e * d.P.nb_tv * kTvParts, d.P.nb_tv,
                       d.P.p_fwd + (size_t)e * d.P.nb_fwd, d.P.nb_fwd, d.P.log, d.P.log_rows, e,
                       d.mu, d.rhod, false, true, d.P.p_rr + (size_t)e * d.P.nbs, d.P.nbs, d.tol);
     }
@@ -364,7 +364,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         bytes += align256(8 * z.N * 4) * 2;         // lam, z
         bytes += align256(2 * z.Pp * 4) * 2;        // gpad, gpadT
         bytes += align256(z.part * 4);
-        bytes += align256(2 * z.nb_tv * 5 * 8) + align256(2 * z.nb_fwd * 8) +
+        bytes += align256(2 * z.nb_tv * kTvParts * 8) + align256(2 * z.nb_fwd * 8) +
                  align256(2 * z.nbs * 8) + align256(2 * z.nbi * 8);
         bytes += align256(2 * sizeof(AdmScalars));
         b->off[i] = total;
@@ -395,7 +395,7 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         d.P.gpad = (float *)take(2 * z.Pp * 4);
         d.P.gpadT = (float *)take(2 * z.Pp * 4);
         d.P.adjpart = (float *)take(z.part * 4);
-        d.P.p_tv = (double *)take(2 * z.nb_tv * 5 * 8);
+        d.P.p_tv = (double *)take(2 * z.nb_tv * kTvParts * 8);
         d.P.p_fwd = (double *)take(2 * z.nb_fwd * 8);
         d.P.p_rr = (double *)take(2 * z.nbs * 8);
         d.P.p_tvo = (double *)take(2 * z.nbi * 8);

@@ -9,6 +9,7 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
                    dect_report *rep, hipStream_t s);
 dect_status adm_state_create(const dect_geometry *g, dect_adm_state **out);
 dect_status adm_state_destroy(dect_adm_state *S);
+dect_status adm_state_reset(dect_adm_state *S);
 void release_adm_states();
 dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
                           const dect_pls_params *P, const float *ew, float *u1, float *u2,
@@ -108,11 +109,19 @@ dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
 
 dect_status dect_pls_decompose3(int32_t nx, int32_t ny, int32_t nz, const float *d_x_high,
                                 const float *d_x_low, const dect_pls_params *params,
-                                float *d_u_water, float *d_u_bone, dect_report *rep, void *stream)
+                                const float *d_edge_w, float *d_u_water, float *d_u_bone,
+                                dect_report *rep, void *stream)
 {
     dect::set_error("");
-    return dect::pls_decompose3(nx, ny, nz, d_x_high, d_x_low, params, d_u_water, d_u_bone, rep,
-                                (hipStream_t)stream);
+    return dect::pls_decompose3(nx, ny, nz, d_x_high, d_x_low, params, d_edge_w, d_u_water,
+                                d_u_bone, rep, (hipStream_t)stream);
+}
+
+dect_status dect_pls_edge_weights3(int32_t nx, int32_t ny, int32_t nz, const float *d_x,
+                                   double tau, double eps, float *d_w, void *stream)
+{
+    dect::set_error("");
+    return dect::pls_edge_weights3(nx, ny, nz, d_x, tau, eps, d_w, (hipStream_t)stream);
 }
 
 dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const float *d_m_low,
@@ -133,6 +142,11 @@ dect_status dect_adm_state_create(const dect_geometry *geom, dect_adm_state **ou
 dect_status dect_adm_state_destroy(dect_adm_state *state)
 {
     return dect::adm_state_destroy(state);
+}
+
+dect_status dect_adm_state_reset(dect_adm_state *state)
+{
+    return dect::adm_state_reset(state);
 }
 
 dect_status dect_pls_decompose(int32_t nx, int32_t ny, const float *d_x_high,
@@ -167,6 +181,7 @@ dect_status dect_release_caches(void)
 {
     (void)hipDeviceSynchronize();
     dect::release_adm_states();
+    dect::release_pls3_work();
     dect::release_tables();
     return DECT_OK;
 }

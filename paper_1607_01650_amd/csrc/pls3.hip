@@ -10,6 +10,9 @@
 // reduces them in a fixed order.
 #include <algorithm>
 #include <cmath>
+#include <memory>
+#include <mutex>
+#include <vector>
 
 #include "volume.h"
 
@@ -284,16 +287,75 @@ __global__ __launch_bounds__(256) void kp3_scalar(PState *ps, const double *__re
     }
 }
 
+// Work buffers of the 3-D decomposition, one set per device, grown on
+// demand and kept between calls.
+struct Pls3Work {
+    DevBuf b1, b2, m2, w, res, dinv, p, q, z, part, bmax, thr, ps;
+};
+
+std::mutex g_pls3_mu;
+std::vector<std::pair<int, std::unique_ptr<Pls3Work>>> g_pls3;
+
+Pls3Work *pls3_work()
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (auto &p : g_pls3)
+        if (p.first == dev) return p.second.get();
+    g_pls3.emplace_back(dev, std::make_unique<Pls3Work>());
+    return g_pls3.back().second.get();
+}
+
+dect_status check_vol(int nx, int ny, int nz, const char *who)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0 || nx > 16384 || ny > 16384 || nz > 16384)
+        return fail(DECT_ERR_INVALID_ARG, std::string(who) + ": volume sizes must be in [1, 16384]");
+    return DECT_OK;
+}
+
+// The 3-D Prewitt map of x and the pair weights [3][N] into w.
+dect_status edges3_into(const Vol &v, const float *x, double tau, double eps, float *w,
+                        Pls3Work *W, hipStream_t s)
+{
+    const int nb = (int)std::min<size_t>(kMaxBlocks, (v.N + 255) / 256);
+    dect_status st;
+    if ((st = W->m2.ensure(v.N * 4)) || (st = W->bmax.ensure(kMaxBlocks * 4)) ||
+        (st = W->thr.ensure(4)))
+        return st;
+    hipLaunchKernelGGL(kp3_m2, dim3(nb), dim3(256), 0, s, v, x, (float *)W->m2.ptr,
+                       (float *)W->bmax.ptr);
+    const float tau2 = (float)(tau * tau);
+    hipLaunchKernelGGL(kp3_thr, dim3(1), dim3(256), 0, s, (const float *)W->bmax.ptr, nb, tau2,
+                       (float *)W->thr.ptr);
+    hipLaunchKernelGGL(kp3_w, dim3(nb), dim3(256), 0, s, v, (const float *)W->m2.ptr,
+                       (const float *)W->thr.ptr, (float)eps, w, w + v.N, w + 2 * v.N);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
 }  // namespace
 
+dect_status pls_edge_weights3(int nx, int ny, int nz, const float *x, double tau, double eps,
+                              float *w, hipStream_t s)
+{
+    if (!x || !w) return fail(DECT_ERR_INVALID_ARG, "dect_pls_edge_weights3: null argument");
+    dect_status st = check_vol(nx, ny, nz, "dect_pls_edge_weights3");
+    if (st) return st;
+    if (!(tau >= 0.0) || !std::isfinite(tau) || !std::isfinite(eps))
+        return fail(DECT_ERR_INVALID_ARG, "dect_pls_edge_weights3: bad tau/eps");
+    const Vol v{nx, ny, nz, (size_t)nx * ny * nz, (size_t)nx * ny};
+    std::lock_guard<std::mutex> lk(g_pls3_mu);
+    return edges3_into(v, x, tau, eps, w, pls3_work(), s);
+}
+
 dect_status pls_decompose3(int nx, int ny, int nz, const float *xh, const float *xl,
-                           const dect_pls_params *p, float *u1, float *u2, dect_report *rep,
-                           hipStream_t s)
+                           const dect_pls_params *p, const float *ew, float *u1, float *u2,
+                           dect_report *rep, hipStream_t s)
 {
     if (!xh || !xl || !p || !u1 || !u2)
         return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose3: null argument");
-    if (nx <= 0 || ny <= 0 || nz <= 0 || nx > 16384 || ny > 16384 || nz > 16384)
-        return fail(DECT_ERR_INVALID_ARG, "volume sizes must be in [1, 16384]");
+    dect_status st = check_vol(nx, ny, nz, "dect_pls_decompose3");
+    if (st) return st;
     if (p->mode != DECT_PLS_IMAGE)
         return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose3 solves the image-space system only");
     if (!(p->gamma >= 0.0) || !(p->edge_eps > 0.0) || !(p->edge_tau >= 0.0) || p->max_iter < 0 ||
@@ -304,38 +366,35 @@ dect_status pls_decompose3(int nx, int ny, int nz, const float *xh, const float 
         return fail(DECT_ERR_INVALID_ARG, "the material matrix of Eq. 12 is singular");
     const Vol v{nx, ny, nz, (size_t)nx * ny * nz, (size_t)nx * ny};
     const int nb = (int)std::min<size_t>(kMaxBlocks, (v.N + 255) / 256);
-    DevBuf bb1, bb2, bm2, bex, bey, bez, bres, bdinv, bp, bq, bz, bpart, bmax, bthr, bps;
-    dect_status st;
-    if ((st = bb1.ensure(v.N * 4)) || (st = bb2.ensure(v.N * 4)) || (st = bm2.ensure(v.N * 4)) ||
-        (st = bex.ensure(v.N * 4)) || (st = bey.ensure(v.N * 4)) || (st = bez.ensure(v.N * 4)) ||
-        (st = bres.ensure(v.N * 4)) || (st = bdinv.ensure(v.N * 4)) || (st = bp.ensure(v.N * 4)) ||
-        (st = bq.ensure(v.N * 4)) || (st = bz.ensure(v.N * 4)) ||
-        (st = bpart.ensure((size_t)R_COUNT * kMaxBlocks * 8)) ||
-        (st = bmax.ensure(kMaxBlocks * 4)) || (st = bthr.ensure(4)) ||
-        (st = bps.ensure(sizeof(PState))))
+    std::lock_guard<std::mutex> lk(g_pls3_mu);
+    Pls3Work *W = pls3_work();
+    if ((st = W->b1.ensure(v.N * 4)) || (st = W->b2.ensure(v.N * 4)) ||
+        (st = W->res.ensure(v.N * 4)) || (st = W->dinv.ensure(v.N * 4)) ||
+        (st = W->p.ensure(v.N * 4)) || (st = W->q.ensure(v.N * 4)) || (st = W->z.ensure(v.N * 4)) ||
+        (st = W->part.ensure((size_t)R_COUNT * kMaxBlocks * 8)) ||
+        (st = W->ps.ensure(sizeof(PState))))
         return st;
-    float *b[2] = {(float *)bb1.ptr, (float *)bb2.ptr};
+    float *b[2] = {(float *)W->b1.ptr, (float *)W->b2.ptr};
     float *us[2] = {u1, u2};
-    const PW w{(const float *)bex.ptr, (const float *)bey.ptr, (const float *)bez.ptr};
-    double *part = (double *)bpart.ptr;
-    PState *ps = (PState *)bps.ptr;
+    double *part = (double *)W->part.ptr;
+    PState *ps = (PState *)W->ps.ptr;
     hipLaunchKernelGGL(kp3_dinv, dim3(nb), dim3(256), 0, s, v, xh, xl, p->eta_water_high,
                        p->eta_bone_high, p->eta_water_low, p->eta_bone_low, b[0], b[1]);
-    hipLaunchKernelGGL(kp3_m2, dim3(nb), dim3(256), 0, s, v, xl, (float *)bm2.ptr,
-                       (float *)bmax.ptr);
-    const float tau2 = (float)(p->edge_tau * p->edge_tau);
-    hipLaunchKernelGGL(kp3_thr, dim3(1), dim3(256), 0, s, (const float *)bmax.ptr, nb, tau2,
-                       (float *)bthr.ptr);
-    hipLaunchKernelGGL(kp3_w, dim3(nb), dim3(256), 0, s, v, (const float *)bm2.ptr,
-                       (const float *)bthr.ptr, (float)p->edge_eps, (float *)bex.ptr,
-                       (float *)bey.ptr, (float *)bez.ptr);
     DECT_HIP(hipGetLastError());
+    const float *wp = ew;
+    if (!wp) {
+        if ((st = W->w.ensure(3 * v.N * 4))) return st;
+        if ((st = edges3_into(v, xl, p->edge_tau, p->edge_eps, (float *)W->w.ptr, W, s)))
+            return st;
+        wp = (const float *)W->w.ptr;
+    }
+    const PW w{wp, wp + v.N, wp + 2 * v.N};
     const float gamma = (float)p->gamma;
     int iters[2] = {0, 0};
     double relres[2] = {0.0, 0.0};
     for (int m = 0; m < 2; ++m) {
-        float *res = (float *)bres.ptr, *dinv = (float *)bdinv.ptr, *pp = (float *)bp.ptr,
-              *q = (float *)bq.ptr, *zv = (float *)bz.ptr;
+        float *res = (float *)W->res.ptr, *dinv = (float *)W->dinv.ptr, *pp = (float *)W->p.ptr,
+              *q = (float *)W->q.ptr, *zv = (float *)W->z.ptr;
         hipLaunchKernelGGL(kp3_setup, dim3(nb), dim3(256), 0, s, v, w, gamma, b[m], us[m], res,
                            dinv, pp, part);
         hipLaunchKernelGGL(kp3_scalar, dim3(1), dim3(256), 0, s, ps, part, nb, 0, p->tol,
@@ -371,6 +430,12 @@ dect_status pls_decompose3(int nx, int ny, int nz, const float *xh, const float 
         rep->status = DECT_OK;
     }
     return DECT_OK;
+}
+
+void release_pls3_work()
+{
+    std::lock_guard<std::mutex> lk(g_pls3_mu);
+    g_pls3.clear();
 }
 
 }  // namespace dect

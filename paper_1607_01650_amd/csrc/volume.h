@@ -16,7 +16,10 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
                     const dect_adm_params *p, float *x_high, float *x_low, dect_report *rep,
                     hipStream_t s);
 dect_status pls_decompose3(int nx, int ny, int nz, const float *xh, const float *xl,
-                           const dect_pls_params *p, float *u1, float *u2, dect_report *rep,
-                           hipStream_t s);
+                           const dect_pls_params *p, const float *ew, float *u1, float *u2,
+                           dect_report *rep, hipStream_t s);
+dect_status pls_edge_weights3(int nx, int ny, int nz, const float *x, double tau, double eps,
+                              float *w, hipStream_t s);
+void release_pls3_work();
 
 }  // namespace dect

@@ -87,7 +87,9 @@ SIGNATURES = {
                                          ct.c_void_p]),
     "dect_pls_decompose3": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
                                        ct.c_void_p, _P(dect_pls_params), ct.c_void_p,
-                                       ct.c_void_p, _P(dect_report), ct.c_void_p]),
+                                       ct.c_void_p, ct.c_void_p, _P(dect_report), ct.c_void_p]),
+    "dect_pls_edge_weights3": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                          ct.c_double, ct.c_double, ct.c_void_p, ct.c_void_p]),
     "dect_adm_tv3": (ct.c_int, [_P(dect_cone_geometry), ct.c_void_p, ct.c_void_p,
                                 _P(dect_adm_params), ct.c_void_p, ct.c_void_p, _P(dect_report),
                                 ct.c_void_p]),
@@ -96,6 +98,7 @@ SIGNATURES = {
                                ct.c_void_p]),
     "dect_adm_state_create": (ct.c_int, [_P(dect_geometry), _P(ct.c_void_p)]),
     "dect_adm_state_destroy": (ct.c_int, [ct.c_void_p]),
+    "dect_adm_state_reset": (ct.c_int, [ct.c_void_p]),
     "dect_pls_decompose": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                       _P(dect_pls_params), ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       _P(dect_report), ct.c_void_p]),
@@ -314,6 +317,10 @@ class AdmState:
                "dect_adm_state_create")
         self.handle = h
 
+    def reset(self):
+        """Empty the state: the next adm_tv call on it starts a new run."""
+        _check(lib().dect_adm_state_reset(self.handle), "dect_adm_state_reset")
+
     def close(self):
         if self.handle is not None and self.handle.value:
             lib().dect_adm_state_destroy(self.handle)
@@ -422,9 +429,10 @@ def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool 
     return AdmResult(xh, xl, rep if want_log else None, log)
 
 
-def pls_decompose3(x_high, x_low, p: C.PlsParams, out: Optional[Tuple] = None):
+def pls_decompose3(x_high, x_low, p: C.PlsParams, out: Optional[Tuple] = None, edge_w=None):
     """PLS decomposition of volumes [nz, ny, nx] (dect_pls_decompose3, image-space
-    system, six-neighbour R): returns (u_water, u_bone, report)."""
+    system, six-neighbour R): returns (u_water, u_bone, report).  edge_w: None
+    (edges detected on x_low) or a [3, nz, ny, nx] pair-weight map."""
     torch = _torch()
     if x_high.dim() != 3:
         raise ValueError("x_high must be [nz, ny, nx]")
@@ -437,15 +445,34 @@ def pls_decompose3(x_high, x_low, p: C.PlsParams, out: Optional[Tuple] = None):
         u1, u2 = out
     _dev(u1, "u_water", (nz, ny, nx))
     _dev(u2, "u_bone", (nz, ny, nx))
+    wp = None
+    if edge_w is not None:
+        _out(edge_w, "edge_w", (3, nz, ny, nx))
+        wp = ct.c_void_p(edge_w.data_ptr())
     prm = dect_pls_params(p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low,
                           p.gamma, p.edge_eps, p.edge_tau, p.max_iter, p.tol,
                           int(getattr(p, "mode", 0)))
     rep = dect_report()
     _check(lib().dect_pls_decompose3(nx, ny, nz, ct.c_void_p(x_high.data_ptr()),
-                                     ct.c_void_p(x_low.data_ptr()), ct.byref(prm),
+                                     ct.c_void_p(x_low.data_ptr()), ct.byref(prm), wp,
                                      ct.c_void_p(u1.data_ptr()), ct.c_void_p(u2.data_ptr()),
                                      ct.byref(rep), _stream()), "dect_pls_decompose3")
     return u1, u2, rep
+
+
+def pls_edge_weights3(x, tau: float, eps: float):
+    """Pair weights [3, nz, ny, nx] (x, y, z pairs) from the 3-D Prewitt map of
+    a volume x [nz, ny, nx] (dect_pls_edge_weights3)."""
+    torch = _torch()
+    if x.dim() != 3:
+        raise ValueError("x must be [nz, ny, nx]")
+    nz, ny, nx = (int(v) for v in x.shape)
+    _dev(x, "x", (nz, ny, nx))
+    w = torch.empty((3, nz, ny, nx), device=x.device, dtype=torch.float32)
+    _check(lib().dect_pls_edge_weights3(nx, ny, nz, ct.c_void_p(x.data_ptr()), float(tau),
+                                        float(eps), ct.c_void_p(w.data_ptr()), _stream()),
+           "dect_pls_edge_weights3")
+    return w
 
 
 class AdmBatch:

@@ -8,9 +8,12 @@ projector and given 0.5 % Gaussian noise; plain ADM-TV provides the input
 Evaluation (time to tolerance): J_ref = J(plain f^200) per phantom, the
 objective of Eq. 4 summed over both energies.  Plain time = time of the first
 k iterations with J(f^k) <= J_ref.  Learned time = 5 iterations + U-Net
-inference + ADM-TV started from the network output until J <= J_ref.  Plain
-ADM stays the judge of the network's error: the continuation runs the
-unchanged method.
+inference + the start check + ADM-TV continued until J <= J_ref.  Plain ADM
+stays the judge of the network's error and its fallback: the continuation
+runs the unchanged method, from the network output when that is finite and
+its objective J(x_net) does not exceed J(f^5), and otherwise by resuming the
+plain run at f^5 (its multipliers and step kept), so that a failed network
+costs only its own time.
 
 Command line (one GPU):
     python -m paper_1607_01650_amd.warmstart --n-train 2000 --n-eval 200 \\
@@ -24,7 +27,7 @@ import dataclasses
 import json
 import math
 import time
-from typing import Dict, Optional, Tuple
+from typing import Callable, Dict, Optional, Tuple
 
 import numpy as np
 import torch
@@ -83,16 +86,46 @@ class Solver:
         self.p = params or C.default_adm_params(geom, LATE)
         self.m = torch.empty((2, geom.n_views, geom.n_bins), device="cuda")
         self.x = torch.empty((2, geom.ny, geom.nx), device="cuda")
+        # resumable runs: the plain one (kept at f^5 as the fallback) and the
+        # one started from the network output
+        self.st_plain = dect.AdmState(geom)
+        self.st_net = dect.AdmState(geom)
 
     def load(self, sino: torch.Tensor):
         self.m.copy_(sino)
 
-    def run(self, iters: int, x0=None, log: bool = False) -> dect.AdmResult:
-        """`iters` iterations from zero (or from x0 = (x_high, x_low)); the
-        result's images are views of this solver's output buffer."""
+    def run(self, iters: int, x0=None, log: bool = False,
+            state: Optional[dect.AdmState] = None) -> dect.AdmResult:
+        """`iters` iterations from zero (or from x0 = (x_high, x_low)), or
+        continued on `state`; the result's images are views of this solver's
+        output buffer."""
         p = dataclasses.replace(self.p, max_iter=iters)
         return dect.adm_tv(self.m[0], self.m[1], self.geom, p, x0=x0, want_log=log,
-                           out=(self.x[0], self.x[1]))
+                           out=(self.x[0], self.x[1]), state=state)
+
+
+def warm_start(net: NN.UNet, sol: Solver, corrupt: Optional[Callable] = None):
+    """Five plain iterations, the network, and the choice of the start.
+
+    Returns (state, kind): the ADM state to continue and why it was chosen:
+    "net" when the network output is finite and J(x_net) <= J(f^5), else
+    "nonfinite" or "objective", and then the state is the plain run itself,
+    resumed at f^5.  `corrupt(y_high, y_low)`, when given, edits the network
+    output in place before the check (a test hook)."""
+    st5 = sol.st_plain
+    st5.reset()
+    J5 = sol.run(EARLY, log=True, state=st5).report.objective
+    yh, yl = NN.predict(net, sol.x[0][None], sol.x[1][None])
+    if corrupt is not None:
+        corrupt(yh, yl)
+    if not bool(torch.isfinite(yh).all() & torch.isfinite(yl).all()):
+        return st5, "nonfinite"
+    stn = sol.st_net
+    stn.reset()
+    Jn = sol.run(0, x0=(yh[0], yl[0]), log=True, state=stn).report.objective
+    if not (math.isfinite(Jn) and Jn <= J5):
+        return st5, "objective"
+    return stn, "net"
 
 
 def make_pairs(geom: C.Geometry, seeds, log_every: int = 0):
@@ -173,8 +206,9 @@ def _timed(fn, reps: int = 3) -> float:
 
 
 def evaluate_case(net: NN.UNet, sol: Solver, sino: torch.Tensor, max_cont: int = 400,
-                  reps: int = 3) -> Dict:
-    """Time to J_ref = J(plain f^200) for one case, plain vs learned."""
+                  reps: int = 3, corrupt: Optional[Callable] = None) -> Dict:
+    """Time to J_ref = J(plain f^200) for one case, plain vs learned (with
+    the fallback of warm_start)."""
     sol.load(sino)
     Jp = sol.run(LATE, log=True).J.sum(axis=1)
     J_ref = float(Jp[LATE])
@@ -194,12 +228,11 @@ def evaluate_case(net: NN.UNet, sol: Solver, sino: torch.Tensor, max_cont: int =
     Jf = sol.run(max_cont, x0=(xf[0].clone(), xf[1].clone()), log=True).J.sum(axis=1)
     k_fbp = first_reach(Jf, J_ref)
 
-    yh, yl = learned_start()
-    x0 = (yh[0].clone(), yl[0].clone())
-    Jc = sol.run(max_cont, x0=x0, log=True).J.sum(axis=1)
+    st, kind = warm_start(net, sol, corrupt)
+    Jc = sol.run(max_cont, log=True, state=st).J.sum(axis=1)
     k_cont = first_reach(Jc, J_ref)
-    row = dict(J_ref=J_ref, k_plain=k_plain, k_cont=k_cont, J_net=float(Jc[0]), k_fbp=k_fbp,
-               J_fbp=float(Jf[0]))
+    row = dict(J_ref=J_ref, k_plain=k_plain, k_cont=k_cont, start=kind, J_start=float(Jc[0]),
+               k_fbp=k_fbp, J_fbp=float(Jf[0]))
     t_plain = _timed(lambda: sol.run(k_plain), reps)
     row["t_plain_ms"] = 1e3 * t_plain
     if k_fbp >= 0:
@@ -215,8 +248,9 @@ def evaluate_case(net: NN.UNet, sol: Solver, sino: torch.Tensor, max_cont: int =
         return row
 
     def learned():
-        a, b = learned_start()
-        sol.run(k_cont, x0=(a[0], b[0]))
+        st2, kind2 = warm_start(net, sol, corrupt)
+        assert kind2 == kind
+        sol.run(k_cont, state=st2)
 
     t_learned = _timed(learned, reps)
     t_net = _timed(lambda: learned_start(), reps)
@@ -244,6 +278,9 @@ def evaluate(net: NN.UNet, geom: C.Geometry, seeds, max_cont: int = 400, reps: i
 
 def summarize(rows) -> Dict:
     ok = [r for r in rows if r["k_cont"] >= 0]
+    starts = {}
+    for r in rows:
+        starts[r.get("start", "net")] = starts.get(r.get("start", "net"), 0) + 1
     ratios = np.array([r["t_learned_ms"] / r["t_plain_ms"] for r in ok])
     it_l = np.array([EARLY + r["k_cont"] for r in ok])
     it_p = np.array([r["k_plain"] for r in ok])
@@ -261,6 +298,8 @@ def summarize(rows) -> Dict:
         "p10_p90_time_ratio": ([float(np.percentile(ratios, 10)), float(np.percentile(ratios, 90))]
                                if len(ratios) else None),
         "iters_saved_median": med(it_p - it_l),
+        "starts": starts,
+        "fallbacks": len(rows) - starts.get("net", 0),
         "rows": rows,
     }
 

@@ -28,3 +28,30 @@ def to_np(t):
 def f32(a):
     """The float32 values a GPU run sees, as float64 for the oracle."""
     return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def edge_weights_agree(w_gpu, em, rel: float = 1e-4):
+    """Compare the GPU's pair weights with the FP64 oracle's edge map `em`.
+
+    The edge map is a threshold decision on |Prewitt gradient|^2: the GPU
+    takes it in FP32, the oracle in FP64, so the two may decide differently
+    only at pixels whose m2 lies within a relative `rel` of the threshold.
+    Every pair weight that touches no such pixel must be equal (as float32).
+    w_gpu: [ndim][...] weights, axis k coupling neighbours along the k-th
+    last array axis.  Returns (pairs that differ, pixels near the threshold)."""
+    w_gpu = np.asarray(w_gpu)
+    near = em.near_threshold(rel)
+    ndim = near.ndim
+    differ = 0
+    for k, w_or in enumerate(em.weights):
+        ax = ndim - 1 - k
+        touch = near.copy()
+        sl_dst = [slice(None)] * ndim
+        sl_src = [slice(None)] * ndim
+        sl_dst[ax] = slice(0, near.shape[ax] - 1)
+        sl_src[ax] = slice(1, None)
+        touch[tuple(sl_dst)] |= near[tuple(sl_src)]
+        d = np.asarray(w_gpu[k], dtype=np.float32) != np.asarray(w_or, dtype=np.float32)
+        assert not np.any(d & ~touch), f"axis {k}: pair weights differ away from the threshold"
+        differ += int(d.sum())
+    return differ, int(near.sum())

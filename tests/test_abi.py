@@ -108,5 +108,9 @@ def test_volume_entry_points_validate_first(lib):
     att = dect.pls_params(C.PlsParams(mode=1))
     sing = dect.dect_pls_params(1.0, 2.0, 2.0, 4.0, 1.0, 0.1, 0.25, 10, 1e-6, 0)
     for nz, prm in ((4, att), (4, sing), (0, p)):
-        assert lib.dect_pls_decompose3(8, 8, nz, buf, buf, ct.byref(prm), buf, buf, None,
+        assert lib.dect_pls_decompose3(8, 8, nz, buf, buf, ct.byref(prm), None, buf, buf, None,
                                        None) == dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_pls_edge_weights3(8, 8, 0, buf, 0.25, 0.1, buf, None) == \
+        dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_pls_edge_weights3(8, 8, 4, buf, -1.0, 0.1, buf, None) == \
+        dect.DECT_ERR_INVALID_ARG

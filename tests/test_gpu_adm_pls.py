@@ -3,8 +3,8 @@
 ADM images after K iterations vs the FP64 oracle: rel-L2 <= 1e-4 at every
 size and view count; the logged objective within 1e-5 relative over the first
 iterations.  PLS on shared FP32 inputs and
-weights: rel-L2 <= 1e-5; the edge map is bit-exact (its threshold decision
-is taken in FP32 on both sides).
+weights: rel-L2 <= 1e-5; the GPU's edge map (an FP32 threshold decision)
+equals the FP64 oracle's away from pixels within 1e-4 of the threshold.
 """
 import dataclasses
 
@@ -15,7 +15,7 @@ from oracle import oracle as O
 from paper_1607_01650_amd import configs as C
 from paper_1607_01650_amd import phantom as P
 
-from helpers import f32, need_gpu, rel_l2, to_dev, to_np
+from helpers import edge_weights_agree, f32, need_gpu, rel_l2, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -111,13 +111,17 @@ def test_adm_nonfinite(torch, tiny):
     assert ei.value.status == dect.DECT_ERR_NONFINITE
 
 
-def test_edge_weights_bitexact(torch, tiny):
+def test_edge_weights_vs_fp64(torch, tiny):
+    """The GPU's FP32 Prewitt decision equals the FP64 oracle's except at
+    pixels within 1e-4 of the threshold."""
     dect = _dect()
-    x = tiny.x_true[1] + 0.002 * np.random.default_rng(5).standard_normal(tiny.x_true[1].shape)
+    x = f32(tiny.x_true[1] + 0.002 * np.random.default_rng(5).standard_normal(tiny.x_true[1].shape))
     w = to_np(dect.pls_edge_weights(to_dev(torch, x), 0.25, 0.1))
-    er, ed, _ = O.edges_f32(x, 0.25, 0.1)
-    assert np.array_equal(w[0], er.astype(np.float64))
-    assert np.array_equal(w[1], ed.astype(np.float64))
+    em = O.edges(x, 0.25, 0.1)
+    differ, near = edge_weights_agree(w, em)
+    print(f"edge weights: {differ} pairs differ, {near} pixels near the threshold, "
+          f"{int(em.edge.sum())} edges", flush=True)
+    assert em.edge.sum() > 50
 
 
 @pytest.mark.parametrize("gamma", [1e-3, 1.0])
@@ -127,18 +131,20 @@ def test_pls_parity_shared_inputs(torch, tiny, gamma):
     xh = f32(tiny.x_true[0] + 0.0005 * rng.standard_normal(tiny.x_true[0].shape))
     xl = f32(tiny.x_true[1] + 0.0005 * rng.standard_normal(tiny.x_true[1].shape))
     p = dataclasses.replace(C.PlsParams(), gamma=gamma, tol=1e-7)
-    er, ed, _ = O.edges_f32(xl, p.edge_tau, p.edge_eps)
-    w = np.stack([er, ed])
+    w = np.stack(O.edges(xl, p.edge_tau, p.edge_eps).weights).astype(np.float32)
     u1, u2, rep = dect.pls_decompose(to_dev(torch, xh), to_dev(torch, xl), p,
                                      edge_w=to_dev(torch, w))
-    r1, r2, its, res = O.pls(xh, xl, p, edge_w=(er, ed), tol=1e-12)
+    r1, r2, its, res = O.pls(xh, xl, p, edge_w=(f32(w[0]), f32(w[1])), tol=1e-12)
     e1, e2 = rel_l2(to_np(u1), r1), rel_l2(to_np(u2), r2)
     print(f"PLS gamma={gamma}: rel-L2 water {e1:.3e} bone {e2:.3e}, GPU iters {rep.iters}, "
           f"oracle iters {its}", flush=True)
     assert e1 <= 1e-5 and e2 <= 1e-5
-    # the full path (edges detected on the GPU) gives the same map, hence the same result
+    # the full path detects edges on the GPU: the same result as the GPU's own
+    # map passed in, bit for bit
     v1, v2, _ = dect.pls_decompose(to_dev(torch, xh), to_dev(torch, xl), p)
-    assert np.array_equal(to_np(v1), to_np(u1)) and np.array_equal(to_np(v2), to_np(u2))
+    wg = dect.pls_edge_weights(to_dev(torch, xl), p.edge_tau, p.edge_eps)
+    g1, g2, _ = dect.pls_decompose(to_dev(torch, xh), to_dev(torch, xl), p, edge_w=wg)
+    assert np.array_equal(to_np(v1), to_np(g1)) and np.array_equal(to_np(v2), to_np(g2))
 
 
 def test_pls_gamma_zero_is_direct(torch, tiny):
@@ -205,17 +211,18 @@ def test_pls_parity_shared_inputs_512(torch, gamma):
     xh = f32(P.rasterize(els, g, 0) + 0.0005 * rng.standard_normal((g.ny, g.nx)))
     xl = f32(P.rasterize(els, g, 1) + 0.0005 * rng.standard_normal((g.ny, g.nx)))
     p = dataclasses.replace(C.PlsParams(), gamma=gamma, tol=1e-7)
-    er, ed, e = O.edges_f32(xl, p.edge_tau, p.edge_eps)
-    assert 1000 < int(np.count_nonzero(e)) < g.nx * g.ny // 4
-    w = np.stack([er, ed])
+    em = O.edges(xl, p.edge_tau, p.edge_eps)
+    assert 1000 < int(np.count_nonzero(em.edge)) < g.nx * g.ny // 4
+    w = np.stack(em.weights).astype(np.float32)
     u1, u2, rep = dect.pls_decompose(to_dev(torch, xh), to_dev(torch, xl), p,
                                      edge_w=to_dev(torch, w))
-    r1, r2, its, res = O.pls(xh, xl, p, edge_w=(er, ed), tol=1e-12)
+    r1, r2, its, res = O.pls(xh, xl, p, edge_w=(f32(w[0]), f32(w[1])), tol=1e-12)
     e1, e2 = rel_l2(to_np(u1), r1), rel_l2(to_np(u2), r2)
     print(f"PLS 512x512 gamma={gamma}: rel-L2 water {e1:.3e} bone {e2:.3e}, GPU iters "
           f"{rep.iters}, oracle iters {its}", flush=True)
     assert e1 <= 1e-5 and e2 <= 1e-5
-    # the GPU's own edge map at this size equals the oracle's
+    # the GPU's own edge map at this size: the oracle's decision away from the threshold
     wg = to_np(dect.pls_edge_weights(to_dev(torch, xl), p.edge_tau, p.edge_eps))
-    assert np.array_equal(wg[0], er.astype(np.float64))
-    assert np.array_equal(wg[1], ed.astype(np.float64))
+    differ, near = edge_weights_agree(wg, em)
+    print(f"PLS 512x512 edge map: {differ} pairs differ, {near} pixels near the threshold",
+          flush=True)

@@ -47,8 +47,8 @@ def test_parity_shared_inputs(torch, geom, gamma):
     dect = _dect()
     xh, xl = _inputs(geom, 3)
     p = dataclasses.replace(C.PlsParams(), gamma=gamma, tol=1e-11, mode=1, max_iter=2000)
-    er, ed, _ = O.edges_f32(xl, p.edge_tau, p.edge_eps)
-    w = np.stack([er, ed])
+    w = np.stack(O.edges(xl, p.edge_tau, p.edge_eps).weights).astype(np.float32)
+    er, ed = f32(w[0]), f32(w[1])
     u1, u2, rep = dect.pls_decompose(to_dev(torch, xh), to_dev(torch, xl), p,
                                      edge_w=to_dev(torch, w))
     r1, r2, its, res = O.pls(xh, xl, p, edge_w=(er, ed), tol=1e-13)

@@ -113,13 +113,15 @@ def test_prewitt_edges_of_a_step():
     """Pi16: a vertical step marks exactly the two columns beside it; the weights
     take eps on every pair that touches them and 1 elsewhere."""
     ny, nx, c0 = 9, 12, 5
-    x = np.zeros((ny, nx), dtype=np.float32)
+    x = np.zeros((ny, nx))
     x[:, c0:] = 1.0
-    er, ed, e = O.edges_f32(x, 0.25, 0.1)
+    em = O.edges(x, 0.25, 0.1)
+    er, ed = em.weights
+    e = em.edge
     expect = np.zeros((ny, nx), dtype=bool)
     expect[:, c0 - 1] = expect[:, c0] = True
     assert np.array_equal(e.astype(bool), expect)
-    eps = np.float32(0.1)
+    eps = 0.1
     for r in range(ny):
         for c in range(nx - 1):
             touch = expect[r, c] or expect[r, c + 1]
@@ -143,3 +145,19 @@ def test_pls_smooths_noise_inside_materials():
         u1, u2, _, _ = O.pls(xh, xl, C.PlsParams(gamma=gamma, edge_tau=2.0))
         sds.append(u2.std())
     assert sds[0] > sds[1] > sds[2]
+
+
+def test_prewitt_magnitude_is_scipys():
+    """The squared gradient magnitude that decides the edges is the Prewitt
+    operator of scipy.ndimage with replicated borders ('nearest'), and the
+    threshold is tau^2 times its maximum."""
+    from scipy import ndimage
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((13, 17))
+    em = O.edges(x, 0.3, 0.1)
+    gx = ndimage.prewitt(x, axis=1, mode="nearest")
+    gy = ndimage.prewitt(x, axis=0, mode="nearest")
+    m2 = gx * gx + gy * gy
+    assert np.abs(em.m2 - m2).max() <= 1e-12 * m2.max()
+    assert abs(em.thr - 0.09 * m2.max()) <= 1e-12 * m2.max()
+    assert np.array_equal(em.edge.astype(bool), em.m2 > em.thr)

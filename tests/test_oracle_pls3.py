@@ -16,25 +16,40 @@ from oracle import oracle as O
 
 
 def test_z_step_marks_two_slices():
-    x = np.zeros((9, 7, 8), dtype=np.float32)
+    x = np.zeros((9, 7, 8))
     x[4:] = 1.0
-    ex, ey, ez, e = O.edges3_f32(x, 0.25, 0.1)
+    em = O.edges3(x, 0.25, 0.1)
+    ex, ey, ez = em.weights
+    e = em.edge
     want = np.zeros_like(e)
     want[3:5] = 1
     assert np.array_equal(e, want)
-    assert np.all(ez[2:5] == np.float32(0.1)) and np.all(ez[5:8] == 1.0) and np.all(ez[8] == 0.0)
+    assert np.all(ez[2:5] == 0.1) and np.all(ez[5:8] == 1.0) and np.all(ez[8] == 0.0)
     assert np.all(ez[:2] == 1.0)
 
 
 def test_x_step_marks_two_columns():
-    x = np.zeros((5, 6, 10), dtype=np.float32)
+    x = np.zeros((5, 6, 10))
     x[:, :, 6:] = 2.0
-    _, _, _, e = O.edges3_f32(x, 0.25, 0.1)
+    e = O.edges3(x, 0.25, 0.1).edge
     want = np.zeros_like(e)
     want[:, :, 5:7] = 1
     assert np.array_equal(e, want)
-    _, _, _, e0 = O.edges3_f32(np.full((4, 5, 6), 3.0, dtype=np.float32), 0.25, 0.1)
+    e0 = O.edges3(np.full((4, 5, 6), 3.0), 0.25, 0.1).edge
     assert not e0.any()
+
+
+def test_prewitt3_magnitude_is_scipys():
+    """Each axis's derivative is scipy.ndimage's Prewitt operator along it
+    (the difference of the neighbouring faces, each face summed over the
+    other two axes), with replicated borders."""
+    from scipy import ndimage
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal((6, 7, 9))
+    em = O.edges3(x, 0.3, 0.1)
+    m2 = sum(ndimage.prewitt(x, axis=a, mode="nearest") ** 2 for a in range(3))
+    assert np.abs(em.m2 - m2).max() <= 1e-12 * m2.max()
+    assert np.array_equal(em.edge.astype(bool), em.m2 > em.thr)
 
 
 def _pairs(nx, ny, nz):
