@@ -232,6 +232,24 @@ dect_status dect_pls_decompose(int32_t nx, int32_t ny, const float *d_x_high,
                                dect_report *rep, void *stream);
 
 /*
+ * dect_pls_decompose for callers that cannot allocate device memory (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results (bit for bit) and errors, and no
+ * allocation of any kind.  Limits: mode DECT_PLS_IMAGE only and
+ * nx * ny <= 262144 pixels (512 x 512); DECT_ERR_INVALID_ARG otherwise.
+ * Its work memory is one library-owned array per GPU (about 17 MB, in the
+ * library's code object), held until the process ends.  All calls on one GPU
+ * share that array, so calls that overlap on one GPU (other streams or
+ * threads) race: the caller serialises them.  Every call writes the parts of
+ * the array it reads before reading them, so nothing needs clearing between
+ * calls.
+ */
+dect_status dect_pls_decompose_noalloc(int32_t nx, int32_t ny, const float *d_x_high,
+                                       const float *d_x_low, const dect_pls_params *params,
+                                       const float *d_edge_w, float *d_u_water, float *d_u_bone,
+                                       dect_report *rep, void *stream);
+
+/*
  * Edge weights e_ik of Eq. 14 from a Prewitt edge map of d_x (Sec. 2.3:
  * small at edges, one elsewhere): m2 = fmaf(gx, gx, gy*gy) with gx, gy the
  * Prewitt responses (replicated borders), edge where m2 > fp32(tau^2) *

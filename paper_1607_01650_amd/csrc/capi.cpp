@@ -16,6 +16,9 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
                           dect_report *rep, hipStream_t s);
 dect_status pls_edge_weights(int nx, int ny, const float *x, double tau, double eps, float *w,
                              hipStream_t s);
+dect_status pls_decompose_noalloc(int nx, int ny, const float *xh, const float *xl,
+                                  const dect_pls_params *P, const float *ew, float *u1,
+                                  float *u2, dect_report *rep, hipStream_t s);
 dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm, int n,
                          dect_batch **out);
 dect_status batch_destroy(dect_batch *b);
@@ -157,6 +160,16 @@ dect_status dect_pls_decompose(int32_t nx, int32_t ny, const float *d_x_high,
     dect::set_error("");
     return dect::pls_decompose(nx, ny, d_x_high, d_x_low, params, d_edge_w, d_u_water, d_u_bone,
                                rep, (hipStream_t)stream);
+}
+
+dect_status dect_pls_decompose_noalloc(int32_t nx, int32_t ny, const float *d_x_high,
+                                       const float *d_x_low, const dect_pls_params *params,
+                                       const float *d_edge_w, float *d_u_water, float *d_u_bone,
+                                       dect_report *rep, void *stream)
+{
+    dect::set_error("");
+    return dect::pls_decompose_noalloc(nx, ny, d_x_high, d_x_low, params, d_edge_w, d_u_water,
+                                       d_u_bone, rep, (hipStream_t)stream);
 }
 
 dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, double tau,

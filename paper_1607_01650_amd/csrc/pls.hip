@@ -10,6 +10,8 @@
 //            per launch.  Scalars are reduced redundantly by every block in
 //            a fixed order, so every block takes the same decision.
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "common.h"
 
@@ -546,6 +548,15 @@ struct PlsWork {
     DevBuf b, res, z, p0, p1, q, minv, w, m2, pmax, prz0, prz1, prr, pbb, ppq, stat, u64;
 };
 
+// Device buffers of one image-space decomposition of N pixels (nblk
+// reduction blocks): D^{-1} x (both materials), PCG vectors, the Jacobi
+// inverse, edge weights and the Prewitt map, per-block partial sums.
+struct PlsBufs {
+    float *b, *res, *z, *p0, *p1, *q, *minv, *w, *m2, *pmax;
+    double *prz0, *prz1, *prr, *pbb, *ppq;
+    PcgStatus *stat;
+};
+
 std::mutex g_pls_mu;
 std::vector<std::pair<int, std::unique_ptr<PlsWork>>> g_pls;
 
@@ -559,6 +570,20 @@ PlsWork *pls_work()
     return g_pls.back().second.get();
 }
 
+dect_status edges_run(int nx, int ny, const float *x, double tau, double eps, float *w,
+                      float *m2, float *pmax, hipStream_t s)
+{
+    const size_t N = (size_t)nx * ny;
+    const int nblk = (int)((N + 256 * kPix - 1) / (256 * kPix));
+    hipLaunchKernelGGL(k_prewitt, dim3(nblk), dim3(256), 0, s, x, m2, pmax, nx, ny);
+    DECT_HIP(hipGetLastError());
+    const float tau2 = (float)(tau * tau);
+    hipLaunchKernelGGL(k_weights, dim3(nblk), dim3(256), 0, s, (const float *)m2,
+                       (const float *)pmax, nblk, tau2, (float)eps, w, nx, ny);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
 dect_status edges_into(int nx, int ny, const float *x, double tau, double eps, float *w,
                        PlsWork *W, hipStream_t s)
 {
@@ -566,13 +591,95 @@ dect_status edges_into(int nx, int ny, const float *x, double tau, double eps, f
     const int nblk = (int)((N + 256 * kPix - 1) / (256 * kPix));
     dect_status st;
     if ((st = W->m2.ensure(N * 4)) || (st = W->pmax.ensure((size_t)nblk * 4))) return st;
-    hipLaunchKernelGGL(k_prewitt, dim3(nblk), dim3(256), 0, s, x, (float *)W->m2.ptr,
-                       (float *)W->pmax.ptr, nx, ny);
+    return edges_run(nx, ny, x, tau, eps, w, (float *)W->m2.ptr, (float *)W->pmax.ptr, s);
+}
+
+dect_status check_pls_args(int nx, int ny, const float *xh, const float *xl,
+                           const dect_pls_params *P, float *u1, float *u2, const char *who)
+{
+    if (nx <= 0 || ny <= 0 || !xh || !xl || !P || !u1 || !u2)
+        return fail(DECT_ERR_INVALID_ARG, std::string(who) + ": bad size or null argument");
+    const double det = P->eta_water_high * P->eta_bone_low - P->eta_bone_high * P->eta_water_low;
+    if (!std::isfinite(det) || det == 0.0)
+        return fail(DECT_ERR_INVALID_ARG, std::string(who) + ": singular decomposition matrix");
+    if (!(P->gamma >= 0.0) || !std::isfinite(P->gamma) || P->max_iter < 0 || !(P->tol >= 0.0))
+        return fail(DECT_ERR_INVALID_ARG, std::string(who) + ": bad gamma/max_iter/tol");
+    if (P->mode != DECT_PLS_IMAGE && P->mode != DECT_PLS_ATTENUATION)
+        return fail(DECT_ERR_INVALID_ARG, std::string(who) + ": unknown mode");
+    return DECT_OK;
+}
+
+// D^{-1} x into u1, u2 and B.b (both materials).
+void dinv_run(int nx, int ny, const float *xh, const float *xl, const dect_pls_params *P,
+              float *u1, float *u2, float *b, hipStream_t s)
+{
+    const size_t N = (size_t)nx * ny;
+    const double det = P->eta_water_high * P->eta_bone_low - P->eta_bone_high * P->eta_water_low;
+    PlsCoef c;
+    c.i11 = (float)(P->eta_bone_low / det);
+    c.i12 = (float)(-P->eta_bone_high / det);
+    c.i21 = (float)(-P->eta_water_low / det);
+    c.i22 = (float)(P->eta_water_high / det);
+    hipLaunchKernelGGL(k_dinv, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, xh, xl, c, u1,
+                       u2, b, N);
+}
+
+// Jacobi-PCG of the image-space system (I + gamma L) u_m = b_m for both
+// materials, from u = b (already in u1, u2), on the pair weights w.
+dect_status pcg_image_run(int nx, int ny, const dect_pls_params *P, const float *w, float *u1,
+                          float *u2, dect_report *rep, const PlsBufs &B, hipStream_t s)
+{
+    const size_t N = (size_t)nx * ny;
+    const int nblk = (int)((N + 256 * kPix - 1) / (256 * kPix));
+    const float gamma = (float)P->gamma;
+    PcgStatus *stat = B.stat;
+    float *pbuf[2] = {B.p0, B.p1};
+    double *rzb[2] = {B.prz0, B.prz1};
+    hipLaunchKernelGGL(k_pcg_setup, dim3(nblk, 2), dim3(256), 0, s, (const float *)B.b, w, gamma,
+                       B.res, B.z, pbuf[0], B.minv, rzb[0], B.prr, B.pbb, stat, nx, ny, nblk);
     DECT_HIP(hipGetLastError());
-    const float tau2 = (float)(tau * tau);
-    hipLaunchKernelGGL(k_weights, dim3(nblk), dim3(256), 0, s, (const float *)W->m2.ptr,
-                       (const float *)W->pmax.ptr, nblk, tau2, (float)eps, w, nx, ny);
+    int it = 0;
+    const int check_every = 16;
+    for (; it < P->max_iter; ++it) {
+        float *pold = pbuf[it & 1], *pnew = pbuf[(it + 1) & 1];
+        const double *rz_prev = rzb[(it + 1) & 1];
+        hipLaunchKernelGGL(k_pcg_a, dim3(nblk, 2), dim3(256), 0, s, (const float *)B.z,
+                           (const float *)pold, pnew, B.q, w, gamma, (const double *)rzb[it & 1],
+                           rz_prev, (const double *)B.prr, (const double *)B.pbb, B.ppq, stat, it,
+                           P->tol, nx, ny, nblk);
+        DECT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_pcg_b, dim3(nblk, 2), dim3(256), 0, s, u1, u2, B.res, B.z,
+                           (const float *)pnew, (const float *)B.q, (const float *)B.minv,
+                           (const double *)rzb[it & 1], (const double *)B.ppq, rzb[(it + 1) & 1],
+                           B.prr, stat, nx, ny, nblk);
+        DECT_HIP(hipGetLastError());
+        if ((it + 1) % check_every == 0) {
+            PcgStatus hs[2];
+            DECT_HIP(hipMemcpyAsync(hs, stat, sizeof(hs), hipMemcpyDeviceToHost, s));
+            DECT_HIP(hipStreamSynchronize(s));
+            if (hs[0].done && hs[1].done) {
+                ++it;
+                break;
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_pcg_final, dim3(2), dim3(256), 0, s, (const double *)B.prr,
+                       (const double *)B.pbb, stat, it, P->tol, nblk);
     DECT_HIP(hipGetLastError());
+    if (rep) {
+        PcgStatus hs[2];
+        DECT_HIP(hipMemcpyAsync(hs, stat, sizeof(hs), hipMemcpyDeviceToHost, s));
+        DECT_HIP(hipStreamSynchronize(s));
+        rep->iters = std::max(hs[0].iters, hs[1].iters);
+        rep->pcg_residual = std::max(hs[0].relres, hs[1].relres);
+        rep->objective = 0.0;
+        rep->rel_change = 0.0;
+        rep->status = (hs[0].done == 3 || hs[1].done == 3) ? DECT_WARN_MAXITER : DECT_OK;
+        if (rep->status == DECT_WARN_MAXITER) {
+            set_error("dect_pls_decompose: PCG reached max_iter above tolerance");
+            return DECT_WARN_MAXITER;
+        }
+    }
     return DECT_OK;
 }
 
@@ -673,20 +780,12 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
                           const dect_pls_params *P, const float *ew, float *u1, float *u2,
                           dect_report *rep, hipStream_t s)
 {
-    if (nx <= 0 || ny <= 0 || !xh || !xl || !P || !u1 || !u2)
-        return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose: bad size or null argument");
-    const double det = P->eta_water_high * P->eta_bone_low - P->eta_bone_high * P->eta_water_low;
-    if (!std::isfinite(det) || det == 0.0)
-        return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose: singular decomposition matrix");
-    if (!(P->gamma >= 0.0) || !std::isfinite(P->gamma) || P->max_iter < 0 || !(P->tol >= 0.0))
-        return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose: bad gamma/max_iter/tol");
-    if (P->mode != DECT_PLS_IMAGE && P->mode != DECT_PLS_ATTENUATION)
-        return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose: unknown mode");
+    dect_status st = check_pls_args(nx, ny, xh, xl, P, u1, u2, "dect_pls_decompose");
+    if (st) return st;
     std::lock_guard<std::mutex> lk(g_pls_mu);
     PlsWork *W = pls_work();
     const size_t N = (size_t)nx * ny;
     const int nblk = (int)((N + 256 * kPix - 1) / (256 * kPix));
-    dect_status st;
     if ((st = W->b.ensure(2 * N * 4)) || (st = W->res.ensure(2 * N * 4)) ||
         (st = W->z.ensure(2 * N * 4)) || (st = W->p0.ensure(2 * N * 4)) ||
         (st = W->p1.ensure(2 * N * 4)) || (st = W->q.ensure(2 * N * 4)) ||
@@ -695,13 +794,7 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
         (st = W->pbb.ensure((size_t)2 * nblk * 8)) || (st = W->ppq.ensure((size_t)2 * nblk * 8)) ||
         (st = W->stat.ensure(2 * sizeof(PcgStatus))))
         return st;
-    PlsCoef c;
-    c.i11 = (float)(P->eta_bone_low / det);
-    c.i12 = (float)(-P->eta_bone_high / det);
-    c.i21 = (float)(-P->eta_water_low / det);
-    c.i22 = (float)(P->eta_water_high / det);
-    hipLaunchKernelGGL(k_dinv, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, xh, xl, c, u1,
-                       u2, (float *)W->b.ptr, N);
+    dinv_run(nx, ny, xh, xl, P, u1, u2, (float *)W->b.ptr, s);
     DECT_HIP(hipGetLastError());
     const float *w = ew;
     if (!w) {
@@ -710,62 +803,124 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
             return st;
         w = (const float *)W->w.ptr;
     }
-    PcgStatus *stat = (PcgStatus *)W->stat.ptr;
     if (P->mode == DECT_PLS_ATTENUATION)
         return pls_attenuation(nx, ny, xh, xl, P, w, u1, u2, rep, W, nblk, s);
-    const float gamma = (float)P->gamma;
-    float *pbuf[2] = {(float *)W->p0.ptr, (float *)W->p1.ptr};
-    double *rzb[2] = {(double *)W->prz0.ptr, (double *)W->prz1.ptr};
-    hipLaunchKernelGGL(k_pcg_setup, dim3(nblk, 2), dim3(256), 0, s, (const float *)W->b.ptr, w,
-                       gamma, (float *)W->res.ptr, (float *)W->z.ptr, pbuf[0],
-                       (float *)W->minv.ptr, rzb[0], (double *)W->prr.ptr,
-                       (double *)W->pbb.ptr, stat, nx, ny, nblk);
-    DECT_HIP(hipGetLastError());
-    int it = 0;
-    const int check_every = 16;
-    for (; it < P->max_iter; ++it) {
-        float *pold = pbuf[it & 1], *pnew = pbuf[(it + 1) & 1];
-        const double *rz_prev = rzb[(it + 1) & 1];
-        hipLaunchKernelGGL(k_pcg_a, dim3(nblk, 2), dim3(256), 0, s, (const float *)W->z.ptr,
-                           (const float *)pold, pnew, (float *)W->q.ptr, w, gamma,
-                           (const double *)rzb[it & 1], rz_prev, (const double *)W->prr.ptr,
-                           (const double *)W->pbb.ptr, (double *)W->ppq.ptr, stat, it, P->tol,
-                           nx, ny, nblk);
-        DECT_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_pcg_b, dim3(nblk, 2), dim3(256), 0, s, u1, u2, (float *)W->res.ptr,
-                           (float *)W->z.ptr, (const float *)pnew, (const float *)W->q.ptr,
-                           (const float *)W->minv.ptr, (const double *)rzb[it & 1],
-                           (const double *)W->ppq.ptr, rzb[(it + 1) & 1], (double *)W->prr.ptr,
-                           stat, nx, ny, nblk);
-        DECT_HIP(hipGetLastError());
-        if ((it + 1) % check_every == 0) {
-            PcgStatus hs[2];
-            DECT_HIP(hipMemcpyAsync(hs, stat, sizeof(hs), hipMemcpyDeviceToHost, s));
-            DECT_HIP(hipStreamSynchronize(s));
-            if (hs[0].done && hs[1].done) {
-                ++it;
-                break;
-            }
-        }
+    PlsBufs B;
+    B.b = (float *)W->b.ptr;
+    B.res = (float *)W->res.ptr;
+    B.z = (float *)W->z.ptr;
+    B.p0 = (float *)W->p0.ptr;
+    B.p1 = (float *)W->p1.ptr;
+    B.q = (float *)W->q.ptr;
+    B.minv = (float *)W->minv.ptr;
+    B.w = nullptr;
+    B.m2 = nullptr;
+    B.pmax = nullptr;
+    B.prz0 = (double *)W->prz0.ptr;
+    B.prz1 = (double *)W->prz1.ptr;
+    B.prr = (double *)W->prr.ptr;
+    B.pbb = (double *)W->pbb.ptr;
+    B.ppq = (double *)W->ppq.ptr;
+    B.stat = (PcgStatus *)W->stat.ptr;
+    return pcg_image_run(nx, ny, P, w, u1, u2, rep, B, s);
+}
+
+// ------------------------------------------------ allocation-free form ---
+// The work memory of dect_pls_decompose_noalloc: one array per GPU, in the
+// code object, sized for kNoAllocMaxPixels pixels.  Host code never passes
+// its name to a kernel (on the host the name is not the device address):
+// hipGetSymbolAddress gives each device's address once, kept in g_scratch.
+constexpr size_t kNoAllocMaxPixels = (size_t)512 * 512;
+constexpr size_t kNoAllocBlocks = (kNoAllocMaxPixels + 256 * kPix - 1) / (256 * kPix);
+constexpr size_t kScratchBytes =
+    16 * 4 * kNoAllocMaxPixels + 10 * 8 * kNoAllocBlocks + 4 * kNoAllocBlocks + (size_t)64 * 1024;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch;  // per device id: the array's device address
+
+dect_status scratch_ptr(void **out)
+{
+    int dev = 0;
+    DECT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DECT_ERR_HIP, std::string("dect_pls_decompose_noalloc: scratch address: ") +
+                                          hipGetErrorString(e));
+        g_scratch[dev] = p;
     }
-    hipLaunchKernelGGL(k_pcg_final, dim3(2), dim3(256), 0, s, (const double *)W->prr.ptr,
-                       (const double *)W->pbb.ptr, stat, it, P->tol, nblk);
-    DECT_HIP(hipGetLastError());
-    if (rep) {
-        PcgStatus hs[2];
-        DECT_HIP(hipMemcpyAsync(hs, stat, sizeof(hs), hipMemcpyDeviceToHost, s));
-        DECT_HIP(hipStreamSynchronize(s));
-        rep->iters = std::max(hs[0].iters, hs[1].iters);
-        rep->pcg_residual = std::max(hs[0].relres, hs[1].relres);
-        rep->objective = 0.0;
-        rep->rel_change = 0.0;
-        rep->status = (hs[0].done == 3 || hs[1].done == 3) ? DECT_WARN_MAXITER : DECT_OK;
-        if (rep->status == DECT_WARN_MAXITER) {
-            set_error("dect_pls_decompose: PCG reached max_iter above tolerance");
-            return DECT_WARN_MAXITER;
-        }
-    }
+    *out = g_scratch[dev];
     return DECT_OK;
+}
+
+// Consecutive 256-byte-aligned pieces of one buffer.
+struct Carve {
+    unsigned char *base;
+    size_t off;
+    template <class T>
+    T *take(size_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = (T *)(base + off);
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+dect_status pls_decompose_noalloc(int nx, int ny, const float *xh, const float *xl,
+                                  const dect_pls_params *P, const float *ew, float *u1,
+                                  float *u2, dect_report *rep, hipStream_t s)
+{
+    dect_status st = check_pls_args(nx, ny, xh, xl, P, u1, u2, "dect_pls_decompose_noalloc");
+    if (st) return st;
+    if (P->mode != DECT_PLS_IMAGE)
+        return fail(DECT_ERR_INVALID_ARG,
+                    "dect_pls_decompose_noalloc: image-space mode (DECT_PLS_IMAGE) only");
+    const size_t N = (size_t)nx * ny;
+    if (N > kNoAllocMaxPixels)
+        return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose_noalloc: at most " +
+                                              std::to_string(kNoAllocMaxPixels) +
+                                              " pixels, got " + std::to_string(N));
+    void *sp = nullptr;
+    if ((st = scratch_ptr(&sp))) return st;
+    const size_t nblk = (N + 256 * kPix - 1) / (256 * kPix);
+    Carve c{(unsigned char *)sp, 0};
+    PlsBufs B;
+    B.b = c.take<float>(2 * N);
+    B.res = c.take<float>(2 * N);
+    B.z = c.take<float>(2 * N);
+    B.p0 = c.take<float>(2 * N);
+    B.p1 = c.take<float>(2 * N);
+    B.q = c.take<float>(2 * N);
+    B.minv = c.take<float>(N);
+    B.w = c.take<float>(2 * N);
+    B.m2 = c.take<float>(N);
+    B.pmax = c.take<float>(nblk);
+    B.prz0 = c.take<double>(2 * nblk);
+    B.prz1 = c.take<double>(2 * nblk);
+    B.prr = c.take<double>(2 * nblk);
+    B.pbb = c.take<double>(2 * nblk);
+    B.ppq = c.take<double>(2 * nblk);
+    B.stat = c.take<PcgStatus>(2);
+    if (c.off > kScratchBytes)
+        return fail(DECT_ERR_INVALID_ARG, "dect_pls_decompose_noalloc: scratch too small");
+    dinv_run(nx, ny, xh, xl, P, u1, u2, B.b, s);
+    DECT_HIP(hipGetLastError());
+    const float *w = ew;
+    if (!w) {
+        if ((st = edges_run(nx, ny, xl, P->edge_tau, P->edge_eps, B.w, B.m2, B.pmax, s)))
+            return st;
+        w = B.w;
+    }
+    return pcg_image_run(nx, ny, P, w, u1, u2, rep, B, s);
 }
 
 }  // namespace dect

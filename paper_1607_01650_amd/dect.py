@@ -102,6 +102,9 @@ SIGNATURES = {
     "dect_pls_decompose": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                       _P(dect_pls_params), ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       _P(dect_report), ct.c_void_p]),
+    "dect_pls_decompose_noalloc": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                      _P(dect_pls_params), ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                      _P(dect_report), ct.c_void_p]),
     "dect_pls_edge_weights": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_double,
                                          ct.c_double, ct.c_void_p, ct.c_void_p]),
     "dect_batch_create": (ct.c_int, [_P(dect_geometry), _P(dect_adm_params), ct.c_int32,
@@ -565,6 +568,31 @@ def pls_decompose(x_high, x_low, p: C.PlsParams, edge_w=None, report: bool = Tru
                                   ct.byref(rep) if report else None, _stream())
     if st not in (DECT_OK, DECT_WARN_MAXITER):
         _check(st, "dect_pls_decompose")
+    return u1, u2, (rep if report else None)
+
+
+def pls_decompose_noalloc(x_high, x_low, p: C.PlsParams, out: Tuple, edge_w=None,
+                          report: bool = True):
+    """dect_pls_decompose_noalloc: the decomposition into the caller's
+    out = (u_water, u_bone) [ny, nx], with no device allocation by the library
+    (image-space mode, at most 512 x 512 pixels) -> (u_water, u_bone, report)."""
+    ny, nx = x_high.shape[-2:]
+    _dev(x_high, "x_high", (ny, nx))
+    _dev(x_low, "x_low", (ny, nx))
+    u1, u2 = out
+    _out(u1, "u_water", (ny, nx))
+    _out(u2, "u_bone", (ny, nx))
+    if edge_w is not None:
+        _out(edge_w, "edge_w", (2, ny, nx))
+    rep = dect_report()
+    prm = pls_params(p)
+    st = lib().dect_pls_decompose_noalloc(
+        nx, ny, ct.c_void_p(x_high.data_ptr()), ct.c_void_p(x_low.data_ptr()), ct.byref(prm),
+        ct.c_void_p(edge_w.data_ptr()) if edge_w is not None else None,
+        ct.c_void_p(u1.data_ptr()), ct.c_void_p(u2.data_ptr()),
+        ct.byref(rep) if report else None, _stream())
+    if st not in (DECT_OK, DECT_WARN_MAXITER):
+        _check(st, "dect_pls_decompose_noalloc")
     return u1, u2, (rep if report else None)
 
 
