@@ -349,8 +349,9 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
  * receives the [max_iter+1][4] rows {J_high, J_low, alpha_high, alpha_low}.
  * The two energies advance together (each with its own step), every
  * projector call walking both volumes at once; state in FP32, reductions in
- * FP64.  Allocates its work buffers per call (per energy about 12 volumes
- * and 2 projection sets) and synchronises the stream before returning.
+ * FP64.  Its work buffers (per energy about 12 volumes and 2 projection
+ * sets) are library-owned per device and kept between calls; the call
+ * synchronises the stream before returning.
  * DECT_ERR_NONFINITE when a logged objective or step is not finite.
  */
 dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
@@ -395,8 +396,45 @@ dect_status dect_pls_edge_weights3(int32_t nx, int32_t ny, int32_t nz, const flo
  * for a geometry: the unit of projector work. */
 dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);
 
-/* Free cached tables and workspaces of the current device. */
+/* Free every library-owned device buffer: cached geometry tables, work
+ * buffers and the ADM states the library made for calls without one (states
+ * and batches that callers created stay).  Waits for the device first. */
 dect_status dect_release_caches(void);
+
+/*
+ * Caller-provided device memory for the library's own buffers (SURVEY
+ * boundary: the library owns its tables and workspace unless the caller
+ * hands it one).  After dect_set_workspace(d_ptr, bytes) every device
+ * allocation the library makes on the current device (geometry tables, work
+ * buffers, ADM states and batches created from then on) is a consecutive
+ * 256-byte-aligned piece of [d_ptr, d_ptr + bytes) instead of a hipMalloc;
+ * pieces are never reused or returned one by one.  A call that needs more
+ * than is left fails with DECT_ERR_INVALID_ARG before launching anything.
+ * The call waits for the device and first releases every buffer the library
+ * holds on this device (as dect_release_caches), so the next calls rebuild
+ * theirs inside the workspace.  d_ptr NULL with bytes 0 returns to hipMalloc.
+ * The caller keeps the memory alive and untouched until it replaces or
+ * clears the workspace, and destroys states and batches created while it was
+ * set before doing so.  d_ptr must be 256-byte aligned (DECT_ERR_INVALID_ARG
+ * otherwise).
+ */
+dect_status dect_set_workspace(void *d_ptr, size_t bytes);
+
+/* Bytes of the current device's caller workspace in use (0 without one). */
+dect_status dect_workspace_used(size_t *bytes);
+
+/*
+ * Bytes the 2-D calls need on geom when the library holds nothing yet: its
+ * geometry tables, one dect_adm_tv run without a caller state (any step
+ * rule), dect_project / dect_backproject / dect_fbp on up to `batch` items
+ * on one stream, and dect_pls_decompose at the geometry's image size in
+ * either mode with edges detected.  Computed by a dry run of those
+ * allocations that builds the tables on the host and touches no device
+ * memory.  Later calls with larger batches, other streams or other
+ * geometries need more.  DECT_ERR_INVALID_ARG for batch <= 0 or bytes NULL;
+ * geometry errors as dect_project.
+ */
+dect_status dect_workspace_size(const dect_geometry *geom, int32_t batch, size_t *bytes);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *dect_last_error(void);

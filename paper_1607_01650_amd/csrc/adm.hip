@@ -697,6 +697,8 @@ static dect_status build_graph(dect_adm_state *S, double tol)
 }
 
 static std::mutex g_adm_mu;
+// rows the device log keeps at least (calls of different lengths share it)
+static constexpr size_t kLogRowsMin = 4096;
 static std::vector<std::unique_ptr<dect_adm_state>> g_tmp_states;
 
 dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
@@ -750,7 +752,8 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     const size_t log_rows = (size_t)K + 1;
     // the device log keeps at least 4096 rows so that calls of different
     // lengths reuse it (and the captured graph that points at it)
-    if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, 4096) * 4 * sizeof(double)))) return st;
+    if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, kLogRowsMin) * 4 * sizeof(double))))
+        return st;
     if (!S->started) {
         const bool warm = (P->flags & DECT_WARM_START) != 0;
         if ((st = adm_start(S, P, mh, ml, warm ? xh : nullptr, warm ? xl : nullptr, s))) return st;
@@ -828,6 +831,21 @@ dect_status adm_state_create(const dect_geometry *g, dect_adm_state **out)
 dect_status adm_state_destroy(dect_adm_state *S)
 {
     delete S;
+    return DECT_OK;
+}
+
+// The buffers one ADM run without a caller state allocates (the state, a log
+// of kLogRowsMin rows, the BB2 / adaptive-step extras), for a dry run under a
+// SizingScope.
+dect_status adm_size_run(const dect_geometry *g)
+{
+    auto S = std::make_unique<dect_adm_state>();
+    dect_status st = state_alloc(S.get(), g);
+    if (st) return st;
+    if ((st = S->logbuf.ensure(kLogRowsMin * 4 * sizeof(double))) ||
+        (st = S->apart.ensure(std::max<size_t>(1, adj_partial_floats(*S->t, 2, S->nvg)) * 4)) ||
+        (st = S->p_yy.ensure((size_t)2 * S->nbi * 8)))
+        return st;
     return DECT_OK;
 }
 

@@ -22,6 +22,8 @@
 //             partials <s,s>, <s,y>
 //   k3_scalar alpha = <s,s>/<s,y> when <s,y> > 0, relative change
 #include <cmath>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "volume.h"
@@ -328,6 +330,29 @@ unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+struct Adm3Work {
+    DevBuf buf[2][10], bpart[2], bsc, blog;
+};
+
+static std::mutex g_adm3_mu;
+static std::vector<std::pair<int, std::unique_ptr<Adm3Work>>> g_adm3;
+
+static Adm3Work *adm3_work()
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (auto &p : g_adm3)
+        if (p.first == dev) return p.second.get();
+    g_adm3.emplace_back(dev, std::make_unique<Adm3Work>());
+    return g_adm3.back().second.get();
+}
+
+void release_adm3_work()
+{
+    std::lock_guard<std::mutex> lk(g_adm3_mu);
+    g_adm3.clear();
+}
+
 dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const float *m_low,
                     const dect_adm_params *p, float *x_high, float *x_low, dect_report *rep,
                     hipStream_t s)
@@ -353,10 +378,15 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const int nbM = (int)std::min<size_t>(kMaxBlk, nblk(M));
     const size_t stride = (size_t)std::max(nbN, nbM);
 
-    // library-owned work buffers of this call (sized to the problem), one
-    // set per energy; the two energies advance together so that every
-    // projector call walks both volumes at once
-    DevBuf buf[2][10], bpart[2], bsc, blog;
+    // library-owned work buffers (one set per device, grown to the problem
+    // and kept between calls), one set per energy; the two energies advance
+    // together so that every projector call walks both volumes at once
+    std::lock_guard<std::mutex> lk(g_adm3_mu);
+    Adm3Work *w3 = adm3_work();
+    auto &buf = w3->buf;
+    auto &bpart = w3->bpart;
+    auto &bsc = w3->bsc;
+    auto &blog = w3->blog;
     const size_t vsz[10] = {d.N, d.N, d.N, d.N, d.N, 3 * d.N, 3 * d.N, 3 * d.N, M, M};
     dect_status st;
     for (int e = 0; e < 2; ++e) {

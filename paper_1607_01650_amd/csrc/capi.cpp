@@ -10,7 +10,6 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
 dect_status adm_state_create(const dect_geometry *g, dect_adm_state **out);
 dect_status adm_state_destroy(dect_adm_state *S);
 dect_status adm_state_reset(dect_adm_state *S);
-void release_adm_states();
 dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
                           const dect_pls_params *P, const float *ew, float *u1, float *u2,
                           dect_report *rep, hipStream_t s);
@@ -28,6 +27,36 @@ dect_status adm_tv_batched(dect_batch *b, const float *const *mh, const float *c
 dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const *ml, int iters,
                        int32_t *chosen, double *ms_per_iter, hipStream_t s);
 dect_status batch_set_groups(dect_batch *b, int groups);
+
+// Bytes the 2-D calls allocate on geom when nothing is held yet: a dry run
+// of their allocations (tables, one ADM run without a caller state, the
+// projector pair and FBP for `batch` items on one stream, PLS in both modes),
+// counted by a SizingScope and never touching device memory.
+dect_status workspace_size(const dect_geometry *g, int batch, size_t *bytes)
+{
+    if (!bytes) return fail(DECT_ERR_INVALID_ARG, "dect_workspace_size: bytes is NULL");
+    if (batch <= 0) return fail(DECT_ERR_INVALID_ARG, "dect_workspace_size: batch must be positive");
+    dect_status st = validate_geometry(g);
+    if (st) return st;
+    SizingScope sc;
+    if ((st = adm_size_run(g)) || (st = proj_size_run(g, batch)) ||
+        (st = fbp_size_run(g, batch)) || (st = pls_size_run((size_t)g->nx * g->ny)))
+        return st;
+    *bytes = sc.bytes;
+    return DECT_OK;
+}
+
+void release_device_buffers()
+{
+    release_adm_states();
+    release_proj_work();
+    release_fbp_work();
+    release_pls_work();
+    release_pls3_work();
+    release_cone_work();
+    release_adm3_work();
+    release_tables();
+}
 }  // namespace dect
 
 extern "C" {
@@ -193,10 +222,26 @@ dect_status dect_count_samples(const dect_geometry *geom, int64_t *out)
 dect_status dect_release_caches(void)
 {
     (void)hipDeviceSynchronize();
-    dect::release_adm_states();
-    dect::release_pls3_work();
-    dect::release_tables();
+    dect::release_device_buffers();
     return DECT_OK;
+}
+
+dect_status dect_set_workspace(void *d_ptr, size_t bytes)
+{
+    dect::set_error("");
+    return dect::set_workspace(d_ptr, bytes);
+}
+
+dect_status dect_workspace_used(size_t *bytes)
+{
+    dect::set_error("");
+    return dect::workspace_used(bytes);
+}
+
+dect_status dect_workspace_size(const dect_geometry *geom, int32_t batch, size_t *bytes)
+{
+    dect::set_error("");
+    return dect::workspace_size(geom, batch, bytes);
 }
 
 const char *dect_last_error(void) { return dect::last_error(); }

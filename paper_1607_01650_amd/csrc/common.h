@@ -159,6 +159,31 @@ dect_status validate_geometry(const dect_geometry *g);
 void release_tables();
 
 // ----------------------------------------------------------- workspaces ---
+// Every device allocation of the library goes through dev_alloc / dev_free.
+// Without a caller workspace they are hipMalloc / hipFree.  With one (set by
+// dect_set_workspace for the current device) dev_alloc hands out consecutive
+// 256-byte-aligned pieces of it and dev_free ignores them: the pieces are
+// released together when the workspace is replaced.
+dect_status dev_alloc(void **p, size_t n);
+void dev_free(void *p);
+
+// A dry run that only counts bytes: while one is active on a thread,
+// dev_alloc returns distinct placeholder addresses that must never be
+// touched (DevBuf skips its clearing and the table upload its copies) and
+// adds the 256-byte-aligned size to `bytes`; dev_free does nothing.
+// get_tables builds tables into the scope instead of the cache.
+struct GeomTables;
+struct SizingScope {
+    size_t bytes = 0;
+    uintptr_t next = 256;
+    std::vector<std::unique_ptr<GeomTables>> tables;
+    SizingScope();
+    ~SizingScope();
+    SizingScope(const SizingScope &) = delete;
+    SizingScope &operator=(const SizingScope &) = delete;
+};
+bool sizing_active();
+
 // A growable device buffer owned by the library.
 struct DevBuf {
     void *ptr = nullptr;
@@ -166,6 +191,26 @@ struct DevBuf {
     dect_status ensure(size_t n, bool zero = false);
     ~DevBuf();
 };
+
+// Frees every library-owned device buffer of the current device: geometry
+// tables, work buffers and the ADM states the library made for calls
+// without one (not states or batches that callers created).
+void release_device_buffers();
+void release_adm_states();
+void release_proj_work();
+void release_fbp_work();
+void release_pls_work();
+void release_pls3_work();
+void release_cone_work();
+void release_adm3_work();
+dect_status set_workspace(void *p, size_t bytes);
+dect_status workspace_used(size_t *bytes);
+dect_status workspace_size(const dect_geometry *g, int batch, size_t *bytes);
+// dry runs of each part (under a SizingScope)
+dect_status adm_size_run(const dect_geometry *g);
+dect_status proj_size_run(const dect_geometry *g, int batch);
+dect_status fbp_size_run(const dect_geometry *g, int batch);
+dect_status pls_size_run(size_t n_pixels);
 
 // ------------------------------------------------------------ projector ---
 struct ProjWork {

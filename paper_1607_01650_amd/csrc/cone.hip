@@ -517,4 +517,10 @@ dect_status cone_backproject2(const dect_cone_geometry *g, const float *const pr
     return cone_backproject_n<2>(g, proj, vol, s);
 }
 
+void release_cone_work()
+{
+    std::lock_guard<std::mutex> lk(g_cone_mu);
+    g_cone_ws.clear();
+}
+
 }  // namespace dect

@@ -166,6 +166,20 @@ DevBuf *fbp_workspace(hipStream_t s)
 
 }  // namespace
 
+// Bytes of the filtered, padded sinograms of `batch` items (pairs).
+static size_t fbp_work_bytes(const dect_geometry *g, int batch)
+{
+    return (size_t)pairs_of(batch) * g->n_views * (g->n_bins + 2 * kQPad) * sizeof(f2v);
+}
+
+// The work buffer dect_fbp allocates for `batch` sinograms on one stream,
+// for a dry run under a SizingScope.
+dect_status fbp_size_run(const dect_geometry *g, int batch)
+{
+    DevBuf w;
+    return w.ensure(fbp_work_bytes(g, batch));
+}
+
 dect_status fbp(const dect_geometry *g, const float *sino, float *img, int batch, hipStream_t s)
 {
     if (!sino || !img || batch <= 0)
@@ -179,7 +193,7 @@ dect_status fbp(const dect_geometry *g, const float *sino, float *img, int batch
     GeomTables *t = nullptr;
     if ((st = get_tables(g, &t)) != DECT_OK) return st;
     const int V = g->n_views, B = g->n_bins, pairs = pairs_of(batch);
-    const size_t qbytes = (size_t)pairs * V * (B + 2 * kQPad) * sizeof(f2v);
+    const size_t qbytes = fbp_work_bytes(g, batch);
     std::lock_guard<std::mutex> lk(g_fbp_mu);
     DevBuf *w = fbp_workspace(s);
     if (w->bytes < qbytes) {
@@ -201,6 +215,12 @@ dect_status fbp(const dect_geometry *g, const float *sino, float *img, int batch
                        (float)R, (float)(D / du), b0, (float)(2.0 * M_PI / V), img);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
+}
+
+void release_fbp_work()
+{
+    std::lock_guard<std::mutex> lk(g_fbp_mu);
+    g_fbp_ws.clear();
 }
 
 }  // namespace dect

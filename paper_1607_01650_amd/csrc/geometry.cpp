@@ -21,27 +21,127 @@ dect_status fail(dect_status st, const std::string &msg)
 
 const char *last_error() { return g_last_error.c_str(); }
 
+// ------------------------------------------- device memory, workspace ---
+namespace {
+
+struct Arena {
+    int device;
+    unsigned char *base;
+    size_t bytes, used;
+};
+
+std::mutex g_arena_mu;
+std::vector<Arena> g_arenas;  // at most one per device
+thread_local SizingScope *g_sizing = nullptr;
+
+constexpr size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
+SizingScope::SizingScope() { g_sizing = this; }
+
+SizingScope::~SizingScope()
+{
+    tables.clear();  // still counting: their frees do nothing
+    g_sizing = nullptr;
+}
+
+bool sizing_active() { return g_sizing != nullptr; }
+
+dect_status dev_alloc(void **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) return DECT_OK;
+    const size_t a = align256(n);
+    if (g_sizing) {
+        g_sizing->bytes += a;
+        *p = (void *)g_sizing->next;
+        g_sizing->next += a;
+        return DECT_OK;
+    }
+    int dev = 0;
+    DECT_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_arena_mu);
+        for (auto &ar : g_arenas)
+            if (ar.device == dev) {
+                if (ar.bytes - ar.used < a)
+                    return fail(DECT_ERR_INVALID_ARG,
+                                "caller workspace exhausted: " + std::to_string(ar.used) + " of " +
+                                    std::to_string(ar.bytes) + " bytes used, " +
+                                    std::to_string(a) + " more needed");
+                *p = ar.base + ar.used;
+                ar.used += a;
+                return DECT_OK;
+            }
+    }
+    DECT_HIP(hipMalloc(p, n));
+    return DECT_OK;
+}
+
+void dev_free(void *p)
+{
+    if (!p || g_sizing) return;
+    {
+        std::lock_guard<std::mutex> lk(g_arena_mu);
+        for (auto &ar : g_arenas)
+            if ((unsigned char *)p >= ar.base && (unsigned char *)p < ar.base + ar.bytes) return;
+    }
+    (void)hipFree(p);
+}
+
+dect_status set_workspace(void *p, size_t bytes)
+{
+    if ((p == nullptr) != (bytes == 0))
+        return fail(DECT_ERR_INVALID_ARG, "dect_set_workspace: give both a pointer and a size, or neither");
+    if (((uintptr_t)p & 255) != 0)
+        return fail(DECT_ERR_INVALID_ARG, "dect_set_workspace: the workspace must be 256-byte aligned");
+    int dev = 0;
+    DECT_HIP(hipGetDevice(&dev));
+    DECT_HIP(hipDeviceSynchronize());
+    // every buffer the library holds on this device goes first, while the old
+    // workspace (if any) is still known, so its pieces are not passed to hipFree
+    release_device_buffers();
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    for (auto it = g_arenas.begin(); it != g_arenas.end();) {
+        if (it->device == dev) it = g_arenas.erase(it);
+        else ++it;
+    }
+    if (p) g_arenas.push_back(Arena{dev, (unsigned char *)p, bytes, 0});
+    return DECT_OK;
+}
+
+dect_status workspace_used(size_t *bytes)
+{
+    if (!bytes) return fail(DECT_ERR_INVALID_ARG, "dect_workspace_used: bytes is NULL");
+    int dev = 0;
+    DECT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    *bytes = 0;
+    for (auto &ar : g_arenas)
+        if (ar.device == dev) *bytes = ar.used;
+    return DECT_OK;
+}
+
 // ------------------------------------------------------------ DevBuf ---
 dect_status DevBuf::ensure(size_t n, bool zero)
 {
     if (n <= bytes && ptr) return DECT_OK;
     if (ptr) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ptr);
+        if (!g_sizing) (void)hipDeviceSynchronize();
+        dev_free(ptr);
         ptr = nullptr;
         bytes = 0;
     }
     if (n == 0) return DECT_OK;
-    DECT_HIP(hipMalloc(&ptr, n));
+    dect_status st = dev_alloc(&ptr, n);
+    if (st) return st;
     bytes = n;
-    if (zero) DECT_HIP(hipMemset(ptr, 0, n));
+    if (zero && !g_sizing) DECT_HIP(hipMemset(ptr, 0, n));
     return DECT_OK;
 }
 
-DevBuf::~DevBuf()
-{
-    if (ptr) (void)hipFree(ptr);
-}
+DevBuf::~DevBuf() { dev_free(ptr); }
 
 // ---------------------------------------------------------- geometry ---
 bool GeomKey::operator==(const GeomKey &o) const
@@ -53,14 +153,14 @@ bool GeomKey::operator==(const GeomKey &o) const
 
 GeomTables::~GeomTables()
 {
-    if (fwd) (void)hipFree(fwd);
-    if (adj) (void)hipFree(adj);
-    if (len) (void)hipFree(len);
-    if (bundles) (void)hipFree(bundles);
-    if (views) (void)hipFree(views);
-    if (adj_bins) (void)hipFree(adj_bins);
-    if (adj_lanes) (void)hipFree(adj_lanes);
-    if (sid) (void)hipFree(sid);
+    dev_free(fwd);
+    dev_free(adj);
+    dev_free(len);
+    dev_free(bundles);
+    dev_free(views);
+    dev_free(adj_bins);
+    dev_free(adj_lanes);
+    dev_free(sid);
 }
 
 dect_status validate_geometry(const dect_geometry *g)
@@ -150,12 +250,21 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
                 g->det_offset_mm, g->sod_mm, g->sdd_mm, {}, dev};
     if (g->angles_rad) key.angles.assign(g->angles_rad, g->angles_rad + g->n_views);
 
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    for (auto &t : g_cache)
-        if (t->key == key) {
-            *out = t.get();
-            return DECT_OK;
-        }
+    std::unique_lock<std::mutex> lk(g_cache_mu, std::defer_lock);
+    if (g_sizing) {  // a dry run keeps its own tables and never uses the cache
+        for (auto &t : g_sizing->tables)
+            if (t->key == key) {
+                *out = t.get();
+                return DECT_OK;
+            }
+    } else {
+        lk.lock();
+        for (auto &t : g_cache)
+            if (t->key == key) {
+                *out = t.get();
+                return DECT_OK;
+            }
+    }
 
     const int nx = g->nx, ny = g->ny, V = g->n_views, B = g->n_bins;
     const double dl = g->pixel_mm, R = g->sod_mm, D = g->sdd_mm;
@@ -390,30 +499,21 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     t->key = key;
     t->nbundle = nb;
     t->samples = samples;
-    DECT_HIP(hipMalloc(&t->fwd, fwd.size() * sizeof(RayFwd)));
-    DECT_HIP(hipMalloc(&t->adj, adj.size() * sizeof(RayAdj)));
-    DECT_HIP(hipMalloc(&t->len, len.size() * sizeof(float)));
-    DECT_HIP(hipMalloc(&t->bundles, bun.size() * sizeof(Bundle)));
-    DECT_HIP(hipMalloc(&t->views, views.size() * sizeof(ViewInfo)));
-    DECT_HIP(hipMalloc(&t->adj_bins, bins.size() * sizeof(BinRange)));
-    DECT_HIP(hipMalloc(&t->adj_lanes, lanes.size() * sizeof(LaneRange)));
-    if (siddon) {
-        DECT_HIP(hipMalloc(&t->sid, sid.size() * sizeof(SidW)));
-        DECT_HIP(hipMemcpy(t->sid, sid.data(), sid.size() * sizeof(SidW), hipMemcpyHostToDevice));
-    }
-    DECT_HIP(hipMemcpy(t->fwd, fwd.data(), fwd.size() * sizeof(RayFwd), hipMemcpyHostToDevice));
-    DECT_HIP(hipMemcpy(t->adj, adj.data(), adj.size() * sizeof(RayAdj), hipMemcpyHostToDevice));
-    DECT_HIP(hipMemcpy(t->len, len.data(), len.size() * sizeof(float), hipMemcpyHostToDevice));
-    DECT_HIP(hipMemcpy(t->bundles, bun.data(), bun.size() * sizeof(Bundle),
-                       hipMemcpyHostToDevice));
-    DECT_HIP(hipMemcpy(t->views, views.data(), views.size() * sizeof(ViewInfo),
-                       hipMemcpyHostToDevice));
-    DECT_HIP(hipMemcpy(t->adj_bins, bins.data(), bins.size() * sizeof(BinRange),
-                       hipMemcpyHostToDevice));
-    DECT_HIP(hipMemcpy(t->adj_lanes, lanes.data(), lanes.size() * sizeof(LaneRange),
-                       hipMemcpyHostToDevice));
+    auto upload = [&](auto **dst, const auto &v) -> dect_status {
+        const size_t n = v.size() * sizeof(v[0]);
+        dect_status e = dev_alloc((void **)dst, n);
+        if (e) return e;
+        if (!g_sizing && n) DECT_HIP(hipMemcpy(*dst, v.data(), n, hipMemcpyHostToDevice));
+        return DECT_OK;
+    };
+    if ((st = upload(&t->fwd, fwd)) || (st = upload(&t->adj, adj)) || (st = upload(&t->len, len)) ||
+        (st = upload(&t->bundles, bun)) || (st = upload(&t->views, views)) ||
+        (st = upload(&t->adj_bins, bins)) || (st = upload(&t->adj_lanes, lanes)) ||
+        (siddon && (st = upload(&t->sid, sid))))
+        return st;
     *out = t.get();
-    g_cache.push_back(std::move(t));
+    if (g_sizing) g_sizing->tables.push_back(std::move(t));
+    else g_cache.push_back(std::move(t));
     return DECT_OK;
 }
 

@@ -696,6 +696,48 @@ dect_status pls_edge_weights(int nx, int ny, const float *x, double tau, double 
     return edges_into(nx, ny, x, tau, eps, w, pls_work(), s);
 }
 
+// The image-space work buffers of N pixels in nblk reduction blocks.
+static dect_status pls_prepare(PlsWork *W, size_t N, int nblk)
+{
+    dect_status st;
+    if ((st = W->b.ensure(2 * N * 4)) || (st = W->res.ensure(2 * N * 4)) ||
+        (st = W->z.ensure(2 * N * 4)) || (st = W->p0.ensure(2 * N * 4)) ||
+        (st = W->p1.ensure(2 * N * 4)) || (st = W->q.ensure(2 * N * 4)) ||
+        (st = W->minv.ensure(N * 4)) || (st = W->prz0.ensure((size_t)2 * nblk * 8)) ||
+        (st = W->prz1.ensure((size_t)2 * nblk * 8)) || (st = W->prr.ensure((size_t)2 * nblk * 8)) ||
+        (st = W->pbb.ensure((size_t)2 * nblk * 8)) || (st = W->ppq.ensure((size_t)2 * nblk * 8)) ||
+        (st = W->stat.ensure(2 * sizeof(PcgStatus))))
+        return st;
+    return DECT_OK;
+}
+
+// The FP64 vectors of the attenuation-space solve (they replace the FP32
+// ones of the same names).
+static dect_status pls_prepare_att(PlsWork *W, size_t N)
+{
+    dect_status st;
+    if ((st = W->u64.ensure(2 * N * 8)) || (st = W->res.ensure(2 * N * 8)) ||
+        (st = W->z.ensure(2 * N * 8)) || (st = W->p0.ensure(2 * N * 8)) ||
+        (st = W->p1.ensure(2 * N * 8)) || (st = W->q.ensure(2 * N * 8)))
+        return st;
+    return DECT_OK;
+}
+
+// The work buffers of a decomposition of N pixels in both modes with the
+// edges detected, in the order the calls allocate them (image mode first),
+// for a dry run under a SizingScope.
+dect_status pls_size_run(size_t N)
+{
+    const int nblk = (int)((N + 256 * kPix - 1) / (256 * kPix));
+    PlsWork W;
+    dect_status st;
+    if ((st = pls_prepare(&W, N, nblk)) || (st = W.w.ensure(2 * N * 4)) ||
+        (st = W.m2.ensure(N * 4)) || (st = W.pmax.ensure((size_t)nblk * 4)) ||
+        (st = pls_prepare_att(&W, N)))
+        return st;
+    return DECT_OK;
+}
+
 // The attenuation-space system, from u = D^{-1} x already in u1, u2.
 dect_status pls_attenuation(int nx, int ny, const float *xh, const float *xl,
                             const dect_pls_params *P, const float *w, float *u1, float *u2,
@@ -703,10 +745,7 @@ dect_status pls_attenuation(int nx, int ny, const float *xh, const float *xl,
 {
     const size_t N = (size_t)nx * ny;
     dect_status st;
-    if ((st = W->u64.ensure(2 * N * 8)) || (st = W->res.ensure(2 * N * 8)) ||
-        (st = W->z.ensure(2 * N * 8)) || (st = W->p0.ensure(2 * N * 8)) ||
-        (st = W->p1.ensure(2 * N * 8)) || (st = W->q.ensure(2 * N * 8)))
-        return st;
+    if ((st = pls_prepare_att(W, N))) return st;
     AttCoef k;
     k.e1h = P->eta_water_high;
     k.e2h = P->eta_bone_high;
@@ -786,14 +825,7 @@ dect_status pls_decompose(int nx, int ny, const float *xh, const float *xl,
     PlsWork *W = pls_work();
     const size_t N = (size_t)nx * ny;
     const int nblk = (int)((N + 256 * kPix - 1) / (256 * kPix));
-    if ((st = W->b.ensure(2 * N * 4)) || (st = W->res.ensure(2 * N * 4)) ||
-        (st = W->z.ensure(2 * N * 4)) || (st = W->p0.ensure(2 * N * 4)) ||
-        (st = W->p1.ensure(2 * N * 4)) || (st = W->q.ensure(2 * N * 4)) ||
-        (st = W->minv.ensure(N * 4)) || (st = W->prz0.ensure((size_t)2 * nblk * 8)) ||
-        (st = W->prz1.ensure((size_t)2 * nblk * 8)) || (st = W->prr.ensure((size_t)2 * nblk * 8)) ||
-        (st = W->pbb.ensure((size_t)2 * nblk * 8)) || (st = W->ppq.ensure((size_t)2 * nblk * 8)) ||
-        (st = W->stat.ensure(2 * sizeof(PcgStatus))))
-        return st;
+    if ((st = pls_prepare(W, N, nblk))) return st;
     dinv_run(nx, ny, xh, xl, P, u1, u2, (float *)W->b.ptr, s);
     DECT_HIP(hipGetLastError());
     const float *w = ew;
@@ -921,6 +953,12 @@ dect_status pls_decompose_noalloc(int nx, int ny, const float *xh, const float *
         w = B.w;
     }
     return pcg_image_run(nx, ny, P, w, u1, u2, rep, B, s);
+}
+
+void release_pls_work()
+{
+    std::lock_guard<std::mutex> lk(g_pls_mu);
+    g_pls.clear();
 }
 
 }  // namespace dect

@@ -266,6 +266,26 @@ static ProjWork *workspace(hipStream_t s)
     return g_ws.back().second.get();
 }
 
+// Bytes of one interleaved padded layout of `batch` images (pairs).
+static size_t pad_bytes(const dect_geometry *g, int batch)
+{
+    return (size_t)(g->nx + 2 * kPad) * (g->ny + 2 * kPad) * 2 * pairs_of(batch) * sizeof(float);
+}
+
+// The work buffers dect_project and dect_backproject allocate for `batch`
+// images on one stream, for a dry run under a SizingScope.
+dect_status proj_size_run(const dect_geometry *g, int batch)
+{
+    GeomTables *t = nullptr;
+    dect_status st = get_tables(g, &t);
+    if (st) return st;
+    ProjWork w;
+    if ((st = w.pad.ensure(pad_bytes(g, batch))) || (st = w.padT.ensure(pad_bytes(g, batch))) ||
+        (st = w.partial.ensure(adj_partial_floats(*t, batch) * sizeof(float))))
+        return st;
+    return DECT_OK;
+}
+
 dect_status project(const dect_geometry *g, const float *img, float *sino, int batch,
                     hipStream_t s)
 {
@@ -276,8 +296,7 @@ dect_status project(const dect_geometry *g, const float *img, float *sino, int b
     if (st != DECT_OK) return st;
     std::lock_guard<std::mutex> lk(g_ws_mu);
     ProjWork *w = workspace(s);
-    const size_t padn =
-        (size_t)(g->nx + 2 * kPad) * (g->ny + 2 * kPad) * 2 * pairs_of(batch) * sizeof(float);
+    const size_t padn = pad_bytes(g, batch);
     // the padded copies are reused across calls and geometries; k_pad writes
     // them whole, border included
     if (w->pad.bytes < padn) {
@@ -307,6 +326,12 @@ dect_status backproject(const dect_geometry *g, const float *sino, float *img, i
         if ((st = w->partial.ensure(need)) != DECT_OK) return st;
     }
     return launch_adj(*t, sino, img, (float *)w->partial.ptr, batch, 1.0f, s);
+}
+
+void release_proj_work()
+{
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_ws.clear();
 }
 
 }  // namespace dect

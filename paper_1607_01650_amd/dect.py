@@ -99,6 +99,9 @@ SIGNATURES = {
     "dect_adm_state_create": (ct.c_int, [_P(dect_geometry), _P(ct.c_void_p)]),
     "dect_adm_state_destroy": (ct.c_int, [ct.c_void_p]),
     "dect_adm_state_reset": (ct.c_int, [ct.c_void_p]),
+    "dect_set_workspace": (ct.c_int, [ct.c_void_p, ct.c_size_t]),
+    "dect_workspace_used": (ct.c_int, [_P(ct.c_size_t)]),
+    "dect_workspace_size": (ct.c_int, [_P(dect_geometry), ct.c_int32, _P(ct.c_size_t)]),
     "dect_pls_decompose": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                       _P(dect_pls_params), ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       _P(dect_report), ct.c_void_p]),
@@ -610,6 +613,34 @@ def pls_edge_weights(x, tau: float, eps: float):
 
 def release_caches():
     lib().dect_release_caches()
+
+
+def workspace_size(geom: C.Geometry, batch: int = 2) -> int:
+    """Bytes the 2-D calls need on geom (dect_workspace_size)."""
+    out = ct.c_size_t(0)
+    _check(lib().dect_workspace_size(GeomArg(geom).ref, int(batch), ct.byref(out)),
+           "dect_workspace_size")
+    return int(out.value)
+
+
+def set_workspace(buf=None):
+    """Hand the library a device buffer (a uint8 torch tensor) for all its own
+    allocations on its device, or None to return to hipMalloc
+    (dect_set_workspace).  Keep the tensor alive until this is called again."""
+    if buf is None:
+        _check(lib().dect_set_workspace(None, 0), "dect_set_workspace")
+        return
+    torch = _torch()
+    if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("workspace must be a contiguous ROCm device tensor")
+    _check(lib().dect_set_workspace(ct.c_void_p(buf.data_ptr()),
+                                    buf.numel() * buf.element_size()), "dect_set_workspace")
+
+
+def workspace_used() -> int:
+    out = ct.c_size_t(0)
+    _check(lib().dect_workspace_used(ct.byref(out)), "dect_workspace_used")
+    return int(out.value)
 
 
 def version() -> str:
