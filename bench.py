@@ -536,7 +536,16 @@ def batched_extra(n_slices: int, iters: int):
         mh.append(sino[0].contiguous())
         ml.append(sino[1].contiguous())
     b = dect.AdmBatch(geoms, params)
+    b.run(mh, ml, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(mh, ml, iters)
+    torch.cuda.synchronize()
+    t_builtin = time.perf_counter() - t0
+    t0 = time.perf_counter()
     groups, _ = b.tune(mh, ml, iters=4)
+    t_tune = time.perf_counter() - t0
+    per_slice, adj_cu, fwd_cu, _ = b.shape()
     b.run(mh, ml, 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -556,6 +565,9 @@ def batched_extra(n_slices: int, iters: int):
     return {"workload": f"{n_slices} slices x 2 energies, sizes {{256,384,512}}^2, views "
                         "{60,90,180,360}, seed 0",
             "iters": iters, "tuned_view_groups": groups,
+            "tuned_depths": sorted(set(per_slice)), "tuned_adj_blocks_per_cu": adj_cu,
+            "tuned_fwd_blocks_per_cu": fwd_cu, "tune_s": round(t_tune, 2),
+            "ms_per_iteration_builtin_shape": round(1e3 * t_builtin / iters, 3),
             "slice_iters_per_s": round(n_slices * iters / t_batch, 1),
             "ray_updates_per_s": round(samples * iters / t_batch, 1),
             "ms_per_iteration_all_slices": round(1e3 * t_batch / iters, 3),

@@ -273,9 +273,19 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  *   to slice i's sinograms [V_i][B_i] and output images [ny_i][nx_i].
  * objective: NULL or host [n], filled after synchronising the stream with
  *   J(f^K) of Eq. 4 summed over both energies.
- * dect_batch_tune times `iters` iterations for each adjoint view-group depth
- * (2, 4, 8, 16 blocks per output tile) on the given data and keeps the
- * fastest; dect_batch_set_groups fixes it (0 = built-in heuristic).
+ * dect_batch_tune chooses the batch's launch shape by timing `iters`
+ * iterations per candidate on the given data (coordinate descent): for each
+ * class of equal slices (image size and view count, costliest first) the
+ * adjoint view-group depth 1, 2, 4, 8 or 16 (blocks sharing one output
+ * strip, i.e. views per adjoint tile), then the blocks per CU of the
+ * persistent adjoint and forward grids (1, 2 or all that fit).  The choice is
+ * remembered for the process: a batch with the same multiset of slice shapes
+ * (nx, ny, n_views, n_bins) takes it without timing.  *chosen_groups receives
+ * the depth of the costliest slice, *ms_per_iter the tuned time per
+ * iteration.  dect_batch_set_groups fixes one depth for every slice
+ * (0 = built-in heuristic) and drops the tuned shape; dect_batch_shape
+ * reports the depth per slice (host array [n]), the grid caps (0 = all that
+ * fit) and whether the last tune came from the process cache.
  */
 typedef struct dect_batch dect_batch;
 dect_status dect_batch_create(const dect_geometry *geoms, const dect_adm_params *params,
@@ -289,6 +299,9 @@ dect_status dect_batch_tune(dect_batch *batch, const float *const *d_m_high,
                             const float *const *d_m_low, int32_t iters, int32_t *chosen_groups,
                             double *ms_per_iter, void *stream);
 dect_status dect_batch_set_groups(dect_batch *batch, int32_t groups);
+dect_status dect_batch_shape(const dect_batch *batch, int32_t *groups_per_slice,
+                             int32_t *adj_blocks_per_cu, int32_t *fwd_blocks_per_cu,
+                             int32_t *from_cache);
 
 /*
  * 3-D circular cone beam with a flat panel (the scanner of Sec. 3, of which

@@ -8,7 +8,9 @@
 // blocks round-robin; the adjoint's view-group depth (how many blocks share
 // one output tile) is chosen per batch by a timing autotuner.
 #include <algorithm>
+#include <array>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "adm_device.h"
@@ -175,6 +177,12 @@ struct dect_batch {
     int n_tv = 0, n_fwd = 0, n_se = 0, n_upd = 0, n_adj = 0;
     int g_tv = 0, g_fwd = 0, g_se = 0, g_upd = 0, g_adj = 0;
     int nvg_max = 16, group_choice = 0;  // 0: per-slice heuristic, else fixed
+    // autotuned shape: the adjoint view-group depth per slice (0: as
+    // group_choice) and the persistent grids' blocks per CU for the adjoint
+    // and forward phases (0: as many as fit)
+    std::vector<int> slice_groups;
+    int adj_per_cu = 0, fwd_per_cu = 0;
+    bool tuned_from_cache = false;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;
     ~dect_batch()
@@ -200,8 +208,9 @@ dect_status build_work(dect_batch *b)
         const GeomTables &t = *b->t[s];
         // the built-in choice equals the single-slice path's (bitwise equal
         // results); a tuned choice is capped by the views per group
-        int nvg = b->group_choice ? std::min(b->group_choice, std::max(1, d.V / 8))
-                                  : heuristic_groups(t);
+        const int want = (s < (int)b->slice_groups.size() && b->slice_groups[s])
+                             ? b->slice_groups[s] : b->group_choice;
+        int nvg = want ? std::min(want, std::max(1, d.V / 8)) : heuristic_groups(t);
         d.nvg = nvg;
         const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
         const int nstrips = adj_strips(d.nx, d.ny);
@@ -239,18 +248,19 @@ dect_status build_work(dect_batch *b)
     int dev = 0, cus = 0;
     DECT_HIP(hipGetDevice(&dev));
     DECT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    auto grid = [&](const void *fn, int items, int threads = 256) {
+    auto grid = [&](const void *fn, int items, int threads = 256, int cap = 0) {
         int per = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, 0) != hipSuccess ||
             per < 1)
             per = 1;
+        if (cap > 0) per = std::min(per, cap);
         return std::max(1, std::min(items, per * cus));
     };
     b->g_tv = grid((const void *)kb_tv, b->n_tv);
-    b->g_fwd = grid((const void *)kb_fwd, b->n_fwd, kFwdThreads);
+    b->g_fwd = grid((const void *)kb_fwd, b->n_fwd, kFwdThreads, b->fwd_per_cu);
     b->g_se = std::max(1, b->n_se);
     b->g_upd = grid((const void *)kb_update, b->n_upd);
-    b->g_adj = grid((const void *)kb_adj, b->n_adj, kAdjThreads);
+    b->g_adj = grid((const void *)kb_adj, b->n_adj, kAdjThreads, b->adj_per_cu);
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
@@ -467,42 +477,178 @@ dect_status adm_tv_batched(dect_batch *b, const float *const *mh, const float *c
     return DECT_OK;
 }
 
+// Tuned shapes, kept for the process: a batch of the same slice shapes (the
+// multiset of image size, views and bins) reuses them without timing.
+struct TunedShape {
+    std::vector<std::array<int, 4>> shapes;  // sorted (nx, ny, V, B) per slice
+    std::vector<int> groups;                 // per sorted slice
+    int adj_per_cu = 0, fwd_per_cu = 0;
+    double ms = 0.0;
+};
+static std::mutex g_tune_mu;
+static std::vector<TunedShape> g_tuned;
+
+static std::vector<int> shape_order(const dect_batch *b, std::vector<std::array<int, 4>> &shapes)
+{
+    std::vector<int> order(b->n);
+    std::iota(order.begin(), order.end(), 0);
+    auto key = [&](int i) {
+        const SliceDev &d = b->host[i];
+        return std::array<int, 4>{d.nx, d.ny, d.V, d.B};
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key(a) < key(c); });
+    shapes.resize(b->n);
+    for (int k = 0; k < b->n; ++k) shapes[k] = key(order[k]);
+    return order;
+}
+
+// Time `iters` iterations of the current shape (after a 2-iteration warm-up
+// that also captures the graph).
+static dect_status time_shape(dect_batch *b, const float *const *mh, const float *const *ml,
+                              int iters, hipStream_t s, hipEvent_t e0, hipEvent_t e1, double *ms)
+{
+    dect_status st;
+    if ((st = build_work(b)) || (st = batch_run(b, mh, ml, 2, s))) return st;
+    DECT_HIP(hipStreamSynchronize(s));
+    DECT_HIP(hipEventRecord(e0, s));
+    if ((st = batch_run(b, mh, ml, iters, s))) return st;
+    DECT_HIP(hipEventRecord(e1, s));
+    DECT_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    DECT_HIP(hipEventElapsedTime(&t, e0, e1));
+    *ms = t;
+    return DECT_OK;
+}
+
+// Coordinate descent over the batch's shape: for each class of equal slices
+// (image size and views; the costliest class first) the adjoint view-group
+// depth 1, 2, 4, 8 or 16 (how many blocks share one output strip, i.e. how
+// many views each adjoint tile walks), then the blocks per CU of the
+// persistent adjoint and forward grids (1, 2 or as many as fit).  Each
+// candidate is timed over `iters` iterations on the given data; the fastest
+// is kept and remembered for batches of the same slice shapes.
 dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const *ml, int iters,
                        int32_t *chosen, double *ms_per_iter, hipStream_t s)
 {
     if (!b || !mh || !ml || iters < 2)
         return fail(DECT_ERR_INVALID_ARG, "dect_batch_tune: bad arguments");
-    const int options[] = {2, 4, 8, 16};
-    double best = 1e30;
-    int best_g = 0;
+    std::vector<std::array<int, 4>> shapes;
+    const std::vector<int> order = shape_order(b, shapes);
+    // the slice of the costliest class reports its depth in *chosen
+    int big = 0;
+    double big_w = -1.0;
+    for (int i = 0; i < b->n; ++i) {
+        const SliceDev &d = b->host[i];
+        const double w = (double)d.V * std::max(d.nx, d.ny) * std::max(d.nx, d.ny);
+        if (w > big_w) {
+            big_w = w;
+            big = i;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const TunedShape &c : g_tuned)
+            if (c.shapes == shapes) {
+                b->slice_groups.assign(b->n, 0);
+                for (int k = 0; k < b->n; ++k) b->slice_groups[order[k]] = c.groups[k];
+                b->adj_per_cu = c.adj_per_cu;
+                b->fwd_per_cu = c.fwd_per_cu;
+                b->tuned_from_cache = true;
+                dect_status st = build_work(b);
+                if (st) return st;
+                if (chosen) *chosen = b->slice_groups[big];
+                if (ms_per_iter) *ms_per_iter = c.ms / iters;
+                return DECT_OK;
+            }
+    }
+    // classes of equal (nx, ny, V), costliest first
+    std::vector<std::pair<double, std::vector<int>>> classes;
+    for (int i = 0; i < b->n; ++i) {
+        const SliceDev &d = b->host[i];
+        bool found = false;
+        for (auto &c : classes) {
+            const SliceDev &o = b->host[c.second[0]];
+            if (o.nx == d.nx && o.ny == d.ny && o.V == d.V) {
+                c.second.push_back(i);
+                c.first += (double)d.V * d.nx * d.ny;
+                found = true;
+                break;
+            }
+        }
+        if (!found) classes.push_back({(double)d.V * d.nx * d.ny, {i}});
+    }
+    std::stable_sort(classes.begin(), classes.end(),
+                     [](const auto &a, const auto &c) { return a.first > c.first; });
     hipEvent_t e0, e1;
     DECT_HIP(hipEventCreate(&e0));
     DECT_HIP(hipEventCreate(&e1));
     dect_status st = DECT_OK;
-    for (int g : options) {
-        b->group_choice = g;
-        if ((st = build_work(b))) break;
-        // warm-up run also builds the graph; then time `iters` iterations
-        if ((st = batch_run(b, mh, ml, 2, s))) break;
-        DECT_HIP(hipStreamSynchronize(s));
-        DECT_HIP(hipEventRecord(e0, s));
-        if ((st = batch_run(b, mh, ml, iters, s))) break;
-        DECT_HIP(hipEventRecord(e1, s));
-        DECT_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        DECT_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            best_g = g;
+    b->slice_groups.assign(b->n, 0);
+    b->adj_per_cu = 0;
+    b->fwd_per_cu = 0;
+    double best = 0.0;
+    for (int i = 0; i < b->n; ++i) b->slice_groups[i] = adj_groups(*b->t[i], 2);
+    st = time_shape(b, mh, ml, iters, s, e0, e1, &best);
+    for (size_t c = 0; c < classes.size() && !st; ++c) {
+        const std::vector<int> &mem = classes[c].second;
+        const int keep = b->slice_groups[mem[0]];
+        int best_g = keep;
+        for (int g : {1, 2, 4, 8, 16}) {
+            if (g == keep || g > std::max(1, b->host[mem[0]].V / 8)) continue;
+            for (int i : mem) b->slice_groups[i] = g;
+            double ms = 0.0;
+            if ((st = time_shape(b, mh, ml, iters, s, e0, e1, &ms))) break;
+            if (ms < best) {
+                best = ms;
+                best_g = g;
+            }
         }
+        for (int i : mem) b->slice_groups[i] = best_g;
+    }
+    for (int which = 0; which < 2 && !st; ++which) {
+        int &knob = which == 0 ? b->adj_per_cu : b->fwd_per_cu;
+        int best_k = knob;
+        for (int k : {1, 2}) {
+            knob = k;
+            double ms = 0.0;
+            if ((st = time_shape(b, mh, ml, iters, s, e0, e1, &ms))) break;
+            if (ms < best) {
+                best = ms;
+                best_k = k;
+            }
+        }
+        knob = best_k;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
-    b->group_choice = best_g;
+    b->tuned_from_cache = false;
     if ((st = build_work(b))) return st;
-    if (chosen) *chosen = best_g;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        TunedShape c;
+        c.shapes = shapes;
+        c.groups.resize(b->n);
+        for (int k = 0; k < b->n; ++k) c.groups[k] = b->slice_groups[order[k]];
+        c.adj_per_cu = b->adj_per_cu;
+        c.fwd_per_cu = b->fwd_per_cu;
+        c.ms = best;
+        g_tuned.push_back(std::move(c));
+    }
+    if (chosen) *chosen = b->slice_groups[big];
     if (ms_per_iter) *ms_per_iter = best / iters;
+    return DECT_OK;
+}
+
+dect_status batch_shape(const dect_batch *b, int32_t *groups, int32_t *adj_per_cu,
+                        int32_t *fwd_per_cu, int32_t *from_cache)
+{
+    if (!b) return fail(DECT_ERR_INVALID_ARG, "dect_batch_shape: batch is NULL");
+    if (groups)
+        for (int i = 0; i < b->n; ++i) groups[i] = b->host[i].nvg;
+    if (adj_per_cu) *adj_per_cu = b->adj_per_cu;
+    if (fwd_per_cu) *fwd_per_cu = b->fwd_per_cu;
+    if (from_cache) *from_cache = b->tuned_from_cache ? 1 : 0;
     return DECT_OK;
 }
 
@@ -511,6 +657,10 @@ dect_status batch_set_groups(dect_batch *b, int groups)
     if (!b || groups < 0 || groups > b->nvg_max)
         return fail(DECT_ERR_INVALID_ARG, "dect_batch_set_groups: 0 (heuristic) .. 16");
     b->group_choice = groups;
+    b->slice_groups.clear();
+    b->adj_per_cu = 0;
+    b->fwd_per_cu = 0;
+    b->tuned_from_cache = false;
     return build_work(b);
 }
 

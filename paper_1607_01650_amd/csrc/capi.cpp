@@ -27,6 +27,8 @@ dect_status adm_tv_batched(dect_batch *b, const float *const *mh, const float *c
 dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const *ml, int iters,
                        int32_t *chosen, double *ms_per_iter, hipStream_t s);
 dect_status batch_set_groups(dect_batch *b, int groups);
+dect_status batch_shape(const dect_batch *b, int32_t *groups, int32_t *adj_per_cu,
+                        int32_t *fwd_per_cu, int32_t *from_cache);
 
 // Bytes the 2-D calls allocate on geom when nothing is held yet: a dry run
 // of their allocations (tables, one ADM run without a caller state, the
@@ -93,6 +95,15 @@ dect_status dect_batch_set_groups(dect_batch *batch, int32_t groups)
 {
     dect::set_error("");
     return dect::batch_set_groups(batch, groups);
+}
+
+dect_status dect_batch_shape(const dect_batch *batch, int32_t *groups_per_slice,
+                             int32_t *adj_blocks_per_cu, int32_t *fwd_blocks_per_cu,
+                             int32_t *from_cache)
+{
+    dect::set_error("");
+    return dect::batch_shape(batch, groups_per_slice, adj_blocks_per_cu, fwd_blocks_per_cu,
+                             from_cache);
 }
 
 dect_status dect_project(const dect_geometry *geom, const float *d_img, float *d_sino,

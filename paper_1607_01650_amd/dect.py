@@ -118,6 +118,8 @@ SIGNATURES = {
                                        _P(ct.c_double), ct.c_void_p]),
     "dect_batch_tune": (ct.c_int, [ct.c_void_p, _P(ct.c_void_p), _P(ct.c_void_p), ct.c_int32,
                                    _P(ct.c_int32), _P(ct.c_double), ct.c_void_p]),
+    "dect_batch_shape": (ct.c_int, [ct.c_void_p, _P(ct.c_int32), _P(ct.c_int32), _P(ct.c_int32),
+                                    _P(ct.c_int32)]),
     "dect_batch_set_groups": (ct.c_int, [ct.c_void_p, ct.c_int32]),
     "dect_count_samples": (ct.c_int, [_P(dect_geometry), _P(ct.c_int64)]),
     "dect_release_caches": (ct.c_int, []),
@@ -534,6 +536,15 @@ class AdmBatch:
 
     def set_groups(self, groups: int):
         _check(lib().dect_batch_set_groups(self.handle, int(groups)), "dect_batch_set_groups")
+
+    def shape(self):
+        """(view-group depth per slice, adjoint blocks per CU, forward blocks
+        per CU, whether the last tune came from the process cache)."""
+        g = (ct.c_int32 * self.n)()
+        a, f, c = ct.c_int32(0), ct.c_int32(0), ct.c_int32(0)
+        _check(lib().dect_batch_shape(self.handle, g, ct.byref(a), ct.byref(f), ct.byref(c)),
+               "dect_batch_shape")
+        return list(g), int(a.value), int(f.value), bool(c.value)
 
     def close(self):
         if self.handle is not None and self.handle.value:

@@ -4,7 +4,10 @@
   bit for bit (same kernels bodies and reduction trees);
 * with any autotuned grouping it matches the FP64 oracle per slice
   (rel-L2 <= 1e-4) after the iterations;
-* the autotuner returns one of the offered groupings.
+* the autotuner returns one of the offered shapes, and a batch of the same
+  slice shapes takes the remembered choice without timing;
+* at the configuration's sizes (512 x 512 at 360 views, 384 x 384 at 90,
+  256 x 256 at 60) every slice matches the oracle after 200 iterations.
 """
 import numpy as np
 import pytest
@@ -67,7 +70,59 @@ def test_batch_autotune(torch):
     ml = [to_dev(torch, s.sino[1]) for _, s, _ in sl]
     b = dect.AdmBatch([g for g, _, _ in sl], [p for _, _, p in sl])
     groups, ms = b.tune(mh, ml, iters=4)
-    assert groups in (2, 4, 8, 16) and ms > 0
+    per_slice, adj_cu, fwd_cu, cached = b.shape()
+    print(f"tuned: depth per slice {per_slice}, adjoint blocks/CU {adj_cu}, forward {fwd_cu}, "
+          f"{ms:.3f} ms per iteration, cached {cached}", flush=True)
+    assert groups in (1, 2, 4, 8, 16) and ms > 0 and not cached
+    assert all(1 <= g <= max(1, gg.n_views // 8) or g == 1 for g, (gg, _, _) in zip(per_slice, sl))
+    assert adj_cu in (0, 1, 2) and fwd_cu in (0, 1, 2)
     xh, xl, obj = b.run(mh, ml, 6, want_objective=True)
     assert all(np.isfinite(o) for o in obj)
+    b.close()
+    # the same slice shapes in another order: the remembered shape, no timing
+    order = [4, 2, 0, 3, 1]
+    b2 = dect.AdmBatch([sl[i][0] for i in order], [sl[i][2] for i in order])
+    groups2, _ = b2.tune([mh[i] for i in order], [ml[i] for i in order], iters=4)
+    per2, adj2, fwd2, cached2 = b2.shape()
+    assert cached2 and groups2 == groups and (adj2, fwd2) == (adj_cu, fwd_cu)
+    assert per2 == [per_slice[i] for i in order]
+    b2.close()
+
+
+def test_batch_paper_scale_parity(torch):
+    """A batch of the configuration's sizes: a 512 x 512 slice at 360 views
+    (the stored FP64 oracle run of slice 0, 200 iterations), a 384 x 384 slice
+    at 90 views and a 256 x 256 slice at 60 views (the oracle run live), all
+    advanced together for 200 iterations with the built-in grouping and with
+    a tuned one; every image within rel-L2 1e-4 of the oracle."""
+    import os
+    from paper_1607_01650_amd import dect
+    g512 = C.paper_geometry(512, 360)
+    g384 = C.paper_geometry(384, 90)
+    g256 = C.paper_geometry(256, 60)
+    geoms = [g384, g512, g256]
+    sl = [P.make_slice(g384, 7), P.make_slice(g512, 0), P.make_slice(g256, 8)]
+    params = [C.default_adm_params(g, 200) for g in geoms]
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "adm512_v360_k200.npz"))
+    assert float(gold["mu"]) == params[1].mu
+    refs = {}
+    for i in (0, 2):
+        p = params[i]
+        refs[i] = [O.adm(geoms[i], f32(sl[i].sino[e]), beta, p.mu, p.rho, p.xi, 200).x
+                   for e, beta in ((0, p.beta_high), (1, p.beta_low))]
+    refs[1] = [gold["x"][0], gold["x"][1]]
+    mh = [to_dev(torch, s.sino[0]) for s in sl]
+    ml = [to_dev(torch, s.sino[1]) for s in sl]
+    b = dect.AdmBatch(geoms, params)
+    for label in ("built-in", "tuned"):
+        if label == "tuned":
+            groups, ms = b.tune(mh, ml, iters=4)
+            print(f"tuned grouping {groups}, {ms:.3f} ms per iteration", flush=True)
+        xh, xl, _ = b.run(mh, ml, 200)
+        for i, g in enumerate(geoms):
+            for e, x in enumerate((xh[i], xl[i])):
+                err = rel_l2(to_np(x), refs[i][e])
+                print(f"batch {label} {g.nx}x{g.ny} V={g.n_views} energy {e}: rel-L2 {err:.2e}",
+                      flush=True)
+                assert err <= 1e-4
     b.close()
