@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--batch-slices", type=int, default=64,
                     help="slices of the batched multi-slice entry (0: skip)")
     ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--unet-steps", type=int, default=5,
+                    help="timed training steps / inferences of the U-Net entry (0: skip)")
     ap.add_argument("--unrolled-steps", type=int, default=3,
                     help="timed training steps of the unrolled-ADM entry (0: skip)")
     ap.add_argument("--siddon-steps", type=int, default=100,
@@ -213,6 +215,7 @@ def main():
     warm = warm_start_extra(args.warm_cases)
     batched = batched_extra(args.batch_slices, args.batch_iters) if args.batch_slices > 0 else None
     unrolled = unrolled_extra(args.unrolled_steps) if args.unrolled_steps > 0 else None
+    unet = unet_extra(args.unet_steps) if args.unet_steps > 0 else None
     siddon = (siddon_extra(args.siddon_steps, args.kernel_launches)
               if args.siddon_steps > 0 else None)
     fbp = None if args.no_fbp else fbp_extra(max(1, args.kernel_launches))
@@ -260,7 +263,7 @@ def main():
                   "wall_s_timed": round(wall, 4),
                   "pls_ms": round(pls_ms, 3), "pls_pcg_iters": prep.iters,
                   "pls_attenuation_ms": round(pls_att_ms, 3), "pls_attenuation_iters": arep.iters,
-                  "warm_start": warm, "batched": batched, "unrolled": unrolled,
+                  "warm_start": warm, "batched": batched, "unrolled": unrolled, "unet": unet,
                   "siddon": siddon, "fbp": fbp, "nonneg": nonneg, "coupled_tv": coupled,
                   "abb_step": abb, "cone": cone, "adm3": adm3},
     }
@@ -573,6 +576,51 @@ def batched_extra(n_slices: int, iters: int):
             "ms_per_iteration_all_slices": round(1e3 * t_batch / iters, 3),
             "sequential_slice_iters_per_s": round(n_slices * iters / t_seq, 1),
             "speedup_vs_sequential": round(t_seq / t_batch, 3)}
+
+
+def unet_extra(steps: int, batch: int = 8):
+    """The learned warm start's network on the BF16 MFMA kernels: one training
+    step (forward, MSE, backward, Adam) on a batch of 8 2-channel 512 x 512
+    images, and one inference of one image; convolution flops per second."""
+    import torch
+    from paper_1607_01650_amd import nn as NN
+    net = NN.UNet(seed=0)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    f = torch.rand((batch, 2, 512, 512), device="cuda", generator=gen) * 0.05
+    x, base = NN.pack_input(f[:, 0], f[:, 1])
+    tgt = (f.permute(0, 2, 3, 1) * NN.SCALE).contiguous()
+
+    def train_step():
+        r = net.forward(x, keep=True)
+        y = (base + r).contiguous()
+        dy = torch.empty_like(y)
+        NN.mse(y, tgt, dy)
+        net.backward(dy)
+        net.adam_step(1e-4)
+
+    for _ in range(2):
+        train_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        train_step()
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / steps
+    x1 = x[:1].contiguous()
+    for _ in range(2):
+        net.forward(x1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(x1)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / steps
+    fl = net.conv_flops(512, 512)
+    return {"workload": f"U-Net {NN.CH}, batch {batch} x 2 x 512x512, BF16 MFMA",
+            "train_step_ms": round(1e3 * t_train, 3), "infer_ms_1image": round(1e3 * t_inf, 3),
+            "conv_gflop_fwd_per_image": round(fl / 1e9, 2),
+            "train_conv_tflops": round(3 * fl * batch / t_train / 1e12, 2),
+            "infer_conv_tflops": round(fl / t_inf / 1e12, 2)}
 
 
 def unrolled_extra(steps: int, batch: int = 8):

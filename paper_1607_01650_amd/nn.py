@@ -258,6 +258,24 @@ class UNet:
     def n_params(self) -> int:
         return sum(c.n_params() for c in self.layers())
 
+    def conv_flops(self, H: int, W: int) -> int:
+        """Multiply-add work of the convolutions in one forward pass of one
+        H x W image, counted as 2 flops per multiply-add (the backward pass
+        does the same work twice more: input and weight gradients)."""
+        res = [(H >> l) * (W >> l) for l in range(4)]
+        total = 0
+        for lvl in range(4):
+            for c in self.enc[lvl]:
+                total += 2 * res[lvl] * c.k * c.k * c.cin * c.cout
+        for j, lvl in enumerate((3, 2, 1)):   # up[j] reads level 3 - j
+            c = self.up[j]
+            total += 2 * res[lvl] * c.cin * c.cout
+        for j, lvl in enumerate((2, 1, 0)):
+            for c in self.dec[j]:
+                total += 2 * res[lvl] * c.k * c.k * c.cin * c.cout
+        total += 2 * res[0] * self.out.cin * self.out.cout
+        return total
+
     # forward keeps what the backward pass needs
     def forward(self, x, keep: bool = False):
         """x [N,H,W,8] bf16 (H, W divisible by 8) -> residual [N,H,W,8] f32."""
