@@ -8,15 +8,17 @@ with 0.5 % Gaussian noise) are resident in HBM before timing starts.
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (the gather back-projection, timed with HIP events on the stream it
-is launched on) and the FP64 CPU oracle timed on a bounded sample.
+is launched on, set against the VALU issue peak with its instruction count
+from rocprofv3 counters) and the FP64 CPU oracle timed on a bounded sample.
 
 Other modes (for hardware-counter runs under rocprofv3, one GPU):
   --mode projectors   only the back- and forward-projection launches of the
                       roofline entry (same inputs and launch configuration)
   --mode copy         device-to-device copies of --copy-mb MiB: a kernel of
                       known traffic that calibrates FETCH_SIZE / WRITE_SIZE
-  --mode traffic      reads the counter CSVs of those runs (--pmc-dir) and
-                      writes profiles/adjoint_traffic.json (no GPU needed)
+  --mode counters     reads the counter CSVs of those runs (--pmc-dir) and
+                      writes profiles/adm_tv_512x512_360v_counters.json
+                      (no GPU needed)
 """
 from __future__ import annotations
 
@@ -94,10 +96,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-launches", type=int, default=50)
-    ap.add_argument("--mode", choices=["metric", "projectors", "copy", "traffic", "cone"],
+    ap.add_argument("--mode", choices=["metric", "projectors", "copy", "counters", "cone"],
                     default="metric")
     ap.add_argument("--copy-mb", type=int, default=512)
-    ap.add_argument("--pmc-dir", default="pmc", help="directory of the FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--pmc-dir", default="pmc", help="directory of the counter runs (--mode counters)")
     ap.add_argument("--warm-cases", type=int, default=4,
                     help="held-out cases for the learned-warm-start time-to-tol entry")
     ap.add_argument("--batch-slices", type=int, default=64,
@@ -119,8 +121,8 @@ def main():
     ap.add_argument("--adm3-iters", type=int, default=6,
                     help="iterations of the 3-D ADM entry (0: skip; at least 2)")
     args = ap.parse_args()
-    if args.mode == "traffic":
-        return traffic_summary(args.pmc_dir)
+    if args.mode == "counters":
+        return counters_summary(args.pmc_dir)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the whole path on a single MI355X "
               "(multi-GPU sharding is described, not built); use --gpus 1", file=sys.stderr)
@@ -181,7 +183,6 @@ def main():
     S = dect.count_samples(g)
     M, N = g.n_views * g.n_bins, g.nx * g.ny
     adj_bytes = 2 * (8 * S + 4 * M + 4 * N)
-    achieved = adj_bytes / (adj_ms / 1e3) / 1e9
 
     # forward projection of both energies for context
     x = torch.randn((2, g.ny, g.nx), device="cuda")
@@ -225,15 +226,7 @@ def main():
     cone = cone_extra(args.cone_launches) if args.cone_launches > 0 else None
     adm3 = adm3_extra(max(2, args.adm3_iters)) if args.adm3_iters > 0 else None
 
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
-    if os.path.exists(tfile):
-        try:
-            tinfo = json.load(open(tfile))
-            if tinfo.get("kernel_hash") == _kernel_hash():
-                traffic = tinfo.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    roofline = adjoint_roofline(adj_ms, adj_bytes)
 
     out = {
         "metric": "ADM-TV iters/s at 512x512 x 360 views x 2 energies",
@@ -251,12 +244,7 @@ def main():
         "config": {"workload": "adm_tv_512x512_360views_736bins_2energies", "image": 512,
                    "views": 360, "bins": 736, "energies": 2, "sod_mm": g.sod_mm,
                    "sdd_mm": g.sdd_mm, "mu": p.mu, "rho": p.rho, "xi": p.xi},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "k_adj + k_adj_sum (gather back-projection, 2 energies)",
-                     "avg_launch_us": round(adj_ms * 1e3, 2),
-                     "algorithmic_bytes": adj_bytes},
+        "roofline": roofline,
         "extra": {"fwd_projection_us_2energies": round(fwd_ms * 1e3, 2),
                   "samples_per_projection": S,
                   "ray_updates_per_s": round(4 * S * iters_per_s, 1),
@@ -270,6 +258,50 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, s.sino, p)
     print(json.dumps(out), flush=True)
+
+
+def adjoint_roofline(adj_ms: float, adj_bytes: int):
+    """The roofline entry of the dominant kernel, the gather back-projection
+    of both energies (k_adj + k_adj_sum, one dect_backproject launch).
+
+    Its operands come from LDS and L2 (HBM carries a few percent of its
+    algorithmic bytes), and what binds it is instruction issue: the entry
+    sets the wave-level VALU instructions of one launch (counted by rocprofv3,
+    profiles/adm_tv_512x512_360v_counters.json, valid while the kernel sources
+    hash the same) over the launch time measured here against the VALU issue
+    peak (VALU_PEAK_GINST).  The measured HBM bytes of a launch (the same
+    counter file) give `traffic` and the HBM fraction; the algorithmic bytes
+    (8 B per Joseph sample per image + 4 B per ray + 4 B per pixel) over the
+    launch time give the effective gather bandwidth."""
+    t = adj_ms / 1e3
+    eff = adj_bytes / t / 1e9
+    roof = {"bound": "alu", "achieved": None, "peak": round(VALU_PEAK_GINST, 1),
+            "unit": "Ginst/s", "frac": None, "traffic": None,
+            "kernel": "k_adj + k_adj_sum (gather back-projection, 2 energies)",
+            "avg_launch_us": round(adj_ms * 1e3, 2), "algorithmic_bytes": adj_bytes,
+            "effective_gbs": round(eff, 1), "effective_over_hbm_peak": round(eff / HBM_PEAK_GBS, 3),
+            "counters": None}
+    cfile = os.path.join(ROOT, "profiles", "adm_tv_512x512_360v_counters.json")
+    try:
+        info = json.load(open(cfile))
+    except Exception:
+        return roof
+    if info.get("kernel_hash") != _counter_sources_hash():
+        roof["counters"] = "stale (kernel sources changed since the counter runs)"
+        return roof
+    k = info["kernels"]
+    a, s_ = k["k_adj"], k["k_adj_sum"]
+    valu = a["SQ_INSTS_VALU"] + s_["SQ_INSTS_VALU"]
+    traffic = (a["hbm_read_bytes"] + a["hbm_write_bytes"] + s_["hbm_read_bytes"] +
+               s_["hbm_write_bytes"])
+    achieved = valu / t / 1e9
+    roof.update(achieved=round(achieved, 1), frac=round(achieved / VALU_PEAK_GINST, 4),
+                traffic=round(traffic), counters=os.path.relpath(cfile, ROOT),
+                valu_instr_per_launch=valu,
+                hbm_gbs=round(traffic / t / 1e9, 1),
+                hbm_frac=round(traffic / t / 1e9 / HBM_PEAK_GBS, 4),
+                lds_instr_per_launch=a["SQ_INSTS_LDS"] + s_["SQ_INSTS_LDS"])
+    return roof
 
 
 def siddon_extra(steps: int, launches: int):
@@ -663,16 +695,6 @@ def unrolled_extra(steps: int, batch: int = 8):
             "ms_per_train_step": round(ms, 2), "loss_mse": last}
 
 
-def _kernel_hash() -> str:
-    """Hash of the projector sources: counter-derived traffic is only reported
-    for the kernels it was measured on."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in ("projector.hip", "proj_device.h", "common.h"):
-        h.update(open(os.path.join(ROOT, "paper_1607_01650_amd", "csrc", name), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def projector_launches(k: int):
     """The roofline entry's projector launches alone (for counter runs), with
     their average HIP-event time per launch."""
@@ -704,7 +726,7 @@ def projector_launches(k: int):
                       "backproject_us": round(1e3 * ev.ms(a0, a1) / k, 2),
                       "project_us": round(1e3 * ev.ms(f0, f1) / k, 2),
                       "algorithmic_bytes_per_launch": 2 * (8 * S + 4 * M + 4 * N),
-                      "kernel_hash": _kernel_hash()}), flush=True)
+                      "kernel_hash": _counter_sources_hash()}), flush=True)
 
 
 def copy_probe(mb: int, k: int):
@@ -734,9 +756,42 @@ def _pmc_rows(path: str):
     return out
 
 
-def traffic_summary(pmc_dir: str):
-    """HBM bytes per back-projection launch from FETCH_SIZE / WRITE_SIZE runs,
-    each scaled by what the same counter reads for the copy kernel."""
+# Kernels of one ADM-TV iteration (and the bench's standalone projector
+# launches) that the counter summary follows: label -> name test.
+COUNTER_KERNELS = {
+    "k_adj": lambda n: re.search(r"k_adj<", n) is not None,
+    "k_adj_sum": lambda n: "k_adj_sum" in n,
+    "k_fwd (ADM, residual fused)": lambda n: re.search(r"k_fwd<true", n) is not None,
+    "k_fwd (plain)": lambda n: re.search(r"k_fwd<false", n) is not None,
+    "k_tv_fused": lambda n: "k_tv_fused" in n,
+    "k_scalar": lambda n: re.search(r"k_scalar\b", n) is not None and "k_scalar3" not in n,
+    "k_update": lambda n: re.search(r"k_update\b", n) is not None,
+}
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
+               "SQ_INSTS_VMEM_WR", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES"]
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a wave64 VALU instruction occupies a
+# 16-lane SIMD for 4 cycles, so each CU issues at most one wave-level VALU
+# instruction per cycle
+VALU_PEAK_GINST = 256 * 2.4
+
+
+def _counter_sources_hash() -> str:
+    """Hash of the sources of the kernels the counter summary covers."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("projector.hip", "proj_device.h", "common.h", "adm.hip", "adm_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1607_01650_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counters_summary(pmc_dir: str):
+    """Per-dispatch counters (median over the dispatches of each kernel) of
+    the ADM-TV iteration's kernels from the counter runs under pmc_dir: sq/
+    (SQ_COUNTERS), fetch/ and write/ (FETCH_SIZE, WRITE_SIZE), and the copy
+    calibration (copy_fetch/, copy_write/, copy_meta.json).  HBM bytes are the
+    counters scaled by what they read for a device copy of known size.
+    Writes profiles/adm_tv_512x512_360v_counters.json and prints the table
+    of profiles/adm_tv_512x512_360v_counters.md."""
     import glob
     import statistics
 
@@ -747,37 +802,53 @@ def traffic_summary(pmc_dir: str):
             raise SystemExit(f"no counter CSV under {pmc_dir}/{tag}")
         return _pmc_rows(files[0])
 
-    def per_dispatch(rows, match, counter):
+    def med(rows, match, counter):
         vals = []
         for (name, cname), d in rows.items():
             if cname == counter and match(name):
                 vals += list(d.values())
-        return statistics.median(vals) if vals else None, len(vals)
+        return (statistics.median(vals), len(vals)) if vals else (None, 0)
 
-    res = {}
-    for counter, tag in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        copy_rows = load(f"copy_{tag}")
-        proj_rows = load(f"proj_{tag}")
-        is_copy = lambda n: "copy" in n.lower() or "elementwise" in n.lower()
-        ck, nc = per_dispatch(copy_rows, is_copy, counter)
-        # k_adj (any template instance), not k_adj_sum; demangled or mangled
-        is_adj = lambda n: re.search(r"k_adj(<[^>]*>)?\(|\d+k_adj[IE]", n) is not None
-        adj, na = per_dispatch(proj_rows, is_adj, counter)
-        asum, ns = per_dispatch(proj_rows, lambda n: "k_adj_sum" in n, counter)
-        meta = json.load(open(os.path.join(pmc_dir, "copy_meta.json")))
-        true_bytes = meta["bytes_read"] if counter == "FETCH_SIZE" else meta["bytes_written"]
-        factor = ck * 1024.0 / true_bytes
-        res[counter] = {"copy_kib": ck, "copy_true_bytes": true_bytes, "factor": factor,
-                        "k_adj_kib": adj, "k_adj_sum_kib": asum,
-                        "bytes_per_launch": (adj + asum) * 1024.0 / factor,
-                        "dispatches": [nc, na, ns]}
-    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
-    out = {"kernel_hash": _kernel_hash(), "bytes_per_launch": round(total),
-           "counters": res, "pmc_dir": pmc_dir}
-    path = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
-    with open(path, "w") as f:
-        json.dump(out, f, indent=1)
-    print(json.dumps(out), flush=True)
+    meta = json.load(open(os.path.join(pmc_dir, "copy_meta.json")))
+    is_copy = lambda n: "copy" in n.lower() or "elementwise" in n.lower()
+    factor = {}
+    for counter, tag, true_bytes in (("FETCH_SIZE", "copy_fetch", meta["bytes_read"]),
+                                     ("WRITE_SIZE", "copy_write", meta["bytes_written"])):
+        kib, _ = med(load(tag), is_copy, counter)
+        factor[counter] = kib * 1024.0 / true_bytes
+    sq, fetch, write = load("sq"), load("fetch"), load("write")
+    kernels = {}
+    for label, match in COUNTER_KERNELS.items():
+        row = {}
+        for c in SQ_COUNTERS:
+            v, n = med(sq, match, c)
+            row[c] = v
+            row["dispatches"] = max(row.get("dispatches", 0), n)
+        f, _ = med(fetch, match, "FETCH_SIZE")
+        w, _ = med(write, match, "WRITE_SIZE")
+        row["hbm_read_bytes"] = None if f is None else f * 1024.0 / factor["FETCH_SIZE"]
+        row["hbm_write_bytes"] = None if w is None else w * 1024.0 / factor["WRITE_SIZE"]
+        if row.get("SQ_WAVES"):
+            row["valu_per_wave"] = row["SQ_INSTS_VALU"] / row["SQ_WAVES"]
+            row["lds_per_wave"] = row["SQ_INSTS_LDS"] / row["SQ_WAVES"]
+        kernels[label] = row
+    out = {"kernel_hash": _counter_sources_hash(), "copy_factor": factor, "kernels": kernels,
+           "pmc_dir": pmc_dir}
+    base = os.path.join(ROOT, "profiles", "adm_tv_512x512_360v_counters")
+    with open(base + ".json", "w") as fh:
+        json.dump(out, fh, indent=1)
+    lines = ["| kernel | dispatches | waves | VALU instr / wave | LDS instr / wave | VALU instr "
+             "per dispatch | HBM read MB | HBM write MB |", "|---|---|---|---|---|---|---|---|"]
+    for label, r in kernels.items():
+        if not r.get("SQ_WAVES"):
+            continue
+        lines.append(f"| `{label}` | {r['dispatches']} | {r['SQ_WAVES']:.0f} | "
+                     f"{r['valu_per_wave']:.0f} | {r['lds_per_wave']:.0f} | "
+                     f"{r['SQ_INSTS_VALU']:.4g} | "
+                     f"{(r['hbm_read_bytes'] or 0) / 1e6:.1f} | "
+                     f"{(r['hbm_write_bytes'] or 0) / 1e6:.1f} |")
+    print("\n".join(lines), flush=True)
+
 
 
 if __name__ == "__main__":
