@@ -537,6 +537,7 @@ def warm_start_extra(n: int):
     ok = [r for r in rows if r["k_cont"] >= 0]
     med = lambda a: float(np.median(a)) if len(a) else None
     return {"workload": "512x512, 90 views, 736 bins, 2 energies; J_ref = J(plain f^200)",
+            "record_200_cases": "profiles/warmstart_eval_512x512_90v.md",
             "cases": n, "reached": len(ok),
             "median_iters_plain": med([r["k_plain"] for r in rows]),
             "median_iters_learned": med([W.EARLY + r["k_cont"] for r in ok]),

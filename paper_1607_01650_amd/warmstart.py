@@ -285,7 +285,10 @@ def summarize(rows) -> Dict:
     it_l = np.array([EARLY + r["k_cont"] for r in ok])
     it_p = np.array([r["k_plain"] for r in ok])
     med = lambda a: float(np.median(a)) if len(a) else float("nan")
+    fb = [r for r in rows if r.get("k_fbp", -1) >= 0 and np.isfinite(r.get("t_fbp_ms", np.nan))]
     return {
+        "fbp": {"reached": len(fb),
+                "median_time_ratio": med([r["t_fbp_ms"] / r["t_plain_ms"] for r in fb])},
         "n": len(rows), "reached": len(ok),
         "median_k_plain": med([r["k_plain"] for r in rows]),
         "median_iters_learned": med(it_l),
@@ -304,21 +307,76 @@ def summarize(rows) -> Dict:
     }
 
 
-def save_weights(net: NN.UNet, path: str):
-    sd = net.state_dict()
+def save_weights(net: NN.UNet, path: str, optimizer: bool = True):
+    """FP32 master weights and biases; with optimizer, also the Adam moments
+    and step count, so that training can resume exactly where it stopped."""
     arrs = {}
-    for k, (w, b) in sd.items():
-        arrs[k + "_w"] = w.numpy()
-        arrs[k + "_b"] = b.numpy()
+    for i, c in enumerate(net.layers()):
+        arrs[f"l{i}_w"] = c.w.cpu().numpy()
+        arrs[f"l{i}_b"] = c.b.cpu().numpy()
+        if optimizer:
+            arrs[f"l{i}_mw"] = c.mw.cpu().numpy()
+            arrs[f"l{i}_vw"] = c.vw.cpu().numpy()
+            arrs[f"l{i}_mb"] = c.mb.cpu().numpy()
+            arrs[f"l{i}_vb"] = c.vb.cpu().numpy()
+    if optimizer:
+        arrs["adam_step"] = np.array(net.step, dtype=np.int64)
     np.savez(path, **arrs)
 
 
 def load_weights(net: NN.UNet, path: str):
+    """Weights (and the Adam state when the file holds it) saved by save_weights."""
     z = np.load(path, allow_pickle=False)
     sd = {}
     for i, _ in enumerate(net.layers()):
         sd[f"l{i}"] = (torch.as_tensor(z[f"l{i}_w"]), torch.as_tensor(z[f"l{i}_b"]))
     net.load_state_dict(sd)
+    if "adam_step" in z.files:
+        for i, c in enumerate(net.layers()):
+            c.mw.copy_(torch.as_tensor(z[f"l{i}_mw"]))
+            c.vw.copy_(torch.as_tensor(z[f"l{i}_vw"]))
+            c.mb.copy_(torch.as_tensor(z[f"l{i}_mb"]))
+            c.vb.copy_(torch.as_tensor(z[f"l{i}_vb"]))
+        net.step = int(z["adam_step"])
+
+
+def summary_markdown(out: Dict, command: str) -> str:
+    """A short text record of an evaluation: the figures, not the rows."""
+    ev = out["eval"]
+    lo, hi = ev["p10_p90_time_ratio"] or (float("nan"), float("nan"))
+    lines = [
+        f"# Learned warm start: time to the plain method's objective, {ev['n']} held-out phantoms",
+        "",
+        "Command (from the repository root, one MI355X):",
+        "",
+        f"    {command}",
+        "",
+        f"Workload: {out['workload']}; held-out phantoms (seeds {EVAL_SEED0} .. "
+        f"{EVAL_SEED0 + ev['n'] - 1}, never seen in training); J_ref = J(plain f^{LATE}) per "
+        "phantom (Eq. 4, both energies).  Plain: ADM-TV until J <= J_ref.  Learned: "
+        f"{EARLY} plain iterations, the U-Net, the start check, then ADM-TV until J <= J_ref; "
+        "a start that is not finite or whose objective exceeds J(f^5) falls back to the "
+        "plain run resumed at f^5.  Wall times are medians of repeated runs on the GPU.",
+        "",
+        "| figure | value |",
+        "|---|---|",
+        f"| cases / reached J_ref | {ev['n']} / {ev['reached']} |",
+        f"| starts from the network / fallbacks | {ev['starts'].get('net', 0)} / {ev['fallbacks']} |",
+        f"| median plain iterations | {ev['median_k_plain']:.0f} |",
+        f"| median learned iterations (5 + continuation) | {ev['median_iters_learned']:.0f} |",
+        f"| median plain time | {ev['median_t_plain_ms']:.2f} ms |",
+        f"| median learned time (incl. network and check) | {ev['median_t_learned_ms']:.2f} ms |",
+        f"| median network start (5 iterations + U-Net) | {ev['median_t_start_ms']:.2f} ms |",
+        f"| median time ratio learned / plain | {ev['median_time_ratio']:.3f} |",
+        f"| p10 - p90 time ratio | {lo:.3f} - {hi:.3f} |",
+        f"| learned faster than plain | {100 * ev['frac_faster']:.1f} % of cases |",
+        f"| median iterations saved | {ev['iters_saved_median']:.0f} |",
+    ]
+    if "fbp" in ev:
+        f = ev["fbp"]
+        lines.append(f"| FBP start: reached / median time ratio | {f['reached']} / "
+                     f"{f['median_time_ratio']:.3f} |")
+    return "\n".join(lines) + "\n"
 
 
 def main(argv=None):
@@ -335,6 +393,7 @@ def main(argv=None):
     ap.add_argument("--weights-in", default=None)
     ap.add_argument("--weights-out", default=None)
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--md-out", default=None, help="short text record of the evaluation")
     a = ap.parse_args(argv)
     geom = C.paper_geometry(a.size, a.views)
     net = NN.UNet(seed=0)
@@ -364,6 +423,12 @@ def main(argv=None):
     if a.json_out:
         with open(a.json_out, "w") as f:
             json.dump(out, f, indent=1)
+    if a.md_out and "eval" in out:
+        import sys
+        cmd = "python -m paper_1607_01650_amd.warmstart " + " ".join(argv if argv is not None
+                                                                     else sys.argv[1:])
+        with open(a.md_out, "w") as f:
+            f.write(summary_markdown(out, cmd))
 
 
 if __name__ == "__main__":

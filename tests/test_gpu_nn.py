@@ -198,3 +198,38 @@ def test_unet_learns(torch):
         net.backward(dy)
         net.adam_step(2e-3)
     assert losses[-1] < 0.2 * losses[0], losses[::8]
+
+
+def test_checkpoint_resumes_training_exactly(torch, tmp_path):
+    """Weights saved with the Adam moments and step, loaded into a network of
+    other initial weights: one more training step on both gives the same
+    weights bit for bit (the checkpoint holds the whole training state)."""
+    from paper_1607_01650_amd import nn as NN
+    from paper_1607_01650_amd import warmstart as W
+    ch = (8, 16, 16, 24)
+    rng = np.random.default_rng(21)
+    f = torch.as_tensor(rng.uniform(0, 0.05, (2, 2, 32, 64)), dtype=torch.float32).cuda()
+    x, base = NN.pack_input(f[:, 0], f[:, 1])
+    tgt = (f.permute(0, 2, 3, 1) * NN.SCALE).contiguous()
+
+    def step(net):
+        r = net.forward(x, keep=True)
+        y = (base + r).contiguous()
+        dy = torch.empty_like(y)
+        NN.mse(y, tgt, dy)
+        net.backward(dy)
+        net.adam_step(1e-3)
+
+    a = NN.UNet(seed=3, ch=ch)
+    for _ in range(3):
+        step(a)
+    path = str(tmp_path / "ckpt.npz")
+    W.save_weights(a, path)
+    b = NN.UNet(seed=4, ch=ch)
+    W.load_weights(b, path)
+    assert b.step == a.step == 3
+    step(a)
+    step(b)
+    for ca, cb in zip(a.layers(), b.layers()):
+        assert torch.equal(ca.w, cb.w) and torch.equal(ca.b, cb.b)
+        assert torch.equal(ca.mw, cb.mw) and torch.equal(ca.vw, cb.vw)
