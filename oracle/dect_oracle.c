@@ -1043,7 +1043,7 @@ void or_gradT3(int nx, int ny, int nz, const double *g3, double *out)
 /* m [V][J][B] projections of one energy; x_out [nz][ny][nx] = f / beta;
  * log [(K+1)][5] as in or_adm. */
 int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double rho, double xi,
-            int K, double *x_out, double *log)
+            int K, double tol, const double *x0, double *x_out, double *log)
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
     const size_t N = (size_t)nx * ny * nz;
@@ -1056,6 +1056,8 @@ int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double r
     }
     double *gs = calloc(M, 8), *r = calloc(M, 8), *p = calloc(M, 8);
     for (size_t j = 0; j < M; ++j) gs[j] = beta * m[j];
+    if (x0)  /* warm start f = beta x0; lambda = 0 either way */
+        for (size_t i = 0; i < N; ++i) f[i] = beta * x0[i];
     or_project3(g, f, r);
     for (size_t j = 0; j < M; ++j) r[j] -= gs[j];
     or_backproject3(g, r, h);
@@ -1118,6 +1120,10 @@ int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double r
         grad3(nx, ny, nz, f, d[0], d[1], d[2]);
         for (int a = 0; a < 3; ++a)
             for (size_t i = 0; i < N; ++i) l[a][i] -= xi * (d[a][i] - z[a][i]);
+        if (tol > 0.0 && relchg < tol) {  /* the stop rule of Sec. 3 */
+            ++k;
+            break;
+        }
     }
     if (log) {
         grad3(nx, ny, nz, f, d[0], d[1], d[2]);

@@ -47,6 +47,37 @@ def test_single_slice_is_the_fan_beam_run():
     assert np.allclose(log3[:, 1], r2.log[:41, 1], rtol=1e-9, atol=0)
 
 
+def test_single_slice_warm_start_and_stop_rule_match_the_fan_beam_run():
+    """With a start image and a tolerance the one-slice run still equals the
+    pinned 2-D ADM: same start f = beta x0, same stopping iteration."""
+    g3 = C.ConeGeometry(nx=16, ny=16, nz=1, voxel_mm=1.0, n_views=20, n_bins=26, n_rows=1,
+                        bin_mm=1.4, row_mm=1.0, sod_mm=70.0, sdd_mm=140.0)
+    g2 = g3.central_plane()
+    rng = np.random.default_rng(3)
+    m = rng.random((g3.n_views, 1, g3.n_bins)) * 4.0
+    x0 = rng.random((1, 16, 16))
+    x3, log3, k3 = O.adm3(g3, m, 1.1, 0.6, 16.0, 4.0, 400, tol=1e-3, x0=x0, with_iters=True)
+    r2 = O.adm(g2, m[:, 0, :], 1.1, 0.6, 16.0, 4.0, 400, tol=1e-3, x0=x0[0])
+    assert 1 < k3 < 400 and k3 == r2.iters
+    assert np.abs(x3[0] - r2.x).max() <= 1e-9 * np.abs(r2.x).max()
+    assert np.allclose(log3[:k3 + 1, 0], r2.log[:k3 + 1, 0], rtol=1e-9, atol=0)
+    # the stop is the first iteration whose relative change (column 3, the
+    # change of the step that ends before the row) falls below tol
+    assert log3[k3, 3] < 1e-3 and np.all(log3[1:k3, 3] >= 1e-3)
+
+
+def test_warm_start_from_a_constant_consistent_volume_is_a_fixed_point():
+    """A constant volume has zero TV; with data that volume projects to, the
+    start is a minimiser of Eq. 4, so the first step changes nothing (the
+    gradient of Eq. 10 vanishes there with lambda = 0 and z = grad f = 0)."""
+    g = SMALL3
+    x0 = np.full((g.nz, g.ny, g.nx), 0.37)
+    m = O.project3(g, x0)
+    x, log, k = O.adm3(g, m, 1.0, 0.8, 16.0, 4.0, 3, tol=1e-12, x0=x0, with_iters=True)
+    assert np.abs(x - x0).max() <= 1e-12
+    assert log[0, 0] <= 1e-20 and log[1, 3] <= 1e-14 and k == 1
+
+
 def test_zero_data_stays_zero():
     x, log = O.adm3(SMALL3, np.zeros((8, 5, 12)), 1.0, 1.0, 16.0, 4.0, 5)
     assert not np.any(x) and not np.any(log[:, 0])
