@@ -356,15 +356,24 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
  * over backward differences along x, y and z -- the six-neighbour form --
  * and the isotropic shrinkage of Eq. 8 on the 3-vector), with A the
  * cone-beam pair above.  d_m_* [n_views][n_rows][n_bins] device, d_x_*
- * [nz][ny][nx] device outputs (x = f / beta).  params as for dect_adm_tv
- * except: flags must be 0 (zero start, BB1 step; else DECT_ERR_INVALID_ARG)
- * and tol must be 0 (fixed iteration count); params->log, when not NULL,
- * receives the [max_iter+1][4] rows {J_high, J_low, alpha_high, alpha_low}.
+ * [nz][ny][nx] device outputs (x = f / beta), and with DECT_WARM_START
+ * also the start images (f = beta x; they may be the same buffers).  params
+ * as for dect_adm_tv except that flags may hold DECT_WARM_START only (BB1
+ * step, per-energy TV; else DECT_ERR_INVALID_ARG) and tol must be finite
+ * and >= 0.  tol > 0: each energy stops after the first iteration whose
+ * relative change |f^{k+1}-f^k| / |f^k| is below tol, the other running on
+ * until it stops too or max_iter is reached (the host reads both relative
+ * changes after every iteration, one stream synchronisation each).
+ * params->log, when not NULL, receives the [max_iter+1][4] rows {J_high,
+ * J_low, alpha_high, alpha_low}; an energy's rows after its last iteration
+ * hold zeros.  rep->iters is the larger of the two iteration counts.
  * The two energies advance together (each with its own step), every
- * projector call walking both volumes at once; state in FP32, reductions in
- * FP64.  Its work buffers (per energy about 12 volumes and 2 projection
- * sets) are library-owned per device and kept between calls; the call
- * synchronises the stream before returning.
+ * projector call walking both volumes at once.  The iterate and the
+ * residual A f - beta m are pairs of FP32 values updated in FP64 (the
+ * residual by the recurrence r -= alpha A G), the rest of the state FP32,
+ * reductions FP64.  Its work buffers (per energy 13 volumes and 4
+ * projection sets) are library-owned per device and kept between calls;
+ * the call synchronises the stream before returning.
  * DECT_ERR_NONFINITE when a logged objective or step is not finite.
  */
 dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,

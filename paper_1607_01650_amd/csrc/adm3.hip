@@ -3,24 +3,33 @@
 // deferred multiplier step of Eq. 7 and the BB1 step of Eq. 9), with the
 // cone-beam projector pair as A.  The two energies advance together (each
 // with its own state, step and partial sums) so that every projector call
-// walks both volumes at once; state in FP32, every reduction in FP64 from
-// per-block partial sums reduced in a fixed order by one block, scalars and
-// the log kept on the device.
+// walks both volumes at once.  The iterate f and the residual r = A f -
+// beta m are unevaluated sums of two FP32 values (f + flo, r + rlo, the low
+// part within half an ulp of the high one), updated in FP64; the other
+// state is FP32.  Every reduction is FP64 from per-block partial sums
+// reduced in a fixed order by one block; scalars and the log stay on the
+// device.
 //
+// Set-up: f + flo = beta x0 (or 0), lambda = z = 0, r + rlo = A f - beta m
+// (the projector's FP64 ray sums, minus beta m in FP64), h = mu A^T r.
 // Iteration k (element-wise kernels: grid-stride loops over at most 2048
 // blocks, so the one-block reductions read few partial sums):
 //   k3_tv     lambda -= xi (grad f - z) (k > 0: the previous iteration's
 //             multiplier step, grad f being the new image's), z = shrink(
 //             grad f - lambda / rho, 1 / rho), W = rho (grad f - z) - lambda;
 //             partials TV(f), |grad f - z|^2
-//   k3_g      G = grad^T W + h; partial |G|^2   (k = 0 also |grad G|^2, and
-//             A G through the cone projector for the exact first step)
-//   k3_scalar log row k
-//   k3_step   s = -alpha G, f += s; partial |f^k|^2
-//   A f       r = A f - beta m; partial |r|^2
+//   k3_g      G = grad^T W + h; partial |G|^2   (k = 0 also |grad G|^2)
+//   A G       p + plo, the FP64 ray sums of G split in two FP32 parts
+//   k3_scalar (k = 0) the exact line search along -G; then log row k
+//   k3_step   s = -alpha G, f += s in FP64; partials |f^k|^2, <s,s>
+//   k3_rupd   r -= alpha (p + plo) in FP64, so that r stays A f - beta m
+//             without projecting f; partial |r|^2
 //   A^T r     h' = mu A^T r, y = h' - h + rho grad^T grad s, h = h';
-//             partials <s,s>, <s,y>
+//             partial <s,y>
 //   k3_scalar alpha = <s,s>/<s,y> when <s,y> > 0, relative change
+// With a tolerance the host reads both relative changes after every
+// iteration and stops an energy at the first one below it (the stop rule of
+// Sec. 3); the other energy runs on alone.
 #include <cmath>
 #include <memory>
 #include <mutex>
@@ -50,6 +59,20 @@ __device__ __forceinline__ void block_sum(double v, double *out)
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// Backward differences of f + flo: each part differenced in FP32 (exact for
+// neighbouring values within a factor of two of each other) and the two
+// differences added.
+__device__ __forceinline__ void grad2_at(const Dims &d, const float *__restrict__ f,
+                                         const float *__restrict__ flo, size_t i, int c, int r,
+                                         int z, float &gx, float &gy, float &gz)
+{
+    const float fi = f[i], li = flo[i];
+    const size_t P = (size_t)d.nx * d.ny;
+    gx = c >= 1 ? (fi - f[i - 1]) + (li - flo[i - 1]) : 0.f;
+    gy = r >= 1 ? (fi - f[i - d.nx]) + (li - flo[i - d.nx]) : 0.f;
+    gz = z >= 1 ? (fi - f[i - P]) + (li - flo[i - P]) : 0.f;
+}
+
 __device__ __forceinline__ void grad_at(const Dims &d, const float *__restrict__ f, size_t i,
                                         int c, int r, int z, float &gx, float &gy, float &gz)
 {
@@ -70,6 +93,7 @@ __device__ __forceinline__ void coords(const Dims &d, size_t i, int &c, int &r, 
 constexpr int kMaxBlk = 2048;  // grid of the element-wise kernels (grid-stride loops)
 
 __global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f,
+                                             const float *__restrict__ flo,
                                              float *__restrict__ lam, float *__restrict__ zz,
                                              float *__restrict__ W, int first, float xi, float rho,
                                              double *__restrict__ part, size_t stride)
@@ -79,7 +103,7 @@ __global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f
         int c, r, z;
         coords(d, i, c, r, z);
         float g[3];
-        grad_at(d, f, i, c, r, z, g[0], g[1], g[2]);
+        grad2_at(d, f, flo, i, c, r, z, g[0], g[1], g[2]);
         float l[3], v[3];
         for (int a = 0; a < 3; ++a) {
             l[a] = lam[a * d.N + i];
@@ -104,6 +128,7 @@ __global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f
 
 // TV(f) alone (the last log row).
 __global__ __launch_bounds__(256) void k3_tvonly(Dims d, const float *__restrict__ f,
+                                                 const float *__restrict__ flo,
                                                  double *__restrict__ part, size_t stride)
 {
     double tv = 0.0;
@@ -111,7 +136,7 @@ __global__ __launch_bounds__(256) void k3_tvonly(Dims d, const float *__restrict
         int c, r, z;
         coords(d, i, c, r, z);
         float g[3];
-        grad_at(d, f, i, c, r, z, g[0], g[1], g[2]);
+        grad2_at(d, f, flo, i, c, r, z, g[0], g[1], g[2]);
         tv += sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
     }
     block_sum(tv, part + Q_TV * stride + blockIdx.x);
@@ -176,51 +201,90 @@ struct Scal3 {
     double alpha, relchg, rr;
 };
 
+// s = -alpha G and (f + flo) += s in FP64, split again; partials |f^k|^2
+// (the image before the step) and <s,s>, both in FP64.
 __global__ __launch_bounds__(256) void k3_step(Dims d, const float *__restrict__ G,
-                                               float *__restrict__ f, float *__restrict__ s,
-                                               const Scal3 *__restrict__ sc,
+                                               float *__restrict__ f, float *__restrict__ flo,
+                                               float *__restrict__ s, const Scal3 *__restrict__ sc,
                                                double *__restrict__ part, size_t stride)
 {
-    double ff = 0.0;
+    const double alpha = sc->alpha;
+    double ff = 0.0, ss = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
-        const float fo = f[i];
-        const float fn = fo - (float)sc->alpha * G[i];
-        s[i] = fn - fo;
-        f[i] = fn;
-        ff += (double)fo * fo;
+        const double fo = (double)f[i] + (double)flo[i];
+        const double sd = -alpha * (double)G[i];
+        const double fn = fo + sd;
+        const float hi = (float)fn;
+        f[i] = hi;
+        flo[i] = (float)(fn - (double)hi);
+        s[i] = (float)sd;
+        ff += fo * fo;
+        ss += sd * sd;
     }
     block_sum(ff, part + Q_FF * stride + blockIdx.x);
+    block_sum(ss, part + Q_SS * stride + blockIdx.x);
 }
 
-// r = p - gs over the projections (in place in p); partial |r|^2.
-__global__ __launch_bounds__(256) void k3_resid(float *__restrict__ p, const float *__restrict__ gs,
-                                                size_t M, double *__restrict__ part, size_t stride)
+// (r + rlo) -= alpha (p + plo) in FP64, split again; partial |r|^2.
+__global__ __launch_bounds__(256) void k3_rupd(float *__restrict__ r, float *__restrict__ rlo,
+                                               const float *__restrict__ p,
+                                               const float *__restrict__ plo,
+                                               const Scal3 *__restrict__ sc, size_t M,
+                                               double *__restrict__ part, size_t stride)
 {
+    const double alpha = sc->alpha;
     double rr = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (size_t)gridDim.x * 256) {
-        const float r = p[i] - gs[i];
-        p[i] = r;
-        rr += (double)r * r;
+        const double v = ((double)r[i] + (double)rlo[i]) - alpha * ((double)p[i] + (double)plo[i]);
+        const float hi = (float)v;
+        r[i] = hi;
+        rlo[i] = (float)(v - (double)hi);
+        rr += v * v;
     }
     block_sum(rr, part + Q_RR * stride + blockIdx.x);
 }
 
-// gs = beta m
-__global__ __launch_bounds__(256) void k3_scale(const float *__restrict__ m, float beta, size_t M,
-                                                float *__restrict__ gs)
+// r + rlo = (p + plo) - beta m in FP64 (p == NULL: a zero image, A f = 0);
+// partial |r|^2.
+__global__ __launch_bounds__(256) void k3_rinit(const float *__restrict__ p,
+                                                const float *__restrict__ plo,
+                                                const float *__restrict__ m, double beta, size_t M,
+                                                float *__restrict__ r, float *__restrict__ rlo,
+                                                double *__restrict__ part, size_t stride)
 {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (size_t)gridDim.x * 256)
-        gs[i] = beta * m[i];
+    double rr = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (size_t)gridDim.x * 256) {
+        const double af = p ? (double)p[i] + (double)plo[i] : 0.0;
+        const double v = af - beta * (double)m[i];
+        const float hi = (float)v;
+        r[i] = hi;
+        rlo[i] = (float)(v - (double)hi);
+        rr += v * v;
+    }
+    block_sum(rr, part + Q_RR * stride + blockIdx.x);
 }
 
-// h' = mu hb; y = h' - h + rho grad^T grad s; h = h'.  With s == NULL only h
-// is formed (the start).
+// f + flo = beta x0 (x0 == NULL: zero).
+__global__ __launch_bounds__(256) void k3_start(const float *__restrict__ x0, double beta,
+                                                size_t n, float *__restrict__ f,
+                                                float *__restrict__ flo)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double v = x0 ? beta * (double)x0[i] : 0.0;
+        const float hi = (float)v;
+        f[i] = hi;
+        flo[i] = (float)(v - (double)hi);
+    }
+}
+
+// h' = mu hb; y = h' - h + rho grad^T grad s; h = h'; partial <s,y>.  With
+// s == NULL only h is formed (the start).
 __global__ __launch_bounds__(256) void k3_y(Dims d, const float *__restrict__ hb,
                                             float *__restrict__ h, const float *__restrict__ s,
                                             float mu, float rho, double *__restrict__ part,
                                             size_t stride)
 {
-    double ss = 0.0, sy = 0.0;
+    double sy = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         const float hn = mu * hb[i];
         if (s) {
@@ -238,13 +302,11 @@ __global__ __launch_bounds__(256) void k3_y(Dims d, const float *__restrict__ hb
             if (z >= 1) l += si - s[i - P];
             if (z + 1 <= d.nz - 1) l -= s[i + P] - si;
             const float y = (hn - h[i]) + rho * l;
-            ss += (double)si * si;
             sy += (double)si * y;
         }
         h[i] = hn;
     }
-    block_sum(ss, part + Q_SS * stride + blockIdx.x);
-    block_sum(sy, part + Q_SY * stride + blockIdx.x);
+    if (s) block_sum(sy, part + Q_SY * stride + blockIdx.x);
 }
 
 __device__ double reduce_q(const double *__restrict__ part, size_t stride, int q, int nb)
@@ -319,11 +381,13 @@ __global__ __launch_bounds__(256) void k3_zero(float *__restrict__ p, size_t n)
         p[i] = 0.f;
 }
 
-__global__ __launch_bounds__(256) void k3_out(const float *__restrict__ f, float inv_beta, size_t n,
+// x = (f + flo) / beta
+__global__ __launch_bounds__(256) void k3_out(const float *__restrict__ f,
+                                              const float *__restrict__ flo, double beta, size_t n,
                                               float *__restrict__ x)
 {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-        x[i] = f[i] * inv_beta;
+        x[i] = (float)(((double)f[i] + (double)flo[i]) / beta);
 }
 
 unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
@@ -331,7 +395,7 @@ unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 struct Adm3Work {
-    DevBuf buf[2][10], bpart[2], bsc, blog;
+    DevBuf buf[2][13], bpart[2], bsc, blog;
 };
 
 static std::mutex g_adm3_mu;
@@ -359,10 +423,12 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
 {
     if (!g || !p || !m_high || !m_low || !x_high || !x_low)
         return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: null argument");
-    if (p->flags != 0)
-        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3 takes no flags (zero start, BB1 step)");
-    if (p->tol != 0.0)
-        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3 runs a fixed iteration count (tol = 0)");
+    if (p->flags & ~DECT_WARM_START)
+        return fail(DECT_ERR_INVALID_ARG,
+                    "dect_adm_tv3 takes no flag but DECT_WARM_START (BB1 step, no projection "
+                    "onto f >= 0, per-energy TV)");
+    if (!(p->tol >= 0.0) || !std::isfinite(p->tol))
+        return fail(DECT_ERR_INVALID_ARG, "tol must be finite and >= 0");
     if (p->max_iter < 0 || p->max_iter > 1000000)
         return fail(DECT_ERR_INVALID_ARG, "max_iter out of range");
     if (!(p->mu > 0.0) || !(p->rho > 0.0) || !(p->xi >= 0.0) || !(p->beta_high > 0.0) ||
@@ -374,6 +440,7 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const Dims d{g->nx, g->ny, g->nz, (size_t)g->nx * g->ny * g->nz};
     const size_t M = (size_t)g->n_views * g->n_rows * g->n_bins;
     const int K = p->max_iter;
+    const bool warm = (p->flags & DECT_WARM_START) != 0;
     const int nbN = (int)std::min<size_t>(kMaxBlk, nblk(d.N));
     const int nbM = (int)std::min<size_t>(kMaxBlk, nblk(M));
     const size_t stride = (size_t)std::max(nbN, nbM);
@@ -387,21 +454,21 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     auto &bpart = w3->bpart;
     auto &bsc = w3->bsc;
     auto &blog = w3->blog;
-    const size_t vsz[10] = {d.N, d.N, d.N, d.N, d.N, 3 * d.N, 3 * d.N, 3 * d.N, M, M};
+    enum { B_F, B_FLO, B_S, B_G, B_H, B_HB, B_LAM, B_Z, B_W, B_R, B_RLO, B_P, B_PLO, B_COUNT };
+    const size_t vsz[B_COUNT] = {d.N, d.N, d.N, d.N, d.N, d.N, 3 * d.N, 3 * d.N, 3 * d.N,
+                                 M,   M,   M,   M};
     dect_status st;
     for (int e = 0; e < 2; ++e) {
-        for (int a = 0; a < 10; ++a)
+        for (int a = 0; a < B_COUNT; ++a)
             if ((st = buf[e][a].ensure(vsz[a] * 4))) return st;
         if ((st = bpart[e].ensure(Q_COUNT * stride * 8))) return st;
     }
     if ((st = bsc.ensure(2 * sizeof(Scal3))) || (st = blog.ensure((size_t)(K + 1) * 5 * 8 * 2)))
         return st;
-    float *f[2], *sv[2], *G[2], *h[2], *hb[2], *lam[2], *zz[2], *W[2], *gs[2], *pr[2];
+    float *V[2][B_COUNT];
     double *part[2];
     for (int e = 0; e < 2; ++e) {
-        float **dst[10] = {&f[e], &sv[e], &G[e], &h[e], &hb[e], &lam[e], &zz[e], &W[e], &gs[e],
-                           &pr[e]};
-        for (int a = 0; a < 10; ++a) *dst[a] = (float *)buf[e][a].ptr;
+        for (int a = 0; a < B_COUNT; ++a) V[e][a] = (float *)buf[e][a].ptr;
         part[e] = (double *)bpart[e].ptr;
     }
     double *dlog = (double *)blog.ptr;
@@ -410,91 +477,118 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const float *ms[2] = {m_high, m_low};
     float *xs[2] = {x_high, x_low};
     const double betas[2] = {p->beta_high, p->beta_low};
-    const float *cf[2] = {f[0], f[1]}, *cG[2] = {G[0], G[1]}, *cpr[2] = {pr[0], pr[1]};
+    const float *cf[2] = {V[0][B_F], V[1][B_F]}, *cG[2] = {V[0][B_G], V[1][B_G]};
+    const float *cr[2] = {V[0][B_R], V[1][B_R]};
+    float *pp[2] = {V[0][B_P], V[1][B_P]}, *plo[2] = {V[0][B_PLO], V[1][B_PLO]};
+    float *hb[2] = {V[0][B_HB], V[1][B_HB]};
 
+    // set-up: f + flo = beta x0 (or 0), lambda = z = 0, r = A f - beta m,
+    // h = mu A^T r
     for (int e = 0; e < 2; ++e) {
-        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, f[e], d.N);
-        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, lam[e], 3 * d.N);
-        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, zz[e], 3 * d.N);
-        hipLaunchKernelGGL(k3_scale, dim3(nbM), dim3(256), 0, s, ms[e], (float)betas[e], M, gs[e]);
+        hipLaunchKernelGGL(k3_start, dim3(nbN), dim3(256), 0, s,
+                           warm ? (const float *)xs[e] : (const float *)nullptr, betas[e], d.N,
+                           V[e][B_F], V[e][B_FLO]);
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, V[e][B_LAM], 3 * d.N);
+        hipLaunchKernelGGL(k3_zero, dim3(nbN), dim3(256), 0, s, V[e][B_Z], 3 * d.N);
     }
-    // r = A 0 - gs, h = mu A^T r
-    if ((st = cone_project2(g, cf, pr, s))) return st;
+    DECT_HIP(hipGetLastError());
+    // A f of the high parts (flo, below half an ulp of f, is not projected)
+    if (warm && (st = cone_project2_lo(g, cf, pp, plo, s))) return st;
     for (int e = 0; e < 2; ++e)
-        hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr[e], gs[e], M, part[e], stride);
-    if ((st = cone_backproject2(g, cpr, hb, s))) return st;
+        hipLaunchKernelGGL(k3_rinit, dim3(nbM), dim3(256), 0, s,
+                           warm ? (const float *)pp[e] : (const float *)nullptr,
+                           (const float *)plo[e], ms[e], betas[e], M, V[e][B_R], V[e][B_RLO],
+                           part[e], stride);
+    if ((st = cone_backproject2(g, cr, hb, s))) return st;
     for (int e = 0; e < 2; ++e) {
-        hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb[e], h[e], (const float *)nullptr,
-                           mu, rho, part[e], stride);
+        hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, (const float *)hb[e], V[e][B_H],
+                           (const float *)nullptr, mu, rho, part[e], stride);
         hipLaunchKernelGGL(k3_init, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbM);
     }
     DECT_HIP(hipGetLastError());
-    for (int k = 0; k < K; ++k) {
+
+    // each energy runs until max_iter or, with a tolerance, until its
+    // relative change first falls below it; stop[e] = its iteration count
+    int stop[2] = {K, K};
+    bool done[2] = {false, false};
+    for (int k = 0; k < K && !(done[0] && done[1]); ++k) {
         for (int e = 0; e < 2; ++e) {
-            hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, f[e], lam[e], zz[e], W[e],
+            if (done[e]) continue;
+            hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_F],
+                               (const float *)V[e][B_FLO], V[e][B_LAM], V[e][B_Z], V[e][B_W],
                                k == 0 ? 1 : 0, xi, rho, part[e], stride);
-            hipLaunchKernelGGL(k3_g, dim3(nbN), dim3(256), 0, s, d, W[e], h[e], G[e], part[e],
-                               stride);
+            hipLaunchKernelGGL(k3_g, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_W],
+                               (const float *)V[e][B_H], V[e][B_G], part[e], stride);
         }
-        if (k == 0) {
-            if ((st = cone_project2(g, cG, pr, s))) return st;
-            for (int e = 0; e < 2; ++e) {
-                hipLaunchKernelGGL(k3_sumsq, dim3(nbM), dim3(256), 0, s, pr[e], M, (int)Q_PP,
-                                   part[e], stride);
-                hipLaunchKernelGGL(k3_gradnorm, dim3(nbN), dim3(256), 0, s, d, G[e], part[e],
-                                   stride);
+        // p + plo = A G (a stopped energy's G is stale and its p unused)
+        if ((st = cone_project2_lo(g, cG, pp, plo, s))) return st;
+        for (int e = 0; e < 2; ++e) {
+            if (done[e]) continue;
+            if (k == 0) {
+                hipLaunchKernelGGL(k3_sumsq, dim3(nbM), dim3(256), 0, s, (const float *)pp[e], M,
+                                   (int)Q_PP, part[e], stride);
+                hipLaunchKernelGGL(k3_gradnorm, dim3(nbN), dim3(256), 0, s, d,
+                                   (const float *)V[e][B_G], part[e], stride);
                 hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride,
                                    nbN, nbM, 0, p->mu, p->rho, (double *)nullptr);
             }
-        }
-        for (int e = 0; e < 2; ++e) {
             hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN,
                                nbM, 1, p->mu, p->rho, dlog + ((size_t)e * (K + 1) + k) * 5);
-            hipLaunchKernelGGL(k3_step, dim3(nbN), dim3(256), 0, s, d, G[e], f[e], sv[e], sc + e,
-                               part[e], stride);
-        }
-        if ((st = cone_project2(g, cf, pr, s))) return st;
-        for (int e = 0; e < 2; ++e)
-            hipLaunchKernelGGL(k3_resid, dim3(nbM), dim3(256), 0, s, pr[e], gs[e], M, part[e],
+            hipLaunchKernelGGL(k3_step, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_G],
+                               V[e][B_F], V[e][B_FLO], V[e][B_S], sc + e, part[e], stride);
+            hipLaunchKernelGGL(k3_rupd, dim3(nbM), dim3(256), 0, s, V[e][B_R], V[e][B_RLO],
+                               (const float *)pp[e], (const float *)plo[e], sc + e, M, part[e],
                                stride);
-        if ((st = cone_backproject2(g, cpr, hb, s))) return st;
+        }
+        if ((st = cone_backproject2(g, cr, hb, s))) return st;
         for (int e = 0; e < 2; ++e) {
-            hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, hb[e], h[e],
-                               (const float *)sv[e], mu, rho, part[e], stride);
+            if (done[e]) continue;
+            hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, (const float *)hb[e],
+                               V[e][B_H], (const float *)V[e][B_S], mu, rho, part[e], stride);
             hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN,
                                nbM, 2, p->mu, p->rho, (double *)nullptr);
         }
         DECT_HIP(hipGetLastError());
+        if (p->tol > 0.0) {
+            Scal3 hs[2];
+            DECT_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+            DECT_HIP(hipStreamSynchronize(s));
+            for (int e = 0; e < 2; ++e)
+                if (!done[e] && hs[e].relchg < p->tol) {
+                    done[e] = true;
+                    stop[e] = k + 1;
+                }
+        }
     }
     for (int e = 0; e < 2; ++e) {
-        hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, f[e], part[e], stride);
+        hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_F],
+                           (const float *)V[e][B_FLO], part[e], stride);
         hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN, nbM,
-                           3, p->mu, p->rho, dlog + ((size_t)e * (K + 1) + K) * 5);
-        hipLaunchKernelGGL(k3_out, dim3(nbN), dim3(256), 0, s, f[e], (float)(1.0 / betas[e]), d.N,
-                           xs[e]);
+                           3, p->mu, p->rho, dlog + ((size_t)e * (K + 1) + stop[e]) * 5);
+        hipLaunchKernelGGL(k3_out, dim3(nbN), dim3(256), 0, s, (const float *)V[e][B_F],
+                           (const float *)V[e][B_FLO], betas[e], d.N, xs[e]);
     }
     DECT_HIP(hipGetLastError());
-    // the work buffers are freed at return: wait for the stream first
     std::vector<double> hlog((size_t)(K + 1) * 5 * 2);
     DECT_HIP(hipMemcpyAsync(hlog.data(), dlog, hlog.size() * 8, hipMemcpyDeviceToHost, s));
     DECT_HIP(hipStreamSynchronize(s));
+    auto row = [&](int e, int k) { return &hlog[((size_t)e * (K + 1) + k) * 5]; };
     // J and the step must stay finite (the relative change after the first
     // step of a zero start is infinite by definition)
     bool finite = true;
-    for (size_t r = 0; r < hlog.size() / 5; ++r)
-        finite = finite && std::isfinite(hlog[r * 5]) && std::isfinite(hlog[r * 5 + 1]);
+    for (int e = 0; e < 2; ++e)
+        for (int k = 0; k <= stop[e]; ++k)
+            finite = finite && std::isfinite(row(e, k)[0]) && std::isfinite(row(e, k)[1]);
     if (p->log)
-        for (int k = 0; k <= K; ++k) {
-            p->log[k * 4 + 0] = hlog[(size_t)k * 5];
-            p->log[k * 4 + 1] = hlog[(size_t)(K + 1) * 5 + (size_t)k * 5];
-            p->log[k * 4 + 2] = hlog[(size_t)k * 5 + 1];
-            p->log[k * 4 + 3] = hlog[(size_t)(K + 1) * 5 + (size_t)k * 5 + 1];
-        }
+        for (int k = 0; k <= K; ++k)
+            for (int e = 0; e < 2; ++e) {  // rows after an energy's stop hold zeros
+                p->log[k * 4 + e] = k <= stop[e] ? row(e, k)[0] : 0.0;
+                p->log[k * 4 + 2 + e] = k <= stop[e] ? row(e, k)[1] : 0.0;
+            }
     if (rep) {
-        rep->iters = K;
-        rep->objective = hlog[(size_t)K * 5] + hlog[(size_t)(K + 1) * 5 + (size_t)K * 5];
-        rep->rel_change = std::max(hlog[(size_t)K * 5 + 3],
-                                   hlog[(size_t)(K + 1) * 5 + (size_t)K * 5 + 3]);
+        rep->iters = std::max(stop[0], stop[1]);
+        rep->objective = row(0, stop[0])[0] + row(1, stop[1])[0];
+        rep->rel_change = std::max(row(0, stop[0])[3], row(1, stop[1])[3]);
         rep->pcg_residual = 0.0;
         rep->status = finite ? DECT_OK : DECT_ERR_NONFINITE;
     }

@@ -153,7 +153,9 @@ template <int NE>
 __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ vx,
                                                   const float *__restrict__ vy,
                                                   float *__restrict__ proj0,
-                                                  float *__restrict__ proj1)
+                                                  float *__restrict__ proj1,
+                                                  float *__restrict__ lo0,
+                                                  float *__restrict__ lo1)
 {
     const size_t nray = (size_t)g.V * g.J * g.B;
     const size_t rid = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -198,8 +200,18 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
 #pragma unroll
         for (int e = 0; e < NE; ++e) acc[e] += (double)s[e];
     }
-    proj0[rid] = (float)(acc[0] * (double)r.L);
-    if constexpr (NE == 2) proj1[rid] = (float)(acc[1] * (double)r.L);
+    // the FP64 ray sum rounded to FP32; with lo buffers also its rounding
+    // error, so that proj + lo carries the sum to about 2^-48
+    const double v0 = acc[0] * (double)r.L;
+    const float h0 = (float)v0;
+    proj0[rid] = h0;
+    if (lo0) lo0[rid] = (float)(v0 - (double)h0);
+    if constexpr (NE == 2) {
+        const double v1 = acc[1] * (double)r.L;
+        const float h1 = (float)v1;
+        proj1[rid] = h1;
+        if (lo1) lo1[rid] = (float)(v1 - (double)h1);
+    }
 }
 
 // Per (view, bin): the ray's 32.32 in-plane coordinate at plane 0 and its
@@ -425,9 +437,10 @@ dect_status cone_setup(const dect_cone_geometry *g, ConeDev &d, ConeWork *w, hip
 }
 
 // Both projectors for NE volumes (1 or 2) sharing one geometry.
+// lo: NULL, or NE buffers for the rounding errors of the FP32 results.
 template <int NE>
 dect_status cone_project_n(const dect_cone_geometry *g, const float *const *vol,
-                           float *const *proj, hipStream_t s)
+                           float *const *proj, float *const *lo, hipStream_t s)
 {
     for (int e = 0; e < NE; ++e)
         if (!vol[e] || !proj[e]) return fail(DECT_ERR_INVALID_ARG, "dect_cone_project: null buffer");
@@ -452,7 +465,8 @@ dect_status cone_project_n(const dect_cone_geometry *g, const float *const *vol,
     DECT_HIP(hipGetLastError());
     const size_t nray = (size_t)d.V * d.J * d.B;
     hipLaunchKernelGGL(k_cone_fwd<NE>, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, s, d,
-                       (const float *)w->vx.ptr, (const float *)w->vy.ptr, proj[0], proj[NE - 1]);
+                       (const float *)w->vx.ptr, (const float *)w->vy.ptr, proj[0], proj[NE - 1],
+                       lo ? lo[0] : (float *)nullptr, lo ? lo[NE - 1] : (float *)nullptr);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -496,7 +510,7 @@ dect_status cone_backproject_n(const dect_cone_geometry *g, const float *const *
 dect_status cone_project(const dect_cone_geometry *g, const float *vol, float *proj,
                          hipStream_t s)
 {
-    return cone_project_n<1>(g, &vol, &proj, s);
+    return cone_project_n<1>(g, &vol, &proj, nullptr, s);
 }
 
 dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, float *vol,
@@ -508,7 +522,13 @@ dect_status cone_backproject(const dect_cone_geometry *g, const float *proj, flo
 dect_status cone_project2(const dect_cone_geometry *g, const float *const vol[2],
                           float *const proj[2], hipStream_t s)
 {
-    return cone_project_n<2>(g, vol, proj, s);
+    return cone_project_n<2>(g, vol, proj, nullptr, s);
+}
+
+dect_status cone_project2_lo(const dect_cone_geometry *g, const float *const vol[2],
+                             float *const proj[2], float *const lo[2], hipStream_t s)
+{
+    return cone_project_n<2>(g, vol, proj, lo, s);
 }
 
 dect_status cone_backproject2(const dect_cone_geometry *g, const float *const proj[2],

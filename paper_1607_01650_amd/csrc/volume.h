@@ -9,6 +9,10 @@ namespace dect {
 // together, interleaved; each result equal to the single-volume call's).
 dect_status cone_project2(const dect_cone_geometry *g, const float *const vol[2],
                           float *const proj[2], hipStream_t s);
+// cone_project2 that also writes lo[e] = (FP64 ray sum) - proj[e] rounded to
+// FP32, so that proj + lo is the ray sum to about 2^-48 relative.
+dect_status cone_project2_lo(const dect_cone_geometry *g, const float *const vol[2],
+                             float *const proj[2], float *const lo[2], hipStream_t s);
 dect_status cone_backproject2(const dect_cone_geometry *g, const float *const proj[2],
                               float *const vol[2], hipStream_t s);
 

@@ -402,12 +402,13 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
 
 
 def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool = False,
-            out: Optional[Tuple] = None) -> AdmResult:
+            out: Optional[Tuple] = None, x0=None) -> AdmResult:
     """ADM-TV of both energies on a volume with the cone-beam pair
     (dect_adm_tv3): m_* [V, rows, bins] device projections -> x_high, x_low
-    [nz, ny, nx]; zero start, BB1 step, fixed iteration count.  With
-    want_log, the log [max_iter+1, 4] = (J_high, J_low, alpha_high,
-    alpha_low) and the report."""
+    [nz, ny, nx]; BB1 step, from zero or from x0 = (x_high, x_low) (copied
+    into the outputs, which the call then reads as its start), each energy
+    stopping early when p.tol > 0.  With want_log, the log [max_iter+1, 4]
+    = (J_high, J_low, alpha_high, alpha_low) and the report."""
     torch = _torch()
     shp = (geom.n_views, geom.n_rows, geom.n_bins)
     _dev(m_high, "m_high", shp)
@@ -422,6 +423,14 @@ def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool 
     flags = (DECT_NONNEG if getattr(p, "nonneg", False) else 0) | \
         (DECT_COUPLED_TV if getattr(p, "coupled_tv", False) else 0) | \
         _STEP_FLAGS[getattr(p, "step", "bb1")]
+    if x0 is not None:
+        _dev(x0[0], "x0_high", (geom.nz, geom.ny, geom.nx))
+        _dev(x0[1], "x0_low", (geom.nz, geom.ny, geom.nx))
+        if x0[0].data_ptr() != xh.data_ptr():
+            xh.copy_(x0[0])
+        if x0[1].data_ptr() != xl.data_ptr():
+            xl.copy_(x0[1])
+        flags |= DECT_WARM_START
     log = None
     logp = None
     if want_log:
