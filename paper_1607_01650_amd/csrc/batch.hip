@@ -21,7 +21,6 @@ namespace dect {
 struct SliceDev {
     int nx, ny, V, B, nbundle, nvg, M;
     const RayFwd *fwd;
-    const RayAdj *adj;
     const float *len;
     const Bundle *bundles;
     const BinRange *bins;
@@ -157,7 +156,7 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
             float *p[2];
             for (int e = 0; e < 2; ++e)
                 p[e] = d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
-            adj_block<2, false>(sh, s, d.adj, d.fwd, d.len, nullptr, d.bins, d.lanes, d.nx, d.ny,
+            adj_block<2, false>(sh, s, d.fwd, d.len, nullptr, d.bins, d.lanes, d.nx, d.ny,
                                 d.V, d.B, strip, g, d.nvg, p, stage, nullptr);
         }
         __syncthreads();
@@ -423,7 +422,6 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         d.M = (int)z.M;
         d.nbundle = t.nbundle;
         d.fwd = t.fwd;
-        d.adj = t.adj;
         d.len = t.len;
         d.bundles = t.bundles;
         d.bins = t.adj_bins;

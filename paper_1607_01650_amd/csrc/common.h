@@ -47,10 +47,6 @@ struct SidW {
     uint32_t c;
     float inv;
 };
-struct RayAdj {  // the same two numbers as doubles (exact: |values| < 2^53)
-    double a;
-    double k;
-};
 // Per (view, 64-bin bundle): union of the valid driving-line ranges of the
 // bundle's x-major lanes [x0, x1] and y-major lanes [y0, y1] (empty: x0 > x1).
 struct Bundle {
@@ -140,7 +136,6 @@ struct GeomTables {
     GeomKey key;
     int nbundle = 0;
     RayFwd *fwd = nullptr;     // [V*B]
-    RayAdj *adj = nullptr;     // [V*B]
     float *len = nullptr;      // [V*B] path length per driving line (pixel/|cos|)
     Bundle *bundles = nullptr; // [ceil(V / kFwdViews) * nbundle]
     ViewInfo *views = nullptr; // [V]

@@ -154,7 +154,6 @@ bool GeomKey::operator==(const GeomKey &o) const
 GeomTables::~GeomTables()
 {
     dev_free(fwd);
-    dev_free(adj);
     dev_free(len);
     dev_free(bundles);
     dev_free(views);
@@ -270,7 +269,6 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     const double dl = g->pixel_mm, R = g->sod_mm, D = g->sdd_mm;
     const int nb = (B + kBundle - 1) / kBundle;
     std::vector<RayFwd> fwd((size_t)V * B);
-    std::vector<RayAdj> adj((size_t)V * B);
     std::vector<float> len((size_t)V * B);
     const bool siddon = g->model == DECT_SIDDON;
     std::vector<SidW> sid(siddon ? (size_t)V * B : 0);
@@ -316,7 +314,6 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
                 sid[i].inv = kabs ? (float)(kTwo32 / (double)kabs) : 0.0f;
             }
             fwd[i] = {afx, kfx};
-            adj[i] = {(double)afx / kTwo32, (double)kfx / kTwo32};
             len[i] = xm ? (float)L : -(float)L;  // sign marks the class
             major[b] = xm;
             valid_range(afx, kfx, xm ? nx : ny, xm ? ny : nx, &lo[b], &hi[b]);
@@ -506,7 +503,7 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
         if (!g_sizing && n) DECT_HIP(hipMemcpy(*dst, v.data(), n, hipMemcpyHostToDevice));
         return DECT_OK;
     };
-    if ((st = upload(&t->fwd, fwd)) || (st = upload(&t->adj, adj)) || (st = upload(&t->len, len)) ||
+    if ((st = upload(&t->fwd, fwd)) || (st = upload(&t->len, len)) ||
         (st = upload(&t->bundles, bun)) || (st = upload(&t->views, views)) ||
         (st = upload(&t->adj_bins, bins)) || (st = upload(&t->adj_lanes, lanes)) ||
         (siddon && (st = upload(&t->sid, sid))))

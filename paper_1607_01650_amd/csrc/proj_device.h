@@ -15,27 +15,16 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 // pair in the interleaved padded layout
 typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
 
-// Back-projector bin walk.  DECT_ADJ_LANES 1: every lane walks only the bins
-// that hit its own driving line inside the strip (exact per-lane ranges from
-// the host), reading their ray data from a per-wavefront LDS stage; 0: all
-// lanes take every bin of the strip's range together (ray data broadcast
-// with v_readlane).  Each accumulator element receives the same contributions
-// in the same order either way, so both give bitwise the same result.
-#ifndef DECT_ADJ_LANES
-#define DECT_ADJ_LANES 1
-#endif
-
 // Adjoint accumulation: a block's kAdjWaves wavefronts share one strip and split
 // its view group between them; each adds into its own LDS copy of the strip,
 // stored tap-line-major with row stride kSL (the 64 lanes of an access hit
-// distinct banks) plus kAccOff spare lines on each side.  With per-lane ranges
-// every bin a lane takes has its first tap on lines -1 .. kSW - 1, so one
-// spare line per side suffices (a lane with no bin left adds zero to lines -1
-// and 0, which leaves them as they are); the shared walk clamps the first
-// tap line to [-2, kSW], so that every tap outside the strip lands on one of
-// two spare lines per side.  For a pair of images each element holds both
+// distinct banks) plus one spare line on each side.  Every lane walks only
+// the bins that hit its own driving line inside the strip (exact per-lane
+// ranges from the host), so every bin it takes has its first tap on lines
+// -1 .. kSW - 1; a lane with no bin left adds zero to lines -1 and 0, which
+// leaves them as they are.  For a pair of images each element holds both
 // images' values side by side.
-constexpr int kAccOff = DECT_ADJ_LANES ? 1 : 2;
+constexpr int kAccOff = 1;
 constexpr int kAccRows = kSW + 2 * kAccOff;
 constexpr int kAccSize = kAccRows * kSL;
 
@@ -55,14 +44,6 @@ struct AdjStage {  // one 64-bin chunk per wavefront
     AdjRay ray[kAdjWaves * 64];
     f2v ly[kAdjWaves * 64];  // |path length| x sinogram value of each image
 };
-
-// The back-projector evaluates the line coordinate of a bin at a lane either
-// in FP64 (DECT_ADJ_INT 0: the exact doubles a + k * lane) or in 32.32
-// fixed point (1: one 32 x 32 -> 64-bit multiply-add); both give the same
-// tap line and the same FP32 weight as the forward pass.
-#ifndef DECT_ADJ_INT
-#define DECT_ADJ_INT 1
-#endif
 
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
@@ -235,14 +216,16 @@ __device__ __forceinline__ double lane_sum(double v)
 // 2) that share the geometry, view group g of nvg.  The block's partial image
 // of this (class, group) for image i is written to part[i] (a full [ny][nx]
 // plane, normal layout; only this strip's pixels).  Per view, each wavefront
-// walks the bins `bins` lists for its strip: up to 64 bins' ray data are
-// loaded at once (lane j holds bin j) and broadcast bin by bin; every lane
-// evaluates the ray on its own driving line and adds the two interpolation
-// taps of every image, which lie on consecutive tap lines, with one paired
-// LDS read and write (no atomics: the copy is the wave's own).
+// stages the ray data of up to 64 of the strip's bins in LDS (lane j holds
+// bin j: the strip-relative 32.32 line coordinate and slope, and |path
+// length| x sinogram value per image); every lane then takes the bins of its
+// own range in bin order, evaluates the ray on its own driving line (one
+// 32 x 32 -> 64-bit multiply-add, so the tap line and FP32 weight are the
+// forward pass's) and adds the two interpolation taps of every image, which
+// lie on consecutive tap lines, with one paired LDS read and write (no
+// atomics: the copy is the wave's own).
 template <int NE, bool SID>
 __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const (&sino)[NE],
-                                          const RayAdj *__restrict__ rays,
                                           const RayFwd *__restrict__ rays_fx,
                                           const float *__restrict__ len,
                                           const SidW *__restrict__ sid,
@@ -265,9 +248,6 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
     for (int i = lane; i < kAccSize; i += 64) my[i] = E(0.f);
     // acc line j holds tap line t0 + j - kAccOff
     E *col = my + lane;
-#if !DECT_ADJ_INT
-    const double ld = (double)lane;  // this lane's driving line, relative to l0
-#endif
     const BinRange *sb = bins + (size_t)strip * V;
 
     const int v_begin = (int)((int64_t)V * g / nvg), v_end = (int)((int64_t)V * (g + 1) / nvg);
@@ -275,11 +255,8 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
         const BinRange br = sb[v];
         const int lo = __builtin_amdgcn_readfirstlane(br.lo);
         const int hi = __builtin_amdgcn_readfirstlane(br.hi);
-        const RayAdj *rv = rays + (size_t)v * B;
         const RayFwd *rfv = rays_fx + (size_t)v * B;
         const float *lv = len + (size_t)v * B;
-#if DECT_ADJ_LANES && DECT_ADJ_INT
-        (void)rv;
         if (lo > hi) continue;
         const LaneRange lr = lanes[((size_t)strip * V + v) * kSL + lane];
         // a strip range too long for the table: every lane takes all of it
@@ -361,116 +338,6 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 step(stage.ray[j], stage.ly[j], sj, ok);
             }
         }
-#else
-        (void)lanes;
-        (void)stage;
-        (void)sid_stage;
-        static_assert(!SID || DECT_ADJ_INT, "the Siddon weight needs the fixed-point position");
-        for (int cb = lo; cb <= hi; cb += 64) {
-            // lane j: bin cb + j, its line coordinate moved to the strip
-            // origin, q' = (a + k l0 - t0) + k lane (exact: all terms are
-            // multiples of 2^-32 below 2^21)
-            const int bj = cb + lane;
-            float lyj[NE];
-#pragma unroll
-            for (int i = 0; i < NE; ++i) lyj[i] = 0.f;
-#if DECT_ADJ_INT
-            int64_t aj = 0, kj = 0;
-#else
-            double ajd = 0.0, kjd = 0.0;
-#endif
-            SidW sw_j{0xFFFFFFFFu, 0.f};
-            if (bj <= hi) {
-#if DECT_ADJ_INT
-                const RayFwd t = rfv[bj];
-                aj = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
-                kj = t.k_fx;
-#else
-                const RayAdj t = rv[bj];
-                ajd = fma(t.k, (double)l0, t.a) - (double)t0;
-                kjd = t.k;
-#endif
-                const float L = fabsf(lv[bj]);
-#pragma unroll
-                for (int i = 0; i < NE; ++i) lyj[i] = L * sino[i][(size_t)v * B + bj];
-                if constexpr (SID) sw_j = sid[(size_t)v * B + bj];
-            }
-#if !DECT_ADJ_INT
-            const int64_t aj = __double_as_longlong(ajd), kj = __double_as_longlong(kjd);
-#endif
-            const int alo = (int)aj, ahi = (int)(aj >> 32), klo = (int)kj, khi = (int)(kj >> 32);
-            int ly_bits[NE];
-#pragma unroll
-            for (int i = 0; i < NE; ++i) ly_bits[i] = __float_as_int(lyj[i]);
-            const int nj = min(64, hi - cb + 1);
-            // bin j's first tap line (strip-relative, clamped) and weight at
-            // this lane
-            auto pos = [&](int j, int &i0, float &w) {
-                const uint32_t a_lo = (uint32_t)__builtin_amdgcn_readlane(alo, j);
-                const uint32_t a_hi = (uint32_t)__builtin_amdgcn_readlane(ahi, j);
-                const uint32_t k_lo = (uint32_t)__builtin_amdgcn_readlane(klo, j);
-                const uint32_t k_hi = (uint32_t)__builtin_amdgcn_readlane(khi, j);
-#if DECT_ADJ_INT
-                // q = a + (k_hi 2^32 + k_lo) lane; k_hi is -1, 0 or 1
-                const uint64_t p = (uint64_t)k_lo * (uint32_t)lane + (((uint64_t)a_hi << 32) | a_lo);
-                const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)k_hi, lane);
-                i0 = min(max(qh, -2), kSW);
-                const uint32_t lo = (uint32_t)p;
-                if constexpr (SID) {
-                    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)sw_j.c, j);
-                    const float inv =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sw_j.inv), j));
-                    w = (lo > c ? (float)(lo - c) * inv : 0.f) * kTwoM32;
-                } else {
-                    w = (float)lo * kTwoM32;
-                }
-#else
-                const double a = __longlong_as_double((int64_t)(((uint64_t)a_hi << 32) | a_lo));
-                const double k = __longlong_as_double((int64_t)(((uint64_t)k_hi << 32) | k_lo));
-                const double q = fma(k, ld, a);
-                const double fl = floor(q);
-                i0 = min(max((int)fl, -2), kSW);
-                w = (float)(q - fl);
-#endif
-            };
-            auto bin_y = [&](int j, int i) {
-                return __int_as_float(__builtin_amdgcn_readlane(ly_bits[i], j));
-            };
-            // bin j's contributions added to the values of its two tap lines
-            auto add = [&](E &u0, E &u1, float w, int j) {
-                if constexpr (NE == 1) {
-                    const float ly = bin_y(j, 0);
-                    u0 += fmaf(-w, ly, ly);
-                    u1 = fmaf(w, ly, u1);
-                } else {
-                    const float y0 = bin_y(j, 0);
-                    const float y1 = bin_y(j, 1);
-                    u0.x += fmaf(-w, y0, y0);
-                    u0.y += fmaf(-w, y1, y1);
-                    u1.x = fmaf(w, y0, u1.x);
-                    u1.y = fmaf(w, y1, u1.y);
-                }
-            };
-            // one bin after the other, in bin order: this lane's tap pair of
-            // every image, one paired LDS read and write
-            auto tap = [&](int j) {
-                int i0;
-                float w;
-                pos(j, i0, w);
-                E *pp = col + (i0 + kAccOff) * kSL;
-                E u0 = pp[0], u1 = pp[kSL];
-                add(u0, u1, w, j);
-                pp[0] = u0;
-                pp[kSL] = u1;
-            };
-            int j = 0;
-            for (; j + 1 < nj; j += 2) {
-                tap(j);
-                tap(j + 1);
-            }
-            if (j < nj) tap(j);
-        }
-#endif
     }
     __syncthreads();
     // the copies summed in wave order; stored in normal image layout

@@ -117,7 +117,6 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd(const float *__restrict__ p
 // item0); part: [batch][2][nvg] planes of nx*ny floats.
 template <int NE, bool SID>
 __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ sino,
-                                                     const RayAdj *__restrict__ rays,
                                                      const RayFwd *__restrict__ rays_fx,
                                                      const float *__restrict__ len,
                                                      const SidW *__restrict__ sid,
@@ -144,7 +143,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
         s[i] = sino + (size_t)(e0 + i) * M;
         p[i] = part + ((size_t)(e0 + i) * 2 * nvg + (size_t)cls * nvg + g) * plane;
     }
-    adj_block<NE, SID>(sh, s, rays, rays_fx, len, sid, bins, lanes, nx, ny, V, B, strip, g, nvg, p,
+    adj_block<NE, SID>(sh, s, rays_fx, len, sid, bins, lanes, nx, ny, V, B, strip, g, nvg, p,
                        stage, sid_stage);
 }
 
@@ -229,7 +228,7 @@ dect_status launch_adj(const GeomTables &t, const float *sino, float *img, float
     const size_t plane = (size_t)k.nx * k.ny;
     const unsigned strips = (unsigned)adj_strips(k.nx, k.ny);
     auto go = [&](auto kern, unsigned items, int item0) {
-        hipLaunchKernelGGL(kern, dim3(strips, nvg, items), dim3(kAdjThreads), 0, s, sino, t.adj,
+        hipLaunchKernelGGL(kern, dim3(strips, nvg, items), dim3(kAdjThreads), 0, s, sino,
                            t.fwd, t.len, t.sid, t.adj_bins, t.adj_lanes, k.nx, k.ny, k.V, k.B, nvg,
                            item0, partial);
     };
