@@ -414,6 +414,61 @@ dect_status dect_pls_decompose3(int32_t nx, int32_t ny, int32_t nz, const float 
 dect_status dect_pls_edge_weights3(int32_t nx, int32_t ny, int32_t nz, const float *d_x,
                                    double tau, double eps, float *d_w, void *stream);
 
+/*
+ * Unrolled ADM-TV (the reconstruction procedure of Eq. 10 with a given step
+ * alpha_k in place of the BB step, and learnable (mu_k, rho_k, xi_k,
+ * alpha_k)), the differentiable path of the learned parameters.  A step
+ * runs as: p = A f (dect_project), r = p - g (dect_unrolled_residual),
+ * hb = A^T r (dect_backproject), then dect_unrolled_step.  Their
+ * vector-Jacobian products are dect_backproject, identity, dect_project and
+ * dect_unrolled_step_backward.
+ *
+ * dect_unrolled_residual: d_r[i] = d_p[i] - d_g[i] for i < n, device
+ * buffers of n float32 (d_r may equal d_p).  DECT_ERR_INVALID_ARG for n < 0
+ * or a NULL buffer with n > 0.
+ */
+dect_status dect_unrolled_residual(int64_t n, const float *d_p, const float *d_g, float *d_r,
+                                   void *stream);
+
+/*
+ * One unrolled step for `batch` images [batch][ny][nx] (float32, device):
+ *   z       = shrink(grad f - lambda / rho, 1 / rho)                   (Eq. 8)
+ *   G       = mu hb + grad^T (rho (grad f - z) - lambda)               (Eq. 9)
+ *   f_out   = f - alpha G
+ *   lam_out = lambda - xi (grad f_out - z)                             (Eq. 7)
+ * grad: the backward differences of Eq. 2 (x along a row, y down the
+ * columns; zero on the first column and row), grad^T its exact adjoint;
+ * shrink(v, t) = max(|v| - t, 0) v / |v| with |v| evaluated as sqrt(max(
+ * |v|^2, 1e-30)).  lambda = (d_lx, d_ly); d_hb = A^T (A f - g) of each
+ * image; d_params: device float32 [4] = (mu, rho, xi, alpha), read on the
+ * device (no host synchronisation).  Outputs must not overlap the inputs or
+ * each other (DECT_ERR_INVALID_ARG); bad sizes give DECT_ERR_INVALID_ARG.
+ * Asynchronous on `stream`; no allocation.
+ */
+dect_status dect_unrolled_step(int32_t nx, int32_t ny, int32_t batch, const float *d_f,
+                               const float *d_lx, const float *d_ly, const float *d_hb,
+                               const float *d_params, float *d_f_out, float *d_lx_out,
+                               float *d_ly_out, void *stream);
+
+/*
+ * The vector-Jacobian product of dect_unrolled_step at (d_f, d_lx, d_ly,
+ * d_hb, d_params) for the cotangents d_gf_out, d_glx_out, d_gly_out of its
+ * three outputs: d_gf, d_glx, d_gly, d_ghb receive the cotangents of f,
+ * lambda and hb ([batch][ny][nx] float32, device) and d_gparams (device
+ * float32 [4]) those of (mu, rho, xi, alpha), each the FP64 sum of per-block
+ * partial sums in a fixed order (bitwise reproducible).  The shrinkage is
+ * differentiated where |v| > 1/rho and has zero derivative elsewhere.
+ * Outputs must not overlap the inputs or each other.  Work memory (six
+ * images of the batch) is library-owned per device and kept between calls
+ * (or drawn from the workspace of dect_set_workspace).
+ */
+dect_status dect_unrolled_step_backward(int32_t nx, int32_t ny, int32_t batch, const float *d_f,
+                                        const float *d_lx, const float *d_ly, const float *d_hb,
+                                        const float *d_params, const float *d_gf_out,
+                                        const float *d_glx_out, const float *d_gly_out,
+                                        float *d_gf, float *d_glx, float *d_gly, float *d_ghb,
+                                        float *d_gparams, void *stream);
+
 /* Number of Joseph samples (ray, line) with the crossing inside (-1, n)
  * for a geometry: the unit of projector work. */
 dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);

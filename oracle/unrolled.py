@@ -11,6 +11,17 @@ import numpy as np
 from . import oracle as O
 
 
+def step(g_geom, g_data, f, lx, ly, mu, rho, xi, alpha):
+    """One step from (f, lambda): returns (f', lambda_x', lambda_y')."""
+    h = mu * O.backproject(g_geom, O.project(g_geom, f) - g_data)
+    dx, dy = O.grad(f)
+    zx, zy = O.shrink(dx - lx / rho, dy - ly / rho, 1.0 / rho)
+    G = h + O.gradT(rho * (dx - zx) - lx, rho * (dy - zy) - ly)
+    f = f - alpha * G
+    nx_, ny_ = O.grad(f)
+    return f, lx - xi * (nx_ - zx), ly - xi * (ny_ - zy)
+
+
 def unrolled(g_geom, g_data, params, f0=None):
     """params: sequence of (mu, rho, xi, alpha); g_data [V][B] (beta-scaled)."""
     ny, nx = g_geom.ny, g_geom.nx
@@ -18,12 +29,5 @@ def unrolled(g_geom, g_data, params, f0=None):
     lx = np.zeros((ny, nx))
     ly = np.zeros((ny, nx))
     for (mu, rho, xi, alpha) in params:
-        h = mu * O.backproject(g_geom, O.project(g_geom, f) - g_data)
-        dx, dy = O.grad(f)
-        zx, zy = O.shrink(dx - lx / rho, dy - ly / rho, 1.0 / rho)
-        G = h + O.gradT(rho * (dx - zx) - lx, rho * (dy - zy) - ly)
-        f = f - alpha * G
-        nx_, ny_ = O.grad(f)
-        lx = lx - xi * (nx_ - zx)
-        ly = ly - xi * (ny_ - zy)
+        f, lx, ly = step(g_geom, g_data, f, lx, ly, mu, rho, xi, alpha)
     return f

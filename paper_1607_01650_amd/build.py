@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdect.so")
 SOURCES = ["geometry.cpp", "projector.hip", "fbp.hip", "adm.hip", "pls.hip", "capi.cpp", "nn.hip",
-           "batch.hip", "cone.hip", "adm3.hip", "pls3.hip"]
+           "batch.hip", "cone.hip", "adm3.hip", "pls3.hip", "unrolled.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -29,6 +29,15 @@ dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const
 dect_status batch_set_groups(dect_batch *b, int groups);
 dect_status batch_shape(const dect_batch *b, int32_t *groups, int32_t *adj_per_cu,
                         int32_t *fwd_per_cu, int32_t *from_cache);
+dect_status unrolled_residual(int64_t n, const float *p, const float *g, float *r, hipStream_t s);
+dect_status unrolled_step(int nx, int ny, int batch, const float *f, const float *lx,
+                          const float *ly, const float *hb, const float *prm, float *fo,
+                          float *lxo, float *lyo, hipStream_t s);
+dect_status unrolled_step_backward(int nx, int ny, int batch, const float *f, const float *lx,
+                                   const float *ly, const float *hb, const float *prm,
+                                   const float *gfo, const float *glxo, const float *glyo,
+                                   float *gf, float *glx, float *gly, float *ghb, float *gprm,
+                                   hipStream_t s);
 
 // Bytes the 2-D calls allocate on geom when nothing is held yet: a dry run
 // of their allocations (tables, one ADM run without a caller state, the
@@ -57,6 +66,7 @@ void release_device_buffers()
     release_pls3_work();
     release_cone_work();
     release_adm3_work();
+    release_unrolled_work();
     release_tables();
 }
 }  // namespace dect
@@ -253,6 +263,36 @@ dect_status dect_workspace_size(const dect_geometry *geom, int32_t batch, size_t
 {
     dect::set_error("");
     return dect::workspace_size(geom, batch, bytes);
+}
+
+dect_status dect_unrolled_residual(int64_t n, const float *d_p, const float *d_g, float *d_r,
+                                   void *stream)
+{
+    dect::set_error("");
+    return dect::unrolled_residual(n, d_p, d_g, d_r, (hipStream_t)stream);
+}
+
+dect_status dect_unrolled_step(int32_t nx, int32_t ny, int32_t batch, const float *d_f,
+                               const float *d_lx, const float *d_ly, const float *d_hb,
+                               const float *d_params, float *d_f_out, float *d_lx_out,
+                               float *d_ly_out, void *stream)
+{
+    dect::set_error("");
+    return dect::unrolled_step(nx, ny, batch, d_f, d_lx, d_ly, d_hb, d_params, d_f_out, d_lx_out,
+                               d_ly_out, (hipStream_t)stream);
+}
+
+dect_status dect_unrolled_step_backward(int32_t nx, int32_t ny, int32_t batch, const float *d_f,
+                                        const float *d_lx, const float *d_ly, const float *d_hb,
+                                        const float *d_params, const float *d_gf_out,
+                                        const float *d_glx_out, const float *d_gly_out,
+                                        float *d_gf, float *d_glx, float *d_gly, float *d_ghb,
+                                        float *d_gparams, void *stream)
+{
+    dect::set_error("");
+    return dect::unrolled_step_backward(nx, ny, batch, d_f, d_lx, d_ly, d_hb, d_params, d_gf_out,
+                                        d_glx_out, d_gly_out, d_gf, d_glx, d_gly, d_ghb,
+                                        d_gparams, (hipStream_t)stream);
 }
 
 const char *dect_last_error(void) { return dect::last_error(); }

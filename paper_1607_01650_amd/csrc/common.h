@@ -198,6 +198,7 @@ void release_pls_work();
 void release_pls3_work();
 void release_cone_work();
 void release_adm3_work();
+void release_unrolled_work();
 dect_status set_workspace(void *p, size_t bytes);
 dect_status workspace_used(size_t *bytes);
 dect_status workspace_size(const dect_geometry *g, int batch, size_t *bytes);

@@ -121,6 +121,11 @@ SIGNATURES = {
     "dect_batch_shape": (ct.c_int, [ct.c_void_p, _P(ct.c_int32), _P(ct.c_int32), _P(ct.c_int32),
                                     _P(ct.c_int32)]),
     "dect_batch_set_groups": (ct.c_int, [ct.c_void_p, ct.c_int32]),
+    "dect_unrolled_residual": (ct.c_int, [ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                          ct.c_void_p]),
+    "dect_unrolled_step": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32] + [ct.c_void_p] * 9),
+    "dect_unrolled_step_backward": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32] +
+                                    [ct.c_void_p] * 14),
     "dect_count_samples": (ct.c_int, [_P(dect_geometry), _P(ct.c_int64)]),
     "dect_release_caches": (ct.c_int, []),
     "dect_last_error": (ct.c_char_p, []),
@@ -565,6 +570,65 @@ class AdmBatch:
             self.close()
         except Exception:
             pass
+
+
+def _vp(t):
+    return ct.c_void_p(t.data_ptr())
+
+
+def unrolled_residual(p, g, out=None):
+    """r = p - g on the device (dect_unrolled_residual); p, g float32
+    contiguous device tensors of one shape."""
+    torch = _torch()
+    if tuple(p.shape) != tuple(g.shape):
+        raise ValueError(f"p {tuple(p.shape)} and g {tuple(g.shape)} differ in shape")
+    _dev(p, "p", tuple(p.shape[-2:]))
+    _dev(g, "g", tuple(g.shape[-2:]))
+    if out is None:
+        out = torch.empty_like(p)
+    _out(out, "out", tuple(p.shape))
+    _check(lib().dect_unrolled_residual(p.numel(), _vp(p), _vp(g), _vp(out), _stream()),
+           "dect_unrolled_residual")
+    return out
+
+
+def _unrolled_shape(f):
+    if f.dim() != 3:
+        raise ValueError("unrolled step images must be [batch, ny, nx]")
+    return tuple(int(v) for v in f.shape)
+
+
+def unrolled_step(f, lx, ly, hb, params):
+    """One unrolled ADM-TV step (dect_unrolled_step): f, lx, ly, hb [B, ny,
+    nx]; params a device float32 [4] = (mu, rho, xi, alpha).  Returns
+    (f', lx', ly')."""
+    torch = _torch()
+    b, ny, nx = _unrolled_shape(f)
+    for t, n in ((f, "f"), (lx, "lx"), (ly, "ly"), (hb, "hb")):
+        _out(t, n, (b, ny, nx))
+    _out(params, "params", (4,))
+    fo, lxo, lyo = (torch.empty_like(f) for _ in range(3))
+    _check(lib().dect_unrolled_step(nx, ny, b, _vp(f), _vp(lx), _vp(ly), _vp(hb), _vp(params),
+                                    _vp(fo), _vp(lxo), _vp(lyo), _stream()), "dect_unrolled_step")
+    return fo, lxo, lyo
+
+
+def unrolled_step_backward(f, lx, ly, hb, params, gfo, glxo, glyo):
+    """Vector-Jacobian product of unrolled_step (dect_unrolled_step_backward):
+    returns (gf, glx, gly, ghb, gparams[4])."""
+    torch = _torch()
+    b, ny, nx = _unrolled_shape(f)
+    for t, n in ((f, "f"), (lx, "lx"), (ly, "ly"), (hb, "hb"), (gfo, "gf_out"),
+                 (glxo, "glx_out"), (glyo, "gly_out")):
+        _out(t, n, (b, ny, nx))
+    _out(params, "params", (4,))
+    gf, glx, gly, ghb = (torch.empty_like(f) for _ in range(4))
+    gp = torch.empty(4, device=f.device, dtype=torch.float32)
+    _check(lib().dect_unrolled_step_backward(nx, ny, b, _vp(f), _vp(lx), _vp(ly), _vp(hb),
+                                             _vp(params), _vp(gfo), _vp(glxo), _vp(glyo),
+                                             _vp(gf), _vp(glx), _vp(gly), _vp(ghb), _vp(gp),
+                                             _stream()), "dect_unrolled_step_backward")
+    return gf, glx, gly, ghb, gp
 
 
 def pls_params(p: C.PlsParams) -> dect_pls_params:

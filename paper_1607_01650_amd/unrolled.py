@@ -7,9 +7,12 @@ with the BB step replaced by a learnable step alpha_k and learnable
     G      = mu_k A^T (A f - g) + grad^T(rho_k (grad f - z) - lambda)   (Eq. 9)
     f     <- f - alpha_k G
     lambda <- lambda - xi_k (grad f - z)                                (Eq. 7)
-A and A^T are the hand-written projector pair (autograd-aware); the
-finite differences and shrinkage are elementwise torch ops on the device.
-Activations are checkpointed every `checkpoint_every` steps.
+Every step of it runs in libdect: A and A^T are the hand-written projector
+pair, r = A f - g is dect_unrolled_residual, and the differences, the
+shrinkage, G and both updates are dect_unrolled_step, whose backward is the
+hand-written dect_unrolled_step_backward.  Torch only records the graph and
+holds the tensors.  Activations are checkpointed every `checkpoint_every`
+steps.
 """
 from __future__ import annotations
 
@@ -21,50 +24,46 @@ from torch.utils.checkpoint import checkpoint
 
 from . import autograd as AG
 from . import configs as C
+from . import dect
 
 
-def grad2d(x: torch.Tensor):
-    """Backward differences of Eq. 2 (zero on the first column/row)."""
-    gx = torch.zeros_like(x)
-    gy = torch.zeros_like(x)
-    gx[..., :, 1:] = x[..., :, 1:] - x[..., :, :-1]
-    gy[..., 1:, :] = x[..., 1:, :] - x[..., :-1, :]
-    return gx, gy
+class _Residual(torch.autograd.Function):
+    """r = p - g (g is data: it gets no gradient)."""
+
+    @staticmethod
+    def forward(ctx, p, g):
+        return dect.unrolled_residual(p.contiguous(), g.contiguous())
+
+    @staticmethod
+    def backward(ctx, gr):
+        return gr, None
 
 
-def grad2d_T(px: torch.Tensor, py: torch.Tensor) -> torch.Tensor:
-    """Exact adjoint of grad2d."""
-    out = torch.zeros_like(px)
-    out[..., :, 1:] += px[..., :, 1:]
-    out[..., :, :-1] -= px[..., :, 1:]
-    out[..., 1:, :] += py[..., 1:, :]
-    out[..., :-1, :] -= py[..., 1:, :]
-    return out
+class _Step(torch.autograd.Function):
+    """(f, lambda_x, lambda_y, hb = A^T r, (mu, rho, xi, alpha)) -> (f', lambda')."""
 
+    @staticmethod
+    def forward(ctx, f, lx, ly, hb, params):
+        f, lx, ly, hb = (t.contiguous() for t in (f, lx, ly, hb))
+        params = params.contiguous()
+        ctx.save_for_backward(f, lx, ly, hb, params)
+        return dect.unrolled_step(f, lx, ly, hb, params)
 
-def shrink(vx: torch.Tensor, vy: torch.Tensor, t: torch.Tensor):
-    """Isotropic shrinkage max(|v| - t, 0) v / |v| (zero where |v| <= t).
-
-    |v| is evaluated as sqrt(max(|v|^2, 1e-30)): identical for |v| > 1e-15 (far
-    below any threshold t), and finite in value and gradient at v = 0.
-    """
-    n = torch.sqrt(torch.clamp(vx * vx + vy * vy, min=1e-30))
-    s = torch.clamp(n - t, min=0.0) / n
-    return s * vx, s * vy
+    @staticmethod
+    def backward(ctx, gfo, glxo, glyo):
+        f, lx, ly, hb, params = ctx.saved_tensors
+        cot = [torch.zeros_like(f) if t is None else t.contiguous() for t in (gfo, glxo, glyo)]
+        gf, glx, gly, ghb, gp = dect.unrolled_step_backward(f, lx, ly, hb, params, *cot)
+        return gf, glx, gly, ghb, gp
 
 
 def adm_step(f, lx, ly, g, geom: C.Geometry, mu, rho, xi, alpha):
-    """One unrolled ADM-TV step for a batch f [B, ny, nx], g [B, V, bins]."""
-    r = AG.project(f, geom) - g
-    h = mu * AG.backproject(r, geom)
-    dx, dy = grad2d(f)
-    zx, zy = shrink(dx - lx / rho, dy - ly / rho, 1.0 / rho)
-    G = h + grad2d_T(rho * (dx - zx) - lx, rho * (dy - zy) - ly)
-    f = f - alpha * G
-    nx_, ny_ = grad2d(f)
-    lx = lx - xi * (nx_ - zx)
-    ly = ly - xi * (ny_ - zy)
-    return f, lx, ly
+    """One unrolled ADM-TV step for a batch f [B, ny, nx], g [B, V, bins];
+    mu, rho, xi, alpha: 0-d float32 device tensors."""
+    r = _Residual.apply(AG.project(f, geom), g)
+    hb = AG.backproject(r, geom)
+    params = torch.stack((mu, rho, xi, alpha))
+    return _Step.apply(f, lx, ly, hb, params)
 
 
 class UnrolledADM(torch.nn.Module):

@@ -116,3 +116,27 @@ def test_volume_entry_points_validate_first(lib):
         dect.DECT_ERR_INVALID_ARG
     assert lib.dect_pls_edge_weights3(8, 8, 4, buf, -1.0, 0.1, buf, None) == \
         dect.DECT_ERR_INVALID_ARG
+
+
+def test_unrolled_entry_points_validate_first(lib):
+    """The unrolled step and its backward reject bad sizes, NULL buffers and
+    outputs that overlap inputs on the host, before any device work."""
+    a, b, c, d, e, p = (ct.c_void_p(4096 * k) for k in range(1, 7))
+    o1, o2, o3 = (ct.c_void_p(1 << 24 + k) for k in range(3))
+    inv = dect.DECT_ERR_INVALID_ARG
+    assert lib.dect_unrolled_residual(-1, a, b, c, None) == inv
+    assert lib.dect_unrolled_residual(8, None, b, c, None) == inv
+    assert lib.dect_unrolled_residual(0, None, None, None, None) == dect.DECT_OK
+    assert lib.dect_unrolled_step(0, 8, 1, a, b, c, d, p, o1, o2, o3, None) == inv
+    assert lib.dect_unrolled_step(8, 8, -1, a, b, c, d, p, o1, o2, o3, None) == inv
+    assert lib.dect_unrolled_step(8, 8, 1, a, b, None, d, p, o1, o2, o3, None) == inv
+    assert lib.dect_unrolled_step(8, 8, 1, a, b, c, d, p, a, o2, o3, None) == inv  # f_out = f
+    assert lib.dect_unrolled_step(8, 8, 1, a, b, c, d, p, o1, o1, o3, None) == inv
+    assert lib.dect_unrolled_step(8, 8, 0, a, b, c, d, p, o1, o2, o3, None) == dect.DECT_OK
+    g4 = ct.c_void_p(1 << 28)
+    assert lib.dect_unrolled_step_backward(8, 8, 1, a, b, c, d, p, e, o1, o2, o3,
+                                           ct.c_void_p(1 << 27), ct.c_void_p(1 << 26),
+                                           None, g4, None) == inv  # ghb NULL
+    assert lib.dect_unrolled_step_backward(8, 8, 1, a, b, c, d, p, e, o1, o2, e,
+                                           ct.c_void_p(1 << 27), ct.c_void_p(1 << 26),
+                                           ct.c_void_p(1 << 25), g4, None) == inv  # gf = gf_out

@@ -5,7 +5,11 @@
 * unrolled ADM forward vs the FP64 oracle of the same steps (rel-L2 <= 1e-4);
 * gradients w.r.t. the learnable step parameters vs central differences of
   the FP64 oracle;
-* checkpointing every 2 steps gives the same gradients as no checkpointing.
+* checkpointing every 2 steps gives the same gradients as no checkpointing;
+* one step (dect_unrolled_step) from a nonzero (f, lambda) vs the oracle
+  step, and its vector-Jacobian product (dect_unrolled_step_backward and the
+  projector pair) vs central differences of the oracle step along random
+  directions and along each parameter.
 """
 import numpy as np
 import pytest
@@ -136,3 +140,78 @@ def test_checkpointing_matches_plain_backward(torch):
         (f.double() ** 2).sum().backward()
         out.append(np.concatenate([p.grad.cpu().numpy() for p in model.parameters()]))
     assert np.array_equal(out[0], out[1])
+
+
+def _step_inputs(g, seed):
+    """f: a phantom image; lambda: random multipliers of the size rho times
+    the image's gradients, so that the shrinkage is active at some pixels
+    and not at others; g: the phantom's data plus noise.  All FP32."""
+    s = P.make_slice(g, seed, n_inserts=4, r_obj=25.0)
+    rng = np.random.default_rng(50 + seed)
+    f = f32(s.x_true[1] * (1.0 + 0.05 * rng.standard_normal(s.x_true[1].shape)))
+    lx = f32(0.02 * rng.standard_normal(f.shape))
+    ly = f32(0.02 * rng.standard_normal(f.shape))
+    return f, lx, ly, f32(s.sino[1])
+
+
+def test_unrolled_step_forward_parity(torch):
+    """One step from a nonzero (f, lambda): f' and lambda' vs the FP64
+    oracle step on the same FP32 inputs."""
+    from paper_1607_01650_amd import unrolled as U
+    g = SMALL
+    f, lx, ly, gd = _step_inputs(g, 5)
+    prm = (0.8, 512.0, 128.0, 3e-4)
+    t = [to_dev(torch, a)[None] for a in (f, lx, ly, gd)]
+    p = [torch.tensor(v, dtype=torch.float32, device="cuda") for v in prm]
+    with torch.no_grad():
+        fo, lxo, lyo = U.adm_step(t[0], t[1], t[2], t[3], g, *p)
+    ref = OU.step(g, gd, f, lx, ly, *[float(np.float32(v)) for v in prm])
+    errs = [rel_l2(to_np(a[0]), b) for a, b in zip((fo, lxo, lyo), ref)]
+    print(f"unrolled step: f' {errs[0]:.2e}, lambda_x' {errs[1]:.2e}, lambda_y' {errs[2]:.2e}",
+          flush=True)
+    assert max(errs) <= 1e-5
+
+
+def test_unrolled_step_vjp_vs_oracle_differences(torch):
+    """dect_unrolled_step_backward (with the projector pair's autograd):
+    <grad L, d> for L = <c, (f', lambda')> with random cotangents c, along
+    random directions d in (f, lambda_x, lambda_y) and along each of the
+    four parameters, against central differences of the FP64 oracle step."""
+    from paper_1607_01650_amd import unrolled as U
+    g = SMALL
+    f, lx, ly, gd = _step_inputs(g, 6)
+    prm = np.array([0.8, 512.0, 128.0, 3e-4], dtype=np.float32).astype(np.float64)
+    rng = np.random.default_rng(7)
+    cot = [rng.standard_normal(f.shape) for _ in range(3)]
+    t = [to_dev(torch, a)[None].requires_grad_(True) for a in (f, lx, ly)]
+    p = [torch.tensor(v, dtype=torch.float32, device="cuda", requires_grad=True) for v in prm]
+    out = U.adm_step(t[0], t[1], t[2], to_dev(torch, gd)[None], g, *p)
+    L = sum((o[0].double() * to_dev(torch, c).double()).sum() for o, c in zip(out, cot))
+    grads = torch.autograd.grad(L, t + p)
+    gx = [to_np(q[0]) for q in grads[:3]]
+    gp = [float(q) for q in grads[3:]]
+
+    def oracle_L(ff, xx, yy, pp):
+        return sum(np.sum(a * c) for a, c in zip(OU.step(g, gd, ff, xx, yy, *pp), cot))
+
+    base = [f, lx, ly]
+    for k in range(3):
+        d = [rng.standard_normal(f.shape) for _ in range(3)]
+        # small enough that no pixel's shrinkage crosses its kink |v| = 1/rho
+        # (the oracle's quotient is then stable to ~1e-8 as eps varies 10x)
+        eps = 1e-7 * max(np.abs(a).max() for a in base)
+        up = [b + eps * e for b, e in zip(base, d)]
+        dn = [b - eps * e for b, e in zip(base, d)]
+        fd = (oracle_L(*up, prm) - oracle_L(*dn, prm)) / (2 * eps)
+        an = sum(np.sum(a * e) for a, e in zip(gx, d))
+        print(f"step VJP direction {k}: analytic {an:.6e}, oracle differences {fd:.6e}",
+              flush=True)
+        assert abs(an - fd) <= 2e-4 * abs(fd), (k, an, fd)
+    for j, name in enumerate(("mu", "rho", "xi", "alpha")):
+        h = 1e-6
+        up, dn = prm.copy(), prm.copy()
+        up[j] *= 1 + h
+        dn[j] *= 1 - h
+        fd = (oracle_L(f, lx, ly, up) - oracle_L(f, lx, ly, dn)) / (2 * h * prm[j])
+        print(f"step VJP {name}: analytic {gp[j]:.6e}, oracle differences {fd:.6e}", flush=True)
+        assert abs(gp[j] - fd) <= 1e-3 * abs(fd), (name, gp[j], fd)
