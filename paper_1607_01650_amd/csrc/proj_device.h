@@ -6,6 +6,8 @@
 // interpolation tap are computed once and applied to both images.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace dect {
@@ -40,9 +42,13 @@ struct AdjShared {
 struct alignas(16) AdjRay {
     int64_t a, k;  // strip-relative 32.32 line coordinate at lane 0, slope
 };
-struct AdjStage {  // one 64-bin chunk per wavefront
-    AdjRay ray[kAdjWaves * 64];
-    f2v ly[kAdjWaves * 64];  // |path length| x sinogram value of each image
+// Stage slots: one 64-bin chunk per wavefront, then one null slot per
+// wavefront (a bin that puts zero weight on the spare line -1 and adds zero)
+// for the steps of a lane past its last bin.
+constexpr int kStageSlots = kAdjWaves * 64 + kAdjWaves;
+struct AdjStage {
+    AdjRay ray[kStageSlots];
+    f2v ly[kStageSlots];  // |path length| x sinogram value of each image
 };
 
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
@@ -248,6 +254,13 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
     for (int i = lane; i < kAccSize; i += 64) my[i] = E(0.f);
     // acc line j holds tap line t0 + j - kAccOff
     E *col = my + lane;
+    // this wavefront's null slot: tap line -1 (strip-relative) at every
+    // lane with weight zero on line 0, and zero values
+    if (lane == 0) {
+        stage.ray[kAdjWaves * 64 + wid] = AdjRay{-(int64_t(1) << 32), 0};
+        stage.ly[kAdjWaves * 64 + wid] = f2v(0.f);
+        if constexpr (SID) sid_stage[kAdjWaves * 64 + wid] = SidW{0xFFFFFFFFu, 0.f};
+    }
     const BinRange *sb = bins + (size_t)strip * V;
 
     const int v_begin = (int)((int64_t)V * g / nvg), v_end = (int)((int64_t)V * (g + 1) / nvg);
@@ -260,84 +273,101 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
         if (lo > hi) continue;
         const LaneRange lr = lanes[((size_t)strip * V + v) * kSL + lane];
         // a strip range too long for the table: every lane takes all of it
+        // (and bins that miss a lane's line are masked)
         const bool whole = hi - lo > kLaneRangeMax;
         const int lfirst = whole ? 0 : (int)lr.first, llast = whole ? hi - lo : (int)lr.last;
         const int sbase = wid * 64;
-        for (int cb = lo; cb <= hi; cb += 64) {
-            // stage: lane j holds bin cb + j (strip-relative line coordinate)
-            const int bj = cb + lane;
-            AdjRay me{0, 0};
-            f2v my_ly = f2v(0.f);
-            SidW my_sw{0xFFFFFFFFu, 0.f};
-            if (bj <= hi) {
-                const RayFwd t = rfv[bj];
-                me.a = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
-                me.k = t.k_fx;
-                const float L = fabsf(lv[bj]);
-                my_ly.x = L * sino[0][(size_t)v * B + bj];
-                if constexpr (NE > 1) my_ly.y = L * sino[NE - 1][(size_t)v * B + bj];
-                if constexpr (SID) my_sw = sid[(size_t)v * B + bj];
-            }
-            stage.ray[sbase + lane] = me;
-            stage.ly[sbase + lane] = my_ly;
-            if constexpr (SID) sid_stage[sbase + lane] = my_sw;
-            // this lane's bins in the chunk: [f, e], chunk-relative
-            const int rel = cb - lo;
-            const int f = max(lfirst, rel) - rel;
-            const int e = min(llast, rel + 63) - rel;
-            const int n = e - f + 1;
-            // no lane has more bins in a chunk than its whole range holds
-            const int steps = __builtin_amdgcn_readfirstlane(br.steps);
-            // one step: bin b (staged) at this lane.  A lane past its last bin,
-            // or taking a bin that misses its line (a strip range without
-            // lane ranges), adds zero to lines -1 and 0
-            auto step = [&](const AdjRay &b, f2v y, SidW sw, bool ok) {
-                const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
-                const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
-                ok = ok && qh >= -1 && qh <= kSW - 1;
-                const int i0 = ok ? qh : -1;
-                if (!ok) y = f2v(0.f);
-                const uint32_t lo = (uint32_t)p;
-                float w;
-                if constexpr (SID) w = (lo > sw.c ? (float)(lo - sw.c) * sw.inv : 0.f) * kTwoM32;
-                else w = (float)lo * kTwoM32;
-                E *pp = col + (i0 + kAccOff) * kSL;
-                E u0 = pp[0], u1 = pp[kSL];
-                if constexpr (NE == 1) {
-                    u0 += fmaf(-w, y.x, y.x);
-                    u1 = fmaf(w, y.x, u1);
-                } else {
-                    u0.x += fmaf(-w, y.x, y.x);
-                    u0.y += fmaf(-w, y.y, y.y);
-                    u1.x = fmaf(w, y.x, u1.x);
-                    u1.y = fmaf(w, y.y, u1.y);
+        const int snull = kAdjWaves * 64 + wid;
+        // no lane has more bins in a chunk than its whole range holds
+        const int steps = __builtin_amdgcn_readfirstlane(br.steps);
+        // the 64-bin chunks of the strip range; kExact: every bin a lane
+        // takes is one of its own (its first tap line lies in -1 .. kSW - 1
+        // by the host's exact per-lane ranges), so only the steps past its
+        // last bin need care, and they take the null slot
+        auto chunks = [&](auto exact_tag) {
+            constexpr bool kExact = decltype(exact_tag)::value;
+            for (int cb = lo; cb <= hi; cb += 64) {
+                // stage: lane j holds bin cb + j (strip-relative line coordinate)
+                const int bj = cb + lane;
+                AdjRay me{0, 0};
+                f2v my_ly = f2v(0.f);
+                SidW my_sw{0xFFFFFFFFu, 0.f};
+                if (bj <= hi) {
+                    const RayFwd t = rfv[bj];
+                    me.a = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
+                    me.k = t.k_fx;
+                    const float L = fabsf(lv[bj]);
+                    my_ly.x = L * sino[0][(size_t)v * B + bj];
+                    if constexpr (NE > 1) my_ly.y = L * sino[NE - 1][(size_t)v * B + bj];
+                    if constexpr (SID) my_sw = sid[(size_t)v * B + bj];
                 }
-                pp[0] = u0;
-                pp[kSL] = u1;
-            };
-            // two steps at a time, both bins' stage reads issued first
-            int t = 0;
-            for (; t + 1 < steps; t += 2) {
-                const bool ok0 = t < n, ok1 = t + 1 < n;
-                const int j0 = sbase + (ok0 ? f + t : 0), j1 = sbase + (ok1 ? f + t + 1 : 0);
-                const AdjRay b0 = stage.ray[j0], b1 = stage.ray[j1];
-                const f2v y0 = stage.ly[j0], y1 = stage.ly[j1];
-                SidW s0{0u, 0.f}, s1{0u, 0.f};
-                if constexpr (SID) {
-                    s0 = sid_stage[j0];
-                    s1 = sid_stage[j1];
+                stage.ray[sbase + lane] = me;
+                stage.ly[sbase + lane] = my_ly;
+                if constexpr (SID) sid_stage[sbase + lane] = my_sw;
+                // this lane's bins in the chunk: [f, e], chunk-relative
+                const int rel = cb - lo;
+                const int f = max(lfirst, rel) - rel;
+                const int e = min(llast, rel + 63) - rel;
+                const int n = e - f + 1;
+                // one step: bin b (staged) at this lane.  Masked mode: a lane
+                // past its last bin, or taking a bin that misses its line,
+                // adds zero to lines -1 and 0
+                auto step = [&](const AdjRay &b, f2v y, SidW sw, bool ok) {
+                    const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
+                    const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
+                    int i0 = qh;
+                    if constexpr (!kExact) {
+                        ok = ok && qh >= -1 && qh <= kSW - 1;
+                        i0 = ok ? qh : -1;
+                        if (!ok) y = f2v(0.f);
+                    }
+                    const uint32_t lo = (uint32_t)p;
+                    float w;
+                    if constexpr (SID) w = (lo > sw.c ? (float)(lo - sw.c) * sw.inv : 0.f) * kTwoM32;
+                    else w = (float)lo * kTwoM32;
+                    E *pp = col + (i0 + kAccOff) * kSL;
+                    E u0 = pp[0], u1 = pp[kSL];
+                    if constexpr (NE == 1) {
+                        u0 += fmaf(-w, y.x, y.x);
+                        u1 = fmaf(w, y.x, u1);
+                    } else {
+                        u0.x += fmaf(-w, y.x, y.x);
+                        u0.y += fmaf(-w, y.y, y.y);
+                        u1.x = fmaf(w, y.x, u1.x);
+                        u1.y = fmaf(w, y.y, u1.y);
+                    }
+                    pp[0] = u0;
+                    pp[kSL] = u1;
+                };
+                // the stage slot of step t at this lane
+                auto slot = [&](int t) {
+                    if constexpr (kExact) return t < n ? sbase + f + t : snull;
+                    else return sbase + (t < n ? f + t : 0);
+                };
+                // two steps at a time, both bins' stage reads issued first
+                int t = 0;
+                for (; t + 1 < steps; t += 2) {
+                    const int j0 = slot(t), j1 = slot(t + 1);
+                    const AdjRay b0 = stage.ray[j0], b1 = stage.ray[j1];
+                    const f2v y0 = stage.ly[j0], y1 = stage.ly[j1];
+                    SidW s0{0u, 0.f}, s1{0u, 0.f};
+                    if constexpr (SID) {
+                        s0 = sid_stage[j0];
+                        s1 = sid_stage[j1];
+                    }
+                    step(b0, y0, s0, t < n);
+                    step(b1, y1, s1, t + 1 < n);
                 }
-                step(b0, y0, s0, ok0);
-                step(b1, y1, s1, ok1);
+                if (t < steps) {
+                    const int j = slot(t);
+                    SidW sj{0u, 0.f};
+                    if constexpr (SID) sj = sid_stage[j];
+                    step(stage.ray[j], stage.ly[j], sj, t < n);
+                }
             }
-            if (t < steps) {
-                const bool ok = t < n;
-                const int j = sbase + (ok ? f + t : 0);
-                SidW sj{0u, 0.f};
-                if constexpr (SID) sj = sid_stage[j];
-                step(stage.ray[j], stage.ly[j], sj, ok);
-            }
-        }
+        };
+        if (whole) chunks(std::false_type{});
+        else chunks(std::true_type{});
     }
     __syncthreads();
     // the copies summed in wave order; stored in normal image layout

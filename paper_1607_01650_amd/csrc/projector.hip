@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj(const float *__restrict__ s
 {
     __shared__ AdjShared<NE> sh;
     __shared__ AdjStage stage;
-    __shared__ SidW sid_stage[SID ? kAdjWaves * 64 : 1];
+    __shared__ SidW sid_stage[SID ? kStageSlots : 1];
     // (strip, view group, items) blocks in XCD order: the blocks of one XCD
     // share a view group's rays and sinogram rows
     const unsigned item = xcd_order(block_linear(), grid_blocks());
