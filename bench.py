@@ -683,7 +683,7 @@ def unrolled_extra(steps: int, batch: int = 8):
         loss = ((f - target) ** 2).mean()
         loss.backward()
         opt.step()
-        return float(loss)
+        return float(loss.detach())
 
     step()
     torch.cuda.synchronize()

@@ -371,8 +371,8 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
  * projector call walking both volumes at once.  The iterate and the
  * residual A f - beta m are pairs of FP32 values updated in FP64 (the
  * residual by the recurrence r -= alpha A G), the rest of the state FP32,
- * reductions FP64.  Its work buffers (per energy 13 volumes and 4
- * projection sets) are library-owned per device and kept between calls;
+ * reductions FP64.  Its work buffers (per energy 15 volume-sized arrays
+ * and 4 projection sets) are library-owned per device and kept between calls;
  * the call synchronises the stream before returning.
  * DECT_ERR_NONFINITE when a logged objective or step is not finite.
  */
@@ -479,9 +479,9 @@ dect_status dect_count_samples(const dect_geometry *geom, int64_t *out);
 dect_status dect_release_caches(void);
 
 /*
- * Caller-provided device memory for the library's own buffers (SURVEY
- * boundary: the library owns its tables and workspace unless the caller
- * hands it one).  After dect_set_workspace(d_ptr, bytes) every device
+ * Caller-provided device memory for the library's own buffers (the
+ * library owns its tables and work buffers unless the caller hands it a
+ * region).  After dect_set_workspace(d_ptr, bytes) every device
  * allocation the library makes on the current device (geometry tables, work
  * buffers, ADM states and batches created from then on) is a consecutive
  * 256-byte-aligned piece of [d_ptr, d_ptr + bytes) instead of a hipMalloc;
