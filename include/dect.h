@@ -110,6 +110,11 @@ typedef struct {
     double *log;      /* host [max_iter+1][4] or NULL: per energy-pair row
                          {J_high(f^k), J_low(f^k), alpha_high^k, alpha_low^k};
                          filling it synchronises the stream */
+    double *log_aux;  /* host [max_iter+1][4] or NULL: per row {|grad f - z|_high,
+                         |grad f - z|_low, |G|_high, |G|_low} of the iteration's
+                         z-step and f-gradient (Eqs. 8-9), before its step; the
+                         final row holds zeros.  Filling it synchronises the
+                         stream.  (The batched call takes neither log.) */
 } dect_adm_params;
 
 /* PLS decomposition parameters (Eqs. 11-15, Sec. 2.4, Sec. 3). */

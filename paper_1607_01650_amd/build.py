@@ -43,7 +43,8 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(f"--- {src} ---\n{text}\n")
         raise RuntimeError("libdect build failed: " + ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -399,8 +399,10 @@ __global__ __launch_bounds__(256) void k_final_J(AdmScalars *__restrict__ sc,
     double J = tot[0] + 0.5 * mu * s.rr;
     int64_t row = s.iter - s.log_base;
     if (log && row >= 0 && row < log_rows) {
-        log[row * 4 + e] = J;
-        log[row * 4 + 2 + e] = s.alpha;
+        log[row * kLogW + e] = J;
+        log[row * kLogW + 2 + e] = s.alpha;
+        log[row * kLogW + 4 + e] = 0.0;
+        log[row * kLogW + 6 + e] = 0.0;
     }
     s.J = J;
 }
@@ -525,7 +527,7 @@ static AdmPtrs ptrs_of(dect_adm_state *S)
     P.p_ff = (double *)S->p_ff.ptr;
     P.p_gs = (double *)S->p_gs.ptr;
     P.log = (double *)S->logbuf.ptr;
-    P.log_rows = (int)(S->logbuf.bytes / 32);
+    P.log_rows = (int)(S->logbuf.bytes / (kLogW * sizeof(double)));
     P.sc = (AdmScalars *)S->sc.ptr;
     P.nb_tv = S->nb_tv;
     P.nb_fwd = S->nb_fwd;
@@ -579,6 +581,7 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     float *z_in = z + (size_t)par * 4 * N, *z_out = z + (size_t)(1 - par) * 4 * N;
     AdmScalars *sc = (AdmScalars *)S->sc.ptr;
     dim3 gtv((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY, 2);
+    DECT_TRACE("adm iteration");
     hipLaunchKernelGGL(S->coupled ? k_tv_fused<true> : k_tv_fused<false>, gtv, dim3(256), 0, s,
                        (const float *)S->f.ptr, (const float *)S->adjpart.ptr, S->nvg,
                        (float)S->mu, lam_in, z_in, lam_out, z_out, (float *)S->gpad.ptr,
@@ -597,7 +600,8 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     }
     hipLaunchKernelGGL(k_scalar, dim3(2), dim3(256), 0, s, sc, (const double *)S->p_tv.ptr,
                        S->nb_tv, (const double *)S->p_fwd.ptr, S->nb_fwd,
-                       (double *)S->logbuf.ptr, (int)(S->logbuf.bytes / 32), S->mu, S->rho,
+                       (double *)S->logbuf.ptr, (int)(S->logbuf.bytes / (kLogW * sizeof(double))),
+                       S->mu, S->rho,
                        S->nonneg ? 1 : 0, (const double *)S->p_rr.ptr, S->nbs, tol,
                        S->step_rule, (const double *)S->p_yy.ptr, S->nbi);
     DECT_HIP(hipGetLastError());
@@ -752,9 +756,10 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
     const size_t log_rows = (size_t)K + 1;
     // the device log keeps at least 4096 rows so that calls of different
     // lengths reuse it (and the captured graph that points at it)
-    if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, kLogRowsMin) * 4 * sizeof(double))))
+    if ((st = S->logbuf.ensure(std::max<size_t>(log_rows, kLogRowsMin) * kLogW * sizeof(double))))
         return st;
     if (!S->started) {
+        DECT_TRACE("adm set-up");
         const bool warm = (P->flags & DECT_WARM_START) != 0;
         if ((st = adm_start(S, P, mh, ml, warm ? xh : nullptr, warm ? xl : nullptr, s))) return st;
     }
@@ -785,22 +790,35 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         S->parity = 0;
         ++k;
     }
-    for (; k + 2 <= K; k += 2) DECT_HIP(hipGraphLaunch(S->graph, s));
+    if (k + 2 <= K) {
+        DECT_TRACE("adm iteration pairs (graph)");
+        for (; k + 2 <= K; k += 2) DECT_HIP(hipGraphLaunch(S->graph, s));
+    }
     if (k < K) {
         if ((st = launch_iter(S, 0, P->tol, s))) return st;
         S->parity = 1;
         ++k;
     }
     // outputs and the final objective
-    if ((st = adm_finish(*S->t, ptrs_of(S), xh, xl, S->mu, S->bh, S->bl, s, S->coupled)))
-        return st;
-    if (rep || P->log) {
+    {
+        DECT_TRACE("adm finish");
+        if ((st = adm_finish(*S->t, ptrs_of(S), xh, xl, S->mu, S->bh, S->bl, s, S->coupled)))
+            return st;
+    }
+    if (rep || P->log || P->log_aux) {
         DECT_HIP(hipStreamSynchronize(s));
         AdmScalars hs[2];
         DECT_HIP(hipMemcpy(hs, S->sc.ptr, sizeof(hs), hipMemcpyDeviceToHost));
-        if (P->log)
-            DECT_HIP(hipMemcpy(P->log, S->logbuf.ptr, log_rows * 4 * sizeof(double),
+        if (P->log || P->log_aux) {
+            std::vector<double> h(log_rows * kLogW);
+            DECT_HIP(hipMemcpy(h.data(), S->logbuf.ptr, h.size() * sizeof(double),
                                hipMemcpyDeviceToHost));
+            for (size_t r = 0; r < log_rows; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    if (P->log) P->log[r * 4 + c] = h[r * kLogW + c];
+                    if (P->log_aux) P->log_aux[r * 4 + c] = h[r * kLogW + 4 + c];
+                }
+        }
         dect_status rs = DECT_OK;
         int nf = 0;
         for (int e = 0; e < 2; ++e)
@@ -842,7 +860,7 @@ dect_status adm_size_run(const dect_geometry *g)
     auto S = std::make_unique<dect_adm_state>();
     dect_status st = state_alloc(S.get(), g);
     if (st) return st;
-    if ((st = S->logbuf.ensure(kLogRowsMin * 4 * sizeof(double))) ||
+    if ((st = S->logbuf.ensure(kLogRowsMin * kLogW * sizeof(double))) ||
         (st = S->apart.ensure(std::max<size_t>(1, adj_partial_floats(*S->t, 2, S->nvg)) * 4)) ||
         (st = S->p_yy.ensure((size_t)2 * S->nbi * 8)))
         return st;

@@ -512,6 +512,7 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     int stop[2] = {K, K};
     bool done[2] = {false, false};
     for (int k = 0; k < K && !(done[0] && done[1]); ++k) {
+        DECT_TRACE("adm3 iteration");
         for (int e = 0; e < 2; ++e) {
             if (done[e]) continue;
             hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_F],
@@ -579,12 +580,18 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     for (int e = 0; e < 2; ++e)
         for (int k = 0; k <= stop[e]; ++k)
             finite = finite && std::isfinite(row(e, k)[0]) && std::isfinite(row(e, k)[1]);
-    if (p->log)
-        for (int k = 0; k <= K; ++k)
-            for (int e = 0; e < 2; ++e) {  // rows after an energy's stop hold zeros
-                p->log[k * 4 + e] = k <= stop[e] ? row(e, k)[0] : 0.0;
-                p->log[k * 4 + 2 + e] = k <= stop[e] ? row(e, k)[1] : 0.0;
+    for (int k = 0; k <= K; ++k)
+        for (int e = 0; e < 2; ++e) {  // rows after an energy's stop hold zeros
+            const bool in = k <= stop[e];
+            if (p->log) {
+                p->log[k * 4 + e] = in ? row(e, k)[0] : 0.0;
+                p->log[k * 4 + 2 + e] = in ? row(e, k)[1] : 0.0;
             }
+            if (p->log_aux) {
+                p->log_aux[k * 4 + e] = in ? row(e, k)[2] : 0.0;
+                p->log_aux[k * 4 + 2 + e] = in ? row(e, k)[4] : 0.0;
+            }
+        }
     if (rep) {
         rep->iters = std::max(stop[0], stop[1]);
         rep->objective = row(0, stop[0])[0] + row(1, stop[1])[0];

@@ -23,6 +23,10 @@ static_assert(kGW * kGH <= 512 && kWW * kWH <= 512, "two pixels per thread at mo
 // FP64 partial sums one TV tile leaves per energy: TV(f), |G|^2, |grad G|^2,
 // |grad f - z|^2, |f|^2, <G_prev, h>, <G, h>
 constexpr int kTvParts = 7;
+// Device log row: J_high, J_low, alpha_high, alpha_low, |grad f - z|_high,
+// |grad f - z|_low, |G|_high, |G|_low (the last four before the row's step;
+// zero on the final row)
+constexpr int kLogW = 8;
 
 struct AdmScalars {
     double alpha;   // step used by the next update
@@ -419,8 +423,10 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
         const int64_t k = s.iter;
         int64_t row = k - s.log_base;
         if (log && row >= 0 && row < log_rows) {
-            log[row * 4 + col] = J;
-            log[row * 4 + 2 + col] = alpha;
+            log[row * kLogW + col] = J;
+            log[row * kLogW + 2 + col] = alpha;
+            log[row * kLogW + 4 + col] = sqrt(tot[3]);
+            log[row * kLogW + 6 + col] = sqrt(gg);
         }
         s.J = J;
         s.alpha = alpha;

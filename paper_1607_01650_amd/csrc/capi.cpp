@@ -88,6 +88,7 @@ dect_status dect_adm_tv_batched(dect_batch *batch, const float *const *d_m_high,
                                 void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_adm_tv_batched");
     return dect::adm_tv_batched(batch, d_m_high, d_m_low, d_x_high, d_x_low, iters, objective,
                                 (hipStream_t)stream);
 }
@@ -97,6 +98,7 @@ dect_status dect_batch_tune(dect_batch *batch, const float *const *d_m_high,
                             double *ms_per_iter, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_batch_tune");
     return dect::batch_tune(batch, d_m_high, d_m_low, iters, chosen_groups, ms_per_iter,
                             (hipStream_t)stream);
 }
@@ -120,6 +122,7 @@ dect_status dect_project(const dect_geometry *geom, const float *d_img, float *d
                          int32_t batch, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_project");
     return dect::project(geom, d_img, d_sino, batch, (hipStream_t)stream);
 }
 
@@ -127,6 +130,7 @@ dect_status dect_backproject(const dect_geometry *geom, const float *d_sino, flo
                              int32_t batch, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_backproject");
     return dect::backproject(geom, d_sino, d_img, batch, (hipStream_t)stream);
 }
 
@@ -134,6 +138,7 @@ dect_status dect_fbp(const dect_geometry *geom, const float *d_sino, float *d_im
                      void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_fbp");
     return dect::fbp(geom, d_sino, d_img, batch, (hipStream_t)stream);
 }
 
@@ -141,6 +146,7 @@ dect_status dect_cone_project(const dect_cone_geometry *geom, const float *d_vol
                               void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_cone_project");
     return dect::cone_project(geom, d_vol, d_proj, (hipStream_t)stream);
 }
 
@@ -148,6 +154,7 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
                                   float *d_vol, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_cone_backproject");
     return dect::cone_backproject(geom, d_proj, d_vol, (hipStream_t)stream);
 }
 
@@ -156,6 +163,7 @@ dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
                          float *d_x_low, dect_report *rep, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_adm_tv3");
     return dect::adm_tv3(geom, d_m_high, d_m_low, params, d_x_high, d_x_low, rep,
                          (hipStream_t)stream);
 }
@@ -166,6 +174,7 @@ dect_status dect_pls_decompose3(int32_t nx, int32_t ny, int32_t nz, const float 
                                 dect_report *rep, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_pls_decompose3");
     return dect::pls_decompose3(nx, ny, nz, d_x_high, d_x_low, params, d_edge_w, d_u_water,
                                 d_u_bone, rep, (hipStream_t)stream);
 }
@@ -182,6 +191,7 @@ dect_status dect_adm_tv(const dect_geometry *geom, const float *d_m_high, const 
                         dect_adm_state *state, dect_report *rep, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_adm_tv");
     return dect::adm_tv(geom, d_m_high, d_m_low, params, d_x_high, d_x_low, state, rep,
                         (hipStream_t)stream);
 }
@@ -208,6 +218,7 @@ dect_status dect_pls_decompose(int32_t nx, int32_t ny, const float *d_x_high,
                                dect_report *rep, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_pls_decompose");
     return dect::pls_decompose(nx, ny, d_x_high, d_x_low, params, d_edge_w, d_u_water, d_u_bone,
                                rep, (hipStream_t)stream);
 }
@@ -218,6 +229,7 @@ dect_status dect_pls_decompose_noalloc(int32_t nx, int32_t ny, const float *d_x_
                                        dect_report *rep, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_pls_decompose_noalloc");
     return dect::pls_decompose_noalloc(nx, ny, d_x_high, d_x_low, params, d_edge_w, d_u_water,
                                        d_u_bone, rep, (hipStream_t)stream);
 }
@@ -278,6 +290,7 @@ dect_status dect_unrolled_step(int32_t nx, int32_t ny, int32_t batch, const floa
                                float *d_ly_out, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_unrolled_step");
     return dect::unrolled_step(nx, ny, batch, d_f, d_lx, d_ly, d_hb, d_params, d_f_out, d_lx_out,
                                d_ly_out, (hipStream_t)stream);
 }
@@ -290,6 +303,7 @@ dect_status dect_unrolled_step_backward(int32_t nx, int32_t ny, int32_t batch, c
                                         float *d_gparams, void *stream)
 {
     dect::set_error("");
+    DECT_TRACE("dect_unrolled_step_backward");
     return dect::unrolled_step_backward(nx, ny, batch, d_f, d_lx, d_ly, d_hb, d_params, d_gf_out,
                                         d_glx_out, d_gly_out, d_gf, d_glx, d_gly, d_ghb,
                                         d_gparams, (hipStream_t)stream);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <memory>
@@ -24,6 +25,19 @@ dect_status fail(dect_status st, const std::string &msg);
             return ::dect::fail(DECT_ERR_HIP, std::string(#expr " failed: ") +            \
                                                   hipGetErrorString(e_));                 \
     } while (0)
+
+// -------------------------------------------------------------- tracing ---
+// A roctx range over a scope (host side: it brackets the enqueueing of the
+// scope's launches, and shows in rocprofv3 --marker-trace beside the kernels).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+#define DECT_TRACE_CAT2(a, b) a##b
+#define DECT_TRACE_CAT(a, b) DECT_TRACE_CAT2(a, b)
+#define DECT_TRACE(name) ::dect::TraceRange DECT_TRACE_CAT(trace_range_, __LINE__)(name)
 
 // ------------------------------------------------------------- geometry ---
 // Joseph line coordinate in 32.32 fixed point: the crossing of ray (v,b)

@@ -58,7 +58,8 @@ class dect_cone_geometry(ct.Structure):
 class dect_adm_params(ct.Structure):
     _fields_ = [("mu", ct.c_double), ("rho", ct.c_double), ("xi", ct.c_double),
                 ("beta_high", ct.c_double), ("beta_low", ct.c_double), ("max_iter", ct.c_int32),
-                ("tol", ct.c_double), ("flags", ct.c_int32), ("log", ct.POINTER(ct.c_double))]
+                ("tol", ct.c_double), ("flags", ct.c_int32), ("log", ct.POINTER(ct.c_double)),
+                ("log_aux", ct.POINTER(ct.c_double))]
 
 
 class dect_pls_params(ct.Structure):
@@ -347,8 +348,20 @@ class AdmState:
 
 
 class AdmResult:
-    def __init__(self, x_high, x_low, report, log):
+    def __init__(self, x_high, x_low, report, log, log_aux=None):
         self.x_high, self.x_low, self.report, self.log = x_high, x_low, report, log
+        self.log_aux = log_aux
+
+    @property
+    def primal_residual(self):
+        """|grad f - z| per logged iteration, [rows][2] (high, low); zero on
+        the final row."""
+        return None if self.log_aux is None else self.log_aux[:, 0:2]
+
+    @property
+    def grad_norm(self):
+        """|G| (the f-gradient of Eq. 9) per logged iteration, [rows][2]."""
+        return None if self.log_aux is None else self.log_aux[:, 2:4]
 
     @property
     def J(self):
@@ -367,7 +380,8 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
 
     m_high/m_low: [V, B] device sinograms.  x0: optional (x_high, x_low) warm
     start.  Returns x_high, x_low [ny, nx] and, with want_log, the per-iteration
-    log [max_iter+1, 4] = (J_high, J_low, alpha_high, alpha_low).
+    log [max_iter+1, 4] = (J_high, J_low, alpha_high, alpha_low) and the
+    auxiliary log (|grad f - z|, |G| per energy).
     """
     torch = _torch()
     _dev(m_high, "m_high", (geom.n_views, geom.n_bins))
@@ -389,13 +403,15 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
     flags |= _STEP_FLAGS[getattr(p, "step", "bb1")]
     _dev(xh, "x_high", (geom.ny, geom.nx))
     _dev(xl, "x_low", (geom.ny, geom.nx))
-    log = None
-    logp = None
+    log = aux = None
+    logp = auxp = None
     if want_log:
         log = np.zeros((p.max_iter + 1, 4))
+        aux = np.zeros((p.max_iter + 1, 4))
         logp = log.ctypes.data_as(ct.POINTER(ct.c_double))
+        auxp = aux.ctypes.data_as(ct.POINTER(ct.c_double))
     prm = dect_adm_params(p.mu, p.rho, p.xi, p.beta_high, p.beta_low, p.max_iter, p.tol, flags,
-                          logp)
+                          logp, auxp)
     rep = dect_report()
     st = lib().dect_adm_tv(GeomArg(geom).ref, ct.c_void_p(m_high.data_ptr()),
                            ct.c_void_p(m_low.data_ptr()), ct.byref(prm),
@@ -403,7 +419,7 @@ def adm_tv(m_high, m_low, geom: C.Geometry, p: C.AdmParams, x0=None,
                            state.handle if state is not None else None,
                            ct.byref(rep) if want_log else None, _stream())
     _check(st, "dect_adm_tv")
-    return AdmResult(xh, xl, rep if want_log else None, log)
+    return AdmResult(xh, xl, rep if want_log else None, log, aux)
 
 
 def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool = False,
@@ -436,19 +452,21 @@ def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool 
         if x0[1].data_ptr() != xl.data_ptr():
             xl.copy_(x0[1])
         flags |= DECT_WARM_START
-    log = None
-    logp = None
+    log = aux = None
+    logp = auxp = None
     if want_log:
         log = np.zeros((p.max_iter + 1, 4))
+        aux = np.zeros((p.max_iter + 1, 4))
         logp = log.ctypes.data_as(ct.POINTER(ct.c_double))
+        auxp = aux.ctypes.data_as(ct.POINTER(ct.c_double))
     prm = dect_adm_params(p.mu, p.rho, p.xi, p.beta_high, p.beta_low, p.max_iter, p.tol, flags,
-                          logp)
+                          logp, auxp)
     rep = dect_report()
     _check(lib().dect_adm_tv3(ConeArg(geom).ref, ct.c_void_p(m_high.data_ptr()),
                               ct.c_void_p(m_low.data_ptr()), ct.byref(prm),
                               ct.c_void_p(xh.data_ptr()), ct.c_void_p(xl.data_ptr()),
                               ct.byref(rep), _stream()), "dect_adm_tv3")
-    return AdmResult(xh, xl, rep if want_log else None, log)
+    return AdmResult(xh, xl, rep if want_log else None, log, aux)
 
 
 def pls_decompose3(x_high, x_low, p: C.PlsParams, out: Optional[Tuple] = None, edge_w=None):

@@ -76,6 +76,10 @@ def test_parity(torch, geom, iters, seed):
         assert jrel.max() <= 1e-4
         assert arel[:10].max() <= 1e-4
         assert arel.max() <= 1e-3
+        # auxiliary log: |grad f - z| (rows 1.., zero at the zero start) and |G|
+        pres = np.abs(r.log_aux[1:iters, e] - log[1:iters, 2]) / log[1:iters, 2]
+        gerr = np.abs(r.log_aux[:iters, 2 + e] - log[:iters, 4]) / log[:iters, 4]
+        assert pres.max() <= 1e-3 and gerr.max() <= 1e-4, (pres.max(), gerr.max())
     assert r.report.iters == iters
 
 

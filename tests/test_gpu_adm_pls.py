@@ -53,9 +53,19 @@ def test_adm_tiny_parity(torch, tiny):
     for e, xe in enumerate((r.x_high, r.x_low)):
         err = rel_l2(to_np(xe), ref[e].x)
         jerr = np.max(np.abs(r.J[:, e] - ref[e].J) / np.abs(ref[e].J))
-        print(f"tiny ADM energy {e}: image rel-L2 {err:.3e}, max J rel err {jerr:.3e}", flush=True)
+        # the auxiliary log: |grad f - z| and |G| of each iteration (Eqs. 8-9)
+        # (row 0: the zero start has grad f = z = 0)
+        pres = np.abs(r.primal_residual[1:50, e] - ref[e].log[1:50, 2]) / ref[e].log[1:50, 2]
+        gerr = np.abs(r.grad_norm[:50, e] - ref[e].log[:50, 4]) / ref[e].log[:50, 4]
+        print(f"tiny ADM energy {e}: image rel-L2 {err:.3e}, max J rel err {jerr:.3e}, "
+              f"|grad f - z| rel err {pres[:10].max():.2e} (k<=10) {pres.max():.2e}, "
+              f"|G| rel err {gerr[:11].max():.2e} {gerr.max():.2e}", flush=True)
         assert err <= 1e-4
         assert jerr <= 1e-5
+        assert r.primal_residual[0, e] == 0.0 and ref[e].log[0, 2] == 0.0
+        assert pres[:10].max() <= 1e-4 and pres.max() <= 1e-3
+        assert gerr[:11].max() <= 1e-4 and gerr.max() <= 1e-3
+        assert r.primal_residual[50, e] == 0.0 and r.grad_norm[50, e] == 0.0
 
 
 def test_adm_resume_bitwise(torch, tiny):
