@@ -6,21 +6,25 @@
 //              z^{k+1} = shrink(grad f^k - lambda^k / rho, 1/rho) (Eq. 8),
 //              G^k = h^k + grad^T(rho (grad f^k - z^{k+1}) - lambda^k) (Eq. 9),
 //              with per-block partial sums of TV(f^k), |G|^2, |grad G|^2,
-//              |grad f - z|^2 and |f|^2.  G is written straight into the two
-//              zero-padded layouts the forward projector reads.
+//              |grad f - z|^2, |f|^2, <G^{k-1}, h^k> and <G^k, h^k>.  G is
+//              written straight into the two zero-padded layouts the forward
+//              projector reads (G^{k-1} is read at each pixel first).
 //   fwd      : p = A G^k, |p|^2.
-//   scalar   : |r^k|^2 from the previous update's partials; c^k = |G^k|^2 /
-//              (mu |A G^k|^2 + rho |grad G^k|^2).  The BB1 step <s,s>/<s,y>
-//              of s = -alpha G^k, y = (mu A^T A + rho grad^T grad) s equals
-//              c^k, so alpha^{k+1} = c^k and alpha^0 = c^0 (the exact
-//              line-search step); logs J^k, counts the iteration and applies
-//              the relative-change stop rule (effective after this update).
+//   scalar   : |r^k|^2 from the previous update's partials; alpha^0 = |G^0|^2
+//              / (mu |A G^0|^2 + rho |grad G^0|^2) (the exact line-search
+//              step), then the BB1 step <s,s>/<s,y> of s = -alpha G^{k-1}, y
+//              = h^k - h^{k-1} + rho grad^T grad s: alpha |G^{k-1}|^2 /
+//              (<G^{k-1}, h^{k-1}> - <G^{k-1}, h^k> + alpha rho |grad
+//              G^{k-1}|^2), kept when the denominator is not positive; logs
+//              J^k, counts the iteration and applies the relative-change stop
+//              rule (effective after this update).
 //   update   : f^{k+1} = f^k - alpha^k G^k, r^{k+1} = r^k - alpha^k p (so r
 //              stays A f - g without projecting f), partials of |r^{k+1}|^2.
 //   adj      : h^{k+1} = mu A^T r^{k+1}.
 // Every reduction is a fixed-order tree in FP64: reruns are bitwise equal.
 // lambda and z alternate between two buffers (the stencil reads neighbours'
-// old values), so a captured graph holds an even/odd pair of iterations.
+// old values), so iterations are captured per starting parity: graphs of 8,
+// 2 and 1 iterations for each.
 #include <cmath>
 #include <cstring>
 
@@ -443,12 +447,23 @@ struct dect_adm_state {
     void *graph_log = nullptr;
     size_t graph_log_bytes = 0;
     double graph_tol = -1.0;
-    hipGraphExec_t graph = nullptr;
+    double graph_mu = -1.0, graph_rho = -1.0, graph_xi = -1.0;
+    // captured iterations: [start parity][kGraphIters index]
+    hipGraphExec_t graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     hipStream_t cap = nullptr;
     int parity = 0;  // lambda/z buffer holding the current values
+    void drop_graphs()
+    {
+        for (auto &gp : graph)
+            for (auto &gx : gp)
+                if (gx) {
+                    (void)hipGraphExecDestroy(gx);
+                    gx = nullptr;
+                }
+    }
     ~dect_adm_state()
     {
-        if (graph) (void)hipGraphExecDestroy(graph);
+        drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -676,17 +691,22 @@ static dect_status adm_start(dect_adm_state *S, const dect_adm_params *P, const 
     return DECT_OK;
 }
 
-// The graph of an even/odd iteration pair.
-static dect_status build_graph(dect_adm_state *S, double tol)
+// Iteration counts of the captured graphs (each replay of a longer graph
+// saves the gaps between replays of shorter ones).
+static constexpr int kGraphIters[3] = {1, 2, 8};
+
+// The graph of kGraphIters[gi] iterations starting on lambda/z parity `par`.
+static dect_status build_graph(dect_adm_state *S, double tol, int par, int gi)
 {
-    if (S->graph) {
-        (void)hipGraphExecDestroy(S->graph);
-        S->graph = nullptr;
+    hipGraphExec_t &out = S->graph[par][gi];
+    if (out) {
+        (void)hipGraphExecDestroy(out);
+        out = nullptr;
     }
     if (!S->cap) DECT_HIP(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
     DECT_HIP(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
-    dect_status st = launch_iter(S, 0, tol, S->cap);
-    if (!st) st = launch_iter(S, 1, tol, S->cap);
+    dect_status st = DECT_OK;
+    for (int i = 0; i < kGraphIters[gi] && !st; ++i) st = launch_iter(S, par ^ (i & 1), tol, S->cap);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(S->cap, &graph);
     if (st) {
@@ -694,7 +714,7 @@ static dect_status build_graph(dect_adm_state *S, double tol)
         return st;
     }
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&S->graph, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(DECT_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     return DECT_OK;
@@ -764,13 +784,17 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         if ((st = adm_start(S, P, mh, ml, warm ? xh : nullptr, warm ? xl : nullptr, s))) return st;
     }
     if ((st = adm_mark_log(ptrs_of(S), s))) return st;
-    // the log buffer and tol are baked into the graph's kernel arguments:
-    // rebuild only when they change
-    if (K >= 2 && (!S->graph || S->graph_log != S->logbuf.ptr ||
-                   S->graph_log_bytes != S->logbuf.bytes || S->graph_tol != P->tol ||
-                   S->graph_nonneg != (int)S->nonneg || S->graph_coupled != (int)S->coupled ||
-                   S->graph_step != S->step_rule)) {
-        if ((st = build_graph(S, P->tol))) return st;
+    // the log buffer, tol, the variant and (mu, rho, xi) are baked into the
+    // graphs' kernel arguments: drop them when these change (each is captured
+    // again when first needed)
+    if (S->graph_log != S->logbuf.ptr || S->graph_log_bytes != S->logbuf.bytes ||
+        S->graph_tol != P->tol || S->graph_nonneg != (int)S->nonneg ||
+        S->graph_coupled != (int)S->coupled || S->graph_step != S->step_rule ||
+        S->graph_mu != S->mu || S->graph_rho != S->rho || S->graph_xi != S->xi) {
+        S->drop_graphs();
+        S->graph_mu = S->mu;
+        S->graph_rho = S->rho;
+        S->graph_xi = S->xi;
         S->graph_log = S->logbuf.ptr;
         S->graph_log_bytes = S->logbuf.bytes;
         S->graph_tol = P->tol;
@@ -785,18 +809,28 @@ dect_status adm_tv(const dect_geometry *g, const float *mh, const float *ml,
         ++k;
     }
     if (k > 0 || K > 0) S->fresh = false;
-    if (S->parity == 1 && k < K) {  // realign so the graph starts on parity 0
-        if ((st = launch_iter(S, 1, P->tol, s))) return st;
-        S->parity = 0;
-        ++k;
+    // runs of 8, then pairs, then a single iteration, each replayed from a
+    // graph captured for the current parity.  A call of two or more
+    // iterations captures all six shapes at once, so that later calls (a
+    // resumed state lands on either parity) replay without capturing; a call
+    // of one iteration captures none.
+    if (K - k >= 2 && !S->graph[0][1]) {
+        DECT_TRACE("adm graph capture");
+        for (int par = 0; par < 2; ++par)
+            for (int gi = 0; gi < 3; ++gi)
+                if ((st = build_graph(S, P->tol, par, gi))) return st;
     }
     if (k + 2 <= K) {
-        DECT_TRACE("adm iteration pairs (graph)");
-        for (; k + 2 <= K; k += 2) DECT_HIP(hipGraphLaunch(S->graph, s));
+        DECT_TRACE("adm iterations (graph)");
+        for (int gi = 2; gi >= 1; --gi) {
+            const int n = kGraphIters[gi];  // even: the parity is unchanged
+            for (; k + n <= K; k += n) DECT_HIP(hipGraphLaunch(S->graph[S->parity][gi], s));
+        }
     }
     if (k < K) {
-        if ((st = launch_iter(S, 0, P->tol, s))) return st;
-        S->parity = 1;
+        if (S->graph[S->parity][0]) DECT_HIP(hipGraphLaunch(S->graph[S->parity][0], s));
+        else if ((st = launch_iter(S, S->parity, P->tol, s))) return st;
+        S->parity ^= 1;
         ++k;
     }
     // outputs and the final objective

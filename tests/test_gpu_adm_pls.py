@@ -236,3 +236,22 @@ def test_pls_parity_shared_inputs_512(torch, gamma):
     differ, near = edge_weights_agree(wg, em)
     print(f"PLS 512x512 edge map: {differ} pairs differ, {near} pixels near the threshold",
           flush=True)
+
+
+def test_adm_parameters_change_between_calls(torch, tiny):
+    """Calls without a state reuse the library's state of the geometry; a
+    call with other (mu, rho, xi) must not replay iterations captured with
+    the previous ones: it equals the same run on a fresh state, bit for bit,
+    for even and odd iteration counts."""
+    dect = _dect()
+    g = C.TINY
+    mh, ml = to_dev(torch, tiny.sino[0]), to_dev(torch, tiny.sino[1])
+    p = C.default_adm_params(g, 6)
+    for change, iters in (({"mu": 2.0 * p.mu}, 6), ({"rho": 0.5 * p.rho, "xi": 0.5 * p.xi}, 7)):
+        dect.adm_tv(mh, ml, g, p)  # captures the iterations with p
+        q = dataclasses.replace(p, max_iter=iters, **change)
+        got = dect.adm_tv(mh, ml, g, q)
+        st = dect.AdmState(g)
+        want = dect.adm_tv(mh, ml, g, q, state=st)
+        st.close()
+        assert torch.equal(got.x_high, want.x_high) and torch.equal(got.x_low, want.x_low), change
