@@ -86,7 +86,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
     constexpr int MT = conv_mt(NT);
     constexpr int TR = 2 * MT;
     constexpr int CoutP = NT * 16;
-    __shared__ __align__(16) unsigned char lds_raw[kConvLds];
+    // dynamic LDS, sized by the launch to this layer's window and output
+    // tile (conv_fwd_lds): small layers keep more blocks per CU
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     u16 *win = (u16 *)lds_raw;
     const int n = blockIdx.z, r0 = blockIdx.y * TR, c0 = blockIdx.x * 32;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -833,6 +835,18 @@ inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+// LDS bytes k_conv_fwd<NT> uses for a layer: the largest staged input window
+// and, unless an FP32 tile goes straight from the registers, the output tile.
+static size_t conv_fwd_lds(int nt, int Cin, int ks, int out_f32)
+{
+    const int mt = conv_mt(nt), tr = 2 * mt, halo = ks == 3 ? 1 : 0;
+    const size_t cc = (size_t)std::min(kConvChunk, Cin);
+    const size_t win = (size_t)(tr + 2 * halo) * (32 + 2 * halo) * (cc + 8) * 2;
+    const size_t tile = (size_t)tr * 32 * nt * 16 * (out_f32 ? 4 : 2);
+    const bool tile_in_lds = !(out_f32 && tile > (size_t)kConvLds);
+    return std::max(win, tile_in_lds ? tile : (size_t)0);
+}
+
 extern "C" {
 
 const char *dect_nn_last_error(void) { return g_nn_err; }
@@ -852,8 +866,9 @@ dect_status dect_nn_conv_fwd(const void *x, const void *w, const float *bias, vo
 #define CASE(nt)                                                                         \
     case nt: {                                                                           \
         dim3 grid((W + 31) / 32, (H + 2 * conv_mt(nt) - 1) / (2 * conv_mt(nt)), N);      \
-        hipLaunchKernelGGL(k_conv_fwd<nt>, grid, dim3(256), 0, s, X, Wk, bias, y, H, W, Cin, \
-                           Cout, ksize, relu, out_f32);                                  \
+        hipLaunchKernelGGL(k_conv_fwd<nt>, grid, dim3(256),                                \
+                           (unsigned)conv_fwd_lds(nt, Cin, ksize, out_f32), s, X, Wk, bias, y, \
+                           H, W, Cin, Cout, ksize, relu, out_f32);                       \
     } break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
