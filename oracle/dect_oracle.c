@@ -29,8 +29,9 @@
  *                                gradient magnitude and threshold in FP64
  *   or_laplacian                 the Hessian of R(u) (Eq. 14), halved
  *   or_pcg                       Jacobi-preconditioned CG for Eq. 15
- *   or_pcg_att                   the attenuation-space variant |x - Du|^2 +
- *                                gamma R(u), both materials coupled
+ *   or_pcg_att / or_pcg_att3     the attenuation-space variant |x - Du|^2 +
+ *                                gamma R(u), both materials coupled (image and
+ *                                volume)
  *
  * Readings of the paper taken here (each is also listed in the design notes):
  *   - separable TV per energy block, zero difference on the first row/column;
@@ -695,19 +696,23 @@ int or_pcg(int nx, int ny, const double *er, const double *ed, double gamma, con
  * conjugate gradients preconditioned with the 2 x 2 per-pixel diagonal block
  * D^T D + gamma diag(L), from u = D^{-1} x, until |res| <= tol |D^T x| (joint
  * norms over both materials) or max_iter iterations.  Returns the iterations.
+ * The core takes the grid's L (lapf on one material image) and diag(L) (dg),
+ * so that the image and the volume solvers share it.
  */
-int or_pcg_att(int nx, int ny, const double *er, const double *ed, double e1h, double e2h,
-               double e1l, double e2l, double gamma, const double *xh, const double *xl,
-               double *u1, double *u2, int max_iter, double tol, double *relres)
+typedef void (*or_lap_fn)(const void *ctx, const double *u, double *out);
+
+static int pcg_att_core(size_t N, or_lap_fn lapf, const void *ctx, const double *dg, double e1h,
+                        double e2h, double e1l, double e2l, double gamma, const double *xh,
+                        const double *xl, double *u1, double *u2, int max_iter, double tol,
+                        double *relres)
 {
-    const size_t N = (size_t)nx * ny;
     /* D^T D = [[g11, g12], [g12, g22]] */
     const double g11 = e1h * e1h + e1l * e1l, g12 = e1h * e2h + e1l * e2l;
     const double g22 = e2h * e2h + e2l * e2l;
     double *c = malloc(2 * N * sizeof(double)), *u = malloc(2 * N * sizeof(double));
     double *res = malloc(2 * N * sizeof(double)), *z = malloc(2 * N * sizeof(double));
     double *p = malloc(2 * N * sizeof(double)), *q = malloc(2 * N * sizeof(double));
-    double *lap = malloc(N * sizeof(double)), *dg = malloc(N * sizeof(double));
+    double *lap = malloc(N * sizeof(double));
     double det = e1h * e2l - e2h * e1l;
     for (size_t i = 0; i < N; ++i) {
         c[i] = e1h * xh[i] + e1l * xl[i];
@@ -715,20 +720,10 @@ int or_pcg_att(int nx, int ny, const double *er, const double *ed, double e1h, d
         u[i] = (e2l * xh[i] - e2h * xl[i]) / det;
         u[N + i] = (e1h * xl[i] - e1l * xh[i]) / det;
     }
-    for (int r = 0; r < ny; ++r)
-        for (int cc = 0; cc < nx; ++cc) {
-            size_t i = (size_t)r * nx + cc;
-            double d = 0.0;
-            if (cc + 1 < nx) d += er[i];
-            if (cc >= 1) d += er[i - 1];
-            if (r + 1 < ny) d += ed[i];
-            if (r >= 1) d += ed[i - nx];
-            dg[i] = d;
-        }
     /* q = A v for the two-material vector v */
     #define APPLY(v, out)                                                         \
         for (int m = 0; m < 2; ++m) {                                             \
-            or_laplacian(nx, ny, er, ed, (v) + m * N, lap);                       \
+            lapf(ctx, (v) + m * N, lap);                                          \
             for (size_t i = 0; i < N; ++i) {                                      \
                 double dd = m == 0 ? g11 * (v)[i] + g12 * (v)[N + i]              \
                                    : g12 * (v)[i] + g22 * (v)[N + i];             \
@@ -773,7 +768,41 @@ int or_pcg_att(int nx, int ny, const double *er, const double *ed, double e1h, d
     memcpy(u1, u, N * sizeof(double));
     memcpy(u2, u + N, N * sizeof(double));
     if (relres) *relres = rn / cn;
-    free(c); free(u); free(res); free(z); free(p); free(q); free(lap); free(dg);
+    free(c); free(u); free(res); free(z); free(p); free(q); free(lap);
+    return it;
+}
+
+typedef struct {
+    int nx, ny;
+    const double *er, *ed;
+} or_lap2_ctx;
+
+static void lap2_of(const void *ctx, const double *u, double *out)
+{
+    const or_lap2_ctx *k = (const or_lap2_ctx *)ctx;
+    or_laplacian(k->nx, k->ny, k->er, k->ed, u, out);
+}
+
+int or_pcg_att(int nx, int ny, const double *er, const double *ed, double e1h, double e2h,
+               double e1l, double e2l, double gamma, const double *xh, const double *xl,
+               double *u1, double *u2, int max_iter, double tol, double *relres)
+{
+    const size_t N = (size_t)nx * ny;
+    double *dg = malloc(N * sizeof(double));
+    for (int r = 0; r < ny; ++r)
+        for (int cc = 0; cc < nx; ++cc) {
+            size_t i = (size_t)r * nx + cc;
+            double d = 0.0;
+            if (cc + 1 < nx) d += er[i];
+            if (cc >= 1) d += er[i - 1];
+            if (r + 1 < ny) d += ed[i];
+            if (r >= 1) d += ed[i - nx];
+            dg[i] = d;
+        }
+    const or_lap2_ctx ctx = {nx, ny, er, ed};
+    int it = pcg_att_core(N, lap2_of, &ctx, dg, e1h, e2h, e1l, e2l, gamma, xh, xl, u1, u2,
+                          max_iter, tol, relres);
+    free(dg);
     return it;
 }
 
@@ -1264,5 +1293,45 @@ int or_pcg3(int nx, int ny, int nz, const double *ex, const double *ey, const do
     }
     if (relres) *relres = rn / bn;
     free(res); free(zv); free(p); free(q); free(dinv);
+    return it;
+}
+
+typedef struct {
+    int nx, ny, nz;
+    const double *ex, *ey, *ez;
+} or_lap3_ctx;
+
+static void lap3_of(const void *ctx, const double *u, double *out)
+{
+    const or_lap3_ctx *k = (const or_lap3_ctx *)ctx;
+    or_laplacian3(k->nx, k->ny, k->nz, k->ex, k->ey, k->ez, u, out);
+}
+
+/* Attenuation-space PLS on a volume (as or_pcg_att, with R of Eq. 14 over
+ * the six face neighbours). */
+int or_pcg_att3(int nx, int ny, int nz, const double *ex, const double *ey, const double *ez,
+                double e1h, double e2h, double e1l, double e2l, double gamma, const double *xh,
+                const double *xl, double *u1, double *u2, int max_iter, double tol,
+                double *relres)
+{
+    const size_t P = (size_t)nx * ny, N = P * nz;
+    double *dg = malloc(N * sizeof(double));
+    for (int z = 0; z < nz; ++z)
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)z * P + (size_t)r * nx + c;
+                double d = 0.0;
+                if (c + 1 < nx) d += ex[i];
+                if (c >= 1) d += ex[i - 1];
+                if (r + 1 < ny) d += ey[i];
+                if (r >= 1) d += ey[i - nx];
+                if (z + 1 < nz) d += ez[i];
+                if (z >= 1) d += ez[i - P];
+                dg[i] = d;
+            }
+    const or_lap3_ctx ctx = {nx, ny, nz, ex, ey, ez};
+    int it = pcg_att_core(N, lap3_of, &ctx, dg, e1h, e2h, e1l, e2l, gamma, xh, xl, u1, u2,
+                          max_iter, tol, relres);
+    free(dg);
     return it;
 }

@@ -90,6 +90,9 @@ def lib():
         L.or_pcg3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, d, pd, pd, ct.c_int, d,
                               pd]
         L.or_pcg3.restype = ct.c_int
+        L.or_pcg_att3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, d, d, d, d, d, pd,
+                                  pd, pd, pd, ct.c_int, d, pd]
+        L.or_pcg_att3.restype = ct.c_int
         L.or_adm3.restype = ct.c_int
         L.or_grad3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
         L.or_gradT3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
@@ -406,11 +409,33 @@ def pcg3(ex, ey, ez, gamma: float, b, max_iter: int = 500, tol: float = 1e-12):
     return u, int(it), float(rr.value)
 
 
-def pls3(xh, xl, p, tol: float = 1e-12):
+def pcg_att3(ex, ey, ez, eta, gamma: float, xh, xl, max_iter: int = 500, tol: float = 1e-12):
+    """Attenuation-space PLS system on a volume [nz][ny][nx] with the
+    six-neighbour L, both materials coupled; returns (u1, u2, iters, relres)."""
+    ex, ey, ez, xh, xl = _f64(ex), _f64(ey), _f64(ez), _f64(xh), _f64(xl)
+    nz, ny, nx = xh.shape
+    u1, u2 = np.empty_like(xh), np.empty_like(xh)
+    rr = ct.c_double(0.0)
+    it = lib().or_pcg_att3(nx, ny, nz, _p(ex), _p(ey), _p(ez), *[float(e) for e in eta],
+                           float(gamma), _p(xh), _p(xl), _p(u1), _p(u2), int(max_iter),
+                           float(tol), ct.byref(rr))
+    return u1, u2, int(it), float(rr.value)
+
+
+def pls3(xh, xl, p, tol: float = 1e-12, edge_w=None):
     """3-D decomposition of volumes [nz][ny][nx]: D^{-1} x per voxel, 3-D
-    Prewitt edge weights on x_l, PCG per material with the six-neighbour L."""
+    Prewitt edge weights on x_l (or the given [3][nz][ny][nx] map), then PCG
+    per material with the six-neighbour L (image mode) or the coupled
+    attenuation-space system (p.mode == 1)."""
+    if edge_w is None:
+        ex, ey, ez = edges3(xl, p.edge_tau, p.edge_eps).weights
+    else:
+        ex, ey, ez = edge_w[0], edge_w[1], edge_w[2]
+    if getattr(p, "mode", 0) == 1:
+        eta = (p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
+        u1, u2, it, _ = pcg_att3(ex, ey, ez, eta, p.gamma, xh, xl, p.max_iter, tol)
+        return u1, u2, it
     b1, b2 = dinv(xh, xl, p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
-    ex, ey, ez = edges3(xl, p.edge_tau, p.edge_eps).weights
     u1, i1, _ = pcg3(ex, ey, ez, p.gamma, b1, p.max_iter, tol)
     u2, i2, _ = pcg3(ex, ey, ez, p.gamma, b2, p.max_iter, tol)
     return u1, u2, max(i1, i2)

@@ -8,11 +8,19 @@ over the six face neighbours, edges from the 3-D Prewitt operator):
   pair by pair over the face neighbours; L 1 = 0; on a one-slice volume it is
   the 2-D Laplacian, bit for bit;
 * PCG solves (I + gamma L) u = b as numpy.linalg.solve does on the dense
-  matrix assembled pair by pair.
+  matrix assembled pair by pair;
+* the attenuation-space system on a volume, (D^T D (x) I + gamma I (x) L) u
+  = D^T x, is solved as numpy.linalg.solve does on that matrix assembled from
+  the 2 x 2 D of Eq. 12 and the pairwise L; gamma = 0 gives D^{-1} x; a
+  one-slice volume gives the 2-D solver's result bit for bit.
 """
 import numpy as np
 
 from oracle import oracle as O
+from paper_1607_01650_amd import configs as C
+
+ETA = (C.PlsParams().eta_water_high, C.PlsParams().eta_bone_high,
+       C.PlsParams().eta_water_low, C.PlsParams().eta_bone_low)
 
 
 def test_z_step_marks_two_slices():
@@ -103,3 +111,54 @@ def test_pcg3_matches_dense_solve():
     u, it, rr = O.pcg3(w[0], w[1], w[2], gamma, b, 500, 1e-13)
     ref = np.linalg.solve(A, b.reshape(-1)).reshape(nz, ny, nx)
     assert np.abs(u - ref).max() <= 1e-11 * np.abs(ref).max() and rr <= 1e-13 and it < 500
+
+
+def _vol_weights(rng, nz, ny, nx):
+    w = [np.where(rng.random((nz, ny, nx)) < 0.2, 0.1, 1.0) for _ in range(3)]
+    w[0][:, :, -1] = 0.0
+    w[1][:, -1, :] = 0.0
+    w[2][-1] = 0.0
+    return w
+
+
+def test_attenuation_solver_matches_dense_solve():
+    rng = np.random.default_rng(3)
+    nz, ny, nx = 3, 5, 4
+    N = nx * ny * nz
+    w = _vol_weights(rng, nz, ny, nx)
+    gamma = 2e-3
+    L = np.zeros((N, N))
+    wf = [a.reshape(-1) for a in w]
+    for a, i, k in _pairs(nx, ny, nz):
+        L[i, i] += wf[a][i]
+        L[k, k] += wf[a][i]
+        L[i, k] -= wf[a][i]
+        L[k, i] -= wf[a][i]
+    e1h, e2h, e1l, e2l = ETA
+    D = np.array([[e1h, e2h], [e1l, e2l]])
+    A = np.kron(D.T @ D, np.eye(N)) + gamma * np.kron(np.eye(2), L)
+    xh = 0.02 + 0.01 * rng.random((nz, ny, nx))
+    xl = 0.025 + 0.02 * rng.random((nz, ny, nx))
+    rhs = np.concatenate([D[0, 0] * xh.ravel() + D[1, 0] * xl.ravel(),
+                          D[0, 1] * xh.ravel() + D[1, 1] * xl.ravel()])
+    ref = np.linalg.solve(A, rhs)
+    u1, u2, it, rr = O.pcg_att3(w[0], w[1], w[2], ETA, gamma, xh, xl, 2000, 1e-14)
+    got = np.concatenate([u1.ravel(), u2.ravel()])
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max() and rr <= 1e-14 and it < 2000
+    # gamma = 0: the direct decomposition
+    d1, d2 = O.dinv(xh, xl, *ETA)
+    z1, z2, _, _ = O.pcg_att3(w[0], w[1], w[2], ETA, 0.0, xh, xl, 50, 1e-14)
+    assert np.abs(z1 - d1).max() <= 1e-12 * np.abs(d1).max()
+    assert np.abs(z2 - d2).max() <= 1e-12 * np.abs(d2).max()
+
+
+def test_attenuation_solver_one_slice_is_2d():
+    rng = np.random.default_rng(4)
+    ny, nx = 9, 11
+    w = _vol_weights(rng, 1, ny, nx)
+    w[2][:] = 0.0
+    xh = 0.02 + 0.01 * rng.random((1, ny, nx))
+    xl = 0.025 + 0.02 * rng.random((1, ny, nx))
+    a1, a2, ia, ra = O.pcg_att3(w[0], w[1], w[2], ETA, 1e-3, xh, xl, 200, 1e-12)
+    b1, b2, ib, rb = O.pcg_att(w[0][0], w[1][0], ETA, 1e-3, xh[0], xl[0], 200, 1e-12)
+    assert ia == ib and np.array_equal(a1[0], b1) and np.array_equal(a2[0], b2)
