@@ -387,18 +387,23 @@ dect_status dect_adm_tv3(const dect_cone_geometry *geom, const float *d_m_high,
 
 /*
  * PLS decomposition of volumes (Eqs. 11-15 with R of Eq. 14 over the six
- * face neighbours): u = D^{-1} x per voxel (Eq. 12), then (I + gamma L) u_m
- * = (D^{-1} x)_m per material by Jacobi-PCG from u = D^{-1} x, L the
- * six-neighbour Laplacian with pair weights from d_edge_w.  Device buffers
- * d_x_* [nz][ny][nx] in, d_u_water / d_u_bone [nz][ny][nx] out.
+ * face neighbours), L the six-neighbour Laplacian with pair weights from
+ * d_edge_w.  DECT_PLS_IMAGE: u = D^{-1} x per voxel (Eq. 12), then (I +
+ * gamma L) u_m = (D^{-1} x)_m per material by Jacobi-PCG from u = D^{-1} x
+ * (FP32 vectors, FP64 dot products).  DECT_PLS_ATTENUATION: the coupled
+ * system (D^T D (x) I + gamma I (x) L) u = D^T x of |x - D u|^2 + gamma R(u),
+ * block-Jacobi CG from D^{-1} x with one tolerance over both materials, in
+ * FP64.  Device buffers d_x_* [nz][ny][nx] in, d_u_water / d_u_bone
+ * [nz][ny][nx] out.
  * d_edge_w: NULL to detect edges on d_x_low (dect_pls_edge_weights3), or a
  *   [3][nz][ny][nx] map of pair weights (x, y and z pairs as there).
- * params as for dect_pls_decompose with mode DECT_PLS_IMAGE only (else
- * DECT_ERR_INVALID_ARG); stops when |res| <= tol |b| or after max_iter
- * iterations per material.  Work buffers (about 10 volumes) are
- * library-owned per device and kept between calls; the call synchronises
- * the stream.  rep: iters (the larger of the two materials) and
- * pcg_residual.
+ * params as for dect_pls_decompose; stops when |res| <= tol |b| or after
+ * max_iter iterations (per material in image mode).  Work buffers (about 10
+ * FP32 volumes in image mode, 10 FP64 ones in the attenuation mode) are
+ * library-owned per device and kept between calls; the call synchronises the
+ * stream.  rep: iters (the larger of the two materials) and pcg_residual;
+ * DECT_WARN_MAXITER (also returned) when max_iter stopped a solve above its
+ * tolerance, the outputs then holding the last iterate.
  */
 dect_status dect_pls_decompose3(int32_t nx, int32_t ny, int32_t nz, const float *d_x_high,
                                 const float *d_x_low, const dect_pls_params *params,

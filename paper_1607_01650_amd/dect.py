@@ -470,9 +470,11 @@ def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool 
 
 
 def pls_decompose3(x_high, x_low, p: C.PlsParams, out: Optional[Tuple] = None, edge_w=None):
-    """PLS decomposition of volumes [nz, ny, nx] (dect_pls_decompose3, image-space
-    system, six-neighbour R): returns (u_water, u_bone, report).  edge_w: None
-    (edges detected on x_low) or a [3, nz, ny, nx] pair-weight map."""
+    """PLS decomposition of volumes [nz, ny, nx] (dect_pls_decompose3,
+    six-neighbour R; p.mode 0 the image-space system, 1 the attenuation-space
+    one): returns (u_water, u_bone, report); report.status is
+    DECT_WARN_MAXITER when max_iter stopped a solve above tolerance.  edge_w:
+    None (edges detected on x_low) or a [3, nz, ny, nx] pair-weight map."""
     torch = _torch()
     if x_high.dim() != 3:
         raise ValueError("x_high must be [nz, ny, nx]")
@@ -493,10 +495,12 @@ def pls_decompose3(x_high, x_low, p: C.PlsParams, out: Optional[Tuple] = None, e
                           p.gamma, p.edge_eps, p.edge_tau, p.max_iter, p.tol,
                           int(getattr(p, "mode", 0)))
     rep = dect_report()
-    _check(lib().dect_pls_decompose3(nx, ny, nz, ct.c_void_p(x_high.data_ptr()),
-                                     ct.c_void_p(x_low.data_ptr()), ct.byref(prm), wp,
-                                     ct.c_void_p(u1.data_ptr()), ct.c_void_p(u2.data_ptr()),
-                                     ct.byref(rep), _stream()), "dect_pls_decompose3")
+    st = lib().dect_pls_decompose3(nx, ny, nz, ct.c_void_p(x_high.data_ptr()),
+                                   ct.c_void_p(x_low.data_ptr()), ct.byref(prm), wp,
+                                   ct.c_void_p(u1.data_ptr()), ct.c_void_p(u2.data_ptr()),
+                                   ct.byref(rep), _stream())
+    if st not in (DECT_OK, DECT_WARN_MAXITER):
+        _check(st, "dect_pls_decompose3")
     return u1, u2, rep
 
 

@@ -107,9 +107,9 @@ def test_volume_entry_points_validate_first(lib):
         assert lib.dect_adm_tv3(dect.ConeArg(g).ref, buf, buf, ct.byref(prm), buf, buf, None,
                                 None) == dect.DECT_ERR_INVALID_ARG
     p = dect.pls_params(C.PlsParams())
-    att = dect.pls_params(C.PlsParams(mode=1))
     sing = dect.dect_pls_params(1.0, 2.0, 2.0, 4.0, 1.0, 0.1, 0.25, 10, 1e-6, 0)
-    for nz, prm in ((4, att), (4, sing), (0, p)):
+    bad_mode = dect.pls_params(C.PlsParams(mode=7))
+    for nz, prm in ((4, bad_mode), (4, sing), (0, p)):
         assert lib.dect_pls_decompose3(8, 8, nz, buf, buf, ct.byref(prm), None, buf, buf, None,
                                        None) == dect.DECT_ERR_INVALID_ARG
     assert lib.dect_pls_edge_weights3(8, 8, 0, buf, 0.25, 0.1, buf, None) == \

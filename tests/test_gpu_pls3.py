@@ -8,7 +8,12 @@ oracle (pls3) on the same FP32 volumes:
   rel-L2 1e-5 (the GPU solves to 1e-7 in FP32 vectors); the GPU's own FP32
   edge map equals the oracle's except next to voxels within 1e-4 of the
   threshold, and the full path equals the call given that map;
-* gamma = 0 gives D^{-1} x itself; the attenuation-space mode is refused.
+* gamma = 0 gives D^{-1} x itself; an unknown mode is refused; a solve cut
+  by max_iter reports DECT_WARN_MAXITER;
+* the attenuation-space mode (the coupled system of |x - Du|^2 + gamma R(u))
+  against the oracle's solver on the same FP32 volumes and shared edge map,
+  gamma 1e-5 .. 1e-3: rel-L2 <= 1e-6 (FP64 solve, FP32 outputs); gamma = 0
+  gives D^{-1} x.
 """
 import numpy as np
 import pytest
@@ -79,7 +84,33 @@ def test_gamma_zero_and_refusal(torch):
     assert rel_l2(to_np(u1), d1) <= 1e-6 and rel_l2(to_np(u2), d2) <= 1e-6
     assert rep.iters == 0
     with pytest.raises(dect.DectError):
-        dect.pls_decompose3(to_dev(torch, xh), to_dev(torch, xl), C.PlsParams(mode=1))
+        dect.pls_decompose3(to_dev(torch, xh), to_dev(torch, xl), C.PlsParams(mode=7))
+    for mode in (0, 1):
+        q = C.PlsParams(gamma=1.0, mode=mode, max_iter=2, tol=1e-14)
+        _, _, rep = dect.pls_decompose3(to_dev(torch, xh), to_dev(torch, xl), q)
+        assert rep.status == dect.DECT_WARN_MAXITER and rep.iters == 2
+
+
+@pytest.mark.parametrize("geom,seed,gamma", [(SMALL, 6, 1e-5), (SMALL, 7, 1e-3),
+                                              (RAGGED, 8, 1e-4)],
+                         ids=["small-1e-5", "small-1e-3", "ragged-1e-4"])
+def test_attenuation_mode_parity(torch, geom, seed, gamma):
+    from paper_1607_01650_amd import dect
+    xh, xl = _volumes(geom, seed)
+    p = C.PlsParams(gamma=gamma, tol=1e-11, mode=1, max_iter=3000)
+    w = np.stack(O.edges3(xl, p.edge_tau, p.edge_eps).weights).astype(np.float32)
+    u1, u2, rep = dect.pls_decompose3(to_dev(torch, xh), to_dev(torch, xl), p,
+                                      edge_w=to_dev(torch, w))
+    r1, r2, it = O.pls3(xh, xl, p, tol=1e-13, edge_w=[f32(a) for a in w])
+    e1, e2 = rel_l2(to_np(u1), r1), rel_l2(to_np(u2), r2)
+    print(f"3-D attenuation PLS {geom.nx}x{geom.ny}x{geom.nz} gamma {gamma}: water rel-L2 "
+          f"{e1:.2e}, bone {e2:.2e}, GPU iters {rep.iters} (oracle {it})", flush=True)
+    assert e1 <= 1e-6 and e2 <= 1e-6
+    assert rep.status == 0 and rep.pcg_residual <= 1e-11
+    z1, z2, _ = dect.pls_decompose3(to_dev(torch, xh), to_dev(torch, xl),
+                                    C.PlsParams(gamma=0.0, mode=1))
+    d1, d2 = O.dinv(xh, xl, p.eta_water_high, p.eta_bone_high, p.eta_water_low, p.eta_bone_low)
+    assert rel_l2(to_np(z1), d1) <= 1e-6 and rel_l2(to_np(z2), d2) <= 1e-6
 
 
 def test_full_size_residual(torch):
