@@ -1070,9 +1070,10 @@ void or_gradT3(int nx, int ny, int nz, const double *g3, double *out)
 }
 
 /* m [V][J][B] projections of one energy; x_out [nz][ny][nx] = f / beta;
- * log [(K+1)][5] as in or_adm. */
+ * log [(K+1)][5] as in or_adm; nonneg and step_rule as in or_adm. */
 int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double rho, double xi,
-            int K, double tol, const double *x0, double *x_out, double *log)
+            int K, double tol, const double *x0, double *x_out, double *log, int nonneg,
+            int step_rule)
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
     const size_t N = (size_t)nx * ny * nz;
@@ -1132,6 +1133,8 @@ int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double r
         memcpy(fo, f, N * 8);
         memcpy(ho, h, N * 8);
         for (size_t i = 0; i < N; ++i) f[i] -= alpha * G[i];
+        if (nonneg)  /* projection onto the non-negative volumes */
+            for (size_t i = 0; i < N; ++i) f[i] = f[i] > 0.0 ? f[i] : 0.0;
         or_project3(g, f, r);
         for (size_t j = 0; j < M; ++j) r[j] -= gs[j];
         or_backproject3(g, r, h);
@@ -1141,8 +1144,13 @@ int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double r
         grad3(nx, ny, nz, sv, w[0], w[1], w[2]);
         gradT3(nx, ny, nz, w[0], w[1], w[2], t1);
         for (size_t i = 0; i < N; ++i) y[i] = (h[i] - ho[i]) + rho * t1[i];
-        double ss = dot(N, sv, sv), sy = dot(N, sv, y);
-        if (sy > 0.0) alpha = ss / sy;
+        double ss = dot(N, sv, sv), sy = dot(N, sv, y), yy = dot(N, y, y);
+        if (sy > 0.0) {
+            const double bb1 = ss / sy, bb2 = yy > 0.0 ? sy / yy : bb1;
+            if (step_rule == 1) alpha = bb2;
+            else if (step_rule == 2) alpha = bb2 / bb1 < 0.5 ? bb2 : bb1;  /* adaptive */
+            else alpha = bb1;
+        }
         double fn = sqrt(dot(N, fo, fo));
         relchg = fn > 0.0 ? sqrt(ss) / fn : (ss > 0.0 ? INFINITY : 0.0);
         /* multiplier step (Eq. 7) */

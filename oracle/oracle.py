@@ -83,7 +83,8 @@ def lib():
         L.or_adm_coupled.argtypes = [P(_Geom), pd, pd, d, d, d, ct.c_int, pd, pd, pd, ct.c_int]
         L.or_project3.argtypes = [P(_Geom3), pd, pd]
         L.or_backproject3.argtypes = [P(_Geom3), pd, pd]
-        L.or_adm3.argtypes = [P(_Geom3), pd, d, d, d, d, ct.c_int, d, pd, pd, pd]
+        L.or_adm3.argtypes = [P(_Geom3), pd, d, d, d, d, ct.c_int, d, pd, pd, pd, ct.c_int,
+                              ct.c_int]
         L.or_edges3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, d, d, pd, pd, pd,
                                 P(ct.c_uint8), pd, pd]
         L.or_laplacian3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, pd, pd]
@@ -200,19 +201,21 @@ def backproject3(g, proj: np.ndarray) -> np.ndarray:
 
 
 def adm3(g, m: np.ndarray, beta: float, mu: float, rho: float, xi: float, iters: int,
-         tol: float = 0.0, x0: Optional[np.ndarray] = None, with_iters: bool = False):
+         tol: float = 0.0, x0: Optional[np.ndarray] = None, with_iters: bool = False,
+         nonneg: bool = False, step: str = "bb1"):
     """ADM-TV (Eq. 10) of one energy on a volume with the cone-beam pair and
     the 3-D TV, from zero or from x0 (f = beta x0), stopping early when the
-    relative image change falls below tol; returns (x = f / beta
-    [nz][ny][nx], log [(iters+1)][5]) and, with with_iters, the iteration
-    count."""
+    relative image change falls below tol; nonneg and step as in adm().
+    Returns (x = f / beta [nz][ny][nx], log [(iters+1)][5]) and, with
+    with_iters, the iteration count."""
     og = OGeom3(g)
     mm = _f64(m).reshape(og.n_views, og.n_rows, og.n_bins)
     x = np.empty((og.nz, og.ny, og.nx))
     log = np.zeros((iters + 1, 5))
     x0c = None if x0 is None else _f64(x0).reshape(og.nz, og.ny, og.nx)
     k = lib().or_adm3(ct.byref(og.s), _p(mm), float(beta), float(mu), float(rho), float(xi),
-                      int(iters), float(tol), _p(x0c), _p(x), _p(log))
+                      int(iters), float(tol), _p(x0c), _p(x), _p(log), 1 if nonneg else 0,
+                      {"bb1": 0, "bb2": 1, "abb": 2}[step])
     if with_iters:
         return x, log, int(k)
     return x, log

@@ -6,7 +6,9 @@ the 3-vector, the cone-beam projector pair):
   column, row and slice) and their adjoint satisfies the adjoint identity;
 * a one-slice volume seen by a one-row panel is the fan-beam problem: the
   run equals the pinned 2-D ADM of the central plane (the z-differences
-  vanish and the central row is the fan-beam projector);
+  vanish and the central row is the fan-beam projector), also with the
+  projection onto f >= 0, the BB2 and adaptive steps, a start image and the
+  stop rule;
 * zero data keeps the volume exactly zero;
 * on a dense 6 x 6 x 4 problem the objective reaches the minimum of Eq. 4
   with the 3-D TV found by an independent algorithm (Chambolle-Pock).
@@ -45,6 +47,25 @@ def test_single_slice_is_the_fan_beam_run():
     assert np.abs(x3[0] - r2.x).max() <= 1e-9 * np.abs(r2.x).max()
     assert np.allclose(log3[:, 0], r2.log[:41, 0], rtol=1e-9, atol=0)
     assert np.allclose(log3[:, 1], r2.log[:41, 1], rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("nonneg,step", [(True, "bb1"), (False, "bb2"), (False, "abb"),
+                                         (True, "abb")])
+def test_single_slice_variants_are_the_fan_beam_runs(nonneg, step):
+    """The projection onto f >= 0 and the BB2 / adaptive steps: a one-slice
+    volume seen by a one-row panel runs exactly the pinned 2-D variant."""
+    g3 = C.ConeGeometry(nx=20, ny=18, nz=1, voxel_mm=1.0, n_views=16, n_bins=30, n_rows=1,
+                        bin_mm=1.5, row_mm=1.0, sod_mm=80.0, sdd_mm=160.0, det_offset_mm=0.3)
+    g2 = g3.central_plane()
+    rng = np.random.default_rng(11)
+    m = rng.random((g3.n_views, 1, g3.n_bins)) * 5.0 - 1.0  # inconsistent: f >= 0 binds
+    x3, log3 = O.adm3(g3, m, 0.9, 0.7, 16.0, 4.0, 40, nonneg=nonneg, step=step)
+    r2 = O.adm(g2, m[:, 0, :], 0.9, 0.7, 16.0, 4.0, 40, nonneg=nonneg, step=step)
+    assert np.abs(x3[0] - r2.x).max() <= 1e-9 * np.abs(r2.x).max()
+    assert np.allclose(log3[:, 0], r2.log[:41, 0], rtol=1e-9, atol=0)
+    assert np.allclose(log3[:, 1], r2.log[:41, 1], rtol=1e-9, atol=0)
+    if nonneg:
+        assert x3.min() >= 0.0 and (x3 == 0.0).sum() > 0
 
 
 def test_single_slice_warm_start_and_stop_rule_match_the_fan_beam_run():
