@@ -363,8 +363,11 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
  * cone-beam pair above.  d_m_* [n_views][n_rows][n_bins] device, d_x_*
  * [nz][ny][nx] device outputs (x = f / beta), and with DECT_WARM_START
  * also the start images (f = beta x; they may be the same buffers).  params
- * as for dect_adm_tv except that flags may hold DECT_WARM_START only (BB1
- * step, per-energy TV; else DECT_ERR_INVALID_ARG) and tol must be finite
+ * as for dect_adm_tv, flags DECT_WARM_START, DECT_NONNEG (each step
+ * projected onto f >= 0, the BB step from the projected step; the residual
+ * follows A s of that step, so A G is formed for the first step only),
+ * DECT_STEP_BB2 or DECT_STEP_ABB (which here combine with DECT_NONNEG);
+ * DECT_COUPLED_TV is refused (DECT_ERR_INVALID_ARG).  tol must be finite
  * and >= 0.  tol > 0: each energy stops after the first iteration whose
  * relative change |f^{k+1}-f^k| / |f^k| is below tol, the other running on
  * until it stops too or max_iter is reached (the host reads both relative

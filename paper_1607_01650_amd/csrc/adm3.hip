@@ -22,11 +22,14 @@
 //   A G       p + plo, the FP64 ray sums of G split in two FP32 parts
 //   k3_scalar (k = 0) the exact line search along -G; then log row k
 //   k3_step   s = -alpha G, f += s in FP64; partials |f^k|^2, <s,s>
+//             (DECT_NONNEG: s the step to max(f - alpha G, 0), in FP32)
 //   k3_rupd   r -= alpha (p + plo) in FP64, so that r stays A f - beta m
-//             without projecting f; partial |r|^2
+//             without projecting f (DECT_NONNEG: r += A s, projecting s;
+//             A G is then formed for the first step only); partial |r|^2
 //   A^T r     h' = mu A^T r, y = h' - h + rho grad^T grad s, h = h';
-//             partial <s,y>
-//   k3_scalar alpha = <s,s>/<s,y> when <s,y> > 0, relative change
+//             partials <s,y>, <y,y>
+//   k3_scalar alpha = <s,s>/<s,y> (BB1), <s,y>/<y,y> (BB2) or the adaptive
+//             choice when <s,y> > 0, relative change
 // With a tolerance the host reads both relative changes after every
 // iteration and stops an energy at the first one below it (the stop rule of
 // Sec. 3); the other energy runs on alone.
@@ -40,7 +43,7 @@
 namespace dect {
 namespace {
 
-enum { Q_TV, Q_PRES, Q_GG, Q_GRADG, Q_PP, Q_FF, Q_RR, Q_SS, Q_SY, Q_COUNT };
+enum { Q_TV, Q_PRES, Q_GG, Q_GRADG, Q_PP, Q_FF, Q_RR, Q_SS, Q_SY, Q_YY, Q_COUNT };
 
 struct Dims {
     int nx, ny, nz;
@@ -202,22 +205,34 @@ struct Scal3 {
 };
 
 // s = -alpha G and (f + flo) += s in FP64, split again; partials |f^k|^2
-// (the image before the step) and <s,s>, both in FP64.
+// (the image before the step) and <s,s>, both in FP64.  nonneg: the step is
+// projected onto f >= 0, s = max(f - alpha G, 0) - f rounded toward zero to
+// FP32 (so that f + s >= 0), and f advances by exactly that s, so that the
+// residual recurrence r += A s stays the residual of f.
 __global__ __launch_bounds__(256) void k3_step(Dims d, const float *__restrict__ G,
                                                float *__restrict__ f, float *__restrict__ flo,
                                                float *__restrict__ s, const Scal3 *__restrict__ sc,
-                                               double *__restrict__ part, size_t stride)
+                                               int nonneg, double *__restrict__ part,
+                                               size_t stride)
 {
     const double alpha = sc->alpha;
     double ff = 0.0, ss = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         const double fo = (double)f[i] + (double)flo[i];
-        const double sd = -alpha * (double)G[i];
+        double sd = -alpha * (double)G[i];
+        float sf;
+        if (nonneg) {
+            const double t = fo + sd;
+            sf = __double2float_rz((t > 0.0 ? t : 0.0) - fo);
+            sd = (double)sf;
+        } else {
+            sf = (float)sd;
+        }
         const double fn = fo + sd;
         const float hi = (float)fn;
         f[i] = hi;
         flo[i] = (float)(fn - (double)hi);
-        s[i] = (float)sd;
+        s[i] = sf;
         ff += fo * fo;
         ss += sd * sd;
     }
@@ -225,17 +240,19 @@ __global__ __launch_bounds__(256) void k3_step(Dims d, const float *__restrict__
     block_sum(ss, part + Q_SS * stride + blockIdx.x);
 }
 
-// (r + rlo) -= alpha (p + plo) in FP64, split again; partial |r|^2.
+// (r + rlo) += c (p + plo) in FP64, split again; partial |r|^2.  c = -alpha
+// with p + plo = A G (plain step), or c = 1 with p + plo = A s (projected
+// step).
 __global__ __launch_bounds__(256) void k3_rupd(float *__restrict__ r, float *__restrict__ rlo,
                                                const float *__restrict__ p,
                                                const float *__restrict__ plo,
-                                               const Scal3 *__restrict__ sc, size_t M,
-                                               double *__restrict__ part, size_t stride)
+                                               const Scal3 *__restrict__ sc, int by_step,
+                                               size_t M, double *__restrict__ part, size_t stride)
 {
-    const double alpha = sc->alpha;
+    const double coef = by_step ? 1.0 : -sc->alpha;
     double rr = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (size_t)gridDim.x * 256) {
-        const double v = ((double)r[i] + (double)rlo[i]) - alpha * ((double)p[i] + (double)plo[i]);
+        const double v = ((double)r[i] + (double)rlo[i]) + coef * ((double)p[i] + (double)plo[i]);
         const float hi = (float)v;
         r[i] = hi;
         rlo[i] = (float)(v - (double)hi);
@@ -277,14 +294,14 @@ __global__ __launch_bounds__(256) void k3_start(const float *__restrict__ x0, do
     }
 }
 
-// h' = mu hb; y = h' - h + rho grad^T grad s; h = h'; partial <s,y>.  With
-// s == NULL only h is formed (the start).
+// h' = mu hb; y = h' - h + rho grad^T grad s; h = h'; partials <s,y> and
+// <y,y>.  With s == NULL only h is formed (the start).
 __global__ __launch_bounds__(256) void k3_y(Dims d, const float *__restrict__ hb,
                                             float *__restrict__ h, const float *__restrict__ s,
                                             float mu, float rho, double *__restrict__ part,
                                             size_t stride)
 {
-    double sy = 0.0;
+    double sy = 0.0, yy = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         const float hn = mu * hb[i];
         if (s) {
@@ -303,10 +320,14 @@ __global__ __launch_bounds__(256) void k3_y(Dims d, const float *__restrict__ hb
             if (z + 1 <= d.nz - 1) l -= s[i + P] - si;
             const float y = (hn - h[i]) + rho * l;
             sy += (double)si * y;
+            yy += (double)y * y;
         }
         h[i] = hn;
     }
-    if (s) block_sum(sy, part + Q_SY * stride + blockIdx.x);
+    if (s) {
+        block_sum(sy, part + Q_SY * stride + blockIdx.x);
+        block_sum(yy, part + Q_YY * stride + blockIdx.x);
+    }
 }
 
 __device__ double reduce_q(const double *__restrict__ part, size_t stride, int q, int nb)
@@ -326,11 +347,13 @@ __device__ double reduce_q(const double *__restrict__ part, size_t stride, int q
 
 // phase 0: first step's line search (alpha = |G|^2 / (mu |A G|^2 + rho |grad G|^2))
 // phase 1: log row k (J, alpha, ...) before the f-step
-// phase 2: BB1 step and relative change after the f-step
+// phase 2: the BB step (step_rule 0 BB1, 1 BB2, 2 adaptive) and the relative
+//          change after the f-step
 // phase 3: last log row
 __global__ __launch_bounds__(256) void k3_scalar(Scal3 *sc, const double *__restrict__ part,
                                                  size_t stride, int nbN, int nbM, int phase,
-                                                 double mu, double rho, double *log_row)
+                                                 double mu, double rho, int step_rule,
+                                                 double *log_row)
 {
     if (phase == 0) {
         const double gg = reduce_q(part, stride, Q_GG, nbN);
@@ -355,10 +378,15 @@ __global__ __launch_bounds__(256) void k3_scalar(Scal3 *sc, const double *__rest
         const double rr = reduce_q(part, stride, Q_RR, nbM);
         const double ss = reduce_q(part, stride, Q_SS, nbN);
         const double sy = reduce_q(part, stride, Q_SY, nbN);
+        const double yy = reduce_q(part, stride, Q_YY, nbN);
         const double ff = reduce_q(part, stride, Q_FF, nbN);
         if (threadIdx.x == 0) {
             sc->rr = rr;
-            if (sy > 0.0) sc->alpha = ss / sy;
+            if (sy > 0.0) {  // BB1, BB2 or the adaptive choice; else keep alpha
+                const double bb1 = ss / sy, bb2 = yy > 0.0 ? sy / yy : bb1;
+                sc->alpha = step_rule == 1 ? bb2 : step_rule == 2 ? (bb2 / bb1 < 0.5 ? bb2 : bb1)
+                                                                   : bb1;
+            }
             const double fn = sqrt(ff);
             sc->relchg = fn > 0.0 ? sqrt(ss) / fn : (ss > 0.0 ? INFINITY : 0.0);
         }
@@ -423,10 +451,11 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
 {
     if (!g || !p || !m_high || !m_low || !x_high || !x_low)
         return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: null argument");
-    if (p->flags & ~DECT_WARM_START)
+    if (p->flags & ~(DECT_WARM_START | DECT_NONNEG | DECT_STEP_BB2 | DECT_STEP_ABB))
         return fail(DECT_ERR_INVALID_ARG,
-                    "dect_adm_tv3 takes no flag but DECT_WARM_START (BB1 step, no projection "
-                    "onto f >= 0, per-energy TV)");
+                    "dect_adm_tv3: DECT_COUPLED_TV is not available on volumes (per-energy TV)");
+    if ((p->flags & DECT_STEP_BB2) && (p->flags & DECT_STEP_ABB))
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: DECT_STEP_BB2 and DECT_STEP_ABB exclude each other");
     if (!(p->tol >= 0.0) || !std::isfinite(p->tol))
         return fail(DECT_ERR_INVALID_ARG, "tol must be finite and >= 0");
     if (p->max_iter < 0 || p->max_iter > 1000000)
@@ -441,6 +470,8 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const size_t M = (size_t)g->n_views * g->n_rows * g->n_bins;
     const int K = p->max_iter;
     const bool warm = (p->flags & DECT_WARM_START) != 0;
+    const int nonneg = (p->flags & DECT_NONNEG) ? 1 : 0;
+    const int step_rule = (p->flags & DECT_STEP_BB2) ? 1 : (p->flags & DECT_STEP_ABB) ? 2 : 0;
     const int nbN = (int)std::min<size_t>(kMaxBlk, nblk(d.N));
     const int nbM = (int)std::min<size_t>(kMaxBlk, nblk(M));
     const size_t stride = (size_t)std::max(nbN, nbM);
@@ -521,8 +552,9 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
             hipLaunchKernelGGL(k3_g, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_W],
                                (const float *)V[e][B_H], V[e][B_G], part[e], stride);
         }
-        // p + plo = A G (a stopped energy's G is stale and its p unused)
-        if ((st = cone_project2_lo(g, cG, pp, plo, s))) return st;
+        // p + plo = A G (a stopped energy's G is stale and its p unused); the
+        // projected iteration needs it for the first (Cauchy) step only
+        if ((!nonneg || k == 0) && (st = cone_project2_lo(g, cG, pp, plo, s))) return st;
         for (int e = 0; e < 2; ++e) {
             if (done[e]) continue;
             if (k == 0) {
@@ -531,15 +563,25 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
                 hipLaunchKernelGGL(k3_gradnorm, dim3(nbN), dim3(256), 0, s, d,
                                    (const float *)V[e][B_G], part[e], stride);
                 hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride,
-                                   nbN, nbM, 0, p->mu, p->rho, (double *)nullptr);
+                                   nbN, nbM, 0, p->mu, p->rho, step_rule, (double *)nullptr);
             }
             hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN,
-                               nbM, 1, p->mu, p->rho, dlog + ((size_t)e * (K + 1) + k) * 5);
+                               nbM, 1, p->mu, p->rho, step_rule, dlog + ((size_t)e * (K + 1) + k) * 5);
             hipLaunchKernelGGL(k3_step, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_G],
-                               V[e][B_F], V[e][B_FLO], V[e][B_S], sc + e, part[e], stride);
-            hipLaunchKernelGGL(k3_rupd, dim3(nbM), dim3(256), 0, s, V[e][B_R], V[e][B_RLO],
-                               (const float *)pp[e], (const float *)plo[e], sc + e, M, part[e],
-                               stride);
+                               V[e][B_F], V[e][B_FLO], V[e][B_S], sc + e, nonneg, part[e], stride);
+            if (!nonneg)
+                hipLaunchKernelGGL(k3_rupd, dim3(nbM), dim3(256), 0, s, V[e][B_R], V[e][B_RLO],
+                                   (const float *)pp[e], (const float *)plo[e], sc + e, 0, M,
+                                   part[e], stride);
+        }
+        if (nonneg) {  // r += A s of the projected step
+            const float *cs[2] = {V[0][B_S], V[1][B_S]};
+            if ((st = cone_project2_lo(g, cs, pp, plo, s))) return st;
+            for (int e = 0; e < 2; ++e)
+                if (!done[e])
+                    hipLaunchKernelGGL(k3_rupd, dim3(nbM), dim3(256), 0, s, V[e][B_R],
+                                       V[e][B_RLO], (const float *)pp[e], (const float *)plo[e],
+                                       sc + e, 1, M, part[e], stride);
         }
         if ((st = cone_backproject2(g, cr, hb, s))) return st;
         for (int e = 0; e < 2; ++e) {
@@ -547,7 +589,7 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
             hipLaunchKernelGGL(k3_y, dim3(nbN), dim3(256), 0, s, d, (const float *)hb[e],
                                V[e][B_H], (const float *)V[e][B_S], mu, rho, part[e], stride);
             hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN,
-                               nbM, 2, p->mu, p->rho, (double *)nullptr);
+                               nbM, 2, p->mu, p->rho, step_rule, (double *)nullptr);
         }
         DECT_HIP(hipGetLastError());
         if (p->tol > 0.0) {
@@ -565,7 +607,7 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
         hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_F],
                            (const float *)V[e][B_FLO], part[e], stride);
         hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN, nbM,
-                           3, p->mu, p->rho, dlog + ((size_t)e * (K + 1) + stop[e]) * 5);
+                           3, p->mu, p->rho, step_rule, dlog + ((size_t)e * (K + 1) + stop[e]) * 5);
         hipLaunchKernelGGL(k3_out, dim3(nbN), dim3(256), 0, s, (const float *)V[e][B_F],
                            (const float *)V[e][B_FLO], betas[e], d.N, xs[e]);
     }

@@ -3,7 +3,8 @@
 each energy on the same FP32 inputs: a 32 x 28 x 12 volume (30 views, 10 x 48
 panel, 30 iterations), a ragged one (37 x 29 x 9, detector offset, 25
 iterations) and a 128 x 128 x 16 one (90 views, 16 x 192 panel, 40
-iterations); a warm start; the relative-change stop rule.
+iterations); a warm start; the relative-change stop rule; the projection
+onto f >= 0 and the BB2 / adaptive steps.
 
 * Images: rel-L2 <= 1e-4.
 * The logged objective of Eq. 4: within 1e-5 over the first 10 iterations,
@@ -160,12 +161,40 @@ def test_tolerance_stop_parity(torch):
     assert r.report.iters == max(its)
 
 
+@pytest.mark.parametrize("nonneg,step", [(True, "bb1"), (False, "bb2"), (False, "abb"),
+                                         (True, "abb")],
+                         ids=["nonneg", "bb2", "abb", "nonneg-abb"])
+def test_variant_parity(torch, nonneg, step):
+    """DECT_NONNEG (the projected step, the residual following A s) and the
+    BB2 / adaptive steps against the oracle's same variants; with noise
+    strong enough that f >= 0 binds at many voxels."""
+    from paper_1607_01650_amd import dect
+    g, iters = VOL, 20
+    m = _data(g, 9)
+    rng = np.random.default_rng(9)
+    m = [f32(a + 0.05 * a.max() * rng.standard_normal(a.shape)) for a in m]
+    p = dataclasses.replace(PARAMS, max_iter=iters, nonneg=nonneg, step=step)
+    r = dect.adm_tv3(to_dev(torch, m[0]), to_dev(torch, m[1]), g, p, want_log=True)
+    for e, (xe, beta) in enumerate(((r.x_high, p.beta_high), (r.x_low, p.beta_low))):
+        x, log = O.adm3(g, m[e], beta, p.mu, p.rho, p.xi, iters, nonneg=nonneg, step=step)
+        err = rel_l2(to_np(xe), x)
+        jrel = np.abs(r.log[:, e] - log[:, 0]) / np.abs(log[:, 0])
+        arel = np.abs(r.log[1:, 2 + e] - log[1:, 1]) / np.abs(log[1:, 1])
+        zeros = int((x == 0.0).sum())
+        print(f"3-D ADM {step}{' nonneg' if nonneg else ''} energy {e}: image rel-L2 {err:.2e}, "
+              f"J rel err {jrel.max():.2e}, step rel err k<=10 {arel[:10].max():.2e}, "
+              f"all {arel.max():.2e}, oracle zero voxels {zeros}", flush=True)
+        assert err <= 1e-4 and jrel.max() <= 1e-4
+        assert arel[:10].max() <= 1e-4 and arel.max() <= 1e-3
+        if nonneg:
+            assert to_np(xe).min() >= 0.0 and zeros > 100
+
+
 def test_refusals(torch):
     from paper_1607_01650_amd import dect
     g = VOL
     z = torch.zeros((g.n_views, g.n_rows, g.n_bins), device="cuda")
-    for change in ({"nonneg": True}, {"coupled_tv": True}, {"step": "bb2"}, {"step": "abb"},
-                   {"tol": -1e-3}, {"tol": float("nan")}):
+    for change in ({"coupled_tv": True}, {"tol": -1e-3}, {"tol": float("nan")}):
         with pytest.raises(dect.DectError):
             dect.adm_tv3(z, z, g, dataclasses.replace(PARAMS, max_iter=2, **change))
 
