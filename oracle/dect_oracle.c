@@ -1181,6 +1181,117 @@ int or_adm3(const or_geom3 *g, const double *m, double beta, double mu, double r
     return k;
 }
 
+/*
+ * ADM-TV of both energies on a volume with the TV coupled across them (as
+ * or_adm_coupled, with the 3-D differences): the z-step shrinks the 6-vector
+ * (grad f_high, grad f_low) at every voxel, |v|^2 summed as energy 0's three
+ * components and then energy 1's; each energy keeps its own f-step, BB1 step
+ * and multiplier.  Fixed iteration count.
+ * In:  m [2][V][J][B], beta[2], x0 [2][nz][ny][nx] or NULL.
+ * Out: x_out [2][nz][ny][nx]; log [2][(K+1)][2] rows (J part, alpha^k) per
+ *      energy: energy 0 carries the joint TV, energy 1 none.
+ */
+void or_adm3_coupled(const or_geom3 *g, const double *m, const double *beta, double mu,
+                     double rho, double xi, int K, const double *x0, double *x_out, double *log,
+                     int nonneg)
+{
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t M = (size_t)g->n_views * g->n_rows * g->n_bins;
+    double *f[2], *fo[2], *G[2], *h[2], *ho[2], *l[2][3], *z[2][3], *d[2][3], *gs[2], *r[2];
+    double *w[3], alpha[2] = {0.0, 0.0};
+    for (int a = 0; a < 3; ++a) w[a] = calloc(N, 8);
+    double *t1 = calloc(N, 8), *sv = calloc(N, 8), *y = calloc(N, 8), *p = calloc(M, 8);
+    for (int e = 0; e < 2; ++e) {
+        f[e] = calloc(N, 8); fo[e] = calloc(N, 8); G[e] = calloc(N, 8);
+        h[e] = calloc(N, 8); ho[e] = calloc(N, 8);
+        for (int a = 0; a < 3; ++a) {
+            l[e][a] = calloc(N, 8); z[e][a] = calloc(N, 8); d[e][a] = calloc(N, 8);
+        }
+        gs[e] = calloc(M, 8); r[e] = calloc(M, 8);
+        for (size_t j = 0; j < M; ++j) gs[e][j] = beta[e] * m[e * M + j];
+        if (x0)
+            for (size_t i = 0; i < N; ++i) f[e][i] = beta[e] * x0[e * N + i];
+        or_project3(g, f[e], r[e]);
+        for (size_t j = 0; j < M; ++j) r[e][j] -= gs[e][j];
+        or_backproject3(g, r[e], h[e]);
+        for (size_t i = 0; i < N; ++i) h[e][i] *= mu;
+    }
+    for (int k = 0; k <= K; ++k) {
+        for (int e = 0; e < 2; ++e) grad3(nx, ny, nz, f[e], d[e][0], d[e][1], d[e][2]);
+        double tvj = 0.0;
+        for (size_t i = 0; i < N; ++i) {
+            double q = 0.0;
+            for (int e = 0; e < 2; ++e)
+                for (int a = 0; a < 3; ++a) q += d[e][a][i] * d[e][a][i];
+            tvj += sqrt(q);
+        }
+        for (int e = 0; e < 2; ++e) {
+            double *row = log + ((size_t)e * (K + 1) + k) * 2;
+            row[0] = (e == 0 ? tvj : 0.0) + 0.5 * mu * dot(M, r[e], r[e]);
+            row[1] = alpha[e];
+        }
+        if (k == K) break;
+        /* joint z-step */
+        for (size_t i = 0; i < N; ++i) {
+            double v[2][3], q = 0.0;
+            for (int e = 0; e < 2; ++e)
+                for (int a = 0; a < 3; ++a) {
+                    v[e][a] = d[e][a][i] - l[e][a][i] / rho;
+                    q += v[e][a] * v[e][a];
+                }
+            const double n = sqrt(q);
+            const double sh = n > 1.0 / rho ? (n - 1.0 / rho) / n : 0.0;
+            for (int e = 0; e < 2; ++e)
+                for (int a = 0; a < 3; ++a) z[e][a][i] = sh * v[e][a];
+        }
+        for (int e = 0; e < 2; ++e) {
+            /* G (Eq. 9) */
+            for (int a = 0; a < 3; ++a)
+                for (size_t i = 0; i < N; ++i)
+                    w[a][i] = rho * (d[e][a][i] - z[e][a][i]) - l[e][a][i];
+            gradT3(nx, ny, nz, w[0], w[1], w[2], G[e]);
+            for (size_t i = 0; i < N; ++i) G[e][i] += h[e][i];
+            if (k == 0) {  /* exact minimiser of the f-subproblem along -G */
+                or_project3(g, G[e], p);
+                grad3(nx, ny, nz, G[e], w[0], w[1], w[2]);
+                double den = mu * dot(M, p, p) + rho * (dot(N, w[0], w[0]) + dot(N, w[1], w[1]) +
+                                                       dot(N, w[2], w[2]));
+                double gg = dot(N, G[e], G[e]);
+                alpha[e] = den > 0.0 ? gg / den : 0.0;
+                log[((size_t)e * (K + 1) + k) * 2 + 1] = alpha[e];
+            }
+            memcpy(fo[e], f[e], N * 8);
+            memcpy(ho[e], h[e], N * 8);
+            for (size_t i = 0; i < N; ++i) f[e][i] -= alpha[e] * G[e][i];
+            if (nonneg)
+                for (size_t i = 0; i < N; ++i) f[e][i] = f[e][i] > 0.0 ? f[e][i] : 0.0;
+            or_project3(g, f[e], r[e]);
+            for (size_t j = 0; j < M; ++j) r[e][j] -= gs[e][j];
+            or_backproject3(g, r[e], h[e]);
+            for (size_t i = 0; i < N; ++i) h[e][i] *= mu;
+            for (size_t i = 0; i < N; ++i) sv[i] = f[e][i] - fo[e][i];
+            grad3(nx, ny, nz, sv, w[0], w[1], w[2]);
+            gradT3(nx, ny, nz, w[0], w[1], w[2], t1);
+            for (size_t i = 0; i < N; ++i) y[i] = (h[e][i] - ho[e][i]) + rho * t1[i];
+            double ss = dot(N, sv, sv), sy = dot(N, sv, y);
+            if (sy > 0.0) alpha[e] = ss / sy;
+            /* multiplier step (Eq. 7) */
+            grad3(nx, ny, nz, f[e], w[0], w[1], w[2]);
+            for (int a = 0; a < 3; ++a)
+                for (size_t i = 0; i < N; ++i) l[e][a][i] -= xi * (w[a][i] - z[e][a][i]);
+        }
+    }
+    for (int e = 0; e < 2; ++e)
+        for (size_t i = 0; i < N; ++i) x_out[e * N + i] = f[e][i] / beta[e];
+    for (int e = 0; e < 2; ++e) {
+        free(f[e]); free(fo[e]); free(G[e]); free(h[e]); free(ho[e]); free(gs[e]); free(r[e]);
+        for (int a = 0; a < 3; ++a) { free(l[e][a]); free(z[e][a]); free(d[e][a]); }
+    }
+    for (int a = 0; a < 3; ++a) free(w[a]);
+    free(t1); free(sv); free(y); free(p);
+}
+
 /* ------------------------------------------------------------ 3-D PLS ---
  * Eqs. 13-15 on a volume: R of Eq. 14 over the six face neighbours, edges
  * from the 3-D Prewitt operator in FP64: per axis, the sum over the 3 x 3

@@ -94,6 +94,8 @@ def lib():
         L.or_pcg_att3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd, pd, d, d, d, d, d, pd,
                                   pd, pd, pd, ct.c_int, d, pd]
         L.or_pcg_att3.restype = ct.c_int
+        L.or_adm3_coupled.argtypes = [P(_Geom3), pd, pd, d, d, d, ct.c_int, pd, pd, pd,
+                                      ct.c_int]
         L.or_adm3.restype = ct.c_int
         L.or_grad3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
         L.or_gradT3.argtypes = [ct.c_int, ct.c_int, ct.c_int, pd, pd]
@@ -410,6 +412,26 @@ def pcg3(ex, ey, ez, gamma: float, b, max_iter: int = 500, tol: float = 1e-12):
     it = lib().or_pcg3(nx, ny, nz, _p(ex), _p(ey), _p(ez), float(gamma), _p(b), _p(u),
                        int(max_iter), float(tol), ct.byref(rr))
     return u, int(it), float(rr.value)
+
+
+def adm3_coupled(g, m_high, m_low, beta_high: float, beta_low: float, mu: float, rho: float,
+                 xi: float, iters: int, x0=None, nonneg: bool = False):
+    """ADM-TV of both energies on a volume with the 3-D TV coupled across them
+    (joint z-step over the 6-vector).  Returns (x [2][nz][ny][nx], J
+    [iters+1][2], alpha [iters+1][2]); energy 0's J column carries the joint
+    TV."""
+    og = OGeom3(g)
+    shp = (og.n_views, og.n_rows, og.n_bins)
+    m = np.ascontiguousarray(np.stack([_f64(m_high).reshape(shp), _f64(m_low).reshape(shp)]))
+    beta = np.array([beta_high, beta_low], dtype=np.float64)
+    vshp = (og.nz, og.ny, og.nx)
+    x0c = None if x0 is None else np.ascontiguousarray(
+        np.stack([_f64(x0[0]).reshape(vshp), _f64(x0[1]).reshape(vshp)]))
+    x = np.empty((2,) + vshp)
+    log = np.zeros((2, iters + 1, 2))
+    lib().or_adm3_coupled(ct.byref(og.s), _p(m), _p(beta), float(mu), float(rho), float(xi),
+                          int(iters), _p(x0c), _p(x), _p(log), 1 if nonneg else 0)
+    return x, log[:, :, 0].T.copy(), log[:, :, 1].T.copy()
 
 
 def pcg_att3(ex, ey, ez, eta, gamma: float, xh, xl, max_iter: int = 500, tol: float = 1e-12):

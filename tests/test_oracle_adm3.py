@@ -157,3 +157,74 @@ def test_reaches_the_minimum_of_eq4_in_3d():
     Jstar = _cp3(A, m, mu, _dense_diffs(g.nx, g.ny, g.nz), 60000)
     _, log = O.adm3(g, m.reshape(g.n_views, g.n_rows, g.n_bins), 1.0, mu, 16.0, 4.0, 6000)
     assert abs(log[-1, 0] - Jstar) <= 1e-6 * Jstar, (log[-1, 0], Jstar)
+
+
+def test_coupled_single_slice_is_the_fan_beam_coupled_run():
+    g3 = C.ConeGeometry(nx=20, ny=18, nz=1, voxel_mm=1.0, n_views=16, n_bins=30, n_rows=1,
+                        bin_mm=1.5, row_mm=1.0, sod_mm=80.0, sdd_mm=160.0, det_offset_mm=0.3)
+    g2 = g3.central_plane()
+    rng = np.random.default_rng(12)
+    mh = rng.random((g3.n_views, 1, g3.n_bins)) * 5.0
+    ml = rng.random((g3.n_views, 1, g3.n_bins)) * 6.0
+    for nonneg in (False, True):
+        x3, J3, a3 = O.adm3_coupled(g3, mh, ml, 1.0, 0.8, 0.7, 16.0, 4.0, 30, nonneg=nonneg)
+        x2, J2, a2 = O.adm_coupled(g2, mh[:, 0], ml[:, 0], 1.0, 0.8, 0.7, 16.0, 4.0, 30,
+                                   nonneg=nonneg)
+        assert np.abs(x3[:, 0] - x2).max() <= 1e-9 * np.abs(x2).max()
+        assert np.allclose(J3, J2, rtol=1e-9, atol=0) and np.allclose(a3, a2, rtol=1e-9, atol=0)
+
+
+def test_coupled_with_an_empty_second_energy_is_the_single_energy_run():
+    """With no data in the low energy its volume stays zero, the joint norm is
+    the high energy's own, and the run is or_adm3's bit for bit."""
+    g = SMALL3
+    rng = np.random.default_rng(13)
+    mh = rng.random((g.n_views, g.n_rows, g.n_bins)) * 4.0
+    x, J, a = O.adm3_coupled(g, mh, np.zeros_like(mh), 1.0, 0.8, 0.7, 16.0, 4.0, 25)
+    x1, log1 = O.adm3(g, mh, 1.0, 0.7, 16.0, 4.0, 25)
+    assert not np.any(x[1]) and np.array_equal(x[0], x1)
+    assert np.array_equal(J[:, 0], log1[:, 0]) and np.array_equal(a[:, 0], log1[:, 1])
+
+
+def _cp3_coupled(A, m, mu, D, iters):
+    """Chambolle-Pock on min sum_i |(D f_h, D f_l)_i| + mu/2 sum_e |A f_e - m_e|^2,
+    the norm over the 6-vector of both energies' differences at voxel i."""
+    N = A.shape[1]
+    K1 = np.vstack(D)  # [3N, N]
+    tau = sig = 0.99 / np.linalg.norm(K1, 2)
+    Minv = np.linalg.inv(np.eye(N) + tau * mu * A.T @ A)
+    f = [np.zeros(N), np.zeros(N)]
+    fb = [a.copy() for a in f]
+    p = [np.zeros(3 * N), np.zeros(3 * N)]
+    for _ in range(iters):
+        q = [p[e] + sig * (K1 @ fb[e]) for e in range(2)]
+        qq = [a.reshape(3, N) for a in q]
+        nrm = np.maximum(1.0, np.sqrt((qq[0] ** 2).sum(0) + (qq[1] ** 2).sum(0)))
+        p = [(a / nrm).reshape(-1) for a in qq]
+        for e in range(2):
+            fo = f[e]
+            f[e] = Minv @ (f[e] - tau * (K1.T @ p[e]) + tau * mu * (A.T @ m[e]))
+            fb[e] = 2 * f[e] - fo
+    gd = [np.stack([Dk @ f[e] for Dk in D]) for e in range(2)]
+    tv = np.sum(np.sqrt((gd[0] ** 2).sum(0) + (gd[1] ** 2).sum(0)))
+    return tv + 0.5 * mu * sum(np.sum((A @ f[e] - m[e]) ** 2) for e in range(2))
+
+
+@pytest.mark.slow
+def test_coupled_reaches_the_vectorial_tv_minimum():
+    g = SMALL3
+    N = g.nx * g.ny * g.nz
+    A = np.stack([O.project3(g, np.eye(N)[i].reshape(g.nz, g.ny, g.nx)).reshape(-1)
+                  for i in range(N)], axis=1)
+    rng = np.random.default_rng(14)
+    xt = np.zeros((g.nz, g.ny, g.nx))
+    xt[1:3, 1:5, 2:5] = 1.0
+    xt[2, 2:4, 3] = 2.0
+    m = [A @ xt.reshape(-1) + 0.05 * rng.standard_normal(A.shape[0]),
+         A @ (1.3 * xt).reshape(-1) + 0.05 * rng.standard_normal(A.shape[0])]
+    mu = 0.5
+    Jstar = _cp3_coupled(A, m, mu, _dense_diffs(g.nx, g.ny, g.nz), 60000)
+    shp = (g.n_views, g.n_rows, g.n_bins)
+    _, J, _ = O.adm3_coupled(g, m[0].reshape(shp), m[1].reshape(shp), 1.0, 1.0, mu, 16.0, 4.0,
+                             6000)
+    assert abs(J[-1].sum() - Jstar) <= 1e-6 * Jstar, (J[-1].sum(), Jstar)
