@@ -85,9 +85,10 @@ enum {
                             kept when the denominator is not positive.  The
                             step's own projection A s replaces A G after the
                             first iteration. */
-    DECT_COUPLED_TV = 4, /* the TV norm of Eq. 2 over the 4-vector of both energies'
-                            gradients (one joint z-step; each energy keeps its own
-                            f-step and BB step); log column J_high then holds the
+    DECT_COUPLED_TV = 4, /* the TV norm of Eq. 2 over the 4-vector (on volumes the
+                            6-vector) of both energies' gradients (one joint
+                            z-step; each energy keeps its own f-step and BB
+                            step); log column J_high then holds the
                             joint TV and J_low none, so the two sum to the
                             objective.  Needs tol = 0 (fixed iteration count). */
     DECT_STEP_BB2 = 8,   /* BB2 step <s,y>/<y,y> instead of BB1 <s,s>/<s,y> (Eq. 9
@@ -366,9 +367,10 @@ dect_status dect_cone_backproject(const dect_cone_geometry *geom, const float *d
  * as for dect_adm_tv, flags DECT_WARM_START, DECT_NONNEG (each step
  * projected onto f >= 0, the BB step from the projected step; the residual
  * follows A s of that step, so A G is formed for the first step only),
- * DECT_STEP_BB2 or DECT_STEP_ABB (which here combine with DECT_NONNEG);
- * DECT_COUPLED_TV is refused (DECT_ERR_INVALID_ARG).  tol must be finite
- * and >= 0.  tol > 0: each energy stops after the first iteration whose
+ * DECT_STEP_BB2 or DECT_STEP_ABB (which here combine with DECT_NONNEG),
+ * DECT_COUPLED_TV (the shrinkage of Eq. 8 on the 6-vector of both energies'
+ * gradients; BB1 step and tol = 0 only, else DECT_ERR_INVALID_ARG; J_high
+ * then holds the joint TV and J_low none).  tol must be finite and >= 0.  tol > 0: each energy stops after the first iteration whose
  * relative change |f^{k+1}-f^k| / |f^k| is below tol, the other running on
  * until it stops too or max_iter is reached (the host reads both relative
  * changes after every iteration, one stream synchronisation each).

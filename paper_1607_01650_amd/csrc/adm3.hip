@@ -30,6 +30,8 @@
 //             partials <s,y>, <y,y>
 //   k3_scalar alpha = <s,s>/<s,y> (BB1), <s,y>/<y,y> (BB2) or the adaptive
 //             choice when <s,y> > 0, relative change
+// DECT_COUPLED_TV: k3_tv_coupled takes the z-step of both energies at once,
+// shrinking the 6-vector of their gradients (a fixed iteration count).
 // With a tolerance the host reads both relative changes after every
 // iteration and stops an energy at the first one below it (the stop rule of
 // Sec. 3); the other energy runs on alone.
@@ -95,44 +97,103 @@ __device__ __forceinline__ void coords(const Dims &d, size_t i, int &c, int &r, 
 
 constexpr int kMaxBlk = 2048;  // grid of the element-wise kernels (grid-stride loops)
 
-__global__ __launch_bounds__(256) void k3_tv(Dims d, const float *__restrict__ f,
-                                             const float *__restrict__ flo,
-                                             float *__restrict__ lam, float *__restrict__ zz,
-                                             float *__restrict__ W, int first, float xi, float rho,
-                                             double *__restrict__ part, size_t stride)
+// One energy's state at the z-step.
+struct TvSet {
+    const float *f, *flo;
+    float *lam, *zz, *W;
+    double *part;
+};
+
+// grad f at voxel i, the deferred multiplier step (k > 0) and v = grad f -
+// lambda / rho of one energy.
+__device__ __forceinline__ void tv_pre(const Dims &d, const TvSet &S, size_t i, int c, int r,
+                                       int z, int first, float xi, float rho, float g[3],
+                                       float l[3], float v[3])
+{
+    grad2_at(d, S.f, S.flo, i, c, r, z, g[0], g[1], g[2]);
+    for (int a = 0; a < 3; ++a) {
+        l[a] = S.lam[a * d.N + i];
+        if (!first) l[a] -= xi * (g[a] - S.zz[a * d.N + i]);
+        v[a] = g[a] - l[a] / rho;
+    }
+}
+
+// z = sh v, W = rho (grad f - z) - lambda, lambda stored; returns
+// |grad f - z|^2 at voxel i.
+__device__ __forceinline__ double tv_post(const Dims &d, const TvSet &S, size_t i, float sh,
+                                          float rho, const float g[3], const float l[3],
+                                          const float v[3])
+{
+    double pres = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const float za = sh * v[a];
+        S.lam[a * d.N + i] = l[a];
+        S.zz[a * d.N + i] = za;
+        S.W[a * d.N + i] = rho * (g[a] - za) - l[a];
+        pres += (double)(g[a] - za) * (g[a] - za);
+    }
+    return pres;
+}
+
+__device__ __forceinline__ float shrink_factor(float mag, float rho)
+{
+    const float t = 1.f / rho;
+    return mag > t ? (mag - t) / mag : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k3_tv(Dims d, TvSet S, int first, float xi, float rho,
+                                             size_t stride)
 {
     double tv = 0.0, pres = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
         int c, r, z;
         coords(d, i, c, r, z);
-        float g[3];
-        grad2_at(d, f, flo, i, c, r, z, g[0], g[1], g[2]);
-        float l[3], v[3];
-        for (int a = 0; a < 3; ++a) {
-            l[a] = lam[a * d.N + i];
-            if (!first) l[a] -= xi * (g[a] - zz[a * d.N + i]);
-            v[a] = g[a] - l[a] / rho;
-        }
-        const float mag = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        const float t = 1.f / rho;
-        const float sh = mag > t ? (mag - t) / mag : 0.f;
-        for (int a = 0; a < 3; ++a) {
-            const float za = sh * v[a];
-            lam[a * d.N + i] = l[a];
-            zz[a * d.N + i] = za;
-            W[a * d.N + i] = rho * (g[a] - za) - l[a];
-            pres += (double)(g[a] - za) * (g[a] - za);
-        }
+        float g[3], l[3], v[3];
+        tv_pre(d, S, i, c, r, z, first, xi, rho, g, l, v);
+        const float sh = shrink_factor(sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]), rho);
+        pres += tv_post(d, S, i, sh, rho, g, l, v);
         tv += sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
     }
-    block_sum(tv, part + Q_TV * stride + blockIdx.x);
-    block_sum(pres, part + Q_PRES * stride + blockIdx.x);
+    block_sum(tv, S.part + Q_TV * stride + blockIdx.x);
+    block_sum(pres, S.part + Q_PRES * stride + blockIdx.x);
 }
 
-// TV(f) alone (the last log row).
+// The z-step with the TV coupled across the energies: one shrinkage of the
+// 6-vector (v_high, v_low) at every voxel, its squared norm summed over the
+// high energy's three components and then the low energy's.  The joint TV
+// goes to the high energy's partials, zero to the low energy's.
+__global__ __launch_bounds__(256) void k3_tv_coupled(Dims d, TvSet S0, TvSet S1, int first,
+                                                     float xi, float rho, size_t stride)
+{
+    double tv = 0.0, pr0 = 0.0, pr1 = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
+        int c, r, z;
+        coords(d, i, c, r, z);
+        float g0[3], l0[3], v0[3], g1[3], l1[3], v1[3];
+        tv_pre(d, S0, i, c, r, z, first, xi, rho, g0, l0, v0);
+        tv_pre(d, S1, i, c, r, z, first, xi, rho, g1, l1, v1);
+        const float sh = shrink_factor(sqrtf(v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2] +
+                                             v1[0] * v1[0] + v1[1] * v1[1] + v1[2] * v1[2]),
+                                       rho);
+        pr0 += tv_post(d, S0, i, sh, rho, g0, l0, v0);
+        pr1 += tv_post(d, S1, i, sh, rho, g1, l1, v1);
+        tv += sqrt((double)g0[0] * g0[0] + (double)g0[1] * g0[1] + (double)g0[2] * g0[2] +
+                   (double)g1[0] * g1[0] + (double)g1[1] * g1[1] + (double)g1[2] * g1[2]);
+    }
+    block_sum(tv, S0.part + Q_TV * stride + blockIdx.x);
+    block_sum(pr0, S0.part + Q_PRES * stride + blockIdx.x);
+    block_sum(pr1, S1.part + Q_PRES * stride + blockIdx.x);
+    if (threadIdx.x == 0) S1.part[Q_TV * stride + blockIdx.x] = 0.0;
+}
+
+// TV(f) alone (the last log row); with a second energy (f1 != NULL) the
+// joint TV into part0 and zero into part1.
 __global__ __launch_bounds__(256) void k3_tvonly(Dims d, const float *__restrict__ f,
                                                  const float *__restrict__ flo,
-                                                 double *__restrict__ part, size_t stride)
+                                                 const float *__restrict__ f1,
+                                                 const float *__restrict__ flo1,
+                                                 double *__restrict__ part,
+                                                 double *__restrict__ part1, size_t stride)
 {
     double tv = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.N; i += (size_t)gridDim.x * 256) {
@@ -140,9 +201,15 @@ __global__ __launch_bounds__(256) void k3_tvonly(Dims d, const float *__restrict
         coords(d, i, c, r, z);
         float g[3];
         grad2_at(d, f, flo, i, c, r, z, g[0], g[1], g[2]);
-        tv += sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
+        double q = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+        if (f1) {
+            grad2_at(d, f1, flo1, i, c, r, z, g[0], g[1], g[2]);
+            q += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+        }
+        tv += sqrt(q);
     }
     block_sum(tv, part + Q_TV * stride + blockIdx.x);
+    if (f1 && threadIdx.x == 0) part1[Q_TV * stride + blockIdx.x] = 0.0;
 }
 
 // grad^T of a 3-component field at voxel i (exact adjoint of grad_at).
@@ -451,9 +518,13 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
 {
     if (!g || !p || !m_high || !m_low || !x_high || !x_low)
         return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: null argument");
-    if (p->flags & ~(DECT_WARM_START | DECT_NONNEG | DECT_STEP_BB2 | DECT_STEP_ABB))
+    if (p->flags & ~(DECT_WARM_START | DECT_NONNEG | DECT_COUPLED_TV | DECT_STEP_BB2 | DECT_STEP_ABB))
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: unknown flag");
+    if ((p->flags & DECT_COUPLED_TV) && (p->flags & (DECT_STEP_BB2 | DECT_STEP_ABB)))
+        return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: coupled TV takes the BB1 step only");
+    if ((p->flags & DECT_COUPLED_TV) && p->tol != 0.0)
         return fail(DECT_ERR_INVALID_ARG,
-                    "dect_adm_tv3: DECT_COUPLED_TV is not available on volumes (per-energy TV)");
+                    "dect_adm_tv3: coupled TV runs a fixed iteration count (tol 0)");
     if ((p->flags & DECT_STEP_BB2) && (p->flags & DECT_STEP_ABB))
         return fail(DECT_ERR_INVALID_ARG, "dect_adm_tv3: DECT_STEP_BB2 and DECT_STEP_ABB exclude each other");
     if (!(p->tol >= 0.0) || !std::isfinite(p->tol))
@@ -471,6 +542,7 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     const int K = p->max_iter;
     const bool warm = (p->flags & DECT_WARM_START) != 0;
     const int nonneg = (p->flags & DECT_NONNEG) ? 1 : 0;
+    const bool coupled = (p->flags & DECT_COUPLED_TV) != 0;
     const int step_rule = (p->flags & DECT_STEP_BB2) ? 1 : (p->flags & DECT_STEP_ABB) ? 2 : 0;
     const int nbN = (int)std::min<size_t>(kMaxBlk, nblk(d.N));
     const int nbM = (int)std::min<size_t>(kMaxBlk, nblk(M));
@@ -538,17 +610,25 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
     }
     DECT_HIP(hipGetLastError());
 
+    auto tvset = [&](int e) {
+        return TvSet{V[e][B_F], V[e][B_FLO], V[e][B_LAM], V[e][B_Z], V[e][B_W], part[e]};
+    };
+
     // each energy runs until max_iter or, with a tolerance, until its
     // relative change first falls below it; stop[e] = its iteration count
     int stop[2] = {K, K};
     bool done[2] = {false, false};
     for (int k = 0; k < K && !(done[0] && done[1]); ++k) {
         DECT_TRACE("adm3 iteration");
+        // coupled: one joint z-step (tol is 0, so neither energy stops early)
+        if (coupled)
+            hipLaunchKernelGGL(k3_tv_coupled, dim3(nbN), dim3(256), 0, s, d, tvset(0), tvset(1),
+                               k == 0 ? 1 : 0, xi, rho, stride);
         for (int e = 0; e < 2; ++e) {
             if (done[e]) continue;
-            hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_F],
-                               (const float *)V[e][B_FLO], V[e][B_LAM], V[e][B_Z], V[e][B_W],
-                               k == 0 ? 1 : 0, xi, rho, part[e], stride);
+            if (!coupled)
+                hipLaunchKernelGGL(k3_tv, dim3(nbN), dim3(256), 0, s, d, tvset(e), k == 0 ? 1 : 0,
+                                   xi, rho, stride);
             hipLaunchKernelGGL(k3_g, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_W],
                                (const float *)V[e][B_H], V[e][B_G], part[e], stride);
         }
@@ -603,9 +683,15 @@ dect_status adm_tv3(const dect_cone_geometry *g, const float *m_high, const floa
                 }
         }
     }
+    if (coupled)
+        hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, (const float *)V[0][B_F],
+                           (const float *)V[0][B_FLO], (const float *)V[1][B_F],
+                           (const float *)V[1][B_FLO], part[0], part[1], stride);
     for (int e = 0; e < 2; ++e) {
-        hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_F],
-                           (const float *)V[e][B_FLO], part[e], stride);
+        if (!coupled)
+            hipLaunchKernelGGL(k3_tvonly, dim3(nbN), dim3(256), 0, s, d, (const float *)V[e][B_F],
+                               (const float *)V[e][B_FLO], (const float *)nullptr,
+                               (const float *)nullptr, part[e], (double *)nullptr, stride);
         hipLaunchKernelGGL(k3_scalar, dim3(1), dim3(256), 0, s, sc + e, part[e], stride, nbN, nbM,
                            3, p->mu, p->rho, step_rule, dlog + ((size_t)e * (K + 1) + stop[e]) * 5);
         hipLaunchKernelGGL(k3_out, dim3(nbN), dim3(256), 0, s, (const float *)V[e][B_F],

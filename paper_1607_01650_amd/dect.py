@@ -426,9 +426,9 @@ def adm_tv3(m_high, m_low, geom: C.ConeGeometry, p: C.AdmParams, want_log: bool 
             out: Optional[Tuple] = None, x0=None) -> AdmResult:
     """ADM-TV of both energies on a volume with the cone-beam pair
     (dect_adm_tv3): m_* [V, rows, bins] device projections -> x_high, x_low
-    [nz, ny, nx]; BB1 step, from zero or from x0 = (x_high, x_low) (copied
-    into the outputs, which the call then reads as its start), each energy
-    stopping early when p.tol > 0.  With want_log, the log [max_iter+1, 4]
+    [nz, ny, nx]; the step rule, projection and coupled TV of p, from zero
+    or from x0 = (x_high, x_low) (copied into the outputs, which the call
+    then reads as its start), each energy stopping early when p.tol > 0.  With want_log, the log [max_iter+1, 4]
     = (J_high, J_low, alpha_high, alpha_low) and the report."""
     torch = _torch()
     shp = (geom.n_views, geom.n_rows, geom.n_bins)

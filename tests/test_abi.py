@@ -100,7 +100,8 @@ def test_volume_entry_points_validate_first(lib):
         assert lib.dect_cone_backproject(dect.ConeArg(gg).ref, buf, buf, None) == want, gg
     assert lib.dect_cone_project(None, buf, buf, None) == dect.DECT_ERR_INVALID_ARG
     assert lib.dect_cone_project(dect.ConeArg(g).ref, None, buf, None) == dect.DECT_ERR_INVALID_ARG
-    for flags, tol in ((dect.DECT_COUPLED_TV, 0.0), (dect.DECT_STEP_BB2 | dect.DECT_STEP_ABB, 0.0),
+    for flags, tol in ((dect.DECT_COUPLED_TV, 1e-3), (dect.DECT_COUPLED_TV | dect.DECT_STEP_ABB, 0.0),
+                       (dect.DECT_STEP_BB2 | dect.DECT_STEP_ABB, 0.0), (64, 0.0),
                        (0, -1e-3), (0, float("nan")), (dect.DECT_WARM_START, float("inf"))):
         prm = dect.dect_adm_params(1.0, 16.0, 4.0, 1.0, 0.8, 5, tol, flags, None)
         assert lib.dect_adm_tv3(dect.ConeArg(g).ref, buf, buf, ct.byref(prm), buf, buf, None,

@@ -4,7 +4,8 @@ each energy on the same FP32 inputs: a 32 x 28 x 12 volume (30 views, 10 x 48
 panel, 30 iterations), a ragged one (37 x 29 x 9, detector offset, 25
 iterations) and a 128 x 128 x 16 one (90 views, 16 x 192 panel, 40
 iterations); a warm start; the relative-change stop rule; the projection
-onto f >= 0 and the BB2 / adaptive steps.
+onto f >= 0 and the BB2 / adaptive steps; the TV coupled across the two
+energies (or_adm3_coupled).
 
 * Images: rel-L2 <= 1e-4.
 * The logged objective of Eq. 4: within 1e-5 over the first 10 iterations,
@@ -194,7 +195,8 @@ def test_refusals(torch):
     from paper_1607_01650_amd import dect
     g = VOL
     z = torch.zeros((g.n_views, g.n_rows, g.n_bins), device="cuda")
-    for change in ({"coupled_tv": True}, {"tol": -1e-3}, {"tol": float("nan")}):
+    for change in ({"coupled_tv": True, "tol": 1e-3}, {"coupled_tv": True, "step": "bb2"},
+                   {"tol": -1e-3}, {"tol": float("nan")}):
         with pytest.raises(dect.DectError):
             dect.adm_tv3(z, z, g, dataclasses.replace(PARAMS, max_iter=2, **change))
 
@@ -230,3 +232,44 @@ def test_full_size_first_iteration(torch):
         assert err <= 1e-5
         assert abs(r.log[0, e] - j0) <= 1e-9 * j0
         assert abs(r.log[0, 2 + e] - alpha0) <= 1e-5 * alpha0
+
+
+@pytest.mark.parametrize("geom,seed,nonneg,warm", [(VOL, 5, False, False), (RAGGED, 6, False, False),
+                                                   (VOL, 7, True, False), (RAGGED, 8, False, True)],
+                         ids=["volume", "ragged", "nonneg", "warm-start"])
+def test_coupled_parity(torch, geom, seed, nonneg, warm):
+    """DECT_COUPLED_TV: one joint z-step over the 6-vector of both energies'
+    gradients, each energy keeping its own f-step and BB1 step; the high
+    energy's J column holds the joint TV, the low one's none."""
+    from paper_1607_01650_amd import dect
+    iters = 25
+    m = _data(geom, seed)
+    if nonneg:
+        rng = np.random.default_rng(seed)
+        m = [f32(a + 0.05 * a.max() * rng.standard_normal(a.shape)) for a in m]
+    x0s = None
+    if warm:
+        x0 = _start_volume(geom, seed)
+        x0s = (x0, f32(1.3 * x0))
+    p = dataclasses.replace(PARAMS, max_iter=iters, coupled_tv=True, nonneg=nonneg)
+    r = dect.adm_tv3(to_dev(torch, m[0]), to_dev(torch, m[1]), geom, p, want_log=True,
+                     x0=None if x0s is None else (to_dev(torch, x0s[0]), to_dev(torch, x0s[1])))
+    x, J, a = O.adm3_coupled(geom, m[0], m[1], p.beta_high, p.beta_low, p.mu, p.rho, p.xi, iters,
+                             x0=x0s, nonneg=nonneg)
+    for e, xe in enumerate((r.x_high, r.x_low)):
+        err = rel_l2(to_np(xe), x[e])
+        jrel = np.abs(r.log[:, e] - J[:, e]) / np.abs(J[:, e])
+        arel = np.abs(r.log[1:, 2 + e] - a[1:, e]) / np.abs(a[1:, e])
+        print(f"3-D coupled ADM {geom.nx}x{geom.ny}x{geom.nz}{' nonneg' if nonneg else ''}"
+              f"{' warm' if warm else ''} energy {e}: image rel-L2 {err:.2e}, J rel err "
+              f"{jrel.max():.2e}, alpha rel err k<=10 {arel[:10].max():.2e}, all "
+              f"{arel.max():.2e}", flush=True)
+        assert err <= 1e-4 and jrel.max() <= 1e-4
+        assert arel[:10].max() <= 1e-4 and arel.max() <= 1e-3
+        if nonneg:
+            assert to_np(xe).min() >= 0.0
+    # the coupling matters here: the per-energy run ends elsewhere
+    xs, _ = O.adm3(geom, m[0], p.beta_high, p.mu, p.rho, p.xi, iters, nonneg=nonneg,
+                   x0=None if x0s is None else x0s[0])
+    assert rel_l2(xs, x[0]) > 1e-3
+    assert r.report.iters == iters
