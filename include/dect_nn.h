@@ -33,6 +33,15 @@ dect_status dect_nn_conv_fwd(const void *x, const void *w, const float *bias, vo
                              int32_t H, int32_t W, int32_t Cin, int32_t Cout, int32_t ksize,
                              int32_t relu, int32_t out_f32, void *stream);
 
+/* dect_nn_conv_fwd with a ReLU's backward fused into the output: y = 0
+ * where mask <= 0 (mask [N][H][W][Cout] bfloat16, 16-byte aligned: the
+ * output of the ReLU that fed the layer whose input gradient this is).
+ * Bit for bit dect_nn_relu_bwd(dect_nn_conv_fwd(...), mask). */
+dect_status dect_nn_conv_fwd_masked(const void *x, const void *w, const float *bias,
+                                    const void *mask, void *y, int32_t N, int32_t H, int32_t W,
+                                    int32_t Cin, int32_t Cout, int32_t ksize, int32_t relu,
+                                    int32_t out_f32, void *stream);
+
 /* Weights of the input-gradient convolution: wd[tap'][CinP][Cout] =
  * w[taps-1-tap'][co][ci] (CinP = Cin rounded up to 16, extra rows zero). */
 dect_status dect_nn_weight_flip(const void *w, void *wd, int32_t Cin, int32_t Cout, int32_t ksize,
@@ -70,6 +79,12 @@ dect_status dect_nn_concat(void *a, void *b, void *z, size_t P, int32_t C1, int3
 
 /* z = a + b (bfloat16, n elements, FP32 arithmetic). */
 dect_status dect_nn_add(const void *a, const void *b, void *z, size_t n, void *stream);
+
+/* z = bf16(a + b) where y > 0, else 0 (bfloat16, n elements): the gradient
+ * of a sum that feeds a ReLU's backward, bit for bit dect_nn_relu_bwd(
+ * dect_nn_add(a, b), y). */
+dect_status dect_nn_add_relu_bwd(const void *a, const void *b, const void *y, void *z, size_t n,
+                                 void *stream);
 
 /* FP32 <-> bfloat16 (round to nearest even). */
 dect_status dect_nn_convert(const void *src, void *dst, size_t n, int32_t to_bf16, void *stream);

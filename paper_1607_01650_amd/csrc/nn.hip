@@ -81,7 +81,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
                                                   const u16 *__restrict__ Wk,
                                                   const float *__restrict__ bias,
                                                   void *__restrict__ Y, int H, int W, int Cin,
-                                                  int Cout, int ks, int relu, int out_f32)
+                                                  int Cout, int ks, int relu, int out_f32,
+                                                  const u16 *__restrict__ mask)
 {
     constexpr int MT = conv_mt(NT);
     constexpr int TR = 2 * MT;
@@ -184,9 +185,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
                 for (int q = 0; q < 4; ++q) {
                     const int rr = r0 + (j >> 1), cc = c0 + 16 * (j & 1) + 4 * grp + q;
                     if (rr < H && cc < W && co < Cout) {
+                        const size_t o = (img + (size_t)rr * W + cc) * Cout + co;
                         float v = acc[i][t][q] + bb;
                         if (relu) v = fmaxf(v, 0.f);
-                        ((float *)Y)[(img + (size_t)rr * W + cc) * Cout + co] = v;
+                        if (mask && !(bf2f(mask[o]) > 0.f)) v = 0.f;
+                        ((float *)Y)[o] = v;
                     }
                 }
             }
@@ -222,8 +225,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
             const int rr = r0 + (p >> 5), cc = c0 + (p & 31);
             if (rr < H && cc < W) {
                 const size_t o = (img + (size_t)rr * W + cc) * Cout + e;
-                if (out_f32) ((float *)Y)[o] = ((const float *)lds_raw)[p * CoutP + e];
-                else ((u16 *)Y)[o] = ((const u16 *)lds_raw)[p * CoutP + e];
+                const bool keep = !mask || bf2f(mask[o]) > 0.f;
+                if (out_f32) ((float *)Y)[o] = keep ? ((const float *)lds_raw)[p * CoutP + e] : 0.f;
+                else ((u16 *)Y)[o] = keep ? ((const u16 *)lds_raw)[p * CoutP + e] : (u16)0;
             }
         }
         return;
@@ -234,280 +238,228 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
         const int rr = r0 + (p >> 5), cc = c0 + (p & 31);
         if (rr < H && cc < W) {
             const size_t o = (img + (size_t)rr * W + cc) * Cout + e;
-            if (out_f32)
-                *(uint4 *)((float *)Y + o) = *(const uint4 *)((const float *)lds_raw + p * CoutP + e);
-            else
-                *(uint4 *)((u16 *)Y + o) = *(const uint4 *)((const u16 *)lds_raw + p * CoutP + e);
+            if (out_f32) {
+                uint4 v = *(const uint4 *)((const float *)lds_raw + p * CoutP + e);
+                if (mask) {
+                    const uint2 mk = *(const uint2 *)(mask + o);
+                    const u16 *em = (const u16 *)&mk;
+                    uint32_t *ev = (uint32_t *)&v;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (!(bf2f(em[q]) > 0.f)) ev[q] = 0u;
+                }
+                *(uint4 *)((float *)Y + o) = v;
+            } else {
+                uint4 v = *(const uint4 *)((const u16 *)lds_raw + p * CoutP + e);
+                if (mask) {
+                    const uint4 mk = *(const uint4 *)(mask + o);
+                    const u16 *em = (const u16 *)&mk;
+                    u16 *ev = (u16 *)&v;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (!(bf2f(em[q]) > 0.f)) ev[q] = 0;
+                }
+                *(uint4 *)((u16 *)Y + o) = v;
+            }
         }
     }
 }
 
 // ----------------------------------------------------------- conv wgrad ---
-// Partial weight gradient of one tap over a chunk of PIX * kch pixels.
-// dZ [P][Cout] (P = N*H*W pixels, Cout % 8 == 0), X [P][Cin] (Cin % 8 == 0),
-// part [nchunk][taps][CoutP][Cin] f32.  (The bias gradient is a separate
-// column sum of dZ, k_bias_partial.)
-// Block = 256 threads.  Each step stages PIX pixels of dZ and of the shifted
-// X transposed in LDS (channel-major, pixel-contiguous rows), so the MFMA
-// fragments (K = 32 pixels) are 16-byte reads, and every wave's TPW output
-// tiles take PIX / 32 matrix-core steps per stage.  TPW is sized to the layer
-// (tiles / 4 rounded up to 2, 4, 8, 16 or 24), which keeps the registers of
-// small layers few and their blocks many per CU: other blocks' matrix work
-// covers one block's staging loads.
-constexpr size_t kWgLdsMax = 65536;
+// Partial weight and bias gradients of one chunk: a strip of kWgPix columns
+// (from c0) of image n over rows [r0, r0 + 4 kst), in steps of four rows.
+// dZ [N][H][W][Cout], X [N][H][W][Cin] (channel counts multiples of 8).
+// Block = 4 waves; wave w takes row r + w of each step.  Per step the block
+// stages, transposed into LDS ([channel][column], bf16):
+//   dZ of the four rows, its TMS output-channel tiles,
+//   X of rows r - 1 .. r + 4 (r .. r + 3 for 1x1), columns c0 - 1 ..
+//   c0 + kWgPix + 2 (c0 .. for 1x1), its TNS input-channel tiles,
+// zero outside the image.  For every k-step of 32 pixels a wave loads its
+// dZ fragments once and, per kernel row dr and input tile, one 16-byte read
+// of the X row plus the next dword, which give the column shifts 0, 1 and 2
+// of the three taps (dr, dc); so each (tap, co tile, ci tile) product is one
+// matrix-core step and dZ and X are read from HBM once per chunk (X rows
+// r - 1 and r + 4 twice).  Threads t < 4 * 16 TMS of the ci-split 0 blocks
+// also sum their dZ row and channel (the bias gradient).  At the end the
+// four waves' sums are added in wave order through LDS and written to
+// part[chunk][taps][CoutP][Cin], the bias to part[chunk][len + co] (len =
+// taps CoutP Cin): every chunk's row is written whole by its split blocks.
+// blockIdx.x = chunk * nsplit + split, split = sm * nsn + sn (co tiles sm
+// TMS.., ci tiles sn TNS..), chunk = strip * nrc + row chunk.
+constexpr int kWgPix = 64;
+constexpr int kWgLD = kWgPix + 8;  // bf16 row stride of the staged arrays
 
-// 128 pixels per stage, or 64 when the staged channels (CoutP + CinP) would
-// not fit 64 KB of LDS at 128.
-inline int wgrad_pix(int CoutP, int CinP)
-{
-    return (size_t)(CoutP + CinP) * (128 + 8) * 2 <= kWgLdsMax ? 128 : 64;
-}
+__host__ __device__ constexpr int wg_xrows(int ks) { return ks == 3 ? 6 : 4; }
 
-template <int PIX, int TPW>
-__global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ dZ,
-                                                    const u16 *__restrict__ X,
-                                                    float *__restrict__ part, int N, int H, int W,
-                                                    int Cin, int Cout, int taps, int kch)
+template <int KS, int TMS, int TNS>
+__global__ __launch_bounds__(256, 2) void k_wgrad(const u16 *__restrict__ dZ,
+                                               const u16 *__restrict__ X,
+                                               float *__restrict__ part, int H, int W, int Cin,
+                                               int Cout, int nstrip, int nrc, int kst, int nsn,
+                                               int nsplit, size_t len, size_t pstride)
 {
-    constexpr int LD = PIX + 8;  // bf16 row stride
-    extern __shared__ u16 lds[];
-    const int CoutP = (Cout + 15) / 16 * 16, CinP = (Cin + 15) / 16 * 16;
-    u16 *sZ = lds;                       // [CoutP][LD]
-    u16 *sX = lds + (size_t)CoutP * LD;  // [CinP][LD]
-    const int chunk = blockIdx.x, tap = blockIdx.y;
+    constexpr int T = KS * KS, XR = wg_xrows(KS), ZC = 16 * TMS, XC = 16 * TNS;
+    constexpr int halo = KS == 3 ? 1 : 0;
+    constexpr int K4X = (kWgPix + 4 * halo) / 4;  // 4-column groups of a staged X row
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    u16 *sZ = (u16 *)lds_raw;           // [4][ZC][kWgLD]
+    u16 *sX = sZ + 4 * ZC * kWgLD;      // [XR][XC][kWgLD]: element k is column c0 - halo + k
+    const int split = blockIdx.x % nsplit, chunk = blockIdx.x / nsplit;
+    const int sm = split / nsn, sn = split - sm * nsn;
+    const int rc = chunk % nrc, strip = chunk / nrc;
+    const int n = strip / nstrip, c0 = (strip - n * nstrip) * kWgPix;
+    const int co0 = sm * ZC, ci0 = sn * XC;
+    const int CoutP = (Cout + 15) / 16 * 16;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int m = lane & 15, grp = lane >> 4;
-    const int tilesN = CinP / 16, ntiles = (CoutP / 16) * tilesN;
-    const size_t P = (size_t)N * H * W, HW = (size_t)H * W;
-    const int dr = taps == 9 ? tap / 3 - 1 : 0, dc = taps == 9 ? tap % 3 - 1 : 0;
-    // staging items: 4 consecutive pixels x 8 channels (four 16-byte loads,
-    // transposed in registers into eight 8-byte LDS writes, one per channel)
-    const int zitems = (PIX / 4) * (CoutP / 8), total = zitems + (PIX / 4) * (CinP / 8);
-    // each wave owns tiles wid, wid + 4, ... (at most TPW per wave)
-    f32x4 acc[TPW];
+    const size_t img = (size_t)n * H * W;
+    const bool bias = sn == 0;
+    f32x4 acc[T][TMS][TNS];
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kk = 0; kk < kch; ++kk) {
-        const size_t p0 = ((size_t)chunk * kch + kk) * PIX;
-        if (p0 >= P) break;
-        __syncthreads();  // the previous step's tiles are done with the LDS
-        for (int it = threadIdx.x; it < total; it += 256) {
-            const bool isz = it < zitems;
-            const int j = isz ? it : it - zitems;
-            const int C = isz ? Cout : Cin, CP8 = (isz ? CoutP : CinP) / 8;
-            const int px4 = j / CP8, c8 = (j - px4 * CP8) * 8;
-            uint4 v[4];
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                v[u] = make_uint4(0, 0, 0, 0);
-                const size_t p = p0 + 4 * px4 + u;
-                if (p < P && c8 < C) {
-                    if (isz) {
-                        v[u] = *(const uint4 *)(dZ + p * Cout + c8);
-                    } else {
-                        const size_t n = p / HW;
-                        const int rem = (int)(p - n * HW);
-                        const int rr = rem / W + dr, cc = rem % W + dc;
-                        if (rr >= 0 && rr < H && cc >= 0 && cc < W)
-                            v[u] = *(const uint4 *)(X + ((n * H + rr) * W + cc) * Cin + c8);
-                    }
-                }
-            }
-            u16 *dst = (isz ? sZ : sX) + (size_t)c8 * LD + 4 * px4;
-            const u16 *e0 = (const u16 *)&v[0], *e1 = (const u16 *)&v[1];
-            const u16 *e2 = (const u16 *)&v[2], *e3 = (const u16 *)&v[3];
+        for (int i = 0; i < TMS; ++i)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                uint2 w;
-                w.x = (uint32_t)e0[q] | ((uint32_t)e1[q] << 16);
-                w.y = (uint32_t)e2[q] | ((uint32_t)e3[q] << 16);
-                *(uint2 *)(dst + (size_t)q * LD) = w;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            const int tt = wid + 4 * i;
-            if (tt < ntiles) {
-                const int tm = tt / tilesN, tn = tt - tm * tilesN;
-#pragma unroll
-                for (int ks = 0; ks < PIX; ks += 32) {
-                    Frag a, b;
-                    a.u = *(const uint4 *)(sZ + (size_t)(tm * 16 + m) * LD + ks + 8 * grp);
-                    b.u = *(const uint4 *)(sX + (size_t)(tn * 16 + m) * LD + ks + 8 * grp);
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[i], 0, 0, 0);
-                }
-            }
-        }
-    }
-    // D[co = 16 tm + 4 grp + i][ci = 16 tn + m], stored as [CoutP][Cin]
-    float *dst = part + ((size_t)chunk * taps + tap) * CoutP * Cin;
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int tt = wid + 4 * i;
-        if (tt < ntiles) {
-            const int tm = tt / tilesN, tn = tt - tm * tilesN;
-            const int ci = tn * 16 + m;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (ci < Cin) dst[(size_t)(tm * 16 + 4 * grp + q) * Cin + ci] = acc[i][q];
-        }
-    }
-}
-
-// Weight gradient of a 3x3 convolution, the three taps of one kernel row per
-// block, for W a multiple of PIX: each step takes PIX pixels of one image
-// row.  It stages dZ of those pixels (transposed, [co][pixel]) and the input
-// row r + dr over columns c0-1 .. c0+PIX (transposed, [ci][column]) once, and
-// each of the three taps dc reads its operand from that row at a column
-// shift of 0, 1 or 2: 16-byte aligned for shift 0, rebuilt from an aligned
-// 16-byte read and the next dword (funnel shift) for 1 and 2.  blockIdx.y =
-// dr-row (0..2) x split; a block owns up to 4 TPW (tap, 16x16 output tile)
-// pairs of its row.  part [nchunk][9][CoutP][Cin] f32, as k_conv_wgrad.
-template <int PIX, int TPW>
-__global__ __launch_bounds__(256) void k_conv_wgrad_rows(const u16 *__restrict__ dZ,
-                                                         const u16 *__restrict__ X,
-                                                         float *__restrict__ part, int N, int H,
-                                                         int W, int Cin, int Cout, int kch,
-                                                         int nsplit)
-{
-    constexpr int LD = PIX + 8;  // bf16 row stride of both staged arrays
-    extern __shared__ u16 lds[];
-    const int CoutP = (Cout + 15) / 16 * 16, CinP = (Cin + 15) / 16 * 16;
-    u16 *sZ = lds;                       // [CoutP][LD]
-    u16 *sX = lds + (size_t)CoutP * LD;  // [CinP][LD]: element k is column c0 - 1 + k
-    const int chunk = blockIdx.x, d = blockIdx.y / nsplit, split = blockIdx.y - d * nsplit;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int m = lane & 15, grp = lane >> 4;
-    const int tilesN = CinP / 16, ntiles = (CoutP / 16) * tilesN, npairs = 3 * ntiles;
-    const int pair0 = split * 4 * TPW;
-    const size_t P = (size_t)N * H * W, HW = (size_t)H * W;
-    const int K4 = (PIX + 4) / 4;  // 4-column groups of the staged row (columns up to c0 + PIX + 2)
-    const int zitems = (PIX / 4) * (CoutP / 8), xitems = K4 * (CinP / 8);
-    f32x4 acc[TPW];
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kk = 0; kk < kch; ++kk) {
-        const size_t p0 = ((size_t)chunk * kch + kk) * PIX;
-        if (p0 >= P) break;
-        const size_t n = p0 / HW;
-        const int rem = (int)(p0 - n * HW);
-        const int r = rem / W, c0 = rem - r * W;
-        const int rr = r + d - 1;
-        __syncthreads();  // the previous step's tiles are done with the LDS
+            for (int j = 0; j < TNS; ++j) acc[t][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    constexpr int zitems = 4 * (kWgPix / 4) * (ZC / 8), xitems = XR * K4X * (XC / 8);
+    for (int st = 0; st < kst; ++st) {
+        const int r = (rc * kst + st) * 4;
+        if (r >= H) break;
+        __syncthreads();  // the previous step is done with the LDS
         for (int it = threadIdx.x; it < zitems + xitems; it += 256) {
             uint4 v[4];
             u16 *dst;
             if (it < zitems) {
-                const int CP8 = CoutP / 8;
-                const int px4 = it / CP8, c8 = (it - px4 * CP8) * 8;
+                constexpr int per_row = (kWgPix / 4) * (ZC / 8);
+                const int q = it / per_row, rem = it - q * per_row;
+                const int px4 = rem / (ZC / 8), o8 = (rem - px4 * (ZC / 8)) * 8;
+                const int rr = r + q, co = co0 + o8;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
+                    const int cc = c0 + 4 * px4 + u;
                     v[u] = make_uint4(0, 0, 0, 0);
-                    if (c8 < Cout) v[u] = *(const uint4 *)(dZ + (p0 + 4 * px4 + u) * Cout + c8);
+                    if (rr < H && cc < W && co < Cout)
+                        v[u] = *(const uint4 *)(dZ + (img + (size_t)rr * W + cc) * Cout + co);
                 }
-                dst = sZ + (size_t)c8 * LD + 4 * px4;
+                dst = sZ + (size_t)(q * ZC + o8) * kWgLD + 4 * px4;
             } else {
-                const int j = it - zitems, CP8 = CinP / 8;
-                const int k4 = j / CP8, c8 = (j - k4 * CP8) * 8;
+                constexpr int per_row = K4X * (XC / 8);
+                const int j = it - zitems;
+                const int q = j / per_row, rem = j - q * per_row;
+                const int k4 = rem / (XC / 8), o8 = (rem - k4 * (XC / 8)) * 8;
+                const int rr = r - halo + q, ci = ci0 + o8;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
+                    const int cc = c0 - halo + 4 * k4 + u;
                     v[u] = make_uint4(0, 0, 0, 0);
-                    const int cc = c0 - 1 + 4 * k4 + u;
-                    if (c8 < Cin && rr >= 0 && rr < H && cc >= 0 && cc < W)
-                        v[u] = *(const uint4 *)(X + ((n * H + rr) * W + cc) * Cin + c8);
+                    if (rr >= 0 && rr < H && cc >= 0 && cc < W && ci < Cin)
+                        v[u] = *(const uint4 *)(X + (img + (size_t)rr * W + cc) * Cin + ci);
                 }
-                dst = sX + (size_t)c8 * LD + 4 * k4;
+                dst = sX + (size_t)(q * XC + o8) * kWgLD + 4 * k4;
             }
             const u16 *e0 = (const u16 *)&v[0], *e1 = (const u16 *)&v[1];
             const u16 *e2 = (const u16 *)&v[2], *e3 = (const u16 *)&v[3];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int e = 0; e < 8; ++e) {
                 uint2 w;
-                w.x = (uint32_t)e0[q] | ((uint32_t)e1[q] << 16);
-                w.y = (uint32_t)e2[q] | ((uint32_t)e3[q] << 16);
-                *(uint2 *)(dst + (size_t)q * LD) = w;
+                w.x = (uint32_t)e0[e] | ((uint32_t)e1[e] << 16);
+                w.y = (uint32_t)e2[e] | ((uint32_t)e3[e] << 16);
+                *(uint2 *)(dst + (size_t)e * kWgLD) = w;
             }
         }
         __syncthreads();
+        if (bias && (int)threadIdx.x < 4 * ZC) {  // row t / ZC, channel t % ZC
+            const u16 *zr = sZ + (size_t)threadIdx.x * kWgLD;
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            const int pi = pair0 + wid + 4 * i;
-            if (pi < npairs) {
-                const int sh = pi / ntiles, tt = pi - sh * ntiles;  // column shift 0..2
-                const int tm = tt / tilesN, tn = tt - tm * tilesN;
-                const u16 *zr = sZ + (size_t)(tm * 16 + m) * LD + 8 * grp;
-                const u16 *xr = sX + (size_t)(tn * 16 + m) * LD + 8 * grp;
+            for (int k = 0; k < kWgPix; k += 8) {
+                const uint4 v = *(const uint4 *)(zr + k);
+                const u16 *e = (const u16 *)&v;
 #pragma unroll
-                for (int ks = 0; ks < PIX; ks += 32) {
-                    Frag a, b;
-                    a.u = *(const uint4 *)(zr + ks);
-                    const uint4 v = *(const uint4 *)(xr + ks);
-                    if (sh == 0) {
-                        b.u = v;
-                    } else {
-                        const uint32_t nx = *(const uint32_t *)(xr + ks + 8);
-                        if (sh == 2) {
-                            b.u = make_uint4(v.y, v.z, v.w, nx);
-                        } else {
-                            b.u = make_uint4(__builtin_amdgcn_alignbit(v.y, v.x, 16),
-                                             __builtin_amdgcn_alignbit(v.z, v.y, 16),
-                                             __builtin_amdgcn_alignbit(v.w, v.z, 16),
-                                             __builtin_amdgcn_alignbit(nx, v.w, 16));
-                        }
-                    }
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[i], 0, 0, 0);
-                }
+                for (int q = 0; q < 8; ++q) bsum += bf2f(e[q]);
             }
         }
-    }
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int pi = pair0 + wid + 4 * i;
-        if (pi < npairs) {
-            const int sh = pi / ntiles, tt = pi - sh * ntiles;
-            const int tm = tt / tilesN, tn = tt - tm * tilesN;
-            float *dst = part + ((size_t)chunk * 9 + 3 * d + sh) * CoutP * Cin;
-            const int ci = tn * 16 + m;
+        for (int ks = 0; ks < kWgPix; ks += 32) {
+            Frag a[TMS];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (ci < Cin) dst[(size_t)(tm * 16 + 4 * grp + q) * Cin + ci] = acc[i][q];
+            for (int i = 0; i < TMS; ++i)
+                a[i].u = *(const uint4 *)(sZ + (size_t)(wid * ZC + i * 16 + m) * kWgLD + 8 * grp + ks);
+#pragma unroll
+            for (int dr = 0; dr < KS; ++dr)
+#pragma unroll
+                for (int j = 0; j < TNS; ++j) {
+                    const u16 *xr = sX + (size_t)((wid + dr) * XC + j * 16 + m) * kWgLD + 8 * grp + ks;
+                    Frag b0;
+                    b0.u = *(const uint4 *)xr;
+                    if constexpr (KS == 1) {
+#pragma unroll
+                        for (int i = 0; i < TMS; ++i)
+                            acc[0][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i].v, b0.v,
+                                                                                   acc[0][i][j], 0, 0, 0);
+                    } else {
+                        const uint4 v = b0.u;
+                        const uint32_t nx = *(const uint32_t *)(xr + 8);
+                        Frag b1, b2;
+                        b1.u = make_uint4(__builtin_amdgcn_alignbit(v.y, v.x, 16),
+                                          __builtin_amdgcn_alignbit(v.z, v.y, 16),
+                                          __builtin_amdgcn_alignbit(v.w, v.z, 16),
+                                          __builtin_amdgcn_alignbit(nx, v.w, 16));
+                        b2.u = make_uint4(v.y, v.z, v.w, nx);
+#pragma unroll
+                        for (int i = 0; i < TMS; ++i) {
+                            acc[3 * dr][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a[i].v, b0.v, acc[3 * dr][i][j], 0, 0, 0);
+                            acc[3 * dr + 1][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a[i].v, b1.v, acc[3 * dr + 1][i][j], 0, 0, 0);
+                            acc[3 * dr + 2][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a[i].v, b2.v, acc[3 * dr + 2][i][j], 0, 0, 0);
+                        }
+                    }
+                }
         }
     }
-}
-
-// Bias gradient partials: dbp[b][co] = sum of dZ[p][co] over the pixels of
-// block b (kBiasPix of them).  Thread t sums channel group t % (Cout / 8) over
-// pixels t / (Cout / 8), + 256 / (Cout / 8), ...; the threads of a group are
-// then added in thread order.
-constexpr int kBiasPix = 2048;
-__global__ __launch_bounds__(256) void k_bias_partial(const u16 *__restrict__ dZ,
-                                                      float *__restrict__ dbp, size_t P, int Cout,
-                                                      int CoutP)
-{
-    __shared__ float red[256][9];
-    const int g8 = Cout / 8;  // Cout % 8 == 0, Cout <= 256 -> g8 <= 32
-    const int grpi = threadIdx.x % g8, row = threadIdx.x / g8, rows = 256 / g8;
-    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const size_t p0 = (size_t)blockIdx.x * kBiasPix;
-    if (row < rows)
-        for (int px = row; px < kBiasPix; px += rows) {
-            const size_t p = p0 + px;
-            if (p >= P) break;
-            const uint4 v = *(const uint4 *)(dZ + p * Cout + 8 * grpi);
-            const u16 *e = (const u16 *)&v;
+    // the waves' sums, added in wave order, one tap at a time
+    float *red = (float *)lds_raw;  // [3][TMS][TNS][4][64]
+    float *dst = part + (size_t)chunk * pstride;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] += bf2f(e[q]);
+    for (int t = 0; t < T; ++t) {
+        __syncthreads();
+        if (wid > 0) {
+#pragma unroll
+            for (int i = 0; i < TMS; ++i)
+#pragma unroll
+                for (int j = 0; j < TNS; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        red[((((wid - 1) * TMS + i) * TNS + j) * 4 + q) * 64 + lane] = acc[t][i][j][q];
         }
+        __syncthreads();
+        if (wid == 0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) red[threadIdx.x][q] = a[q];
-    __syncthreads();
-    if ((int)threadIdx.x < CoutP) {
-        const int co = threadIdx.x;
-        float sum = 0.f;
-        if (co < Cout)
-            for (int r = 0; r < rows; ++r) sum += red[r * g8 + co / 8][co % 8];
-        dbp[(size_t)blockIdx.x * CoutP + co] = sum;
+            for (int i = 0; i < TMS; ++i)
+#pragma unroll
+                for (int j = 0; j < TNS; ++j) {
+                    const int ci = ci0 + j * 16 + m;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float v = acc[t][i][j][q];
+#pragma unroll
+                        for (int w = 0; w < 3; ++w) v += red[(((w * TMS + i) * TNS + j) * 4 + q) * 64 + lane];
+                        if (ci < Cin)
+                            dst[((size_t)t * CoutP + co0 + i * 16 + 4 * grp + q) * Cin + ci] = v;
+                    }
+                }
+        }
+    }
+    if (bias) {
+        __syncthreads();
+        if ((int)threadIdx.x < 4 * ZC) red[threadIdx.x] = bsum;
+        __syncthreads();
+        if ((int)threadIdx.x < ZC) {
+            const int c = threadIdx.x;
+            dst[len + co0 + c] = ((red[c] + red[ZC + c]) + red[2 * ZC + c]) + red[3 * ZC + c];
+        }
     }
 }
 
@@ -532,25 +484,29 @@ __global__ __launch_bounds__(256) void k_sum_seg(const float *__restrict__ part,
     seg[(size_t)blockIdx.y * len + i] = (a0 + a1) + (a2 + a3);
 }
 
-// out[i] = sum_s seg[s][i] in segment order
-__global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ part,
-                                                    float *__restrict__ out, int nchunk,
-                                                    size_t len)
+// The sum of the nseg segments in segment order: element i < len0 to out0[i],
+// the rest to out1[i - len0].
+__global__ __launch_bounds__(256) void k_sum_out(const float *__restrict__ seg,
+                                                 float *__restrict__ out0, float *__restrict__ out1,
+                                                 int nseg, size_t len0, size_t len)
 {
-    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= len) return;
     float s = 0.f;
-    for (int q = 0; q < nchunk; ++q) s += part[(size_t)q * len + i];
-    out[i] = s;
+    for (int q = 0; q < nseg; ++q) s += seg[(size_t)q * len + i];
+    if (i < len0) out0[i] = s;
+    else out1[i - len0] = s;
 }
 
 // Segments for summing nchunk partials of len values: enough blocks to
-// spread the reads over the GPU, at least 8 chunks per segment.
+// spread the reads over the GPU, at least 4 chunks per segment and at most
+// 64 segments (the second pass adds them one after another).
 inline int sum_segments(int nchunk, size_t len)
 {
     const size_t bx = (len + 255) / 256;
     size_t S = (2048 + bx - 1) / bx;
-    S = std::min<size_t>(S, (size_t)std::max(1, nchunk / 8));
+    S = std::min<size_t>(S, (size_t)std::max(1, nchunk / 4));
+    S = std::min<size_t>(S, 64);
     return (int)std::max<size_t>(1, S);
 }
 
@@ -664,6 +620,28 @@ __global__ void k_add(const u16 *__restrict__ a, const u16 *__restrict__ b, u16 
 {
     size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) z[i] = f2bf(bf2f(a[i]) + bf2f(b[i]));
+}
+
+// z = bf16(a + b) where y > 0, else 0 (a sum's gradient through a ReLU)
+__global__ void k_add_relu_bwd(const u16 *__restrict__ a, const u16 *__restrict__ b,
+                               const u16 *__restrict__ y, u16 *__restrict__ z, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    z[i] = bf2f(y[i]) > 0.f ? f2bf(bf2f(a[i]) + bf2f(b[i])) : (u16)0;
+}
+
+__global__ void k_add_relu_bwd8(const uint4 *__restrict__ a, const uint4 *__restrict__ b,
+                                const uint4 *__restrict__ y, uint4 *__restrict__ z, size_t n8)
+{
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n8) return;
+    uint4 x = a[i], w = b[i], m = y[i], r;
+    const u16 *ex = (const u16 *)&x, *ew = (const u16 *)&w, *em = (const u16 *)&m;
+    u16 *er = (u16 *)&r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) er[q] = bf2f(em[q]) > 0.f ? f2bf(bf2f(ex[q]) + bf2f(ew[q])) : (u16)0;
+    z[i] = r;
 }
 
 __global__ void k_add8(const uint4 *__restrict__ a, const uint4 *__restrict__ b,
@@ -851,24 +829,27 @@ extern "C" {
 
 const char *dect_nn_last_error(void) { return g_nn_err; }
 
-dect_status dect_nn_conv_fwd(const void *x, const void *w, const float *bias, void *y, int32_t N,
-                             int32_t H, int32_t W, int32_t Cin, int32_t Cout, int32_t ksize,
-                             int32_t relu, int32_t out_f32, void *stream)
+static dect_status conv_fwd_launch(const void *x, const void *w, const float *bias,
+                                   const void *mask, void *y, int32_t N, int32_t H, int32_t W,
+                                   int32_t Cin, int32_t Cout, int32_t ksize, int32_t relu,
+                                   int32_t out_f32, void *stream)
 {
     if (!x || !w || !y || N <= 0 || H <= 0 || W <= 0 || Cin <= 0 || Cout <= 0)
         return nn_fail(DECT_ERR_INVALID_ARG, "conv_fwd: bad arguments");
     if (Cin % 8 != 0 || Cout > 256 || (ksize != 1 && ksize != 3))
         return nn_fail(DECT_ERR_INVALID_ARG, "conv_fwd: Cin % 8, Cout <= 256, ksize in {1,3}");
+    if (mask && (((uintptr_t)mask & 15) != 0))
+        return nn_fail(DECT_ERR_INVALID_ARG, "conv_fwd: mask must be 16-byte aligned");
     const int NT = (Cout + 15) / 16;
     hipStream_t s = (hipStream_t)stream;
-    const u16 *X = (const u16 *)x, *Wk = (const u16 *)w;
+    const u16 *X = (const u16 *)x, *Wk = (const u16 *)w, *Mk = (const u16 *)mask;
     switch (NT) {
 #define CASE(nt)                                                                         \
     case nt: {                                                                           \
         dim3 grid((W + 31) / 32, (H + 2 * conv_mt(nt) - 1) / (2 * conv_mt(nt)), N);      \
         hipLaunchKernelGGL(k_conv_fwd<nt>, grid, dim3(256),                                \
                            (unsigned)conv_fwd_lds(nt, Cin, ksize, out_f32), s, X, Wk, bias, y, \
-                           H, W, Cin, Cout, ksize, relu, out_f32);                       \
+                           H, W, Cin, Cout, ksize, relu, out_f32, Mk);                   \
     } break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
@@ -878,72 +859,88 @@ dect_status dect_nn_conv_fwd(const void *x, const void *w, const float *bias, vo
     return DECT_OK;
 }
 
-// Pixel steps per wgrad block: enough blocks (chunks x taps) to fill the
-// GPU several times over, at most 4096 pixels per block.
-static int wgrad_steps(size_t P, int taps, int pix)
+dect_status dect_nn_conv_fwd(const void *x, const void *w, const float *bias, void *y, int32_t N,
+                             int32_t H, int32_t W, int32_t Cin, int32_t Cout, int32_t ksize,
+                             int32_t relu, int32_t out_f32, void *stream)
 {
-    const size_t steps = (P + pix - 1) / pix;
-    const size_t want_chunks = (4096 + (size_t)taps - 1) / taps;
-    size_t kch = (steps + want_chunks - 1) / want_chunks;
-    return (int)std::max<size_t>(1, std::min<size_t>(4096 / pix, kch));
+    return conv_fwd_launch(x, w, bias, nullptr, y, N, H, W, Cin, Cout, ksize, relu, out_f32,
+                           stream);
+}
+
+dect_status dect_nn_conv_fwd_masked(const void *x, const void *w, const float *bias,
+                                    const void *mask, void *y, int32_t N, int32_t H, int32_t W,
+                                    int32_t Cin, int32_t Cout, int32_t ksize, int32_t relu,
+                                    int32_t out_f32, void *stream)
+{
+    if (!mask) return nn_fail(DECT_ERR_INVALID_ARG, "conv_fwd_masked: null mask");
+    return conv_fwd_launch(x, w, bias, mask, y, N, H, W, Cin, Cout, ksize, relu, out_f32, stream);
+}
+
+// Tiles per weight-gradient block: TMS output-channel x TNS input-channel
+// tiles (taps x TMS x TNS accumulators of four floats per lane: at most 144
+// for 3x3; staged rows within 64 KB of LDS for 1x1), the first entry of a
+// fixed list that divides the layer's tile counts.
+struct WgTiles {
+    int tms, tns;
+};
+
+static WgTiles wgrad_tiles(int ks, int TM, int TN)
+{
+    static const WgTiles k3[] = {{2, 2}, {3, 1}, {2, 1}, {1, 2}, {1, 1}};
+    static const WgTiles k1[] = {{4, 2}, {3, 3}, {2, 3}, {3, 2}, {4, 1}, {2, 2},
+                                 {3, 1}, {1, 3}, {2, 1}, {1, 2}, {1, 1}};
+    const WgTiles *list = ks == 3 ? k3 : k1;
+    const int n = ks == 3 ? 5 : 11;
+    for (int i = 0; i < n; ++i)
+        if (TM % list[i].tms == 0 && TN % list[i].tns == 0) return list[i];
+    return {1, 1};
 }
 
 struct WgradPlan {
-    int rows;                 // 1: k_conv_wgrad_rows (all taps per block), 0: per tap
-    int pix, kch, nchunk, nsplit, tpw, nbias, segw, segb;
-    size_t lds, part_floats, dbp_floats, segw_floats, segb_floats;
+    int tms, tns, nsm, nsn, nstrip, nrc, kst, nchunk, nseg;
+    size_t lds, len, pstride;
 };
 
 static WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int ksize)
 {
     WgradPlan q;
     const int CoutP = (Cout + 15) / 16 * 16, CinP = (Cin + 15) / 16 * 16;
-    const size_t P = (size_t)N * H * W;
-    const int taps = ksize * ksize;
-    const int ntiles = (CoutP / 16) * (CinP / 16);
-    q.rows = 0;
-    q.nsplit = 1;
-    if (ksize == 3) {  // the row-window kernel: widest pixel step that fits
-        for (int pix : {128, 64, 32}) {
-            const size_t lds = (size_t)(CoutP + CinP) * (pix + 8) * 2;
-            if (W % pix == 0 && lds <= kWgLdsMax) {
-                q.rows = 1;
-                q.pix = pix;
-                q.lds = lds;
-                break;
-            }
-        }
-    }
-    if (q.rows) {
-        const int pairs = 3 * ntiles;  // per kernel row
-        q.tpw = pairs <= 16 ? 4 : (pairs <= 32 ? 8 : 16);
-        q.nsplit = (pairs + 4 * q.tpw - 1) / (4 * q.tpw);
-        const size_t steps = P / q.pix;
-        const size_t want = (2048 + 3 * (size_t)q.nsplit - 1) / (3 * q.nsplit);  // chunks
-        q.kch = (int)std::max<size_t>(1, std::min<size_t>(4096 / q.pix, (steps + want - 1) / want));
-    } else {
-        q.pix = wgrad_pix(CoutP, CinP);
-        q.lds = (size_t)(CoutP + CinP) * (q.pix + 8) * 2;
-        q.tpw = (ntiles + 3) / 4;
-        q.kch = wgrad_steps(P, taps, q.pix);
-    }
-    q.nchunk = (int)((P + (size_t)q.pix * q.kch - 1) / ((size_t)q.pix * q.kch));
-    const size_t len = (size_t)taps * CoutP * Cin;
-    q.nbias = (int)((P + kBiasPix - 1) / kBiasPix);
-    q.segw = sum_segments(q.nchunk, len);
-    q.segb = sum_segments(q.nbias, (size_t)CoutP);
-    q.part_floats = (size_t)q.nchunk * len;
-    q.dbp_floats = (size_t)q.nbias * CoutP;
-    q.segw_floats = (size_t)q.segw * len;
-    q.segb_floats = (size_t)q.segb * CoutP;
+    const WgTiles t = wgrad_tiles(ksize, CoutP / 16, CinP / 16);
+    q.tms = t.tms;
+    q.tns = t.tns;
+    q.nsm = CoutP / 16 / t.tms;
+    q.nsn = CinP / 16 / t.tns;
+    const int nsplit = q.nsm * q.nsn;
+    q.nstrip = (W + kWgPix - 1) / kWgPix;
+    const size_t RG = (size_t)(H + 3) / 4;  // steps of four rows per strip
+    const size_t strips = (size_t)N * q.nstrip;
+    q.len = (size_t)ksize * ksize * CoutP * Cin;
+    q.pstride = q.len + CoutP;
+    // about 768 blocks (three per CU), fewer while the partials would
+    // outweigh twice the layer's own bytes
+    size_t kst = std::max<size_t>(1, (strips * RG * nsplit + 767) / 768);
+    const double in_bytes = (double)N * H * W * (Cin + Cout) * 2;
+    while (kst < RG && (double)strips * ((RG + kst - 1) / kst) * q.pstride * 4 > 2.0 * in_bytes)
+        kst *= 2;
+    kst = std::min(kst, RG);
+    q.kst = (int)kst;
+    q.nrc = (int)((RG + kst - 1) / kst);
+    q.nchunk = (int)(strips * q.nrc);
+    q.nseg = sum_segments(q.nchunk, q.pstride);
+    const size_t stage =
+        ((size_t)4 * 16 * t.tms + (size_t)wg_xrows(ksize) * 16 * t.tns) * kWgLD * sizeof(u16);
+    const size_t red = (size_t)3 * t.tms * t.tns * 4 * 64 * sizeof(float);
+    q.lds = std::max(stage, red);
     return q;
 }
 
 size_t dect_nn_wgrad_workspace(int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t Cout,
                                int32_t ksize)
 {
+    if (N <= 0 || H <= 0 || W <= 0 || Cin <= 0 || Cout <= 0 || (ksize != 1 && ksize != 3))
+        return 0;
     const WgradPlan q = wgrad_plan(N, H, W, Cin, Cout, ksize);
-    return (q.part_floats + q.dbp_floats + q.segw_floats + q.segb_floats) * sizeof(float);
+    return ((size_t)q.nchunk + q.nseg) * q.pstride * sizeof(float);
 }
 
 dect_status dect_nn_conv_wgrad(const void *dz, const void *x, float *dw, float *db, int32_t N,
@@ -952,67 +949,37 @@ dect_status dect_nn_conv_wgrad(const void *dz, const void *x, float *dw, float *
 {
     if (!dz || !x || !dw || !db || !workspace || N <= 0 || H <= 0 || W <= 0)
         return nn_fail(DECT_ERR_INVALID_ARG, "conv_wgrad: bad arguments");
-    if (Cin % 8 != 0 || Cout % 8 != 0 || Cin > 256 || Cout > 256 || (ksize != 1 && ksize != 3))
+    if (Cin <= 0 || Cout <= 0 || Cin % 8 != 0 || Cout % 8 != 0 || Cin > 256 || Cout > 256 ||
+        (ksize != 1 && ksize != 3))
         return nn_fail(DECT_ERR_INVALID_ARG, "conv_wgrad: Cin, Cout % 8 and <= 256");
-    const int CoutP = (Cout + 15) / 16 * 16, CinP = (Cin + 15) / 16 * 16;
-    const int ntiles = (CoutP / 16) * (CinP / 16);
-    if (ntiles > 4 * 24) return nn_fail(DECT_ERR_INVALID_ARG, "conv_wgrad: Cout*Cin tile count too large");
     if (ws_bytes < dect_nn_wgrad_workspace(N, H, W, Cin, Cout, ksize))
         return nn_fail(DECT_ERR_INVALID_ARG, "conv_wgrad: workspace too small");
-    const int taps = ksize * ksize;
     const WgradPlan q = wgrad_plan(N, H, W, Cin, Cout, ksize);
+    const size_t nblk = (size_t)q.nchunk * q.nsm * q.nsn;
+    if (nblk > 0x7fffffffu) return nn_fail(DECT_ERR_INVALID_ARG, "conv_wgrad: problem too large");
     float *part = (float *)workspace;
-    float *dbp = part + q.part_floats;
-    float *segw = dbp + q.dbp_floats;
-    float *segb = segw + q.segw_floats;
+    float *seg = part + (size_t)q.nchunk * q.pstride;
     hipStream_t s = (hipStream_t)stream;
-    const size_t lds = q.lds;
-    if (lds > kWgLdsMax) return nn_fail(DECT_ERR_INVALID_ARG, "conv_wgrad: too many channels");
-    const int tpw = q.tpw;
-    const dim3 grid(q.nchunk, taps);
     const u16 *Z = (const u16 *)dz, *Xp = (const u16 *)x;
-#define WR(pix, t)                                                                         \
-    hipLaunchKernelGGL((k_conv_wgrad_rows<pix, t>), dim3(q.nchunk, 3 * q.nsplit), dim3(256), \
-                       lds, s, Z, Xp, part, N, H, W, Cin, Cout, q.kch, q.nsplit)
-#define WG(pix, t)                                                                          \
-    hipLaunchKernelGGL((k_conv_wgrad<pix, t>), grid, dim3(256), lds, s, Z, Xp, part, N, H, W,  \
-                       Cin, Cout, taps, q.kch)
-#define WRT(pix)                           \
-    if (tpw == 4) WR(pix, 4);              \
-    else if (tpw == 8) WR(pix, 8);         \
-    else WR(pix, 16);
-    if (q.rows) {
-        if (q.pix == 128) { WRT(128) }
-        else if (q.pix == 64) { WRT(64) }
-        else { WRT(32) }
-    } else if (q.pix == 128) {
-        if (tpw <= 2) WG(128, 2);
-        else if (tpw <= 4) WG(128, 4);
-        else if (tpw <= 8) WG(128, 8);
-        else if (tpw <= 16) WG(128, 16);
-        else WG(128, 24);
-    } else {
-        if (tpw <= 2) WG(64, 2);
-        else if (tpw <= 4) WG(64, 4);
-        else if (tpw <= 8) WG(64, 8);
-        else if (tpw <= 16) WG(64, 16);
-        else WG(64, 24);
+    bool launched = false;
+#define WG(ks, a, b)                                                                          \
+    if (!launched && ksize == ks && q.tms == a && q.tns == b) {                               \
+        hipLaunchKernelGGL((k_wgrad<ks, a, b>), dim3((unsigned)nblk), dim3(256), q.lds, s, Z, \
+                           Xp, part, H, W, Cin, Cout, q.nstrip, q.nrc, q.kst, q.nsn,          \
+                           q.nsm * q.nsn, q.len, q.pstride);                                  \
+        launched = true;                                                                      \
     }
+    WG(3, 2, 2) WG(3, 3, 1) WG(3, 2, 1) WG(3, 1, 2) WG(3, 1, 1)
+    WG(1, 4, 2) WG(1, 3, 3) WG(1, 2, 3) WG(1, 3, 2) WG(1, 4, 1) WG(1, 2, 2)
+    WG(1, 3, 1) WG(1, 1, 3) WG(1, 2, 1) WG(1, 1, 2) WG(1, 1, 1)
 #undef WG
-#undef WR
-#undef WRT
+    if (!launched) return nn_fail(DECT_ERR_INVALID_ARG, "conv_wgrad: no kernel for this tiling");
     NN_HIP(hipGetLastError());
-    const size_t len = (size_t)taps * CoutP * Cin;
-    const int Lw = (q.nchunk + q.segw - 1) / q.segw, Lb = (q.nbias + q.segb - 1) / q.segb;
-    hipLaunchKernelGGL(k_sum_seg, dim3(blocks(len), q.segw), dim3(256), 0, s, part, segw,
-                       q.nchunk, len, Lw);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(len)), dim3(256), 0, s, segw, dw, q.segw, len);
-    hipLaunchKernelGGL(k_bias_partial, dim3(q.nbias), dim3(256), 0, s, Z, dbp, (size_t)N * H * W,
-                       Cout, CoutP);
-    hipLaunchKernelGGL(k_sum_seg, dim3(blocks(CoutP), q.segb), dim3(256), 0, s, dbp, segb,
-                       q.nbias, (size_t)CoutP, Lb);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(CoutP)), dim3(256), 0, s, segb, db, q.segb,
-                       (size_t)CoutP);
+    const int L = (q.nchunk + q.nseg - 1) / q.nseg;
+    hipLaunchKernelGGL(k_sum_seg, dim3(blocks(q.pstride), q.nseg), dim3(256), 0, s, part, seg,
+                       q.nchunk, q.pstride, L);
+    hipLaunchKernelGGL(k_sum_out, dim3(blocks(q.pstride)), dim3(256), 0, s, seg, dw, db, q.nseg,
+                       q.len, q.pstride);
     NN_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -1109,6 +1076,21 @@ dect_status dect_nn_add(const void *a, const void *b, void *z, size_t n, void *s
     else
         hipLaunchKernelGGL(k_add, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream,
                            (const u16 *)a, (const u16 *)b, (u16 *)z, n);
+    NN_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+dect_status dect_nn_add_relu_bwd(const void *a, const void *b, const void *y, void *z, size_t n,
+                                 void *stream)
+{
+    if (n == 0) return DECT_OK;
+    if (!a || !b || !y || !z) return nn_fail(DECT_ERR_INVALID_ARG, "add_relu_bwd: null argument");
+    if (n % 8 == 0 && aligned16(a) && aligned16(b) && aligned16(y) && aligned16(z))
+        hipLaunchKernelGGL(k_add_relu_bwd8, dim3(blocks(n / 8)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint4 *)a, (const uint4 *)b, (const uint4 *)y, (uint4 *)z, n / 8);
+    else
+        hipLaunchKernelGGL(k_add_relu_bwd, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream,
+                           (const u16 *)a, (const u16 *)b, (const u16 *)y, (u16 *)z, n);
     NN_HIP(hipGetLastError());
     return DECT_OK;
 }

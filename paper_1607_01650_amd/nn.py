@@ -33,6 +33,9 @@ def _lib():
         P, vp, i32, d, sz = ct.POINTER, ct.c_void_p, ct.c_int32, ct.c_double, ct.c_size_t
         sig = {
             "dect_nn_conv_fwd": [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, vp],
+            "dect_nn_conv_fwd_masked": [vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32,
+                                        i32, vp],
+            "dect_nn_add_relu_bwd": [vp, vp, vp, vp, sz, vp],
             "dect_nn_weight_flip": [vp, vp, i32, i32, i32, vp],
             "dect_nn_conv_wgrad": [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, sz, vp],
             "dect_nn_relu_bwd": [vp, vp, vp, sz, vp],
@@ -71,13 +74,20 @@ def _s():
 
 
 # ---------------------------------------------------------------- ops ---
-def conv_fwd(x, w, b, cout, ksize, relu, out_f32=False):
-    """x [N,H,W,Cin] bf16, w [taps,CoutP,Cin] bf16, b [CoutP] f32."""
+def conv_fwd(x, w, b, cout, ksize, relu, out_f32=False, mask=None):
+    """x [N,H,W,Cin] bf16, w [taps,CoutP,Cin] bf16, b [CoutP] f32; with mask
+    [N,H,W,cout] bf16 the output is zero where mask <= 0 (a ReLU's backward)."""
     N, H, W, Cin = x.shape
     y = torch.empty((N, H, W, cout), device=x.device,
                     dtype=torch.float32 if out_f32 else torch.bfloat16)
-    _ck(_lib().dect_nn_conv_fwd(_p(x), _p(w), _p(b), _p(y), N, H, W, Cin, cout, ksize,
-                                int(relu), int(out_f32), _s()), "conv_fwd")
+    if mask is None:
+        _ck(_lib().dect_nn_conv_fwd(_p(x), _p(w), _p(b), _p(y), N, H, W, Cin, cout, ksize,
+                                    int(relu), int(out_f32), _s()), "conv_fwd")
+    else:
+        assert mask.shape == y.shape and mask.dtype == torch.bfloat16 and mask.is_contiguous()
+        _ck(_lib().dect_nn_conv_fwd_masked(_p(x), _p(w), _p(b), _p(mask), _p(y), N, H, W, Cin,
+                                           cout, ksize, int(relu), int(out_f32), _s()),
+            "conv_fwd_masked")
     return y
 
 
@@ -166,6 +176,13 @@ def add(a, b):
     return z
 
 
+def add_relu_bwd(a, b, y):
+    """(a + b) where y > 0, else 0 (bf16): a sum's gradient through a ReLU."""
+    z = torch.empty_like(a)
+    _ck(_lib().dect_nn_add_relu_bwd(_p(a), _p(b), _p(y), _p(z), a.numel(), _s()), "add_relu_bwd")
+    return z
+
+
 def to_bf16(x):
     y = torch.empty(x.shape, device=x.device, dtype=torch.bfloat16)
     _ck(_lib().dect_nn_convert(_p(x.contiguous()), _p(y), x.numel(), 1, _s()), "convert")
@@ -214,12 +231,17 @@ class Conv:
     def forward(self, x, out_f32=False):
         return conv_fwd(x, self.wb, self.b, self.cout, self.k, self.relu, out_f32)
 
-    def backward(self, dy, x, y):
-        """dy at the output (bf16); returns dx (bf16); accumulates gw, gb."""
-        dz = relu_bwd(dy, y) if self.relu else dy
+    def backward(self, dy, x, y, dy_masked=False, mask_dx=False, need_dx=True):
+        """dy at the output (bf16; dy_masked: already through this layer's
+        ReLU backward); fills gw, gb and returns dx (bf16), or None without
+        need_dx.  mask_dx: x is a ReLU's output, and dx leaves through that
+        ReLU's backward (fused into the input-gradient convolution)."""
+        dz = relu_bwd(dy, y) if self.relu and not dy_masked else dy
         conv_wgrad(dz, x, self.cout, self.k, self.gw, self.gb)
+        if not need_dx:
+            return None
         wd = weight_flip(self.wb, self.cin, self.cout, self.k)
-        return conv_fwd(dz, wd, None, self.cin, self.k, False)
+        return conv_fwd(dz, wd, None, self.cin, self.k, False, mask=x if mask_dx else None)
 
     def adam(self, lr, step, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
         L = _lib()
@@ -314,29 +336,34 @@ class UNet:
 
     def backward(self, dy):
         """dy: gradient at the f32 output [N,H,W,8]; fills every layer's gw/gb."""
+        # Every ReLU's backward is fused into the gradient that reaches it:
+        # the input-gradient convolution of the layer it feeds (mask_dx), or
+        # the skip connection's sum ahead of a pooling.  The network input
+        # needs no gradient.
         t = self._t
-        dh = self.out.backward(to_bf16(dy), t["dout_in"], None)
+        dh = self.out.backward(to_bf16(dy), t["dout_in"], None, mask_dx=True)
         dskip = [None, None, None]
         # decoder in reverse order: j = 2 (level 0) ... j = 0 (level 2)
         for j in (2, 1, 0):
             lvl = (2, 1, 0)[j]
             c = self.ch[lvl]
-            da = self.dec[j][1].backward(dh, t[f"d{j}a"], t[f"d{j}b"])
-            dz = self.dec[j][0].backward(da, t[f"z{j}"], t[f"d{j}a"])
+            da = self.dec[j][1].backward(dh, t[f"d{j}a"], t[f"d{j}b"], dy_masked=True,
+                                         mask_dx=True)
+            dz = self.dec[j][0].backward(da, t[f"z{j}"], t[f"d{j}a"], dy_masked=True)
             du, ds = split(dz, c)
             dskip[lvl] = ds
             dt = unshuffle(du, c)
-            dh = self.up[j].backward(dt, t[f"uin{j}"], None)
+            dh = self.up[j].backward(dt, t[f"uin{j}"], None, mask_dx=True)
         # encoder in reverse
         for lvl in (3, 2, 1, 0):
             if lvl < 3:
-                db_ = pool_bwd(dh, t[f"i{lvl}"])
-                dh = add(db_, dskip[lvl])
+                dh = add_relu_bwd(pool_bwd(dh, t[f"i{lvl}"]), dskip[lvl], t[f"e{lvl}b"])
             inp = t["x"] if lvl == 0 else t[f"p{lvl - 1}"]
-            da = self.enc[lvl][1].backward(dh, t[f"e{lvl}a"], t[f"e{lvl}b"])
-            dh = self.enc[lvl][0].backward(da, inp, t[f"e{lvl}a"])
+            da = self.enc[lvl][1].backward(dh, t[f"e{lvl}a"], t[f"e{lvl}b"], dy_masked=True,
+                                           mask_dx=True)
+            dh = self.enc[lvl][0].backward(da, inp, t[f"e{lvl}a"], dy_masked=True,
+                                           need_dx=lvl > 0)
         self._t = None
-        return dh
 
     def adam_step(self, lr: float):
         self.step += 1

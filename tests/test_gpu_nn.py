@@ -38,7 +38,9 @@ CASES = [  # N, H, W, Cin, Cout, k
     (2, 8, 72, 8, 32, 3), (1, 16, 64, 32, 48, 3), (1, 4, 130, 96, 64, 3),
     (2, 8, 64, 128, 64, 3), (1, 8, 64, 96, 256, 1), (2, 3, 256, 8, 32, 3),
     (1, 5, 128, 64, 32, 3), (1, 6, 40, 32, 8, 1), (1, 4, 64, 16, 200, 3)]
-GRAD_CASES = CASES[:7]  # the weight gradient's row-window kernel at 128-, 64- and 32-pixel steps
+# the weight gradient on ragged strips and rows, 1x1 and 3x3, one to thirteen
+# tile splits, and (last) several four-row steps per block
+GRAD_CASES = CASES + [(4, 256, 256, 32, 32, 3)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[str(c) for c in CASES])
@@ -233,3 +235,25 @@ def test_checkpoint_resumes_training_exactly(torch, tmp_path):
     for ca, cb in zip(a.layers(), b.layers()):
         assert torch.equal(ca.w, cb.w) and torch.equal(ca.b, cb.b)
         assert torch.equal(ca.mw, cb.mw) and torch.equal(ca.vw, cb.vw)
+
+
+def test_fused_relu_backward_is_bitwise_the_unfused_path(torch):
+    """dect_nn_conv_fwd_masked and dect_nn_add_relu_bwd equal the ReLU
+    backward applied after the plain calls, bit for bit (bf16 and FP32
+    outputs, a ragged width, and the element-wise fallback)."""
+    nn = _nn()
+    rng = np.random.default_rng(11)
+    for (N, H, W, Ci, Co, k) in [(2, 8, 72, 32, 48, 3), (1, 5, 40, 16, 24, 1), (1, 4, 33, 8, 12, 3)]:
+        dz = _bf(torch, rng.standard_normal((N, H, W, Ci)))
+        w = _bf(torch, rng.standard_normal((k * k, (Co + 15) // 16 * 16, Ci)) * 0.1)
+        mask = _bf(torch, rng.standard_normal((N, H, W, Co)))
+        for f32 in (False, True):
+            plain = nn.conv_fwd(dz, w, None, Co, k, False, out_f32=f32)
+            fused = nn.conv_fwd(dz, w, None, Co, k, False, out_f32=f32, mask=mask)
+            ref = torch.where(mask.float() > 0, plain, torch.zeros_like(plain))
+            assert torch.equal(fused, ref)
+    a, b, y = (_bf(torch, rng.standard_normal((3, 7, 9, 16))) for _ in range(3))
+    assert torch.equal(nn.add_relu_bwd(a, b, y), nn.relu_bwd(nn.add(a, b), y))
+    n = 1001  # not a multiple of 8: the element-wise kernel
+    a, b, y = (_bf(torch, rng.standard_normal(n)) for _ in range(3))
+    assert torch.equal(nn.add_relu_bwd(a, b, y), nn.relu_bwd(nn.add(a, b), y))
