@@ -76,6 +76,62 @@ static_assert((2 * conv_mt(16) + 2) * 34 * (kConvChunk + 8) * 2 <= kConvLds &&
                   (2 * conv_mt(6) + 2) * 34 * (kConvChunk + 8) * 2 <= kConvLds,
               "the staged input window must fit the LDS");
 
+// The output tile [TR * 32 pixels][CoutP] staged in LDS (bf16, or FP32 with
+// out_f32) to Y [.][H][W][Cout] as 16-byte stores where the channel count
+// allows, zero where mask (when given) is not positive.
+template <int CoutP>
+__device__ __forceinline__ void conv_store_tile(const unsigned char *lds_raw, void *__restrict__ Y,
+                                                const u16 *__restrict__ mask, size_t img, int r0,
+                                                int c0, int TR, int H, int W, int Cout,
+                                                int out_f32)
+{
+    const int epv = out_f32 ? 4 : 8;  // elements per 16-byte store
+    if (Cout % epv != 0) {            // channel counts off the 16-byte grid: one at a time
+        for (int it = threadIdx.x; it < TR * 32 * Cout; it += 256) {
+            const int p = it / Cout, e = it - p * Cout;
+            const int rr = r0 + (p >> 5), cc = c0 + (p & 31);
+            if (rr < H && cc < W) {
+                const size_t o = (img + (size_t)rr * W + cc) * Cout + e;
+                const bool keep = !mask || bf2f(mask[o]) > 0.f;
+                if (out_f32) ((float *)Y)[o] = keep ? ((const float *)lds_raw)[p * CoutP + e] : 0.f;
+                else ((u16 *)Y)[o] = keep ? ((const u16 *)lds_raw)[p * CoutP + e] : (u16)0;
+            }
+        }
+        return;
+    }
+    const int vpp = Cout / epv;  // stores per pixel
+    for (int it = threadIdx.x; it < TR * 32 * vpp; it += 256) {
+        const int p = it / vpp, e = (it - p * vpp) * epv;
+        const int rr = r0 + (p >> 5), cc = c0 + (p & 31);
+        if (rr < H && cc < W) {
+            const size_t o = (img + (size_t)rr * W + cc) * Cout + e;
+            if (out_f32) {
+                uint4 v = *(const uint4 *)((const float *)lds_raw + p * CoutP + e);
+                if (mask) {
+                    const uint2 mk = *(const uint2 *)(mask + o);
+                    const u16 *em = (const u16 *)&mk;
+                    uint32_t *ev = (uint32_t *)&v;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (!(bf2f(em[q]) > 0.f)) ev[q] = 0u;
+                }
+                *(uint4 *)((float *)Y + o) = v;
+            } else {
+                uint4 v = *(const uint4 *)((const u16 *)lds_raw + p * CoutP + e);
+                if (mask) {
+                    const uint4 mk = *(const uint4 *)(mask + o);
+                    const u16 *em = (const u16 *)&mk;
+                    u16 *ev = (u16 *)&v;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (!(bf2f(em[q]) > 0.f)) ev[q] = 0;
+                }
+                *(uint4 *)((u16 *)Y + o) = v;
+            }
+        }
+    }
+}
+
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
                                                   const u16 *__restrict__ Wk,
@@ -218,51 +274,151 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
         }
     }
     __syncthreads();
-    const int epv = out_f32 ? 4 : 8;  // elements per 16-byte store
-    if (Cout % epv != 0) {            // channel counts off the 16-byte grid: one at a time
-        for (int it = threadIdx.x; it < TR * 32 * Cout; it += 256) {
-            const int p = it / Cout, e = it - p * Cout;
-            const int rr = r0 + (p >> 5), cc = c0 + (p & 31);
-            if (rr < H && cc < W) {
-                const size_t o = (img + (size_t)rr * W + cc) * Cout + e;
-                const bool keep = !mask || bf2f(mask[o]) > 0.f;
-                if (out_f32) ((float *)Y)[o] = keep ? ((const float *)lds_raw)[p * CoutP + e] : 0.f;
-                else ((u16 *)Y)[o] = keep ? ((const u16 *)lds_raw)[p * CoutP + e] : (u16)0;
+    conv_store_tile<CoutP>(lds_raw, Y, mask, img, r0, c0, TR, H, W, Cout, out_f32);
+}
+
+// ------------------------------------------------------ conv fwd, 3x3 ---
+// The 3x3 forward / input-gradient convolution for Cout <= 64 and Cin >= 16.  Block: 4
+// waves on TR x 32 output pixels of one image (TR = 2 MT); wave w takes the
+// column half w & 1 and the MT rows (w >> 1) MT .. of the tile.  Input
+// channels go in chunks of 32 (zero beyond Cin): per chunk the block stages
+// the input window (TR + 2 rows x 34 columns) and the chunk's weights of all
+// nine taps in LDS, each with 16-byte loads issued in groups of eight before
+// their LDS writes.  Then for each column shift dc a wave reads the MT + 2
+// window-row fragments it needs once and uses each for the three kernel rows
+// dr (output row i takes window row i + dr), so a window fragment feeds up
+// to 3 NT matrix-core steps and a weight fragment MT.  Pixel and weight rows
+// are 80 bytes apart in LDS: a 16-lane fragment read touches every bank once.
+constexpr int kC3Chunk = 32;
+constexpr int kC3PS = kC3Chunk + 8;  // bf16 stride of a staged pixel or weight row
+constexpr int conv3_mt(int nt) { return nt <= 3 ? 4 : 2; }
+
+__host__ __device__ constexpr size_t conv3_lds(int nt, int out_f32)
+{
+    const size_t tr = 2 * conv3_mt(nt);
+    const size_t stage = ((tr + 2) * 34 + 9 * 16 * (size_t)nt) * kC3PS * 2;
+    const size_t tile = tr * 32 * 16 * (size_t)nt * (out_f32 ? 4 : 2);
+    return stage > tile ? stage : tile;
+}
+static_assert(conv3_lds(1, 1) <= 65536 && conv3_lds(2, 1) <= 65536 && conv3_lds(3, 1) <= 65536 &&
+                  conv3_lds(4, 1) <= 65536,
+              "the 3x3 kernel's LDS must fit 64 KB");
+
+// n items of 16 bytes: item k of this thread is it = threadIdx.x + 256 k;
+// src(it) gives the global address (or null: zero), dst(it) the LDS one.
+// Loads go out in groups of eight before their writes.
+template <int NIT, class Src, class Dst>
+__device__ __forceinline__ void stage16(int n, Src src, Dst dst)
+{
+#pragma unroll
+    for (int g = 0; g < NIT; g += 8) {
+        uint4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = threadIdx.x + 256 * (g + k);
+            v[k] = make_uint4(0, 0, 0, 0);
+            if (g + k < NIT && it < n) {
+                const u16 *p = src(it);
+                if (p) v[k] = *(const uint4 *)p;
             }
         }
-        return;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = threadIdx.x + 256 * (g + k);
+            if (g + k < NIT && it < n) *(uint4 *)dst(it) = v[k];
+        }
     }
-    const int vpp = Cout / epv;  // stores per pixel
-    for (int it = threadIdx.x; it < TR * 32 * vpp; it += 256) {
-        const int p = it / vpp, e = (it - p * vpp) * epv;
-        const int rr = r0 + (p >> 5), cc = c0 + (p & 31);
-        if (rr < H && cc < W) {
-            const size_t o = (img + (size_t)rr * W + cc) * Cout + e;
-            if (out_f32) {
-                uint4 v = *(const uint4 *)((const float *)lds_raw + p * CoutP + e);
-                if (mask) {
-                    const uint2 mk = *(const uint2 *)(mask + o);
-                    const u16 *em = (const u16 *)&mk;
-                    uint32_t *ev = (uint32_t *)&v;
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3(const u16 *__restrict__ X,
+                                               const u16 *__restrict__ Wk,
+                                               const float *__restrict__ bias,
+                                               void *__restrict__ Y, int H, int W, int Cin,
+                                               int Cout, int relu, int out_f32,
+                                               const u16 *__restrict__ mask)
+{
+    constexpr int MT = conv3_mt(NT), TR = 2 * MT, CoutP = 16 * NT;
+    constexpr int HR = TR + 2, HC = 34;
+    constexpr int NWIN = HR * HC * 4, NWTS = 9 * CoutP * 4;  // 16-byte items
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    u16 *win = (u16 *)lds_raw;            // [HR][HC][kC3PS]
+    u16 *wts = win + HR * HC * kC3PS;     // [9][CoutP][kC3PS]
+    const int n = blockIdx.z, r0 = blockIdx.y * TR, c0 = blockIdx.x * 32;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int m = lane & 15, grp = lane >> 4;
+    const int h = wid & 1, rg = wid >> 1;
+    const size_t img = (size_t)n * H * W;
+    f32x4 acc[MT][NT];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (!(bf2f(em[q]) > 0.f)) ev[q] = 0u;
-                }
-                *(uint4 *)((float *)Y + o) = v;
-            } else {
-                uint4 v = *(const uint4 *)((const u16 *)lds_raw + p * CoutP + e);
-                if (mask) {
-                    const uint4 mk = *(const uint4 *)(mask + o);
-                    const u16 *em = (const u16 *)&mk;
-                    u16 *ev = (u16 *)&v;
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (!(bf2f(em[q]) > 0.f)) ev[q] = 0;
-                }
-                *(uint4 *)((u16 *)Y + o) = v;
+        for (int t = 0; t < NT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int cc0 = 0; cc0 < Cin; cc0 += kC3Chunk) {
+        __syncthreads();  // the previous chunk is done with the LDS
+        stage16<(NWIN + 255) / 256>(
+            NWIN,
+            [&](int it) -> const u16 * {
+                const int px = it >> 2, ci = cc0 + (it & 3) * 8;
+                const int hr = px / HC, hc = px - hr * HC;
+                const int rr = r0 - 1 + hr, cc = c0 - 1 + hc;
+                if (rr < 0 || rr >= H || cc < 0 || cc >= W || ci >= Cin) return nullptr;
+                return X + (img + (size_t)rr * W + cc) * Cin + ci;
+            },
+            [&](int it) { return win + (it >> 2) * kC3PS + (it & 3) * 8; });
+        stage16<(NWTS + 255) / 256>(
+            NWTS,
+            [&](int it) -> const u16 * {
+                const int row = it >> 2, ci = cc0 + (it & 3) * 8;  // row = tap CoutP + co
+                return ci < Cin ? Wk + (size_t)row * Cin + ci : nullptr;
+            },
+            [&](int it) { return wts + (it >> 2) * kC3PS + (it & 3) * 8; });
+        __syncthreads();
+#pragma unroll
+        for (int dc = 0; dc < 3; ++dc) {
+            Frag a[MT + 2];
+#pragma unroll
+            for (int q = 0; q < MT + 2; ++q)
+                a[q].u = *(const uint4 *)(win + ((rg * MT + q) * HC + 16 * h + m + dc) * kC3PS +
+                                          8 * grp);
+#pragma unroll
+            for (int dr = 0; dr < 3; ++dr) {
+                Frag b[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    b[t].u = *(const uint4 *)(wts + ((3 * dr + dc) * CoutP + 16 * t + m) * kC3PS +
+                                              8 * grp);
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i + dr].v, b[t].v,
+                                                                            acc[i][t], 0, 0, 0);
             }
         }
     }
+    // epilogue: D[pixel 4 grp + q of the wave's row i][co = 16 t + m], through
+    // LDS [pixel][co] (pixel = row * 32 + column within the tile)
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + m;
+        const float bb = (bias && co < Cout) ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            const int pbase = (rg * MT + i) * 32 + 16 * h + 4 * grp;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float v = acc[i][t][q] + bb;
+                if (relu) v = fmaxf(v, 0.f);
+                const int p = pbase + q;
+                if (out_f32) ((float *)lds_raw)[p * CoutP + co] = v;
+                else ((u16 *)lds_raw)[p * CoutP + co] = f2bf(v);
+            }
+        }
+    }
+    __syncthreads();
+    conv_store_tile<CoutP>(lds_raw, Y, mask, img, r0, c0, TR, H, W, Cout, out_f32);
 }
 
 // ----------------------------------------------------------- conv wgrad ---
@@ -843,6 +999,24 @@ static dect_status conv_fwd_launch(const void *x, const void *w, const float *bi
     const int NT = (Cout + 15) / 16;
     hipStream_t s = (hipStream_t)stream;
     const u16 *X = (const u16 *)x, *Wk = (const u16 *)w, *Mk = (const u16 *)mask;
+    // the 3x3 kernel where it measured faster: up to 48 output channels, or
+    // 64 from at least 64 input channels (its 32-channel chunks waste the
+    // matrix cores on fewer than 16 input channels)
+    if (ksize == 3 && Cin >= 16 && (NT <= 3 || (NT == 4 && Cin >= 64))) {
+        switch (NT) {
+#define CASE3(nt)                                                                           \
+    case nt: {                                                                              \
+        constexpr int tr = 2 * conv3_mt(nt);                                                \
+        hipLaunchKernelGGL(k_conv3<nt>, dim3((W + 31) / 32, (H + tr - 1) / tr, N), dim3(256), \
+                           (unsigned)conv3_lds(nt, out_f32), s, X, Wk, bias, y, H, W, Cin,  \
+                           Cout, relu, out_f32, Mk);                                        \
+    } break;
+            CASE3(1) CASE3(2) CASE3(3) CASE3(4)
+#undef CASE3
+        }
+        NN_HIP(hipGetLastError());
+        return DECT_OK;
+    }
     switch (NT) {
 #define CASE(nt)                                                                         \
     case nt: {                                                                           \

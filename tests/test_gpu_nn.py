@@ -60,8 +60,13 @@ def test_conv_fwd(torch, case):
     assert rel_l2(y32, ref) <= 1e-5
     yr = _np(nn.conv_fwd(xt, wt, bt, Co, k, True))
     rr = R.bf16(np.maximum(ref, 0))
-    ulp = np.abs(rr) * 2.0 ** -7 + 1e-30
-    assert np.all(np.abs(yr - rr) <= ulp)
+    # one bfloat16 ulp, plus the FP32 sum's own error (its order is the
+    # kernel's), which can move a value within it of zero across the ReLU
+    e = 1e-5 * np.sqrt(np.mean(ref ** 2))
+    bound = np.abs(rr) * 2.0 ** -7 + e
+    bad = np.abs(yr - rr) - bound
+    i = np.unravel_index(np.argmax(bad), bad.shape)
+    assert bad[i] <= 0, (i, yr[i], rr[i], ref[i])
 
 
 @pytest.mark.parametrize("case", GRAD_CASES, ids=[str(c) for c in GRAD_CASES])
