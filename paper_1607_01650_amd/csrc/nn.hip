@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
 }
 
 // ------------------------------------------------------ conv fwd, 3x3 ---
-// The 3x3 forward / input-gradient convolution for Cout <= 64 and Cin >= 16.  Block: 4
+// The 3x3 forward / input-gradient convolution for Cout <= 128 and Cin >= 16.  Block: 4
 // waves on TR x 32 output pixels of one image (TR = 2 MT); wave w takes the
 // column half w & 1 and the MT rows (w >> 1) MT .. of the tile.  Input
 // channels go in chunks of 32 (zero beyond Cin): per chunk the block stages
@@ -291,7 +291,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X,
 // are 80 bytes apart in LDS: a 16-lane fragment read touches every bank once.
 constexpr int kC3Chunk = 32;
 constexpr int kC3PS = kC3Chunk + 8;  // bf16 stride of a staged pixel or weight row
-constexpr int conv3_mt(int nt) { return nt <= 3 ? 4 : 2; }
+constexpr int conv3_mt(int) { return 4; }
+// the 3x3 kernel up to 128 output channels from at least 16 input channels
+// (its 32-channel chunks waste the matrix cores on fewer); its LDS (the
+// weights of 128 output channels take 92 KB) fits the 160 KB of a CU
+inline bool conv3_use(int nt, int cin) { return cin >= 16 && nt <= 8; }
+constexpr size_t kC3LdsMax = 163840;
 
 __host__ __device__ constexpr size_t conv3_lds(int nt, int out_f32)
 {
@@ -300,9 +305,7 @@ __host__ __device__ constexpr size_t conv3_lds(int nt, int out_f32)
     const size_t tile = tr * 32 * 16 * (size_t)nt * (out_f32 ? 4 : 2);
     return stage > tile ? stage : tile;
 }
-static_assert(conv3_lds(1, 1) <= 65536 && conv3_lds(2, 1) <= 65536 && conv3_lds(3, 1) <= 65536 &&
-                  conv3_lds(4, 1) <= 65536,
-              "the 3x3 kernel's LDS must fit 64 KB");
+static_assert(conv3_lds(8, 1) <= kC3LdsMax, "the 3x3 kernel's LDS must fit a CU");
 
 // n items of 16 bytes: item k of this thread is it = threadIdx.x + 256 k;
 // src(it) gives the global address (or null: zero), dst(it) the LDS one.
@@ -999,10 +1002,7 @@ static dect_status conv_fwd_launch(const void *x, const void *w, const float *bi
     const int NT = (Cout + 15) / 16;
     hipStream_t s = (hipStream_t)stream;
     const u16 *X = (const u16 *)x, *Wk = (const u16 *)w, *Mk = (const u16 *)mask;
-    // the 3x3 kernel where it measured faster: up to 48 output channels, or
-    // 64 from at least 64 input channels (its 32-channel chunks waste the
-    // matrix cores on fewer than 16 input channels)
-    if (ksize == 3 && Cin >= 16 && (NT <= 3 || (NT == 4 && Cin >= 64))) {
+    if (ksize == 3 && conv3_use(NT, Cin)) {
         switch (NT) {
 #define CASE3(nt)                                                                           \
     case nt: {                                                                              \
@@ -1011,8 +1011,9 @@ static dect_status conv_fwd_launch(const void *x, const void *w, const float *bi
                            (unsigned)conv3_lds(nt, out_f32), s, X, Wk, bias, y, H, W, Cin,  \
                            Cout, relu, out_f32, Mk);                                        \
     } break;
-            CASE3(1) CASE3(2) CASE3(3) CASE3(4)
+            CASE3(1) CASE3(2) CASE3(3) CASE3(4) CASE3(5) CASE3(6) CASE3(7) CASE3(8)
 #undef CASE3
+            default: return nn_fail(DECT_ERR_INVALID_ARG, "conv_fwd: no 3x3 kernel for this width");
         }
         NN_HIP(hipGetLastError());
         return DECT_OK;
