@@ -6,7 +6,9 @@
 // slice); a captured hipGraph replays an even/odd pair of iterations.  Items are
 // sorted by estimated cost (longest first) and handed to the persistent
 // blocks round-robin; the adjoint's view-group depth (how many blocks share
-// one output tile) is chosen per batch by a timing autotuner.
+// one output tile) is chosen per batch by a timing autotuner.  Slices with
+// the coupled TV, and Siddon slices, get lists of their own in the phases
+// that differ (the stencil; the projectors), each one more persistent launch.
 #include <algorithm>
 #include <array>
 #include <cstring>
@@ -25,6 +27,8 @@ struct SliceDev {
     const Bundle *bundles;
     const BinRange *bins;
     const LaneRange *lanes;
+    const SidW *sid;  // Siddon weight terms (null: Joseph)
+    int coupled;      // the TV couples the two energies
     float rho, xi, muf;
     double mu, rhod, tol;
     AdmPtrs P;
@@ -54,7 +58,9 @@ __device__ __forceinline__ AdmImg img_of(const SliceDev &d, int e, int par)
                   d.muf};
 }
 
-// item = (slice, energy, tile row, tile column)
+// item = (slice, energy, tile row, tile column); COUPLED: slices whose TV
+// couples the energies (the tile also reads the other energy's state)
+template <bool COUPLED>
 __global__ __launch_bounds__(256) void kb_tv(const SliceDev *__restrict__ S,
                                              const int4 *__restrict__ items, int n, int par)
 {
@@ -65,14 +71,29 @@ __global__ __launch_bounds__(256) void kb_tv(const SliceDev *__restrict__ S,
         if (!d.P.sc[e].stopped && !d.P.sc[e].stop_next) {
             const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
             const size_t blk = (size_t)e * gx * gy + (size_t)w.z * gx + w.w;
-            tv_tile(w.z * kTY, w.w * kTX, img_of(d, e, par), d.P.p_tv + blk * kTvParts,
-                    d.P.sc[e].pending != 0, d.nx, d.ny, d.rho, d.xi);
+            AdmImg m = img_of(d, e, par);
+            if constexpr (COUPLED) {
+                const size_t N = (size_t)d.nx * d.ny;
+                const int o = 1 - e;
+                const float *lin = d.P.lam + (size_t)par * 4 * N, *zin = d.P.z + (size_t)par * 4 * N;
+                m.f2 = d.P.f + o * N;
+                m.flo2 = d.P.flo + o * N;
+                m.lxi2 = lin + (2 * o) * N;
+                m.lyi2 = lin + (2 * o + 1) * N;
+                m.zxi2 = zin + (2 * o) * N;
+                m.zyi2 = zin + (2 * o + 1) * N;
+                m.pending2 = d.P.sc[o].pending != 0;
+                m.record_tv = e == 0;
+            }
+            tv_tile<COUPLED>(w.z * kTY, w.w * kTX, m, d.P.p_tv + blk * kTvParts,
+                             d.P.sc[e].pending != 0, d.nx, d.ny, d.rho, d.xi);
         }
         __syncthreads();
     }
 }
 
-// item = (slice, (view, bundle) block): both energies
+// item = (slice, (view, bundle) block): both energies; SID: Siddon slices
+template <bool SID>
 __global__ __launch_bounds__(kFwdThreads) void kb_fwd(const SliceDev *__restrict__ S,
                                                       const int4 *__restrict__ items, int n)
 {
@@ -90,7 +111,7 @@ __global__ __launch_bounds__(kFwdThreads) void kb_fwd(const SliceDev *__restrict
                 o.sub_scale[e] = 0.0;
             }
             double res[2];
-            fwd_block<false>(sh, d.P.gpad, d.P.gpadT, d.fwd, d.len, nullptr, d.bundles, o, d.nx,
+            fwd_block<SID>(sh, d.P.gpad, d.P.gpadT, d.fwd, d.len, d.sid, d.bundles, o, d.nx,
                              d.ny, d.V, d.B, d.nbundle, blk, 1.0f, res);
             if (threadIdx.x < 64) {  // the values live in wavefront 0
                 const double t0 = lane_sum(res[0] * res[0]);
@@ -139,12 +160,15 @@ __global__ __launch_bounds__(256) void kb_update(const SliceDev *__restrict__ S,
     }
 }
 
-// item = (slice, strip of either ray class, view group): both energies
+// item = (slice, strip of either ray class, view group): both energies;
+// SID: Siddon slices
+template <bool SID>
 __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict__ S,
                                               const int4 *__restrict__ items, int n)
 {
     __shared__ AdjShared<2> sh;
     __shared__ AdjStage stage;
+    __shared__ SidW sid_stage[SID ? kStageSlots : 1];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
         const SliceDev &d = S[w.x];
@@ -156,8 +180,8 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
             float *p[2];
             for (int e = 0; e < 2; ++e)
                 p[e] = d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
-            adj_block<2, false>(sh, s, d.fwd, d.len, nullptr, d.bins, d.lanes, d.nx, d.ny,
-                                d.V, d.B, strip, g, d.nvg, p, stage, nullptr);
+            adj_block<2, SID>(sh, s, d.fwd, d.len, d.sid, d.bins, d.lanes, d.nx, d.ny, d.V,
+                              d.B, strip, g, d.nvg, p, stage, SID ? sid_stage : nullptr);
         }
         __syncthreads();
     }
@@ -172,9 +196,10 @@ struct dect_batch {
     std::vector<dect_adm_params> prm;
     std::vector<dect::SliceDev> host;
     std::vector<size_t> off;  // arena offsets per slice
-    dect::DevBuf arena, slices, w_tv, w_fwd, w_se, w_upd, w_adj;
-    int n_tv = 0, n_fwd = 0, n_se = 0, n_upd = 0, n_adj = 0;
-    int g_tv = 0, g_fwd = 0, g_se = 0, g_upd = 0, g_adj = 0;
+    // work lists; the stencil's split by coupled TV, the projectors' by model
+    dect::DevBuf arena, slices, w_tv[2], w_fwd[2], w_se, w_upd, w_adj[2];
+    int n_tv[2] = {0, 0}, n_fwd[2] = {0, 0}, n_se = 0, n_upd = 0, n_adj[2] = {0, 0};
+    int g_tv[2] = {0, 0}, g_fwd[2] = {0, 0}, g_se = 0, g_upd = 0, g_adj[2] = {0, 0};
     int nvg_max = 16, group_choice = 0;  // 0: per-slice heuristic, else fixed
     // autotuned shape: the adjoint view-group depth per slice (0: as
     // group_choice) and the persistent grids' blocks per CU for the adjoint
@@ -201,7 +226,7 @@ int heuristic_groups(const GeomTables &t) { return adj_groups(t, 2); }
 // Work lists and persistent grid sizes for the current view-group choice.
 dect_status build_work(dect_batch *b)
 {
-    std::vector<std::pair<double, int4>> tv, fwd, se, upd, adj;
+    std::vector<std::pair<double, int4>> tv[2], fwd[2], se, upd, adj[2];
     for (int s = 0; s < b->n; ++s) {
         SliceDev &d = b->host[s];
         const GeomTables &t = *b->t[s];
@@ -213,18 +238,19 @@ dect_status build_work(dect_batch *b)
         d.nvg = nvg;
         const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
         const int nstrips = adj_strips(d.nx, d.ny);
+        const int c = d.coupled ? 1 : 0, m = d.sid ? 1 : 0;
         for (int e = 0; e < 2; ++e) {
             for (int ty = 0; ty < gy; ++ty)
-                for (int tx = 0; tx < gx; ++tx) tv.push_back({1.0, make_int4(s, e, ty, tx)});
+                for (int tx = 0; tx < gx; ++tx) tv[c].push_back({1.0, make_int4(s, e, ty, tx)});
             se.push_back({1.0, make_int4(s, e, 0, 0)});
             for (int k = 0; k < d.P.nbi + d.P.nbs; ++k) upd.push_back({1.0, make_int4(s, e, k, 0)});
         }
         // the projectors carry both energies per item
         for (int k = 0; k < d.P.nb_fwd; ++k)
-            fwd.push_back({(double)std::max(d.nx, d.ny), make_int4(s, k, 0, 0)});
+            fwd[m].push_back({(double)std::max(d.nx, d.ny), make_int4(s, k, 0, 0)});
         for (int strip = 0; strip < nstrips; ++strip)
             for (int g = 0; g < nvg; ++g)
-                adj.push_back({(double)d.V / nvg, make_int4(s, strip, g, 0)});
+                adj[m].push_back({(double)d.V / nvg, make_int4(s, strip, g, 0)});
     }
     auto upload = [&](std::vector<std::pair<double, int4>> &v, DevBuf &buf, int &count) {
         std::stable_sort(v.begin(), v.end(),
@@ -238,10 +264,12 @@ dect_status build_work(dect_batch *b)
         return DECT_OK;
     };
     dect_status st;
-    if ((st = upload(tv, b->w_tv, b->n_tv)) || (st = upload(fwd, b->w_fwd, b->n_fwd)) ||
-        (st = upload(se, b->w_se, b->n_se)) || (st = upload(upd, b->w_upd, b->n_upd)) ||
-        (st = upload(adj, b->w_adj, b->n_adj)))
-        return st;
+    for (int k = 0; k < 2; ++k)
+        if ((st = upload(tv[k], b->w_tv[k], b->n_tv[k])) ||
+            (st = upload(fwd[k], b->w_fwd[k], b->n_fwd[k])) ||
+            (st = upload(adj[k], b->w_adj[k], b->n_adj[k])))
+            return st;
+    if ((st = upload(se, b->w_se, b->n_se)) || (st = upload(upd, b->w_upd, b->n_upd))) return st;
     DECT_HIP(hipMemcpy(b->slices.ptr, b->host.data(), b->host.size() * sizeof(SliceDev),
                        hipMemcpyHostToDevice));
     int dev = 0, cus = 0;
@@ -255,11 +283,14 @@ dect_status build_work(dect_batch *b)
         if (cap > 0) per = std::min(per, cap);
         return std::max(1, std::min(items, per * cus));
     };
-    b->g_tv = grid((const void *)kb_tv, b->n_tv);
-    b->g_fwd = grid((const void *)kb_fwd, b->n_fwd, kFwdThreads, b->fwd_per_cu);
+    b->g_tv[0] = grid((const void *)kb_tv<false>, b->n_tv[0]);
+    b->g_tv[1] = grid((const void *)kb_tv<true>, b->n_tv[1]);
+    b->g_fwd[0] = grid((const void *)kb_fwd<false>, b->n_fwd[0], kFwdThreads, b->fwd_per_cu);
+    b->g_fwd[1] = grid((const void *)kb_fwd<true>, b->n_fwd[1], kFwdThreads, b->fwd_per_cu);
     b->g_se = std::max(1, b->n_se);
     b->g_upd = grid((const void *)kb_update, b->n_upd);
-    b->g_adj = grid((const void *)kb_adj, b->n_adj, kAdjThreads, b->adj_per_cu);
+    b->g_adj[0] = grid((const void *)kb_adj<false>, b->n_adj[0], kAdjThreads, b->adj_per_cu);
+    b->g_adj[1] = grid((const void *)kb_adj<true>, b->n_adj[1], kAdjThreads, b->adj_per_cu);
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
@@ -270,11 +301,20 @@ dect_status build_work(dect_batch *b)
 dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
 {
     const SliceDev *S = (const SliceDev *)b->slices.ptr;
-    hipLaunchKernelGGL(kb_tv, dim3(b->g_tv), dim3(256), 0, s, S, (const int4 *)b->w_tv.ptr, b->n_tv,
-                       par);
+    // each phase: one persistent launch per non-empty list
+    if (b->n_tv[0])
+        hipLaunchKernelGGL(kb_tv<false>, dim3(b->g_tv[0]), dim3(256), 0, s, S,
+                           (const int4 *)b->w_tv[0].ptr, b->n_tv[0], par);
+    if (b->n_tv[1])
+        hipLaunchKernelGGL(kb_tv<true>, dim3(b->g_tv[1]), dim3(256), 0, s, S,
+                           (const int4 *)b->w_tv[1].ptr, b->n_tv[1], par);
     DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_fwd, dim3(b->g_fwd), dim3(kFwdThreads), 0, s, S, (const int4 *)b->w_fwd.ptr,
-                       b->n_fwd);
+    if (b->n_fwd[0])
+        hipLaunchKernelGGL(kb_fwd<false>, dim3(b->g_fwd[0]), dim3(kFwdThreads), 0, s, S,
+                           (const int4 *)b->w_fwd[0].ptr, b->n_fwd[0]);
+    if (b->n_fwd[1])
+        hipLaunchKernelGGL(kb_fwd<true>, dim3(b->g_fwd[1]), dim3(kFwdThreads), 0, s, S,
+                           (const int4 *)b->w_fwd[1].ptr, b->n_fwd[1]);
     DECT_HIP(hipGetLastError());
     hipLaunchKernelGGL(kb_scalar, dim3(b->g_se), dim3(256), 0, s, S, (const int4 *)b->w_se.ptr,
                        b->n_se);
@@ -282,9 +322,12 @@ dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
     hipLaunchKernelGGL(kb_update, dim3(b->g_upd), dim3(256), 0, s, S, (const int4 *)b->w_upd.ptr,
                        b->n_upd);
     DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_adj, dim3(b->g_adj), dim3(kAdjThreads), 0, s, S,
-                       (const int4 *)b->w_adj.ptr,
-                       b->n_adj);
+    if (b->n_adj[0])
+        hipLaunchKernelGGL(kb_adj<false>, dim3(b->g_adj[0]), dim3(kAdjThreads), 0, s, S,
+                           (const int4 *)b->w_adj[0].ptr, b->n_adj[0]);
+    if (b->n_adj[1])
+        hipLaunchKernelGGL(kb_adj<true>, dim3(b->g_adj[1]), dim3(kAdjThreads), 0, s, S,
+                           (const int4 *)b->w_adj[1].ptr, b->n_adj[1]);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -351,11 +394,12 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         const dect_adm_params &p = prm[i];
         if (!(p.mu > 0) || !(p.rho > 0) || !(p.xi >= 0) || !(p.beta_high > 0) || !(p.beta_low > 0))
             return fail(DECT_ERR_INVALID_ARG, "dect_batch_create: invalid ADM parameters");
-        if (geoms[i].model != DECT_JOSEPH)
-            return fail(DECT_ERR_INVALID_ARG, "batched ADM runs the Joseph model only");
-        if (p.flags & (DECT_NONNEG | DECT_COUPLED_TV | DECT_STEP_BB2 | DECT_STEP_ABB))
+        if (p.flags & (DECT_NONNEG | DECT_STEP_BB2 | DECT_STEP_ABB))
             return fail(DECT_ERR_INVALID_ARG,
-                        "batched ADM has no non-negative, coupled-TV or BB2 variant");
+                        "batched ADM has no non-negative or BB2 / adaptive variant");
+        if ((p.flags & DECT_COUPLED_TV) && p.tol != 0.0)
+            return fail(DECT_ERR_INVALID_ARG,
+                        "batched ADM: coupled TV runs a fixed iteration count (tol 0)");
         if ((st = get_tables(&geoms[i], &b->t[i]))) return st;
         const GeomTables &t = *b->t[i];
         Sizes &z = sz[i];
@@ -426,6 +470,8 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         d.bundles = t.bundles;
         d.bins = t.adj_bins;
         d.lanes = t.adj_lanes;
+        d.sid = t.sid;
+        d.coupled = (prm[i].flags & DECT_COUPLED_TV) ? 1 : 0;
         d.rho = (float)prm[i].rho;
         d.xi = (float)prm[i].xi;
         d.muf = (float)prm[i].mu;
@@ -457,7 +503,8 @@ dect_status adm_tv_batched(dect_batch *b, const float *const *mh, const float *c
     if (st) return st;
     for (int i = 0; i < b->n; ++i) {
         const dect_adm_params &p = b->prm[i];
-        if ((st = adm_finish(*b->t[i], b->host[i].P, xh[i], xl[i], p.mu, p.beta_high, p.beta_low, s)))
+        if ((st = adm_finish(*b->t[i], b->host[i].P, xh[i], xl[i], p.mu, p.beta_high, p.beta_low, s,
+                             b->host[i].coupled != 0)))
             return st;
     }
     if (objective) {
@@ -478,7 +525,7 @@ dect_status adm_tv_batched(dect_batch *b, const float *const *mh, const float *c
 // Tuned shapes, kept for the process: a batch of the same slice shapes (the
 // multiset of image size, views and bins) reuses them without timing.
 struct TunedShape {
-    std::vector<std::array<int, 4>> shapes;  // sorted (nx, ny, V, B) per slice
+    std::vector<std::array<int, 6>> shapes;  // sorted (nx, ny, V, B, model, coupled) per slice
     std::vector<int> groups;                 // per sorted slice
     int adj_per_cu = 0, fwd_per_cu = 0;
     double ms = 0.0;
@@ -486,13 +533,13 @@ struct TunedShape {
 static std::mutex g_tune_mu;
 static std::vector<TunedShape> g_tuned;
 
-static std::vector<int> shape_order(const dect_batch *b, std::vector<std::array<int, 4>> &shapes)
+static std::vector<int> shape_order(const dect_batch *b, std::vector<std::array<int, 6>> &shapes)
 {
     std::vector<int> order(b->n);
     std::iota(order.begin(), order.end(), 0);
     auto key = [&](int i) {
         const SliceDev &d = b->host[i];
-        return std::array<int, 4>{d.nx, d.ny, d.V, d.B};
+        return std::array<int, 6>{d.nx, d.ny, d.V, d.B, d.sid ? 1 : 0, d.coupled};
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key(a) < key(c); });
     shapes.resize(b->n);
@@ -530,7 +577,7 @@ dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const
 {
     if (!b || !mh || !ml || iters < 2)
         return fail(DECT_ERR_INVALID_ARG, "dect_batch_tune: bad arguments");
-    std::vector<std::array<int, 4>> shapes;
+    std::vector<std::array<int, 6>> shapes;
     const std::vector<int> order = shape_order(b, shapes);
     // the slice of the costliest class reports its depth in *chosen
     int big = 0;

@@ -7,7 +7,10 @@
 * the autotuner returns one of the offered shapes, and a batch of the same
   slice shapes takes the remembered choice without timing;
 * at the configuration's sizes (512 x 512 at 360 views, 384 x 384 at 90,
-  256 x 256 at 60) every slice matches the oracle after 200 iterations.
+  256 x 256 at 60) every slice matches the oracle after 200 iterations;
+* Siddon slices and slices with the coupled TV, mixed with plain Joseph
+  ones, reproduce their single-slice runs bit for bit; the projected and
+  BB2 / adaptive variants are refused.
 """
 import numpy as np
 import pytest
@@ -130,3 +133,37 @@ def test_batch_paper_scale_parity(torch):
                       flush=True)
                 assert err <= 1e-4
     b.close()
+
+
+def test_batch_siddon_and_coupled_bitwise(torch):
+    """A batch that mixes both projector models and coupled / per-energy TV
+    (their own persistent launches per phase) equals each slice's
+    single-slice run bit for bit, objective included."""
+    import dataclasses
+    from paper_1607_01650_amd import dect
+    specs = [(64, 30, 0, False), (96, 45, 1, False), (80, 36, 0, True), (64, 40, 1, True),
+             (72, 24, 1, False)]
+    sl = []
+    for i, (n, V, model, coupled) in enumerate(specs):
+        g = C.Geometry(nx=n, ny=n, pixel_mm=1.0, n_views=V, n_bins=int(round(1.4375 * n)),
+                       bin_mm=2.4, sod_mm=500.0, sdd_mm=1000.0, model=model)
+        s = P.make_slice(g, 60 + i, n_inserts=4, r_obj=0.4 * n)
+        p = C.AdmParams(mu=45.0 / V, rho=1024.0, xi=256.0, beta_high=1.0, beta_low=0.79,
+                        coupled_tv=coupled)
+        sl.append((g, s, p))
+    iters = 21  # odd: the last iteration runs outside the graph
+    mh = [to_dev(torch, s.sino[0]) for _, s, _ in sl]
+    ml = [to_dev(torch, s.sino[1]) for _, s, _ in sl]
+    b = dect.AdmBatch([g for g, _, _ in sl], [p for _, _, p in sl])
+    xh, xl, obj = b.run(mh, ml, iters, want_objective=True)
+    for i, (g, s, p) in enumerate(sl):
+        r = dect.adm_tv(mh[i], ml[i], g, dataclasses.replace(p, max_iter=iters), want_log=True)
+        assert np.array_equal(to_np(xh[i]), to_np(r.x_high)), i
+        assert np.array_equal(to_np(xl[i]), to_np(r.x_low)), i
+        assert obj[i] == pytest.approx(r.report.objective, rel=1e-12), i
+    b.close()
+    g, s, p = sl[0]
+    for change in ({"nonneg": True}, {"step": "bb2"}, {"step": "abb"},
+                   {"coupled_tv": True, "tol": 1e-4}):
+        with pytest.raises(dect.DectError):
+            dect.AdmBatch([g], [dataclasses.replace(p, **change)])

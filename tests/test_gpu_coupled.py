@@ -9,7 +9,8 @@ its minimum within ~25 iterations; from there the BB step is formed from
 differences of nearly equal iterates and amplifies rounding (measured: J
 within 1.4e-5 and alpha within 2e-4 late in the run, while the final images
 agree to 8e-8).  Resuming through a state is bitwise equal to one call; a
-tolerance stop and the batched ADM are refused.
+tolerance stop is refused, in the batched ADM too (which otherwise takes the
+coupled TV).
 """
 import dataclasses
 
@@ -92,5 +93,5 @@ def test_resume_and_refusals(torch):
     st.close()
     with pytest.raises(dect.DectError):
         dect.adm_tv(mh, ml, g, dataclasses.replace(p, tol=1e-3))
-    with pytest.raises(dect.DectError):
-        dect.AdmBatch([g], [p])
+    with pytest.raises(dect.DectError):  # the batch takes the coupled TV at tol 0 only
+        dect.AdmBatch([g], [dataclasses.replace(p, tol=1e-3)])

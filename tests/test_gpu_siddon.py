@@ -13,7 +13,8 @@ Sec. 2.1) against the FP64 oracle's Siddon walk.
 * ADM-TV of both energies on the Siddon model, 50 iterations on the tiny
   workload: image rel-L2 <= 1e-4, objective within 1e-5; 200 iterations at
   512 x 512 x 360 views against the stored oracle run;
-* the batched ADM and an unknown model value are refused.
+* an unknown model value is refused (the batched ADM takes Siddon slices:
+  test_gpu_batch.py).
 """
 import math
 
@@ -137,8 +138,6 @@ def test_adm_tiny_parity(torch):
 
 def test_refusals(torch):
     dect = _dect()
-    with pytest.raises(dect.DectError):
-        dect.AdmBatch([TINY_S], [C.default_adm_params(C.TINY, 5)])
     bad = C.Geometry(**{**C.TINY.__dict__, "model": 2})
     with pytest.raises(dect.DectError):
         dect.project(torch.zeros((C.TINY.ny, C.TINY.nx), device="cuda"), bad)
