@@ -272,9 +272,11 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  * every phase of an iteration is one persistent launch over a work list that
  * spans all slices, replayed from a hipGraph.  Starts from zero images.
  * geoms/params: host arrays [n] (params[i].max_iter and DECT_WARM_START are ignored);
- *   each slice takes either projector model and DECT_COUPLED_TV (with tol
- *   0); DECT_NONNEG, DECT_STEP_BB2 and DECT_STEP_ABB are refused
- *   (DECT_ERR_INVALID_ARG).
+ *   each slice takes either projector model and the flags of dect_adm_tv
+ *   with the same restrictions (DECT_COUPLED_TV with tol 0; DECT_STEP_BB2 /
+ *   DECT_STEP_ABB neither together nor with DECT_NONNEG; else
+ *   DECT_ERR_INVALID_ARG); every slice's result is bit for bit its
+ *   dect_adm_tv run with the same view grouping.
  * d_m_high, d_m_low, d_x_high, d_x_low: host arrays [n] of device pointers
  *   to slice i's sinograms [V_i][B_i] and output images [ny_i][nx_i].
  * objective: NULL or host [n], filled after synchronising the stream with
@@ -286,7 +288,7 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  * strip, i.e. views per adjoint tile), then the blocks per CU of the
  * persistent adjoint and forward grids (1, 2 or all that fit).  The choice is
  * remembered for the process: a batch with the same multiset of slice shapes
- * (nx, ny, n_views, n_bins, model, coupled TV) takes it without timing.  *chosen_groups receives
+ * (nx, ny, n_views, n_bins, model, variant flags) takes it without timing.  *chosen_groups receives
  * the depth of the costliest slice, *ms_per_iter the tuned time per
  * iteration.  dect_batch_set_groups fixes one depth for every slice
  * (0 = built-in heuristic) and drops the tuned shape; dect_batch_shape

@@ -97,11 +97,9 @@ __global__ __launch_bounds__(256) void k_scalar(AdmScalars *__restrict__ sc,
 }
 
 // ------------------------------------------------ non-negative variant ---
-// Projected f-step: t = (f + flo) - alpha G, f' = max(t, 0).  The step s =
-// f' - f is kept in FP32 (rounded toward zero where the projection clips, so
-// f + s >= 0) and f advances by exactly that s, so that r + A s stays the
-// residual of f.  s goes to the transposed padded layout (G, in the other
-// layout, is still read by neighbouring threads); partials <s,s>, |f|^2.
+// The projected step (nn_step_chunk), |grad s|^2 and s in both layouts
+// (nn_grad_chunk), r += A s (nn_resid_chunk) and the step's scalars
+// (nn_rr_energy), one block per chunk and energy.
 __global__ __launch_bounds__(256) void k_nn_step(float *__restrict__ f,
                                                  const float *__restrict__ gpad,
                                                  float *__restrict__ gpadT,
@@ -112,35 +110,9 @@ __global__ __launch_bounds__(256) void k_nn_step(float *__restrict__ f,
 {
     const int e = blockIdx.y;
     if (sc[e].stopped) return;
-    const double alpha = sc[e].alpha;
     const size_t N = (size_t)nx * ny;
-    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
-    float *fe = f + e * N, *fle = f + 2 * N + e * N;
-    double v[2] = {0.0, 0.0};
-    for (int j = 0; j < 4; ++j) {
-        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
-        if (i < N) {
-            const int r = (int)(i / nx), c = (int)(i % nx);
-            const double g = gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e];
-            const double fo = (double)fe[i] + (double)fle[i];
-            const double t = fo - alpha * g;
-            float s32 = t > 0.0 ? (float)(t - fo) : __double2float_rz(-fo);
-            if (fo + (double)s32 < 0.0) s32 = __double2float_rz(-fo);
-            const double fn = fo + (double)s32;
-            const float hi = (float)fn;
-            fe[i] = hi;
-            fle[i] = (float)(fn - (double)hi);
-            gpadT[2 * ((size_t)(c + kPad) * pny + r + kPad) + e] = s32;
-            v[0] += (double)s32 * (double)s32;
-            v[1] += fo * fo;
-        }
-    }
-    __shared__ double tot[2];
-    block_sum<2>(v, tot);
-    if (threadIdx.x == 0) {
-        p_ss[(size_t)e * nbi + blockIdx.x] = tot[0];
-        p_ff[(size_t)e * nbi + blockIdx.x] = tot[1];
-    }
+    nn_step_chunk(blockIdx.x, e, f + e * N, f + 2 * N + e * N, gpad, gpadT, sc[e].alpha,
+                  p_ss + (size_t)e * nbi, p_ff + (size_t)e * nbi, nx, ny);
 }
 
 // |grad s|^2 partials (backward differences of Eq. 2) and s copied into the
@@ -153,26 +125,7 @@ __global__ __launch_bounds__(256) void k_nn_grad(float *__restrict__ gpad,
 {
     const int e = blockIdx.y;
     if (sc[e].stopped) return;
-    const size_t N = (size_t)nx * ny;
-    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
-    auto sT = [&](int r, int c) {
-        return gpadT[2 * ((size_t)(c + kPad) * pny + r + kPad) + e];
-    };
-    double v[1] = {0.0};
-    for (int j = 0; j < 4; ++j) {
-        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
-        if (i < N) {
-            const int r = (int)(i / nx), c = (int)(i % nx);
-            const float si = sT(r, c);
-            const double gx = c >= 1 ? (double)si - (double)sT(r, c - 1) : 0.0;
-            const double gy = r >= 1 ? (double)si - (double)sT(r - 1, c) : 0.0;
-            gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e] = si;
-            v[0] += gx * gx + gy * gy;
-        }
-    }
-    __shared__ double tot[1];
-    block_sum<1>(v, tot);
-    if (threadIdx.x == 0) p_gs[(size_t)e * nbi + blockIdx.x] = tot[0];
+    nn_grad_chunk(blockIdx.x, e, gpad, gpadT, p_gs + (size_t)e * nbi, nx, ny);
 }
 
 // (r + rlo) += (p + plo) = A s in FP64; partial |r|^2.
@@ -184,22 +137,8 @@ __global__ __launch_bounds__(256) void k_nn_resid(float *__restrict__ r,
     const int e = blockIdx.y;
     if (sc[e].stopped) return;
     const size_t Ms = (size_t)M;
-    float *re = r + e * Ms, *rle = r + 2 * Ms + e * Ms;
-    const float *pe = p + e * Ms, *ple = p + 2 * Ms + e * Ms;
-    double v[1] = {0.0};
-    for (int j = 0; j < 4; ++j) {
-        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
-        if (i < Ms) {
-            const double d = ((double)re[i] + (double)rle[i]) + ((double)pe[i] + (double)ple[i]);
-            const float hi = (float)d;
-            re[i] = hi;
-            rle[i] = (float)(d - (double)hi);
-            v[0] += d * d;
-        }
-    }
-    __shared__ double tot[1];
-    block_sum<1>(v, tot);
-    if (threadIdx.x == 0) p_rr[(size_t)e * nbs + blockIdx.x] = tot[0];
+    nn_resid_chunk(blockIdx.x, r + e * Ms, r + 2 * Ms + e * Ms, p + e * Ms, p + 2 * Ms + e * Ms,
+                   p_rr + (size_t)e * nbs, M);
 }
 
 // |r|^2, <s,s>, <s,y> = mu |A s|^2 + rho |grad s|^2 and |s| / |f| from the
@@ -214,31 +153,9 @@ __global__ __launch_bounds__(256) void k_nn_rr(AdmScalars *__restrict__ sc,
                                                double mu, double rho, double tol)
 {
     const int e = blockIdx.x;
-    AdmScalars &s = sc[e];
-    const bool run = !s.stopped;
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (run) {
-        for (int i = threadIdx.x; i < nbs; i += 256) v[0] += p_rr[(size_t)e * nbs + i];
-        for (int i = threadIdx.x; i < nbi; i += 256) {
-            v[1] += p_ss[(size_t)e * nbi + i];
-            v[2] += p_ff[(size_t)e * nbi + i];
-            v[3] += p_gs[(size_t)e * nbi + i];
-        }
-        for (int i = threadIdx.x; i < nb_fwd; i += 256) v[4] += p_as[(size_t)e * nb_fwd + i];
-    }
-    __shared__ double tot[5];
-    block_sum<5>(v, tot);
-    if (run && threadIdx.x == 0) {
-        const double ss = tot[1], ff = tot[2];
-        s.rr = tot[0];
-        s.ss = ss;
-        s.sy = mu * tot[4] + rho * tot[3];
-        s.relchg = ff > 0.0 ? sqrt(ss) / sqrt(ff) : (ss > 0.0 ? INFINITY : 0.0);
-        s.pending = 1;
-        s.iter += 1;
-        if (tol > 0.0 && s.relchg < tol) s.stopped = 1;
-    }
-    __syncthreads();
+    nn_rr_energy(sc[e], p_rr + (size_t)e * nbs, nbs, p_ss + (size_t)e * nbi,
+                 p_ff + (size_t)e * nbi, p_gs + (size_t)e * nbi, nbi, p_as + (size_t)e * nb_fwd,
+                 nb_fwd, mu, rho, tol);
 }
 
 // blocks [0, nbi): f -= alpha G (image); blocks [nbi, nbi+nbs): r -= alpha p
@@ -268,8 +185,7 @@ __global__ __launch_bounds__(256) void k_rr(AdmScalars *__restrict__ sc,
 }
 
 // BB2 / adaptive steps: partials of |mu A^T A G + rho grad^T grad G|^2 per
-// block of 1024 pixels, from the partial planes of A^T (A G) (summed in plane
-// order) and G in the padded layout (still this iteration's G).
+// block of 1024 pixels.
 __global__ __launch_bounds__(256) void k_yy(const float *__restrict__ apart, int nplanes,
                                             float mu, const float *__restrict__ gpad, float rho,
                                             const AdmScalars *__restrict__ sc,
@@ -278,31 +194,8 @@ __global__ __launch_bounds__(256) void k_yy(const float *__restrict__ apart, int
     const int e = blockIdx.y;
     if (sc[e].stopped) return;
     const size_t N = (size_t)nx * ny;
-    const int pnx = nx + 2 * kPad;
-    const float *ap = apart + (size_t)e * nplanes * N;
-    auto G = [&](int r, int c) { return gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e]; };
-    // backward difference along x / y at (r, c) (zero on the first column / row)
-    auto gx = [&](int r, int c) { return c >= 1 ? G(r, c) - G(r, c - 1) : 0.f; };
-    auto gy = [&](int r, int c) { return r >= 1 ? G(r, c) - G(r - 1, c) : 0.f; };
-    double v[1] = {0.0};
-    for (int j = 0; j < 4; ++j) {
-        const size_t i = ((size_t)blockIdx.x * 4 + j) * 256 + threadIdx.x;
-        if (i < N) {
-            const int r = (int)(i / nx), c = (int)(i % nx);
-            float a = 0.f;
-            for (int q = 0; q < nplanes; ++q) a += ap[(size_t)q * N + i];
-            float lt = 0.f;  // (grad^T grad G) at (r, c)
-            if (c >= 1) lt += gx(r, c);
-            if (c + 1 <= nx - 1) lt -= gx(r, c + 1);
-            if (r >= 1) lt += gy(r, c);
-            if (r + 1 <= ny - 1) lt -= gy(r + 1, c);
-            const double y = (double)mu * a + (double)rho * lt;
-            v[0] += y * y;
-        }
-    }
-    __shared__ double tot[1];
-    block_sum<1>(v, tot);
-    if (threadIdx.x == 0) p_yy[(size_t)e * nbi + blockIdx.x] = tot[0];
+    yy_chunk(blockIdx.x, e, apart + (size_t)e * nplanes * N, nplanes, mu, gpad, rho,
+             p_yy + (size_t)e * nbi, nx, ny);
 }
 
 // ------------------------------------------------------------- set-up ---

@@ -447,6 +447,171 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
     __syncthreads();
 }
 
+// ------------------------------------------------ non-negative variant ---
+// Chunk bx of 1024 pixels of energy e (fe, fle its f and f_lo; gpad, gpadT
+// the interleaved padded layouts).  Projected f-step: t = (f + flo) - alpha
+// G, f' = max(t, 0).  The step s = f' - f is kept in FP32 (rounded toward
+// zero where the projection clips, so f + s >= 0) and f advances by exactly
+// that s, so that r + A s stays the residual of f.  s goes to the transposed
+// padded layout (G, in the other layout, is still read by neighbouring
+// threads); partials <s,s> and |f|^2 into p_ss_e[bx], p_ff_e[bx].
+__device__ __forceinline__ void nn_step_chunk(int bx, int e, float *__restrict__ fe,
+                                              float *__restrict__ fle,
+                                              const float *__restrict__ gpad,
+                                              float *__restrict__ gpadT, double alpha,
+                                              double *__restrict__ p_ss_e,
+                                              double *__restrict__ p_ff_e, int nx, int ny)
+{
+    const size_t N = (size_t)nx * ny;
+    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
+    double v[2] = {0.0, 0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            const double g = gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e];
+            const double fo = (double)fe[i] + (double)fle[i];
+            const double t = fo - alpha * g;
+            float s32 = t > 0.0 ? (float)(t - fo) : __double2float_rz(-fo);
+            if (fo + (double)s32 < 0.0) s32 = __double2float_rz(-fo);
+            const double fn = fo + (double)s32;
+            const float hi = (float)fn;
+            fe[i] = hi;
+            fle[i] = (float)(fn - (double)hi);
+            gpadT[2 * ((size_t)(c + kPad) * pny + r + kPad) + e] = s32;
+            v[0] += (double)s32 * (double)s32;
+            v[1] += fo * fo;
+        }
+    }
+    __shared__ double tot[2];
+    block_sum<2>(v, tot);
+    if (threadIdx.x == 0) {
+        p_ss_e[bx] = tot[0];
+        p_ff_e[bx] = tot[1];
+    }
+}
+
+// |grad s|^2 partial of chunk bx (backward differences of Eq. 2) and s copied
+// into the normal padded layout, so that the forward projector reads s in both.
+__device__ __forceinline__ void nn_grad_chunk(int bx, int e, float *__restrict__ gpad,
+                                              const float *__restrict__ gpadT,
+                                              double *__restrict__ p_gs_e, int nx, int ny)
+{
+    const size_t N = (size_t)nx * ny;
+    const int pnx = nx + 2 * kPad, pny = ny + 2 * kPad;
+    auto sT = [&](int r, int c) { return gpadT[2 * ((size_t)(c + kPad) * pny + r + kPad) + e]; };
+    double v[1] = {0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            const float si = sT(r, c);
+            const double gx = c >= 1 ? (double)si - (double)sT(r, c - 1) : 0.0;
+            const double gy = r >= 1 ? (double)si - (double)sT(r - 1, c) : 0.0;
+            gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e] = si;
+            v[0] += gx * gx + gy * gy;
+        }
+    }
+    __shared__ double tot[1];
+    block_sum<1>(v, tot);
+    if (threadIdx.x == 0) p_gs_e[bx] = tot[0];
+}
+
+// Sinogram chunk bx: (r + rlo) += (p + plo) = A s in FP64; partial |r|^2.
+__device__ __forceinline__ void nn_resid_chunk(int bx, float *__restrict__ re,
+                                               float *__restrict__ rle,
+                                               const float *__restrict__ pe,
+                                               const float *__restrict__ ple,
+                                               double *__restrict__ p_rr_e, int M)
+{
+    const size_t Ms = (size_t)M;
+    double v[1] = {0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+        if (i < Ms) {
+            const double d = ((double)re[i] + (double)rle[i]) + ((double)pe[i] + (double)ple[i]);
+            const float hi = (float)d;
+            re[i] = hi;
+            rle[i] = (float)(d - (double)hi);
+            v[0] += d * d;
+        }
+    }
+    __shared__ double tot[1];
+    block_sum<1>(v, tot);
+    if (threadIdx.x == 0) p_rr_e[bx] = tot[0];
+}
+
+// One block per energy: |r|^2, <s,s>, <s,y> = mu |A s|^2 + rho |grad s|^2 and
+// |s| / |f| from the partials; counts the iteration, marks the deferred
+// multiplier step and applies the relative-change stop rule.
+__device__ __forceinline__ void nn_rr_energy(AdmScalars &s, const double *__restrict__ p_rr_e,
+                                             int nbs, const double *__restrict__ p_ss_e,
+                                             const double *__restrict__ p_ff_e,
+                                             const double *__restrict__ p_gs_e, int nbi,
+                                             const double *__restrict__ p_as_e, int nb_fwd,
+                                             double mu, double rho, double tol)
+{
+    const bool run = !s.stopped;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (run) {
+        for (int i = threadIdx.x; i < nbs; i += 256) v[0] += p_rr_e[i];
+        for (int i = threadIdx.x; i < nbi; i += 256) {
+            v[1] += p_ss_e[i];
+            v[2] += p_ff_e[i];
+            v[3] += p_gs_e[i];
+        }
+        for (int i = threadIdx.x; i < nb_fwd; i += 256) v[4] += p_as_e[i];
+    }
+    __shared__ double tot[5];
+    block_sum<5>(v, tot);
+    if (run && threadIdx.x == 0) {
+        const double ss = tot[1], ff = tot[2];
+        s.rr = tot[0];
+        s.ss = ss;
+        s.sy = mu * tot[4] + rho * tot[3];
+        s.relchg = ff > 0.0 ? sqrt(ss) / sqrt(ff) : (ss > 0.0 ? INFINITY : 0.0);
+        s.pending = 1;
+        s.iter += 1;
+        if (tol > 0.0 && s.relchg < tol) s.stopped = 1;
+    }
+    __syncthreads();
+}
+
+// BB2 / adaptive steps: the partial of |mu A^T A G + rho grad^T grad G|^2 of
+// chunk bx of energy e, from the nplanes partial planes ap_e of A^T (A G)
+// (summed in plane order) and G in the padded layout (still this
+// iteration's G).
+__device__ __forceinline__ void yy_chunk(int bx, int e, const float *__restrict__ ap_e,
+                                         int nplanes, float mu, const float *__restrict__ gpad,
+                                         float rho, double *__restrict__ p_yy_e, int nx, int ny)
+{
+    const size_t N = (size_t)nx * ny;
+    const int pnx = nx + 2 * kPad;
+    auto G = [&](int r, int c) { return gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad) + e]; };
+    // backward difference along x / y at (r, c) (zero on the first column / row)
+    auto gx = [&](int r, int c) { return c >= 1 ? G(r, c) - G(r, c - 1) : 0.f; };
+    auto gy = [&](int r, int c) { return r >= 1 ? G(r, c) - G(r - 1, c) : 0.f; };
+    double v[1] = {0.0};
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+        if (i < N) {
+            const int r = (int)(i / nx), c = (int)(i % nx);
+            float a = 0.f;
+            for (int q = 0; q < nplanes; ++q) a += ap_e[(size_t)q * N + i];
+            float lt = 0.f;  // (grad^T grad G) at (r, c)
+            if (c >= 1) lt += gx(r, c);
+            if (c + 1 <= nx - 1) lt -= gx(r, c + 1);
+            if (r >= 1) lt += gy(r, c);
+            if (r + 1 <= ny - 1) lt -= gy(r + 1, c);
+            const double y = (double)mu * a + (double)rho * lt;
+            v[0] += y * y;
+        }
+    }
+    __shared__ double tot[1];
+    block_sum<1>(v, tot);
+    if (threadIdx.x == 0) p_yy_e[bx] = tot[0];
+}
+
 // ------------------------------------------------------------- update ---
 // Chunk bx of 1024 elements: bx < nbi updates the image (f + flo) -= alpha G
 // in FP64, split again into f + flo; otherwise sinogram chunk bx - nbi:

@@ -8,7 +8,11 @@
 // blocks round-robin; the adjoint's view-group depth (how many blocks share
 // one output tile) is chosen per batch by a timing autotuner.  Slices with
 // the coupled TV, and Siddon slices, get lists of their own in the phases
-// that differ (the stencil; the projectors), each one more persistent launch.
+// that differ (the stencil; the projectors), each one more persistent launch;
+// the projected slices (DECT_NONNEG) replace the update by the projected
+// step, a forward projection of it and its residual update, and the BB2 /
+// adaptive slices add a back-projection of A G and the |y|^2 partials, each
+// phase over the slices that have it.
 #include <algorithm>
 #include <array>
 #include <cstring>
@@ -29,6 +33,10 @@ struct SliceDev {
     const LaneRange *lanes;
     const SidW *sid;  // Siddon weight terms (null: Joseph)
     int coupled;      // the TV couples the two energies
+    int nonneg;       // every f-step projected onto f >= 0
+    int step_rule;    // 0 BB1, 1 BB2, 2 adaptive
+    float *apart;     // BB2 / adaptive: [2][2 nvg] partial planes of A^T (A G)
+    double *p_yy;     // BB2 / adaptive: [2][nbi] partials of |y|^2
     float rho, xi, muf;
     double mu, rhod, tol;
     AdmPtrs P;
@@ -136,7 +144,9 @@ __global__ __launch_bounds__(256) void kb_scalar(const SliceDev *__restrict__ S,
         const int e = w.y;
         scalar_energy(d.P.sc[e], d.P.p_tv + (size_t)e * d.P.nb_tv * kTvParts, d.P.nb_tv,
                       d.P.p_fwd + (size_t)e * d.P.nb_fwd, d.P.nb_fwd, d.P.log, d.P.log_rows, e,
-                      d.mu, d.rhod, false, true, d.P.p_rr + (size_t)e * d.P.nbs, d.P.nbs, d.tol);
+                      d.mu, d.rhod, d.nonneg != 0, d.nonneg == 0,
+                      d.P.p_rr + (size_t)e * d.P.nbs, d.P.nbs, d.tol, d.step_rule,
+                      d.p_yy ? d.p_yy + (size_t)e * d.P.nbi : nullptr, d.P.nbi);
     }
 }
 
@@ -160,8 +170,91 @@ __global__ __launch_bounds__(256) void kb_update(const SliceDev *__restrict__ S,
     }
 }
 
-// item = (slice, strip of either ray class, view group): both energies;
-// SID: Siddon slices
+// Projected step (DECT_NONNEG): item = (slice, energy, image chunk).
+__global__ __launch_bounds__(256) void kb_nn_step(const SliceDev *__restrict__ S,
+                                                  const int4 *__restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        const SliceDev &d = S[w.x];
+        const int e = w.y;
+        if (!d.P.sc[e].stopped) {
+            const size_t N = (size_t)d.nx * d.ny;
+            nn_step_chunk(w.z, e, d.P.f + e * N, d.P.flo + e * N, d.P.gpad, d.P.gpadT,
+                          d.P.sc[e].alpha, d.P.p_ss + (size_t)e * d.P.nbi,
+                          d.P.p_ff + (size_t)e * d.P.nbi, d.nx, d.ny);
+        }
+        __syncthreads();
+    }
+}
+
+// |grad s|^2 and s into both padded layouts: item = (slice, energy, image chunk).
+__global__ __launch_bounds__(256) void kb_nn_grad(const SliceDev *__restrict__ S,
+                                                  const int4 *__restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        const SliceDev &d = S[w.x];
+        const int e = w.y;
+        if (!d.P.sc[e].stopped)
+            nn_grad_chunk(w.z, e, d.P.gpad, d.P.gpadT, d.P.p_gs + (size_t)e * d.P.nbi, d.nx,
+                          d.ny);
+        __syncthreads();
+    }
+}
+
+// r += A s: item = (slice, energy, sinogram chunk).
+__global__ __launch_bounds__(256) void kb_nn_resid(const SliceDev *__restrict__ S,
+                                                   const int4 *__restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        const SliceDev &d = S[w.x];
+        const int e = w.y;
+        if (!d.P.sc[e].stopped) {
+            const size_t M = (size_t)d.M;
+            nn_resid_chunk(w.z, d.P.r + e * M, d.P.rlo + e * M, d.P.p + e * M, d.P.plo + e * M,
+                           d.P.p_rr + (size_t)e * d.P.nbs, d.M);
+        }
+        __syncthreads();
+    }
+}
+
+// The projected step's scalars: item = (slice, energy).
+__global__ __launch_bounds__(256) void kb_nn_rr(const SliceDev *__restrict__ S,
+                                                const int4 *__restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        const SliceDev &d = S[w.x];
+        const int e = w.y;
+        nn_rr_energy(d.P.sc[e], d.P.p_rr + (size_t)e * d.P.nbs, d.P.nbs,
+                     d.P.p_ss + (size_t)e * d.P.nbi, d.P.p_ff + (size_t)e * d.P.nbi,
+                     d.P.p_gs + (size_t)e * d.P.nbi, d.P.nbi, d.P.p_fwd + (size_t)e * d.P.nb_fwd,
+                     d.P.nb_fwd, d.mu, d.rhod, d.tol);
+    }
+}
+
+// |y|^2 partials of the BB2 / adaptive steps: item = (slice, energy, image chunk).
+__global__ __launch_bounds__(256) void kb_yy(const SliceDev *__restrict__ S,
+                                             const int4 *__restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        const SliceDev &d = S[w.x];
+        const int e = w.y;
+        if (!d.P.sc[e].stopped) {
+            const size_t N = (size_t)d.nx * d.ny;
+            yy_chunk(w.z, e, d.apart + (size_t)e * 2 * d.nvg * N, 2 * d.nvg, d.muf, d.P.gpad,
+                     d.rho, d.p_yy + (size_t)e * d.P.nbi, d.nx, d.ny);
+        }
+        __syncthreads();
+    }
+}
+
+// item = (slice, strip of either ray class, view group, source): both
+// energies; SID: Siddon slices.  source 0: r into the partial planes of
+// mu A^T r; 1 (BB2 / adaptive): p = A G into those of A^T A G.
 template <bool SID>
 __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict__ S,
                                               const int4 *__restrict__ items, int n)
@@ -176,10 +269,12 @@ __global__ __launch_bounds__(kAdjThreads) void kb_adj(const SliceDev *__restrict
         const size_t plane = (size_t)d.nx * d.ny;
         const int cls = strip < adj_strips_x(d.nx, d.ny) ? 0 : 1;
         if (!(d.P.sc[0].stopped && d.P.sc[1].stopped)) {
-            const float *s[2] = {d.P.r, d.P.r + d.M};
+            const float *src = w.w ? d.P.p : d.P.r;
+            float *dst = w.w ? d.apart : d.P.adjpart;
+            const float *s[2] = {src, src + d.M};
             float *p[2];
             for (int e = 0; e < 2; ++e)
-                p[e] = d.P.adjpart + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
+                p[e] = dst + ((size_t)e * 2 * d.nvg + (size_t)cls * d.nvg + g) * plane;
             adj_block<2, SID>(sh, s, d.fwd, d.len, d.sid, d.bins, d.lanes, d.nx, d.ny, d.V,
                               d.B, strip, g, d.nvg, p, stage, SID ? sid_stage : nullptr);
         }
@@ -196,10 +291,17 @@ struct dect_batch {
     std::vector<dect_adm_params> prm;
     std::vector<dect::SliceDev> host;
     std::vector<size_t> off;  // arena offsets per slice
-    // work lists; the stencil's split by coupled TV, the projectors' by model
-    dect::DevBuf arena, slices, w_tv[2], w_fwd[2], w_se, w_upd, w_adj[2];
-    int n_tv[2] = {0, 0}, n_fwd[2] = {0, 0}, n_se = 0, n_upd = 0, n_adj[2] = {0, 0};
-    int g_tv[2] = {0, 0}, g_fwd[2] = {0, 0}, g_se = 0, g_upd = 0, g_adj[2] = {0, 0};
+    // a work list of one phase: items, count, persistent grid
+    struct WList {
+        dect::DevBuf buf;
+        int n = 0, g = 0;
+    };
+    // the stencil's lists split by coupled TV, the projectors' by model;
+    // fwdn: A G (first iteration) and A s of the projected slices; adjp: A^T
+    // A G of the BB2 / adaptive slices
+    dect::DevBuf arena, slices;
+    WList tv[2], fwd[2], fwdn[2], se, upd, nnc, nnr, nne, adjp[2], yyc, adj[2];
+    bool any_nonneg = false;
     int nvg_max = 16, group_choice = 0;  // 0: per-slice heuristic, else fixed
     // autotuned shape: the adjoint view-group depth per slice (0: as
     // group_choice) and the persistent grids' blocks per CU for the adjoint
@@ -226,7 +328,9 @@ int heuristic_groups(const GeomTables &t) { return adj_groups(t, 2); }
 // Work lists and persistent grid sizes for the current view-group choice.
 dect_status build_work(dect_batch *b)
 {
-    std::vector<std::pair<double, int4>> tv[2], fwd[2], se, upd, adj[2];
+    std::vector<std::pair<double, int4>> tv[2], fwd[2], fwdn[2], se, upd, nnc, nnr, nne, adjp[2],
+        yyc, adj[2];
+    b->any_nonneg = false;
     for (int s = 0; s < b->n; ++s) {
         SliceDev &d = b->host[s];
         const GeomTables &t = *b->t[s];
@@ -239,37 +343,52 @@ dect_status build_work(dect_batch *b)
         const int gx = (d.nx + kTX - 1) / kTX, gy = (d.ny + kTY - 1) / kTY;
         const int nstrips = adj_strips(d.nx, d.ny);
         const int c = d.coupled ? 1 : 0, m = d.sid ? 1 : 0;
+        b->any_nonneg = b->any_nonneg || d.nonneg;
         for (int e = 0; e < 2; ++e) {
             for (int ty = 0; ty < gy; ++ty)
                 for (int tx = 0; tx < gx; ++tx) tv[c].push_back({1.0, make_int4(s, e, ty, tx)});
             se.push_back({1.0, make_int4(s, e, 0, 0)});
-            for (int k = 0; k < d.P.nbi + d.P.nbs; ++k) upd.push_back({1.0, make_int4(s, e, k, 0)});
+            if (d.nonneg) {
+                for (int k = 0; k < d.P.nbi; ++k) nnc.push_back({1.0, make_int4(s, e, k, 0)});
+                for (int k = 0; k < d.P.nbs; ++k) nnr.push_back({1.0, make_int4(s, e, k, 0)});
+                nne.push_back({1.0, make_int4(s, e, 0, 0)});
+            } else {
+                for (int k = 0; k < d.P.nbi + d.P.nbs; ++k)
+                    upd.push_back({1.0, make_int4(s, e, k, 0)});
+            }
+            if (d.step_rule)
+                for (int k = 0; k < d.P.nbi; ++k) yyc.push_back({1.0, make_int4(s, e, k, 0)});
         }
         // the projectors carry both energies per item
         for (int k = 0; k < d.P.nb_fwd; ++k)
-            fwd[m].push_back({(double)std::max(d.nx, d.ny), make_int4(s, k, 0, 0)});
+            (d.nonneg ? fwdn : fwd)[m].push_back({(double)std::max(d.nx, d.ny),
+                                                  make_int4(s, k, 0, 0)});
         for (int strip = 0; strip < nstrips; ++strip)
-            for (int g = 0; g < nvg; ++g)
+            for (int g = 0; g < nvg; ++g) {
                 adj[m].push_back({(double)d.V / nvg, make_int4(s, strip, g, 0)});
+                if (d.step_rule) adjp[m].push_back({(double)d.V / nvg, make_int4(s, strip, g, 1)});
+            }
     }
-    auto upload = [&](std::vector<std::pair<double, int4>> &v, DevBuf &buf, int &count) {
+    auto upload = [&](std::vector<std::pair<double, int4>> &v, dect_batch::WList &w) {
         std::stable_sort(v.begin(), v.end(),
                          [](const auto &a, const auto &c) { return a.first > c.first; });
         std::vector<int4> flat(v.size());
         for (size_t i = 0; i < v.size(); ++i) flat[i] = v[i].second;
-        count = (int)flat.size();
-        dect_status st = buf.ensure(std::max<size_t>(1, flat.size()) * sizeof(int4));
+        w.n = (int)flat.size();
+        dect_status st = w.buf.ensure(std::max<size_t>(1, flat.size()) * sizeof(int4));
         if (st) return st;
-        DECT_HIP(hipMemcpy(buf.ptr, flat.data(), flat.size() * sizeof(int4), hipMemcpyHostToDevice));
+        DECT_HIP(hipMemcpy(w.buf.ptr, flat.data(), flat.size() * sizeof(int4), hipMemcpyHostToDevice));
         return DECT_OK;
     };
     dect_status st;
     for (int k = 0; k < 2; ++k)
-        if ((st = upload(tv[k], b->w_tv[k], b->n_tv[k])) ||
-            (st = upload(fwd[k], b->w_fwd[k], b->n_fwd[k])) ||
-            (st = upload(adj[k], b->w_adj[k], b->n_adj[k])))
+        if ((st = upload(tv[k], b->tv[k])) || (st = upload(fwd[k], b->fwd[k])) ||
+            (st = upload(fwdn[k], b->fwdn[k])) || (st = upload(adj[k], b->adj[k])) ||
+            (st = upload(adjp[k], b->adjp[k])))
             return st;
-    if ((st = upload(se, b->w_se, b->n_se)) || (st = upload(upd, b->w_upd, b->n_upd))) return st;
+    if ((st = upload(se, b->se)) || (st = upload(upd, b->upd)) || (st = upload(nnc, b->nnc)) ||
+        (st = upload(nnr, b->nnr)) || (st = upload(nne, b->nne)) || (st = upload(yyc, b->yyc)))
+        return st;
     DECT_HIP(hipMemcpy(b->slices.ptr, b->host.data(), b->host.size() * sizeof(SliceDev),
                        hipMemcpyHostToDevice));
     int dev = 0, cus = 0;
@@ -283,14 +402,22 @@ dect_status build_work(dect_batch *b)
         if (cap > 0) per = std::min(per, cap);
         return std::max(1, std::min(items, per * cus));
     };
-    b->g_tv[0] = grid((const void *)kb_tv<false>, b->n_tv[0]);
-    b->g_tv[1] = grid((const void *)kb_tv<true>, b->n_tv[1]);
-    b->g_fwd[0] = grid((const void *)kb_fwd<false>, b->n_fwd[0], kFwdThreads, b->fwd_per_cu);
-    b->g_fwd[1] = grid((const void *)kb_fwd<true>, b->n_fwd[1], kFwdThreads, b->fwd_per_cu);
-    b->g_se = std::max(1, b->n_se);
-    b->g_upd = grid((const void *)kb_update, b->n_upd);
-    b->g_adj[0] = grid((const void *)kb_adj<false>, b->n_adj[0], kAdjThreads, b->adj_per_cu);
-    b->g_adj[1] = grid((const void *)kb_adj<true>, b->n_adj[1], kAdjThreads, b->adj_per_cu);
+    b->tv[0].g = grid((const void *)kb_tv<false>, b->tv[0].n);
+    b->tv[1].g = grid((const void *)kb_tv<true>, b->tv[1].n);
+    for (int k = 0; k < 2; ++k) {
+        const void *kf = k ? (const void *)kb_fwd<true> : (const void *)kb_fwd<false>;
+        const void *ka = k ? (const void *)kb_adj<true> : (const void *)kb_adj<false>;
+        b->fwd[k].g = grid(kf, b->fwd[k].n, kFwdThreads, b->fwd_per_cu);
+        b->fwdn[k].g = grid(kf, b->fwdn[k].n, kFwdThreads, b->fwd_per_cu);
+        b->adj[k].g = grid(ka, b->adj[k].n, kAdjThreads, b->adj_per_cu);
+        b->adjp[k].g = grid(ka, b->adjp[k].n, kAdjThreads, b->adj_per_cu);
+    }
+    b->se.g = std::max(1, b->se.n);
+    b->nne.g = std::max(1, b->nne.n);
+    b->upd.g = grid((const void *)kb_update, b->upd.n);
+    b->nnc.g = grid((const void *)kb_nn_step, b->nnc.n);
+    b->nnr.g = grid((const void *)kb_nn_resid, b->nnr.n);
+    b->yyc.g = grid((const void *)kb_yy, b->yyc.n);
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
@@ -298,36 +425,44 @@ dect_status build_work(dect_batch *b)
     return DECT_OK;
 }
 
-dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s)
+// One iteration of every slice; `first`: the projected slices' first step
+// also needs A G (the exact line search along -G).
+dect_status launch_batch_iter(dect_batch *b, int par, hipStream_t s, bool first = false)
 {
     const SliceDev *S = (const SliceDev *)b->slices.ptr;
+    using Kern = void (*)(const SliceDev *, const int4 *, int);
+    auto go = [&](Kern fn, const dect_batch::WList &w, int threads) {
+        if (w.n)
+            hipLaunchKernelGGL(fn, dim3(w.g), dim3(threads), 0, s, S, (const int4 *)w.buf.ptr, w.n);
+    };
     // each phase: one persistent launch per non-empty list
-    if (b->n_tv[0])
-        hipLaunchKernelGGL(kb_tv<false>, dim3(b->g_tv[0]), dim3(256), 0, s, S,
-                           (const int4 *)b->w_tv[0].ptr, b->n_tv[0], par);
-    if (b->n_tv[1])
-        hipLaunchKernelGGL(kb_tv<true>, dim3(b->g_tv[1]), dim3(256), 0, s, S,
-                           (const int4 *)b->w_tv[1].ptr, b->n_tv[1], par);
-    DECT_HIP(hipGetLastError());
-    if (b->n_fwd[0])
-        hipLaunchKernelGGL(kb_fwd<false>, dim3(b->g_fwd[0]), dim3(kFwdThreads), 0, s, S,
-                           (const int4 *)b->w_fwd[0].ptr, b->n_fwd[0]);
-    if (b->n_fwd[1])
-        hipLaunchKernelGGL(kb_fwd<true>, dim3(b->g_fwd[1]), dim3(kFwdThreads), 0, s, S,
-                           (const int4 *)b->w_fwd[1].ptr, b->n_fwd[1]);
-    DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_scalar, dim3(b->g_se), dim3(256), 0, s, S, (const int4 *)b->w_se.ptr,
-                       b->n_se);
-    DECT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(kb_update, dim3(b->g_upd), dim3(256), 0, s, S, (const int4 *)b->w_upd.ptr,
-                       b->n_upd);
-    DECT_HIP(hipGetLastError());
-    if (b->n_adj[0])
-        hipLaunchKernelGGL(kb_adj<false>, dim3(b->g_adj[0]), dim3(kAdjThreads), 0, s, S,
-                           (const int4 *)b->w_adj[0].ptr, b->n_adj[0]);
-    if (b->n_adj[1])
-        hipLaunchKernelGGL(kb_adj<true>, dim3(b->g_adj[1]), dim3(kAdjThreads), 0, s, S,
-                           (const int4 *)b->w_adj[1].ptr, b->n_adj[1]);
+    if (b->tv[0].n)
+        hipLaunchKernelGGL(kb_tv<false>, dim3(b->tv[0].g), dim3(256), 0, s, S,
+                           (const int4 *)b->tv[0].buf.ptr, b->tv[0].n, par);
+    if (b->tv[1].n)
+        hipLaunchKernelGGL(kb_tv<true>, dim3(b->tv[1].g), dim3(256), 0, s, S,
+                           (const int4 *)b->tv[1].buf.ptr, b->tv[1].n, par);
+    go(kb_fwd<false>, b->fwd[0], kFwdThreads);
+    go(kb_fwd<true>, b->fwd[1], kFwdThreads);
+    if (first) {
+        go(kb_fwd<false>, b->fwdn[0], kFwdThreads);
+        go(kb_fwd<true>, b->fwdn[1], kFwdThreads);
+    }
+    go(kb_scalar, b->se, 256);
+    go(kb_update, b->upd, 256);
+    // the projected slices: the step, s in both layouts, r += A s, scalars
+    go(kb_nn_step, b->nnc, 256);
+    go(kb_nn_grad, b->nnc, 256);
+    go(kb_fwd<false>, b->fwdn[0], kFwdThreads);
+    go(kb_fwd<true>, b->fwdn[1], kFwdThreads);
+    go(kb_nn_resid, b->nnr, 256);
+    go(kb_nn_rr, b->nne, 256);
+    // the BB2 / adaptive slices: A^T A G and |y|^2 for the next step
+    go(kb_adj<false>, b->adjp[0], kAdjThreads);
+    go(kb_adj<true>, b->adjp[1], kAdjThreads);
+    go(kb_yy, b->yyc, 256);
+    go(kb_adj<false>, b->adj[0], kAdjThreads);
+    go(kb_adj<true>, b->adj[1], kAdjThreads);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -368,6 +503,11 @@ dect_status batch_run(dect_batch *b, const float *const *mh, const float *const 
     }
     if ((st = batch_graph(b))) return st;
     int k = 0;
+    if (b->any_nonneg && iters > 0) {  // the projected slices' first step starts from A G
+        if ((st = launch_batch_iter(b, 0, s, true))) return st;
+        if (iters > 1 && (st = launch_batch_iter(b, 1, s))) return st;
+        k = std::min(iters, 2);
+    }
     for (; k + 2 <= iters; k += 2) DECT_HIP(hipGraphLaunch(b->graph, s));
     if (k < iters && (st = launch_batch_iter(b, 0, s))) return st;
     return DECT_OK;
@@ -394,9 +534,11 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         const dect_adm_params &p = prm[i];
         if (!(p.mu > 0) || !(p.rho > 0) || !(p.xi >= 0) || !(p.beta_high > 0) || !(p.beta_low > 0))
             return fail(DECT_ERR_INVALID_ARG, "dect_batch_create: invalid ADM parameters");
-        if (p.flags & (DECT_NONNEG | DECT_STEP_BB2 | DECT_STEP_ABB))
+        if ((p.flags & DECT_STEP_BB2) && (p.flags & DECT_STEP_ABB))
+            return fail(DECT_ERR_INVALID_ARG, "DECT_STEP_BB2 and DECT_STEP_ABB exclude each other");
+        if ((p.flags & (DECT_STEP_BB2 | DECT_STEP_ABB)) && (p.flags & DECT_NONNEG))
             return fail(DECT_ERR_INVALID_ARG,
-                        "batched ADM has no non-negative or BB2 / adaptive variant");
+                        "the BB2 / adaptive steps have no non-negative variant");
         if ((p.flags & DECT_COUPLED_TV) && p.tol != 0.0)
             return fail(DECT_ERR_INVALID_ARG,
                         "batched ADM: coupled TV runs a fixed iteration count (tol 0)");
@@ -420,6 +562,9 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         bytes += align256(2 * z.nb_tv * kTvParts * 8) + align256(2 * z.nb_fwd * 8) +
                  align256(2 * z.nbs * 8) + align256(2 * z.nbi * 8);
         bytes += align256(2 * sizeof(AdmScalars));
+        if (p.flags & DECT_NONNEG) bytes += 3 * align256(2 * z.nbi * 8);  // <s,s>, |f|^2, |grad s|^2
+        if (p.flags & (DECT_STEP_BB2 | DECT_STEP_ABB))
+            bytes += align256(z.part * 4) + align256(2 * z.nbi * 8);     // A^T A G planes, |y|^2
         b->off[i] = total;
         total += bytes;
     }
@@ -453,6 +598,17 @@ dect_status batch_create(const dect_geometry *geoms, const dect_adm_params *prm,
         d.P.p_rr = (double *)take(2 * z.nbs * 8);
         d.P.p_tvo = (double *)take(2 * z.nbi * 8);
         d.P.sc = (AdmScalars *)take(2 * sizeof(AdmScalars));
+        d.nonneg = (prm[i].flags & DECT_NONNEG) ? 1 : 0;
+        d.step_rule = (prm[i].flags & DECT_STEP_BB2) ? 1 : (prm[i].flags & DECT_STEP_ABB) ? 2 : 0;
+        if (d.nonneg) {
+            d.P.p_ss = (double *)take(2 * z.nbi * 8);
+            d.P.p_ff = (double *)take(2 * z.nbi * 8);
+            d.P.p_gs = (double *)take(2 * z.nbi * 8);
+        }
+        if (d.step_rule) {
+            d.apart = (float *)take(z.part * 4);
+            d.p_yy = (double *)take(2 * z.nbi * 8);
+        }
         d.P.log = nullptr;
         d.P.log_rows = 0;
         d.P.nb_tv = (int)z.nb_tv;
@@ -525,7 +681,7 @@ dect_status adm_tv_batched(dect_batch *b, const float *const *mh, const float *c
 // Tuned shapes, kept for the process: a batch of the same slice shapes (the
 // multiset of image size, views and bins) reuses them without timing.
 struct TunedShape {
-    std::vector<std::array<int, 6>> shapes;  // sorted (nx, ny, V, B, model, coupled) per slice
+    std::vector<std::array<int, 8>> shapes;  // sorted (nx, ny, V, B, model, variants) per slice
     std::vector<int> groups;                 // per sorted slice
     int adj_per_cu = 0, fwd_per_cu = 0;
     double ms = 0.0;
@@ -533,13 +689,14 @@ struct TunedShape {
 static std::mutex g_tune_mu;
 static std::vector<TunedShape> g_tuned;
 
-static std::vector<int> shape_order(const dect_batch *b, std::vector<std::array<int, 6>> &shapes)
+static std::vector<int> shape_order(const dect_batch *b, std::vector<std::array<int, 8>> &shapes)
 {
     std::vector<int> order(b->n);
     std::iota(order.begin(), order.end(), 0);
     auto key = [&](int i) {
         const SliceDev &d = b->host[i];
-        return std::array<int, 6>{d.nx, d.ny, d.V, d.B, d.sid ? 1 : 0, d.coupled};
+        return std::array<int, 8>{d.nx, d.ny, d.V, d.B, d.sid ? 1 : 0, d.coupled, d.nonneg,
+                                  d.step_rule};
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key(a) < key(c); });
     shapes.resize(b->n);
@@ -577,7 +734,7 @@ dect_status batch_tune(dect_batch *b, const float *const *mh, const float *const
 {
     if (!b || !mh || !ml || iters < 2)
         return fail(DECT_ERR_INVALID_ARG, "dect_batch_tune: bad arguments");
-    std::vector<std::array<int, 6>> shapes;
+    std::vector<std::array<int, 8>> shapes;
     const std::vector<int> order = shape_order(b, shapes);
     // the slice of the costliest class reports its depth in *chosen
     int big = 0;

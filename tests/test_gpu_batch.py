@@ -8,9 +8,10 @@
   slice shapes takes the remembered choice without timing;
 * at the configuration's sizes (512 x 512 at 360 views, 384 x 384 at 90,
   256 x 256 at 60) every slice matches the oracle after 200 iterations;
-* Siddon slices and slices with the coupled TV, mixed with plain Joseph
-  ones, reproduce their single-slice runs bit for bit; the projected and
-  BB2 / adaptive variants are refused.
+* Siddon slices and slices with the coupled TV, the projection onto f >= 0
+  and the BB2 / adaptive steps, mixed with plain Joseph ones, reproduce their
+  single-slice runs bit for bit, also after one and two iterations (the
+  projected slices' first step runs outside the captured graph).
 """
 import numpy as np
 import pytest
@@ -162,8 +163,44 @@ def test_batch_siddon_and_coupled_bitwise(torch):
         assert np.array_equal(to_np(xl[i]), to_np(r.x_low)), i
         assert obj[i] == pytest.approx(r.report.objective, rel=1e-12), i
     b.close()
-    g, s, p = sl[0]
-    for change in ({"nonneg": True}, {"step": "bb2"}, {"step": "abb"},
-                   {"coupled_tv": True, "tol": 1e-4}):
+
+
+def test_batch_variants_bitwise(torch):
+    """Projected (Joseph and Siddon, with and without the coupled TV), BB2
+    and adaptive slices in one batch with a plain one: each equals its
+    single-slice run bit for bit after 1, 2 and 21 iterations; the
+    combinations the single-slice path refuses are refused."""
+    import dataclasses
+    from paper_1607_01650_amd import dect
+    specs = [(64, 30, 0, dict(nonneg=True)), (72, 36, 1, dict(nonneg=True)),
+             (80, 40, 0, dict(step="bb2")), (64, 30, 1, dict(step="abb")),
+             (96, 45, 0, dict(nonneg=True, coupled_tv=True)),
+             (64, 24, 0, dict(step="abb", coupled_tv=True)), (72, 30, 0, {})]
+    sl = []
+    rng = np.random.default_rng(5)
+    for i, (n, V, model, kw) in enumerate(specs):
+        g = C.Geometry(nx=n, ny=n, pixel_mm=1.0, n_views=V, n_bins=int(round(1.4375 * n)),
+                       bin_mm=2.4, sod_mm=500.0, sdd_mm=1000.0, model=model)
+        s = P.make_slice(g, 80 + i, n_inserts=4, r_obj=0.4 * n)
+        # noisy data, so that the projection binds at many pixels
+        sino = [f32(a + 0.05 * a.max() * rng.standard_normal(a.shape)) for a in s.sino]
+        p = C.AdmParams(mu=45.0 / V, rho=1024.0, xi=256.0, beta_high=1.0, beta_low=0.79, **kw)
+        sl.append((g, sino, p))
+    mh = [to_dev(torch, s[0]) for _, s, _ in sl]
+    ml = [to_dev(torch, s[1]) for _, s, _ in sl]
+    b = dect.AdmBatch([g for g, _, _ in sl], [p for _, _, p in sl])
+    for iters in (1, 2, 21):
+        xh, xl, obj = b.run(mh, ml, iters, want_objective=True)
+        for i, (g, s, p) in enumerate(sl):
+            r = dect.adm_tv(mh[i], ml[i], g, dataclasses.replace(p, max_iter=iters),
+                            want_log=True)
+            assert np.array_equal(to_np(xh[i]), to_np(r.x_high)), (iters, i)
+            assert np.array_equal(to_np(xl[i]), to_np(r.x_low)), (iters, i)
+            assert obj[i] == pytest.approx(r.report.objective, rel=1e-12), (iters, i)
+            if p.nonneg:
+                assert to_np(xh[i]).min() >= 0.0 and to_np(xl[i]).min() >= 0.0
+    b.close()
+    g, _, p = sl[-1]
+    for change in ({"nonneg": True, "step": "bb2"}, {"coupled_tv": True, "tol": 1e-4}):
         with pytest.raises(dect.DectError):
             dect.AdmBatch([g], [dataclasses.replace(p, **change)])

@@ -10,7 +10,8 @@ oracle's projected run.
   unconstrained run at 360 views;
 * resuming through a state is bitwise equal to one call; a state started
   without the flag refuses to continue with it; the tolerance stop agrees
-  with the oracle's iteration count; the batched ADM refuses the flag.
+  with the oracle's iteration count; the batched ADM takes the flag but
+  not with the BB2 step.
 """
 import dataclasses
 import os
@@ -125,7 +126,9 @@ def test_tol_stop(torch):
 
 
 def test_batch_refuses(torch):
+    """The batch takes the projection, but not with the BB2 step (as the
+    single-slice path)."""
     dect = _dect()
     with pytest.raises(dect.DectError):
         dect.AdmBatch([C.TINY], [dataclasses.replace(C.default_adm_params(C.TINY, 5),
-                                                     nonneg=True)])
+                                                     nonneg=True, step="bb2")])
