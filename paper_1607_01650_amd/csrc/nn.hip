@@ -1052,20 +1052,23 @@ dect_status dect_nn_conv_fwd_masked(const void *x, const void *w, const float *b
 }
 
 // Tiles per weight-gradient block: TMS output-channel x TNS input-channel
-// tiles (taps x TMS x TNS accumulators of four floats per lane: at most 144
+// tiles (taps x TMS x TNS accumulators of four floats per lane: at most 108
 // for 3x3; staged rows within 64 KB of LDS for 1x1), the first entry of a
-// fixed list that divides the layer's tile counts.
+// fixed list that divides the layer's tile counts.  For 3x3, two tiles per
+// block measured fastest: (2, 2) needs 226 registers (two waves per SIMD),
+// (2, 1) about 140 (three), which outweighs reading dZ once per input tile
+// pair instead of once; (1, 1) reads both operands too often.
 struct WgTiles {
     int tms, tns;
 };
 
 static WgTiles wgrad_tiles(int ks, int TM, int TN)
 {
-    static const WgTiles k3[] = {{2, 2}, {3, 1}, {2, 1}, {1, 2}, {1, 1}};
+    static const WgTiles k3[] = {{2, 1}, {3, 1}, {1, 2}, {1, 1}};
     static const WgTiles k1[] = {{4, 2}, {3, 3}, {2, 3}, {3, 2}, {4, 1}, {2, 2},
                                  {3, 1}, {1, 3}, {2, 1}, {1, 2}, {1, 1}};
     const WgTiles *list = ks == 3 ? k3 : k1;
-    const int n = ks == 3 ? 5 : 11;
+    const int n = ks == 3 ? 4 : 11;
     for (int i = 0; i < n; ++i)
         if (TM % list[i].tms == 0 && TN % list[i].tns == 0) return list[i];
     return {1, 1};
@@ -1144,7 +1147,7 @@ dect_status dect_nn_conv_wgrad(const void *dz, const void *x, float *dw, float *
                            q.nsm * q.nsn, q.len, q.pstride);                                  \
         launched = true;                                                                      \
     }
-    WG(3, 2, 2) WG(3, 3, 1) WG(3, 2, 1) WG(3, 1, 2) WG(3, 1, 1)
+    WG(3, 3, 1) WG(3, 2, 1) WG(3, 1, 2) WG(3, 1, 1)
     WG(1, 4, 2) WG(1, 3, 3) WG(1, 2, 3) WG(1, 3, 2) WG(1, 4, 1) WG(1, 2, 2)
     WG(1, 3, 1) WG(1, 1, 3) WG(1, 2, 1) WG(1, 1, 2) WG(1, 1, 1)
 #undef WG
