@@ -149,15 +149,20 @@ def _layers_np(net):
     return out
 
 
-def test_unet_forward_and_gradients_vs_oracle(torch):
+@pytest.mark.parametrize("N,H,W", [(2, 32, 64), (1, 256, 256)], ids=["2x32x64", "1x256x256"])
+def test_unet_forward_and_gradients_vs_oracle(torch, N, H, W):
+    """The production network (channels 32/48/64/96): small images, and
+    256 x 256, where every kernel runs its full-size path (several row and
+    column tiles, weight-gradient blocks of several steps, many partial
+    chunks); the FP64 oracle takes about 15 s there."""
     nn = _nn()
     net = nn.UNet(seed=1)
     for c in net.layers():  # non-zero biases exercise the bias paths
         c.b.copy_(torch.randn(c.b.shape) * 0.05 * (torch.arange(c.coutp) < c.cout).float())
     assert 480_000 < net.n_params() < 520_000
     rng = np.random.default_rng(5)
-    x = np.zeros((2, 32, 64, 8))
-    x[..., :2] = R.bf16(rng.uniform(0, 1.5, (2, 32, 64, 2)))
+    x = np.zeros((N, H, W, 8))
+    x[..., :2] = R.bf16(rng.uniform(0, 1.5, (N, H, W, 2)))
     xt = _bf(torch, x)
     y = net.forward(xt, keep=True)
     L = _layers_np(net)
@@ -165,8 +170,8 @@ def test_unet_forward_and_gradients_vs_oracle(torch):
     err = rel_l2(_np(y), ry)
     print(f"U-Net forward rel-L2 vs oracle {err:.2e}", flush=True)
     assert err <= 1e-2
-    dy = np.zeros((2, 32, 64, 8))
-    dy[..., :2] = rng.standard_normal((2, 32, 64, 2)) * 1e-3
+    dy = np.zeros((N, H, W, 8))
+    dy[..., :2] = rng.standard_normal((N, H, W, 2)) * 1e-3
     # the backward pass is checked on the GPU's own forward activations: the
     # ReLU masks and pooling choices are then identical on both sides, and the
     # two differ only by accumulation order (and the bf16 roundings it flips)
