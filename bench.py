@@ -575,7 +575,7 @@ def warm_start_extra(n: int):
 def batched_extra(n_slices: int, iters: int):
     """Many slices of uneven size and view count (sizes {256, 384, 512}^2, views
     {60, 90, 180, 360}, seed 0), both energies, advanced together by the
-    batched ADM (one persistent launch per phase, graph replay, autotuned view
+    batched ADM (one launch per phase, graph replay, autotuned view
     grouping): slice-iterations/s, beside the same slices run one after
     another through dect_adm_tv."""
     import numpy as np

@@ -269,7 +269,7 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
 /*
  * Batched ADM-TV (Eq. 10 for many slices at once): slices of uneven image
  * size, view count and parameters, both energies each, advanced together;
- * every phase of an iteration is one persistent launch over a work list that
+ * every phase of an iteration is one launch over a work list that
  * spans all slices, replayed from a hipGraph.  Starts from zero images.
  * geoms/params: host arrays [n] (params[i].max_iter and DECT_WARM_START are ignored);
  *   each slice takes either projector model and the flags of dect_adm_tv
@@ -285,15 +285,16 @@ dect_status dect_pls_edge_weights(int32_t nx, int32_t ny, const float *d_x, doub
  * iterations per candidate on the given data (coordinate descent): for each
  * class of equal slices (image size and view count, costliest first) the
  * adjoint view-group depth 1, 2, 4, 8 or 16 (blocks sharing one output
- * strip, i.e. views per adjoint tile), then the blocks per CU of the
- * persistent adjoint and forward grids (1, 2 or all that fit).  The choice is
- * remembered for the process: a batch with the same multiset of slice shapes
- * (nx, ny, n_views, n_bins, model, variant flags) takes it without timing.  *chosen_groups receives
- * the depth of the costliest slice, *ms_per_iter the tuned time per
- * iteration.  dect_batch_set_groups fixes one depth for every slice
- * (0 = built-in heuristic) and drops the tuned shape; dect_batch_shape
- * reports the depth per slice (host array [n]), the grid caps (0 = all that
- * fit) and whether the last tune came from the process cache.
+ * strip, i.e. views per adjoint tile), then the adjoint and forward grids
+ * (one block per work item, or a persistent grid of 1 or 2 blocks per CU).
+ * The choice is remembered for the process: a batch with the same multiset
+ * of slice shapes (nx, ny, n_views, n_bins, model, variant flags) takes it
+ * without timing.  *chosen_groups receives the depth of the costliest slice,
+ * *ms_per_iter the tuned time per iteration.  dect_batch_set_groups fixes
+ * one depth for every slice (0 = built-in heuristic) and drops the tuned
+ * shape; dect_batch_shape reports the depth per slice (host array [n]), the
+ * grids (0 = one block per work item, k = k blocks per CU) and whether the
+ * last tune came from the process cache.
  */
 typedef struct dect_batch dect_batch;
 dect_status dect_batch_create(const dect_geometry *geoms, const dect_adm_params *params,
