@@ -369,7 +369,9 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     // when its line coordinate q, linear along the lane axis, enters the tap
     // interval (t0 - 1, t0 + kSW) somewhere on the strip's lanes).
     const int nsx = adj_strips_x(nx, ny), nst = adj_strips(nx, ny);
-    if ((double)nst * V * sizeof(BinRange) > (double)(size_t(1) << 30))
+    // the adjoint's tables stay below 4 GiB each (2048^2 x 720 views needs
+    // 1.5 GB of lane ranges; HBM holds 288 GB)
+    if ((double)nst * V * sizeof(BinRange) > (double)(size_t(1) << 32))
         return fail(DECT_ERR_GEOMETRY, "geometry too large for the back-projector's bin table");
     std::vector<BinRange> bins((size_t)nst * V);
     const int64_t one = int64_t(1) << 32;
@@ -436,7 +438,7 @@ dect_status get_tables(const dect_geometry *g, GeomTables **out)
     // zero).  Ranges are stored relative to the strip's lo as bytes; a strip
     // range of more than 256 bins stores none (the kernel then gives every
     // lane the whole range, a superset, which changes no result).
-    if ((double)nst * V * kSL * sizeof(LaneRange) > (double)(size_t(1) << 30))
+    if ((double)nst * V * kSL * sizeof(LaneRange) > (double)(size_t(1) << 32))
         return fail(DECT_ERR_GEOMETRY, "geometry too large for the back-projector's lane table");
     std::vector<LaneRange> lanes((size_t)nst * V * kSL, LaneRange{1, 0});
     for (int sI = 0; sI < nst; ++sI) {

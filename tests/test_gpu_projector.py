@@ -138,3 +138,28 @@ def test_sample_count_matches_oracle(torch):
     dect = _dect()
     for g in (C.TINY, RAGGED):
         assert dect.count_samples(g) == O.count_samples(g)
+
+
+# 4x the metric image along each side at the same physical size (0.25 mm
+# pixels), twice the views and 4x the bins: a size far past the benchmark's,
+# where the adjoint's strip count, the lane-range tables and the forward's
+# line ranges all grow past their tested values.
+LARGE = C.Geometry(nx=2048, ny=2048, pixel_mm=0.25, n_views=720, n_bins=2944, bin_mm=0.6,
+                   sod_mm=1000.0, sdd_mm=2000.0, det_offset_mm=0.15)
+
+
+def test_large_pair_parity(torch):
+    """2048 x 2048, 720 views, 2944 bins: both projectors against the FP64
+    oracle (about 10 s each on the host) and the adjoint identity."""
+    dect = _dect()
+    g = LARGE
+    x = f32(P.random_image(g, 21))
+    y = f32(P.random_sino(g, 22))
+    ax = to_np(dect.project(to_dev(torch, x), g))
+    aty = to_np(dect.backproject(to_dev(torch, y), g))
+    e1 = rel_l2(ax, O.project(g, x))
+    e2 = rel_l2(aty, O.backproject(g, y))
+    lhs, rhs = float(np.sum(ax.astype(np.float64) * y)), float(np.sum(x.astype(np.float64) * aty))
+    adj = abs(lhs - rhs) / (np.linalg.norm(ax) * np.linalg.norm(y))
+    print(f"2048x2048 V=720 B=2944: A {e1:.2e}, A^T {e2:.2e}, adjoint {adj:.1e}", flush=True)
+    assert e1 <= TOL and e2 <= TOL and adj <= 1e-6
