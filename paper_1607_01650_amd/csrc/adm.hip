@@ -35,19 +35,22 @@ namespace dect {
 namespace {
 
 // ------------------------------------------------------------- kernels ---
+// TV stencil: one block per tile of kTX x kTY pixels and energy (tile index
+// = energy * tiles per energy + tile row * tile columns + tile column, also
+// the slot of its partial sums), taken in XCD order (each XCD a band of tile
+// rows, whose halos its blocks share).
 template <bool COUPLED>
 __global__ __launch_bounds__(256) void k_tv_fused(
     const float *__restrict__ f, const float *__restrict__ hpart, int nvg, float mu,
     const float *__restrict__ lam_in,
     const float *__restrict__ z_in, float *__restrict__ lam_out, float *__restrict__ z_out,
     float *__restrict__ gpad, float *__restrict__ gpadT, double *__restrict__ partial,
-    const AdmScalars *__restrict__ sc, int nx, int ny, float rho, float xi)
+    const AdmScalars *__restrict__ sc, int nx, int ny, float rho, float xi, int tiles_x,
+    int tiles_y)
 {
-    // tiles in XCD order: each XCD takes a band of tile rows (shared halos)
-    const unsigned gx = gridDim.x, gy = gridDim.y;
-    const unsigned tile = xcd_order(block_linear(), grid_blocks());
-    const int e = (int)(tile / (gx * gy));
-    const int ty = (int)(tile / gx % gy), tx = (int)(tile % gx);
+    const unsigned tpe = (unsigned)(tiles_x * tiles_y);
+    const unsigned tile = xcd_order(blockIdx.x, gridDim.x);
+    const int e = (int)(tile / tpe), tl = (int)(tile % tpe);
     if (sc[e].stopped || sc[e].stop_next) return;
     const size_t N = (size_t)nx * ny;
     AdmImg m{f + e * N,
@@ -76,8 +79,8 @@ __global__ __launch_bounds__(256) void k_tv_fused(
         m.pending2 = sc[o].pending != 0;
         m.record_tv = e == 0;
     }
-    tv_tile<COUPLED>(ty * kTY, tx * kTX, m, partial + (size_t)tile * kTvParts, sc[e].pending != 0, nx,
-                     ny, rho, xi);
+    tv_tile<COUPLED>(tl / tiles_x * kTY, tl % tiles_x * kTX, m, partial + (size_t)tile * kTvParts,
+                     sc[e].pending != 0, nx, ny, rho, xi);
 }
 
 // One block per energy.  nb_tv/nb_fwd: partial counts per energy.
@@ -488,13 +491,13 @@ static dect_status launch_iter(dect_adm_state *S, int par, double tol, hipStream
     float *lam_in = lam + (size_t)par * 4 * N, *lam_out = lam + (size_t)(1 - par) * 4 * N;
     float *z_in = z + (size_t)par * 4 * N, *z_out = z + (size_t)(1 - par) * 4 * N;
     AdmScalars *sc = (AdmScalars *)S->sc.ptr;
-    dim3 gtv((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY, 2);
+    const int tiles_x = (nx + kTX - 1) / kTX, tiles_y = (ny + kTY - 1) / kTY;
     DECT_TRACE("adm iteration");
-    hipLaunchKernelGGL(S->coupled ? k_tv_fused<true> : k_tv_fused<false>, gtv, dim3(256), 0, s,
-                       (const float *)S->f.ptr, (const float *)S->adjpart.ptr, S->nvg,
-                       (float)S->mu, lam_in, z_in, lam_out, z_out, (float *)S->gpad.ptr,
-                       (float *)S->gpadT.ptr, (double *)S->p_tv.ptr, sc, nx, ny, (float)S->rho,
-                       (float)S->xi);
+    hipLaunchKernelGGL(S->coupled ? k_tv_fused<true> : k_tv_fused<false>,
+                       dim3(2 * tiles_x * tiles_y), dim3(256), 0, s, (const float *)S->f.ptr,
+                       (const float *)S->adjpart.ptr, S->nvg, (float)S->mu, lam_in, z_in, lam_out,
+                       z_out, (float *)S->gpad.ptr, (float *)S->gpadT.ptr, (double *)S->p_tv.ptr,
+                       sc, nx, ny, (float)S->rho, (float)S->xi, tiles_x, tiles_y);
     DECT_HIP(hipGetLastError());
     float *p = (float *)S->p.ptr;
     dect_status st = DECT_OK;

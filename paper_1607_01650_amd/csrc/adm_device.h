@@ -44,10 +44,34 @@ struct AdmScalars {
     int64_t log_base;  // iteration index of log row 0 for this call
 };
 
+// v of this lane moved along the wavefront by the DPP control CTRL (rows of 16
+// lanes not in ROW_MASK, and lanes whose source lies outside their row, get
+// 0); an FP64 value moves as its two 32-bit halves
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum of v over the 64 lanes of a full wavefront, in a fixed order, returned
+// to every lane: a prefix sum within each row of 16 lanes (shifts by 1, 2, 4
+// and 8 lanes), then rows 1 and 3 add the total of the row before them (the
+// row's last lane, broadcast), and rows 2 and 3 add lane 31; lane 63 then
+// holds the total, which is read back as a wavefront-uniform value.  Every
+// step is a VALU lane move, with no LDS round trip.
 __device__ __forceinline__ double wave_sum(double v)
 {
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_f64<0x111>(v);       // row_shr:1
+    v += dpp_f64<0x112>(v);       // row_shr:2
+    v += dpp_f64<0x114>(v);       // row_shr:4
+    v += dpp_f64<0x118>(v);       // row_shr:8
+    v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Fixed-order sum over a 256-thread block of NV values; every thread gets
@@ -124,9 +148,92 @@ struct AdmImg {
 // <G_prev, h>, <G, h>) of the tile, where G_prev is the value the padded G
 // buffer holds at the tile's pixels before this tile overwrites it (the
 // previous iteration's G) and h = mu A^T r the data term of this G.
-template <bool COUPLED = false>
-__device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part,
-                                        bool pending, int nx, int ny, float rho, float xi)
+//
+// A tile runs in two stages.  tv_load issues every global read the tile
+// needs into registers and uses none of them: the first kTvHq partial planes
+// of h on the thread's (at most two) G-region pixels, lambda and z on its
+// w-region pixels, f and f_lo on its f-region pixels, and the previous G at
+// its own pixel.  tv_compute then does the arithmetic.  The tile's reads thus
+// go out as one batch: one memory latency, not one per plane group and input
+// kind.
+constexpr int kTvHq = 8;
+static_assert(kFW * kFH <= 512, "f region: two pixels per thread at most");
+
+template <bool COUPLED>
+struct TvIn {
+    float h[2][kTvHq];
+    float lx[2], ly[2], zx[2], zy[2];
+    float lx2[2], ly2[2], zx2[2], zy2[2];  // coupled TV: the other energy's
+    float f[2], fl[2], f2[2], fl2[2];
+    float gprev;
+};
+
+// Region pixel i of a tile (rows and columns from (r0 + d, c0 + d), w wide, n
+// pixels): its image offset, and whether it exists and lies in the image.
+__device__ __forceinline__ bool tv_pix(int i, int w, int n, int r0, int c0, int d, int nx, int ny,
+                                       size_t &o)
+{
+    const int r = r0 + d + i / w, c = c0 + d + i % w;
+    const bool ok = i < n && r >= 0 && r < ny && c >= 0 && c < nx;
+    o = ok ? (size_t)r * nx + c : 0;
+    return ok;
+}
+
+// Every load is unconditional: one outside the image (or a plane beyond the
+// slice's count, or z while no multiplier step is pending) reads element 0
+// of its array instead, and tv_compute discards it.  No load sits under a
+// branch, where the compiler would fold the first use into the branch and
+// wait for the load there.
+template <bool COUPLED>
+__device__ __forceinline__ void tv_load(int r0, int c0, const AdmImg &m, int nx, int ny,
+                                        TvIn<COUPLED> &in)
+{
+    const size_t N = (size_t)nx * ny;
+    const int hq = m.hq < kTvHq ? m.hq : kTvHq;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        size_t o;
+        tv_pix(threadIdx.x + 256 * k, kGW, kGW * kGH, r0, c0, -1, nx, ny, o);
+#pragma unroll
+        for (int u = 0; u < kTvHq; ++u) in.h[k][u] = m.h[u < hq ? o + (size_t)u * N : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        size_t o;
+        tv_pix(threadIdx.x + 256 * k, kWW, kWW * kWH, r0, c0, -1, nx, ny, o);
+        in.lx[k] = m.lxi[o];
+        in.ly[k] = m.lyi[o];
+        in.zx[k] = m.zxi[o];
+        in.zy[k] = m.zyi[o];
+        if constexpr (COUPLED) {
+            in.lx2[k] = m.lxi2[o];
+            in.ly2[k] = m.lyi2[o];
+            in.zx2[k] = m.zxi2[o];
+            in.zy2[k] = m.zyi2[o];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        size_t o;
+        tv_pix(threadIdx.x + 256 * k, kFW, kFW * kFH, r0, c0, -2, nx, ny, o);
+        in.f[k] = m.f[o];
+        in.fl[k] = m.flo[o];
+        if constexpr (COUPLED) {
+            in.f2[k] = m.f2[o];
+            in.fl2[k] = m.flo2[o];
+        }
+    }
+    {
+        const int r = r0 + (int)threadIdx.x / kTX, c = c0 + (int)threadIdx.x % kTX;
+        const size_t pnx = (size_t)nx + 2 * kPad;
+        in.gprev = m.gpad[r < ny && c < nx ? 2 * ((size_t)(r + kPad) * pnx + c + kPad) : 0];
+    }
+}
+
+template <bool COUPLED>
+__device__ __forceinline__ void tv_compute(int r0, int c0, const AdmImg &m, const TvIn<COUPLED> &in,
+                                           double *part, bool pending, int nx, int ny, float rho,
+                                           float xi)
 {
     __shared__ float sf[kFH][kFW + 1], sl[kFH][kFW + 1];
     __shared__ float sf2[COUPLED ? kFH : 1][COUPLED ? kFW + 1 : 1];
@@ -136,10 +243,24 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     __shared__ double outv[kTvParts];
     const float inv_rho = 1.0f / rho;
 
-    // h = hmu * (sum of the partial planes, in plane order) on the G region
-    // (a thread holds at most two of its pixels).  It
-    // depends on nothing else here, so its loads go out first, eight planes
-    // at a time, and overlap the tile loads below.
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < kFW * kFH) {
+            size_t o;
+            const bool ok = tv_pix(i, kFW, kFW * kFH, r0, c0, -2, nx, ny, o);
+            const int rr = i / kFW, cc = i % kFW;
+            sf[rr][cc] = ok ? in.f[k] : 0.f;
+            sl[rr][cc] = ok ? in.fl[k] : 0.f;
+            if constexpr (COUPLED) {
+                sf2[rr][cc] = ok ? in.f2[k] : 0.f;
+                sl2[rr][cc] = ok ? in.fl2[k] : 0.f;
+            }
+        }
+    }
+
+    // h = hmu * (sum of the partial planes, in plane order) on the G region;
+    // planes beyond the first kTvHq are read here
     float hsum[2] = {0.f, 0.f};
     {
         const size_t N = (size_t)nx * ny;
@@ -149,58 +270,16 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             const int rr = i / kGW, cc = i % kGW;
             const int r = r0 - 1 + rr, c = c0 - 1 + cc;
             if (i < kGW * kGH && r >= 0 && r < ny && c >= 0 && c < nx) {
-                const float *hp = m.h + (size_t)r * nx + c;
                 float acc = 0.f;
-                for (int q0 = 0; q0 < m.hq; q0 += 8) {
-                    float t[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) t[u] = q0 + u < m.hq ? hp[(size_t)(q0 + u) * N] : 0.f;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (q0 + u < m.hq) acc += t[u];
+                for (int u = 0; u < kTvHq; ++u)
+                    if (u < m.hq) acc += in.h[k][u];
+                if (m.hq > kTvHq) {
+                    const float *hp = m.h + (size_t)r * nx + c;
+                    for (int q = kTvHq; q < m.hq; ++q) acc += hp[(size_t)q * N];
                 }
                 hsum[k] = acc * m.hmu;
             }
-        }
-    }
-
-    // lambda (and z for the deferred multiplier step) on the w region (at
-    // most two of its pixels per thread), loaded ahead too
-    float lxv[2] = {0.f, 0.f}, lyv[2] = {0.f, 0.f}, zxv[2] = {0.f, 0.f}, zyv[2] = {0.f, 0.f};
-    float lx2v[2] = {0.f, 0.f}, ly2v[2] = {0.f, 0.f}, zx2v[2] = {0.f, 0.f}, zy2v[2] = {0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int i = threadIdx.x + 256 * k;
-        const int rr = i / kWW, cc = i % kWW;
-        const int r = r0 - 1 + rr, c = c0 - 1 + cc;
-        if (i < kWW * kWH && r >= 0 && r < ny && c >= 0 && c < nx) {
-            const size_t o = (size_t)r * nx + c;
-            lxv[k] = m.lxi[o];
-            lyv[k] = m.lyi[o];
-            if (pending) {
-                zxv[k] = m.zxi[o];
-                zyv[k] = m.zyi[o];
-            }
-            if constexpr (COUPLED) {
-                lx2v[k] = m.lxi2[o];
-                ly2v[k] = m.lyi2[o];
-                if (m.pending2) {
-                    zx2v[k] = m.zxi2[o];
-                    zy2v[k] = m.zyi2[o];
-                }
-            }
-        }
-    }
-
-    for (int i = threadIdx.x; i < kFW * kFH; i += 256) {
-        int rr = i / kFW, cc = i % kFW;
-        int r = r0 - 2 + rr, c = c0 - 2 + cc;
-        const bool in = r >= 0 && r < ny && c >= 0 && c < nx;
-        sf[rr][cc] = in ? m.f[(size_t)r * nx + c] : 0.f;
-        sl[rr][cc] = in ? m.flo[(size_t)r * nx + c] : 0.f;
-        if constexpr (COUPLED) {
-            sf2[rr][cc] = in ? m.f2[(size_t)r * nx + c] : 0.f;
-            sl2[rr][cc] = in ? m.flo2[(size_t)r * nx + c] : 0.f;
         }
     }
     __syncthreads();
@@ -218,10 +297,10 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             float fc = sf[rr + 1][cc + 1], lc = sl[rr + 1][cc + 1];
             float dx = c >= 1 ? (fc - sf[rr + 1][cc]) + (lc - sl[rr + 1][cc]) : 0.f;
             float dy = r >= 1 ? (fc - sf[rr][cc + 1]) + (lc - sl[rr][cc + 1]) : 0.f;
-            float lx = lxv[k], ly = lyv[k];
+            float lx = in.lx[k], ly = in.ly[k];  // loaded at this pixel (it is in the image)
             if (pending) {
-                lx -= xi * (dx - zxv[k]);
-                ly -= xi * (dy - zyv[k]);
+                lx -= xi * (dx - in.zx[k]);
+                ly -= xi * (dy - in.zy[k]);
             }
             float vx = dx - lx / rho, vy = dy - ly / rho;
             float n, tvi;
@@ -232,10 +311,10 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
                 float f2c = sf2[rr + 1][cc + 1], l2c = sl2[rr + 1][cc + 1];
                 float dx2 = c >= 1 ? (f2c - sf2[rr + 1][cc]) + (l2c - sl2[rr + 1][cc]) : 0.f;
                 float dy2 = r >= 1 ? (f2c - sf2[rr][cc + 1]) + (l2c - sl2[rr][cc + 1]) : 0.f;
-                float lx2 = lx2v[k], ly2 = ly2v[k];
+                float lx2 = in.lx2[k], ly2 = in.ly2[k];
                 if (m.pending2) {
-                    lx2 -= xi * (dx2 - zx2v[k]);
-                    ly2 -= xi * (dy2 - zy2v[k]);
+                    lx2 -= xi * (dx2 - in.zx2[k]);
+                    ly2 -= xi * (dy2 - in.zy2[k]);
                 }
                 float vx2 = dx2 - lx2 / rho, vy2 = dy2 - ly2 / rho;
                 const float a = vx * vx + vy * vy, b = vx2 * vx2 + vy2 * vy2;
@@ -299,13 +378,11 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
             float gy = r >= 1 ? gv - sg[rr][cc + 1] : 0.f;
             gg = (double)gv * gv;
             gradg = (double)gx * gx + (double)gy * gy;
-            // this pixel's previous G is read by this thread alone, before it
-            // is replaced
-            float* gp = m.gpad + 2 * ((size_t)(r + kPad) * pnx + c + kPad);
-            const float gprev = *gp;
-            gh_old = (double)gprev * hv;
+            // the previous G at this pixel was read by this thread alone (in
+            // tv_load), before it is replaced here
+            gh_old = (double)in.gprev * hv;
             gh = (double)gv * hv;
-            *gp = gv;
+            m.gpad[2 * ((size_t)(r + kPad) * pnx + c + kPad)] = gv;
         }
         // transposed write: consecutive threads take consecutive rows of one
         // column, i.e. consecutive elements of a line of the transposed copy
@@ -318,6 +395,15 @@ __device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double 
     block_sum<kTvParts>(v, outv);
     if (threadIdx.x < kTvParts) part[threadIdx.x] = outv[threadIdx.x];
     __syncthreads();
+}
+
+template <bool COUPLED = false>
+__device__ __forceinline__ void tv_tile(int r0, int c0, const AdmImg &m, double *part,
+                                        bool pending, int nx, int ny, float rho, float xi)
+{
+    TvIn<COUPLED> in;
+    tv_load<COUPLED>(r0, c0, m, nx, ny, in);
+    tv_compute<COUPLED>(r0, c0, m, in, part, pending, nx, ny, rho, xi);
 }
 
 // ------------------------------------------------------------- scalar ---
