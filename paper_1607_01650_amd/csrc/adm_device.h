@@ -436,31 +436,51 @@ __device__ __forceinline__ void scalar_energy(AdmScalars &s, const double *__res
 #pragma unroll
     for (int j = 0; j < kNV; ++j) v[j] = 0.0;
     if (run) {
-        if (fresh_rr)
-            for (int i = threadIdx.x; i < nbs; i += 256) v[kRR] += p_rr[i];
         if (want_yy)
             for (int i = threadIdx.x; i < nyy; i += 256) v[kYY] += p_yy[i];
-        // thread t adds entries t, t + 256, ... in that order; several loads
-        // are issued together
-        for (int i0 = threadIdx.x; i0 < nb_tv; i0 += 256 * 4) {
-            double t[4][kP];
+        // thread t adds entries t, t + 256, ... of each list in that order.
+        // The reads go out in rounds: one round loads the next kScRR, kScTV
+        // and kScF of the thread's entries of p_rr, the tile partials and the
+        // forward partials, unconditionally (an index past a list's end reads
+        // its entry 0, which is not added), and only then adds them: a read
+        // under a branch would be waited for where the branches join.  At
+        // 512 x 512 and 360 views one round holds them all.
+        constexpr int kScRR = 2, kScTV = 4, kScF = 24;
+        const int nrr = fresh_rr ? nbs : 0;
+        const int rounds = std::max(std::max((nrr + 256 * kScRR - 1) / (256 * kScRR),
+                                             (nb_tv + 256 * kScTV - 1) / (256 * kScTV)),
+                                    (nb_fwd + 256 * kScF - 1) / (256 * kScF));
+        for (int q = 0; q < rounds; ++q) {
+            double trr[kScRR], ttv[kScTV][kP], tf[kScF];
+            const int irr = threadIdx.x + 256 * kScRR * q, itv = threadIdx.x + 256 * kScTV * q,
+                      ifw = threadIdx.x + 256 * kScF * q;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + 256 * u;
-#pragma unroll
-                for (int j = 0; j < kP; ++j) t[u][j] = i < nb_tv ? pt[(size_t)i * kP + j] : 0.0;
+            for (int u = 0; u < kScRR; ++u) {
+                const int i = irr + 256 * u;
+                trr[u] = p_rr[i < nrr ? i : 0];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < kScTV; ++u) {
+                const int i = itv + 256 * u;
 #pragma unroll
-                for (int j = 0; j < kP; ++j) v[j] += t[u][j];
-        }
-        for (int i0 = threadIdx.x; i0 < nb_fwd; i0 += 256 * 8) {
-            double t[8];
+                for (int j = 0; j < kP; ++j) ttv[u][j] = pt[(size_t)(i < nb_tv ? i : 0) * kP + j];
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = i0 + 256 * u < nb_fwd ? pf[i0 + 256 * u] : 0.0;
+            for (int u = 0; u < kScF; ++u) {
+                const int i = ifw + 256 * u;
+                tf[u] = pf[i < nb_fwd ? i : 0];
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[kFwd] += t[u];
+            for (int u = 0; u < kScRR; ++u)
+                if (irr + 256 * u < nrr) v[kRR] += trr[u];
+#pragma unroll
+            for (int u = 0; u < kScTV; ++u)
+                if (itv + 256 * u < nb_tv)
+#pragma unroll
+                    for (int j = 0; j < kP; ++j) v[j] += ttv[u][j];
+#pragma unroll
+            for (int u = 0; u < kScF; ++u)
+                if (ifw + 256 * u < nb_fwd) v[kFwd] += tf[u];
         }
     }
     block_sum<kNV>(v, tot);
@@ -712,16 +732,28 @@ __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
                                              double *__restrict__ p_rr, double alpha, int nx,
                                              int ny, int M, int nbi)
 {
+    // the four elements' loads go out together, unconditionally (an element
+    // past the end reads element 0 and is neither computed nor stored), then
+    // the arithmetic and the stores
     __shared__ double tot[1];
     const size_t N = (size_t)nx * ny;
     if (bx < nbi) {
         const int pnx = nx + 2 * kPad;
+        float g[4], a[4], b[4];
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
-            size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+            const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+            const unsigned ic = i < N ? (unsigned)i : 0u;  // images hold fewer than 2^31 pixels
+            const int rr = (int)(ic / (unsigned)nx), cc = (int)ic - rr * nx;
+            g[j] = gpad_e[2 * ((size_t)(rr + kPad) * pnx + cc + kPad)];
+            a[j] = fe[ic];
+            b[j] = fle[ic];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
             if (i < N) {
-                int rr = (int)(i / nx), cc = (int)(i % nx);
-                const double g = gpad_e[2 * ((size_t)(rr + kPad) * pnx + cc + kPad)];
-                const double d = ((double)fe[i] + (double)fle[i]) - alpha * g;
+                const double d = ((double)a[j] + (double)b[j]) - alpha * (double)g[j];
                 const float hi = (float)d;
                 fe[i] = hi;
                 fle[i] = (float)(d - (double)hi);
@@ -730,12 +762,23 @@ __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
         return;  // uniform across the block
     }
     const int bs = bx - nbi;
-    double acc[1] = {0.0};
+    float a[4], b[4], c[4], e[4];
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-        size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
+        const size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
+        const size_t ic = (int)i < M ? i : 0;
+        a[j] = re[ic];
+        b[j] = rle[ic];
+        c[j] = pe[ic];
+        e[j] = ple[ic];
+    }
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
         if ((int)i < M) {
-            const double d = ((double)re[i] + (double)rle[i]) -
-                             alpha * ((double)pe[i] + (double)ple[i]);
+            const double d = ((double)a[j] + (double)b[j]) -
+                             alpha * ((double)c[j] + (double)e[j]);
             const float hi = (float)d;
             re[i] = hi;
             rle[i] = (float)(d - (double)hi);
