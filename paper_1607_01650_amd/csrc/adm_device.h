@@ -74,18 +74,64 @@ __device__ __forceinline__ double wave_sum(double v)
     return __hiloint2double(hi, lo);
 }
 
+// x + y where lanes 0-31 take x of lanes l and l + 32, lanes 32-63 y of lanes
+// l - 32 and l (permlane32 swap of the upper half of x with the lower half of
+// y); with ROWS16, rows of 16 lanes instead: even rows take x of rows r and
+// r + 1, odd rows y of rows r - 1 and r
+template <bool ROWS16>
+__device__ __forceinline__ double swap_add(double x, double y)
+{
+    const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+    const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+    if constexpr (ROWS16) {
+        const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+    } else {
+        const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+    }
+}
+
 // Fixed-order sum over a 256-thread block of NV values; every thread gets
-// the totals in `out` (LDS).  Ends with a barrier.
+// the totals in `out` (LDS).  Ends with a barrier.  For 3 to 8 values the
+// wavefront reduces them together: each exchange step halves the values a
+// lane holds and doubles the lanes each partial covers (wave halves, then
+// row pairs, then the two halves of each row: 8 values, 4, 2, 1), and a
+// butterfly over the last 8 lanes completes each sum, so that lane 8 j holds
+// value j's wavefront total.  The four wavefronts' totals are added in
+// wavefront order.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *out)
 {
     __shared__ double sh[4][NV];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if constexpr (NV >= 3 && NV <= 8) {
+        double a[8];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-    if (lane == 0)
+        for (int j = 0; j < 8; ++j) a[j] = j < NV ? v[j] : 0.0;
+        double b[4], c[2];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) sh[wid][i] = v[i];
+        for (int j = 0; j < 4; ++j) b[j] = swap_add<false>(a[j], a[j + 4]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) c[j] = swap_add<true>(b[j], b[j + 2]);
+        // lanes with bit 3 clear keep c[0] and send c[1] to lane l ^ 8
+        // (row_ror:8), the others the reverse
+        const bool up = (lane & 8) != 0;
+        const double keep = up ? c[1] : c[0], send = up ? c[0] : c[1];
+        double d = keep + dpp_f64<0x128>(send);
+        d += dpp_f64<0xB1>(d);   // quad_perm [1, 0, 3, 2]
+        d += dpp_f64<0x4E>(d);   // quad_perm [2, 3, 0, 1]
+        d += dpp_f64<0x141>(d);  // row_half_mirror
+        if ((lane & 7) == 0 && (lane >> 3) < NV) sh[wid][lane >> 3] = d;
+    } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) sh[wid][i] = v[i];
+    }
     __syncthreads();
     if ((int)threadIdx.x < NV) {
         int t = threadIdx.x;
