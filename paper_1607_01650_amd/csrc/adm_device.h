@@ -778,28 +778,16 @@ __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
                                              double *__restrict__ p_rr, double alpha, int nx,
                                              int ny, int M, int nbi)
 {
-    // the four elements' loads go out together, unconditionally (an element
-    // past the end reads element 0 and is neither computed nor stored), then
-    // the arithmetic and the stores
     __shared__ double tot[1];
     const size_t N = (size_t)nx * ny;
     if (bx < nbi) {
         const int pnx = nx + 2 * kPad;
-        float g[4], a[4], b[4];
-#pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
-            const unsigned ic = i < N ? (unsigned)i : 0u;  // images hold fewer than 2^31 pixels
-            const int rr = (int)(ic / (unsigned)nx), cc = (int)ic - rr * nx;
-            g[j] = gpad_e[2 * ((size_t)(rr + kPad) * pnx + cc + kPad)];
-            a[j] = fe[ic];
-            b[j] = fle[ic];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
+            size_t i = ((size_t)bx * 4 + j) * 256 + threadIdx.x;
             if (i < N) {
-                const double d = ((double)a[j] + (double)b[j]) - alpha * (double)g[j];
+                int rr = (int)(i / nx), cc = (int)(i % nx);
+                const double g = gpad_e[2 * ((size_t)(rr + kPad) * pnx + cc + kPad)];
+                const double d = ((double)fe[i] + (double)fle[i]) - alpha * g;
                 const float hi = (float)d;
                 fe[i] = hi;
                 fle[i] = (float)(d - (double)hi);
@@ -808,23 +796,12 @@ __device__ __forceinline__ void update_chunk(int bx, float *__restrict__ fe,
         return;  // uniform across the block
     }
     const int bs = bx - nbi;
-    float a[4], b[4], c[4], e[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
-        const size_t ic = (int)i < M ? i : 0;
-        a[j] = re[ic];
-        b[j] = rle[ic];
-        c[j] = pe[ic];
-        e[j] = ple[ic];
-    }
     double acc[1] = {0.0};
-#pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
+        size_t i = ((size_t)bs * 4 + j) * 256 + threadIdx.x;
         if ((int)i < M) {
-            const double d = ((double)a[j] + (double)b[j]) -
-                             alpha * ((double)c[j] + (double)e[j]);
+            const double d = ((double)re[i] + (double)rle[i]) -
+                             alpha * ((double)pe[i] + (double)ple[i]);
             const float hi = (float)d;
             re[i] = hi;
             rle[i] = (float)(d - (double)hi);
