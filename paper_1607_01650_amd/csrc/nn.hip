@@ -13,8 +13,11 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "../../include/dect_nn.h"
 
@@ -482,13 +485,19 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const u16 *__restrict__ dZ,
             for (int j = 0; j < TNS; ++j) acc[t][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
     constexpr int zitems = 4 * (kWgPix / 4) * (ZC / 8), xitems = XR * K4X * (XC / 8);
-    for (int st = 0; st < kst; ++st) {
-        const int r = (rc * kst + st) * 4;
-        if (r >= H) break;
-        __syncthreads();  // the previous step is done with the LDS
-        for (int it = threadIdx.x; it < zitems + xitems; it += 256) {
-            uint4 v[4];
-            u16 *dst;
+    constexpr int NIT = (zitems + xitems + 255) / 256;  // staging items per thread
+    // Staging item it = threadIdx.x + 256 q: four pixels by eight channels of
+    // dZ (it < zitems) or X.  A step's loads are unconditional (a pixel or
+    // channel outside the tensor reads its first element and is stored as
+    // zero), so they are in flight together, and the next step's loads go
+    // out before this step's matrix-core work.
+    uint4 sv[NIT][4];
+    unsigned sok[NIT];
+    auto stage_load = [&](int r) {
+#pragma unroll
+        for (int qi = 0; qi < NIT; ++qi) {
+            const int it = threadIdx.x + 256 * qi;
+            unsigned ok = 0;
             if (it < zitems) {
                 constexpr int per_row = (kWgPix / 4) * (ZC / 8);
                 const int q = it / per_row, rem = it - q * per_row;
@@ -497,26 +506,49 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const u16 *__restrict__ dZ,
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int cc = c0 + 4 * px4 + u;
-                    v[u] = make_uint4(0, 0, 0, 0);
-                    if (rr < H && cc < W && co < Cout)
-                        v[u] = *(const uint4 *)(dZ + (img + (size_t)rr * W + cc) * Cout + co);
+                    const bool in = rr < H && cc < W && co < Cout;
+                    ok |= (unsigned)in << u;
+                    sv[qi][u] = *(const uint4 *)(dZ + (in ? (img + (size_t)rr * W + cc) * Cout + co : 0));
                 }
-                dst = sZ + (size_t)(q * ZC + o8) * kWgLD + 4 * px4;
             } else {
                 constexpr int per_row = K4X * (XC / 8);
-                const int j = it - zitems;
-                const int q = j / per_row, rem = j - q * per_row;
+                const int jj = it < zitems + xitems ? it - zitems : 0;
+                const int q = jj / per_row, rem = jj - q * per_row;
                 const int k4 = rem / (XC / 8), o8 = (rem - k4 * (XC / 8)) * 8;
                 const int rr = r - halo + q, ci = ci0 + o8;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int cc = c0 - halo + 4 * k4 + u;
-                    v[u] = make_uint4(0, 0, 0, 0);
-                    if (rr >= 0 && rr < H && cc >= 0 && cc < W && ci < Cin)
-                        v[u] = *(const uint4 *)(X + (img + (size_t)rr * W + cc) * Cin + ci);
+                    const bool in = it < zitems + xitems && rr >= 0 && rr < H && cc >= 0 &&
+                                    cc < W && ci < Cin;
+                    ok |= (unsigned)in << u;
+                    sv[qi][u] = *(const uint4 *)(X + (in ? (img + (size_t)rr * W + cc) * Cin + ci : 0));
                 }
+            }
+            sok[qi] = ok;
+        }
+    };
+    auto stage_store = [&]() {
+#pragma unroll
+        for (int qi = 0; qi < NIT; ++qi) {
+            const int it = threadIdx.x + 256 * qi;
+            if (it >= zitems + xitems) break;
+            u16 *dst;
+            if (it < zitems) {
+                constexpr int per_row = (kWgPix / 4) * (ZC / 8);
+                const int q = it / per_row, rem = it - q * per_row;
+                const int px4 = rem / (ZC / 8), o8 = (rem - px4 * (ZC / 8)) * 8;
+                dst = sZ + (size_t)(q * ZC + o8) * kWgLD + 4 * px4;
+            } else {
+                constexpr int per_row = K4X * (XC / 8);
+                const int jj = it - zitems;
+                const int q = jj / per_row, rem = jj - q * per_row;
+                const int k4 = rem / (XC / 8), o8 = (rem - k4 * (XC / 8)) * 8;
                 dst = sX + (size_t)(q * XC + o8) * kWgLD + 4 * k4;
             }
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = (sok[qi] >> u) & 1u ? sv[qi][u] : make_uint4(0, 0, 0, 0);
             const u16 *e0 = (const u16 *)&v[0], *e1 = (const u16 *)&v[1];
             const u16 *e2 = (const u16 *)&v[2], *e3 = (const u16 *)&v[3];
 #pragma unroll
@@ -527,7 +559,14 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const u16 *__restrict__ dZ,
                 *(uint2 *)(dst + (size_t)e * kWgLD) = w;
             }
         }
+    };
+    const int st0 = rc * kst, nst = min(kst, (H + 3) / 4 - st0);
+    stage_load(st0 * 4);
+    for (int st = 0; st < nst; ++st) {
+        __syncthreads();  // the previous step is done with the LDS
+        stage_store();
         __syncthreads();
+        if (st + 1 < nst) stage_load((st0 + st + 1) * 4);
         if (bias && (int)threadIdx.x < 4 * ZC) {  // row t / ZC, channel t % ZC
             const u16 *zr = sZ + (size_t)threadIdx.x * kWgLD;
 #pragma unroll
@@ -1079,6 +1118,43 @@ struct WgradPlan {
     size_t lds, len, pstride;
 };
 
+static const void *wgrad_kernel(int ks, int tms, int tns)
+{
+#define WGK(k, a, b) \
+    if (ks == k && tms == a && tns == b) return (const void *)k_wgrad<k, a, b>;
+    WGK(3, 3, 1) WGK(3, 2, 1) WGK(3, 1, 2) WGK(3, 1, 1)
+    WGK(1, 4, 2) WGK(1, 3, 3) WGK(1, 2, 3) WGK(1, 3, 2) WGK(1, 4, 1) WGK(1, 2, 2)
+    WGK(1, 3, 1) WGK(1, 1, 3) WGK(1, 2, 1) WGK(1, 1, 2) WGK(1, 1, 1)
+#undef WGK
+    return nullptr;
+}
+
+// Blocks of a tiling's kernel resident on the current device at once (its
+// compute units times the blocks per unit its registers and LDS allow),
+// queried once per device and tiling.
+static int wgrad_resident(int ks, int tms, int tns, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::array<int, 4>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const std::array<int, 4> key{dev, ks, tms, tns};
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    const void *k = wgrad_kernel(ks, tms, tns);
+    if (!k || dev < 0 ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per_cu <= 0 || cus <= 0) {
+        (void)hipGetLastError();
+        per_cu = 2;
+        cus = 256;
+    }
+    return cache[key] = per_cu * cus;
+}
+
 static WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int ksize)
 {
     WgradPlan q;
@@ -1094,9 +1170,14 @@ static WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int ksize)
     const size_t strips = (size_t)N * q.nstrip;
     q.len = (size_t)ksize * ksize * CoutP * Cin;
     q.pstride = q.len + CoutP;
-    // about 768 blocks (three per CU), fewer while the partials would
-    // outweigh twice the layer's own bytes
-    size_t kst = std::max<size_t>(1, (strips * RG * nsplit + 767) / 768);
+    const size_t stage =
+        ((size_t)4 * 16 * t.tms + (size_t)wg_xrows(ksize) * 16 * t.tns) * kWgLD * sizeof(u16);
+    const size_t red = (size_t)3 * t.tms * t.tns * 4 * 64 * sizeof(float);
+    q.lds = std::max(stage, red);
+    // one round of resident blocks, fewer while the partials would outweigh
+    // twice the layer's own bytes
+    const size_t target = (size_t)wgrad_resident(ksize, t.tms, t.tns, q.lds);
+    size_t kst = std::max<size_t>(1, (strips * RG * nsplit + target - 1) / target);
     const double in_bytes = (double)N * H * W * (Cin + Cout) * 2;
     while (kst < RG && (double)strips * ((RG + kst - 1) / kst) * q.pstride * 4 > 2.0 * in_bytes)
         kst *= 2;
@@ -1105,10 +1186,6 @@ static WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int ksize)
     q.nrc = (int)((RG + kst - 1) / kst);
     q.nchunk = (int)(strips * q.nrc);
     q.nseg = sum_segments(q.nchunk, q.pstride);
-    const size_t stage =
-        ((size_t)4 * 16 * t.tms + (size_t)wg_xrows(ksize) * 16 * t.tns) * kWgLD * sizeof(u16);
-    const size_t red = (size_t)3 * t.tms * t.tns * 4 * 64 * sizeof(float);
-    q.lds = std::max(stage, red);
     return q;
 }
 
