@@ -263,36 +263,77 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
     }
     const BinRange *sb = bins + (size_t)strip * V;
 
+    // Views v_begin + wid, + kAdjWaves, ... of this wavefront.  The ray data
+    // of a view's first 64-bin chunk and its lane ranges are loaded while the
+    // previous view is walked: right after a view's first chunk is staged,
+    // the same registers receive the next view's, whose bin range was read
+    // one view earlier still.  These loads are unconditional (a bin past the
+    // range reads the range's first bin, or bin 0 of an empty range, and a
+    // view past the end reads the wavefront's first view; none of it is
+    // used), so the compiler does not wait for them at a branch, and the bin
+    // range is read by every lane (a vector load: a scalar one would be
+    // waited for together with the walk's LDS reads).  Further chunks of a
+    // view are loaded when they are reached.
     const int v_begin = (int)((int64_t)V * g / nvg), v_end = (int)((int64_t)V * (g + 1) / nvg);
-    for (int v = v_begin + wid; v < v_end; v += kAdjWaves) {
-        const BinRange br = sb[v];
-        const int lo = __builtin_amdgcn_readfirstlane(br.lo);
-        const int hi = __builtin_amdgcn_readfirstlane(br.hi);
-        const RayFwd *rfv = rays_fx + (size_t)v * B;
-        const float *lv = len + (size_t)v * B;
-        if (lo > hi) continue;
-        const LaneRange lr = lanes[((size_t)strip * V + v) * kSL + lane];
-        // a strip range too long for the table: every lane takes all of it
-        // (and bins that miss a lane's line are masked)
-        const bool whole = hi - lo > kLaneRangeMax;
-        const int lfirst = whole ? 0 : (int)lr.first, llast = whole ? hi - lo : (int)lr.last;
-        const int sbase = wid * 64;
+    const int vfirst = v_begin + wid;
+    if (vfirst >= v_end) goto done;
+    {
+        int vzero;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+        auto load_br = [&](int v) { return sb[(v < v_end ? v : vfirst) + vzero]; };
+        struct Pre {
+            RayFwd t;
+            float L, y0, y1;
+            SidW sw;
+            LaneRange lr;
+        };
+        auto load_pre = [&](int v, int lo, int hi) {
+            Pre q;
+            const int vv = v < v_end ? v : vfirst;
+            const int bj = lo + lane;
+            const int bc = lo > hi ? 0 : (bj <= hi ? bj : lo);
+            const size_t o = (size_t)vv * B + bc;
+            q.t = rays_fx[o];
+            q.L = len[o];
+            q.y0 = sino[0][o];
+            q.y1 = sino[NE - 1][o];
+            q.sw = SidW{0xFFFFFFFFu, 0.f};
+            if constexpr (SID) q.sw = sid[o];
+            q.lr = lanes[((size_t)strip * V + vv) * kSL + lane];
+            return q;
+        };
         const int snull = kAdjWaves * 64 + wid;
-        // no lane has more bins in a chunk than its whole range holds
-        const int steps = __builtin_amdgcn_readfirstlane(br.steps);
-        // the 64-bin chunks of the strip range; kExact: every bin a lane
-        // takes is one of its own (its first tap line lies in -1 .. kSW - 1
-        // by the host's exact per-lane ranges), so only the steps past its
-        // last bin need care, and they take the null slot
-        auto chunks = [&](auto exact_tag) {
-            constexpr bool kExact = decltype(exact_tag)::value;
-            for (int cb = lo; cb <= hi; cb += 64) {
-                // stage: lane j holds bin cb + j (strip-relative line coordinate)
+        const int sbase = wid * 64;
+        BinRange bcur = load_br(vfirst);
+        int lo = __builtin_amdgcn_readfirstlane(bcur.lo);
+        int hi = __builtin_amdgcn_readfirstlane(bcur.hi);
+        int steps = __builtin_amdgcn_readfirstlane(bcur.steps);
+        Pre pre = load_pre(vfirst, lo, hi);
+        BinRange bnext = load_br(vfirst + kAdjWaves);
+        for (int v = vfirst; v < v_end; v += kAdjWaves) {
+            const RayFwd *rfv = rays_fx + (size_t)v * B;
+            const float *lv = len + (size_t)v * B;
+            // a strip range too long for the table: every lane takes all of it
+            // (and bins that miss a lane's line are masked)
+            const bool whole = hi - lo > kLaneRangeMax;
+            const int lfirst = whole ? 0 : (int)pre.lr.first, llast = whole ? hi - lo : (int)pre.lr.last;
+            // stage chunk cb: lane j holds bin cb + j (strip-relative line
+            // coordinate); the first chunk from the prefetched registers
+            auto stage_chunk = [&](int cb) {
                 const int bj = cb + lane;
                 AdjRay me{0, 0};
                 f2v my_ly = f2v(0.f);
                 SidW my_sw{0xFFFFFFFFu, 0.f};
-                if (bj <= hi) {
+                if (cb == lo) {
+                    if (bj <= hi) {
+                        me.a = pre.t.a_fx + pre.t.k_fx * l0 - ((int64_t)t0 << 32);
+                        me.k = pre.t.k_fx;
+                        const float L = fabsf(pre.L);
+                        my_ly.x = L * pre.y0;
+                        if constexpr (NE > 1) my_ly.y = L * pre.y1;
+                        if constexpr (SID) my_sw = pre.sw;
+                    }
+                } else if (bj <= hi) {
                     const RayFwd t = rfv[bj];
                     me.a = t.a_fx + t.k_fx * l0 - ((int64_t)t0 << 32);
                     me.k = t.k_fx;
@@ -304,71 +345,97 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                 stage.ray[sbase + lane] = me;
                 stage.ly[sbase + lane] = my_ly;
                 if constexpr (SID) sid_stage[sbase + lane] = my_sw;
-                // this lane's bins in the chunk: [f, e], chunk-relative
-                const int rel = cb - lo;
-                const int f = max(lfirst, rel) - rel;
-                const int e = min(llast, rel + 63) - rel;
-                const int n = e - f + 1;
-                // one step: bin b (staged) at this lane.  Masked mode: a lane
-                // past its last bin, or taking a bin that misses its line,
-                // adds zero to lines -1 and 0
-                auto step = [&](const AdjRay &b, f2v y, SidW sw, bool ok) {
-                    const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
-                    const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
-                    int i0 = qh;
-                    if constexpr (!kExact) {
-                        ok = ok && qh >= -1 && qh <= kSW - 1;
-                        i0 = ok ? qh : -1;
-                        if (!ok) y = f2v(0.f);
+            };
+            if (lo <= hi) stage_chunk(lo);
+            // the next view's bin range (read one view ago), then its first
+            // chunk into the registers just staged, and the range after it
+            const int nlo = __builtin_amdgcn_readfirstlane(bnext.lo);
+            const int nhi = __builtin_amdgcn_readfirstlane(bnext.hi);
+            const int nsteps = __builtin_amdgcn_readfirstlane(bnext.steps);
+            pre = load_pre(v + kAdjWaves, nlo, nhi);
+            bnext = load_br(v + 2 * kAdjWaves);
+            // the 64-bin chunks of the strip range; kExact: every bin a lane
+            // takes is one of its own (its first tap line lies in -1 .. kSW - 1
+            // by the host's exact per-lane ranges), so only the steps past its
+            // last bin need care, and they take the null slot
+            auto chunks = [&](auto exact_tag) {
+                constexpr bool kExact = decltype(exact_tag)::value;
+                for (int cb = lo; cb <= hi; cb += 64) {
+                    if (cb != lo) stage_chunk(cb);
+                    // this lane's bins in the chunk: [f, e], chunk-relative
+                    const int rel = cb - lo;
+                    const int f = max(lfirst, rel) - rel;
+                    const int e = min(llast, rel + 63) - rel;
+                    const int n = e - f + 1;
+                    // one step: bin b (staged) at this lane.  Masked mode: a lane
+                    // past its last bin, or taking a bin that misses its line,
+                    // adds zero to lines -1 and 0
+                    auto step = [&](const AdjRay &b, f2v y, SidW sw, bool ok) {
+                        const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
+                        const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
+                        int i0 = qh;
+                        if constexpr (!kExact) {
+                            ok = ok && qh >= -1 && qh <= kSW - 1;
+                            i0 = ok ? qh : -1;
+                            if (!ok) y = f2v(0.f);
+                        }
+                        const uint32_t lo32 = (uint32_t)p;
+                        float w;
+                        if constexpr (SID)
+                            w = (lo32 > sw.c ? (float)(lo32 - sw.c) * sw.inv : 0.f) * kTwoM32;
+                        else
+                            w = (float)lo32 * kTwoM32;
+                        E *pp = col + (i0 + kAccOff) * kSL;
+                        E u0 = pp[0], u1 = pp[kSL];
+                        if constexpr (NE == 1) {
+                            u0 += fmaf(-w, y.x, y.x);
+                            u1 = fmaf(w, y.x, u1);
+                        } else {
+                            u0.x += fmaf(-w, y.x, y.x);
+                            u0.y += fmaf(-w, y.y, y.y);
+                            u1.x = fmaf(w, y.x, u1.x);
+                            u1.y = fmaf(w, y.y, u1.y);
+                        }
+                        pp[0] = u0;
+                        pp[kSL] = u1;
+                    };
+                    // the stage slot of step t at this lane
+                    auto slot = [&](int t) {
+                        if constexpr (kExact) return t < n ? sbase + f + t : snull;
+                        else return sbase + (t < n ? f + t : 0);
+                    };
+                    // two steps at a time, both bins' stage reads issued first
+                    int t = 0;
+                    for (; t + 1 < steps; t += 2) {
+                        const int j0 = slot(t), j1 = slot(t + 1);
+                        const AdjRay b0 = stage.ray[j0], b1 = stage.ray[j1];
+                        const f2v y0 = stage.ly[j0], y1 = stage.ly[j1];
+                        SidW s0{0u, 0.f}, s1{0u, 0.f};
+                        if constexpr (SID) {
+                            s0 = sid_stage[j0];
+                            s1 = sid_stage[j1];
+                        }
+                        step(b0, y0, s0, t < n);
+                        step(b1, y1, s1, t + 1 < n);
                     }
-                    const uint32_t lo = (uint32_t)p;
-                    float w;
-                    if constexpr (SID) w = (lo > sw.c ? (float)(lo - sw.c) * sw.inv : 0.f) * kTwoM32;
-                    else w = (float)lo * kTwoM32;
-                    E *pp = col + (i0 + kAccOff) * kSL;
-                    E u0 = pp[0], u1 = pp[kSL];
-                    if constexpr (NE == 1) {
-                        u0 += fmaf(-w, y.x, y.x);
-                        u1 = fmaf(w, y.x, u1);
-                    } else {
-                        u0.x += fmaf(-w, y.x, y.x);
-                        u0.y += fmaf(-w, y.y, y.y);
-                        u1.x = fmaf(w, y.x, u1.x);
-                        u1.y = fmaf(w, y.y, u1.y);
+                    if (t < steps) {
+                        const int j = slot(t);
+                        SidW sj{0u, 0.f};
+                        if constexpr (SID) sj = sid_stage[j];
+                        step(stage.ray[j], stage.ly[j], sj, t < n);
                     }
-                    pp[0] = u0;
-                    pp[kSL] = u1;
-                };
-                // the stage slot of step t at this lane
-                auto slot = [&](int t) {
-                    if constexpr (kExact) return t < n ? sbase + f + t : snull;
-                    else return sbase + (t < n ? f + t : 0);
-                };
-                // two steps at a time, both bins' stage reads issued first
-                int t = 0;
-                for (; t + 1 < steps; t += 2) {
-                    const int j0 = slot(t), j1 = slot(t + 1);
-                    const AdjRay b0 = stage.ray[j0], b1 = stage.ray[j1];
-                    const f2v y0 = stage.ly[j0], y1 = stage.ly[j1];
-                    SidW s0{0u, 0.f}, s1{0u, 0.f};
-                    if constexpr (SID) {
-                        s0 = sid_stage[j0];
-                        s1 = sid_stage[j1];
-                    }
-                    step(b0, y0, s0, t < n);
-                    step(b1, y1, s1, t + 1 < n);
                 }
-                if (t < steps) {
-                    const int j = slot(t);
-                    SidW sj{0u, 0.f};
-                    if constexpr (SID) sj = sid_stage[j];
-                    step(stage.ray[j], stage.ly[j], sj, t < n);
-                }
+            };
+            if (lo <= hi) {
+                if (whole) chunks(std::false_type{});
+                else chunks(std::true_type{});
             }
-        };
-        if (whole) chunks(std::false_type{});
-        else chunks(std::true_type{});
+            lo = nlo;
+            hi = nhi;
+            steps = nsteps;
+        }
     }
+done:
     __syncthreads();
     // the copies summed in wave order; stored in normal image layout
     for (int i = threadIdx.x; i < kSW * kSL; i += kAdjThreads) {
