@@ -299,7 +299,9 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             q.y1 = sino[NE - 1][o];
             q.sw = SidW{0xFFFFFFFFu, 0.f};
             if constexpr (SID) q.sw = sid[o];
-            q.lr = lanes[((size_t)strip * V + vv) * kSL + lane];
+            // (an empty range reads one entry for every lane: the lane-range
+            // table is the kernel's largest input)
+            q.lr = lanes[lo > hi ? 0 : ((size_t)strip * V + vv) * kSL + lane];
             return q;
         };
         const int snull = kAdjWaves * 64 + wid;
