@@ -280,7 +280,10 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
     {
         int vzero;
         asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
-        auto load_br = [&](int v) { return sb[(v < v_end ? v : vfirst) + vzero]; };
+        auto load_br = [&](int v) {
+            return *(const BinRange *)((const char *)(sb + (v < v_end ? v : vfirst)) +
+                                       (unsigned)vzero);
+        };
         struct Pre {
             RayFwd t;
             float L, y0, y1;
@@ -288,20 +291,27 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             LaneRange lr;
         };
         auto load_pre = [&](int v, int lo, int hi) {
+            // wavefront-uniform bases (scalar registers) plus 32-bit byte
+            // offsets per lane
             Pre q;
             const int vv = v < v_end ? v : vfirst;
-            const int bj = lo + lane;
-            const int bc = lo > hi ? 0 : (bj <= hi ? bj : lo);
-            const size_t o = (size_t)vv * B + bc;
-            q.t = rays_fx[o];
-            q.L = len[o];
-            q.y0 = sino[0][o];
-            q.y1 = sino[NE - 1][o];
+            const bool empty = lo > hi;
+            const unsigned bc = empty ? 0u : (unsigned)min(lo + lane, hi);
+            const size_t vb = (size_t)vv * B;
+            auto at = [](const auto *base, unsigned bytes) {
+                return *(const std::remove_cv_t<std::remove_reference_t<decltype(*base)>> *)(
+                    (const char *)base + bytes);
+            };
+            q.t = at(rays_fx + vb, bc * (unsigned)sizeof(RayFwd));
+            q.L = at(len + vb, bc * 4u);
+            q.y0 = at(sino[0] + vb, bc * 4u);
+            q.y1 = at(sino[NE - 1] + vb, bc * 4u);
             q.sw = SidW{0xFFFFFFFFu, 0.f};
-            if constexpr (SID) q.sw = sid[o];
+            if constexpr (SID) q.sw = at(sid + vb, bc * (unsigned)sizeof(SidW));
             // (an empty range reads one entry for every lane: the lane-range
             // table is the kernel's largest input)
-            q.lr = lanes[lo > hi ? 0 : ((size_t)strip * V + vv) * kSL + lane];
+            q.lr = at(lanes + ((size_t)strip * V + vv) * kSL,
+                      empty ? 0u : (unsigned)lane * (unsigned)sizeof(LaneRange));
             return q;
         };
         const int snull = kAdjWaves * 64 + wid;
