@@ -384,7 +384,13 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
                     // adds zero to lines -1 and 0
                     auto step = [&](const AdjRay &b, f2v y, SidW sw, bool ok) {
                         const uint64_t p = (uint64_t)(uint32_t)b.k * (uint32_t)lane + (uint64_t)b.a;
-                        const int qh = (int)(uint32_t)(p >> 32) + __mul24((int)(b.k >> 32), lane);
+                        // high word + k_hi lane as a 24-bit multiply-add (k_hi is -1, 0
+                    // or 1); written out, because the compiler otherwise forms it
+                    // with a second 64-bit multiply-add
+                    int qh;
+                    asm("v_mad_i32_i24 %0, %1, %2, %3"
+                        : "=v"(qh)
+                        : "v"((int)(b.k >> 32)), "v"(lane), "v"((int)(uint32_t)(p >> 32)));
                         int i0 = qh;
                         if constexpr (!kExact) {
                             ok = ok && qh >= -1 && qh <= kSW - 1;
