@@ -297,7 +297,9 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             const int vv = v < v_end ? v : vfirst;
             const bool empty = lo > hi;
             const unsigned bc = empty ? 0u : (unsigned)min(lo + lane, hi);
-            const size_t vb = (size_t)vv * B;
+            // an empty range reads the tables' first entries (lines that stay in
+            // cache), not each view's own
+            const size_t vb = empty ? 0 : (size_t)vv * B;
             auto at = [](const auto *base, unsigned bytes) {
                 return *(const std::remove_cv_t<std::remove_reference_t<decltype(*base)>> *)(
                     (const char *)base + bytes);
@@ -308,9 +310,8 @@ __device__ __forceinline__ void adj_block(AdjShared<NE> &sh, const float *const 
             q.y1 = at(sino[NE - 1] + vb, bc * 4u);
             q.sw = SidW{0xFFFFFFFFu, 0.f};
             if constexpr (SID) q.sw = at(sid + vb, bc * (unsigned)sizeof(SidW));
-            // (an empty range reads one entry for every lane: the lane-range
-            // table is the kernel's largest input)
-            q.lr = at(lanes + ((size_t)strip * V + vv) * kSL,
+            // (the lane-range table is the kernel's largest input)
+            q.lr = at(empty ? lanes : lanes + ((size_t)strip * V + vv) * kSL,
                       empty ? 0u : (unsigned)lane * (unsigned)sizeof(LaneRange));
             return q;
         };
