@@ -77,6 +77,18 @@ dect_status dect_nn_shuffle(const void *src, void *dst, int32_t N, int32_t Hin, 
 dect_status dect_nn_concat(void *a, void *b, void *z, size_t P, int32_t C1, int32_t C2,
                            int32_t inverse, void *stream);
 
+/* Depth-to-space of t followed by the channel concat with s, in one pass (the
+ * decoder's upsampled input joined to its skip connection):
+ * z[n][h][w] = (shuffle(t)[n][h][w], s[n][h][w]), t [N][Hin][Win][4 C1], s
+ * [N][2 Hin][2 Win][C2], z [N][2 Hin][2 Win][C1 + C2] (bfloat16, device
+ * memory owned by the caller).  inverse = 1 splits z into t (the inverse
+ * shuffle of z's first C1 channels) and s.  Element for element the same as
+ * dect_nn_shuffle then dect_nn_concat (or dect_nn_concat's split then the
+ * inverse shuffle).  C1, C2 positive multiples of 8 and 16-byte aligned
+ * pointers, else DECT_ERR_INVALID_ARG. */
+dect_status dect_nn_shuffle_concat(void *t, void *s, void *z, int32_t N, int32_t Hin, int32_t Win,
+                                   int32_t C1, int32_t C2, int32_t inverse, void *stream);
+
 /* z = a + b (bfloat16, n elements, FP32 arithmetic). */
 dect_status dect_nn_add(const void *a, const void *b, void *z, size_t n, void *stream);
 

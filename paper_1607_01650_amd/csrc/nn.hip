@@ -869,6 +869,30 @@ __global__ void k_concat8(uint4 *__restrict__ a, uint4 *__restrict__ b, uint4 *_
     else *s = z[i];
 }
 
+// z = (depth-to-space of t: C1 channels, s: C2 channels) in 8-channel pieces,
+// one thread per piece of z; inverse: t and s from z
+__global__ void k_shuffle_concat8(uint4 *__restrict__ t, uint4 *__restrict__ s,
+                                  uint4 *__restrict__ z, int N, int Hin, int Win, int C1, int C2,
+                                  int inverse)
+{
+    const int g1 = C1 / 8, g = (C1 + C2) / 8;
+    const int H = 2 * Hin, W = 2 * Win;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)N * H * W * g) return;
+    const size_t p = i / g;
+    const int c = (int)(i - p * g);
+    uint4 *src;
+    if (c < g1) {
+        const int w = (int)(p % W), h = (int)((p / W) % H), n = (int)(p / ((size_t)W * H));
+        src = t + (((size_t)n * Hin + h / 2) * Win + w / 2) * (4 * g1) +
+              ((h % 2) * 2 + (w % 2)) * g1 + c;
+    } else {
+        src = s + p * (g - g1) + (c - g1);
+    }
+    if (!inverse) z[i] = *src;
+    else *src = z[i];
+}
+
 // depth-to-space in 8-channel pieces (C % 8 == 0)
 __global__ void k_shuffle8(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int N, int Hin,
                            int Win, int C, int inverse)
@@ -1318,6 +1342,22 @@ dect_status dect_nn_concat(void *a, void *b, void *z, size_t P, int32_t C1, int3
     else
         hipLaunchKernelGGL(k_concat, dim3(blocks(total)), dim3(256), 0, (hipStream_t)stream,
                            (u16 *)a, (u16 *)b, (u16 *)z, P, C1, C2, inverse);
+    NN_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+dect_status dect_nn_shuffle_concat(void *t, void *s, void *z, int32_t N, int32_t Hin, int32_t Win,
+                                   int32_t C1, int32_t C2, int32_t inverse, void *stream)
+{
+    if (!t || !s || !z || N <= 0 || Hin <= 0 || Win <= 0 || C1 <= 0 || C2 <= 0 ||
+        C1 % 8 != 0 || C2 % 8 != 0 || !aligned16(t) || !aligned16(s) || !aligned16(z))
+        return nn_fail(DECT_ERR_INVALID_ARG,
+                       "shuffle_concat: channels must be positive multiples of 8, pointers "
+                       "16-byte aligned");
+    const size_t pieces = (size_t)N * 4 * Hin * Win * ((C1 + C2) / 8);
+    hipLaunchKernelGGL(k_shuffle_concat8, dim3(blocks(pieces)), dim3(256), 0,
+                       (hipStream_t)stream, (uint4 *)t, (uint4 *)s, (uint4 *)z, N, Hin, Win, C1,
+                       C2, inverse);
     NN_HIP(hipGetLastError());
     return DECT_OK;
 }

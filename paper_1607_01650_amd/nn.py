@@ -42,6 +42,7 @@ def _lib():
             "dect_nn_pool": [vp, vp, vp, i32, i32, i32, i32, i32, vp],
             "dect_nn_shuffle": [vp, vp, i32, i32, i32, i32, i32, vp],
             "dect_nn_concat": [vp, vp, vp, sz, i32, i32, i32, vp],
+            "dect_nn_shuffle_concat": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
             "dect_nn_add": [vp, vp, vp, sz, vp],
             "dect_nn_convert": [vp, vp, sz, i32, vp],
             "dect_nn_adam": [vp, vp, vp, vp, vp, sz, d, d, d, d, i32, d, vp],
@@ -168,6 +169,26 @@ def split(z, c1):
     b = torch.empty((N, H, W, C - c1), device=z.device, dtype=torch.bfloat16)
     _ck(_lib().dect_nn_concat(_p(a), _p(b), _p(z), N * H * W, c1, C - c1, 1, _s()), "split")
     return a, b
+
+
+def shuffle_concat(t, s, c):
+    """concat(shuffle(t, c), s) in one pass."""
+    N, Hin, Win, _ = t.shape
+    C2 = s.shape[-1]
+    z = torch.empty((N, 2 * Hin, 2 * Win, c + C2), device=t.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_shuffle_concat(_p(t), _p(s), _p(z), N, Hin, Win, c, C2, 0, _s()),
+        "shuffle_concat")
+    return z
+
+
+def split_unshuffle(z, c):
+    """(unshuffle(a, c), b) for (a, b) = split(z, c), in one pass."""
+    N, H, W, C = z.shape
+    t = torch.empty((N, H // 2, W // 2, 4 * c), device=z.device, dtype=torch.bfloat16)
+    s = torch.empty((N, H, W, C - c), device=z.device, dtype=torch.bfloat16)
+    _ck(_lib().dect_nn_shuffle_concat(_p(t), _p(s), _p(z), N, H // 2, W // 2, c, C - c, 1,
+                                      _s()), "split_unshuffle")
+    return t, s
 
 
 def add(a, b):
@@ -317,8 +338,7 @@ class UNet:
         for j, lvl in enumerate((2, 1, 0)):
             c = self.ch[lvl]
             tt = self.up[j].forward(h)
-            u = shuffle(tt, c)
-            z = concat(u, skips[lvl])
+            z = shuffle_concat(tt, skips[lvl], c)
             a = self.dec[j][0].forward(z)
             b = self.dec[j][1].forward(a)
             t[f"uin{j}"], t[f"z{j}"], t[f"d{j}a"], t[f"d{j}b"] = h, z, a, b
@@ -350,9 +370,8 @@ class UNet:
             da = self.dec[j][1].backward(dh, t[f"d{j}a"], t[f"d{j}b"], dy_masked=True,
                                          mask_dx=True)
             dz = self.dec[j][0].backward(da, t[f"z{j}"], t[f"d{j}a"], dy_masked=True)
-            du, ds = split(dz, c)
+            dt, ds = split_unshuffle(dz, c)
             dskip[lvl] = ds
-            dt = unshuffle(du, c)
             dh = self.up[j].backward(dt, t[f"uin{j}"], None, mask_dx=True)
         # encoder in reverse
         for lvl in (3, 2, 1, 0):

@@ -12,8 +12,8 @@ from paper_1607_01650_amd import dect
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    text = open(os.path.join(ROOT, "include", "dect.h")).read()
+def _declared(header="dect.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(dect_[a-z0-9_]+)\s*\(", text)))
 
@@ -31,6 +31,18 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(dect.SIGNATURES), "binding and header disagree"
+
+
+def test_every_header_symbol_is_exported(lib):
+    """Every entry point that any header under include/ declares (the network
+    kernels' dect_nn.h too) is exported by the one library."""
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert "dect_nn.h" in headers
+    for h in headers:
+        names = _declared(h)
+        assert names, h
+        for n in names:
+            assert hasattr(lib, n), (h, n)
 
 
 def test_version(lib):

@@ -114,6 +114,27 @@ def test_pool_shuffle_concat_exact(torch):
     assert np.array_equal(_np(nn.add(_bf(torch, a), _bf(torch, a))), R.bf16(2 * a))
 
 
+@pytest.mark.parametrize("c1,c2", [(24, 16), (48, 48), (8, 32)])
+def test_shuffle_concat_is_the_two_passes(torch, c1, c2):
+    """dect_nn_shuffle_concat equals shuffle then concat, and its inverse split
+    then unshuffle, bit for bit (odd image sizes, uneven channel splits)."""
+    nn = _nn()
+    rng = np.random.default_rng(5)
+    t = _bf(torch, R.bf16(rng.standard_normal((2, 3, 5, 4 * c1))))
+    s = _bf(torch, R.bf16(rng.standard_normal((2, 6, 10, c2))))
+    z = nn.shuffle_concat(t, s, c1)
+    ref = nn.concat(nn.shuffle(t, c1), s)
+    assert np.array_equal(_np(z), _np(ref))
+    t2, s2 = nn.split_unshuffle(z, c1)
+    a, b = nn.split(ref, c1)
+    assert np.array_equal(_np(t2), _np(nn.unshuffle(a, c1)))
+    assert np.array_equal(_np(t2), _np(t)) and np.array_equal(_np(s2), _np(s))
+    dect = __import__("paper_1607_01650_amd.dect", fromlist=["DectError"])
+    with pytest.raises(dect.DectError):  # channels not a multiple of 8
+        nn._ck(nn._lib().dect_nn_shuffle_concat(nn._p(t), nn._p(s), nn._p(z), 2, 3, 5, 12, c2,
+                                                0, nn._s()), "shuffle_concat")
+
+
 def test_adam_and_mse(torch):
     nn = _nn()
     rng = np.random.default_rng(4)
